@@ -1,0 +1,284 @@
+"""Seeded synthetic workloads (inputs only).
+
+This module builds the initial state that both the GPU library and the CPU
+oracle receive: solvent positions and velocities, rigid-body templates (surface
+sites in the principal frame, principal moments, mass), body placement,
+orientations and momenta.  It performs none of the per-step arithmetic of the
+method; it only draws and arranges inputs.
+
+Recipe (the paper's workloads, Sec. II and III; its equilibrated suspension
+configurations are not available, so random sequential addition stands in):
+
+* Solvent: uniform positions in the periodic box, Maxwell-Boltzmann velocities
+  at kT, mass m, a fixed number density per cell (Sec. II.A: 5 per cell).
+* Colloids: spheres whose surface sites lie on a Fibonacci lattice (the paper
+  uses a twice-subdivided icosahedron; any discretization is allowed by the
+  method, Sec. II.B), site mass 5 (Sec. II.B).  The sites are recentred on
+  their centre of mass and rotated into the principal frame, so the inertia
+  tensor is diagonal in the body frame.
+* Body positions by random sequential addition with a minimum centre distance,
+  orientations uniform on SO(3), linear velocities N(0, kT/M), body-frame
+  angular momenta N(0, kT I_k).  Total momentum is then removed.
+* Solvent particles are stored in the order of their initial (unshifted) cell,
+  which is only a choice of labels.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# Rigid-body templates
+
+def fibonacci_sphere(nsites: int, radius: float) -> np.ndarray:
+    """Sites on a sphere: z_i = 1 - (2i+1)/n, azimuth i * pi * (3 - sqrt 5)."""
+    i = np.arange(nsites, dtype=np.float64)
+    z = 1.0 - (2.0 * i + 1.0) / nsites
+    phi = i * math.pi * (3.0 - math.sqrt(5.0))
+    rxy = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return radius * np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], axis=1)
+
+
+def cube_surface(edge: float = 4.0, per_side: int = 5) -> np.ndarray:
+    """per_side x per_side grid on each of the 6 faces of a cube (150 sites for 5)."""
+    h = 0.5 * edge
+    g = (np.arange(per_side) + 0.5) / per_side * edge - h
+    u, w = np.meshgrid(g, g, indexing="ij")
+    u, w = u.ravel(), w.ravel()
+    faces = []
+    for axis in range(3):
+        for sgn in (-1.0, 1.0):
+            f = np.zeros((u.size, 3))
+            f[:, axis] = sgn * h
+            f[:, (axis + 1) % 3] = u
+            f[:, (axis + 2) % 3] = w
+            faces.append(f)
+    return np.concatenate(faces)
+
+
+def rod_surface(length: float = 10.0, radius: float = 1.0, rings: int = 18,
+                per_ring: int = 10) -> np.ndarray:
+    """Open cylinder: rings of sites, odd rings rotated by half a spacing."""
+    out = []
+    for k in range(rings):
+        z = -0.5 * length + (k + 0.5) * length / rings
+        off = (math.pi / per_ring) if (k % 2) else 0.0
+        ang = off + 2.0 * math.pi * np.arange(per_ring) / per_ring
+        out.append(np.stack([radius * np.cos(ang), radius * np.sin(ang), np.full(per_ring, z)], 1))
+    return np.concatenate(out)
+
+
+def dumbbell_surface(radius: float = 1.5, separation: float = 4.0, per_sphere: int = 80):
+    s = fibonacci_sphere(per_sphere, radius)
+    a = s + np.array([0.0, 0.0, 0.5 * separation])
+    b = s - np.array([0.0, 0.0, 0.5 * separation])
+    return np.concatenate([a, b])
+
+
+def rigid_template(sites: np.ndarray, site_mass: float):
+    """Recentre sites on their centre of mass and rotate into the principal frame.
+
+    Returns (dhat [S_b,3], principal moments [3], total mass).
+    """
+    sites = np.asarray(sites, dtype=np.float64)
+    m = np.full(sites.shape[0], float(site_mass))
+    M = float(m.sum())
+    com = (m[:, None] * sites).sum(0) / M
+    d = sites - com
+    r2 = (d * d).sum(1)
+    Itens = (m[:, None, None] * (r2[:, None, None] * np.eye(3)[None] - d[:, :, None] * d[:, None, :])).sum(0)
+    evals, evecs = np.linalg.eigh(Itens)
+    if np.linalg.det(evecs) < 0:
+        evecs[:, 2] = -evecs[:, 2]
+    dhat = d @ evecs
+    return dhat, evals.copy(), M, m
+
+
+def random_quaternions(rng, n: int) -> np.ndarray:
+    """Uniform unit quaternions (Shoemake), rows (w, x, y, z)."""
+    u1, u2, u3 = rng.random(n), rng.random(n), rng.random(n)
+    q = np.stack([np.sqrt(1 - u1) * np.sin(2 * np.pi * u2), np.sqrt(1 - u1) * np.cos(2 * np.pi * u2),
+                  np.sqrt(u1) * np.sin(2 * np.pi * u3), np.sqrt(u1) * np.cos(2 * np.pi * u3)], 1)
+    return q / np.linalg.norm(q, axis=1, keepdims=True)
+
+
+def rsa_positions(rng, box, n: int, dmin: float, max_tries: int = 200000000) -> np.ndarray:
+    """Random sequential addition of n points, minimum-image distance >= dmin."""
+    box = np.asarray(box, dtype=np.float64)
+    ng = np.maximum(1, np.floor(box / dmin).astype(int))
+    cw = box / ng
+    grid: dict = {}
+    pts = np.zeros((n, 3))
+    placed, tries = 0, 0
+    while placed < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("random sequential addition did not converge")
+        p = rng.random(3) * box
+        g = np.floor(p / cw).astype(int) % ng
+        ok = True
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    key = ((g[0] + dx) % ng[0], (g[1] + dy) % ng[1], (g[2] + dz) % ng[2])
+                    for j in grid.get(key, ()):
+                        dr = p - pts[j]
+                        dr -= box * np.round(dr / box)
+                        if dr @ dr < dmin * dmin:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if ok:
+            pts[placed] = p
+            grid.setdefault((g[0], g[1], g[2]), []).append(placed)
+            placed += 1
+    return pts
+
+
+# ---------------------------------------------------------------------------
+# Systems
+
+def srd_params(seed: int, kT_cell: float = 1.0, dt: float = 0.1, alpha_deg: float = 130.0,
+               kT: float = 1.0, wca=None, thermalize: int = 1) -> dict:
+    a = math.radians(alpha_deg)
+    return dict(dt=dt, cos_a=math.cos(a), sin_a=math.sin(a), kT=kT, kT_cell=kT_cell,
+                seed=int(seed), thermalize=int(thermalize), wca=dict(wca or {"mode": 0}))
+
+
+def make_system(ncell, density, templates, centres, quats, rng, kT: float = 1.0,
+                a: float = 1.0, m: float = 1.0, n_solvent=None, sort_solvent: bool = True,
+                zero_momentum: bool = True) -> dict:
+    """Assemble one periodic system.
+
+    templates: list (one per body) of (dhat [S_b,3], I [3], M, site masses [S_b]).
+    centres: [B,3] body centres; quats: [B,4] orientations (w,x,y,z).
+    """
+    ncell = tuple(int(n) for n in ncell)
+    L = np.array(ncell, dtype=np.float64) * a
+    C = ncell[0] * ncell[1] * ncell[2]
+    N = int(round(density * C)) if n_solvent is None else int(n_solvent)
+    x = rng.random((N, 3)) * L
+    x = np.minimum(x, np.nextafter(L, 0))
+    v = rng.normal(0.0, math.sqrt(kT / m), size=(N, 3))
+    if sort_solvent and N > 0:
+        j = np.floor(x / a).astype(np.int64)
+        j = np.minimum(j, np.array(ncell) - 1)
+        cid = (j[:, 2] * ncell[1] + j[:, 1]) * ncell[0] + j[:, 0]
+        order = np.argsort(cid, kind="stable")
+        x, v = x[order], v[order]
+
+    B = len(templates)
+    R = np.zeros((3, B)); q = np.zeros((4, B)); P = np.zeros((3, B)); p = np.zeros((4, B))
+    Mv = np.zeros(B); Iv = np.zeros((3, B))
+    dh, sm, off = [], [], [0]
+    for b, (dhat, I, M, ms) in enumerate(templates):
+        R[:, b] = np.asarray(centres[b], dtype=np.float64) % L
+        qb = np.asarray(quats[b], dtype=np.float64)
+        q[:, b] = qb / np.linalg.norm(qb)
+        Mv[b] = M
+        Iv[:, b] = I
+        P[:, b] = rng.normal(0.0, math.sqrt(kT * M), size=3)
+        Lh = rng.normal(0.0, 1.0, size=3) * np.sqrt(kT * np.asarray(I))
+        w, xq, yq, zq = q[:, b]
+        # conjugate quaternion momentum p = 2 q (x) (0, Lhat)
+        p[:, b] = 2.0 * np.array([-xq * Lh[0] - yq * Lh[1] - zq * Lh[2],
+                                  w * Lh[0] - zq * Lh[1] + yq * Lh[2],
+                                  zq * Lh[0] + w * Lh[1] - xq * Lh[2],
+                                  -yq * Lh[0] + xq * Lh[1] + w * Lh[2]])
+        dh.append(np.asarray(dhat)); sm.append(np.asarray(ms)); off.append(off[-1] + len(ms))
+    if zero_momentum and (N > 0 or B > 0):
+        Ptot = m * v.sum(0) + P.sum(1)
+        Mtot = m * N + Mv.sum()
+        vcm = Ptot / Mtot
+        v -= vcm
+        P -= Mv[None, :] * vcm[:, None]
+    dhat = np.concatenate(dh).T.copy() if B else np.zeros((3, 0))
+    return dict(ncell=ncell, a=float(a), m=float(m),
+                x=np.ascontiguousarray(x.T), v=np.ascontiguousarray(v.T),
+                R=R, img=np.zeros((3, B), dtype=np.int32), q=q, P=P, p=p,
+                F=np.zeros((3, B)), T=np.zeros((3, B)), M=Mv, I=Iv,
+                site_off=np.array(off, dtype=np.int64), dhat=np.ascontiguousarray(dhat),
+                sm=np.concatenate(sm) if B else np.zeros(0))
+
+
+def sphere_template(radius: float, nsites: int, site_mass: float = 5.0):
+    dhat, I, M, ms = rigid_template(fibonacci_sphere(nsites, radius), site_mass)
+    return (dhat, I, M, ms)
+
+
+def single_sphere(ncell=(10, 10, 10), density=5, radius=2.0, nsites=100, site_mass=5.0,
+                  centre=None, seed=1, kT=1.0, identity=True):
+    """One Fibonacci sphere in a cubic periodic box (the single-particle validation case)."""
+    rng = np.random.default_rng(seed)
+    L = np.array(ncell, dtype=np.float64)
+    centre = 0.5 * L if centre is None else np.asarray(centre, dtype=np.float64)
+    tpl = sphere_template(radius, nsites, site_mass)
+    quat = np.array([[1.0, 0.0, 0.0, 0.0]]) if identity else random_quaternions(rng, 1)
+    return make_system(ncell, density, [tpl], [centre], quat, rng, kT=kT)
+
+
+def suspension(ncell, density, nbodies, radius=3.0, nsites=200, site_mass=5.0, seed=2, kT=1.0):
+    """Hard-sphere suspension: RSA sphere centres at least one diameter apart."""
+    rng = np.random.default_rng(seed)
+    L = np.array(ncell, dtype=np.float64)
+    tpl = sphere_template(radius, nsites, site_mass)
+    centres = rsa_positions(rng, L, nbodies, 2.0 * radius) if nbodies else np.zeros((0, 3))
+    quats = random_quaternions(rng, nbodies)
+    return make_system(ncell, density, [tpl] * nbodies, centres, quats, rng, kT=kT)
+
+
+# ---------------------------------------------------------------------------
+# The five named workloads
+
+def wca_spheres(sigma=6.0, eps=1.0, delta=0.0):
+    return {"mode": 1, "eps": eps, "sigma": sigma, "delta": delta}
+
+
+def config(i: int, kT_cell: float = 1.0):
+    """Return (workload, params, meta) for named workload i.
+
+    0  single sphere r=2 (100 sites) in 10^3 cells, 5/cell; 100 steps; seed 1
+    1  suspension: 60^3 cells, 5/cell, 191 spheres r=3 (200 sites), WCA sigma=6; seed 2
+    2  large suspension: 200^3 cells, 10/cell, spheres r=3 at volume fraction 0.3; seed 3
+    3  batched: 512 cubic boxes, edge U{12..24}, 5/cell, one sphere r=2 each; seed 4
+    """
+    if i == 0:
+        wl = single_sphere((10, 10, 10), 5, 2.0, 100, 5.0, centre=(5.0, 5.0, 5.0), seed=1)
+        return wl, srd_params(1, kT_cell=kT_cell), dict(name="single sphere 10^3 cells", steps=100)
+    if i == 1:
+        wl = suspension((60, 60, 60), 5, 191, 3.0, 200, 5.0, seed=2)
+        return wl, srd_params(2, kT_cell=kT_cell, wca=wca_spheres()), dict(
+            name="hard-sphere suspension 60^3 cells, 1.08M solvent, 191 spheres x 200 sites",
+            steps=1000)
+    if i == 2:
+        vsph = 4.0 / 3.0 * math.pi * 27.0
+        nb = int(round(0.3 * 200 ** 3 / vsph))
+        wl = suspension((200, 200, 200), 10, nb, 3.0, 200, 5.0, seed=3)
+        return wl, srd_params(3, kT_cell=kT_cell, wca=wca_spheres()), dict(
+            name="large suspension 200^3 cells, 80M solvent, %d spheres x 200 sites" % nb, steps=200)
+    if i == 3:
+        return batched_replicas(512, seed=4, kT_cell=kT_cell)
+    raise ValueError("unknown workload %d" % i)
+
+
+def batched_replicas(nrep=512, seed=4, lo=12, hi=24, density=5, kT_cell=1.0):
+    """Independent cubic boxes with integer edges drawn uniformly from lo..hi."""
+    rng = np.random.default_rng(seed)
+    edges = rng.integers(lo, hi + 1, size=nrep)
+    tpl = sphere_template(2.0, 100, 5.0)
+    systems = []
+    for r in range(nrep):
+        n = int(edges[r])
+        rr = np.random.default_rng([seed, r])
+        systems.append(make_system((n, n, n), density, [tpl], [(0.5 * n, 0.5 * n, 0.5 * n)],
+                                   np.array([[1.0, 0.0, 0.0, 0.0]]), rr))
+    return systems, srd_params(seed, kT_cell=kT_cell), dict(
+        name="%d replicas, edges %d..%d cells, 5/cell, one sphere r=2 each" % (nrep, lo, hi),
+        steps=10000)
