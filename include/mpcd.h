@@ -1,0 +1,234 @@
+/*
+ * mpcd.h -- C ABI of libmpcd.so: one step of multiparticle collision dynamics
+ * (MPCD, stochastic rotation dynamics) with colloids represented as rigid
+ * bodies of discrete surface sites, as hand-written HIP kernels for gfx950.
+ *
+ * Method: Bush, Palmer, Howard, "Simulating hydrodynamic interactions in
+ * colloidal suspensions using multiparticle collision dynamics with rigid-body
+ * constraints", arXiv 2604.14307.  Section/equation numbers below refer to it.
+ *
+ * One step, in this order (the paper does not fix the order; the collision is
+ * taken at the start of the step and the collision period equals the step):
+ *   sites_thermalize  Eq. (5) site positions/velocities, then Eq. (7)
+ *   mpcd_bin          random grid shift + counting sort of solvent and sites
+ *   mpcd_collide      per-cell SRD rotation (+ optional cell thermostat),
+ *                     optionally fused with the solvent streaming
+ *   sites_to_body     net momentum J and angular momentum K of each body's sites
+ *   body_integrate    impulse (J, K) + quaternion velocity-Verlet (Miller et al.)
+ *   mpcd_stream       ballistic solvent streaming (when not fused)
+ *   mpcd_advance_step step counter += 1 (on the device)
+ * mpcd_step runs the whole sequence.
+ *
+ * Conventions (all entry points):
+ *  - Every array argument is a DEVICE pointer unless marked "host".  The caller
+ *    owns and allocates every buffer, including the workspace of
+ *    mpcd_workspace_bytes() bytes.  The library keeps no pointer after a call.
+ *  - Arrays are component-major ("SoA"): x[0..n) are the x components,
+ *    x[n..2n) the y components, x[2n..3n) the z components.  Per-system arrays
+ *    (ncell, offsets) are system-major.  Quaternions are (w, x, y, z).
+ *  - Solvent and site positions/velocities are double when prec == MPCD_F64,
+ *    float when prec == MPCD_F32.  Body arrays are always double.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*), allocate nothing, never synchronize (except mpcd_status) and are
+ *    graph-capturable.  The step index is read from a device uint64_t so a
+ *    captured graph replays correctly.
+ *  - Several independent periodic boxes ("systems", e.g. replicas) may be
+ *    advanced together: nsys > 1 with per-system offsets.  A system's results
+ *    do not depend on the other systems.
+ *  - Random numbers: Philox4x64-10, key (seed, purpose), counter
+ *    (step, entity, replica0 + system, call); purpose 0 grid shift (entity 0),
+ *    1 collision axis (entity = cell index within its system), 2 thermostat
+ *    (entity = cell), 3 site velocities (entity = site index within its system).
+ *  - Limits: total solvent + sites < 2^31; total cells < 2^31.
+ *
+ * Errors: 0 on success, else a negative code below; nothing is launched then.
+ * Device-side anomalies set sticky bits in the workspace, read by mpcd_status.
+ */
+#ifndef MPCD_H
+#define MPCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { MPCD_F64 = 0, MPCD_F32 = 1 };
+
+enum {
+    MPCD_OK = 0,
+    MPCD_EINVAL = -1,     /* null/misaligned pointer, bad size or parameter */
+    MPCD_EWORKSPACE = -2, /* workspace too small */
+    MPCD_EHIP = -3,       /* a HIP call failed: see mpcd_last_hip_error() */
+    MPCD_ENOTSUP = -4     /* unsupported precision/feature combination */
+};
+
+/* Sticky status bits. */
+#define MPCD_FLAG_NONFINITE 1u /* a NaN/Inf velocity, position or momentum    */
+#define MPCD_FLAG_ESCAPE 2u    /* a particle moved more than one box length    */
+#define MPCD_FLAG_FIXOVF 4u    /* FP32 path: fixed-point cell sum overflow     */
+#define MPCD_FLAG_RNGLOOP 8u   /* a rejection sampler used all 64 Philox calls */
+
+/* Geometry and sizes of nsys independent periodic boxes of cubic cells. */
+typedef struct {
+    int32_t nsys;         /* number of systems (>= 1)                          */
+    int32_t prec;         /* MPCD_F64 or MPCD_F32 solvent/site storage          */
+    double a;             /* cell edge (> 0); box edge of system r = ncell * a  */
+    double m_solvent;     /* solvent particle mass (> 0)                        */
+    int64_t n_solvent;    /* host: total solvent particles over all systems     */
+    int64_t n_sites;      /* host: total surface sites                          */
+    int64_t n_bodies;     /* host: total rigid bodies                           */
+    int64_t n_cells;      /* host: total cells = sum over r of nx*ny*nz         */
+    uint64_t replica0;    /* host: Philox replica id of system 0                */
+    const int32_t *ncell;    /* [3*nsys] cells per axis (nx,ny,nz) of system r  */
+    const int64_t *solv_off; /* [nsys+1] solvent of system r: [off[r], off[r+1]) */
+    const int64_t *cell_off; /* [nsys+1] global cell index of system r's cell 0  */
+    const int64_t *body_off; /* [nsys+1] bodies of system r                      */
+} mpcd_sys;
+
+/* Rigid bodies (always double).  Body b owns sites [site_off[b], site_off[b+1]). */
+typedef struct {
+    double *pos;            /* [3B] centre of mass R, wrapped into [0, L)      */
+    int32_t *image;         /* [3B] periodic image counters of R                */
+    double *quat;           /* [4B] orientation q (w,x,y,z), body -> space      */
+    double *mom;            /* [3B] linear momentum P                           */
+    double *angmom;         /* [4B] conjugate quaternion momentum p (Miller)    */
+    double *force;          /* [3B] force from the last evaluation              */
+    double *torque;         /* [3B] torque (space frame) from the last evaluation */
+    const double *mass;     /* [B] total mass M = sum of site masses            */
+    const double *inertia;  /* [3B] principal moments (body frame is principal) */
+    const int64_t *site_off;  /* [B+1]                                          */
+    const int32_t *site_body; /* [S] body of each site                          */
+    const double *site_d;     /* [3S] body-frame site offsets from R            */
+    const double *site_m;     /* [S] site masses                                */
+} mpcd_bodies;
+
+/* Colloid repulsion, Eq. (1): core-shifted WCA between body centres. */
+typedef struct {
+    int32_t mode;        /* 0 off, 1 between body centres                      */
+    double eps, sigma, delta;
+} mpcd_wca;
+
+/* Scalars of one step. */
+typedef struct {
+    double dt;           /* step = collision period (0.1 tau in the paper)     */
+    double cos_a, sin_a; /* SRD rotation angle (130 degrees in the paper)      */
+    double kT;           /* site thermalization temperature, Eq. (7)           */
+    double kT_cell;      /* cell thermostat temperature; <= 0 turns it off     */
+    uint64_t seed;       /* Philox key word 0                                  */
+    int32_t thermalize;  /* 1: Eq. (7) thermalization; 0: rigid velocities only */
+    int32_t fuse_stream; /* 1: stream the solvent inside mpcd_collide          */
+    mpcd_wca wca;
+} mpcd_params;
+
+/* All buffers of one step (for mpcd_step and graph capture). */
+typedef struct {
+    const mpcd_sys *sys;   /* host pointer to the geometry                      */
+    mpcd_bodies bodies;
+    void *x, *v;           /* [3N] solvent positions, velocities (prec)         */
+    const int32_t *tag;    /* [N] solvent identities, or NULL (= index)         */
+    void *xs, *vs;         /* [3S] site positions, velocities (prec)            */
+    double *J, *K;         /* [3B] collision impulse and angular impulse        */
+    uint64_t *d_step;      /* device step counter                               */
+    void *ws;              /* workspace                                         */
+    size_t ws_bytes;
+    mpcd_params par;
+} mpcd_step_args;
+
+/* Workspace bytes for sys (host-side sizes only).  The workspace holds the cell
+ * counts and starts, the per-particle cell/slot/permutation, the per-step grid
+ * shifts, per-site scratch and the status word.  Initialise once with
+ * mpcd_ws_init before the first step. */
+size_t mpcd_workspace_bytes(const mpcd_sys *sys);
+
+/* Byte offsets inside the workspace (for inspection by tests and tools):
+ * out[0] status word (uint32), out[1] grid shifts [3*nsys] (double),
+ * out[2] cell_start [n_cells+1] (int32), out[3] permutation [N+S] (int32,
+ * particles grouped by global cell), out[4] cell of each particle (int32),
+ * out[5] slot within the cell (int32), out[6] site offsets d_j [3S] (double),
+ * out[7] site velocities entering the collision [3S] (double). */
+int mpcd_workspace_offsets(const mpcd_sys *sys, int64_t out[8]);
+
+/* Zero the counters and the status word of a fresh workspace. */
+int mpcd_ws_init(void *stream, const mpcd_sys *sys, void *ws, size_t ws_bytes);
+
+/* Ballistic streaming, Sec. II.A: x <- wrap(x + v dt) per component, one
+ * periodic correction.  x, v: [3N] (prec). */
+int mpcd_stream(void *stream, const mpcd_sys *sys, void *x, const void *v, double dt,
+                void *ws, size_t ws_bytes);
+
+/* Random grid shift and cell binning, Sec. II.A.  Shift s in [-a/2, a/2)^3 per
+ * system and step on a 2^-24 a grid; particle k (solvent 0..N-1, then sites
+ * N..N+S-1) goes to cell floor((x - s)/a) mod n of its system; counting sort
+ * (count, exclusive scan, scatter) into the workspace.  x: [3N], xs: [3S]
+ * (prec); bodies supplies site_body/site_off (may be NULL when S == 0). */
+int mpcd_bin(void *stream, const mpcd_sys *sys, const void *x, const void *xs,
+             const mpcd_bodies *bodies, uint64_t seed, const uint64_t *d_step, void *ws,
+             size_t ws_bytes);
+
+/* SRD collision, Sec. II.A; sites take part like heavy solvent, Sec. II.B.2.
+ * For every cell with >= 2 particles: M, P summed over its members (FP64: in
+ * ascending identity -- solvent tag, then N_total + site index; FP32: exact
+ * int64 fixed-point sums at 2^-32), u = P/M, random axis n, rotation R(n, a);
+ * with kT_cell > 0 the relative kinetic energy E is rescaled to
+ * kT_cell * Gamma(3(n_c - 1)/2) (Eq. (6) with 3(n_c-1) degrees of freedom);
+ * v <- u + lambda R (v - u).  When x_stream != NULL the solvent is then streamed
+ * by dt in the same pass.  Requires mpcd_bin for the same step.
+ * v: [3N], vs: [3S] (prec, in place); tag: [N] or NULL. */
+int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
+                 const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
+                 uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes,
+                 void *x_stream, double dt);
+
+/* Site positions and thermalized velocities, Eqs. (5) and (7).  Per body:
+ * V = P/M, omega = A (Lhat / I) with Lhat_k = p . P_k q / 2; site offset
+ * d_j = A dhat_j, position wrap(R + d_j); random velocities vt_j ~ N(0, kT/m_j);
+ * Vt = sum m_j vt_j / M, Lt = sum d_j x m_j vt_j, wt = A((A^T Lt) / I) (site
+ * order); v_j = (V - Vt) + (omega - wt) x d_j + vt_j.  thermalize == 0 gives the
+ * rigid velocities of Eq. (5).  Writes xs, vs: [3S] (prec) and keeps d_j and
+ * the velocities entering the collision in the workspace. */
+int sites_thermalize(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, double kT,
+                     int32_t thermalize, uint64_t seed, const uint64_t *d_step, void *xs,
+                     void *vs, void *ws, size_t ws_bytes);
+
+/* Momentum transfer, Sec. II.B.2: J_b = sum_j m_j (v_j - v_j^pre),
+ * K_b = sum_j d_j x m_j (v_j - v_j^pre) in site order, double.  J, K: [3B]. */
+int sites_to_body(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const void *vs,
+                  void *ws, size_t ws_bytes, double *J, double *K);
+
+/* Body update: P += J, p += 2 S(q)(0, A^T K); then one quaternion velocity-
+ * Verlet step (Miller et al., cited in Sec. II.B.2): half kick with the stored
+ * F, T; drift R += dt P/M (wrap, image); NO_SQUISH free rotation about body
+ * axes 3,2,1,2,3 for dt/2, dt/2, dt, dt/2, dt/2; new F, T from Eq. (1); half
+ * kick.  J, K may be NULL (no impulse). */
+int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const double *J,
+                   const double *K, const mpcd_wca *wca, double dt, void *ws, size_t ws_bytes);
+
+/* Evaluate F, T at the current positions (Eq. (1)); call once before the first
+ * step so the first half kick uses the right force. */
+int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca,
+                void *ws, size_t ws_bytes);
+
+/* *d_step += 1 on the device. */
+int mpcd_advance_step(void *stream, uint64_t *d_step);
+
+/* One whole step (the sequence above), then mpcd_advance_step. */
+int mpcd_step(void *stream, const mpcd_step_args *args);
+
+/* Capture nsteps calls of mpcd_step into a HIP graph (stream must not be the
+ * null stream); replay with mpcd_graph_launch; free with mpcd_graph_destroy. */
+int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, void **graph_exec);
+int mpcd_graph_launch(void *stream, void *graph_exec);
+int mpcd_graph_destroy(void *graph_exec);
+
+/* Synchronize the stream and copy the sticky status bits to *flags (host). */
+int mpcd_status(void *stream, const void *ws, size_t ws_bytes, uint32_t *flags);
+
+/* The HIP error code of the last MPCD_EHIP return (per thread). */
+int mpcd_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPCD_H */

@@ -1,0 +1,228 @@
+// detrand.hpp -- device-side deterministic primitives for the MPCD step.
+//
+// Counter-based random numbers (Philox4x64-10, Salmon et al., SC'11), a
+// project-written natural log (atanh series) and sin/cos (Taylor series after a
+// two-part pi/2 reduction), and the samplers built on them: the random grid
+// shift, Marsaglia-polar normals, the Marsaglia (1972) random unit axis and the
+// Marsaglia-Tsang (2000) gamma variate.  With contraction disabled
+// (-ffp-contract=off) every + - * / sqrt below is one correctly rounded IEEE
+// operation in the order written, so a host implementation of the same
+// definitions draws bit-identical numbers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpcd {
+
+enum : uint64_t { RNG_SHIFT = 0, RNG_AXIS = 1, RNG_THERMO = 2, RNG_SITE = 3 };
+constexpr int RNG_MAX_CALLS = 64;
+
+constexpr uint32_t ST_NONFINITE = 1u, ST_ESCAPE = 2u, ST_FIXOVF = 4u, ST_RNGLOOP = 8u;
+
+struct Words {
+    uint64_t w[4];
+};
+
+// Philox4x64-10: counter (c0..c3), key (k0, k1).
+__device__ __forceinline__ Words philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                            uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B97F4A7C15ull;
+            k1 += 0xBB67AE8584CAA73Bull;
+        }
+        const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+        const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0;
+        const uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    Words r;
+    r.w[0] = c0; r.w[1] = c1; r.w[2] = c2; r.w[3] = c3;
+    return r;
+}
+
+// Stream of (seed, purpose) at (step, entity, replica), call index `call`.
+__device__ __forceinline__ Words rng_draw(uint64_t seed, uint64_t purpose, uint64_t step,
+                                          uint64_t entity, uint64_t replica, uint64_t call)
+{
+    return philox4x64(step, entity, replica, call, seed, purpose);
+}
+
+__device__ __forceinline__ double unit53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
+
+// ln x = e ln2 + 2 atanh(t), x = f 2^e with f in (sqrt(2)/2, sqrt(2)], t = (f-1)/(f+1).
+__device__ inline double det_log(double x)
+{
+    if (x != x) return x;
+    if (x < 0.0) return __builtin_nan("");
+    if (x == 0.0) return -__builtin_inf();
+    if (x == __builtin_inf()) return x;
+    int adj = 0;
+    if (x < 0x1p-1022) {
+        x = x * 0x1p54;
+        adj = -54;
+    }
+    uint64_t bits = (uint64_t)__double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7ffu) - 1023 + adj;
+    bits = (bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull;
+    double f = __longlong_as_double((long long)bits);
+    if (f > 0x1.6a09e667f3bcdp+0) {
+        f = 0.5 * f;
+        e = e + 1;
+    }
+    const double t = (f - 1.0) / (f + 1.0);
+    const double t2 = t * t;
+    double p = 1.0 / 21.0;
+    p = p * t2 + 1.0 / 19.0;
+    p = p * t2 + 1.0 / 17.0;
+    p = p * t2 + 1.0 / 15.0;
+    p = p * t2 + 1.0 / 13.0;
+    p = p * t2 + 1.0 / 11.0;
+    p = p * t2 + 1.0 / 9.0;
+    p = p * t2 + 1.0 / 7.0;
+    p = p * t2 + 1.0 / 5.0;
+    p = p * t2 + 1.0 / 3.0;
+    p = p * t2 + 1.0;
+    const double de = (double)e;
+    const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
+    return de * ln2_hi + ((2.0 * t) * p + de * ln2_lo);
+}
+
+// sin and cos of th.
+__device__ inline void det_sincos(double th, double *s_out, double *c_out)
+{
+    const double pio2_hi = 0x1.921fb54400000p+0, pio2_lo = 0x1.0b4611a626331p-34;
+    const double kf = rint(th * 0x1.45f306dc9c883p-1);
+    const long long k = (long long)kf;
+    const double r = (th - kf * pio2_hi) - kf * pio2_lo;
+    const double r2 = r * r;
+    double ps = 1.0 / 355687428096000.0;
+    ps = ps * r2 - 1.0 / 1307674368000.0;
+    ps = ps * r2 + 1.0 / 6227020800.0;
+    ps = ps * r2 - 1.0 / 39916800.0;
+    ps = ps * r2 + 1.0 / 362880.0;
+    ps = ps * r2 - 1.0 / 5040.0;
+    ps = ps * r2 + 1.0 / 120.0;
+    ps = ps * r2 - 1.0 / 6.0;
+    const double sn = r + (r * r2) * ps;
+    double pc = 1.0 / 6402373705728000.0;
+    pc = pc * r2 - 1.0 / 20922789888000.0;
+    pc = pc * r2 + 1.0 / 87178291200.0;
+    pc = pc * r2 - 1.0 / 479001600.0;
+    pc = pc * r2 + 1.0 / 3628800.0;
+    pc = pc * r2 - 1.0 / 40320.0;
+    pc = pc * r2 + 1.0 / 720.0;
+    pc = pc * r2 - 1.0 / 24.0;
+    pc = pc * r2 + 1.0 / 2.0;
+    const double cs = 1.0 - r2 * pc;
+    switch ((int)(k & 3)) {
+    case 0: *s_out = sn; *c_out = cs; break;
+    case 1: *s_out = cs; *c_out = -sn; break;
+    case 2: *s_out = -sn; *c_out = -cs; break;
+    default: *s_out = -cs; *c_out = sn; break;
+    }
+}
+
+// Grid shift component k in [-a/2, a/2) on a 2^-24 a grid.
+__device__ __forceinline__ double shift_component(uint64_t w, double a)
+{
+    const double q = (double)(int64_t)(w >> 40) - 8388608.0;
+    return (q * 0x1p-24) * a;
+}
+
+// Three standard normals (polar method; pairs (w0,w1) then (w2,w3) of
+// successive calls; the spare normal of the last pair is dropped).
+__device__ inline uint32_t site_normals(uint64_t seed, uint64_t step, uint64_t site, uint64_t replica,
+                                        double z[3])
+{
+    int have = 0;
+    for (int call = 0; call < RNG_MAX_CALLS && have < 3; ++call) {
+        const Words w = rng_draw(seed, RNG_SITE, step, site, replica, (uint64_t)call);
+#pragma unroll
+        for (int pair = 0; pair < 2; ++pair) {
+            if (have >= 3) break;
+            const double x1 = 2.0 * unit53(w.w[2 * pair]) - 1.0;
+            const double x2 = 2.0 * unit53(w.w[2 * pair + 1]) - 1.0;
+            const double t = x1 * x1 + x2 * x2;
+            if (t > 0.0 && t < 1.0) {
+                const double f = sqrt((-2.0 * det_log(t)) / t);
+                z[have] = x1 * f;
+                have = have + 1;
+                if (have < 3) {
+                    z[have] = x2 * f;
+                    have = have + 1;
+                }
+            }
+        }
+    }
+    if (have < 3) {
+        for (int i = have; i < 3; ++i) z[i] = 0.0;
+        return ST_RNGLOOP;
+    }
+    return 0;
+}
+
+// Uniform random unit vector: accept (x1,x2) inside the unit disk,
+// n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1-2t).
+__device__ inline uint32_t cell_axis(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
+                                     double n[3])
+{
+    for (int call = 0; call < RNG_MAX_CALLS; ++call) {
+        const Words w = rng_draw(seed, RNG_AXIS, step, cell, replica, (uint64_t)call);
+#pragma unroll
+        for (int pair = 0; pair < 2; ++pair) {
+            const double x1 = 2.0 * unit53(w.w[2 * pair]) - 1.0;
+            const double x2 = 2.0 * unit53(w.w[2 * pair + 1]) - 1.0;
+            const double t = x1 * x1 + x2 * x2;
+            if (t > 0.0 && t < 1.0) {
+                const double r = sqrt(1.0 - t);
+                n[0] = (2.0 * x1) * r;
+                n[1] = (2.0 * x2) * r;
+                n[2] = 1.0 - 2.0 * t;
+                return 0;
+            }
+        }
+    }
+    n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+    return ST_RNGLOOP;
+}
+
+// Gamma(shape k >= 1) variate by Marsaglia-Tsang; iteration i uses call i.
+__device__ inline uint32_t gamma_variate(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
+                                         double k, double *g)
+{
+    const double d = k - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    for (int call = 0; call < RNG_MAX_CALLS; ++call) {
+        const Words w = rng_draw(seed, RNG_THERMO, step, cell, replica, (uint64_t)call);
+        const double x1 = 2.0 * unit53(w.w[0]) - 1.0;
+        const double x2 = 2.0 * unit53(w.w[1]) - 1.0;
+        const double t = x1 * x1 + x2 * x2;
+        if (!(t > 0.0 && t < 1.0)) continue;
+        const double z = x1 * sqrt((-2.0 * det_log(t)) / t);
+        double v = 1.0 + c * z;
+        if (v <= 0.0) continue;
+        v = (v * v) * v;
+        const double u = unit53(w.w[2]);
+        const double z2 = z * z;
+        if (u < 1.0 - 0.0331 * (z2 * z2)) {
+            *g = d * v;
+            return 0;
+        }
+        if (det_log(u) < (0.5 * z) * z + d * ((1.0 - v) + det_log(v))) {
+            *g = d * v;
+            return 0;
+        }
+    }
+    *g = d;
+    return ST_RNGLOOP;
+}
+
+}  // namespace mpcd

@@ -1,0 +1,103 @@
+"""ctypes binding of libmpcd.so (argument marshalling only).
+
+Every step of the MPCD path runs in the HIP kernels of libmpcd.so; this module
+loads the library, packs torch device tensors into the C-ABI structs and calls
+the entry points declared in include/mpcd.h with the same names.  There is no
+CPU fallback: loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpcd.so")
+
+MPCD_F64, MPCD_F32 = 0, 1
+FLAG_NONFINITE, FLAG_ESCAPE, FLAG_FIXOVF, FLAG_RNGLOOP = 1, 2, 4, 8
+
+EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mpcd_stream", "mpcd_bin", "mpcd_collide",
+           "sites_thermalize", "sites_to_body", "body_integrate", "body_forces",
+           "mpcd_advance_step", "mpcd_step", "mpcd_graph_create", "mpcd_graph_launch",
+           "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error")
+
+vp = C.c_void_p
+
+
+class MpcdSys(C.Structure):
+    _fields_ = [("nsys", C.c_int32), ("prec", C.c_int32), ("a", C.c_double), ("m_solvent", C.c_double),
+                ("n_solvent", C.c_int64), ("n_sites", C.c_int64), ("n_bodies", C.c_int64),
+                ("n_cells", C.c_int64), ("replica0", C.c_uint64),
+                ("ncell", vp), ("solv_off", vp), ("cell_off", vp), ("body_off", vp)]
+
+
+class MpcdBodies(C.Structure):
+    _fields_ = [("pos", vp), ("image", vp), ("quat", vp), ("mom", vp), ("angmom", vp),
+                ("force", vp), ("torque", vp), ("mass", vp), ("inertia", vp),
+                ("site_off", vp), ("site_body", vp), ("site_d", vp), ("site_m", vp)]
+
+
+class MpcdWca(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("eps", C.c_double), ("sigma", C.c_double), ("delta", C.c_double)]
+
+
+class MpcdParams(C.Structure):
+    _fields_ = [("dt", C.c_double), ("cos_a", C.c_double), ("sin_a", C.c_double), ("kT", C.c_double),
+                ("kT_cell", C.c_double), ("seed", C.c_uint64), ("thermalize", C.c_int32),
+                ("fuse_stream", C.c_int32), ("wca", MpcdWca)]
+
+
+class MpcdStepArgs(C.Structure):
+    _fields_ = [("sys", C.POINTER(MpcdSys)), ("bodies", MpcdBodies), ("x", vp), ("v", vp), ("tag", vp),
+                ("xs", vp), ("vs", vp), ("J", vp), ("K", vp), ("d_step", vp), ("ws", vp),
+                ("ws_bytes", C.c_size_t), ("par", MpcdParams)]
+
+
+_lib = None
+
+
+class MpcdError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH):
+    """Load libmpcd.so.  Raises if it is missing: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MpcdError("libmpcd.so not built (%s); run __graft_entry__.build()" % path)
+    L = C.CDLL(path)
+    sp, bp, wp = C.POINTER(MpcdSys), C.POINTER(MpcdBodies), C.POINTER(MpcdWca)
+    sz, dbl, u64, i32 = C.c_size_t, C.c_double, C.c_uint64, C.c_int32
+    sig = {
+        "mpcd_workspace_bytes": (sz, [sp]),
+        "mpcd_workspace_offsets": (C.c_int, [sp, C.POINTER(C.c_int64)]),
+        "mpcd_ws_init": (C.c_int, [vp, sp, vp, sz]),
+        "mpcd_stream": (C.c_int, [vp, sp, vp, vp, dbl, vp, sz]),
+        "mpcd_bin": (C.c_int, [vp, sp, vp, vp, bp, u64, vp, vp, sz]),
+        "mpcd_collide": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, u64, vp, vp, sz, vp, dbl]),
+        "sites_thermalize": (C.c_int, [vp, sp, bp, dbl, i32, u64, vp, vp, vp, vp, sz]),
+        "sites_to_body": (C.c_int, [vp, sp, bp, vp, vp, sz, vp, vp]),
+        "body_integrate": (C.c_int, [vp, sp, bp, vp, vp, wp, dbl, vp, sz]),
+        "body_forces": (C.c_int, [vp, sp, bp, wp, vp, sz]),
+        "mpcd_advance_step": (C.c_int, [vp, vp]),
+        "mpcd_step": (C.c_int, [vp, C.POINTER(MpcdStepArgs)]),
+        "mpcd_graph_create": (C.c_int, [vp, C.POINTER(MpcdStepArgs), i32, C.POINTER(vp)]),
+        "mpcd_graph_launch": (C.c_int, [vp, vp]),
+        "mpcd_graph_destroy": (C.c_int, [vp]),
+        "mpcd_status": (C.c_int, [vp, vp, sz, C.POINTER(C.c_uint32)]),
+        "mpcd_last_hip_error": (C.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str = "mpcd call"):
+    if rc != 0:
+        hip = load().mpcd_last_hip_error()
+        raise MpcdError("%s failed: rc=%d (hip error %d)" % (what, rc, hip))

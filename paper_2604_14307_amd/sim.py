@@ -1,0 +1,244 @@
+"""Device-resident system state and calls into libmpcd.so.
+
+``GPUSystem`` packs one or more independent periodic systems (workload dicts
+from :mod:`paper_2604_14307_amd.workloads`) into torch device tensors, owns the
+workspace and the device step counter, and exposes each C-ABI entry point as a
+method.  PyTorch provides device memory and the stream; all arithmetic of the
+step runs in the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import lib as L
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+class GPUSystem:
+    def __init__(self, systems, params: dict, prec: str = "f64", replica0: int = 0,
+                 device: str = "cuda:0", fuse_stream: bool = True):
+        self.lib = L.load()
+        if isinstance(systems, dict):
+            systems = [systems]
+        self.nsys = len(systems)
+        self.device = torch.device(device)
+        self.prec = L.MPCD_F64 if prec == "f64" else L.MPCD_F32
+        self.real = torch.float64 if self.prec == L.MPCD_F64 else torch.float32
+        self.params = dict(params)
+        a = float(systems[0]["a"])
+        m = float(systems[0]["m"])
+        for s in systems:
+            if float(s["a"]) != a or float(s["m"]) != m:
+                raise ValueError("all systems must share the cell edge and solvent mass")
+        dev = self.device
+        ncell = np.array([s["ncell"] for s in systems], dtype=np.int32).reshape(-1)
+        Ns = [s["x"].shape[1] for s in systems]
+        Cs = [int(np.prod(s["ncell"])) for s in systems]
+        Bs = [s["M"].shape[0] for s in systems]
+        Ss = [s["sm"].shape[0] for s in systems]
+        self.N, self.C, self.B, self.S = sum(Ns), sum(Cs), sum(Bs), sum(Ss)
+        self.solv_off_h = np.concatenate([[0], np.cumsum(Ns)]).astype(np.int64)
+        self.cell_off_h = np.concatenate([[0], np.cumsum(Cs)]).astype(np.int64)
+        self.body_off_h = np.concatenate([[0], np.cumsum(Bs)]).astype(np.int64)
+        self.site_sys_off_h = np.concatenate([[0], np.cumsum(Ss)]).astype(np.int64)
+        self.ncell_h = ncell.reshape(-1, 3)
+
+        def cat(key, dtype, rows):
+            if sum(s[key].shape[-1] for s in systems) == 0:
+                return torch.zeros((rows, 0), dtype=dtype, device=dev)
+            arr = np.concatenate([np.asarray(s[key]).reshape(rows, -1) for s in systems], axis=1)
+            return torch.tensor(arr, dtype=dtype, device=dev).contiguous()
+
+        def cat1(key, dtype):
+            arr = np.concatenate([np.asarray(s[key]).reshape(-1) for s in systems])
+            return torch.tensor(arr, dtype=dtype, device=dev).contiguous()
+
+        self.ncell = torch.tensor(ncell, dtype=torch.int32, device=dev)
+        self.solv_off = torch.tensor(self.solv_off_h, device=dev)
+        self.cell_off = torch.tensor(self.cell_off_h, device=dev)
+        self.body_off = torch.tensor(self.body_off_h, device=dev)
+        self.x = cat("x", self.real, 3)
+        self.v = cat("v", self.real, 3)
+        self.tag = None
+        self.pos = cat("R", torch.float64, 3)
+        self.image = cat("img", torch.int32, 3)
+        self.quat = cat("q", torch.float64, 4)
+        self.mom = cat("P", torch.float64, 3)
+        self.angmom = cat("p", torch.float64, 4)
+        self.force = cat("F", torch.float64, 3)
+        self.torque = cat("T", torch.float64, 3)
+        self.mass = cat1("M", torch.float64)
+        self.inertia = cat("I", torch.float64, 3)
+        site_off, site_body, base, bbase = [0], [], 0, 0
+        for s in systems:
+            so = np.asarray(s["site_off"], dtype=np.int64)
+            site_off.extend((so[1:] + base).tolist())
+            for b in range(len(so) - 1):
+                site_body.extend([bbase + b] * int(so[b + 1] - so[b]))
+            base += int(so[-1])
+            bbase += len(so) - 1
+        self.site_off = torch.tensor(np.array(site_off, dtype=np.int64), device=dev)
+        self.site_body = torch.tensor(np.array(site_body, dtype=np.int32), device=dev)
+        self.site_d = cat("dhat", torch.float64, 3)
+        self.site_m = cat1("sm", torch.float64)
+        self.xs = torch.zeros((3, self.S), dtype=self.real, device=dev)
+        self.vs = torch.zeros((3, self.S), dtype=self.real, device=dev)
+        self.J = torch.zeros((3, self.B), dtype=torch.float64, device=dev)
+        self.K = torch.zeros((3, self.B), dtype=torch.float64, device=dev)
+        self.d_step = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        self.csys = L.MpcdSys(nsys=self.nsys, prec=self.prec, a=a, m_solvent=m, n_solvent=self.N,
+                              n_sites=self.S, n_bodies=self.B, n_cells=self.C, replica0=replica0,
+                              ncell=_ptr(self.ncell), solv_off=_ptr(self.solv_off),
+                              cell_off=_ptr(self.cell_off), body_off=_ptr(self.body_off))
+        self.ws_bytes = int(self.lib.mpcd_workspace_bytes(C.byref(self.csys)))
+        if self.ws_bytes == 0:
+            raise L.MpcdError("invalid system description")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        offs = (C.c_int64 * 8)()
+        L.check(self.lib.mpcd_workspace_offsets(C.byref(self.csys), offs), "mpcd_workspace_offsets")
+        self.ws_off = dict(zip(("status", "shift", "cell_start", "perm", "cellid", "slot", "site_d", "vpre"),
+                               [int(o) for o in offs]))
+        self.cbodies = L.MpcdBodies(
+            pos=_ptr(self.pos), image=_ptr(self.image), quat=_ptr(self.quat), mom=_ptr(self.mom),
+            angmom=_ptr(self.angmom), force=_ptr(self.force), torque=_ptr(self.torque),
+            mass=_ptr(self.mass), inertia=_ptr(self.inertia), site_off=_ptr(self.site_off),
+            site_body=_ptr(self.site_body), site_d=_ptr(self.site_d), site_m=_ptr(self.site_m))
+        w = self.params.get("wca", {"mode": 0})
+        self.cwca = L.MpcdWca(mode=int(w.get("mode", 0)), eps=float(w.get("eps", 0.0)),
+                              sigma=float(w.get("sigma", 0.0)), delta=float(w.get("delta", 0.0)))
+        self.fuse_stream = bool(fuse_stream)
+        L.check(self.lib.mpcd_ws_init(self.stream, C.byref(self.csys), _ptr(self.ws), self.ws_bytes),
+                "mpcd_ws_init")
+        self._graph = None
+
+    # ------------------------------------------------------------------
+    @property
+    def stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def set_step(self, n: int):
+        self.d_step.fill_(int(n))
+
+    def step_args(self) -> L.MpcdStepArgs:
+        p = self.params
+        par = L.MpcdParams(dt=p["dt"], cos_a=p["cos_a"], sin_a=p["sin_a"], kT=p["kT"], kT_cell=p["kT_cell"],
+                           seed=p["seed"], thermalize=int(p.get("thermalize", 1)),
+                           fuse_stream=int(self.fuse_stream), wca=self.cwca)
+        self._args = L.MpcdStepArgs(sys=C.pointer(self.csys), bodies=self.cbodies, x=_ptr(self.x), v=_ptr(self.v),
+                                    tag=_ptr(self.tag), xs=_ptr(self.xs), vs=_ptr(self.vs), J=_ptr(self.J),
+                                    K=_ptr(self.K), d_step=_ptr(self.d_step), ws=_ptr(self.ws),
+                                    ws_bytes=self.ws_bytes, par=par)
+        return self._args
+
+    # --- entry points -------------------------------------------------
+    def sites_thermalize(self):
+        p = self.params
+        L.check(self.lib.sites_thermalize(self.stream, C.byref(self.csys), C.byref(self.cbodies), p["kT"],
+                                          int(p.get("thermalize", 1)), p["seed"], _ptr(self.d_step),
+                                          _ptr(self.xs), _ptr(self.vs), _ptr(self.ws), self.ws_bytes),
+                "sites_thermalize")
+
+    def bin(self):
+        L.check(self.lib.mpcd_bin(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.xs),
+                                  C.byref(self.cbodies), self.params["seed"], _ptr(self.d_step),
+                                  _ptr(self.ws), self.ws_bytes), "mpcd_bin")
+
+    def collide(self, stream_x: bool = False):
+        p = self.params
+        L.check(self.lib.mpcd_collide(self.stream, C.byref(self.csys), _ptr(self.v), _ptr(self.tag),
+                                      _ptr(self.vs), C.byref(self.cbodies), p["cos_a"], p["sin_a"],
+                                      p["kT_cell"], p["seed"], _ptr(self.d_step), _ptr(self.ws),
+                                      self.ws_bytes, _ptr(self.x) if stream_x else C.c_void_p(0), p["dt"]),
+                "mpcd_collide")
+
+    def sites_to_body(self):
+        L.check(self.lib.sites_to_body(self.stream, C.byref(self.csys), C.byref(self.cbodies), _ptr(self.vs),
+                                       _ptr(self.ws), self.ws_bytes, _ptr(self.J), _ptr(self.K)),
+                "sites_to_body")
+
+    def body_forces(self):
+        L.check(self.lib.body_forces(self.stream, C.byref(self.csys), C.byref(self.cbodies),
+                                     C.byref(self.cwca), _ptr(self.ws), self.ws_bytes), "body_forces")
+
+    def body_integrate(self, impulse: bool = True):
+        L.check(self.lib.body_integrate(self.stream, C.byref(self.csys), C.byref(self.cbodies),
+                                        _ptr(self.J) if impulse else C.c_void_p(0),
+                                        _ptr(self.K) if impulse else C.c_void_p(0), C.byref(self.cwca),
+                                        self.params["dt"], _ptr(self.ws), self.ws_bytes), "body_integrate")
+
+    def stream_solvent(self):
+        L.check(self.lib.mpcd_stream(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.v),
+                                     self.params["dt"], _ptr(self.ws), self.ws_bytes), "mpcd_stream")
+
+    def advance(self):
+        L.check(self.lib.mpcd_advance_step(self.stream, _ptr(self.d_step)), "mpcd_advance_step")
+
+    def step(self, nsteps: int = 1):
+        args = self.step_args()
+        for _ in range(nsteps):
+            L.check(self.lib.mpcd_step(self.stream, C.byref(args)), "mpcd_step")
+
+    def graph(self, nsteps: int):
+        """Capture nsteps steps into a HIP graph (on a side stream)."""
+        self.release_graph()
+        args = self.step_args()
+        h = C.c_void_p(0)
+        L.check(self.lib.mpcd_graph_create(self.stream, C.byref(args), int(nsteps), C.byref(h)),
+                "mpcd_graph_create")
+        self._graph = h
+        self._graph_args = args
+        return h
+
+    def graph_launch(self):
+        L.check(self.lib.mpcd_graph_launch(self.stream, self._graph), "mpcd_graph_launch")
+
+    def release_graph(self):
+        if self._graph is not None:
+            self.lib.mpcd_graph_destroy(self._graph)
+            self._graph = None
+
+    def status(self) -> int:
+        f = C.c_uint32(0)
+        L.check(self.lib.mpcd_status(self.stream, _ptr(self.ws), self.ws_bytes, C.byref(f)), "mpcd_status")
+        return int(f.value)
+
+    # --- inspection -----------------------------------------------------
+    def ws_view(self, key, dtype, count):
+        off = self.ws_off[key]
+        nbytes = count * torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off:off + nbytes].view(dtype)
+
+    def bins(self):
+        cs = self.ws_view("cell_start", torch.int32, self.C + 1).cpu().numpy().astype(np.int64)
+        perm = self.ws_view("perm", torch.int32, self.N + self.S).cpu().numpy().astype(np.int64)
+        shift = self.ws_view("shift", torch.float64, 3 * self.nsys).cpu().numpy().reshape(-1, 3)
+        return cs, perm, shift
+
+    def site_state(self):
+        d = self.ws_view("site_d", torch.float64, 3 * self.S).cpu().numpy().reshape(3, -1)
+        vpre = self.ws_view("vpre", torch.float64, 3 * self.S).cpu().numpy().reshape(3, -1)
+        return d, vpre
+
+    def download(self):
+        """Per-system dicts of numpy float64 arrays in the oracle's layout."""
+        torch.cuda.synchronize(self.device)
+        g = {k: getattr(self, k).detach().cpu().numpy() for k in
+             ("x", "v", "pos", "image", "quat", "mom", "angmom", "force", "torque", "xs", "vs", "J", "K")}
+        out = []
+        for r in range(self.nsys):
+            n0, n1 = self.solv_off_h[r], self.solv_off_h[r + 1]
+            b0, b1 = self.body_off_h[r], self.body_off_h[r + 1]
+            s0, s1 = self.site_sys_off_h[r], self.site_sys_off_h[r + 1]
+            out.append(dict(x=g["x"][:, n0:n1].astype(np.float64), v=g["v"][:, n0:n1].astype(np.float64),
+                            R=g["pos"][:, b0:b1], img=g["image"][:, b0:b1], q=g["quat"][:, b0:b1],
+                            P=g["mom"][:, b0:b1], p=g["angmom"][:, b0:b1], F=g["force"][:, b0:b1],
+                            T=g["torque"][:, b0:b1], xs=g["xs"][:, s0:s1].astype(np.float64),
+                            vs=g["vs"][:, s0:s1].astype(np.float64), J=g["J"][:, b0:b1], K=g["K"][:, b0:b1]))
+        return out

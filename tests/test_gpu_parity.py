@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+FP64: bit-exact, per stage and per step (both sides evaluate the same
+operations in the same order with contraction off and draw the same Philox
+numbers).  FP32: from an identical (FP32-representable) state, one step is
+within 1e-5 relative velocity error of the FP64 oracle, excluding cells whose
+membership differs because FP32 rounding of x - s moved a particle across a
+cell boundary (counted and bounded).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_14307_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def gpu_system(*a, **k):
+    from paper_2604_14307_amd.sim import GPUSystem
+    return GPUSystem(*a, **k)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+STATE_KEYS = ("x", "v", "R", "img", "q", "P", "p", "F", "T", "xs", "vs")
+
+
+def assert_same(o, gd, keys=STATE_KEYS, where=""):
+    for k in keys:
+        a = getattr(o, k)
+        b = gd[k]
+        assert a.shape == b.shape, (k, a.shape, b.shape)
+        if not np.array_equal(a, b):
+            diff = np.argwhere(a != b)
+            i = tuple(diff[0])
+            raise AssertionError("%s: %s differs at %s (%d elements): oracle %r gpu %r"
+                                 % (where, k, i, len(diff), a[i], b[i]))
+
+
+def run_parity(wl, par, nsteps, fuse=True, check_every=1, step0=0):
+    o = oracle.OracleSystem(wl, par)
+    g = gpu_system(wl, par, prec="f64", fuse_stream=fuse)
+    o.body_forces()
+    g.body_forces()
+    g.set_step(step0)
+    assert_same(o, g.download()[0], ("F", "T"), "initial forces")
+    for n in range(nsteps):
+        assert o.step(step0 + n) == 0
+        g.step(1)
+        if (n + 1) % check_every == 0 or n == nsteps - 1:
+            assert_same(o, g.download()[0], where="step %d" % (step0 + n))
+    assert g.status() == 0
+    return o, g
+
+
+# ---------------------------------------------------------------------------
+
+def test_device_double_sqrt_and_division_are_correctly_rounded():
+    """The FP64 bit-exactness relies on IEEE correctly rounded / and sqrt."""
+    rng = np.random.default_rng(0)
+    n = 1 << 24
+    for _ in range(4):
+        a = np.exp(rng.uniform(-50, 50, n)) * rng.choice([-1.0, 1.0], n)
+        b = np.exp(rng.uniform(-50, 50, n))
+        ta, tb = torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda")
+        assert np.array_equal((ta / tb).cpu().numpy(), a / b)
+        assert np.array_equal(torch.sqrt(tb).cpu().numpy(), np.sqrt(b))
+
+
+def test_stages_bit_exact_single_sphere():
+    wl, par, _ = W.config(0, kT_cell=1.0)
+    o = oracle.OracleSystem(wl, par)
+    g = gpu_system(wl, par, prec="f64")
+    step = 7
+    g.set_step(step)
+    say("thermalize")
+    o.sites_thermalize(step)
+    g.sites_thermalize()
+    gd = g.download()[0]
+    assert_same(o, gd, ("xs", "vs"), "thermalize")
+    d, vpre = g.site_state()
+    assert np.array_equal(d, o.d) and np.array_equal(vpre, o.vpre)
+    say("bin")
+    sh = o.shift(step)
+    cell, cs, mem, _ = o.bin(sh)
+    g.bin()
+    gcs, gperm, gshift = g.bins()
+    assert np.array_equal(gshift[0], sh)
+    assert np.array_equal(gcs, cs)
+    for c in range(o.C):
+        assert np.array_equal(np.sort(gperm[gcs[c]:gcs[c + 1]]), mem[cs[c]:cs[c + 1]])
+    say("collide")
+    o.collide(step, cs, mem)
+    g.collide(stream_x=False)
+    assert_same(o, g.download()[0], ("v", "vs"), "collide")
+    say("transfer")
+    J, K = o.sites_to_body()
+    g.sites_to_body()
+    gd = g.download()[0]
+    assert np.array_equal(J, gd["J"]) and np.array_equal(K, gd["K"])
+    say("stream")
+    o.stream()
+    g.stream_solvent()
+    assert_same(o, g.download()[0], ("x",), "stream")
+    say("bodies")
+    o.body_integrate(J, K)
+    g.body_integrate()
+    assert_same(o, g.download()[0], ("R", "img", "q", "P", "p", "F", "T"), "body_integrate")
+    assert g.status() == 0
+
+
+@pytest.mark.parametrize("kT_cell", [1.0, 0.0])
+def test_single_sphere_100_steps_bit_exact(kT_cell):
+    wl, par, meta = W.config(0, kT_cell=kT_cell)
+    say("single sphere kT_cell=%g" % kT_cell)
+    run_parity(wl, par, meta["steps"])
+
+
+def test_unfused_stream_matches_fused():
+    wl, par, _ = W.config(0)
+    say("unfused")
+    run_parity(wl, par, 20, fuse=False)
+
+
+def test_naive_scheme_bit_exact():
+    wl, par, _ = W.config(0)
+    par = dict(par, thermalize=0)
+    run_parity(wl, par, 20)
+
+
+def test_suspension_with_wca_bit_exact():
+    wl = W.suspension((12, 12, 12), 5, 6, 2.0, 60, 5.0, seed=31)
+    par = W.srd_params(31, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
+    say("suspension 12^3, 6 bodies")
+    run_parity(wl, par, 40, check_every=5)
+
+
+def test_ragged_box_and_density_bit_exact():
+    rng = np.random.default_rng(5)
+    tpl = W.sphere_template(1.5, 40, 5.0)
+    wl = W.make_system((7, 9, 11), 3.7, [tpl, tpl], [(2.0, 3.0, 4.0), (5.0, 6.5, 8.0)],
+                       W.random_quaternions(rng, 2), rng)
+    par = W.srd_params(77, kT_cell=1.0, wca=W.wca_spheres(sigma=3.0))
+    say("ragged 7x9x11")
+    run_parity(wl, par, 30, check_every=3)
+
+
+def test_pure_solvent_and_sites_only():
+    rng = np.random.default_rng(6)
+    wl = W.make_system((6, 6, 6), 5, [], [], np.zeros((0, 4)), rng)
+    say("pure solvent")
+    run_parity(wl, W.srd_params(6), 10)
+    tpl = W.sphere_template(2.0, 80, 5.0)
+    wl = W.make_system((6, 6, 6), 0, [tpl], [(3.0, 3.0, 3.0)], np.array([[1.0, 0, 0, 0]]), rng)
+    say("sites only")
+    run_parity(wl, W.srd_params(7), 10)
+
+
+def test_empty_cells_and_crowded_cells():
+    """Density 0.5 leaves most cells empty or single; a dense clump makes cells
+    with more members than the LDS-ordered fast path holds (slow path)."""
+    rng = np.random.default_rng(8)
+    wl = W.make_system((8, 8, 8), 0.5, [], [], np.zeros((0, 4)), rng)
+    clump = np.array([[2.1], [2.2], [2.3]]) + 0.05 * rng.random((3, 60))
+    wl["x"] = np.concatenate([wl["x"], clump], axis=1)
+    wl["v"] = np.concatenate([wl["v"], 0.01 * rng.normal(size=(3, 60))], axis=1)
+    say("empty + crowded")
+    run_parity(wl, W.srd_params(8, kT_cell=1.0), 5)
+
+
+def test_batched_replicas_match_each_replica_alone():
+    systems, par, _ = W.batched_replicas(nrep=4, seed=9, lo=6, hi=10)
+    say("batched 4 replicas")
+    g = gpu_system(systems, par, prec="f64")
+    g.body_forces()
+    os_ = [oracle.OracleSystem(s, par, replica=r) for r, s in enumerate(systems)]
+    for o in os_:
+        o.body_forces()
+    for n in range(15):
+        for o in os_:
+            assert o.step(n) == 0
+        g.step(1)
+    gd = g.download()
+    for r, o in enumerate(os_):
+        assert_same(o, gd[r], where="replica %d" % r)
+    # replica 2 alone on the GPU with replica id 2 gives the same bits
+    g2 = gpu_system(systems[2], par, prec="f64", replica0=2)
+    g2.body_forces()
+    g2.step(15)
+    assert_same(os_[2], g2.download()[0], where="replica 2 alone")
+
+
+def test_graph_replay_matches_eager():
+    wl, par, _ = W.config(0)
+    say("graph")
+    ge = gpu_system(wl, par, prec="f64")
+    gg = gpu_system(wl, par, prec="f64")
+    for g in (ge, gg):
+        g.body_forces()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        gg.graph(5)
+        for rep in range(4):
+            gg.graph_launch()
+            torch.cuda.synchronize()
+            ge.step(5)
+            torch.cuda.synchronize()
+            a, b = ge.download()[0], gg.download()[0]
+            for k in STATE_KEYS:
+                assert np.array_equal(a[k], b[k]), (rep, k)
+        gg.release_graph()
+
+
+def test_full_size_suspension_bit_exact_few_steps():
+    """60^3 cells, 1.08M solvent, 191 spheres x 200 sites, WCA: the benchmark
+    workload, checked bit for bit over 3 steps."""
+    wl, par, _ = W.config(1)
+    say("full size 60^3")
+    run_parity(wl, par, 3)
+
+
+# ---------------------------------------------------------------------------
+# FP32 form
+
+def cells_of(cs, perm, nt):
+    cell = np.empty(nt, dtype=np.int64)
+    for c in range(len(cs) - 1):
+        cell[perm[cs[c]:cs[c + 1]]] = c
+    return cell
+
+
+def fp32_one_step(wl, par, warm=3):
+    g = gpu_system(wl, par, prec="f32")
+    g.body_forces()
+    g.step(warm)
+    s0 = g.download()[0]
+    step = warm
+    # oracle state = the FP32 state upcast (exactly representable)
+    wl2 = dict(wl)
+    for k in ("x", "v", "R", "img", "q", "P", "p", "F", "T"):
+        wl2[k] = s0[k]
+    o = oracle.OracleSystem(wl2, par)
+    o.sites_thermalize(step)
+    cell64, cs64, mem64, _ = o.bin(o.shift(step))
+    o.collide(step, cs64, mem64)
+    J, K = o.sites_to_body()
+    o.stream()
+    o.body_integrate(J, K)
+    g.sites_thermalize()
+    g.bin()
+    gcs, gperm, _ = g.bins()
+    g.collide(stream_x=True)
+    g.sites_to_body()
+    g.body_integrate()
+    g.advance()
+    s1 = g.download()[0]
+    nt = o.N + o.S
+    cell32 = cells_of(gcs, gperm, nt)
+    bad_cells = np.unique(np.concatenate([cell64[cell32 != cell64], cell32[cell32 != cell64]]))
+    bad = np.isin(cell64, bad_cells) | np.isin(cell32, bad_cells)
+    v64 = np.concatenate([o.v, o.vs], axis=1)[:, ~bad]
+    v32 = np.concatenate([s1["v"], s1["vs"]], axis=1)[:, ~bad]
+    rel = np.linalg.norm(v32 - v64) / np.linalg.norm(v64)
+    return rel, int(bad.sum()), nt, g, o, s1
+
+
+def test_fp32_one_step_within_1e5_of_fp64_oracle():
+    wl, par, _ = W.config(0)
+    rel, nbad, nt, g, o, s1 = fp32_one_step(wl, par)
+    say("fp32 rel err %.3e, excluded %d of %d" % (rel, nbad, nt))
+    assert rel <= 1e-5
+    assert nbad <= 0.01 * nt
+    assert g.status() == 0
+    # the body update is FP64 from (almost) identical impulses
+    assert np.allclose(s1["P"], o.P, rtol=1e-4, atol=1e-6)
+
+
+def test_fp32_full_size_within_1e5():
+    wl, par, _ = W.config(1)
+    rel, nbad, nt, g, o, s1 = fp32_one_step(wl, par, warm=2)
+    say("fp32 full size rel err %.3e, excluded %d of %d" % (rel, nbad, nt))
+    assert rel <= 1e-5
+    assert nbad <= 0.001 * nt
