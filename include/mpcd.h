@@ -69,6 +69,7 @@ enum {
 #define MPCD_FLAG_ESCAPE 2u    /* a particle moved more than one box length    */
 #define MPCD_FLAG_FIXOVF 4u    /* FP32 path: fixed-point cell sum overflow     */
 #define MPCD_FLAG_RNGLOOP 8u   /* a rejection sampler used all 64 Philox calls */
+#define MPCD_FLAG_BINERR 16u   /* inconsistent binning counts (particles dropped) */
 
 /* Geometry and sizes of nsys independent periodic boxes of cubic cells. */
 typedef struct {
@@ -134,6 +135,7 @@ typedef struct {
     void *ws;              /* workspace                                         */
     size_t ws_bytes;
     mpcd_params par;
+    int32_t reorder_every; /* graphs: mpcd_reorder after every this many steps (0: never) */
 } mpcd_step_args;
 
 /* Workspace bytes for sys (host-side sizes only).  The workspace holds the cell
@@ -209,6 +211,14 @@ int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies,
  * step so the first half kick uses the right force. */
 int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca,
                 void *ws, size_t ws_bytes);
+
+/* Storage reorder: permute the solvent (x, v and identity tags, [3N], [3N],
+ * [N]) into the order of the last mpcd_bin (grouped by cell), so that the
+ * gathers of the next steps stay local as the solvent diffuses.  Changes only
+ * where particles are stored: with tags, every result is the same as without
+ * the reorder.  tag must be non-NULL (initially 0..N-1 in system order).
+ * Uses the workspace's staging area; costs two passes over the solvent. */
+int mpcd_reorder(void *stream, const mpcd_sys *sys, void *x, void *v, int32_t *tag, void *ws, size_t ws_bytes);
 
 /* *d_step += 1 on the device. */
 int mpcd_advance_step(void *stream, uint64_t *d_step);

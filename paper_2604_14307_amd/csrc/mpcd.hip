@@ -234,9 +234,36 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20)
 // ---------------------------------------------------------------------------
 // Workspace layout (identical for every call with the same sizes)
 
+// Collision tiles: a block owns cpb consecutive cells (a power of two, at
+// most one per thread), sized so that a tile holds on average at most 70% of
+// the block's LDS member capacity (TILE_T * items).  Binning counts particles
+// per tile first, so the tile shape is fixed by the system sizes and precision.
+constexpr int TILE_T = 256;
+constexpr int ITEMS_F64 = 2, ITEMS_F32 = 4;
+
+struct TileCfg {
+    int cpb, cpb_shift, cap, ntiles;
+};
+
+TileCfg tile_config(const mpcd_sys *s)
+{
+    TileCfg T;
+    const bool f64 = s->prec == MPCD_F64;
+    T.cap = TILE_T * (f64 ? ITEMS_F64 : ITEMS_F32);
+    const double per_cell = (double)(s->n_solvent + s->n_sites) / (double)s->n_cells;
+    int cpb = TILE_T, sh = 8;
+    while (cpb > 8 && (double)cpb * per_cell > 0.7 * T.cap) {
+        cpb >>= 1;
+        --sh;
+    }
+    T.cpb = cpb;
+    T.cpb_shift = sh;
+    T.ntiles = (int)((s->n_cells + cpb - 1) / cpb);
+    return T;
+}
+
 struct Layout {
-    size_t status, shift, counts, cell_start, cellid, slot, perm, partial, site_d, vpre, body_dv,
-        body_dw, total;
+    size_t status, shift, counts, partial, cell_start, cellid, slot, perm, draws, site_d, vpre, rtmp, total;
 };
 
 constexpr int SCAN_T = 1024, SCAN_V = 4, SCAN_TILE = SCAN_T * SCAN_V;
@@ -251,19 +278,22 @@ Layout layout_of(const mpcd_sys *s)
         return o;
     };
     const int64_t NT = s->n_solvent + s->n_sites;
-    const int64_t nb = (s->n_cells + SCAN_TILE - 1) / SCAN_TILE;
+    const int64_t nbc = (s->n_cells + SCAN_TILE - 1) / SCAN_TILE, nbp = (NT + SCAN_TILE - 1) / SCAN_TILE;
+    const int64_t nb = nbc > nbp ? nbc : nbp;
     L.status = take(256);
     L.shift = take(sizeof(double) * 3 * (size_t)s->nsys);
     L.counts = take(sizeof(int32_t) * (size_t)s->n_cells);
+    L.partial = take(sizeof(int32_t) * (size_t)(nb + 1));
     L.cell_start = take(sizeof(int32_t) * (size_t)(s->n_cells + 1));
     L.cellid = take(sizeof(int32_t) * (size_t)NT);
     L.slot = take(sizeof(int32_t) * (size_t)NT);
     L.perm = take(sizeof(int32_t) * (size_t)NT);
-    L.partial = take(sizeof(int32_t) * (size_t)(nb + 1));
+    L.draws = take(sizeof(double) * 4 * (size_t)s->n_cells);
     L.site_d = take(sizeof(double) * 3 * (size_t)s->n_sites);
     L.vpre = take(sizeof(double) * 3 * (size_t)s->n_sites);
-    L.body_dv = take(sizeof(double) * 3 * (size_t)s->n_bodies);
-    L.body_dw = take(sizeof(double) * 3 * (size_t)s->n_bodies);
+    // reorder staging: positions and velocities (prec) and tags of the solvent
+    const size_t es = s->prec == MPCD_F64 ? sizeof(double) : sizeof(float);
+    L.rtmp = take(6 * es * (size_t)s->n_solvent + sizeof(int32_t) * (size_t)s->n_solvent);
     L.total = off;
     return L;
 }
@@ -325,37 +355,118 @@ __global__ void k_shift(SysDev s, uint64_t seed, const uint64_t *d_step, double 
     for (int k = 0; k < 3; ++k) shift[3 * r + k] = shift_component(w.w[k], s.a);
 }
 
+// Blocks are remapped so that each of the 8 XCDs (own L2 each) works on a
+// contiguous range of tiles/chunks.
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ int tile_of_block(int ntiles)
+{
+    const int per = (ntiles + NXCD - 1) / NXCD;
+    return (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+}
+
+inline unsigned xcd_grid(int64_t ntiles)
+{
+    const int64_t per = (ntiles + NXCD - 1) / NXCD;
+    return (unsigned)(per * NXCD);
+}
+
+// Per-cell random draws: the collision axis and, with the thermostat, the
+// Gamma(3(n-1)/2) variate for the cell's member count n, stored as
+// draws[0..2][C] and draws[3][C].  Cells with fewer than two members draw
+// nothing.  (Philox4x64 is a long chain of quarter-rate 64-bit multiplies, so
+// the draws run in high-occupancy kernels rather than inside the collision.)
+__device__ __forceinline__ void draw_cell(const SysDev &s, uint64_t seed, double kT_cell, uint64_t step, int64_t gc,
+                                          int n, double *draws, uint32_t &st)
+{
+    if (n < 2) return;
+    const int64_t C = s.C;
+    const int r = find_sys(s.cell_off, s.nsys, gc);
+    const uint64_t cl = (uint64_t)(gc - s.cell_off[r]);
+    const uint64_t rep = s.replica0 + (uint64_t)r;
+    double nax[3];
+    st |= cell_axis(seed, step, cl, rep, nax);
+    draws[gc] = nax[0];
+    draws[C + gc] = nax[1];
+    draws[2 * C + gc] = nax[2];
+    if (kT_cell > 0.0) {
+        double g;
+        st |= gamma_variate(seed, step, cl, rep, 0.5 * (double)(3 * (n - 1)), &g);
+        draws[3 * C + gc] = g;
+    }
+}
+
+// Binning: atomic counting sort by cell.
+//  1. k_bin_count: cell of every particle and its slot in the cell.  A block
+//     covers BIN_T * BIN_ITEMS consecutive particles; each wave keeps the
+//     atomics of its BIN_ITEMS groups of 64 in flight together, and lanes
+//     whose consecutive particles share a cell (storage ordered by cell) take
+//     their slots with one atomic per run.  Device-scope atomics are
+//     performed beyond the per-XCD L2s on MI355X, so their count and their
+//     spread over many addresses set the cost.
+//  2. k_scan_reduce / k_scan_down: exclusive scan of the counts -> cell_start
+//     (each block adds the earlier tile totals itself) and clears the counts.
+//  3. k_bin_scatter: perm[cell_start[cell] + slot] = particle.
+constexpr int BIN_T = 256, BIN_ITEMS = 4, BIN_CHUNK = BIN_T * BIN_ITEMS;
+
 template <typename Real>
-__global__ void k_bin_count(SysDev s, const Real *x, const Real *xs, const int32_t *site_body,
-                            const double *shift, int32_t *counts, int32_t *cellid, int32_t *slot,
-                            uint32_t *status)
+__global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, const Real *xs,
+                                                     const int32_t *site_body, const double *shift,
+                                                     int32_t *counts, int32_t *cellid, int32_t *slot,
+                                                     uint32_t *status)
 {
     uint32_t st = 0;
     const int64_t NT = s.N + s.S;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < NT;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int r;
-        Real p0, p1, p2;
-        if (k < s.N) {
-            r = find_sys(s.solv_off, s.nsys, k);
-            p0 = x[k]; p1 = x[s.N + k]; p2 = x[2 * s.N + k];
-        } else {
-            const int64_t j = k - s.N;
-            r = find_sys(s.body_off, s.nsys, (int64_t)site_body[j]);
-            p0 = xs[j]; p1 = xs[s.S + j]; p2 = xs[2 * s.S + j];
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = (int64_t)blockIdx.x * BIN_CHUNK + (threadIdx.x & ~63);
+    int32_t gc[BIN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int64_t k = wbase + (int64_t)j * BIN_T + lane;
+        gc[j] = -1;
+        if (k < NT) {
+            int r;
+            Real p0, p1, p2;
+            if (k < s.N) {
+                r = find_sys(s.solv_off, s.nsys, k);
+                p0 = x[k]; p1 = x[s.N + k]; p2 = x[2 * s.N + k];
+            } else {
+                const int64_t q = k - s.N;
+                r = find_sys(s.body_off, s.nsys, (int64_t)site_body[q]);
+                p0 = xs[q]; p1 = xs[s.S + q]; p2 = xs[2 * s.S + q];
+            }
+            const int nx = s.ncell[3 * r], ny = s.ncell[3 * r + 1], nz = s.ncell[3 * r + 2];
+            const int jx = axis_cell(p0, shift[3 * r], s.a, nx, st);
+            const int jy = axis_cell(p1, shift[3 * r + 1], s.a, ny, st);
+            const int jz = axis_cell(p2, shift[3 * r + 2], s.a, nz, st);
+            gc[j] = (int32_t)(s.cell_off[r] + ((int64_t)jz * ny + jy) * nx + jx);
         }
-        const int nx = s.ncell[3 * r], ny = s.ncell[3 * r + 1], nz = s.ncell[3 * r + 2];
-        const int jx = axis_cell(p0, shift[3 * r], s.a, nx, st);
-        const int jy = axis_cell(p1, shift[3 * r + 1], s.a, ny, st);
-        const int jz = axis_cell(p2, shift[3 * r + 2], s.a, nz, st);
-        const int64_t gc = s.cell_off[r] + ((int64_t)jz * ny + jy) * nx + jx;
-        slot[k] = atomicAdd(&counts[gc], 1);
-        cellid[k] = (int32_t)gc;
+    }
+    int hl[BIN_ITEMS], base[BIN_ITEMS];
+    const unsigned long long le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int32_t prev = __shfl_up(gc[j], 1, 64);
+        const bool head = (lane == 0) || (prev != gc[j]);
+        const unsigned long long heads = __ballot(head);
+        hl[j] = 63 - __clzll(heads & le);
+        const unsigned long long above = heads & ~le;
+        const int nh = above ? (__ffsll((long long)above) - 1) : 64;
+        base[j] = (head && gc[j] >= 0) ? atomicAdd(&counts[gc[j]], nh - hl[j]) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int b = __shfl(base[j], hl[j], 64);
+        const int64_t k = wbase + (int64_t)j * BIN_T + lane;
+        if (k < NT) {
+            slot[k] = b + (lane - hl[j]);
+            cellid[k] = gc[j];
+        }
     }
     flag(status, st);
 }
 
-// Block-wide exclusive scan of one value per thread (SCAN_T threads, wave64).
+// Block-wide exclusive scan of one value per thread (blockDim = SCAN_T, wave64).
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *total)
 {
     __shared__ int32_t wsum[SCAN_T / 64];
@@ -397,24 +508,21 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const int32_t *counts, i
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(SCAN_T) void k_scan_partials(int32_t *partial, int64_t nb)
-{
-    __shared__ int32_t tot;
-    int32_t carry = 0;
-    for (int64_t base = 0; base < nb; base += SCAN_T) {
-        const int64_t i = base + threadIdx.x;
-        const int32_t v = (i < nb) ? partial[i] : 0;
-        const int32_t ex = block_exclusive_scan(v, &tot);
-        if (i < nb) partial[i] = carry + ex;
-        carry += tot;
-        __syncthreads();
-    }
-}
-
+// Each block adds the totals of the earlier tiles itself, scans its tile into
+// cell_start and clears the counts for the next step.
 __global__ __launch_bounds__(SCAN_T) void k_scan_down(int32_t *counts, int64_t C, const int32_t *partial,
                                                       int32_t *cell_start, int32_t total)
 {
     __shared__ int32_t tot;
+    __shared__ int32_t pre;
+    int32_t carry = 0;
+    for (int64_t b0 = 0; b0 < (int64_t)blockIdx.x; b0 += SCAN_T) {
+        const int64_t i = b0 + threadIdx.x;
+        (void)block_exclusive_scan(i < (int64_t)blockIdx.x ? partial[i] : 0, &tot);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) pre = carry;
+    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
     int32_t c[SCAN_V];
     int32_t v = 0;
@@ -423,7 +531,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down(int32_t *counts, int64_t C
         c[i] = (base + i < C) ? counts[base + i] : 0;
         v += c[i];
     }
-    int32_t run = partial[blockIdx.x] + block_exclusive_scan(v, &tot);
+    int32_t run = pre + block_exclusive_scan(v, &tot);
 #pragma unroll
     for (int i = 0; i < SCAN_V; ++i) {
         if (base + i < C) {
@@ -435,12 +543,91 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down(int32_t *counts, int64_t C
     if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[C] = total;
 }
 
-__global__ void k_bin_scatter(int64_t NT, const int32_t *cellid, const int32_t *slot,
-                              const int32_t *cell_start, int32_t *perm)
+__global__ __launch_bounds__(BIN_T) void k_bin_scatter(int64_t NT, const int32_t *cellid, const int32_t *slot,
+                                                       const int32_t *cell_start, int32_t *perm, uint32_t *status)
 {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < NT;
-         k += (int64_t)gridDim.x * blockDim.x)
-        perm[cell_start[cellid[k]] + slot[k]] = (int32_t)k;
+    uint32_t st = 0;
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int64_t k = (int64_t)blockIdx.x * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
+        if (k < NT) {
+            const int64_t pos = (int64_t)cell_start[cellid[k]] + slot[k];
+            if (pos >= 0 && pos < NT) perm[pos] = (int32_t)k;
+            else st |= ST_BINERR;
+        }
+    }
+    flag(status, st);
+}
+
+// ---------------------------------------------------------------------------
+// Storage reorder: solvent particles into the order of the last binning (cell
+// order), carrying their identity tags.  Keeps gathers and atomics local as
+// the solvent diffuses; identities keep the FP64 summation order unchanged.
+
+__global__ __launch_bounds__(SCAN_T) void k_reorder_count(const int32_t *perm, int64_t NT, int64_t N, int32_t *partial)
+{
+    __shared__ int32_t tot;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
+    int32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_V; ++i)
+        if (base + i < NT && perm[base + i] < N) v += 1;
+    (void)block_exclusive_scan(v, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(SCAN_T) void k_reorder_gather(const int32_t *perm, int64_t NT, int64_t N,
+                                                           const int32_t *partial, const Real *x, const Real *v,
+                                                           const int32_t *tag, Real *tx, Real *tv, int32_t *ttag)
+{
+    __shared__ int32_t tot;
+    __shared__ int32_t pre;
+    int32_t carry = 0;
+    for (int64_t b0 = 0; b0 < (int64_t)blockIdx.x; b0 += SCAN_T) {
+        const int64_t i = b0 + threadIdx.x;
+        (void)block_exclusive_scan(i < (int64_t)blockIdx.x ? partial[i] : 0, &tot);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) pre = carry;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
+    int32_t k[SCAN_V];
+    int32_t v0 = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_V; ++i) {
+        k[i] = (base + i < NT) ? perm[base + i] : -1;
+        if (k[i] >= 0 && k[i] < N) v0 += 1;
+    }
+    int32_t dst = pre + block_exclusive_scan(v0, &tot);
+#pragma unroll
+    for (int i = 0; i < SCAN_V; ++i) {
+        if (k[i] >= 0 && k[i] < N) {
+            if (dst < N) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    tx[d * N + dst] = x[d * N + k[i]];
+                    tv[d * N + dst] = v[d * N + k[i]];
+                }
+                ttag[dst] = tag[k[i]];
+            }
+            dst += 1;
+        }
+    }
+}
+
+template <typename Real>
+__global__ void k_reorder_copy(int64_t N, Real *x, Real *v, int32_t *tag, const Real *tx, const Real *tv,
+                               const int32_t *ttag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            x[d * N + i] = tx[d * N + i];
+            v[d * N + i] = tv[d * N + i];
+        }
+        tag[i] = ttag[i];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -466,72 +653,78 @@ __device__ __forceinline__ Rot rotation(const double n[3], double ca, double sa)
     return o;
 }
 
-constexpr int COL_T = 128;   // cells per block (one lane per cell)
-constexpr int COL_MAXK = 32; // members ordered in LDS; larger cells use a slower path
-
 struct CollideArgs {
     SysDev s;
     const double *site_m;
     const int32_t *tag;
     const int32_t *cell_start, *perm;
+    const double *draws; // [4][C]: random axis (3) and thermostat gamma variate of each cell
     double cos_a, sin_a, kT_cell, dt;
     uint64_t seed;
     const uint64_t *d_step;
     uint32_t *status;
 };
 
-// FP64: cell sums in ascending identity (tag for solvent, N_total + site index
-// for sites), exactly as a sequential host loop.
-__global__ __launch_bounds__(COL_T) void k_collide_f64(CollideArgs A, double *v, double *vs, double *xstream)
+// Identity order key of particle k: solvent tag (or index), sites N_total + j.
+__device__ __forceinline__ uint32_t ident(const CollideArgs &A, int32_t k)
 {
-    __shared__ uint64_t skey[COL_MAXK * COL_T];
+    return (k < A.s.N && A.tag) ? (uint32_t)A.tag[k] : (uint32_t)k;
+}
+
+// Per-cell draws for the standalone collision entry point.
+__global__ void k_cell_draws(CollideArgs A, double *draws)
+{
     const SysDev &s = A.s;
-    const int t = threadIdx.x;
-    const int64_t gc = (int64_t)blockIdx.x * COL_T + t;
-    if (gc >= s.C) return;
+    uint32_t st = 0;
+    const uint64_t step = *A.d_step;
+    for (int64_t gc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gc < s.C; gc += (int64_t)gridDim.x * blockDim.x)
+        draw_cell(s, A.seed, A.kT_cell, step, gc, A.cell_start[gc + 1] - A.cell_start[gc], draws, st);
+    flag(A.status, st);
+}
+
+__device__ __forceinline__ void read_axis(const CollideArgs &A, int64_t gc, double nax[3])
+{
+    const int64_t C = A.s.C;
+    nax[0] = A.draws[gc];
+    nax[1] = A.draws[C + gc];
+    nax[2] = A.draws[2 * C + gc];
+}
+
+// lambda = sqrt(kT_cell g / E) when E > 0 (cell thermostat), else 1.
+__device__ __forceinline__ double thermostat_factor(const CollideArgs &A, int64_t gc, double E)
+{
+    if (!(E > 0.0)) return 1.0;
+    const double Enew = A.kT_cell * A.draws[3 * A.s.C + gc];
+    return sqrt(Enew / E);
+}
+
+// ---- fallback: one lane per cell, members read from global memory ----------
+// (tiles whose member count exceeds the LDS capacity)
+
+__device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double *v, double *vs, double *xstream,
+                                        uint32_t &st)
+{
+    const SysDev &s = A.s;
     const int b = A.cell_start[gc], e = A.cell_start[gc + 1], n = e - b;
     if (n == 0) return;
-    uint32_t st = 0;
     const int r = find_sys(s.cell_off, s.nsys, gc);
     const int64_t N = s.N, S = s.S;
-
-    auto key_of = [&](int32_t k) -> uint64_t {
-        const uint32_t tg = (k < N && A.tag) ? (uint32_t)A.tag[k] : (uint32_t)k;
-        return ((uint64_t)tg << 32) | (uint32_t)k;
-    };
+    auto key_of = [&](int32_t k) -> uint64_t { return ((uint64_t)ident(A, k) << 32) | (uint32_t)k; };
     auto mass = [&](int32_t k) -> double { return k < N ? s.m : A.site_m[k - N]; };
     auto vel = [&](int32_t k, int d) -> double & { return k < N ? v[d * N + k] : vs[d * S + (k - N)]; };
-
-    const bool fast = n <= COL_MAXK;
-    if (fast && n >= 2) {
-        // insertion into a sorted column of LDS (members arrive nearly ordered)
-        for (int i = 0; i < n; ++i) {
-            const uint64_t kk = key_of(A.perm[b + i]);
-            int pos = i;
-            while (pos > 0 && skey[(pos - 1) * COL_T + t] > kk) {
-                skey[pos * COL_T + t] = skey[(pos - 1) * COL_T + t];
-                --pos;
-            }
-            skey[pos * COL_T + t] = kk;
-        }
-    }
+    // members in ascending identity by repeated selection of the next key
     auto canonical = [&](auto &&fn) {
-        if (fast) {
-            for (int i = 0; i < n; ++i) fn((int32_t)(uint32_t)(skey[i * COL_T + t] & 0xffffffffu));
-        } else {
-            uint64_t lo = 0;
-            for (int i = 0; i < n; ++i) {
-                uint64_t best = ~0ull;
-                for (int j = b; j < e; ++j) {
-                    const uint64_t kk = key_of(A.perm[j]);
-                    if (kk >= lo && kk < best) best = kk;
-                }
-                lo = best + 1;
-                fn((int32_t)(uint32_t)(best & 0xffffffffu));
+        uint64_t lo = 0;
+        for (int i = 0; i < n; ++i) {
+            uint64_t best = ~0ull;
+            for (int j = b; j < e; ++j) {
+                const uint64_t kk = key_of(A.perm[j]);
+                if (kk >= lo && kk < best) best = kk;
             }
+            lo = best + 1;
+            fn((int32_t)(uint32_t)(best & 0xffffffffu));
         }
     };
-
     if (n >= 2) {
         double M = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0;
         canonical([&](int32_t k) {
@@ -541,38 +734,26 @@ __global__ __launch_bounds__(COL_T) void k_collide_f64(CollideArgs A, double *v,
             P1 = P1 + mk * vel(k, 1);
             P2 = P2 + mk * vel(k, 2);
         });
-        const double u0 = P0 / M, u1 = P1 / M, u2 = P2 / M;
-        const uint64_t step = *A.d_step;
-        const uint64_t cl = (uint64_t)(gc - s.cell_off[r]);
-        const uint64_t rep = s.replica0 + (uint64_t)r;
+        const double u[3] = {P0 / M, P1 / M, P2 / M};
         double nax[3];
-        st |= cell_axis(A.seed, step, cl, rep, nax);
+        read_axis(A, gc, nax);
         const Rot R = rotation(nax, A.cos_a, A.sin_a);
         double lam = 1.0;
         if (A.kT_cell > 0.0) {
             double Es = 0.0;
             canonical([&](int32_t k) {
-                const double d0 = vel(k, 0) - u0, d1 = vel(k, 1) - u1, d2 = vel(k, 2) - u2;
+                const double d0 = vel(k, 0) - u[0], d1 = vel(k, 1) - u[1], d2 = vel(k, 2) - u[2];
                 Es = Es + mass(k) * ((d0 * d0 + d1 * d1) + d2 * d2);
             });
-            const double E = 0.5 * Es;
-            if (E > 0.0) {
-                double g;
-                const double shape = 0.5 * (double)(3 * (n - 1));
-                st |= gamma_variate(A.seed, step, cl, rep, shape, &g);
-                const double Enew = A.kT_cell * g;
-                lam = sqrt(Enew / E);
-            }
+            lam = thermostat_factor(A, gc, 0.5 * Es);
         }
         for (int i = b; i < e; ++i) {
             const int32_t k = A.perm[i];
-            const double d0 = vel(k, 0) - u0, d1 = vel(k, 1) - u1, d2 = vel(k, 2) - u2;
-            const double dl[3] = {d0, d1, d2};
-            const double uu[3] = {u0, u1, u2};
+            const double dl[3] = {vel(k, 0) - u[0], vel(k, 1) - u[1], vel(k, 2) - u[2]};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const double rr = (R.R[d][0] * dl[0] + R.R[d][1] * dl[1]) + R.R[d][2] * dl[2];
-                const double vn = uu[d] + lam * rr;
+                const double vn = u[d] + lam * rr;
                 if (!(vn - vn == 0.0)) st |= ST_NONFINITE;
                 vel(k, d) = vn;
             }
@@ -585,69 +766,76 @@ __global__ __launch_bounds__(COL_T) void k_collide_f64(CollideArgs A, double *v,
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const double L = (double)s.ncell[3 * r + d] * s.a;
-                const double y = xstream[d * N + k] + v[d * N + k] * A.dt;
-                xstream[d * N + k] = wrap_d(y, L, st);
+                xstream[d * N + k] = wrap_d(xstream[d * N + k] + v[d * N + k] * A.dt, L, st);
             }
         }
     }
-    flag(A.status, st);
 }
 
-// FP32: exact int64 fixed-point cell sums (scale 2^32) of m, m v and m |v|^2;
-// per-cell quantities in FP64; per-particle rotation in FP32.
-__global__ __launch_bounds__(COL_T) void k_collide_f32(CollideArgs A, float *v, float *vs, float *xstream)
+constexpr double FIX_SCALE = 0x1p32, FIX_LIM = 0x1p62;
+
+// FP32 fixed-point contributions of one particle: m, m v (3), m |v|^2.
+__device__ __forceinline__ void fixed_terms(double mk, float fv0, float fv1, float fv2, long long q[5],
+                                            uint32_t &st)
+{
+    const double v0 = (double)fv0, v1 = (double)fv1, v2 = (double)fv2;
+    const double a0 = (mk * v0) * FIX_SCALE, a1 = (mk * v1) * FIX_SCALE, a2 = (mk * v2) * FIX_SCALE;
+    const double ak = (mk * ((v0 * v0 + v1 * v1) + v2 * v2)) * FIX_SCALE;
+    if (!(fabs(a0) < FIX_LIM && fabs(a1) < FIX_LIM && fabs(a2) < FIX_LIM && ak < FIX_LIM)) {
+        st |= ST_FIXOVF;
+        q[0] = q[1] = q[2] = q[3] = q[4] = 0;
+        return;
+    }
+    q[0] = __double2ll_rn(mk * FIX_SCALE);
+    q[1] = __double2ll_rn(a0);
+    q[2] = __double2ll_rn(a1);
+    q[3] = __double2ll_rn(a2);
+    q[4] = __double2ll_rn(ak);
+}
+
+// Per-cell FP32 collision parameters from exact fixed-point sums: u and
+// lambda R rounded to float.
+__device__ __forceinline__ void f32_cell_params(const CollideArgs &A, int64_t gc, const long long q[5], float uf[3],
+                                                float Rf[3][3])
+{
+    const double Md = (double)q[0];
+    const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
+    double nax[3];
+    read_axis(A, gc, nax);
+    const Rot R = rotation(nax, A.cos_a, A.sin_a);
+    double lam = 1.0;
+    if (A.kT_cell > 0.0) {
+        const double P0 = (double)q[1] * 0x1p-32, P1 = (double)q[2] * 0x1p-32, P2 = (double)q[3] * 0x1p-32;
+        const double E = 0.5 * ((double)q[4] * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
+        lam = thermostat_factor(A, gc, E);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Rf[i][j] = (float)(lam * R.R[i][j]);
+    uf[0] = (float)u0; uf[1] = (float)u1; uf[2] = (float)u2;
+}
+
+__device__ void collide_cell_f32_global(const CollideArgs &A, int64_t gc, float *v, float *vs, float *xstream,
+                                        uint32_t &st)
 {
     const SysDev &s = A.s;
-    const int64_t gc = (int64_t)blockIdx.x * COL_T + threadIdx.x;
-    if (gc >= s.C) return;
     const int b = A.cell_start[gc], e = A.cell_start[gc + 1], n = e - b;
     if (n == 0) return;
-    uint32_t st = 0;
     const int r = find_sys(s.cell_off, s.nsys, gc);
     const int64_t N = s.N, S = s.S;
     auto vel = [&](int32_t k, int d) -> float & { return k < N ? v[d * N + k] : vs[d * S + (k - N)]; };
-
     if (n >= 2) {
-        const double SC = 0x1p32, LIM = 0x1p62;
-        long long Mf = 0, P0 = 0, P1 = 0, P2 = 0, Kf = 0;
+        long long acc[5] = {0, 0, 0, 0, 0};
         for (int i = b; i < e; ++i) {
             const int32_t k = A.perm[i];
-            const double mk = k < N ? s.m : A.site_m[k - N];
-            const double v0 = (double)vel(k, 0), v1 = (double)vel(k, 1), v2 = (double)vel(k, 2);
-            const double q0 = (mk * v0) * SC, q1 = (mk * v1) * SC, q2 = (mk * v2) * SC;
-            const double qk = (mk * ((v0 * v0 + v1 * v1) + v2 * v2)) * SC;
-            if (!(fabs(q0) < LIM && fabs(q1) < LIM && fabs(q2) < LIM && qk < LIM)) st |= ST_FIXOVF;
-            Mf += __double2ll_rn(mk * SC);
-            P0 += __double2ll_rn(q0);
-            P1 += __double2ll_rn(q1);
-            P2 += __double2ll_rn(q2);
-            Kf += __double2ll_rn(qk);
-        }
-        const double Md = (double)Mf;
-        const double u0 = (double)P0 / Md, u1 = (double)P1 / Md, u2 = (double)P2 / Md;
-        const uint64_t step = *A.d_step;
-        const uint64_t cl = (uint64_t)(gc - s.cell_off[r]);
-        const uint64_t rep = s.replica0 + (uint64_t)r;
-        double nax[3];
-        st |= cell_axis(A.seed, step, cl, rep, nax);
-        const Rot R = rotation(nax, A.cos_a, A.sin_a);
-        double lam = 1.0;
-        if (A.kT_cell > 0.0) {
-            const double Pd0 = (double)P0 * 0x1p-32, Pd1 = (double)P1 * 0x1p-32, Pd2 = (double)P2 * 0x1p-32;
-            const double E = 0.5 * ((double)Kf * 0x1p-32 - ((Pd0 * Pd0 + Pd1 * Pd1) + Pd2 * Pd2) / (Md * 0x1p-32));
-            if (E > 0.0) {
-                double g;
-                const double shape = 0.5 * (double)(3 * (n - 1));
-                st |= gamma_variate(A.seed, step, cl, rep, shape, &g);
-                lam = sqrt((A.kT_cell * g) / E);
-            }
-        }
-        float Rf[3][3];
+            long long q[5];
+            fixed_terms(k < N ? s.m : A.site_m[k - N], vel(k, 0), vel(k, 1), vel(k, 2), q, st);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Rf[i][j] = (float)(lam * R.R[i][j]);
-        const float uf[3] = {(float)u0, (float)u1, (float)u2};
+            for (int j = 0; j < 5; ++j) acc[j] += q[j];
+        }
+        float uf[3], Rf[3][3];
+        f32_cell_params(A, gc, acc, uf, Rf);
         for (int i = b; i < e; ++i) {
             const int32_t k = A.perm[i];
             const float dl[3] = {vel(k, 0) - uf[0], vel(k, 1) - uf[1], vel(k, 2) - uf[2]};
@@ -667,8 +855,285 @@ __global__ __launch_bounds__(COL_T) void k_collide_f32(CollideArgs A, float *v, 
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const float L = (float)((double)s.ncell[3 * r + d] * s.a);
-                const float y = xstream[d * N + k] + v[d * N + k] * dtf;
-                xstream[d * N + k] = wrap_f(y, L, st);
+                xstream[d * N + k] = wrap_f(xstream[d * N + k] + v[d * N + k] * dtf, L, st);
+            }
+        }
+    }
+}
+
+// ---- tiled collision: a block owns cpb consecutive cells -------------------
+//
+// The tile's members are a contiguous range of the permutation.  Each thread
+// owns ITEMS members (register-batched, so all of its gathers are in flight at
+// once) and, while those loads are outstanding, draws its cell's random axis
+// and thermostat gamma variate (they depend only on the step, the cell and its
+// member count).  Phase 2, one lane per cell: FP64 orders the cell's keys in
+// LDS and sums in ascending identity; FP32 reads exact int64 fixed-point sums
+// accumulated with LDS atomics in phase 1.  Phase 3 rotates each member and
+// streams the solvent.  Blocks are remapped so that each XCD (8 per MI355X,
+// each with its own L2) processes a contiguous range of tiles.
+
+
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS layout: offsets of s_cs, s_idx, s_cl, s_v, s_key|s_acc, s_par, s_r, end.
+struct TileLayout {
+    size_t cs, idx, cl, v, keyacc, par, r, end;
+};
+
+__host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
+{
+    TileLayout L;
+    size_t o = 0;
+    L.cs = o; o += align16(sizeof(int) * (size_t)(cpb + 1));
+    L.idx = o; o += align16(sizeof(int) * (size_t)cap);
+    L.cl = o; o += align16(sizeof(uint16_t) * (size_t)cap);
+    L.v = o; o += align16((f64 ? 8 : 4) * 3 * (size_t)cap);
+    L.keyacc = o; o += align16(f64 ? sizeof(uint64_t) * (size_t)cap : sizeof(long long) * 5 * (size_t)cpb);
+    L.par = o; o += align16(f64 ? sizeof(double) * 13 * (size_t)cpb : sizeof(float) * 12 * (size_t)cpb);
+    L.r = o; o += align16(sizeof(int) * (size_t)cpb);
+    L.end = o;
+    return L;
+}
+
+template <typename Real> struct RealOps;
+template <> struct RealOps<double> {
+    __device__ static double wrap(double y, double L, uint32_t &st) { return wrap_d(y, L, st); }
+};
+template <> struct RealOps<float> {
+    __device__ static float wrap(float y, float L, uint32_t &st) { return wrap_f(y, L, st); }
+};
+
+template <typename Real, int ITEMS>
+__global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg T, Real *v, Real *vs, Real *xstream)
+{
+    constexpr bool F64 = sizeof(Real) == 8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = tile_of_block(T.ntiles);
+    if (tile >= T.ntiles) return;
+    const SysDev &s = A.s;
+    const int t = threadIdx.x;
+    const int64_t c0 = (int64_t)tile * T.cpb;
+    const int nc = (int)((s.C - c0) < T.cpb ? (s.C - c0) : T.cpb);
+    const int m0 = A.cell_start[c0], nm = A.cell_start[c0 + nc] - m0;
+    uint32_t st = 0;
+    if (nm > T.cap) {
+        for (int c = t; c < nc; c += TILE_T) {
+            if constexpr (F64) collide_cell_f64_global(A, c0 + c, v, vs, xstream, st);
+            else collide_cell_f32_global(A, c0 + c, v, vs, xstream, st);
+        }
+        flag(A.status, st);
+        return;
+    }
+    const int cap = T.cap;
+    const TileLayout Lo = tile_layout(F64, T.cpb, cap);
+    int *s_cs = (int *)(smem + Lo.cs);
+    int *s_idx = (int *)(smem + Lo.idx);
+    uint16_t *s_cl = (uint16_t *)(smem + Lo.cl);
+    Real *s_v = (Real *)(smem + Lo.v);
+    uint64_t *s_key = (uint64_t *)(smem + Lo.keyacc);
+    long long *s_acc = (long long *)(smem + Lo.keyacc);
+    int *s_r = (int *)(smem + Lo.r);
+    const int64_t N = s.N, S = s.S;
+
+    // phase 0: cell ranges, cell of each member slot
+    for (int c = t; c <= nc; c += TILE_T) s_cs[c] = A.cell_start[c0 + c] - m0;
+    if constexpr (!F64) {
+        for (int c = t; c < 5 * nc; c += TILE_T) s_acc[c] = 0;
+    }
+    __syncthreads();
+    if (t < nc) {
+        for (int i = s_cs[t]; i < s_cs[t + 1]; ++i) s_cl[i] = (uint16_t)t;
+    }
+    __syncthreads();
+
+    // phase 1: batched gathers; per-cell draws overlap their latency
+    int kk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int i = t + j * TILE_T;
+        kk[j] = (i < nm) ? A.perm[m0 + i] : -1;
+    }
+    Real va[ITEMS][3];
+    double ma[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int32_t k = kk[j];
+        if (k >= 0) {
+            if (k < N) {
+                va[j][0] = v[k]; va[j][1] = v[N + k]; va[j][2] = v[2 * N + k];
+                ma[j] = s.m;
+            } else {
+                const int64_t q = k - N;
+                va[j][0] = vs[q]; va[j][1] = vs[S + q]; va[j][2] = vs[2 * S + q];
+                ma[j] = A.site_m[q];
+            }
+        }
+    }
+    // this lane's cell: system index and the pre-drawn axis / gamma variate
+    double nax[3] = {0.0, 0.0, 1.0}, gvar = 0.0;
+    if (t < nc) {
+        const int64_t gc = c0 + t;
+        s_r[t] = find_sys(s.cell_off, s.nsys, gc);
+        if (s_cs[t + 1] - s_cs[t] >= 2) {
+            read_axis(A, gc, nax);
+            if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int i = t + j * TILE_T;
+        if (i < nm) {
+            const int32_t k = kk[j];
+            s_idx[i] = k;
+            s_v[i] = va[j][0]; s_v[cap + i] = va[j][1]; s_v[2 * cap + i] = va[j][2];
+            if constexpr (F64) {
+                s_key[i] = ((uint64_t)ident(A, k) << 32) | (uint32_t)i;
+            } else {
+                long long q[5];
+                fixed_terms(ma[j], (float)va[j][0], (float)va[j][1], (float)va[j][2], q, st);
+                const int c = s_cl[i];
+#pragma unroll
+                for (int w = 0; w < 5; ++w)
+                    atomicAdd((unsigned long long *)&s_acc[w * nc + c], (unsigned long long)q[w]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // phase 2: one lane per cell
+    if (t < nc) {
+        const int b = s_cs[t], e = s_cs[t + 1], n = e - b;
+        if (n >= 2) {
+            const double g = gvar;
+            const Rot R = rotation(nax, A.cos_a, A.sin_a);
+            if constexpr (F64) {
+                double *par = (double *)(smem + Lo.par) + 13 * t;
+                for (int i = b + 1; i < e; ++i) {
+                    const uint64_t key = s_key[i];
+                    int pos = i;
+                    while (pos > b && s_key[pos - 1] > key) {
+                        s_key[pos] = s_key[pos - 1];
+                        --pos;
+                    }
+                    s_key[pos] = key;
+                }
+                double M = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0;
+                for (int i = b; i < e; ++i) {
+                    const int li = (int)(uint32_t)(s_key[i] & 0xffffffffu);
+                    const int32_t k = s_idx[li];
+                    const double mk = k < N ? s.m : A.site_m[k - N];
+                    M = M + mk;
+                    P0 = P0 + mk * (double)s_v[li];
+                    P1 = P1 + mk * (double)s_v[cap + li];
+                    P2 = P2 + mk * (double)s_v[2 * cap + li];
+                }
+                const double u0 = P0 / M, u1 = P1 / M, u2 = P2 / M;
+                double lam = 1.0;
+                if (A.kT_cell > 0.0) {
+                    double Es = 0.0;
+                    for (int i = b; i < e; ++i) {
+                        const int li = (int)(uint32_t)(s_key[i] & 0xffffffffu);
+                        const int32_t k = s_idx[li];
+                        const double d0 = (double)s_v[li] - u0, d1 = (double)s_v[cap + li] - u1,
+                                     d2 = (double)s_v[2 * cap + li] - u2;
+                        Es = Es + (k < N ? s.m : A.site_m[k - N]) * ((d0 * d0 + d1 * d1) + d2 * d2);
+                    }
+                    const double E = 0.5 * Es;
+                    if (E > 0.0) lam = sqrt((A.kT_cell * g) / E);
+                }
+                par[0] = u0; par[1] = u1; par[2] = u2; par[3] = lam;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) par[4 + 3 * i + j] = R.R[i][j];
+            } else {
+                float *par = (float *)(smem + Lo.par) + 12 * t;
+                const long long q0 = s_acc[t], q1 = s_acc[nc + t], q2 = s_acc[2 * nc + t],
+                                q3 = s_acc[3 * nc + t], q4 = s_acc[4 * nc + t];
+                const double Md = (double)q0;
+                const double u0 = (double)q1 / Md, u1 = (double)q2 / Md, u2 = (double)q3 / Md;
+                double lam = 1.0;
+                if (A.kT_cell > 0.0) {
+                    const double P0 = (double)q1 * 0x1p-32, P1 = (double)q2 * 0x1p-32, P2 = (double)q3 * 0x1p-32;
+                    const double E = 0.5 * ((double)q4 * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
+                    if (E > 0.0) lam = sqrt((A.kT_cell * g) / E);
+                }
+                par[0] = (float)u0; par[1] = (float)u1; par[2] = (float)u2;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) par[3 + 3 * i + j] = (float)(lam * R.R[i][j]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // phase 3: rotate, write back, stream
+    Real vn[ITEMS][3];
+    bool moved[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int i = t + j * TILE_T;
+        moved[j] = false;
+        if (i < nm) {
+            const int c = s_cl[i];
+            vn[j][0] = s_v[i]; vn[j][1] = s_v[cap + i]; vn[j][2] = s_v[2 * cap + i];
+            if (s_cs[c + 1] - s_cs[c] >= 2) {
+                moved[j] = true;
+                if constexpr (F64) {
+                    const double *par = (const double *)(smem + Lo.par) + 13 * c;
+                    const double dl[3] = {vn[j][0] - par[0], vn[j][1] - par[1], vn[j][2] - par[2]};
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double rr = (par[4 + 3 * d] * dl[0] + par[5 + 3 * d] * dl[1]) + par[6 + 3 * d] * dl[2];
+                        vn[j][d] = par[d] + par[3] * rr;
+                        if (!(vn[j][d] - vn[j][d] == 0.0)) st |= ST_NONFINITE;
+                    }
+                } else {
+                    const float *par = (const float *)(smem + Lo.par) + 12 * c;
+                    const float dl[3] = {vn[j][0] - par[0], vn[j][1] - par[1], vn[j][2] - par[2]};
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        vn[j][d] = par[d] + ((par[3 + 3 * d] * dl[0] + par[4 + 3 * d] * dl[1]) + par[5 + 3 * d] * dl[2]);
+                        if (!(vn[j][d] - vn[j][d] == 0.0f)) st |= ST_NONFINITE;
+                    }
+                }
+            }
+        }
+    }
+    if (xstream) {
+        Real xo[ITEMS][3];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int32_t k = kk[j];
+            if (k >= 0 && k < N) {
+                xo[j][0] = xstream[k]; xo[j][1] = xstream[N + k]; xo[j][2] = xstream[2 * N + k];
+            }
+        }
+        const Real dtr = (Real)A.dt;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int32_t k = kk[j];
+            if (k >= 0 && k < N) {
+                const int r = s_r[s_cl[t + j * TILE_T]];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
+                    xstream[d * N + k] = RealOps<Real>::wrap(xo[j][d] + vn[j][d] * dtr, L, st);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int32_t k = kk[j];
+        if (moved[j]) {
+            if (k < N) {
+                v[k] = vn[j][0]; v[N + k] = vn[j][1]; v[2 * N + k] = vn[j][2];
+            } else {
+                const int64_t q = k - N;
+                vs[q] = vn[j][0]; vs[S + q] = vn[j][1]; vs[2 * S + q] = vn[j][2];
             }
         }
     }
@@ -676,49 +1141,74 @@ __global__ __launch_bounds__(COL_T) void k_collide_f32(CollideArgs A, float *v, 
 }
 
 // ---------------------------------------------------------------------------
-// (a1) site thermalization: one block per body; per-body sums in site order.
+// (a1) site thermalization, Eqs. (5) and (7): one block per body.
+//
+// Each lane takes one site of a chunk: space-frame offset d_j = A dhat_j, site
+// position, random velocity vt_j, and the terms m_j vt_j, d_j x m_j vt_j into
+// LDS.  Lanes 0..5 then each add one of the six components over the chunk in
+// site order (the order of a sequential host loop), carrying their partial
+// sums across chunks.  Lane 0 forms Vt, omega_t and the body's V, omega; all
+// lanes then write v_j = (V - Vt) + (omega - omega_t) x d_j + vt_j.
+// Block 0 also draws the step's grid shifts.
 
-constexpr int BODY_T = 128;
+constexpr int WAVE = 64;
+constexpr int BODY_T = 256;
+constexpr int SH_PAD = BODY_T + 1;  // row padding against LDS bank conflicts
+
+__device__ __forceinline__ void draw_shifts(const SysDev &s, uint64_t seed, uint64_t step, double *shift)
+{
+    for (int r = threadIdx.x; r < s.nsys; r += blockDim.x) {
+        const Words w = rng_draw(seed, RNG_SHIFT, step, 0, s.replica0 + (uint64_t)r, 0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) shift[3 * r + k] = shift_component(w.w[k], s.a);
+    }
+}
+
+// Lanes 0..5 add column t of sh over [0, cnt) in order into acc.
+__device__ __forceinline__ void ordered_add(const double *sh, int cnt, double &acc)
+{
+    const int t = threadIdx.x;
+    if (t < 6) {
+        const double *row = sh + t * SH_PAD;
+        for (int i = 0; i < cnt; ++i) acc = acc + row[i];
+    }
+}
 
 template <typename Real>
-__global__ __launch_bounds__(BODY_T) void k_sites_thermalize(SysDev s, BodyDev bd, double kT, int thermalize,
-                                                             uint64_t seed, const uint64_t *d_step,
-                                                             Real *xs, Real *vs, double *site_d,
-                                                             double *vpre, uint32_t *status)
+__global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, double kT, int thermalize, uint64_t seed,
+                                                       const uint64_t *d_step, Real *xs, Real *vs, double *site_d,
+                                                       double *vpre, double *shift, uint32_t *status)
 {
-    __shared__ double sh[6][BODY_T];
+    __shared__ double sh[6 * SH_PAD];
+    __shared__ double sacc[6];
     __shared__ double dvw[6];
+    const uint64_t step = *d_step;
+    if (shift && blockIdx.x == 0) draw_shifts(s, seed, step, shift);
     const int64_t b = blockIdx.x;
     if (b >= s.B) return;
     const int t = threadIdx.x;
     const int64_t B = s.B, S = s.S;
     uint32_t st = 0;
     const int r = find_sys(s.body_off, s.nsys, b);
-    double q[4], p[4], A[3][3], I[3], V[3], w[3], R[3], Lbox[3];
+    double q[4], A[3][3], R[3], Lbox[3];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { q[i] = bd.quat[i * B + b]; p[i] = bd.angmom[i * B + b]; }
+    for (int i = 0; i < 4; ++i) q[i] = bd.quat[i * B + b];
     quat_matrix(q, A);
-    const double Mb = bd.mass[b];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        I[k] = bd.inertia[k * B + b];
-        V[k] = bd.mom[k * B + b] / Mb;
         R[k] = bd.pos[k * B + b];
         Lbox[k] = (double)s.ncell[3 * r + k] * s.a;
     }
-    body_omega(q, p, A, I, w);
     const int64_t j0 = bd.site_off[b], j1 = bd.site_off[b + 1];
     const int64_t sbase = bd.site_off[s.body_off[r]];
-    const uint64_t step = *d_step;
     const uint64_t rep = s.replica0 + (uint64_t)r;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc = 0.0;
     for (int64_t c0 = j0; c0 < j1; c0 += BODY_T) {
         const int64_t j = c0 + t;
         if (j < j1) {
             const double dh[3] = {bd.site_d[j], bd.site_d[S + j], bd.site_d[2 * S + j]};
-            double d[3];
+            double d[3], vt[3] = {0.0, 0.0, 0.0}, pv[3], c[3];
             matvec(A, dh, d);
-            double vt[3] = {0.0, 0.0, 0.0};
             if (thermalize) {
                 double z[3];
                 st |= site_normals(seed, step, (uint64_t)(j - sbase), rep, z);
@@ -727,7 +1217,6 @@ __global__ __launch_bounds__(BODY_T) void k_sites_thermalize(SysDev s, BodyDev b
                 for (int k = 0; k < 3; ++k) vt[k] = sig * z[k];
             }
             const double mj = bd.site_m[j];
-            double pv[3], c[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 site_d[k * S + j] = d[k];
@@ -737,22 +1226,28 @@ __global__ __launch_bounds__(BODY_T) void k_sites_thermalize(SysDev s, BodyDev b
             }
             cross3(d, pv, c);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) { sh[k][t] = pv[k]; sh[3 + k][t] = c[k]; }
+            for (int k = 0; k < 3; ++k) { sh[k * SH_PAD + t] = pv[k]; sh[(3 + k) * SH_PAD + t] = c[k]; }
         }
         __syncthreads();
-        if (t == 0) {
-            const int cnt = (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T);
-            for (int i = 0; i < cnt; ++i) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) acc[k] = acc[k] + sh[k][i];
-            }
-        }
+        ordered_add(sh, (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T), acc);
         __syncthreads();
     }
+    if (t < 6) sacc[t] = acc;
+    __syncthreads();
     if (t == 0) {
+        double p[4], I[3], V[3], w[3];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p[i] = bd.angmom[i * B + b];
+        const double Mb = bd.mass[b];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            I[k] = bd.inertia[k * B + b];
+            V[k] = bd.mom[k * B + b] / Mb;
+        }
+        body_omega(q, p, A, I, w);
         double Vt[3], Lt[3], Lth[3], wth[3], wt[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { Vt[k] = acc[k] / Mb; Lt[k] = acc[3 + k]; }
+        for (int k = 0; k < 3; ++k) { Vt[k] = sacc[k] / Mb; Lt[k] = sacc[3 + k]; }
         matTvec(A, Lt, Lth);
 #pragma unroll
         for (int k = 0; k < 3; ++k) wth[k] = (I[k] == 0.0) ? 0.0 : Lth[k] / I[k];
@@ -778,19 +1273,15 @@ __global__ __launch_bounds__(BODY_T) void k_sites_thermalize(SysDev s, BodyDev b
     flag(status, st);
 }
 
-// (a4) J = sum m (v - v_pre), K = sum d x m (v - v_pre), site order.
+// (a4) J_b = sum m (v - v_pre), K_b = sum d x m (v - v_pre) in site order;
+// the result is valid in lanes 0..5 (component = lane) of a BODY_T block.
 template <typename Real>
-__global__ __launch_bounds__(BODY_T) void k_sites_to_body(SysDev s, BodyDev bd, const Real *vs,
-                                                          const double *site_d, const double *vpre,
-                                                          double *J, double *K)
+__device__ __forceinline__ double transfer_sums(const BodyDev &bd, int64_t S, int64_t b, const Real *vs,
+                                                const double *site_d, const double *vpre, double *sh)
 {
-    __shared__ double sh[6][BODY_T];
-    const int64_t b = blockIdx.x;
-    if (b >= s.B) return;
     const int t = threadIdx.x;
-    const int64_t B = s.B, S = s.S;
     const int64_t j0 = bd.site_off[b], j1 = bd.site_off[b + 1];
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc = 0.0;
     for (int64_t c0 = j0; c0 < j1; c0 += BODY_T) {
         const int64_t j = c0 + t;
         if (j < j1) {
@@ -803,22 +1294,26 @@ __global__ __launch_bounds__(BODY_T) void k_sites_to_body(SysDev s, BodyDev bd, 
             }
             cross3(d, mdv, c);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) { sh[k][t] = mdv[k]; sh[3 + k][t] = c[k]; }
+            for (int k = 0; k < 3; ++k) { sh[k * SH_PAD + t] = mdv[k]; sh[(3 + k) * SH_PAD + t] = c[k]; }
         }
         __syncthreads();
-        if (t == 0) {
-            const int cnt = (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T);
-            for (int i = 0; i < cnt; ++i) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) acc[k] = acc[k] + sh[k][i];
-            }
-        }
+        ordered_add(sh, (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T), acc);
         __syncthreads();
     }
-    if (t == 0) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) { J[k * B + b] = acc[k]; K[k * B + b] = acc[3 + k]; }
-    }
+    return acc;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(BODY_T) void k_sites_to_body(SysDev s, BodyDev bd, const Real *vs, const double *site_d,
+                                                          const double *vpre, double *J, double *K)
+{
+    __shared__ double sh[6 * SH_PAD];
+    const int64_t b = blockIdx.x;
+    if (b >= s.B) return;
+    const double acc = transfer_sums<Real>(bd, s.S, b, vs, site_d, vpre, sh);
+    const int t = threadIdx.x;
+    if (t < 3) J[t * s.B + b] = acc;
+    else if (t < 6) K[(t - 3) * s.B + b] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -840,13 +1335,11 @@ __device__ __forceinline__ void nosquish(int k, double delta, double Ik, double 
     }
 }
 
-__global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double *K, double dt,
-                             uint32_t *status)
+// Impulse (J, K), half kick with the stored F, T, drift, NO_SQUISH rotation.
+__device__ void body_first_update(const SysDev &s, const BodyDev &bd, int64_t b, const double *Jb,
+                                  const double *Kb, double dt, uint32_t &st)
 {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= s.B) return;
     const int64_t B = s.B;
-    uint32_t st = 0;
     const int r = find_sys(s.body_off, s.nsys, b);
     const double hdt = 0.5 * dt;
     double q[4], p[4], A[3][3], P[3], v3[3], h3[3], dq[4];
@@ -855,13 +1348,13 @@ __global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double
     quat_matrix(q, A);
 #pragma unroll
     for (int k = 0; k < 3; ++k) P[k] = bd.mom[k * B + b];
-    if (J) {
+    if (Jb) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) P[k] = P[k] + J[k * B + b];
+        for (int k = 0; k < 3; ++k) P[k] = P[k] + Jb[k];
     }
-    if (K) {
+    if (Kb) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) v3[k] = K[k * B + b];
+        for (int k = 0; k < 3; ++k) v3[k] = Kb[k];
         matTvec(A, v3, h3);
         qmul_pure(q, h3, dq);
 #pragma unroll
@@ -894,17 +1387,68 @@ __global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double
     nosquish(3, hdt, I3, q, p);
 #pragma unroll
     for (int i = 0; i < 4; ++i) { bd.quat[i * B + b] = q[i]; bd.angmom[i * B + b] = p[i]; }
+}
+
+__global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double *K, double dt,
+                             uint32_t *status)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= s.B) return;
+    uint32_t st = 0;
+    double Jb[3], Kb[3];
+    if (J)
+        for (int k = 0; k < 3; ++k) Jb[k] = J[k * s.B + b];
+    if (K)
+        for (int k = 0; k < 3; ++k) Kb[k] = K[k * s.B + b];
+    body_first_update(s, bd, b, J ? Jb : nullptr, K ? Kb : nullptr, dt, st);
     flag(status, st);
 }
 
-// Core-shifted WCA between body centres, Eq. (1), partners in ascending index.
-__global__ void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, uint32_t *status)
+// Momentum transfer fused with the first half of the body update (one block
+// per body); J and K are also written out.
+template <typename Real>
+__global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd, const Real *vs, const double *site_d,
+                                                           const double *vpre, double *J, double *K, double dt,
+                                                           uint32_t *status)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sh[6 * SH_PAD];
+    __shared__ double jk[6];
+    const int64_t b = blockIdx.x;
+    if (b >= s.B) return;
+    const double acc = transfer_sums<Real>(bd, s.S, b, vs, site_d, vpre, sh);
+    const int t = threadIdx.x;
+    if (t < 6) jk[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t st = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { J[k * s.B + b] = jk[k]; K[k * s.B + b] = jk[3 + k]; }
+        body_first_update(s, bd, b, jk, jk + 3, dt, st);
+        flag(status, st);
+    }
+}
+
+// Core-shifted WCA between body centres, Eq. (1).  One wave per body: lanes
+// evaluate partners in parallel; lanes 0..2 add the x, y, z components of the
+// interacting partners in ascending partner index (the order of a sequential
+// host loop).  With kick != 0 the second half kick follows in the same lane
+// (it needs only this body's new force); with advance_step != NULL block 0
+// then advances the step counter (last kernel of a step).
+constexpr int FRC_T = 64;
+
+__global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, double dt, int kick,
+                                                       uint64_t *advance_step, uint32_t *status)
+{
+    __shared__ double sf[3][FRC_T + 1];
+    __shared__ int shit[FRC_T];
+    __shared__ double fsh[3];
+    const int64_t i = blockIdx.x;
+    if (advance_step && i == 0 && threadIdx.x == 0) *advance_step = *advance_step + 1;
     if (i >= s.B) return;
+    const int t = threadIdx.x;
     const int64_t B = s.B;
     uint32_t st = 0;
-    double f[3] = {0.0, 0.0, 0.0};
+    double f = 0.0;  // component t (lanes 0..2)
     if (wca.mode == 1) {
         const int r = find_sys(s.body_off, s.nsys, i);
         const double rc = wca.delta + 0x1.1f59ac3c7d6c0p+0 * wca.sigma;
@@ -915,58 +1459,76 @@ __global__ void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, uint32_t *stat
             Lb[k] = (double)s.ncell[3 * r + k] * s.a;
             Ri[k] = bd.pos[k * B + i];
         }
-        for (int64_t j = s.body_off[r]; j < s.body_off[r + 1]; ++j) {
-            if (j == i) continue;
-            double dr[3];
+        const int64_t jb = s.body_off[r], je = s.body_off[r + 1];
+        for (int64_t j0 = jb; j0 < je; j0 += FRC_T) {
+            const int64_t j = j0 + t;
+            int hit = 0;
+            double c[3] = {0.0, 0.0, 0.0};
+            if (j < je && j != i) {
+                double dr[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                double t = Ri[k] - bd.pos[k * B + j];
-                if (t > 0.5 * Lb[k]) t = t - Lb[k];
-                else if (t < -0.5 * Lb[k]) t = t + Lb[k];
-                dr[k] = t;
+                for (int k = 0; k < 3; ++k) {
+                    double d = Ri[k] - bd.pos[k * B + j];
+                    if (d > 0.5 * Lb[k]) d = d - Lb[k];
+                    else if (d < -0.5 * Lb[k]) d = d + Lb[k];
+                    dr[k] = d;
+                }
+                const double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
+                if (r2 <= rc2) {
+                    const double rr = sqrt(r2);
+                    const double sh = rr - wca.delta;
+                    if (sh > 0.0) {
+                        const double is = wca.sigma / sh;
+                        const double is2 = is * is;
+                        const double is6 = (is2 * is2) * is2;
+                        const double is12 = is6 * is6;
+                        const double fr = ((24.0 * wca.eps) * (2.0 * is12 - is6)) / sh;
+                        const double fo = fr / rr;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) c[k] = fo * dr[k];
+                        hit = 1;
+                    } else {
+                        st |= ST_NONFINITE;
+                    }
+                }
             }
-            const double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
-            if (!(r2 <= rc2)) continue;
-            const double rr = sqrt(r2);
-            const double sh = rr - wca.delta;
-            if (!(sh > 0.0)) { st |= ST_NONFINITE; continue; }
-            const double is = wca.sigma / sh;
-            const double is2 = is * is;
-            const double is6 = (is2 * is2) * is2;
-            const double is12 = is6 * is6;
-            const double fr = ((24.0 * wca.eps) * (2.0 * is12 - is6)) / sh;
-            const double fo = fr / rr;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) f[k] = f[k] + fo * dr[k];
+            for (int k = 0; k < 3; ++k) sf[k][t] = c[k];
+            shit[t] = hit;
+            __syncthreads();
+            if (t < 3) {
+                const int cnt = (int)((je - j0) < FRC_T ? (je - j0) : FRC_T);
+                for (int q = 0; q < cnt; ++q)
+                    if (shit[q]) f = f + sf[t][q];
+            }
+            __syncthreads();
         }
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) { bd.force[k * B + i] = f[k]; bd.torque[k * B + i] = 0.0; }
-    flag(status, st);
-}
-
-__global__ void k_body_second(SysDev s, BodyDev bd, double dt, uint32_t *status)
-{
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= s.B) return;
-    const int64_t B = s.B;
-    uint32_t st = 0;
-    const double hdt = 0.5 * dt;
-    double q[4], A[3][3], v3[3], h3[3], dq[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) q[i] = bd.quat[i * B + b];
-    quat_matrix(q, A);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double Pk = bd.mom[k * B + b] + hdt * bd.force[k * B + b];
-        if (!(Pk - Pk == 0.0)) st |= ST_NONFINITE;
-        bd.mom[k * B + b] = Pk;
-        v3[k] = bd.torque[k * B + b];
+    if (t < 3) {
+        fsh[t] = f;
+        bd.force[t * B + i] = f;
+        bd.torque[t * B + i] = 0.0;
     }
-    matTvec(A, v3, h3);
-    qmul_pure(q, h3, dq);
+    __syncthreads();
+    if (kick && t == 0) {
+        // second half kick: P += dt/2 F; p += dt S(q)(0, A^T T)
+        const double hdt = 0.5 * dt;
+        double q[4], A[3][3], v3[3], h3[3], dq[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bd.angmom[i * B + b] = bd.angmom[i * B + b] + dt * dq[i];
+        for (int k = 0; k < 4; ++k) q[k] = bd.quat[k * B + i];
+        quat_matrix(q, A);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double Pk = bd.mom[k * B + i] + hdt * fsh[k];
+            if (!(Pk - Pk == 0.0)) st |= ST_NONFINITE;
+            bd.mom[k * B + i] = Pk;
+            v3[k] = 0.0;
+        }
+        matTvec(A, v3, h3);
+        qmul_pure(q, h3, dq);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bd.angmom[k * B + i] = bd.angmom[k * B + i] + dt * dq[k];
+    }
     flag(status, st);
 }
 
@@ -1083,8 +1645,11 @@ int mpcd_ws_init(void *stream, const mpcd_sys *sys, void *ws, size_t ws_bytes)
     const Layout L = layout_of(sys);
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, at<uint32_t>(ws, L.status), (int64_t)64, 0u);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(sys->n_cells, 256)), dim3(256), 0, st,
-                       at<int32_t>(ws, L.counts), sys->n_cells, 0);
+    const int64_t NT = sys->n_solvent + sys->n_sites;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(sys->n_cells, 256)), dim3(256), 0, st, at<int32_t>(ws, L.counts),
+                       sys->n_cells, 0);
+    if (NT > 0)  // the permutation holds valid particle indices from the start
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NT, 256)), dim3(256), 0, st, at<int32_t>(ws, L.perm), NT, 0);
     return launch_check();
 }
 
@@ -1109,8 +1674,8 @@ int mpcd_stream(void *stream, const mpcd_sys *sys, void *x, const void *v, doubl
     return launch_check();
 }
 
-int mpcd_bin(void *stream, const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
-             uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes)
+static int bin_impl(void *stream, const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
+                    uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes, bool draw_shift)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
@@ -1123,33 +1688,86 @@ int mpcd_bin(void *stream, const mpcd_sys *sys, const void *x, const void *xs, c
     const int64_t NT = sys->n_solvent + sys->n_sites, C = sys->n_cells;
     const int64_t nb = (C + SCAN_TILE - 1) / SCAN_TILE;
     double *shift = at<double>(ws, L.shift);
-    int32_t *counts = at<int32_t>(ws, L.counts), *cs = at<int32_t>(ws, L.cell_start);
-    int32_t *cellid = at<int32_t>(ws, L.cellid), *slot = at<int32_t>(ws, L.slot), *perm = at<int32_t>(ws, L.perm);
-    int32_t *partial = at<int32_t>(ws, L.partial);
+    int32_t *counts = at<int32_t>(ws, L.counts), *partial = at<int32_t>(ws, L.partial);
+    int32_t *cs = at<int32_t>(ws, L.cell_start), *cellid = at<int32_t>(ws, L.cellid);
+    int32_t *slot = at<int32_t>(ws, L.slot), *perm = at<int32_t>(ws, L.perm);
     uint32_t *status = at<uint32_t>(ws, L.status);
     const int32_t *site_body = bodies ? bodies->site_body : nullptr;
 
-    hipLaunchKernelGGL(k_shift, dim3(grid_for(sys->nsys, 64)), dim3(64), 0, st, sd, seed, d_step, shift);
+    if (draw_shift)
+        hipLaunchKernelGGL(k_shift, dim3(grid_for(sys->nsys, 64)), dim3(64), 0, st, sd, seed, d_step, shift);
+    const unsigned nchunks = (unsigned)((NT + BIN_CHUNK - 1) / BIN_CHUNK);
     if (NT > 0) {
-        const unsigned g = grid_for(NT, 256);
         if (sys->prec == MPCD_F64)
-            hipLaunchKernelGGL(k_bin_count<double>, dim3(g), dim3(256), 0, st, sd, (const double *)x,
+            hipLaunchKernelGGL(k_bin_count<double>, dim3(nchunks), dim3(BIN_T), 0, st, sd, (const double *)x,
                                (const double *)xs, site_body, shift, counts, cellid, slot, status);
         else
-            hipLaunchKernelGGL(k_bin_count<float>, dim3(g), dim3(256), 0, st, sd, (const float *)x,
+            hipLaunchKernelGGL(k_bin_count<float>, dim3(nchunks), dim3(BIN_T), 0, st, sd, (const float *)x,
                                (const float *)xs, site_body, shift, counts, cellid, slot, status);
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_T), 0, st, partial, nb);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial, cs, (int32_t)NT);
     if (NT > 0)
-        hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(NT, 256)), dim3(256), 0, st, NT, cellid, slot, cs, perm);
+        hipLaunchKernelGGL(k_bin_scatter, dim3(nchunks), dim3(BIN_T), 0, st, NT, cellid, slot, cs, perm, status);
     return launch_check();
 }
+
+int mpcd_bin(void *stream, const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
+             uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes)
+{
+    return bin_impl(stream, sys, x, xs, bodies, seed, d_step, ws, ws_bytes, true);
+}
+
+int mpcd_reorder(void *stream, const mpcd_sys *sys, void *x, void *v, int32_t *tag, void *ws, size_t ws_bytes)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    const int64_t N = sys->n_solvent, NT = sys->n_solvent + sys->n_sites;
+    if (!ok_arr(x, N, esize(sys)) || !ok_arr(v, N, esize(sys)) || !ok_arr(tag, N, 4)) return MPCD_EINVAL;
+    if (N == 0) return MPCD_OK;
+    const Layout L = layout_of(sys);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nb = (NT + SCAN_TILE - 1) / SCAN_TILE;
+    const int32_t *perm = at<int32_t>(ws, L.perm);
+    int32_t *partial = at<int32_t>(ws, L.partial);
+    char *tmp = at<char>(ws, L.rtmp);
+    const size_t es = esize(sys);
+    int32_t *ttag = (int32_t *)(tmp + 6 * es * (size_t)N);
+    const unsigned gc = grid_for(N, 256);
+    hipLaunchKernelGGL(k_reorder_count, dim3((unsigned)nb), dim3(SCAN_T), 0, st, perm, NT, N, partial);
+    if (sys->prec == MPCD_F64) {
+        double *tx = (double *)tmp, *tv = tx + 3 * N;
+        hipLaunchKernelGGL(k_reorder_gather<double>, dim3((unsigned)nb), dim3(SCAN_T), 0, st, perm, NT, N, partial,
+                           (const double *)x, (const double *)v, (const int32_t *)tag, tx, tv, ttag);
+        hipLaunchKernelGGL(k_reorder_copy<double>, dim3(gc), dim3(256), 0, st, N, (double *)x, (double *)v, tag,
+                           (const double *)tx, (const double *)tv, (const int32_t *)ttag);
+    } else {
+        float *tx = (float *)tmp, *tv = tx + 3 * N;
+        hipLaunchKernelGGL(k_reorder_gather<float>, dim3((unsigned)nb), dim3(SCAN_T), 0, st, perm, NT, N, partial,
+                           (const float *)x, (const float *)v, (const int32_t *)tag, tx, tv, ttag);
+        hipLaunchKernelGGL(k_reorder_copy<float>, dim3(gc), dim3(256), 0, st, N, (float *)x, (float *)v, tag,
+                           (const float *)tx, (const float *)tv, (const int32_t *)ttag);
+    }
+    return launch_check();
+}
+
+static int collide_impl(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
+                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell, uint64_t seed,
+                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt,
+                        bool draws_ready);
 
 int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
                  const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell, uint64_t seed,
                  const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt)
+{
+    return collide_impl(stream, sys, v, tag, vs, bodies, cos_a, sin_a, kT_cell, seed, d_step, ws, ws_bytes,
+                        x_stream, dt, false);
+}
+
+static int collide_impl(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
+                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell, uint64_t seed,
+                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt,
+                        bool draws_ready)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
@@ -1165,6 +1783,7 @@ int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag,
     A.tag = tag;
     A.cell_start = at<int32_t>(ws, L.cell_start);
     A.perm = at<int32_t>(ws, L.perm);
+    A.draws = at<double>(ws, L.draws);
     A.cos_a = cos_a;
     A.sin_a = sin_a;
     A.kT_cell = kT_cell;
@@ -1173,19 +1792,25 @@ int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag,
     A.d_step = d_step;
     A.status = at<uint32_t>(ws, L.status);
     hipStream_t st = (hipStream_t)stream;
-    const unsigned g = (unsigned)((sys->n_cells + COL_T - 1) / COL_T);
-    if (sys->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_collide_f64, dim3(g), dim3(COL_T), 0, st, A, (double *)v, (double *)vs,
-                           (double *)x_stream);
+    if (!draws_ready)
+        hipLaunchKernelGGL(k_cell_draws, dim3(grid_for(sys->n_cells, 256)), dim3(256), 0, st, A,
+                           at<double>(ws, L.draws));
+    const bool f64 = sys->prec == MPCD_F64;
+    const TileCfg T = tile_config(sys);
+    const dim3 grid(xcd_grid(T.ntiles));
+    const size_t lds = tile_layout(f64, T.cpb, T.cap).end;
+    if (f64)
+        hipLaunchKernelGGL((k_collide_tiled<double, ITEMS_F64>), grid, dim3(TILE_T), lds, st, A, T, (double *)v,
+                           (double *)vs, (double *)x_stream);
     else
-        hipLaunchKernelGGL(k_collide_f32, dim3(g), dim3(COL_T), 0, st, A, (float *)v, (float *)vs,
-                           (float *)x_stream);
+        hipLaunchKernelGGL((k_collide_tiled<float, ITEMS_F32>), grid, dim3(TILE_T), lds, st, A, T, (float *)v,
+                           (float *)vs, (float *)x_stream);
     return launch_check();
 }
 
-int sites_thermalize(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, double kT,
-                     int32_t thermalize, uint64_t seed, const uint64_t *d_step, void *xs, void *vs, void *ws,
-                     size_t ws_bytes)
+static int thermalize_impl(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, double kT,
+                           int32_t thermalize, uint64_t seed, const uint64_t *d_step, void *xs, void *vs, void *ws,
+                           size_t ws_bytes, bool draw_shift)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
@@ -1193,21 +1818,29 @@ int sites_thermalize(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodie
     if (!ok_arr(xs, sys->n_sites, esize(sys)) || !ok_arr(vs, sys->n_sites, esize(sys)) || !d_step)
         return MPCD_EINVAL;
     if (thermalize && !(kT > 0.0)) return MPCD_EINVAL;
-    if (sys->n_bodies == 0) return MPCD_OK;
+    if (sys->n_bodies == 0 || sys->n_sites == 0) return MPCD_OK;
     const Layout L = layout_of(sys);
     const SysDev sd = make_sysdev(sys);
     const BodyDev bd = make_bodydev(bodies);
     hipStream_t st = (hipStream_t)stream;
-    const dim3 g((unsigned)sys->n_bodies);
+    double *shift = draw_shift ? at<double>(ws, L.shift) : nullptr;
+    double *site_d = at<double>(ws, L.site_d), *vpre = at<double>(ws, L.vpre);
+    uint32_t *status = at<uint32_t>(ws, L.status);
+    const dim3 gb((unsigned)sys->n_bodies);
     if (sys->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_sites_thermalize<double>, g, dim3(BODY_T), 0, st, sd, bd, kT, (int)thermalize, seed,
-                           d_step, (double *)xs, (double *)vs, at<double>(ws, L.site_d), at<double>(ws, L.vpre),
-                           at<uint32_t>(ws, L.status));
+        hipLaunchKernelGGL(k_thermalize<double>, gb, dim3(BODY_T), 0, st, sd, bd, kT, (int)thermalize, seed, d_step,
+                           (double *)xs, (double *)vs, site_d, vpre, shift, status);
     else
-        hipLaunchKernelGGL(k_sites_thermalize<float>, g, dim3(BODY_T), 0, st, sd, bd, kT, (int)thermalize, seed,
-                           d_step, (float *)xs, (float *)vs, at<double>(ws, L.site_d), at<double>(ws, L.vpre),
-                           at<uint32_t>(ws, L.status));
+        hipLaunchKernelGGL(k_thermalize<float>, gb, dim3(BODY_T), 0, st, sd, bd, kT, (int)thermalize, seed, d_step,
+                           (float *)xs, (float *)vs, site_d, vpre, shift, status);
     return launch_check();
+}
+
+int sites_thermalize(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, double kT,
+                     int32_t thermalize, uint64_t seed, const uint64_t *d_step, void *xs, void *vs, void *ws,
+                     size_t ws_bytes)
+{
+    return thermalize_impl(stream, sys, bodies, kT, thermalize, seed, d_step, xs, vs, ws, ws_bytes, false);
 }
 
 int sites_to_body(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const void *vs, void *ws,
@@ -1233,8 +1866,8 @@ int sites_to_body(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, 
     return launch_check();
 }
 
-int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca, void *ws,
-                size_t ws_bytes)
+static int forces_impl(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca, void *ws,
+                       size_t ws_bytes, double dt, int kick, uint64_t *advance_step)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
@@ -1243,9 +1876,16 @@ int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, co
     if (wca->mode == 1 && !(wca->sigma > 0.0 && wca->eps >= 0.0 && wca->delta >= 0.0)) return MPCD_EINVAL;
     if (sys->n_bodies == 0) return MPCD_OK;
     const Layout L = layout_of(sys);
-    hipLaunchKernelGGL(k_body_forces, dim3(grid_for(sys->n_bodies, 64)), dim3(64), 0, (hipStream_t)stream,
-                       make_sysdev(sys), make_bodydev(bodies), *wca, at<uint32_t>(ws, L.status));
+    hipLaunchKernelGGL(k_body_forces, dim3((unsigned)sys->n_bodies), dim3(FRC_T), 0, (hipStream_t)stream,
+                       make_sysdev(sys), make_bodydev(bodies), *wca, dt, kick, advance_step,
+                       at<uint32_t>(ws, L.status));
     return launch_check();
+}
+
+int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca, void *ws,
+                size_t ws_bytes)
+{
+    return forces_impl(stream, sys, bodies, wca, ws, ws_bytes, 0.0, 0, nullptr);
 }
 
 int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const double *J,
@@ -1265,9 +1905,7 @@ int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies,
     uint32_t *status = at<uint32_t>(ws, L.status);
     hipLaunchKernelGGL(k_body_first, dim3(g), dim3(64), 0, st, sd, bd, J, K, dt, status);
     TRY(launch_check());
-    TRY(body_forces(stream, sys, bodies, wca, ws, ws_bytes));
-    hipLaunchKernelGGL(k_body_second, dim3(g), dim3(64), 0, st, sd, bd, dt, status);
-    return launch_check();
+    return forces_impl(stream, sys, bodies, wca, ws, ws_bytes, dt, 1, nullptr);
 }
 
 int mpcd_advance_step(void *stream, uint64_t *d_step)
@@ -1277,20 +1915,42 @@ int mpcd_advance_step(void *stream, uint64_t *d_step)
     return launch_check();
 }
 
+// One step.  Differs from calling the entry points in sequence only by fusion
+// (same operations in the same order): the grid shift is drawn with the site
+// draws, the momentum transfer runs inside the first body half-step, and the
+// step counter advances in the last body kernel.
 int mpcd_step(void *stream, const mpcd_step_args *a)
 {
     if (!a || !a->sys) return MPCD_EINVAL;
     const mpcd_sys *s = a->sys;
     const mpcd_params &p = a->par;
-    TRY(sites_thermalize(stream, s, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->xs, a->vs, a->ws,
-                         a->ws_bytes));
-    TRY(mpcd_bin(stream, s, a->x, a->xs, &a->bodies, p.seed, a->d_step, a->ws, a->ws_bytes));
-    TRY(mpcd_collide(stream, s, a->v, a->tag, a->vs, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed,
-                     a->d_step, a->ws, a->ws_bytes, p.fuse_stream ? a->x : nullptr, p.dt));
-    TRY(sites_to_body(stream, s, &a->bodies, a->vs, a->ws, a->ws_bytes, a->J, a->K));
+    TRY(check_sys(s));
+    TRY(check_ws(s, a->ws, a->ws_bytes));
+    TRY(check_bodies(s, &a->bodies));
+    if (!(p.dt > 0.0) || (p.wca.mode != 0 && p.wca.mode != 1)) return MPCD_EINVAL;
+    if (!ok_arr(a->J, s->n_bodies, 8) || !ok_arr(a->K, s->n_bodies, 8) || !a->d_step) return MPCD_EINVAL;
+    const bool sites = s->n_sites > 0 && s->n_bodies > 0;
+    TRY(thermalize_impl(stream, s, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->xs, a->vs, a->ws,
+                        a->ws_bytes, sites));
+    TRY(bin_impl(stream, s, a->x, a->xs, &a->bodies, p.seed, a->d_step, a->ws, a->ws_bytes, !sites));
+    TRY(collide_impl(stream, s, a->v, a->tag, a->vs, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed,
+                     a->d_step, a->ws, a->ws_bytes, p.fuse_stream ? a->x : nullptr, p.dt, false));
     if (!p.fuse_stream) TRY(mpcd_stream(stream, s, a->x, a->v, p.dt, a->ws, a->ws_bytes));
-    TRY(body_integrate(stream, s, &a->bodies, a->J, a->K, &p.wca, p.dt, a->ws, a->ws_bytes));
-    return mpcd_advance_step(stream, a->d_step);
+    if (s->n_bodies == 0) return mpcd_advance_step(stream, a->d_step);
+    const Layout L = layout_of(s);
+    const SysDev sd = make_sysdev(s);
+    const BodyDev bd = make_bodydev(&a->bodies);
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *status = at<uint32_t>(a->ws, L.status);
+    const dim3 gb((unsigned)s->n_bodies);
+    if (s->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_transfer_first<double>, gb, dim3(BODY_T), 0, st, sd, bd, (const double *)a->vs,
+                           at<double>(a->ws, L.site_d), at<double>(a->ws, L.vpre), a->J, a->K, p.dt, status);
+    else
+        hipLaunchKernelGGL(k_transfer_first<float>, gb, dim3(BODY_T), 0, st, sd, bd, (const float *)a->vs,
+                           at<double>(a->ws, L.site_d), at<double>(a->ws, L.vpre), a->J, a->K, p.dt, status);
+    TRY(launch_check());
+    return forces_impl(stream, s, &a->bodies, &p.wca, a->ws, a->ws_bytes, p.dt, 1, a->d_step);
 }
 
 int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, void **graph_exec)
@@ -1299,7 +1959,11 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
     hipStream_t st = (hipStream_t)stream;
     TRY(hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)));
     int rc = MPCD_OK;
-    for (int i = 0; i < nsteps && rc == MPCD_OK; ++i) rc = mpcd_step(stream, args);
+    for (int i = 0; i < nsteps && rc == MPCD_OK; ++i) {
+        rc = mpcd_step(stream, args);
+        if (rc == MPCD_OK && args->reorder_every > 0 && (i + 1) % args->reorder_every == 0)
+            rc = mpcd_reorder(stream, args->sys, args->x, args->v, (int32_t *)args->tag, args->ws, args->ws_bytes);
+    }
     hipGraph_t graph = nullptr;
     const int rc_end = hip_check(hipStreamEndCapture(st, &graph));
     if (rc != MPCD_OK) {

@@ -14,11 +14,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpcd.so")
 
 MPCD_F64, MPCD_F32 = 0, 1
-FLAG_NONFINITE, FLAG_ESCAPE, FLAG_FIXOVF, FLAG_RNGLOOP = 1, 2, 4, 8
+FLAG_NONFINITE, FLAG_ESCAPE, FLAG_FIXOVF, FLAG_RNGLOOP, FLAG_BINERR = 1, 2, 4, 8, 16
 
 EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mpcd_stream", "mpcd_bin", "mpcd_collide",
            "sites_thermalize", "sites_to_body", "body_integrate", "body_forces",
-           "mpcd_advance_step", "mpcd_step", "mpcd_graph_create", "mpcd_graph_launch",
+           "mpcd_advance_step", "mpcd_step", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
            "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error")
 
 vp = C.c_void_p
@@ -50,7 +50,7 @@ class MpcdParams(C.Structure):
 class MpcdStepArgs(C.Structure):
     _fields_ = [("sys", C.POINTER(MpcdSys)), ("bodies", MpcdBodies), ("x", vp), ("v", vp), ("tag", vp),
                 ("xs", vp), ("vs", vp), ("J", vp), ("K", vp), ("d_step", vp), ("ws", vp),
-                ("ws_bytes", C.c_size_t), ("par", MpcdParams)]
+                ("ws_bytes", C.c_size_t), ("par", MpcdParams), ("reorder_every", C.c_int32)]
 
 
 _lib = None
@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
         "body_forces": (C.c_int, [vp, sp, bp, wp, vp, sz]),
         "mpcd_advance_step": (C.c_int, [vp, vp]),
         "mpcd_step": (C.c_int, [vp, C.POINTER(MpcdStepArgs)]),
+        "mpcd_reorder": (C.c_int, [vp, sp, vp, vp, vp, vp, sz]),
         "mpcd_graph_create": (C.c_int, [vp, C.POINTER(MpcdStepArgs), i32, C.POINTER(vp)]),
         "mpcd_graph_launch": (C.c_int, [vp, vp]),
         "mpcd_graph_destroy": (C.c_int, [vp]),

@@ -65,7 +65,9 @@ class GPUSystem:
         self.body_off = torch.tensor(self.body_off_h, device=dev)
         self.x = cat("x", self.real, 3)
         self.v = cat("v", self.real, 3)
-        self.tag = None
+        # solvent identities (global index in packing order); the storage
+        # reorder permutes them along with x and v
+        self.tag = torch.arange(self.N, dtype=torch.int32, device=dev)
         self.pos = cat("R", torch.float64, 3)
         self.image = cat("img", torch.int32, 3)
         self.quat = cat("q", torch.float64, 4)
@@ -126,7 +128,7 @@ class GPUSystem:
     def set_step(self, n: int):
         self.d_step.fill_(int(n))
 
-    def step_args(self) -> L.MpcdStepArgs:
+    def step_args(self, reorder_every: int = 0) -> L.MpcdStepArgs:
         p = self.params
         par = L.MpcdParams(dt=p["dt"], cos_a=p["cos_a"], sin_a=p["sin_a"], kT=p["kT"], kT_cell=p["kT_cell"],
                            seed=p["seed"], thermalize=int(p.get("thermalize", 1)),
@@ -134,7 +136,7 @@ class GPUSystem:
         self._args = L.MpcdStepArgs(sys=C.pointer(self.csys), bodies=self.cbodies, x=_ptr(self.x), v=_ptr(self.v),
                                     tag=_ptr(self.tag), xs=_ptr(self.xs), vs=_ptr(self.vs), J=_ptr(self.J),
                                     K=_ptr(self.K), d_step=_ptr(self.d_step), ws=_ptr(self.ws),
-                                    ws_bytes=self.ws_bytes, par=par)
+                                    ws_bytes=self.ws_bytes, par=par, reorder_every=int(reorder_every))
         return self._args
 
     # --- entry points -------------------------------------------------
@@ -185,10 +187,15 @@ class GPUSystem:
         for _ in range(nsteps):
             L.check(self.lib.mpcd_step(self.stream, C.byref(args)), "mpcd_step")
 
-    def graph(self, nsteps: int):
-        """Capture nsteps steps into a HIP graph (on a side stream)."""
+    def reorder(self):
+        L.check(self.lib.mpcd_reorder(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.v), _ptr(self.tag),
+                                      _ptr(self.ws), self.ws_bytes), "mpcd_reorder")
+
+    def graph(self, nsteps: int, reorder_every: int = 0):
+        """Capture nsteps steps (with a storage reorder after every reorder_every
+        steps) into a HIP graph; the current stream must not be the null stream."""
         self.release_graph()
-        args = self.step_args()
+        args = self.step_args(reorder_every)
         h = C.c_void_p(0)
         L.check(self.lib.mpcd_graph_create(self.stream, C.byref(args), int(nsteps), C.byref(h)),
                 "mpcd_graph_create")
@@ -231,6 +238,12 @@ class GPUSystem:
         torch.cuda.synchronize(self.device)
         g = {k: getattr(self, k).detach().cpu().numpy() for k in
              ("x", "v", "pos", "image", "quat", "mom", "angmom", "force", "torque", "xs", "vs", "J", "K")}
+        # solvent back into identity order
+        tag = self.tag.cpu().numpy().astype(np.int64)
+        for k in ("x", "v"):
+            a = np.empty_like(g[k])
+            a[:, tag] = g[k]
+            g[k] = a
         out = []
         for r in range(self.nsys):
             n0, n1 = self.solv_off_h[r], self.solv_off_h[r + 1]

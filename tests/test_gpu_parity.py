@@ -46,7 +46,7 @@ def assert_same(o, gd, keys=STATE_KEYS, where=""):
                                  % (where, k, i, len(diff), a[i], b[i]))
 
 
-def run_parity(wl, par, nsteps, fuse=True, check_every=1, step0=0):
+def run_parity(wl, par, nsteps, fuse=True, check_every=1, step0=0, reorder_every=0):
     o = oracle.OracleSystem(wl, par)
     g = gpu_system(wl, par, prec="f64", fuse_stream=fuse)
     o.body_forces()
@@ -56,6 +56,8 @@ def run_parity(wl, par, nsteps, fuse=True, check_every=1, step0=0):
     for n in range(nsteps):
         assert o.step(step0 + n) == 0
         g.step(1)
+        if reorder_every and (n + 1) % reorder_every == 0:
+            g.reorder()
         if (n + 1) % check_every == 0 or n == nsteps - 1:
             assert_same(o, g.download()[0], where="step %d" % (step0 + n))
     assert g.status() == 0
@@ -123,6 +125,16 @@ def test_single_sphere_100_steps_bit_exact(kT_cell):
     wl, par, meta = W.config(0, kT_cell=kT_cell)
     say("single sphere kT_cell=%g" % kT_cell)
     run_parity(wl, par, meta["steps"])
+
+
+def test_storage_reorder_keeps_results_bit_exact():
+    """Reordering the solvent storage (with identity tags) changes nothing."""
+    wl, par, _ = W.config(0)
+    say("reorder every 3 steps")
+    o, g = run_parity(wl, par, 30, reorder_every=3)
+    tag = g.tag.cpu().numpy()
+    assert not np.array_equal(tag, np.arange(len(tag)))  # storage really was permuted
+    assert np.array_equal(np.sort(tag), np.arange(len(tag)))
 
 
 def test_unfused_stream_matches_fused():
@@ -209,11 +221,14 @@ def test_graph_replay_matches_eager():
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
-        gg.graph(5)
+        gg.graph(5, reorder_every=2)
         for rep in range(4):
             gg.graph_launch()
             torch.cuda.synchronize()
-            ge.step(5)
+            for i in range(5):
+                ge.step(1)
+                if (i + 1) % 2 == 0:
+                    ge.reorder()
             torch.cuda.synchronize()
             a, b = ge.download()[0], gg.download()[0]
             for k in STATE_KEYS:
