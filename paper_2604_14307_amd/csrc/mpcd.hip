@@ -268,6 +268,9 @@ struct Layout {
 
 constexpr int SCAN_T = 1024, SCAN_V = 4, SCAN_TILE = SCAN_T * SCAN_V;
 
+// Binning and reorder chunks: BIN_T threads x BIN_ITEMS entries per block.
+constexpr int BIN_T = 256, BIN_ITEMS = 4, BIN_CHUNK = BIN_T * BIN_ITEMS;
+
 Layout layout_of(const mpcd_sys *s)
 {
     Layout L;
@@ -278,7 +281,7 @@ Layout layout_of(const mpcd_sys *s)
         return o;
     };
     const int64_t NT = s->n_solvent + s->n_sites;
-    const int64_t nbc = (s->n_cells + SCAN_TILE - 1) / SCAN_TILE, nbp = (NT + SCAN_TILE - 1) / SCAN_TILE;
+    const int64_t nbc = (s->n_cells + SCAN_TILE - 1) / SCAN_TILE, nbp = (NT + BIN_CHUNK - 1) / BIN_CHUNK;
     const int64_t nb = nbc > nbp ? nbc : nbp;
     L.status = take(256);
     L.shift = take(sizeof(double) * 3 * (size_t)s->nsys);
@@ -377,19 +380,20 @@ inline unsigned xcd_grid(int64_t ntiles)
 // nothing.  (Philox4x64 is a long chain of quarter-rate 64-bit multiplies, so
 // the draws run in high-occupancy kernels rather than inside the collision.)
 __device__ __forceinline__ void draw_cell(const SysDev &s, uint64_t seed, double kT_cell, uint64_t step, int64_t gc,
-                                          int n, double *draws, uint32_t &st)
+                                          int n, int mode, double *draws, uint32_t &st)
 {
-    if (n < 2) return;
     const int64_t C = s.C;
     const int r = find_sys(s.cell_off, s.nsys, gc);
     const uint64_t cl = (uint64_t)(gc - s.cell_off[r]);
     const uint64_t rep = s.replica0 + (uint64_t)r;
-    double nax[3];
-    st |= cell_axis(seed, step, cl, rep, nax);
-    draws[gc] = nax[0];
-    draws[C + gc] = nax[1];
-    draws[2 * C + gc] = nax[2];
-    if (kT_cell > 0.0) {
+    if (mode & 1) {
+        double nax[3];
+        st |= cell_axis(seed, step, cl, rep, nax);
+        draws[gc] = nax[0];
+        draws[C + gc] = nax[1];
+        draws[2 * C + gc] = nax[2];
+    }
+    if ((mode & 2) && kT_cell > 0.0 && n >= 2) {
         double g;
         st |= gamma_variate(seed, step, cl, rep, 0.5 * (double)(3 * (n - 1)), &g);
         draws[3 * C + gc] = g;
@@ -407,27 +411,74 @@ __device__ __forceinline__ void draw_cell(const SysDev &s, uint64_t seed, double
 //  2. k_scan_reduce / k_scan_down: exclusive scan of the counts -> cell_start
 //     (each block adds the earlier tile totals itself) and clears the counts.
 //  3. k_bin_scatter: perm[cell_start[cell] + slot] = particle.
-constexpr int BIN_T = 256, BIN_ITEMS = 4, BIN_CHUNK = BIN_T * BIN_ITEMS;
+
+// Grid shift of system r at a step: a pure function of (seed, step, replica).
+__device__ __forceinline__ void shift_of(const SysDev &s, uint64_t seed, uint64_t step, int r, double sh[3])
+{
+    const Words w = rng_draw(seed, RNG_SHIFT, step, 0, s.replica0 + (uint64_t)r, 0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sh[k] = shift_component(w.w[k], s.a);
+}
+
+// Shifts for a block: taken from `arr` when given; otherwise lane 0 draws the
+// shifts of systems ra and rb into LDS, and a particle of any other system
+// (a chunk spanning three or more systems) draws its own.
+struct BlockShift {
+    const double *arr;
+    const double *lds;  // [2][3]
+    int ra, rb;
+    uint64_t seed, step;
+    __device__ void get(const SysDev &s, int r, double sh[3]) const
+    {
+        if (arr) { sh[0] = arr[3 * r]; sh[1] = arr[3 * r + 1]; sh[2] = arr[3 * r + 2]; }
+        else if (r == ra) { sh[0] = lds[0]; sh[1] = lds[1]; sh[2] = lds[2]; }
+        else if (r == rb) { sh[0] = lds[3]; sh[1] = lds[4]; sh[2] = lds[5]; }
+        else shift_of(s, seed, step, r, sh);
+    }
+};
 
 template <typename Real>
-__global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, const Real *xs,
-                                                     const int32_t *site_body, const double *shift,
-                                                     int32_t *counts, int32_t *cellid, int32_t *slot,
-                                                     uint32_t *status)
+__device__ __forceinline__ int32_t cell_of_pos(const SysDev &s, int r, Real p0, Real p1, Real p2, const double sh[3],
+                                               uint32_t &st)
 {
-    uint32_t st = 0;
-    const int64_t NT = s.N + s.S;
+    const int nx = s.ncell[3 * r], ny = s.ncell[3 * r + 1], nz = s.ncell[3 * r + 2];
+    const int jx = axis_cell(p0, sh[0], s.a, nx, st);
+    const int jy = axis_cell(p1, sh[1], s.a, ny, st);
+    const int jz = axis_cell(p2, sh[2], s.a, nz, st);
+    return (int32_t)(s.cell_off[r] + ((int64_t)jz * ny + jy) * nx + jx);
+}
+
+// Slots for one group of 64 lanes: one atomic per run of equal cells.
+__device__ __forceinline__ void run_slots(int32_t gc, int32_t *counts, int &hl, int &base)
+{
     const int lane = threadIdx.x & 63;
-    const int64_t wbase = (int64_t)blockIdx.x * BIN_CHUNK + (threadIdx.x & ~63);
+    const unsigned long long le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int32_t prev = __shfl_up(gc, 1, 64);
+    const bool head = (lane == 0) || (prev != gc);
+    const unsigned long long heads = __ballot(head);
+    hl = 63 - __clzll(heads & le);
+    const unsigned long long above = heads & ~le;
+    const int nh = above ? (__ffsll((long long)above) - 1) : 64;
+    base = (head && gc >= 0) ? atomicAdd(&counts[gc], nh - hl) : 0;
+}
+
+// One chunk of BIN_CHUNK particles starting at kbase (< k1).
+template <typename Real, bool SITES>
+__device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const int32_t *site_body,
+                          const BlockShift &bs, int32_t *counts, int32_t *cellid, int32_t *slot, int64_t kbase,
+                          int64_t k1, uint32_t &st)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = kbase + (threadIdx.x & ~63);
     int32_t gc[BIN_ITEMS];
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const int64_t k = wbase + (int64_t)j * BIN_T + lane;
         gc[j] = -1;
-        if (k < NT) {
+        if (k < k1) {
             int r;
             Real p0, p1, p2;
-            if (k < s.N) {
+            if (!SITES || k < s.N) {
                 r = find_sys(s.solv_off, s.nsys, k);
                 p0 = x[k]; p1 = x[s.N + k]; p2 = x[2 * s.N + k];
             } else {
@@ -435,41 +486,53 @@ __global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, co
                 r = find_sys(s.body_off, s.nsys, (int64_t)site_body[q]);
                 p0 = xs[q]; p1 = xs[s.S + q]; p2 = xs[2 * s.S + q];
             }
-            const int nx = s.ncell[3 * r], ny = s.ncell[3 * r + 1], nz = s.ncell[3 * r + 2];
-            const int jx = axis_cell(p0, shift[3 * r], s.a, nx, st);
-            const int jy = axis_cell(p1, shift[3 * r + 1], s.a, ny, st);
-            const int jz = axis_cell(p2, shift[3 * r + 2], s.a, nz, st);
-            gc[j] = (int32_t)(s.cell_off[r] + ((int64_t)jz * ny + jy) * nx + jx);
+            double sh[3];
+            bs.get(s, r, sh);
+            gc[j] = cell_of_pos<Real>(s, r, p0, p1, p2, sh, st);
         }
     }
     int hl[BIN_ITEMS], base[BIN_ITEMS];
-    const unsigned long long le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
 #pragma unroll
-    for (int j = 0; j < BIN_ITEMS; ++j) {
-        const int32_t prev = __shfl_up(gc[j], 1, 64);
-        const bool head = (lane == 0) || (prev != gc[j]);
-        const unsigned long long heads = __ballot(head);
-        hl[j] = 63 - __clzll(heads & le);
-        const unsigned long long above = heads & ~le;
-        const int nh = above ? (__ffsll((long long)above) - 1) : 64;
-        base[j] = (head && gc[j] >= 0) ? atomicAdd(&counts[gc[j]], nh - hl[j]) : 0;
-    }
+    for (int j = 0; j < BIN_ITEMS; ++j) run_slots(gc[j], counts, hl[j], base[j]);
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const int b = __shfl(base[j], hl[j], 64);
         const int64_t k = wbase + (int64_t)j * BIN_T + lane;
-        if (k < NT) {
+        if (k < k1) {
             slot[k] = b + (lane - hl[j]);
             cellid[k] = gc[j];
         }
     }
+}
+
+// Systems of the first and last particle of [k0, k1) (k1 > k0).
+__device__ __forceinline__ void chunk_systems(const SysDev &s, const int32_t *site_body, int64_t k0, int64_t k1,
+                                              int &ra, int &rb)
+{
+    ra = k0 < s.N ? find_sys(s.solv_off, s.nsys, k0) : find_sys(s.body_off, s.nsys, (int64_t)site_body[k0 - s.N]);
+    const int64_t kl = k1 - 1;
+    rb = kl < s.N ? find_sys(s.solv_off, s.nsys, kl) : find_sys(s.body_off, s.nsys, (int64_t)site_body[kl - s.N]);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, const Real *xs,
+                                                     const int32_t *site_body, const double *shift,
+                                                     int32_t *counts, int32_t *cellid, int32_t *slot,
+                                                     uint32_t *status, int64_t k0, int64_t k1)
+{
+    uint32_t st = 0;
+    BlockShift bs;
+    bs.arr = shift; bs.lds = nullptr; bs.ra = bs.rb = -1; bs.seed = 0; bs.step = 0;
+    bin_chunk<Real, true>(s, x, xs, site_body, bs, counts, cellid, slot, k0 + (int64_t)blockIdx.x * BIN_CHUNK, k1, st);
     flag(status, st);
 }
 
-// Block-wide exclusive scan of one value per thread (blockDim = SCAN_T, wave64).
+// Block-wide exclusive scan of one value per thread (blockDim = NTHR, wave64).
+template <int NTHR = SCAN_T>
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *total)
 {
-    __shared__ int32_t wsum[SCAN_T / 64];
+    constexpr int NW = NTHR / 64;
+    __shared__ int32_t wsum[NW];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int32_t inc = v;
 #pragma unroll
@@ -480,15 +543,15 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *tota
     if (lane == 63) wsum[wid] = inc;
     __syncthreads();
     if (wid == 0) {
-        int32_t w = (lane < SCAN_T / 64) ? wsum[lane] : 0;
+        int32_t w = (lane < NW) ? wsum[lane] : 0;
         int32_t wi = w;
 #pragma unroll
-        for (int d = 1; d < SCAN_T / 64; d <<= 1) {
+        for (int d = 1; d < NW; d <<= 1) {
             const int32_t y = __shfl_up(wi, d, 64);
             if (lane >= d) wi += y;
         }
-        if (lane < SCAN_T / 64) wsum[lane] = wi - w;
-        if (lane == SCAN_T / 64 - 1) *total = wi;
+        if (lane < NW) wsum[lane] = wi - w;
+        if (lane == NW - 1) *total = wi;
     }
     __syncthreads();
     const int32_t res = wsum[wid] + inc - v;
@@ -564,52 +627,62 @@ __global__ __launch_bounds__(BIN_T) void k_bin_scatter(int64_t NT, const int32_t
 // order), carrying their identity tags.  Keeps gathers and atomics local as
 // the solvent diffuses; identities keep the FP64 summation order unchanged.
 
-__global__ __launch_bounds__(SCAN_T) void k_reorder_count(const int32_t *perm, int64_t NT, int64_t N, int32_t *partial)
+// Solvent count per BIN_CHUNK entries of the permutation.
+__global__ __launch_bounds__(BIN_T) void k_reorder_count(const int32_t *perm, int64_t NT, int64_t N, int32_t *partial)
 {
     __shared__ int32_t tot;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
+    const int64_t base = (int64_t)blockIdx.x * BIN_CHUNK;
     int32_t v = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_V; ++i)
-        if (base + i < NT && perm[base + i] < N) v += 1;
-    (void)block_exclusive_scan(v, &tot);
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int64_t i = base + (int64_t)j * BIN_T + threadIdx.x;
+        if (i < NT && perm[i] < N) v += 1;
+    }
+    (void)block_exclusive_scan<BIN_T>(v, &tot);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-template <typename Real>
-__global__ __launch_bounds__(SCAN_T) void k_reorder_gather(const int32_t *perm, int64_t NT, int64_t N,
-                                                           const int32_t *partial, const Real *x, const Real *v,
-                                                           const int32_t *tag, Real *tx, Real *tv, int32_t *ttag)
+// One block: exclusive scan of nb partial sums in place.
+__global__ __launch_bounds__(SCAN_T) void k_partials_scan(int32_t *partial, int64_t nb)
 {
     __shared__ int32_t tot;
-    __shared__ int32_t pre;
     int32_t carry = 0;
-    for (int64_t b0 = 0; b0 < (int64_t)blockIdx.x; b0 += SCAN_T) {
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_T) {
         const int64_t i = b0 + threadIdx.x;
-        (void)block_exclusive_scan(i < (int64_t)blockIdx.x ? partial[i] : 0, &tot);
+        const int32_t v = (i < nb) ? partial[i] : 0;
+        const int32_t ex = block_exclusive_scan(v, &tot);
+        if (i < nb) partial[i] = carry + ex;
         carry += tot;
+        __syncthreads();
     }
-    if (threadIdx.x == 0) pre = carry;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
-    int32_t k[SCAN_V];
-    int32_t v0 = 0;
+}
+
+// Gather the solvent in permutation order into the staging buffers.
+template <typename Real>
+__global__ __launch_bounds__(BIN_T) void k_reorder_gather(const int32_t *perm, int64_t NT, int64_t N,
+                                                          const int32_t *partial, const Real *x, const Real *v,
+                                                          const int32_t *tag, Real *tx, Real *tv, int32_t *ttag)
+{
+    __shared__ int32_t tot;
+    const int64_t base = (int64_t)blockIdx.x * BIN_CHUNK + (int64_t)threadIdx.x * BIN_ITEMS;
+    int32_t k[BIN_ITEMS];
+    int32_t cnt = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_V; ++i) {
-        k[i] = (base + i < NT) ? perm[base + i] : -1;
-        if (k[i] >= 0 && k[i] < N) v0 += 1;
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        k[j] = (base + j < NT) ? perm[base + j] : -1;
+        if (k[j] >= 0 && k[j] < N) cnt += 1;
     }
-    int32_t dst = pre + block_exclusive_scan(v0, &tot);
+    int32_t dst = partial[blockIdx.x] + block_exclusive_scan<BIN_T>(cnt, &tot);
 #pragma unroll
-    for (int i = 0; i < SCAN_V; ++i) {
-        if (k[i] >= 0 && k[i] < N) {
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        if (k[j] >= 0 && k[j] < N) {
             if (dst < N) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    tx[d * N + dst] = x[d * N + k[i]];
-                    tv[d * N + dst] = v[d * N + k[i]];
+                    tx[d * N + dst] = x[d * N + k[j]];
+                    tv[d * N + dst] = v[d * N + k[j]];
                 }
-                ttag[dst] = tag[k[i]];
+                ttag[dst] = tag[k[j]];
             }
             dst += 1;
         }
@@ -663,6 +736,7 @@ struct CollideArgs {
     uint64_t seed;
     const uint64_t *d_step;
     uint32_t *status;
+    uint64_t *advance_step;  // when set, block 0 advances the step counter (graph schedule)
 };
 
 // Identity order key of particle k: solvent tag (or index), sites N_total + j.
@@ -672,13 +746,46 @@ __device__ __forceinline__ uint32_t ident(const CollideArgs &A, int32_t k)
 }
 
 // Per-cell draws for the standalone collision entry point.
-__global__ void k_cell_draws(CollideArgs A, double *draws)
+// mode 1: the axis of every cell (independent of the binning); 2: the gamma
+// variates (needs this step's cell counts); 3: both.  Extra axis draws for
+// cells with fewer than two members are harmless: each draw is a pure
+// function of (seed, step, cell).
+__global__ void k_cell_draws(CollideArgs A, double *draws, int mode)
 {
     const SysDev &s = A.s;
     uint32_t st = 0;
     const uint64_t step = *A.d_step;
-    for (int64_t gc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gc < s.C; gc += (int64_t)gridDim.x * blockDim.x)
-        draw_cell(s, A.seed, A.kT_cell, step, gc, A.cell_start[gc + 1] - A.cell_start[gc], draws, st);
+    for (int64_t gc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gc < s.C; gc += (int64_t)gridDim.x * blockDim.x) {
+        const int n = (mode & 2) ? A.cell_start[gc + 1] - A.cell_start[gc] : 0;
+        draw_cell(s, A.seed, A.kT_cell, step, gc, n, mode, draws, st);
+    }
+    flag(A.status, st);
+}
+
+// Scatter (blocks [0, nscatter)) fused with the per-cell draws (the other
+// blocks): independent work, one launch; the draws' ALU work overlaps the
+// scatter's memory traffic.
+__global__ __launch_bounds__(BIN_T) void k_scatter_draws(int64_t NT, const int32_t *cellid, const int32_t *slot,
+                                                         int32_t *perm, int nscatter, CollideArgs A, double *draws)
+{
+    uint32_t st = 0;
+    if ((int)blockIdx.x < nscatter) {
+#pragma unroll
+        for (int j = 0; j < BIN_ITEMS; ++j) {
+            const int64_t k = (int64_t)blockIdx.x * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
+            if (k < NT) {
+                const int64_t pos = (int64_t)A.cell_start[cellid[k]] + slot[k];
+                if (pos >= 0 && pos < NT) perm[pos] = (int32_t)k;
+                else st |= ST_BINERR;
+            }
+        }
+    } else {
+        const SysDev &s = A.s;
+        const uint64_t step = *A.d_step;
+        const int64_t stride = (int64_t)(gridDim.x - nscatter) * blockDim.x;
+        for (int64_t gc = (int64_t)(blockIdx.x - nscatter) * blockDim.x + threadIdx.x; gc < s.C; gc += stride)
+            draw_cell(s, A.seed, A.kT_cell, step, gc, A.cell_start[gc + 1] - A.cell_start[gc], 3, draws, st);
+    }
     flag(A.status, st);
 }
 
@@ -889,7 +996,7 @@ __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
     L.idx = o; o += align16(sizeof(int) * (size_t)cap);
     L.cl = o; o += align16(sizeof(uint16_t) * (size_t)cap);
     L.v = o; o += align16((f64 ? 8 : 4) * 3 * (size_t)cap);
-    L.keyacc = o; o += align16(f64 ? sizeof(uint64_t) * (size_t)cap : sizeof(long long) * 5 * (size_t)cpb);
+    L.keyacc = o; o += align16(f64 ? sizeof(uint64_t) * (size_t)cap : 0);
     L.par = o; o += align16(f64 ? sizeof(double) * 13 * (size_t)cpb : sizeof(float) * 12 * (size_t)cpb);
     L.r = o; o += align16(sizeof(int) * (size_t)cpb);
     L.end = o;
@@ -909,6 +1016,7 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
 {
     constexpr bool F64 = sizeof(Real) == 8;
     extern __shared__ __align__(16) unsigned char smem[];
+    if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) *A.advance_step = *A.advance_step + 1;
     const int tile = tile_of_block(T.ntiles);
     if (tile >= T.ntiles) return;
     const SysDev &s = A.s;
@@ -932,54 +1040,45 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
     uint16_t *s_cl = (uint16_t *)(smem + Lo.cl);
     Real *s_v = (Real *)(smem + Lo.v);
     uint64_t *s_key = (uint64_t *)(smem + Lo.keyacc);
-    long long *s_acc = (long long *)(smem + Lo.keyacc);
     int *s_r = (int *)(smem + Lo.r);
     const int64_t N = s.N, S = s.S;
 
-    // phase 0: cell ranges, cell of each member slot
+    // phase 0: the tile's cell ranges; this lane's cell system and draws
     for (int c = t; c <= nc; c += TILE_T) s_cs[c] = A.cell_start[c0 + c] - m0;
-    if constexpr (!F64) {
-        for (int c = t; c < 5 * nc; c += TILE_T) s_acc[c] = 0;
-    }
-    __syncthreads();
+    double nax[3] = {0.0, 0.0, 1.0}, gvar = 0.0;
     if (t < nc) {
-        for (int i = s_cs[t]; i < s_cs[t + 1]; ++i) s_cl[i] = (uint16_t)t;
+        const int64_t gc = c0 + t;
+        s_r[t] = find_sys(s.cell_off, s.nsys, gc);
+        read_axis(A, gc, nax);
+        if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
     }
     __syncthreads();
 
-    // phase 1: batched gathers; per-cell draws overlap their latency
+    // phase 1: batched gathers of v (and x for the streaming); slot -> cell map
     int kk[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int i = t + j * TILE_T;
         kk[j] = (i < nm) ? A.perm[m0 + i] : -1;
     }
-    Real va[ITEMS][3];
-    double ma[ITEMS];
+    Real va[ITEMS][3], xo[ITEMS][3];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int32_t k = kk[j];
         if (k >= 0) {
             if (k < N) {
                 va[j][0] = v[k]; va[j][1] = v[N + k]; va[j][2] = v[2 * N + k];
-                ma[j] = s.m;
+                if (xstream) {
+                    xo[j][0] = xstream[k]; xo[j][1] = xstream[N + k]; xo[j][2] = xstream[2 * N + k];
+                }
             } else {
                 const int64_t q = k - N;
                 va[j][0] = vs[q]; va[j][1] = vs[S + q]; va[j][2] = vs[2 * S + q];
-                ma[j] = A.site_m[q];
             }
         }
     }
-    // this lane's cell: system index and the pre-drawn axis / gamma variate
-    double nax[3] = {0.0, 0.0, 1.0}, gvar = 0.0;
-    if (t < nc) {
-        const int64_t gc = c0 + t;
-        s_r[t] = find_sys(s.cell_off, s.nsys, gc);
-        if (s_cs[t + 1] - s_cs[t] >= 2) {
-            read_axis(A, gc, nax);
-            if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
-        }
-    }
+    const int cb = (t < nc) ? s_cs[t] : 0, ce = (t < nc) ? s_cs[t + 1] : 0;
+    for (int i = cb; i < ce; ++i) s_cl[i] = (uint16_t)t;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int i = t + j * TILE_T;
@@ -987,28 +1086,19 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
             const int32_t k = kk[j];
             s_idx[i] = k;
             s_v[i] = va[j][0]; s_v[cap + i] = va[j][1]; s_v[2 * cap + i] = va[j][2];
-            if constexpr (F64) {
-                s_key[i] = ((uint64_t)ident(A, k) << 32) | (uint32_t)i;
-            } else {
-                long long q[5];
-                fixed_terms(ma[j], (float)va[j][0], (float)va[j][1], (float)va[j][2], q, st);
-                const int c = s_cl[i];
-#pragma unroll
-                for (int w = 0; w < 5; ++w)
-                    atomicAdd((unsigned long long *)&s_acc[w * nc + c], (unsigned long long)q[w]);
-            }
+            if constexpr (F64) s_key[i] = ((uint64_t)ident(A, k) << 32) | (uint32_t)i;
         }
     }
     __syncthreads();
 
     // phase 2: one lane per cell
     if (t < nc) {
-        const int b = s_cs[t], e = s_cs[t + 1], n = e - b;
+        const int b = cb, e = ce, n = e - b;
         if (n >= 2) {
-            const double g = gvar;
             const Rot R = rotation(nax, A.cos_a, A.sin_a);
             if constexpr (F64) {
                 double *par = (double *)(smem + Lo.par) + 13 * t;
+                // ascending identity: insertion into the (nearly ordered) segment
                 for (int i = b + 1; i < e; ++i) {
                     const uint64_t key = s_key[i];
                     int pos = i;
@@ -1040,7 +1130,7 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
                         Es = Es + (k < N ? s.m : A.site_m[k - N]) * ((d0 * d0 + d1 * d1) + d2 * d2);
                     }
                     const double E = 0.5 * Es;
-                    if (E > 0.0) lam = sqrt((A.kT_cell * g) / E);
+                    if (E > 0.0) lam = sqrt((A.kT_cell * gvar) / E);
                 }
                 par[0] = u0; par[1] = u1; par[2] = u2; par[3] = lam;
 #pragma unroll
@@ -1048,16 +1138,24 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
 #pragma unroll
                     for (int j = 0; j < 3; ++j) par[4 + 3 * i + j] = R.R[i][j];
             } else {
+                // exact int64 fixed-point sums over the cell's contiguous members
+                long long q[5] = {0, 0, 0, 0, 0};
+                for (int i = b; i < e; ++i) {
+                    const int32_t k = s_idx[i];
+                    long long w[5];
+                    fixed_terms(k < N ? s.m : A.site_m[k - N], (float)s_v[i], (float)s_v[cap + i],
+                                (float)s_v[2 * cap + i], w, st);
+#pragma unroll
+                    for (int z = 0; z < 5; ++z) q[z] += w[z];
+                }
                 float *par = (float *)(smem + Lo.par) + 12 * t;
-                const long long q0 = s_acc[t], q1 = s_acc[nc + t], q2 = s_acc[2 * nc + t],
-                                q3 = s_acc[3 * nc + t], q4 = s_acc[4 * nc + t];
-                const double Md = (double)q0;
-                const double u0 = (double)q1 / Md, u1 = (double)q2 / Md, u2 = (double)q3 / Md;
+                const double Md = (double)q[0];
+                const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
                 double lam = 1.0;
                 if (A.kT_cell > 0.0) {
-                    const double P0 = (double)q1 * 0x1p-32, P1 = (double)q2 * 0x1p-32, P2 = (double)q3 * 0x1p-32;
-                    const double E = 0.5 * ((double)q4 * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
-                    if (E > 0.0) lam = sqrt((A.kT_cell * g) / E);
+                    const double P0 = (double)q[1] * 0x1p-32, P1 = (double)q[2] * 0x1p-32, P2 = (double)q[3] * 0x1p-32;
+                    const double E = 0.5 * ((double)q[4] * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
+                    if (E > 0.0) lam = sqrt((A.kT_cell * gvar) / E);
                 }
                 par[0] = (float)u0; par[1] = (float)u1; par[2] = (float)u2;
 #pragma unroll
@@ -1069,71 +1167,48 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
     }
     __syncthreads();
 
-    // phase 3: rotate, write back, stream
-    Real vn[ITEMS][3];
-    bool moved[ITEMS];
+    // phase 3: rotate, stream, write back
+    const Real dtr = (Real)A.dt;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int i = t + j * TILE_T;
-        moved[j] = false;
-        if (i < nm) {
-            const int c = s_cl[i];
-            vn[j][0] = s_v[i]; vn[j][1] = s_v[cap + i]; vn[j][2] = s_v[2 * cap + i];
-            if (s_cs[c + 1] - s_cs[c] >= 2) {
-                moved[j] = true;
-                if constexpr (F64) {
-                    const double *par = (const double *)(smem + Lo.par) + 13 * c;
-                    const double dl[3] = {vn[j][0] - par[0], vn[j][1] - par[1], vn[j][2] - par[2]};
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const double rr = (par[4 + 3 * d] * dl[0] + par[5 + 3 * d] * dl[1]) + par[6 + 3 * d] * dl[2];
-                        vn[j][d] = par[d] + par[3] * rr;
-                        if (!(vn[j][d] - vn[j][d] == 0.0)) st |= ST_NONFINITE;
-                    }
-                } else {
-                    const float *par = (const float *)(smem + Lo.par) + 12 * c;
-                    const float dl[3] = {vn[j][0] - par[0], vn[j][1] - par[1], vn[j][2] - par[2]};
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        vn[j][d] = par[d] + ((par[3 + 3 * d] * dl[0] + par[4 + 3 * d] * dl[1]) + par[5 + 3 * d] * dl[2]);
-                        if (!(vn[j][d] - vn[j][d] == 0.0f)) st |= ST_NONFINITE;
-                    }
-                }
-            }
-        }
-    }
-    if (xstream) {
-        Real xo[ITEMS][3];
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int32_t k = kk[j];
-            if (k >= 0 && k < N) {
-                xo[j][0] = xstream[k]; xo[j][1] = xstream[N + k]; xo[j][2] = xstream[2 * N + k];
-            }
-        }
-        const Real dtr = (Real)A.dt;
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int32_t k = kk[j];
-            if (k >= 0 && k < N) {
-                const int r = s_r[s_cl[t + j * TILE_T]];
+        const int32_t k = kk[j];
+        if (i >= nm) continue;
+        const int c = s_cl[i];
+        Real vn[3] = {va[j][0], va[j][1], va[j][2]};
+        const bool moved = (s_cs[c + 1] - s_cs[c]) >= 2;
+        if (moved) {
+            if constexpr (F64) {
+                const double *par = (const double *)(smem + Lo.par) + 13 * c;
+                const double dl[3] = {vn[0] - par[0], vn[1] - par[1], vn[2] - par[2]};
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
-                    xstream[d * N + k] = RealOps<Real>::wrap(xo[j][d] + vn[j][d] * dtr, L, st);
+                    const double rr = (par[4 + 3 * d] * dl[0] + par[5 + 3 * d] * dl[1]) + par[6 + 3 * d] * dl[2];
+                    vn[d] = par[d] + par[3] * rr;
+                    if (!(vn[d] - vn[d] == 0.0)) st |= ST_NONFINITE;
+                }
+            } else {
+                const float *par = (const float *)(smem + Lo.par) + 12 * c;
+                const float dl[3] = {vn[0] - par[0], vn[1] - par[1], vn[2] - par[2]};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    vn[d] = par[d] + ((par[3 + 3 * d] * dl[0] + par[4 + 3 * d] * dl[1]) + par[5 + 3 * d] * dl[2]);
+                    if (!(vn[d] - vn[d] == 0.0f)) st |= ST_NONFINITE;
                 }
             }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int32_t k = kk[j];
-        if (moved[j]) {
             if (k < N) {
-                v[k] = vn[j][0]; v[N + k] = vn[j][1]; v[2 * N + k] = vn[j][2];
+                v[k] = vn[0]; v[N + k] = vn[1]; v[2 * N + k] = vn[2];
             } else {
                 const int64_t q = k - N;
-                vs[q] = vn[j][0]; vs[S + q] = vn[j][1]; vs[2 * S + q] = vn[j][2];
+                vs[q] = vn[0]; vs[S + q] = vn[1]; vs[2 * S + q] = vn[2];
+            }
+        }
+        if (xstream && k < N) {
+            const int r = s_r[c];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
+                xstream[d * N + k] = RealOps<Real>::wrap(xo[j][d] + vn[d] * dtr, L, st);
             }
         }
     }
@@ -1153,6 +1228,7 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
 
 constexpr int WAVE = 64;
 constexpr int BODY_T = 256;
+static_assert(BODY_T == BIN_T, "k_prep bins solvent with BODY_T-thread blocks");
 constexpr int SH_PAD = BODY_T + 1;  // row padding against LDS bank conflicts
 
 __device__ __forceinline__ void draw_shifts(const SysDev &s, uint64_t seed, uint64_t step, double *shift)
@@ -1174,21 +1250,25 @@ __device__ __forceinline__ void ordered_add(const double *sh, int cnt, double &a
     }
 }
 
+// Thermalization of body b by one BODY_T block.  With `counts` set, the
+// block also bins its sites (cell from the stored site position and the grid
+// shift `bsh` of the body's system, which must be visible after the first
+// barrier).
+struct ThermLds {
+    double sh[6 * SH_PAD];
+    double sacc[6];
+    double dvw[6];
+};
+
 template <typename Real>
-__global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, double kT, int thermalize, uint64_t seed,
-                                                       const uint64_t *d_step, Real *xs, Real *vs, double *site_d,
-                                                       double *vpre, double *shift, uint32_t *status)
+__device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, double kT, int thermalize,
+                                uint64_t seed, uint64_t step, Real *xs, Real *vs, double *site_d, double *vpre,
+                                const double *bsh, int32_t *counts, int32_t *cellid, int32_t *slot, ThermLds &lds,
+                                uint32_t &st)
 {
-    __shared__ double sh[6 * SH_PAD];
-    __shared__ double sacc[6];
-    __shared__ double dvw[6];
-    const uint64_t step = *d_step;
-    if (shift && blockIdx.x == 0) draw_shifts(s, seed, step, shift);
-    const int64_t b = blockIdx.x;
-    if (b >= s.B) return;
+    double *sh = lds.sh, *sacc = lds.sacc, *dvw = lds.dvw;
     const int t = threadIdx.x;
     const int64_t B = s.B, S = s.S;
-    uint32_t st = 0;
     const int r = find_sys(s.body_off, s.nsys, b);
     double q[4], A[3][3], R[3], Lbox[3];
 #pragma unroll
@@ -1205,6 +1285,7 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
     double acc = 0.0;
     for (int64_t c0 = j0; c0 < j1; c0 += BODY_T) {
         const int64_t j = c0 + t;
+        Real xr[3] = {(Real)0, (Real)0, (Real)0};
         if (j < j1) {
             const double dh[3] = {bd.site_d[j], bd.site_d[S + j], bd.site_d[2 * S + j]};
             double d[3], vt[3] = {0.0, 0.0, 0.0}, pv[3], c[3];
@@ -1220,7 +1301,8 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 site_d[k * S + j] = d[k];
-                xs[k * S + j] = (Real)wrap_d(R[k] + d[k], Lbox[k], st);
+                xr[k] = (Real)wrap_d(R[k] + d[k], Lbox[k], st);
+                xs[k * S + j] = xr[k];
                 vpre[k * S + j] = vt[k];
                 pv[k] = mj * vt[k];
             }
@@ -1229,6 +1311,17 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
             for (int k = 0; k < 3; ++k) { sh[k * SH_PAD + t] = pv[k]; sh[(3 + k) * SH_PAD + t] = c[k]; }
         }
         __syncthreads();
+        if (counts) {
+            // bin this chunk's sites (all lanes take part in the run detection)
+            const int32_t gc = (j < j1) ? cell_of_pos<Real>(s, r, xr[0], xr[1], xr[2], bsh, st) : -1;
+            int hl, base;
+            run_slots(gc, counts, hl, base);
+            const int bb = __shfl(base, hl, 64);
+            if (j < j1) {
+                slot[s.N + j] = bb + ((threadIdx.x & 63) - hl);
+                cellid[s.N + j] = gc;
+            }
+        }
         ordered_add(sh, (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T), acc);
         __syncthreads();
     }
@@ -1269,6 +1362,59 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
             vs[k * S + j] = vr;
             vpre[k * S + j] = (double)vr;
         }
+    }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, double kT, int thermalize, uint64_t seed,
+                                                       const uint64_t *d_step, Real *xs, Real *vs, double *site_d,
+                                                       double *vpre, uint32_t *status)
+{
+    __shared__ ThermLds lds;
+    const int64_t b = blockIdx.x;
+    if (b >= s.B) return;
+    uint32_t st = 0;
+    thermalize_body<Real>(s, bd, b, kT, thermalize, seed, *d_step, xs, vs, site_d, vpre, nullptr, nullptr, nullptr,
+                          nullptr, lds, st);
+    flag(status, st);
+}
+
+// First kernel of a step: blocks [0, B) thermalize one body each and bin its
+// sites; the remaining blocks bin BIN_CHUNK solvent particles each.  Every
+// block draws the grid shifts it needs; block 0 also stores them.
+template <typename Real>
+__global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT, int thermalize, uint64_t seed,
+                                                 const uint64_t *d_step, const Real *x, Real *xs, Real *vs,
+                                                 double *site_d, double *vpre, int32_t *counts, int32_t *cellid,
+                                                 int32_t *slot, double *shift_out, uint32_t *status)
+{
+    __shared__ double bsh[6];
+    __shared__ int bsr[2];
+    __shared__ ThermLds lds;
+    const uint64_t step = *d_step;
+    uint32_t st = 0;
+    if (blockIdx.x == 0) draw_shifts(s, seed, step, shift_out);
+    if ((int64_t)blockIdx.x < s.B) {
+        const int64_t b = blockIdx.x;
+        if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0))
+            shift_of(s, seed, step, find_sys(s.body_off, s.nsys, b), bsh);
+        thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid, slot,
+                              lds, st);
+    } else {
+        const int64_t kbase = ((int64_t)blockIdx.x - s.B) * BIN_CHUNK;
+        const int64_t k1 = s.N;
+        if (threadIdx.x == 0) {
+            int ra, rb;
+            chunk_systems(s, nullptr, kbase, (kbase + BIN_CHUNK < k1) ? kbase + BIN_CHUNK : k1, ra, rb);
+            bsr[0] = ra;
+            bsr[1] = rb;
+            shift_of(s, seed, step, ra, bsh);
+            if (rb != ra) shift_of(s, seed, step, rb, bsh + 3);
+        }
+        __syncthreads();
+        BlockShift bs;
+        bs.arr = nullptr; bs.lds = bsh; bs.ra = bsr[0]; bs.rb = bsr[1]; bs.seed = seed; bs.step = step;
+        bin_chunk<Real, false>(s, x, nullptr, nullptr, bs, counts, cellid, slot, kbase, k1, st);
     }
     flag(status, st);
 }
@@ -1674,129 +1820,102 @@ int mpcd_stream(void *stream, const mpcd_sys *sys, void *x, const void *v, doubl
     return launch_check();
 }
 
-static int bin_impl(void *stream, const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
-                    uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes, bool draw_shift)
-{
-    TRY(check_sys(sys));
-    TRY(check_ws(sys, ws, ws_bytes));
-    if (!ok_arr(x, sys->n_solvent, esize(sys)) || !ok_arr(xs, sys->n_sites, esize(sys)) || !d_step)
-        return MPCD_EINVAL;
-    if (sys->n_sites > 0 && (!bodies || !bodies->site_body)) return MPCD_EINVAL;
-    const Layout L = layout_of(sys);
-    const SysDev sd = make_sysdev(sys);
-    hipStream_t st = (hipStream_t)stream;
-    const int64_t NT = sys->n_solvent + sys->n_sites, C = sys->n_cells;
-    const int64_t nb = (C + SCAN_TILE - 1) / SCAN_TILE;
-    double *shift = at<double>(ws, L.shift);
-    int32_t *counts = at<int32_t>(ws, L.counts), *partial = at<int32_t>(ws, L.partial);
-    int32_t *cs = at<int32_t>(ws, L.cell_start), *cellid = at<int32_t>(ws, L.cellid);
-    int32_t *slot = at<int32_t>(ws, L.slot), *perm = at<int32_t>(ws, L.perm);
-    uint32_t *status = at<uint32_t>(ws, L.status);
-    const int32_t *site_body = bodies ? bodies->site_body : nullptr;
+// ---------------------------------------------------------------------------
+// Launch helpers (arguments validated by the callers)
 
-    if (draw_shift)
-        hipLaunchKernelGGL(k_shift, dim3(grid_for(sys->nsys, 64)), dim3(64), 0, st, sd, seed, d_step, shift);
-    const unsigned nchunks = (unsigned)((NT + BIN_CHUNK - 1) / BIN_CHUNK);
-    if (NT > 0) {
-        if (sys->prec == MPCD_F64)
-            hipLaunchKernelGGL(k_bin_count<double>, dim3(nchunks), dim3(BIN_T), 0, st, sd, (const double *)x,
-                               (const double *)xs, site_body, shift, counts, cellid, slot, status);
-        else
-            hipLaunchKernelGGL(k_bin_count<float>, dim3(nchunks), dim3(BIN_T), 0, st, sd, (const float *)x,
-                               (const float *)xs, site_body, shift, counts, cellid, slot, status);
-    }
+struct Ctx {
+    const mpcd_sys *sys;
+    SysDev sd;
+    Layout L;
+    void *ws;
+    uint32_t *status;
+};
+
+static Ctx make_ctx(const mpcd_sys *sys, void *ws)
+{
+    Ctx c;
+    c.sys = sys;
+    c.sd = make_sysdev(sys);
+    c.L = layout_of(sys);
+    c.ws = ws;
+    c.status = at<uint32_t>(ws, c.L.status);
+    return c;
+}
+
+static void launch_shift(const Ctx &c, hipStream_t st, uint64_t seed, const uint64_t *d_step)
+{
+    hipLaunchKernelGGL(k_shift, dim3(grid_for(c.sys->nsys, 64)), dim3(64), 0, st, c.sd, seed, d_step,
+                       at<double>(c.ws, c.L.shift));
+}
+
+static void launch_bin_count(const Ctx &c, hipStream_t st, const void *x, const void *xs, const int32_t *site_body,
+                             int64_t k0, int64_t k1)
+{
+    if (k1 <= k0) return;
+    const unsigned g = (unsigned)((k1 - k0 + BIN_CHUNK - 1) / BIN_CHUNK);
+    double *shift = at<double>(c.ws, c.L.shift);
+    int32_t *counts = at<int32_t>(c.ws, c.L.counts), *cellid = at<int32_t>(c.ws, c.L.cellid);
+    int32_t *slot = at<int32_t>(c.ws, c.L.slot);
+    if (c.sys->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_bin_count<double>, dim3(g), dim3(BIN_T), 0, st, c.sd, (const double *)x,
+                           (const double *)xs, site_body, shift, counts, cellid, slot, c.status, k0, k1);
+    else
+        hipLaunchKernelGGL(k_bin_count<float>, dim3(g), dim3(BIN_T), 0, st, c.sd, (const float *)x,
+                           (const float *)xs, site_body, shift, counts, cellid, slot, c.status, k0, k1);
+}
+
+static void launch_scan(const Ctx &c, hipStream_t st)
+{
+    const int64_t NT = c.sys->n_solvent + c.sys->n_sites, C = c.sys->n_cells;
+    const int64_t nb = (C + SCAN_TILE - 1) / SCAN_TILE;
+    int32_t *counts = at<int32_t>(c.ws, c.L.counts), *partial = at<int32_t>(c.ws, c.L.partial);
+    int32_t *cs = at<int32_t>(c.ws, c.L.cell_start);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial, cs, (int32_t)NT);
-    if (NT > 0)
-        hipLaunchKernelGGL(k_bin_scatter, dim3(nchunks), dim3(BIN_T), 0, st, NT, cellid, slot, cs, perm, status);
-    return launch_check();
 }
 
-int mpcd_bin(void *stream, const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
-             uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes)
+static void launch_scatter(const Ctx &c, hipStream_t st)
 {
-    return bin_impl(stream, sys, x, xs, bodies, seed, d_step, ws, ws_bytes, true);
+    const int64_t NT = c.sys->n_solvent + c.sys->n_sites;
+    if (NT == 0) return;
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((NT + BIN_CHUNK - 1) / BIN_CHUNK)), dim3(BIN_T), 0, st, NT,
+                       at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot), at<int32_t>(c.ws, c.L.cell_start),
+                       at<int32_t>(c.ws, c.L.perm), c.status);
 }
 
-int mpcd_reorder(void *stream, const mpcd_sys *sys, void *x, void *v, int32_t *tag, void *ws, size_t ws_bytes)
+static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bodies *bodies, double cos_a,
+                                double sin_a, double kT_cell, uint64_t seed, const uint64_t *d_step, double dt,
+                                uint64_t *advance)
 {
-    TRY(check_sys(sys));
-    TRY(check_ws(sys, ws, ws_bytes));
-    const int64_t N = sys->n_solvent, NT = sys->n_solvent + sys->n_sites;
-    if (!ok_arr(x, N, esize(sys)) || !ok_arr(v, N, esize(sys)) || !ok_arr(tag, N, 4)) return MPCD_EINVAL;
-    if (N == 0) return MPCD_OK;
-    const Layout L = layout_of(sys);
-    hipStream_t st = (hipStream_t)stream;
-    const int64_t nb = (NT + SCAN_TILE - 1) / SCAN_TILE;
-    const int32_t *perm = at<int32_t>(ws, L.perm);
-    int32_t *partial = at<int32_t>(ws, L.partial);
-    char *tmp = at<char>(ws, L.rtmp);
-    const size_t es = esize(sys);
-    int32_t *ttag = (int32_t *)(tmp + 6 * es * (size_t)N);
-    const unsigned gc = grid_for(N, 256);
-    hipLaunchKernelGGL(k_reorder_count, dim3((unsigned)nb), dim3(SCAN_T), 0, st, perm, NT, N, partial);
-    if (sys->prec == MPCD_F64) {
-        double *tx = (double *)tmp, *tv = tx + 3 * N;
-        hipLaunchKernelGGL(k_reorder_gather<double>, dim3((unsigned)nb), dim3(SCAN_T), 0, st, perm, NT, N, partial,
-                           (const double *)x, (const double *)v, (const int32_t *)tag, tx, tv, ttag);
-        hipLaunchKernelGGL(k_reorder_copy<double>, dim3(gc), dim3(256), 0, st, N, (double *)x, (double *)v, tag,
-                           (const double *)tx, (const double *)tv, (const int32_t *)ttag);
-    } else {
-        float *tx = (float *)tmp, *tv = tx + 3 * N;
-        hipLaunchKernelGGL(k_reorder_gather<float>, dim3((unsigned)nb), dim3(SCAN_T), 0, st, perm, NT, N, partial,
-                           (const float *)x, (const float *)v, (const int32_t *)tag, tx, tv, ttag);
-        hipLaunchKernelGGL(k_reorder_copy<float>, dim3(gc), dim3(256), 0, st, N, (float *)x, (float *)v, tag,
-                           (const float *)tx, (const float *)tv, (const int32_t *)ttag);
-    }
-    return launch_check();
-}
-
-static int collide_impl(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
-                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell, uint64_t seed,
-                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt,
-                        bool draws_ready);
-
-int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
-                 const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell, uint64_t seed,
-                 const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt)
-{
-    return collide_impl(stream, sys, v, tag, vs, bodies, cos_a, sin_a, kT_cell, seed, d_step, ws, ws_bytes,
-                        x_stream, dt, false);
-}
-
-static int collide_impl(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
-                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell, uint64_t seed,
-                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt,
-                        bool draws_ready)
-{
-    TRY(check_sys(sys));
-    TRY(check_ws(sys, ws, ws_bytes));
-    if (!ok_arr(v, sys->n_solvent, esize(sys)) || !ok_arr(vs, sys->n_sites, esize(sys)) || !d_step)
-        return MPCD_EINVAL;
-    if (tag && !aligned(tag, 4)) return MPCD_EINVAL;
-    if (sys->n_sites > 0 && (!bodies || !bodies->site_m)) return MPCD_EINVAL;
-    if (x_stream && (!aligned(x_stream, esize(sys)) || !(dt > 0.0))) return MPCD_EINVAL;
-    const Layout L = layout_of(sys);
     CollideArgs A;
-    A.s = make_sysdev(sys);
+    A.s = c.sd;
     A.site_m = bodies ? bodies->site_m : nullptr;
     A.tag = tag;
-    A.cell_start = at<int32_t>(ws, L.cell_start);
-    A.perm = at<int32_t>(ws, L.perm);
-    A.draws = at<double>(ws, L.draws);
+    A.cell_start = at<int32_t>(c.ws, c.L.cell_start);
+    A.perm = at<int32_t>(c.ws, c.L.perm);
+    A.draws = at<double>(c.ws, c.L.draws);
     A.cos_a = cos_a;
     A.sin_a = sin_a;
     A.kT_cell = kT_cell;
     A.dt = dt;
     A.seed = seed;
     A.d_step = d_step;
-    A.status = at<uint32_t>(ws, L.status);
-    hipStream_t st = (hipStream_t)stream;
-    if (!draws_ready)
-        hipLaunchKernelGGL(k_cell_draws, dim3(grid_for(sys->n_cells, 256)), dim3(256), 0, st, A,
-                           at<double>(ws, L.draws));
-    const bool f64 = sys->prec == MPCD_F64;
-    const TileCfg T = tile_config(sys);
+    A.status = c.status;
+    A.advance_step = advance;
+    return A;
+}
+
+static void launch_draws(const Ctx &c, hipStream_t st, const CollideArgs &A, int mode)
+{
+    if (mode == 2 && !(A.kT_cell > 0.0)) return;
+    hipLaunchKernelGGL(k_cell_draws, dim3(grid_for(c.sys->n_cells, 256)), dim3(256), 0, st, A,
+                       at<double>(c.ws, c.L.draws), mode);
+}
+
+static void launch_collide(const Ctx &c, hipStream_t st, const CollideArgs &A, void *v, void *vs, void *x_stream)
+{
+    const bool f64 = c.sys->prec == MPCD_F64;
+    const TileCfg T = tile_config(c.sys);
     const dim3 grid(xcd_grid(T.ntiles));
     const size_t lds = tile_layout(f64, T.cpb, T.cap).end;
     if (f64)
@@ -1805,12 +1924,175 @@ static int collide_impl(void *stream, const mpcd_sys *sys, void *v, const int32_
     else
         hipLaunchKernelGGL((k_collide_tiled<float, ITEMS_F32>), grid, dim3(TILE_T), lds, st, A, T, (float *)v,
                            (float *)vs, (float *)x_stream);
+}
+
+static void launch_thermalize(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, double kT, int thermalize,
+                              uint64_t seed, const uint64_t *d_step, void *xs, void *vs)
+{
+    if (c.sys->n_bodies == 0 || c.sys->n_sites == 0) return;
+    const BodyDev bd = make_bodydev(bodies);
+    double *site_d = at<double>(c.ws, c.L.site_d), *vpre = at<double>(c.ws, c.L.vpre);
+    const dim3 gb((unsigned)c.sys->n_bodies);
+    if (c.sys->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_thermalize<double>, gb, dim3(BODY_T), 0, st, c.sd, bd, kT, thermalize, seed, d_step,
+                           (double *)xs, (double *)vs, site_d, vpre, c.status);
+    else
+        hipLaunchKernelGGL(k_thermalize<float>, gb, dim3(BODY_T), 0, st, c.sd, bd, kT, thermalize, seed, d_step,
+                           (float *)xs, (float *)vs, site_d, vpre, c.status);
+}
+
+// Thermalization + site binning + solvent binning in one launch.
+static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, double kT, int thermalize,
+                        uint64_t seed, const uint64_t *d_step, const void *x, void *xs, void *vs)
+{
+    const int64_t N = c.sys->n_solvent;
+    const int64_t nb = (c.sys->n_sites > 0) ? c.sys->n_bodies : 0;
+    const int64_t nchunks = (N + BIN_CHUNK - 1) / BIN_CHUNK;
+    const BodyDev bd = make_bodydev(bodies);
+    SysDev sd = c.sd;
+    if (nb == 0) sd.B = 0;  // no site work: every block bins solvent
+    const dim3 g((unsigned)(nb + nchunks > 0 ? nb + nchunks : 1));
+    double *site_d = at<double>(c.ws, c.L.site_d), *vpre = at<double>(c.ws, c.L.vpre);
+    int32_t *counts = at<int32_t>(c.ws, c.L.counts), *cellid = at<int32_t>(c.ws, c.L.cellid);
+    int32_t *slot = at<int32_t>(c.ws, c.L.slot);
+    double *shift = at<double>(c.ws, c.L.shift);
+    if (c.sys->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_prep<double>, g, dim3(BODY_T), 0, st, sd, bd, kT, thermalize, seed, d_step,
+                           (const double *)x, (double *)xs, (double *)vs, site_d, vpre, counts, cellid, slot, shift,
+                           c.status);
+    else
+        hipLaunchKernelGGL(k_prep<float>, g, dim3(BODY_T), 0, st, sd, bd, kT, thermalize, seed, d_step,
+                           (const float *)x, (float *)xs, (float *)vs, site_d, vpre, counts, cellid, slot, shift,
+                           c.status);
+}
+
+// Scatter fused with the per-cell draws in one launch.
+static void launch_scatter_draws(const Ctx &c, hipStream_t st, const CollideArgs &A)
+{
+    const int64_t NT = c.sys->n_solvent + c.sys->n_sites;
+    const int nsc = (int)((NT + BIN_CHUNK - 1) / BIN_CHUNK);
+    const int ndr = (int)grid_for(c.sys->n_cells, BIN_T, 8192);
+    hipLaunchKernelGGL(k_scatter_draws, dim3((unsigned)(nsc + ndr)), dim3(BIN_T), 0, st, NT,
+                       at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot), at<int32_t>(c.ws, c.L.perm), nsc,
+                       A, at<double>(c.ws, c.L.draws));
+}
+
+static void launch_transfer_first(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const void *vs, double *J,
+                                  double *K, double dt)
+{
+    if (c.sys->n_bodies == 0) return;
+    const BodyDev bd = make_bodydev(bodies);
+    const dim3 gb((unsigned)c.sys->n_bodies);
+    if (c.sys->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_transfer_first<double>, gb, dim3(BODY_T), 0, st, c.sd, bd, (const double *)vs,
+                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, c.status);
+    else
+        hipLaunchKernelGGL(k_transfer_first<float>, gb, dim3(BODY_T), 0, st, c.sd, bd, (const float *)vs,
+                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, c.status);
+}
+
+static void launch_forces(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca, double dt,
+                          int kick, uint64_t *advance)
+{
+    if (c.sys->n_bodies == 0) return;
+    hipLaunchKernelGGL(k_body_forces, dim3((unsigned)c.sys->n_bodies), dim3(FRC_T), 0, st, c.sd,
+                       make_bodydev(bodies), wca, dt, kick, advance, c.status);
+}
+
+static void launch_reorder(const Ctx &c, hipStream_t st, void *x, void *v, int32_t *tag)
+{
+    const int64_t N = c.sys->n_solvent, NT = c.sys->n_solvent + c.sys->n_sites;
+    if (N == 0) return;
+    const int64_t nb = (NT + BIN_CHUNK - 1) / BIN_CHUNK;
+    const int32_t *perm = at<int32_t>(c.ws, c.L.perm);
+    int32_t *partial = at<int32_t>(c.ws, c.L.partial);
+    char *tmp = at<char>(c.ws, c.L.rtmp);
+    const size_t es = esize(c.sys);
+    int32_t *ttag = (int32_t *)(tmp + 6 * es * (size_t)N);
+    const unsigned gcp = grid_for(N, 256);
+    hipLaunchKernelGGL(k_reorder_count, dim3((unsigned)nb), dim3(BIN_T), 0, st, perm, NT, N, partial);
+    hipLaunchKernelGGL(k_partials_scan, dim3(1), dim3(SCAN_T), 0, st, partial, nb);
+    if (c.sys->prec == MPCD_F64) {
+        double *tx = (double *)tmp, *tv = tx + 3 * N;
+        hipLaunchKernelGGL(k_reorder_gather<double>, dim3((unsigned)nb), dim3(BIN_T), 0, st, perm, NT, N, partial,
+                           (const double *)x, (const double *)v, (const int32_t *)tag, tx, tv, ttag);
+        hipLaunchKernelGGL(k_reorder_copy<double>, dim3(gcp), dim3(256), 0, st, N, (double *)x, (double *)v, tag,
+                           (const double *)tx, (const double *)tv, (const int32_t *)ttag);
+    } else {
+        float *tx = (float *)tmp, *tv = tx + 3 * N;
+        hipLaunchKernelGGL(k_reorder_gather<float>, dim3((unsigned)nb), dim3(BIN_T), 0, st, perm, NT, N, partial,
+                           (const float *)x, (const float *)v, (const int32_t *)tag, tx, tv, ttag);
+        hipLaunchKernelGGL(k_reorder_copy<float>, dim3(gcp), dim3(256), 0, st, N, (float *)x, (float *)v, tag,
+                           (const float *)tx, (const float *)tv, (const int32_t *)ttag);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Entry points
+
+static int bin_checks(const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
+                      const uint64_t *d_step, void *ws, size_t ws_bytes)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    if (!ok_arr(x, sys->n_solvent, esize(sys)) || !ok_arr(xs, sys->n_sites, esize(sys)) || !d_step)
+        return MPCD_EINVAL;
+    if (sys->n_sites > 0 && (!bodies || !bodies->site_body)) return MPCD_EINVAL;
+    return MPCD_OK;
+}
+
+int mpcd_bin(void *stream, const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
+             uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes)
+{
+    TRY(bin_checks(sys, x, xs, bodies, d_step, ws, ws_bytes));
+    const Ctx c = make_ctx(sys, ws);
+    hipStream_t st = (hipStream_t)stream;
+    launch_shift(c, st, seed, d_step);
+    launch_bin_count(c, st, x, xs, bodies ? bodies->site_body : nullptr, 0, sys->n_solvent + sys->n_sites);
+    launch_scan(c, st);
+    launch_scatter(c, st);
     return launch_check();
 }
 
-static int thermalize_impl(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, double kT,
-                           int32_t thermalize, uint64_t seed, const uint64_t *d_step, void *xs, void *vs, void *ws,
-                           size_t ws_bytes, bool draw_shift)
+int mpcd_reorder(void *stream, const mpcd_sys *sys, void *x, void *v, int32_t *tag, void *ws, size_t ws_bytes)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    const int64_t N = sys->n_solvent;
+    if (!ok_arr(x, N, esize(sys)) || !ok_arr(v, N, esize(sys)) || !ok_arr(tag, N, 4)) return MPCD_EINVAL;
+    launch_reorder(make_ctx(sys, ws), (hipStream_t)stream, x, v, tag);
+    return launch_check();
+}
+
+static int collide_checks(const mpcd_sys *sys, const void *v, const int32_t *tag, const void *vs,
+                          const mpcd_bodies *bodies, const uint64_t *d_step, void *ws, size_t ws_bytes,
+                          const void *x_stream, double dt)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    if (!ok_arr(v, sys->n_solvent, esize(sys)) || !ok_arr(vs, sys->n_sites, esize(sys)) || !d_step)
+        return MPCD_EINVAL;
+    if (tag && !aligned(tag, 4)) return MPCD_EINVAL;
+    if (sys->n_sites > 0 && (!bodies || !bodies->site_m)) return MPCD_EINVAL;
+    if (x_stream && (!aligned(x_stream, esize(sys)) || !(dt > 0.0))) return MPCD_EINVAL;
+    return MPCD_OK;
+}
+
+int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
+                 const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell, uint64_t seed,
+                 const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt)
+{
+    TRY(collide_checks(sys, v, tag, vs, bodies, d_step, ws, ws_bytes, x_stream, dt));
+    const Ctx c = make_ctx(sys, ws);
+    hipStream_t st = (hipStream_t)stream;
+    const CollideArgs A = collide_args(c, tag, bodies, cos_a, sin_a, kT_cell, seed, d_step, dt, nullptr);
+    launch_draws(c, st, A, 3);
+    launch_collide(c, st, A, v, vs, x_stream);
+    return launch_check();
+}
+
+static int thermalize_checks(const mpcd_sys *sys, const mpcd_bodies *bodies, double kT, int32_t thermalize,
+                             const uint64_t *d_step, const void *xs, const void *vs, void *ws, size_t ws_bytes)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
@@ -1818,29 +2100,16 @@ static int thermalize_impl(void *stream, const mpcd_sys *sys, const mpcd_bodies 
     if (!ok_arr(xs, sys->n_sites, esize(sys)) || !ok_arr(vs, sys->n_sites, esize(sys)) || !d_step)
         return MPCD_EINVAL;
     if (thermalize && !(kT > 0.0)) return MPCD_EINVAL;
-    if (sys->n_bodies == 0 || sys->n_sites == 0) return MPCD_OK;
-    const Layout L = layout_of(sys);
-    const SysDev sd = make_sysdev(sys);
-    const BodyDev bd = make_bodydev(bodies);
-    hipStream_t st = (hipStream_t)stream;
-    double *shift = draw_shift ? at<double>(ws, L.shift) : nullptr;
-    double *site_d = at<double>(ws, L.site_d), *vpre = at<double>(ws, L.vpre);
-    uint32_t *status = at<uint32_t>(ws, L.status);
-    const dim3 gb((unsigned)sys->n_bodies);
-    if (sys->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_thermalize<double>, gb, dim3(BODY_T), 0, st, sd, bd, kT, (int)thermalize, seed, d_step,
-                           (double *)xs, (double *)vs, site_d, vpre, shift, status);
-    else
-        hipLaunchKernelGGL(k_thermalize<float>, gb, dim3(BODY_T), 0, st, sd, bd, kT, (int)thermalize, seed, d_step,
-                           (float *)xs, (float *)vs, site_d, vpre, shift, status);
-    return launch_check();
+    return MPCD_OK;
 }
 
 int sites_thermalize(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, double kT,
                      int32_t thermalize, uint64_t seed, const uint64_t *d_step, void *xs, void *vs, void *ws,
                      size_t ws_bytes)
 {
-    return thermalize_impl(stream, sys, bodies, kT, thermalize, seed, d_step, xs, vs, ws, ws_bytes, false);
+    TRY(thermalize_checks(sys, bodies, kT, thermalize, d_step, xs, vs, ws, ws_bytes));
+    launch_thermalize(make_ctx(sys, ws), (hipStream_t)stream, bodies, kT, thermalize, seed, d_step, xs, vs);
+    return launch_check();
 }
 
 int sites_to_body(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const void *vs, void *ws,
@@ -1852,40 +2121,35 @@ int sites_to_body(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, 
     if (!ok_arr(vs, sys->n_sites, esize(sys)) || !ok_arr(J, sys->n_bodies, 8) || !ok_arr(K, sys->n_bodies, 8))
         return MPCD_EINVAL;
     if (sys->n_bodies == 0) return MPCD_OK;
-    const Layout L = layout_of(sys);
-    const SysDev sd = make_sysdev(sys);
+    const Ctx c = make_ctx(sys, ws);
     const BodyDev bd = make_bodydev(bodies);
     hipStream_t st = (hipStream_t)stream;
     const dim3 g((unsigned)sys->n_bodies);
     if (sys->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_sites_to_body<double>, g, dim3(BODY_T), 0, st, sd, bd, (const double *)vs,
-                           at<double>(ws, L.site_d), at<double>(ws, L.vpre), J, K);
+        hipLaunchKernelGGL(k_sites_to_body<double>, g, dim3(BODY_T), 0, st, c.sd, bd, (const double *)vs,
+                           at<double>(ws, c.L.site_d), at<double>(ws, c.L.vpre), J, K);
     else
-        hipLaunchKernelGGL(k_sites_to_body<float>, g, dim3(BODY_T), 0, st, sd, bd, (const float *)vs,
-                           at<double>(ws, L.site_d), at<double>(ws, L.vpre), J, K);
+        hipLaunchKernelGGL(k_sites_to_body<float>, g, dim3(BODY_T), 0, st, c.sd, bd, (const float *)vs,
+                           at<double>(ws, c.L.site_d), at<double>(ws, c.L.vpre), J, K);
     return launch_check();
 }
 
-static int forces_impl(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca, void *ws,
-                       size_t ws_bytes, double dt, int kick, uint64_t *advance_step)
+static int wca_check(const mpcd_wca *wca)
 {
-    TRY(check_sys(sys));
-    TRY(check_ws(sys, ws, ws_bytes));
-    TRY(check_bodies(sys, bodies));
     if (!wca || (wca->mode != 0 && wca->mode != 1)) return MPCD_EINVAL;
     if (wca->mode == 1 && !(wca->sigma > 0.0 && wca->eps >= 0.0 && wca->delta >= 0.0)) return MPCD_EINVAL;
-    if (sys->n_bodies == 0) return MPCD_OK;
-    const Layout L = layout_of(sys);
-    hipLaunchKernelGGL(k_body_forces, dim3((unsigned)sys->n_bodies), dim3(FRC_T), 0, (hipStream_t)stream,
-                       make_sysdev(sys), make_bodydev(bodies), *wca, dt, kick, advance_step,
-                       at<uint32_t>(ws, L.status));
-    return launch_check();
+    return MPCD_OK;
 }
 
 int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca, void *ws,
                 size_t ws_bytes)
 {
-    return forces_impl(stream, sys, bodies, wca, ws, ws_bytes, 0.0, 0, nullptr);
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    TRY(check_bodies(sys, bodies));
+    TRY(wca_check(wca));
+    launch_forces(make_ctx(sys, ws), (hipStream_t)stream, bodies, *wca, 0.0, 0, nullptr);
+    return launch_check();
 }
 
 int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const double *J,
@@ -1894,18 +2158,16 @@ int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies,
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
     TRY(check_bodies(sys, bodies));
-    if (!(dt > 0.0) || !wca || (wca->mode != 0 && wca->mode != 1)) return MPCD_EINVAL;
+    TRY(wca_check(wca));
+    if (!(dt > 0.0)) return MPCD_EINVAL;
     if ((J && !aligned(J, 8)) || (K && !aligned(K, 8))) return MPCD_EINVAL;
     if (sys->n_bodies == 0) return MPCD_OK;
-    const Layout L = layout_of(sys);
-    const SysDev sd = make_sysdev(sys);
-    const BodyDev bd = make_bodydev(bodies);
+    const Ctx c = make_ctx(sys, ws);
     hipStream_t st = (hipStream_t)stream;
-    const unsigned g = grid_for(sys->n_bodies, 64);
-    uint32_t *status = at<uint32_t>(ws, L.status);
-    hipLaunchKernelGGL(k_body_first, dim3(g), dim3(64), 0, st, sd, bd, J, K, dt, status);
-    TRY(launch_check());
-    return forces_impl(stream, sys, bodies, wca, ws, ws_bytes, dt, 1, nullptr);
+    hipLaunchKernelGGL(k_body_first, dim3(grid_for(sys->n_bodies, 64)), dim3(64), 0, st, c.sd, make_bodydev(bodies),
+                       J, K, dt, c.status);
+    launch_forces(c, st, bodies, *wca, dt, 1, nullptr);
+    return launch_check();
 }
 
 int mpcd_advance_step(void *stream, uint64_t *d_step)
@@ -1915,47 +2177,53 @@ int mpcd_advance_step(void *stream, uint64_t *d_step)
     return launch_check();
 }
 
-// One step.  Differs from calling the entry points in sequence only by fusion
-// (same operations in the same order): the grid shift is drawn with the site
-// draws, the momentum transfer runs inside the first body half-step, and the
-// step counter advances in the last body kernel.
-int mpcd_step(void *stream, const mpcd_step_args *a)
+static int step_checks(const mpcd_step_args *a)
 {
     if (!a || !a->sys) return MPCD_EINVAL;
     const mpcd_sys *s = a->sys;
     const mpcd_params &p = a->par;
-    TRY(check_sys(s));
-    TRY(check_ws(s, a->ws, a->ws_bytes));
-    TRY(check_bodies(s, &a->bodies));
-    if (!(p.dt > 0.0) || (p.wca.mode != 0 && p.wca.mode != 1)) return MPCD_EINVAL;
-    if (!ok_arr(a->J, s->n_bodies, 8) || !ok_arr(a->K, s->n_bodies, 8) || !a->d_step) return MPCD_EINVAL;
-    const bool sites = s->n_sites > 0 && s->n_bodies > 0;
-    TRY(thermalize_impl(stream, s, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->xs, a->vs, a->ws,
-                        a->ws_bytes, sites));
-    TRY(bin_impl(stream, s, a->x, a->xs, &a->bodies, p.seed, a->d_step, a->ws, a->ws_bytes, !sites));
-    TRY(collide_impl(stream, s, a->v, a->tag, a->vs, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed,
-                     a->d_step, a->ws, a->ws_bytes, p.fuse_stream ? a->x : nullptr, p.dt, false));
-    if (!p.fuse_stream) TRY(mpcd_stream(stream, s, a->x, a->v, p.dt, a->ws, a->ws_bytes));
-    if (s->n_bodies == 0) return mpcd_advance_step(stream, a->d_step);
-    const Layout L = layout_of(s);
-    const SysDev sd = make_sysdev(s);
-    const BodyDev bd = make_bodydev(&a->bodies);
+    TRY(thermalize_checks(s, &a->bodies, p.kT, p.thermalize, a->d_step, a->xs, a->vs, a->ws, a->ws_bytes));
+    TRY(bin_checks(s, a->x, a->xs, &a->bodies, a->d_step, a->ws, a->ws_bytes));
+    TRY(collide_checks(s, a->v, a->tag, a->vs, &a->bodies, a->d_step, a->ws, a->ws_bytes, a->x, p.dt));
+    TRY(wca_check(&p.wca));
+    if (!(p.dt > 0.0)) return MPCD_EINVAL;
+    if (!ok_arr(a->J, s->n_bodies, 8) || !ok_arr(a->K, s->n_bodies, 8)) return MPCD_EINVAL;
+    if (a->reorder_every < 0 || (a->reorder_every > 0 && !ok_arr(a->tag, s->n_solvent, 4))) return MPCD_EINVAL;
+    return MPCD_OK;
+}
+
+// One step: [thermalize + site binning | solvent binning] (one launch), scan,
+// [scatter | per-cell draws] (one launch), collide + stream, transfer fused
+// with the first body half-step, forces fused with the second half kick and
+// the step-counter advance.  The same operations in the same order, per
+// particle, cell and body, as calling the entry points in sequence.
+int mpcd_step(void *stream, const mpcd_step_args *a)
+{
+    TRY(step_checks(a));
+    const mpcd_sys *s = a->sys;
+    const mpcd_params &p = a->par;
+    const Ctx c = make_ctx(s, a->ws);
     hipStream_t st = (hipStream_t)stream;
-    uint32_t *status = at<uint32_t>(a->ws, L.status);
-    const dim3 gb((unsigned)s->n_bodies);
-    if (s->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_transfer_first<double>, gb, dim3(BODY_T), 0, st, sd, bd, (const double *)a->vs,
-                           at<double>(a->ws, L.site_d), at<double>(a->ws, L.vpre), a->J, a->K, p.dt, status);
-    else
-        hipLaunchKernelGGL(k_transfer_first<float>, gb, dim3(BODY_T), 0, st, sd, bd, (const float *)a->vs,
-                           at<double>(a->ws, L.site_d), at<double>(a->ws, L.vpre), a->J, a->K, p.dt, status);
-    TRY(launch_check());
-    return forces_impl(stream, s, &a->bodies, &p.wca, a->ws, a->ws_bytes, p.dt, 1, a->d_step);
+    launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs);
+    launch_scan(c, st);
+    const CollideArgs A = collide_args(c, a->tag, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed, a->d_step, p.dt,
+                                       nullptr);
+    launch_scatter_draws(c, st, A);
+    launch_collide(c, st, A, a->v, a->vs, p.fuse_stream ? a->x : nullptr);
+    if (!p.fuse_stream) TRY(mpcd_stream(stream, s, a->x, a->v, p.dt, a->ws, a->ws_bytes));
+    if (s->n_bodies == 0) {
+        hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a->d_step);
+        return launch_check();
+    }
+    launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt);
+    launch_forces(c, st, &a->bodies, p.wca, p.dt, 1, a->d_step);
+    return launch_check();
 }
 
 int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, void **graph_exec)
 {
     if (!stream || !args || nsteps < 1 || !graph_exec) return MPCD_EINVAL;
+    TRY(step_checks(args));
     hipStream_t st = (hipStream_t)stream;
     TRY(hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)));
     int rc = MPCD_OK;
@@ -1966,14 +2234,10 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
     }
     hipGraph_t graph = nullptr;
     const int rc_end = hip_check(hipStreamEndCapture(st, &graph));
-    if (rc != MPCD_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-    }
-    TRY(rc_end);
+    if (rc == MPCD_OK) rc = rc_end;
     hipGraphExec_t exec = nullptr;
-    rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    (void)hipGraphDestroy(graph);
+    if (rc == MPCD_OK) rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    if (graph) (void)hipGraphDestroy(graph);
     TRY(rc);
     *graph_exec = (void *)exec;
     return MPCD_OK;
