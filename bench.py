@@ -1,24 +1,32 @@
 #!/usr/bin/env python
 """Throughput of the MPCD + rigid-body step on one MI355X.
 
-Workload: hard-sphere suspension, 60^3 cells (a = 1, periodic), 5 solvent per
-cell (1,080,000 solvent), 191 rigid spheres of radius 3 with 200 Fibonacci
-surface sites each (volume fraction 0.1), WCA between body centres (sigma 6,
-eps = kT), SRD 130 degrees, dt = 0.1, kT = 1 with the cell thermostat; synthetic
-seeded inputs (random sequential addition, Maxwell-Boltzmann velocities).
+Headline workload: hard-sphere suspension, 60^3 cells (a = 1, periodic), 5
+solvent per cell (1,080,000 solvent), 191 rigid spheres of radius 3 with 200
+Fibonacci surface sites each (volume fraction 0.1), WCA between body centres
+(sigma 6, eps = kT), SRD 130 degrees, dt = 0.1, kT = 1 with the cell
+thermostat; synthetic seeded inputs (random sequential addition,
+Maxwell-Boltzmann velocities).
 
 One step = site thermalization, grid shift + counting sort, SRD collision
 (fused with solvent streaming), momentum transfer, rigid-body update.  Inputs
-are resident in HBM; the timed region replays a HIP graph of K steps.  The
+are resident in HBM; the timed region replays a HIP graph of the steps.  The
 headline value is the FP32 form (FP32 solvent/sites, exact int64 fixed-point
-cell sums, FP64 bodies); the plain FP64 form is measured alongside.
+cell sums, FP64 bodies); the plain FP64 form is measured alongside, and both
+forms are also run on 512 independent replicas of uneven box size advanced
+together (the batched form).
 
-Prints one JSON line (rank 0, N = 1).
+The dominant kernel (the fused collide + stream pass) is timed on its own with
+HIP events on its stream: back-to-back launches of mpcd_collide_drawn on the
+last step's cell lists and draws.
+
+Prints one JSON line (N = 1).
 """
 import argparse
+import hashlib
 import json
-import math
 import os
+import statistics
 import sys
 import time
 
@@ -26,6 +34,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+REORDER_EVERY = 25  # storage reorder period (steps) inside the timed graphs
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_14307_amd", "csrc", "mpcd.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_collide_tiled_f32_suspension60_traffic.txt")
 
 
 def log(msg):
@@ -33,53 +44,96 @@ def log(msg):
 
 
 def collide_bytes(N, S, prec_bytes):
-    """Algorithmic bytes of one collide launch (fused streaming): read and write
-    each solvent particle's position and velocity once, read and write each
-    site's velocity once and read its mass."""
+    """Algorithmic bytes of one fused collide + stream launch: read and write
+    each solvent particle's position and velocity once (12 components), read
+    and write each site's velocity once and read its mass."""
     return N * 4 * 3 * prec_bytes + S * (2 * 3 * prec_bytes + 8)
 
 
-REORDER_EVERY = 25  # storage reorder period (steps) inside the timed graph
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def run_gpu(wl, par, prec, steps, warmup, kernel_steps):
+def measured_traffic():
+    """HBM bytes per collide launch from the committed rocprofv3 counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps):
     import torch
     from paper_2604_14307_amd.sim import GPUSystem
 
-    g = GPUSystem(wl, par, prec=prec, device="cuda:0")
+    g = GPUSystem(systems, par, prec=prec, device="cuda:0")
     g.body_forces()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
+    per = max(1, steps // repeats)
     with torch.cuda.stream(side):
-        # warmup (eager, also pages in the code objects), then graphs
-        for i in range(warmup):
+        for i in range(warmup):  # eager warmup (also pages in the code objects)
             g.step(1)
             if (i + 1) % REORDER_EVERY == 0:
                 g.reorder()
-        g.graph(steps, reorder_every=REORDER_EVERY)
+        g.graph(per, reorder_every=REORDER_EVERY)
+        g.graph_launch()  # one untimed replay
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(side)
-        g.graph_launch()
-        e1.record(side)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(repeats + 1)]
+        ev[0].record(side)
+        for r in range(repeats):
+            g.graph_launch()
+            ev[r + 1].record(side)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        # dominant-kernel timing on the same stream: replay the graph once more so
-        # the GPU is busy while the host enqueues R collide launches back to back,
-        # then average between two events around them (host launch latency is not
-        # counted).  The extra launches act on the last step's cell lists; their
-        # results are not used.
-        g.graph_launch()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(side)
-        for _ in range(kernel_steps):
-            g.collide(stream_x=True)
-        b.record(side)
-        torch.cuda.synchronize()
-        kms = [a.elapsed_time(b) / kernel_steps]
+        seg = [ev[r].elapsed_time(ev[r + 1]) for r in range(repeats)]
+        kms = None
+        if kernel_reps > 0:
+            # keep the GPU busy with one more replay while the host enqueues the
+            # back-to-back collide launches, so launch latency is not counted
+            g.graph_launch()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(side)
+            for _ in range(kernel_reps):
+                g.collide_drawn(stream_x=True)
+            b.record(side)
+            torch.cuda.synchronize()
+            kms = a.elapsed_time(b) / kernel_reps
         g.release_graph()
         flags = g.status()
-    return dict(ms=ms, collide_ms=sum(kms) / len(kms), flags=flags, N=g.N, S=g.S, B=g.B, C=g.C)
+    if flags != 0:
+        raise SystemExit("device status flags %d in the %s run" % (flags, prec))
+    total_steps = per * repeats
+    ms = sum(seg)
+    return dict(ms=ms, steps=total_steps, ms_step=ms / total_steps,
+                ms_step_median=statistics.median(seg) / per, collide_ms=kms,
+                rate=g.N * total_steps / (ms * 1e-3), N=g.N, S=g.S, B=g.B, C=g.C, nsys=g.nsys)
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of known size, for scaling the FETCH_SIZE/WRITE_SIZE
+    counters (run under rocprofv3 --pmc)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)  # device-to-device copy (blit kernel)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)  # the same traffic through an elementwise kernel
+    torch.cuda.synchronize()
+    log("copy calibration: 3 copies and 3 scale-by-one passes of %d bytes" % nbytes)
 
 
 def cpu_baseline(wl, par, steps):
@@ -92,46 +146,56 @@ def cpu_baseline(wl, par, steps):
     return o.N * steps / dt, dt
 
 
+def summary(r):
+    return {"value": r["rate"], "ms_per_step": r["ms_step"], "ms_per_step_median_replay": r["ms_step_median"],
+            "steps": r["steps"], "solvent": r["N"], "sites": r["S"], "bodies": r["B"], "cells": r["C"],
+            "systems": r["nsys"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--kernel-steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=25)
+    ap.add_argument("--repeats", type=int, default=5, help="graph replays the K timed steps are split into")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--batched-steps", type=int, default=150)
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--large", action="store_true", help="also run the 200^3-cell, 80M-solvent suspension (FP32)")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not an implemented path).", file=sys.stderr)
+        print("bench.py runs on one GPU only: this implementation drives a single MI355X "
+              "(how the step would shard over several GPUs is a design note, not a built path).",
+              file=sys.stderr)
         sys.exit(2)
+    if args.steps < args.repeats:
+        raise SystemExit("--steps must be at least --repeats")
 
     from paper_2604_14307_amd import workloads as W
     wl, par, meta = W.config(1, kT_cell=1.0)
     res = {}
-    for prec in ("f64", "f32"):
-        log("running %s: warmup %d, %d timed steps" % (prec, args.warmup, args.steps))
-        res[prec] = run_gpu(wl, par, prec, args.steps, args.warmup, args.kernel_steps)
+    for prec in (("f32",) if args.no_fp64 else ("f32", "f64")):
+        log("suspension 60^3 %s: warmup %d, %d timed steps in %d replays" % (prec, args.warmup, args.steps,
+                                                                            args.repeats))
+        res[prec] = run_gpu(wl, par, prec, args.steps, args.warmup, args.repeats, args.kernel_reps)
         r = res[prec]
-        log("%s: %.4f ms/step, collide %.4f ms, flags %d" % (prec, r["ms"] / args.steps, r["collide_ms"], r["flags"]))
-        if r["flags"] != 0:
-            raise SystemExit("device status flags %d in the %s run" % (r["flags"], prec))
-
-    r32, r64 = res["f32"], res["f64"]
+        log("%s: %.4f ms/step (median replay %.4f), collide %.2f us" % (prec, r["ms_step"], r["ms_step_median"],
+                                                                        r["collide_ms"] * 1e3))
+    r32 = res["f32"]
     N, S = r32["N"], r32["S"]
-    ms_step = r32["ms"] / args.steps
-    value = N * args.steps / (r32["ms"] * 1e-3)
-    v64 = N * args.steps / (r64["ms"] * 1e-3)
     ach = collide_bytes(N, S, 4) / (r32["collide_ms"] * 1e-3) / 1e9
-    ach64 = collide_bytes(N, S, 8) / (r64["collide_ms"] * 1e-3) / 1e9
     out = {
         "metric": "solvent particle-steps/s",
-        "value": value,
+        "value": r32["rate"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": r32["steps"],
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r32["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -140,20 +204,43 @@ def main():
         "config": {"workload": "hard-sphere suspension: 60^3 cells, 1,080,000 solvent, 191 rigid spheres "
                                "r=3 x 200 sites, WCA sigma=6, SRD 130 deg, dt=0.1, kT=1, cell thermostat",
                    "solvent": N, "sites": S, "bodies": r32["B"], "cells": r32["C"],
-                   "form": "FP32 solvent/sites + int64 fixed-point cell sums + FP64 bodies; HIP graph of K steps"},
-        "fp64": {"value": v64, "ms_per_step": r64["ms"] / args.steps,
-                 "speedup_fp32_vs_fp64": value / v64,
-                 "collide_ms": r64["collide_ms"], "collide_GBs": ach64},
-        "roofline": {"bound": "hbm", "kernel": "k_collide_f32", "achieved": ach, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
-                     "collide_ms": r32["collide_ms"],
+                   "form": "FP32 solvent/sites + int64 fixed-point cell sums + FP64 bodies; "
+                           "HIP graph replays of the step"},
+        "ms_per_step_median_replay": r32["ms_step_median"],
+        "roofline": {"bound": "hbm", "kernel": "k_collide_tiled<float,4> (collide + stream)",
+                     "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(), "avg_launch_us": r32["collide_ms"] * 1e3,
                      "algorithmic_bytes_per_launch": collide_bytes(N, S, 4)},
     }
+    if "f64" in res:
+        r64 = res["f64"]
+        a64 = collide_bytes(N, S, 8) / (r64["collide_ms"] * 1e-3) / 1e9
+        out["fp64"] = dict(summary(r64), speedup_fp32_vs_fp64=r32["rate"] / r64["rate"],
+                           collide_us=r64["collide_ms"] * 1e3, collide_GBs=a64)
+    if not args.no_batched:
+        bsys, bpar, bmeta = W.config(3, kT_cell=1.0)
+        out["batched"] = {"workload": bmeta["name"]}
+        for prec in (("f32",) if args.no_fp64 else ("f32", "f64")):
+            log("batched replicas %s: %d timed steps" % (prec, args.batched_steps))
+            rb = run_gpu(bsys, bpar, prec, args.batched_steps, 10, 3, 0)
+            log("batched %s: %.4f ms/step" % (prec, rb["ms_step"]))
+            out["batched"][prec] = summary(rb)
+        if "f64" in out["batched"]:
+            out["batched"]["speedup_fp32_vs_fp64"] = out["batched"]["f32"]["value"] / out["batched"]["f64"]["value"]
+    if args.large:
+        lw, lpar, lmeta = W.config(2, kT_cell=1.0)
+        log("large suspension FP32: 50 timed steps")
+        rl = run_gpu(lw, lpar, "f32", 50, 5, 5, 5)
+        out["large"] = dict(summary(rl), workload=lmeta["name"], collide_us=rl["collide_ms"] * 1e3,
+                            collide_GBs=collide_bytes(rl["N"], rl["S"], 4) / (rl["collide_ms"] * 1e-3) / 1e9)
+        del lw
+    if args.copy_calibration:
+        copy_calibration()
     if not args.no_cpu_baseline:
         log("oracle on the host: %d steps" % args.cpu_steps)
         rate, secs = cpu_baseline(wl, par, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d steps of the same 60^3 workload (FP64 oracle, 1 thread, %.1f s)"
+                               "sample": "%d steps of the same 60^3 suspension (FP64 C oracle, one thread, %.1f s)"
                                          % (args.cpu_steps, secs)}
     print(json.dumps(out), flush=True)
 

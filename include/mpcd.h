@@ -183,6 +183,19 @@ int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag,
                  uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes,
                  void *x_stream, double dt);
 
+/* mpcd_collide in two parts.  mpcd_cell_draws draws every cell's random axis
+ * (Sec. II.A) and, when kT_cell > 0, its Gamma(3(n_c - 1)/2) variate (Eq. (6))
+ * into the workspace, from the cell occupancies of the last mpcd_bin.
+ * mpcd_collide_drawn then performs the collision of mpcd_collide with those
+ * draws; kT_cell must be the value given to mpcd_cell_draws.  The pair gives
+ * the same results as mpcd_collide. */
+int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t seed,
+                    const uint64_t *d_step, void *ws, size_t ws_bytes);
+int mpcd_collide_drawn(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
+                       const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
+                       const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream,
+                       double dt);
+
 /* Site positions and thermalized velocities, Eqs. (5) and (7).  Per body:
  * V = P/M, omega = A (Lhat / I) with Lhat_k = p . P_k q / 2; site offset
  * d_j = A dhat_j, position wrap(R + d_j); random velocities vt_j ~ N(0, kT/m_j);

@@ -2091,6 +2091,29 @@ int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag,
     return launch_check();
 }
 
+int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t seed, const uint64_t *d_step,
+                    void *ws, size_t ws_bytes)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    if (!d_step) return MPCD_EINVAL;
+    const Ctx c = make_ctx(sys, ws);
+    const CollideArgs A = collide_args(c, nullptr, nullptr, 1.0, 0.0, kT_cell, seed, d_step, 1.0, nullptr);
+    launch_draws(c, (hipStream_t)stream, A, 3);
+    return launch_check();
+}
+
+int mpcd_collide_drawn(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
+                       const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
+                       const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt)
+{
+    TRY(collide_checks(sys, v, tag, vs, bodies, d_step, ws, ws_bytes, x_stream, dt));
+    const Ctx c = make_ctx(sys, ws);
+    const CollideArgs A = collide_args(c, tag, bodies, cos_a, sin_a, kT_cell, 0, d_step, dt, nullptr);
+    launch_collide(c, (hipStream_t)stream, A, v, vs, x_stream);
+    return launch_check();
+}
+
 static int thermalize_checks(const mpcd_sys *sys, const mpcd_bodies *bodies, double kT, int32_t thermalize,
                              const uint64_t *d_step, const void *xs, const void *vs, void *ws, size_t ws_bytes)
 {

@@ -17,6 +17,7 @@ MPCD_F64, MPCD_F32 = 0, 1
 FLAG_NONFINITE, FLAG_ESCAPE, FLAG_FIXOVF, FLAG_RNGLOOP, FLAG_BINERR = 1, 2, 4, 8, 16
 
 EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mpcd_stream", "mpcd_bin", "mpcd_collide",
+           "mpcd_cell_draws", "mpcd_collide_drawn",
            "sites_thermalize", "sites_to_body", "body_integrate", "body_forces",
            "mpcd_advance_step", "mpcd_step", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
            "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error")
@@ -77,6 +78,8 @@ def load(path: str = LIB_PATH):
         "mpcd_stream": (C.c_int, [vp, sp, vp, vp, dbl, vp, sz]),
         "mpcd_bin": (C.c_int, [vp, sp, vp, vp, bp, u64, vp, vp, sz]),
         "mpcd_collide": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, u64, vp, vp, sz, vp, dbl]),
+        "mpcd_cell_draws": (C.c_int, [vp, sp, dbl, u64, vp, vp, sz]),
+        "mpcd_collide_drawn": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, vp, vp, sz, vp, dbl]),
         "sites_thermalize": (C.c_int, [vp, sp, bp, dbl, i32, u64, vp, vp, vp, vp, sz]),
         "sites_to_body": (C.c_int, [vp, sp, bp, vp, vp, sz, vp, vp]),
         "body_integrate": (C.c_int, [vp, sp, bp, vp, vp, wp, dbl, vp, sz]),

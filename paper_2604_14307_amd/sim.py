@@ -160,6 +160,19 @@ class GPUSystem:
                                       self.ws_bytes, _ptr(self.x) if stream_x else C.c_void_p(0), p["dt"]),
                 "mpcd_collide")
 
+    def cell_draws(self):
+        p = self.params
+        L.check(self.lib.mpcd_cell_draws(self.stream, C.byref(self.csys), p["kT_cell"], p["seed"],
+                                         _ptr(self.d_step), _ptr(self.ws), self.ws_bytes), "mpcd_cell_draws")
+
+    def collide_drawn(self, stream_x: bool = False):
+        p = self.params
+        L.check(self.lib.mpcd_collide_drawn(self.stream, C.byref(self.csys), _ptr(self.v), _ptr(self.tag),
+                                            _ptr(self.vs), C.byref(self.cbodies), p["cos_a"], p["sin_a"],
+                                            p["kT_cell"], _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
+                                            _ptr(self.x) if stream_x else C.c_void_p(0), p["dt"]),
+                "mpcd_collide_drawn")
+
     def sites_to_body(self):
         L.check(self.lib.sites_to_body(self.stream, C.byref(self.csys), C.byref(self.cbodies), _ptr(self.vs),
                                        _ptr(self.ws), self.ws_bytes, _ptr(self.J), _ptr(self.K)),

@@ -121,6 +121,26 @@ def test_stages_bit_exact_single_sphere():
 
 
 @pytest.mark.parametrize("kT_cell", [1.0, 0.0])
+def test_split_draws_then_collide_bit_exact(kT_cell):
+    """mpcd_cell_draws + mpcd_collide_drawn equals the oracle's collision."""
+    wl, par, _ = W.config(0, kT_cell=kT_cell)
+    o = oracle.OracleSystem(wl, par)
+    g = gpu_system(wl, par, prec="f64")
+    step = 3
+    g.set_step(step)
+    o.sites_thermalize(step)
+    g.sites_thermalize()
+    cell, cs, mem, _ = o.bin(o.shift(step))
+    g.bin()
+    o.collide(step, cs, mem)
+    say("split collide kT_cell=%g" % kT_cell)
+    g.cell_draws()
+    g.collide_drawn(stream_x=False)
+    assert_same(o, g.download()[0], ("v", "vs"), "split collide")
+    assert g.status() == 0
+
+
+@pytest.mark.parametrize("kT_cell", [1.0, 0.0])
 def test_single_sphere_100_steps_bit_exact(kT_cell):
     wl, par, meta = W.config(0, kT_cell=kT_cell)
     say("single sphere kT_cell=%g" % kT_cell)
