@@ -16,9 +16,10 @@ cell sums, FP64 bodies); the plain FP64 form is measured alongside, and both
 forms are also run on 512 independent replicas of uneven box size advanced
 together (the batched form).
 
-The dominant kernel (the fused collide + stream pass) is timed on its own with
-HIP events on its stream: back-to-back launches of mpcd_collide_drawn on the
-last step's cell lists and draws.
+The solvent is double-buffered: every step writes it out of place in cell
+order.  The dominant kernel (the fused collide + stream pass) is timed on its
+own with HIP events on its stream: back-to-back launches of mpcd_collide_drawn
+repeating the last step's pass (its inputs, cell lists and draws).
 
 Prints one JSON line (N = 1).
 """
@@ -34,7 +35,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-REORDER_EVERY = 25  # storage reorder period (steps) inside the timed graphs
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_14307_amd", "csrc", "mpcd.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_collide_tiled_f32_suspension60_traffic.txt")
 
@@ -82,13 +82,11 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps):
     g.body_forces()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
-    per = max(1, steps // repeats)
+    per = max(2, 2 * (steps // (2 * repeats)))  # out-of-place graphs hold an even number of steps
     with torch.cuda.stream(side):
         for i in range(warmup):  # eager warmup (also pages in the code objects)
             g.step(1)
-            if (i + 1) % REORDER_EVERY == 0:
-                g.reorder()
-        g.graph(per, reorder_every=REORDER_EVERY)
+        g.graph(per)
         g.graph_launch()  # one untimed replay
         torch.cuda.synchronize()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(repeats + 1)]
@@ -101,12 +99,14 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps):
         kms = None
         if kernel_reps > 0:
             # keep the GPU busy with one more replay while the host enqueues the
-            # back-to-back collide launches, so launch latency is not counted
+            # back-to-back launches, so launch latency is not counted; each
+            # launch repeats the last step's collide + stream pass (same inputs,
+            # same cell lists and draws, same output arrays)
             g.graph_launch()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(side)
             for _ in range(kernel_reps):
-                g.collide_drawn(stream_x=True)
+                g.recollide_last(restore_sites=False)
             b.record(side)
             torch.cuda.synchronize()
             kms = a.elapsed_time(b) / kernel_reps

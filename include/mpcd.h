@@ -135,7 +135,19 @@ typedef struct {
     void *ws;              /* workspace                                         */
     size_t ws_bytes;
     mpcd_params par;
-    int32_t reorder_every; /* graphs: mpcd_reorder after every this many steps (0: never) */
+    int32_t reorder_every; /* graphs: mpcd_reorder after every this many steps (0: never;
+                              ignored out of place)                             */
+    /* Out-of-place solvent (all three set, or all NULL): the step reads x, v,
+     * tag and writes the new solvent state to x_out, v_out, tag_out in cell
+     * order (the storage order that makes the next step's gathers and
+     * binning atomics local; it replaces mpcd_reorder).  Requires
+     * fuse_stream = 1; the output arrays may not alias the inputs; the
+     * inputs are left unchanged.  The caller swaps the two sets after each
+     * step.  mpcd_graph_create then captures an even number of steps that
+     * alternate between the two sets, so a replay leaves the state in x, v,
+     * tag (tag must then be non-NULL). */
+    void *x_out, *v_out;   /* [3N] (prec)                                        */
+    int32_t *tag_out;      /* [N]                                                */
 } mpcd_step_args;
 
 /* Workspace bytes for sys (host-side sizes only).  The workspace holds the cell
@@ -147,7 +159,8 @@ size_t mpcd_workspace_bytes(const mpcd_sys *sys);
 /* Byte offsets inside the workspace (for inspection by tests and tools):
  * out[0] status word (uint32), out[1] grid shifts [3*nsys] (double),
  * out[2] cell_start [n_cells+1] (int32), out[3] permutation [N+S] (int32,
- * particles grouped by global cell), out[4] cell of each particle (int32),
+ * particles grouped by global cell, solvent before sites within a cell),
+ * out[4] cell of each particle (int32),
  * out[5] slot within the cell (int32), out[6] site offsets d_j [3S] (double),
  * out[7] site velocities entering the collision [3S] (double). */
 int mpcd_workspace_offsets(const mpcd_sys *sys, int64_t out[8]);
@@ -188,13 +201,16 @@ int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag,
  * into the workspace, from the cell occupancies of the last mpcd_bin.
  * mpcd_collide_drawn then performs the collision of mpcd_collide with those
  * draws; kT_cell must be the value given to mpcd_cell_draws.  The pair gives
- * the same results as mpcd_collide. */
+ * the same results as mpcd_collide.  With x_out, v_out, tag_out non-NULL
+ * (all three) the solvent is collided and streamed out of place, as in
+ * mpcd_step: x_stream (required) and v, tag are read and left unchanged, and
+ * the new state goes to the outputs in cell order. */
 int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t seed,
                     const uint64_t *d_step, void *ws, size_t ws_bytes);
 int mpcd_collide_drawn(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream,
-                       double dt);
+                       double dt, void *x_out, void *v_out, int32_t *tag_out);
 
 /* Site positions and thermalized velocities, Eqs. (5) and (7).  Per body:
  * V = P/M, omega = A (Lhat / I) with Lhat_k = p . P_k q / 2; site offset

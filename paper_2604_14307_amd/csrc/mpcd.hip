@@ -263,7 +263,8 @@ TileCfg tile_config(const mpcd_sys *s)
 }
 
 struct Layout {
-    size_t status, shift, counts, partial, cell_start, cellid, slot, perm, draws, site_d, vpre, rtmp, total;
+    size_t status, shift, counts, partial, cell_start, site_start, cellid, slot, perm, draws, site_d, vpre, rtmp,
+        total;
 };
 
 constexpr int SCAN_T = 1024, SCAN_V = 4, SCAN_TILE = SCAN_T * SCAN_V;
@@ -285,9 +286,10 @@ Layout layout_of(const mpcd_sys *s)
     const int64_t nb = nbc > nbp ? nbc : nbp;
     L.status = take(256);
     L.shift = take(sizeof(double) * 3 * (size_t)s->nsys);
-    L.counts = take(sizeof(int32_t) * (size_t)s->n_cells);
-    L.partial = take(sizeof(int32_t) * (size_t)(nb + 1));
+    L.counts = take(sizeof(uint64_t) * (size_t)s->n_cells);  // packed: solvent (low 32 bits), sites (high)
+    L.partial = take(sizeof(uint64_t) * (size_t)(nb + 1));
     L.cell_start = take(sizeof(int32_t) * (size_t)(s->n_cells + 1));
+    L.site_start = take(sizeof(int32_t) * (size_t)(s->n_cells + 1));
     L.cellid = take(sizeof(int32_t) * (size_t)NT);
     L.slot = take(sizeof(int32_t) * (size_t)NT);
     L.perm = take(sizeof(int32_t) * (size_t)NT);
@@ -408,9 +410,15 @@ __device__ __forceinline__ void draw_cell(const SysDev &s, uint64_t seed, double
 //     their slots with one atomic per run.  Device-scope atomics are
 //     performed beyond the per-XCD L2s on MI355X, so their count and their
 //     spread over many addresses set the cost.
-//  2. k_scan_reduce / k_scan_down: exclusive scan of the counts -> cell_start
-//     (each block adds the earlier tile totals itself) and clears the counts.
-//  3. k_bin_scatter: perm[cell_start[cell] + slot] = particle.
+//     A cell's counter is 64 bits: solvent particles take slots from the low
+//     32 bits and sites from the high 32 bits, so one scan yields both.
+//  2. k_scan_reduce / k_scan_down: exclusive scan of the packed counters ->
+//     cell_start (all members) and site_start (sites in earlier cells); each
+//     block adds the earlier tile totals itself and clears the counters.
+//  3. k_bin_scatter: perm[cell_start[cell] + slot] = particle, solvent first
+//     within each cell, then its sites.  A solvent particle at permutation
+//     position p of cell c is therefore solvent number p - site_start[c] in
+//     cell order, the position the out-of-place collision writes it to.
 
 // Grid shift of system r at a step: a pure function of (seed, step, replica).
 __device__ __forceinline__ void shift_of(const SysDev &s, uint64_t seed, uint64_t step, int r, double sh[3])
@@ -449,23 +457,31 @@ __device__ __forceinline__ int32_t cell_of_pos(const SysDev &s, int r, Real p0, 
 }
 
 // Slots for one group of 64 lanes: one atomic per run of equal cells.
-__device__ __forceinline__ void run_slots(int32_t gc, int32_t *counts, int &hl, int &base)
+// A run is a stretch of lanes with the same cell and kind (solvent or site).
+__device__ __forceinline__ void run_slots(int32_t gc, bool site, unsigned long long *counts, int &hl, int &base)
 {
     const int lane = threadIdx.x & 63;
     const unsigned long long le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    const int32_t prev = __shfl_up(gc, 1, 64);
-    const bool head = (lane == 0) || (prev != gc);
+    const int32_t key = (site && gc >= 0) ? (int32_t)((uint32_t)gc | 0x80000000u) : gc;
+    const int32_t prev = __shfl_up(key, 1, 64);
+    const bool head = (lane == 0) || (prev != key);
     const unsigned long long heads = __ballot(head);
     hl = 63 - __clzll(heads & le);
     const unsigned long long above = heads & ~le;
     const int nh = above ? (__ffsll((long long)above) - 1) : 64;
-    base = (head && gc >= 0) ? atomicAdd(&counts[gc], nh - hl) : 0;
+    base = 0;
+    if (head && gc >= 0) {
+        const int sh = site ? 32 : 0;
+        const unsigned long long old = atomicAdd(&counts[gc], (unsigned long long)(nh - hl) << sh);
+        base = (int)((old >> sh) & 0xffffffffull);
+    }
 }
 
 // One chunk of BIN_CHUNK particles starting at kbase (< k1).
 template <typename Real, bool SITES>
 __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const int32_t *site_body,
-                          const BlockShift &bs, int32_t *counts, int32_t *cellid, int32_t *slot, int64_t kbase,
+                          const BlockShift &bs, unsigned long long *counts, int32_t *cellid, int32_t *slot,
+                          int64_t kbase,
                           int64_t k1, uint32_t &st)
 {
     const int lane = threadIdx.x & 63;
@@ -493,7 +509,8 @@ __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const 
     }
     int hl[BIN_ITEMS], base[BIN_ITEMS];
 #pragma unroll
-    for (int j = 0; j < BIN_ITEMS; ++j) run_slots(gc[j], counts, hl[j], base[j]);
+    for (int j = 0; j < BIN_ITEMS; ++j)
+        run_slots(gc[j], SITES && (wbase + (int64_t)j * BIN_T + lane) >= s.N, counts, hl[j], base[j]);
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const int b = __shfl(base[j], hl[j], 64);
@@ -517,7 +534,7 @@ __device__ __forceinline__ void chunk_systems(const SysDev &s, const int32_t *si
 template <typename Real>
 __global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, const Real *xs,
                                                      const int32_t *site_body, const double *shift,
-                                                     int32_t *counts, int32_t *cellid, int32_t *slot,
+                                                     unsigned long long *counts, int32_t *cellid, int32_t *slot,
                                                      uint32_t *status, int64_t k0, int64_t k1)
 {
     uint32_t st = 0;
@@ -528,93 +545,115 @@ __global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, co
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim = NTHR, wave64).
-template <int NTHR = SCAN_T>
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *total)
+template <int NTHR = SCAN_T, typename T = int32_t>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *total)
 {
     constexpr int NW = NTHR / 64;
-    __shared__ int32_t wsum[NW];
+    __shared__ T wsum[NW];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int32_t inc = v;
+    T inc = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        const int32_t y = __shfl_up(inc, d, 64);
+        const T y = __shfl_up(inc, d, 64);
         if (lane >= d) inc += y;
     }
     if (lane == 63) wsum[wid] = inc;
     __syncthreads();
     if (wid == 0) {
-        int32_t w = (lane < NW) ? wsum[lane] : 0;
-        int32_t wi = w;
+        T w = (lane < NW) ? wsum[lane] : (T)0;
+        T wi = w;
 #pragma unroll
         for (int d = 1; d < NW; d <<= 1) {
-            const int32_t y = __shfl_up(wi, d, 64);
+            const T y = __shfl_up(wi, d, 64);
             if (lane >= d) wi += y;
         }
         if (lane < NW) wsum[lane] = wi - w;
         if (lane == NW - 1) *total = wi;
     }
     __syncthreads();
-    const int32_t res = wsum[wid] + inc - v;
+    const T res = wsum[wid] + inc - v;
     __syncthreads();
     return res;
 }
 
-__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const int32_t *counts, int64_t C, int32_t *partial)
+using u64 = unsigned long long;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const u64 *counts, int64_t C, u64 *partial)
 {
-    __shared__ int32_t tot;
+    __shared__ u64 tot;
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
-    int32_t v = 0;
+    u64 v = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_V; ++i)
         if (base + i < C) v += counts[base + i];
-    (void)block_exclusive_scan(v, &tot);
+    (void)block_exclusive_scan<SCAN_T, u64>(v, &tot);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// Each block adds the totals of the earlier tiles itself, scans its tile into
-// cell_start and clears the counts for the next step.
-__global__ __launch_bounds__(SCAN_T) void k_scan_down(int32_t *counts, int64_t C, const int32_t *partial,
-                                                      int32_t *cell_start, int32_t total)
+// Each block adds the totals of the earlier tiles itself, scans its tile of
+// packed counters into cell_start (solvent + sites) and site_start (sites)
+// and clears the counters for the next step.  Packed sums cannot carry from
+// the low half into the high half: the solvent total is below 2^31.
+__global__ __launch_bounds__(SCAN_T) void k_scan_down(u64 *counts, int64_t C, const u64 *partial,
+                                                      int32_t *cell_start, int32_t *site_start, int32_t total,
+                                                      int32_t total_sites)
 {
-    __shared__ int32_t tot;
-    __shared__ int32_t pre;
-    int32_t carry = 0;
+    __shared__ u64 tot;
+    __shared__ u64 pre;
+    u64 carry = 0;
     for (int64_t b0 = 0; b0 < (int64_t)blockIdx.x; b0 += SCAN_T) {
         const int64_t i = b0 + threadIdx.x;
-        (void)block_exclusive_scan(i < (int64_t)blockIdx.x ? partial[i] : 0, &tot);
+        (void)block_exclusive_scan<SCAN_T, u64>(i < (int64_t)blockIdx.x ? partial[i] : 0ull, &tot);
         carry += tot;
     }
     if (threadIdx.x == 0) pre = carry;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
-    int32_t c[SCAN_V];
-    int32_t v = 0;
+    u64 c[SCAN_V];
+    u64 v = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_V; ++i) {
-        c[i] = (base + i < C) ? counts[base + i] : 0;
+        c[i] = (base + i < C) ? counts[base + i] : 0ull;
         v += c[i];
     }
-    int32_t run = pre + block_exclusive_scan(v, &tot);
+    u64 run = pre + block_exclusive_scan<SCAN_T, u64>(v, &tot);
 #pragma unroll
     for (int i = 0; i < SCAN_V; ++i) {
         if (base + i < C) {
-            cell_start[base + i] = run;
+            const uint32_t ns = (uint32_t)(run & 0xffffffffull), nq = (uint32_t)(run >> 32);
+            cell_start[base + i] = (int32_t)(ns + nq);
+            site_start[base + i] = (int32_t)nq;
             counts[base + i] = 0;
         }
         run += c[i];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[C] = total;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cell_start[C] = total;
+        site_start[C] = total_sites;
+    }
 }
 
-__global__ __launch_bounds__(BIN_T) void k_bin_scatter(int64_t NT, const int32_t *cellid, const int32_t *slot,
-                                                       const int32_t *cell_start, int32_t *perm, uint32_t *status)
+// Position of particle k (cell gc, slot within its kind) in the permutation:
+// solvent first, then the cell's sites.
+__device__ __forceinline__ int64_t perm_pos(const int32_t *cell_start, const int32_t *site_start, int64_t N,
+                                            int64_t k, int32_t gc, int32_t slot)
+{
+    const int32_t b = cell_start[gc];
+    if (k < N) return (int64_t)b + slot;
+    const int32_t nsol = (cell_start[gc + 1] - b) - (site_start[gc + 1] - site_start[gc]);
+    return (int64_t)b + nsol + slot;
+}
+
+__global__ __launch_bounds__(BIN_T) void k_bin_scatter(int64_t NT, int64_t N, const int32_t *cellid,
+                                                       const int32_t *slot, const int32_t *cell_start,
+                                                       const int32_t *site_start, int32_t *perm, uint32_t *status)
 {
     uint32_t st = 0;
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const int64_t k = (int64_t)blockIdx.x * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
         if (k < NT) {
-            const int64_t pos = (int64_t)cell_start[cellid[k]] + slot[k];
+            const int64_t pos = perm_pos(cell_start, site_start, N, k, cellid[k], slot[k]);
             if (pos >= 0 && pos < NT) perm[pos] = (int32_t)k;
             else st |= ST_BINERR;
         }
@@ -730,7 +769,7 @@ struct CollideArgs {
     SysDev s;
     const double *site_m;
     const int32_t *tag;
-    const int32_t *cell_start, *perm;
+    const int32_t *cell_start, *site_start, *perm;
     const double *draws; // [4][C]: random axis (3) and thermostat gamma variate of each cell
     double cos_a, sin_a, kT_cell, dt;
     uint64_t seed;
@@ -774,7 +813,7 @@ __global__ __launch_bounds__(BIN_T) void k_scatter_draws(int64_t NT, const int32
         for (int j = 0; j < BIN_ITEMS; ++j) {
             const int64_t k = (int64_t)blockIdx.x * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
             if (k < NT) {
-                const int64_t pos = (int64_t)A.cell_start[cellid[k]] + slot[k];
+                const int64_t pos = perm_pos(A.cell_start, A.site_start, A.s.N, k, cellid[k], slot[k]);
                 if (pos >= 0 && pos < NT) perm[pos] = (int32_t)k;
                 else st |= ST_BINERR;
             }
@@ -808,38 +847,117 @@ __device__ __forceinline__ double thermostat_factor(const CollideArgs &A, int64_
 // ---- fallback: one lane per cell, members read from global memory ----------
 // (tiles whose member count exceeds the LDS capacity)
 
-__device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double *v, double *vs, double *xstream,
-                                        uint32_t &st)
+template <typename Real> struct RealOps;
+template <> struct RealOps<double> {
+    __device__ static double wrap(double y, double L, uint32_t &st) { return wrap_d(y, L, st); }
+};
+template <> struct RealOps<float> {
+    __device__ static float wrap(float y, float L, uint32_t &st) { return wrap_f(y, L, st); }
+};
+
+// Out-of-place solvent output: the new state of the solvent in cell order
+// (v == nullptr: the collision works in place).
+template <typename Real> struct SolvOut {
+    Real *x, *v;
+    int32_t *tag;
+};
+
+// Velocity of the member at permutation position i (particle k): sites in
+// place; solvent in place, or at its cell-order slot of the output.
+template <typename Real> struct MemberVel {
+    Real *v, *vs, *vo;
+    int64_t N, S, ss;  // ss: sites in the cells before this one
+    __device__ Real &operator()(int i, int32_t k, int d) const
+    {
+        if (k >= N) return vs[d * S + (k - N)];
+        return vo ? vo[d * N + (i - ss)] : v[d * N + k];
+    }
+};
+
+// Cell gc with global-memory traffic only (a tile above the LDS capacity).
+// Out of place, the cell's solvent is first copied to its output slots and
+// collides there; the input arrays are not written.
+// Returns false (and the cell is skipped) when a solvent member's output slot
+// falls outside [0, N), which only a corrupted permutation can cause.
+template <typename Real>
+__device__ bool cell_out_prepare(const CollideArgs &A, int64_t gc, const Real *v, const SolvOut<Real> &O,
+                                 uint32_t &st)
+{
+    if (!O.v) return true;
+    const int64_t N = A.s.N, ss = A.site_start[gc];
+    for (int i = A.cell_start[gc]; i < A.cell_start[gc + 1]; ++i) {
+        const int64_t dst = i - ss;
+        if (A.perm[i] < N && (dst < 0 || dst >= N)) {
+            st |= ST_BINERR;
+            return false;
+        }
+    }
+    for (int i = A.cell_start[gc]; i < A.cell_start[gc + 1]; ++i) {
+        const int32_t k = A.perm[i];
+        if (k >= N) continue;
+        const int64_t dst = i - ss;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) O.v[d * N + dst] = v[d * N + k];
+        O.tag[dst] = A.tag ? A.tag[k] : k;
+    }
+    return true;
+}
+
+template <typename Real>
+__device__ void cell_stream_global(const CollideArgs &A, int64_t gc, const MemberVel<Real> &vel, Real *x,
+                                   const SolvOut<Real> &O, uint32_t &st)
+{
+    if (!x) return;
+    const SysDev &s = A.s;
+    const int64_t N = s.N;
+    const int r = find_sys(s.cell_off, s.nsys, gc);
+    const Real dtr = (Real)A.dt;
+    for (int i = A.cell_start[gc]; i < A.cell_start[gc + 1]; ++i) {
+        const int32_t k = A.perm[i];
+        if (k >= N) continue;
+        Real *xd = O.v ? O.x + (i - vel.ss) : x + k;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
+            xd[d * N] = RealOps<Real>::wrap(x[d * N + k] + vel(i, k, d) * dtr, L, st);
+        }
+    }
+}
+
+__device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double *v, double *vs, double *x,
+                                        const SolvOut<double> &O, uint32_t &st)
 {
     const SysDev &s = A.s;
     const int b = A.cell_start[gc], e = A.cell_start[gc + 1], n = e - b;
     if (n == 0) return;
-    const int r = find_sys(s.cell_off, s.nsys, gc);
     const int64_t N = s.N, S = s.S;
-    auto key_of = [&](int32_t k) -> uint64_t { return ((uint64_t)ident(A, k) << 32) | (uint32_t)k; };
+    if (!cell_out_prepare<double>(A, gc, v, O, st)) return;
+    const MemberVel<double> vel{v, vs, O.v, N, S, A.site_start[gc]};
+    // identity key in the high word, permutation position in the low word
+    auto key_at = [&](int i) -> uint64_t { return ((uint64_t)ident(A, A.perm[i]) << 32) | (uint32_t)i; };
     auto mass = [&](int32_t k) -> double { return k < N ? s.m : A.site_m[k - N]; };
-    auto vel = [&](int32_t k, int d) -> double & { return k < N ? v[d * N + k] : vs[d * S + (k - N)]; };
     // members in ascending identity by repeated selection of the next key
     auto canonical = [&](auto &&fn) {
         uint64_t lo = 0;
-        for (int i = 0; i < n; ++i) {
+        for (int c = 0; c < n; ++c) {
             uint64_t best = ~0ull;
             for (int j = b; j < e; ++j) {
-                const uint64_t kk = key_of(A.perm[j]);
+                const uint64_t kk = key_at(j);
                 if (kk >= lo && kk < best) best = kk;
             }
             lo = best + 1;
-            fn((int32_t)(uint32_t)(best & 0xffffffffu));
+            const int i = (int)(uint32_t)(best & 0xffffffffu);
+            fn(i, A.perm[i]);
         }
     };
     if (n >= 2) {
         double M = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0;
-        canonical([&](int32_t k) {
+        canonical([&](int i, int32_t k) {
             const double mk = mass(k);
             M = M + mk;
-            P0 = P0 + mk * vel(k, 0);
-            P1 = P1 + mk * vel(k, 1);
-            P2 = P2 + mk * vel(k, 2);
+            P0 = P0 + mk * vel(i, k, 0);
+            P1 = P1 + mk * vel(i, k, 1);
+            P2 = P2 + mk * vel(i, k, 2);
         });
         const double u[3] = {P0 / M, P1 / M, P2 / M};
         double nax[3];
@@ -848,35 +966,25 @@ __device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double
         double lam = 1.0;
         if (A.kT_cell > 0.0) {
             double Es = 0.0;
-            canonical([&](int32_t k) {
-                const double d0 = vel(k, 0) - u[0], d1 = vel(k, 1) - u[1], d2 = vel(k, 2) - u[2];
+            canonical([&](int i, int32_t k) {
+                const double d0 = vel(i, k, 0) - u[0], d1 = vel(i, k, 1) - u[1], d2 = vel(i, k, 2) - u[2];
                 Es = Es + mass(k) * ((d0 * d0 + d1 * d1) + d2 * d2);
             });
             lam = thermostat_factor(A, gc, 0.5 * Es);
         }
         for (int i = b; i < e; ++i) {
             const int32_t k = A.perm[i];
-            const double dl[3] = {vel(k, 0) - u[0], vel(k, 1) - u[1], vel(k, 2) - u[2]};
+            const double dl[3] = {vel(i, k, 0) - u[0], vel(i, k, 1) - u[1], vel(i, k, 2) - u[2]};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const double rr = (R.R[d][0] * dl[0] + R.R[d][1] * dl[1]) + R.R[d][2] * dl[2];
                 const double vn = u[d] + lam * rr;
                 if (!(vn - vn == 0.0)) st |= ST_NONFINITE;
-                vel(k, d) = vn;
+                vel(i, k, d) = vn;
             }
         }
     }
-    if (xstream) {
-        for (int i = b; i < e; ++i) {
-            const int32_t k = A.perm[i];
-            if (k >= N) continue;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double L = (double)s.ncell[3 * r + d] * s.a;
-                xstream[d * N + k] = wrap_d(xstream[d * N + k] + v[d * N + k] * A.dt, L, st);
-            }
-        }
-    }
+    cell_stream_global<double>(A, gc, vel, x, O, st);
 }
 
 constexpr double FIX_SCALE = 0x1p32, FIX_LIM = 0x1p62;
@@ -923,21 +1031,21 @@ __device__ __forceinline__ void f32_cell_params(const CollideArgs &A, int64_t gc
     uf[0] = (float)u0; uf[1] = (float)u1; uf[2] = (float)u2;
 }
 
-__device__ void collide_cell_f32_global(const CollideArgs &A, int64_t gc, float *v, float *vs, float *xstream,
-                                        uint32_t &st)
+__device__ void collide_cell_f32_global(const CollideArgs &A, int64_t gc, float *v, float *vs, float *x,
+                                        const SolvOut<float> &O, uint32_t &st)
 {
     const SysDev &s = A.s;
     const int b = A.cell_start[gc], e = A.cell_start[gc + 1], n = e - b;
     if (n == 0) return;
-    const int r = find_sys(s.cell_off, s.nsys, gc);
     const int64_t N = s.N, S = s.S;
-    auto vel = [&](int32_t k, int d) -> float & { return k < N ? v[d * N + k] : vs[d * S + (k - N)]; };
+    if (!cell_out_prepare<float>(A, gc, v, O, st)) return;
+    const MemberVel<float> vel{v, vs, O.v, N, S, A.site_start[gc]};
     if (n >= 2) {
         long long acc[5] = {0, 0, 0, 0, 0};
         for (int i = b; i < e; ++i) {
             const int32_t k = A.perm[i];
             long long q[5];
-            fixed_terms(k < N ? s.m : A.site_m[k - N], vel(k, 0), vel(k, 1), vel(k, 2), q, st);
+            fixed_terms(k < N ? s.m : A.site_m[k - N], vel(i, k, 0), vel(i, k, 1), vel(i, k, 2), q, st);
 #pragma unroll
             for (int j = 0; j < 5; ++j) acc[j] += q[j];
         }
@@ -945,27 +1053,16 @@ __device__ void collide_cell_f32_global(const CollideArgs &A, int64_t gc, float 
         f32_cell_params(A, gc, acc, uf, Rf);
         for (int i = b; i < e; ++i) {
             const int32_t k = A.perm[i];
-            const float dl[3] = {vel(k, 0) - uf[0], vel(k, 1) - uf[1], vel(k, 2) - uf[2]};
+            const float dl[3] = {vel(i, k, 0) - uf[0], vel(i, k, 1) - uf[1], vel(i, k, 2) - uf[2]};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const float vn = uf[d] + ((Rf[d][0] * dl[0] + Rf[d][1] * dl[1]) + Rf[d][2] * dl[2]);
                 if (!(vn - vn == 0.0f)) st |= ST_NONFINITE;
-                vel(k, d) = vn;
+                vel(i, k, d) = vn;
             }
         }
     }
-    if (xstream) {
-        const float dtf = (float)A.dt;
-        for (int i = b; i < e; ++i) {
-            const int32_t k = A.perm[i];
-            if (k >= N) continue;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const float L = (float)((double)s.ncell[3 * r + d] * s.a);
-                xstream[d * N + k] = wrap_f(xstream[d * N + k] + v[d * N + k] * dtf, L, st);
-            }
-        }
-    }
+    cell_stream_global<float>(A, gc, vel, x, O, st);
 }
 
 // ---- tiled collision: a block owns cpb consecutive cells -------------------
@@ -985,7 +1082,7 @@ __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(siz
 
 // LDS layout: offsets of s_cs, s_idx, s_cl, s_v, s_key|s_acc, s_par, s_r, end.
 struct TileLayout {
-    size_t cs, idx, cl, v, keyacc, par, r, end;
+    size_t cs, idx, cl, v, keyacc, par, r, ss, end;
 };
 
 __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
@@ -999,20 +1096,15 @@ __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
     L.keyacc = o; o += align16(f64 ? sizeof(uint64_t) * (size_t)cap : 0);
     L.par = o; o += align16(f64 ? sizeof(double) * 13 * (size_t)cpb : sizeof(float) * 12 * (size_t)cpb);
     L.r = o; o += align16(sizeof(int) * (size_t)cpb);
+    L.ss = o; o += align16(sizeof(int) * (size_t)cpb);
     L.end = o;
     return L;
 }
 
-template <typename Real> struct RealOps;
-template <> struct RealOps<double> {
-    __device__ static double wrap(double y, double L, uint32_t &st) { return wrap_d(y, L, st); }
-};
-template <> struct RealOps<float> {
-    __device__ static float wrap(float y, float L, uint32_t &st) { return wrap_f(y, L, st); }
-};
 
 template <typename Real, int ITEMS>
-__global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg T, Real *v, Real *vs, Real *xstream)
+__global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg T, Real *v, Real *vs, Real *xstream,
+                                                          SolvOut<Real> O)
 {
     constexpr bool F64 = sizeof(Real) == 8;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1027,8 +1119,8 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
     uint32_t st = 0;
     if (nm > T.cap) {
         for (int c = t; c < nc; c += TILE_T) {
-            if constexpr (F64) collide_cell_f64_global(A, c0 + c, v, vs, xstream, st);
-            else collide_cell_f32_global(A, c0 + c, v, vs, xstream, st);
+            if constexpr (F64) collide_cell_f64_global(A, c0 + c, v, vs, xstream, O, st);
+            else collide_cell_f32_global(A, c0 + c, v, vs, xstream, O, st);
         }
         flag(A.status, st);
         return;
@@ -1041,7 +1133,9 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
     Real *s_v = (Real *)(smem + Lo.v);
     uint64_t *s_key = (uint64_t *)(smem + Lo.keyacc);
     int *s_r = (int *)(smem + Lo.r);
+    int *s_ss = (int *)(smem + Lo.ss);
     const int64_t N = s.N, S = s.S;
+    const bool out = O.v != nullptr;
 
     // phase 0: the tile's cell ranges; this lane's cell system and draws
     for (int c = t; c <= nc; c += TILE_T) s_cs[c] = A.cell_start[c0 + c] - m0;
@@ -1049,6 +1143,7 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
     if (t < nc) {
         const int64_t gc = c0 + t;
         s_r[t] = find_sys(s.cell_off, s.nsys, gc);
+        if (out) s_ss[t] = A.site_start[gc];
         read_axis(A, gc, nax);
         if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
     }
@@ -1062,6 +1157,7 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
         kk[j] = (i < nm) ? A.perm[m0 + i] : -1;
     }
     Real va[ITEMS][3], xo[ITEMS][3];
+    int32_t tg[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int32_t k = kk[j];
@@ -1071,6 +1167,7 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
                 if (xstream) {
                     xo[j][0] = xstream[k]; xo[j][1] = xstream[N + k]; xo[j][2] = xstream[2 * N + k];
                 }
+                if (out) tg[j] = A.tag ? A.tag[k] : k;
             } else {
                 const int64_t q = k - N;
                 va[j][0] = vs[q]; va[j][1] = vs[S + q]; va[j][2] = vs[2 * S + q];
@@ -1167,7 +1264,8 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
     }
     __syncthreads();
 
-    // phase 3: rotate, stream, write back
+    // phase 3: rotate, stream, write back (solvent out of place: to its
+    // cell-order slot, every member whether or not its cell collided)
     const Real dtr = (Real)A.dt;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -1196,14 +1294,29 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
                     if (!(vn[d] - vn[d] == 0.0f)) st |= ST_NONFINITE;
                 }
             }
-            if (k < N) {
-                v[k] = vn[0]; v[N + k] = vn[1]; v[2 * N + k] = vn[2];
-            } else {
+            if (k >= N) {
                 const int64_t q = k - N;
                 vs[q] = vn[0]; vs[S + q] = vn[1]; vs[2 * S + q] = vn[2];
+            } else if (!out) {
+                v[k] = vn[0]; v[N + k] = vn[1]; v[2 * N + k] = vn[2];
             }
         }
-        if (xstream && k < N) {
+        if (k >= N) continue;
+        if (out) {
+            const int64_t dst = (int64_t)(m0 + i) - s_ss[c];
+            if (dst < 0 || dst >= N) {  // only with a corrupted permutation
+                st |= ST_BINERR;
+                continue;
+            }
+            const int r = s_r[c];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
+                O.x[d * N + dst] = RealOps<Real>::wrap(xo[j][d] + vn[d] * dtr, L, st);
+                O.v[d * N + dst] = vn[d];
+            }
+            O.tag[dst] = tg[j];
+        } else if (xstream) {
             const int r = s_r[c];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -1263,7 +1376,8 @@ struct ThermLds {
 template <typename Real>
 __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, double kT, int thermalize,
                                 uint64_t seed, uint64_t step, Real *xs, Real *vs, double *site_d, double *vpre,
-                                const double *bsh, int32_t *counts, int32_t *cellid, int32_t *slot, ThermLds &lds,
+                                const double *bsh, unsigned long long *counts, int32_t *cellid, int32_t *slot,
+                                ThermLds &lds,
                                 uint32_t &st)
 {
     double *sh = lds.sh, *sacc = lds.sacc, *dvw = lds.dvw;
@@ -1315,7 +1429,7 @@ __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, d
             // bin this chunk's sites (all lanes take part in the run detection)
             const int32_t gc = (j < j1) ? cell_of_pos<Real>(s, r, xr[0], xr[1], xr[2], bsh, st) : -1;
             int hl, base;
-            run_slots(gc, counts, hl, base);
+            run_slots(gc, true, counts, hl, base);
             const int bb = __shfl(base, hl, 64);
             if (j < j1) {
                 slot[s.N + j] = bb + ((threadIdx.x & 63) - hl);
@@ -1385,7 +1499,8 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
 template <typename Real>
 __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT, int thermalize, uint64_t seed,
                                                  const uint64_t *d_step, const Real *x, Real *xs, Real *vs,
-                                                 double *site_d, double *vpre, int32_t *counts, int32_t *cellid,
+                                                 double *site_d, double *vpre, unsigned long long *counts,
+                                                 int32_t *cellid,
                                                  int32_t *slot, double *shift_out, uint32_t *status)
 {
     __shared__ double bsh[6];
@@ -1792,8 +1907,8 @@ int mpcd_ws_init(void *stream, const mpcd_sys *sys, void *ws, size_t ws_bytes)
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, at<uint32_t>(ws, L.status), (int64_t)64, 0u);
     const int64_t NT = sys->n_solvent + sys->n_sites;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(sys->n_cells, 256)), dim3(256), 0, st, at<int32_t>(ws, L.counts),
-                       sys->n_cells, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * sys->n_cells, 256)), dim3(256), 0, st,
+                       at<int32_t>(ws, L.counts), 2 * sys->n_cells, 0);
     if (NT > 0)  // the permutation holds valid particle indices from the start
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NT, 256)), dim3(256), 0, st, at<int32_t>(ws, L.perm), NT, 0);
     return launch_check();
@@ -1854,7 +1969,8 @@ static void launch_bin_count(const Ctx &c, hipStream_t st, const void *x, const 
     if (k1 <= k0) return;
     const unsigned g = (unsigned)((k1 - k0 + BIN_CHUNK - 1) / BIN_CHUNK);
     double *shift = at<double>(c.ws, c.L.shift);
-    int32_t *counts = at<int32_t>(c.ws, c.L.counts), *cellid = at<int32_t>(c.ws, c.L.cellid);
+    u64 *counts = at<u64>(c.ws, c.L.counts);
+    int32_t *cellid = at<int32_t>(c.ws, c.L.cellid);
     int32_t *slot = at<int32_t>(c.ws, c.L.slot);
     if (c.sys->prec == MPCD_F64)
         hipLaunchKernelGGL(k_bin_count<double>, dim3(g), dim3(BIN_T), 0, st, c.sd, (const double *)x,
@@ -1868,10 +1984,11 @@ static void launch_scan(const Ctx &c, hipStream_t st)
 {
     const int64_t NT = c.sys->n_solvent + c.sys->n_sites, C = c.sys->n_cells;
     const int64_t nb = (C + SCAN_TILE - 1) / SCAN_TILE;
-    int32_t *counts = at<int32_t>(c.ws, c.L.counts), *partial = at<int32_t>(c.ws, c.L.partial);
-    int32_t *cs = at<int32_t>(c.ws, c.L.cell_start);
+    u64 *counts = at<u64>(c.ws, c.L.counts), *partial = at<u64>(c.ws, c.L.partial);
+    int32_t *cs = at<int32_t>(c.ws, c.L.cell_start), *ss = at<int32_t>(c.ws, c.L.site_start);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial, cs, (int32_t)NT);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial, cs, ss, (int32_t)NT,
+                       (int32_t)c.sys->n_sites);
 }
 
 static void launch_scatter(const Ctx &c, hipStream_t st)
@@ -1879,7 +1996,8 @@ static void launch_scatter(const Ctx &c, hipStream_t st)
     const int64_t NT = c.sys->n_solvent + c.sys->n_sites;
     if (NT == 0) return;
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((NT + BIN_CHUNK - 1) / BIN_CHUNK)), dim3(BIN_T), 0, st, NT,
-                       at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot), at<int32_t>(c.ws, c.L.cell_start),
+                       c.sys->n_solvent, at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot),
+                       at<int32_t>(c.ws, c.L.cell_start), at<int32_t>(c.ws, c.L.site_start),
                        at<int32_t>(c.ws, c.L.perm), c.status);
 }
 
@@ -1892,6 +2010,7 @@ static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bod
     A.site_m = bodies ? bodies->site_m : nullptr;
     A.tag = tag;
     A.cell_start = at<int32_t>(c.ws, c.L.cell_start);
+    A.site_start = at<int32_t>(c.ws, c.L.site_start);
     A.perm = at<int32_t>(c.ws, c.L.perm);
     A.draws = at<double>(c.ws, c.L.draws);
     A.cos_a = cos_a;
@@ -1912,18 +2031,24 @@ static void launch_draws(const Ctx &c, hipStream_t st, const CollideArgs &A, int
                        at<double>(c.ws, c.L.draws), mode);
 }
 
-static void launch_collide(const Ctx &c, hipStream_t st, const CollideArgs &A, void *v, void *vs, void *x_stream)
+// x_stream: positions streamed in place, or (out of place) read and streamed
+// into x_out.  v_out == nullptr: in place.
+static void launch_collide(const Ctx &c, hipStream_t st, const CollideArgs &A, void *v, void *vs, void *x_stream,
+                           void *x_out = nullptr, void *v_out = nullptr, int32_t *tag_out = nullptr)
 {
     const bool f64 = c.sys->prec == MPCD_F64;
     const TileCfg T = tile_config(c.sys);
     const dim3 grid(xcd_grid(T.ntiles));
     const size_t lds = tile_layout(f64, T.cpb, T.cap).end;
-    if (f64)
+    if (f64) {
+        const SolvOut<double> O{(double *)x_out, (double *)v_out, tag_out};
         hipLaunchKernelGGL((k_collide_tiled<double, ITEMS_F64>), grid, dim3(TILE_T), lds, st, A, T, (double *)v,
-                           (double *)vs, (double *)x_stream);
-    else
+                           (double *)vs, (double *)x_stream, O);
+    } else {
+        const SolvOut<float> O{(float *)x_out, (float *)v_out, tag_out};
         hipLaunchKernelGGL((k_collide_tiled<float, ITEMS_F32>), grid, dim3(TILE_T), lds, st, A, T, (float *)v,
-                           (float *)vs, (float *)x_stream);
+                           (float *)vs, (float *)x_stream, O);
+    }
 }
 
 static void launch_thermalize(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, double kT, int thermalize,
@@ -1953,7 +2078,8 @@ static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies,
     if (nb == 0) sd.B = 0;  // no site work: every block bins solvent
     const dim3 g((unsigned)(nb + nchunks > 0 ? nb + nchunks : 1));
     double *site_d = at<double>(c.ws, c.L.site_d), *vpre = at<double>(c.ws, c.L.vpre);
-    int32_t *counts = at<int32_t>(c.ws, c.L.counts), *cellid = at<int32_t>(c.ws, c.L.cellid);
+    u64 *counts = at<u64>(c.ws, c.L.counts);
+    int32_t *cellid = at<int32_t>(c.ws, c.L.cellid);
     int32_t *slot = at<int32_t>(c.ws, c.L.slot);
     double *shift = at<double>(c.ws, c.L.shift);
     if (c.sys->prec == MPCD_F64)
@@ -2078,6 +2204,21 @@ static int collide_checks(const mpcd_sys *sys, const void *v, const int32_t *tag
     return MPCD_OK;
 }
 
+// Out-of-place solvent output: all three arrays or none; it needs the input
+// positions (the solvent is streamed into x_out) and may not alias the inputs.
+static int out_checks(const mpcd_sys *sys, const void *v, const int32_t *tag, const void *x, const void *x_out,
+                      const void *v_out, const int32_t *tag_out)
+{
+    if (!x_out && !v_out && !tag_out) return MPCD_OK;
+    const int64_t N = sys->n_solvent;
+    if (N == 0) return MPCD_OK;
+    if (!x_out || !v_out || !tag_out || !x) return MPCD_EINVAL;
+    if (!ok_arr(x_out, N, esize(sys)) || !ok_arr(v_out, N, esize(sys)) || !ok_arr(tag_out, N, 4)) return MPCD_EINVAL;
+    if (x_out == x || x_out == v || v_out == x || v_out == v || (tag && (const void *)tag_out == (const void *)tag))
+        return MPCD_EINVAL;
+    return MPCD_OK;
+}
+
 int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
                  const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell, uint64_t seed,
                  const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt)
@@ -2105,12 +2246,14 @@ int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t 
 
 int mpcd_collide_drawn(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
-                       const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt)
+                       const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt,
+                       void *x_out, void *v_out, int32_t *tag_out)
 {
     TRY(collide_checks(sys, v, tag, vs, bodies, d_step, ws, ws_bytes, x_stream, dt));
+    TRY(out_checks(sys, v, tag, x_stream, x_out, v_out, tag_out));
     const Ctx c = make_ctx(sys, ws);
     const CollideArgs A = collide_args(c, tag, bodies, cos_a, sin_a, kT_cell, 0, d_step, dt, nullptr);
-    launch_collide(c, (hipStream_t)stream, A, v, vs, x_stream);
+    launch_collide(c, (hipStream_t)stream, A, v, vs, x_stream, x_out, v_out, tag_out);
     return launch_check();
 }
 
@@ -2212,6 +2355,8 @@ static int step_checks(const mpcd_step_args *a)
     if (!(p.dt > 0.0)) return MPCD_EINVAL;
     if (!ok_arr(a->J, s->n_bodies, 8) || !ok_arr(a->K, s->n_bodies, 8)) return MPCD_EINVAL;
     if (a->reorder_every < 0 || (a->reorder_every > 0 && !ok_arr(a->tag, s->n_solvent, 4))) return MPCD_EINVAL;
+    TRY(out_checks(s, a->v, a->tag, a->x, a->x_out, a->v_out, a->tag_out));
+    if (a->v_out && !p.fuse_stream) return MPCD_ENOTSUP;
     return MPCD_OK;
 }
 
@@ -2232,7 +2377,10 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
     const CollideArgs A = collide_args(c, a->tag, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed, a->d_step, p.dt,
                                        nullptr);
     launch_scatter_draws(c, st, A);
-    launch_collide(c, st, A, a->v, a->vs, p.fuse_stream ? a->x : nullptr);
+    if (a->v_out)
+        launch_collide(c, st, A, a->v, a->vs, a->x, a->x_out, a->v_out, a->tag_out);
+    else
+        launch_collide(c, st, A, a->v, a->vs, p.fuse_stream ? a->x : nullptr);
     if (!p.fuse_stream) TRY(mpcd_stream(stream, s, a->x, a->v, p.dt, a->ws, a->ws_bytes));
     if (s->n_bodies == 0) {
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a->d_step);
@@ -2247,12 +2395,22 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
 {
     if (!stream || !args || nsteps < 1 || !graph_exec) return MPCD_EINVAL;
     TRY(step_checks(args));
+    if (args->v_out && ((nsteps & 1) || !args->tag)) return MPCD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     TRY(hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)));
     int rc = MPCD_OK;
+    mpcd_step_args swapped = *args;  // odd steps of the out-of-place form: outputs become inputs
+    if (args->v_out) {
+        swapped.x = args->x_out;
+        swapped.v = args->v_out;
+        swapped.tag = args->tag_out;
+        swapped.x_out = args->x;
+        swapped.v_out = args->v;
+        swapped.tag_out = (int32_t *)args->tag;
+    }
     for (int i = 0; i < nsteps && rc == MPCD_OK; ++i) {
-        rc = mpcd_step(stream, args);
-        if (rc == MPCD_OK && args->reorder_every > 0 && (i + 1) % args->reorder_every == 0)
+        rc = mpcd_step(stream, (args->v_out && (i & 1)) ? &swapped : args);
+        if (rc == MPCD_OK && !args->v_out && args->reorder_every > 0 && (i + 1) % args->reorder_every == 0)
             rc = mpcd_reorder(stream, args->sys, args->x, args->v, (int32_t *)args->tag, args->ws, args->ws_bytes);
     }
     hipGraph_t graph = nullptr;

@@ -51,7 +51,8 @@ class MpcdParams(C.Structure):
 class MpcdStepArgs(C.Structure):
     _fields_ = [("sys", C.POINTER(MpcdSys)), ("bodies", MpcdBodies), ("x", vp), ("v", vp), ("tag", vp),
                 ("xs", vp), ("vs", vp), ("J", vp), ("K", vp), ("d_step", vp), ("ws", vp),
-                ("ws_bytes", C.c_size_t), ("par", MpcdParams), ("reorder_every", C.c_int32)]
+                ("ws_bytes", C.c_size_t), ("par", MpcdParams), ("reorder_every", C.c_int32),
+                ("x_out", vp), ("v_out", vp), ("tag_out", vp)]
 
 
 _lib = None
@@ -79,7 +80,7 @@ def load(path: str = LIB_PATH):
         "mpcd_bin": (C.c_int, [vp, sp, vp, vp, bp, u64, vp, vp, sz]),
         "mpcd_collide": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, u64, vp, vp, sz, vp, dbl]),
         "mpcd_cell_draws": (C.c_int, [vp, sp, dbl, u64, vp, vp, sz]),
-        "mpcd_collide_drawn": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, vp, vp, sz, vp, dbl]),
+        "mpcd_collide_drawn": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, vp, vp, sz, vp, dbl, vp, vp, vp]),
         "sites_thermalize": (C.c_int, [vp, sp, bp, dbl, i32, u64, vp, vp, vp, vp, sz]),
         "sites_to_body": (C.c_int, [vp, sp, bp, vp, vp, sz, vp, vp]),
         "body_integrate": (C.c_int, [vp, sp, bp, vp, vp, wp, dbl, vp, sz]),

@@ -22,7 +22,7 @@ def _ptr(t):
 
 class GPUSystem:
     def __init__(self, systems, params: dict, prec: str = "f64", replica0: int = 0,
-                 device: str = "cuda:0", fuse_stream: bool = True):
+                 device: str = "cuda:0", fuse_stream: bool = True, out_of_place: bool = True):
         self.lib = L.load()
         if isinstance(systems, dict):
             systems = [systems]
@@ -66,8 +66,15 @@ class GPUSystem:
         self.x = cat("x", self.real, 3)
         self.v = cat("v", self.real, 3)
         # solvent identities (global index in packing order); the storage
-        # reorder permutes them along with x and v
+        # order changes (out-of-place steps, reorder) carry them along
         self.tag = torch.arange(self.N, dtype=torch.int32, device=dev)
+        # out-of-place steps write the solvent in cell order into a second set
+        # of arrays; the two sets swap roles after every step
+        self.out_of_place = bool(out_of_place) and bool(fuse_stream)
+        if self.out_of_place:
+            self.x2 = torch.empty_like(self.x)
+            self.v2 = torch.empty_like(self.v)
+            self.tag2 = torch.empty_like(self.tag)
         self.pos = cat("R", torch.float64, 3)
         self.image = cat("img", torch.int32, 3)
         self.quat = cat("q", torch.float64, 4)
@@ -133,11 +140,20 @@ class GPUSystem:
         par = L.MpcdParams(dt=p["dt"], cos_a=p["cos_a"], sin_a=p["sin_a"], kT=p["kT"], kT_cell=p["kT_cell"],
                            seed=p["seed"], thermalize=int(p.get("thermalize", 1)),
                            fuse_stream=int(self.fuse_stream), wca=self.cwca)
+        out = self.out_of_place
         self._args = L.MpcdStepArgs(sys=C.pointer(self.csys), bodies=self.cbodies, x=_ptr(self.x), v=_ptr(self.v),
                                     tag=_ptr(self.tag), xs=_ptr(self.xs), vs=_ptr(self.vs), J=_ptr(self.J),
                                     K=_ptr(self.K), d_step=_ptr(self.d_step), ws=_ptr(self.ws),
-                                    ws_bytes=self.ws_bytes, par=par, reorder_every=int(reorder_every))
+                                    ws_bytes=self.ws_bytes, par=par, reorder_every=int(reorder_every),
+                                    x_out=_ptr(self.x2) if out else C.c_void_p(0),
+                                    v_out=_ptr(self.v2) if out else C.c_void_p(0),
+                                    tag_out=_ptr(self.tag2) if out else C.c_void_p(0))
         return self._args
+
+    def _swap(self):
+        self.x, self.x2 = self.x2, self.x
+        self.v, self.v2 = self.v2, self.v
+        self.tag, self.tag2 = self.tag2, self.tag
 
     # --- entry points -------------------------------------------------
     def sites_thermalize(self):
@@ -170,7 +186,8 @@ class GPUSystem:
         L.check(self.lib.mpcd_collide_drawn(self.stream, C.byref(self.csys), _ptr(self.v), _ptr(self.tag),
                                             _ptr(self.vs), C.byref(self.cbodies), p["cos_a"], p["sin_a"],
                                             p["kT_cell"], _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
-                                            _ptr(self.x) if stream_x else C.c_void_p(0), p["dt"]),
+                                            _ptr(self.x) if stream_x else C.c_void_p(0), p["dt"],
+                                            C.c_void_p(0), C.c_void_p(0), C.c_void_p(0)),
                 "mpcd_collide_drawn")
 
     def sites_to_body(self):
@@ -196,17 +213,40 @@ class GPUSystem:
         L.check(self.lib.mpcd_advance_step(self.stream, _ptr(self.d_step)), "mpcd_advance_step")
 
     def step(self, nsteps: int = 1):
-        args = self.step_args()
         for _ in range(nsteps):
+            args = self.step_args()
             L.check(self.lib.mpcd_step(self.stream, C.byref(args)), "mpcd_step")
+            if self.out_of_place:
+                self._swap()
+
+    def recollide_last(self, restore_sites: bool = True):
+        """Repeat the last out-of-place step's collide + stream pass from its
+        inputs into the current arrays.  The sites collide in place, so their
+        velocities entering that collision are restored first (then the result
+        is bit-identical); without the restore, cells with sites see the sites'
+        post-collision velocities (same work, for timing the kernel)."""
+        if not self.out_of_place:
+            raise ValueError("recollide_last needs the out-of-place form")
+        if restore_sites and self.S > 0:
+            self.vs.copy_(self.ws_view("vpre", torch.float64, 3 * self.S).view(3, self.S))
+        p = self.params
+        L.check(self.lib.mpcd_collide_drawn(self.stream, C.byref(self.csys), _ptr(self.v2), _ptr(self.tag2),
+                                            _ptr(self.vs), C.byref(self.cbodies), p["cos_a"], p["sin_a"],
+                                            p["kT_cell"], _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
+                                            _ptr(self.x2), p["dt"], _ptr(self.x), _ptr(self.v), _ptr(self.tag)),
+                "mpcd_collide_drawn")
 
     def reorder(self):
         L.check(self.lib.mpcd_reorder(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.v), _ptr(self.tag),
                                       _ptr(self.ws), self.ws_bytes), "mpcd_reorder")
 
     def graph(self, nsteps: int, reorder_every: int = 0):
-        """Capture nsteps steps (with a storage reorder after every reorder_every
-        steps) into a HIP graph; the current stream must not be the null stream."""
+        """Capture nsteps steps into a HIP graph (the current stream must not be
+        the null stream).  Out of place, nsteps must be even (a replay leaves the
+        state in the current arrays); in place, a storage reorder follows every
+        reorder_every steps."""
+        if self.out_of_place and nsteps % 2:
+            raise ValueError("out-of-place graphs capture an even number of steps")
         self.release_graph()
         args = self.step_args(reorder_every)
         h = C.c_void_p(0)

@@ -46,9 +46,9 @@ def assert_same(o, gd, keys=STATE_KEYS, where=""):
                                  % (where, k, i, len(diff), a[i], b[i]))
 
 
-def run_parity(wl, par, nsteps, fuse=True, check_every=1, step0=0, reorder_every=0):
+def run_parity(wl, par, nsteps, fuse=True, check_every=1, step0=0, reorder_every=0, out_of_place=True):
     o = oracle.OracleSystem(wl, par)
-    g = gpu_system(wl, par, prec="f64", fuse_stream=fuse)
+    g = gpu_system(wl, par, prec="f64", fuse_stream=fuse, out_of_place=out_of_place)
     o.body_forces()
     g.body_forces()
     g.set_step(step0)
@@ -147,11 +147,46 @@ def test_single_sphere_100_steps_bit_exact(kT_cell):
     run_parity(wl, par, meta["steps"])
 
 
+def test_in_place_form_bit_exact():
+    """The in-place form (solvent storage order kept) over 100 steps."""
+    wl, par, meta = W.config(0, kT_cell=1.0)
+    say("in place")
+    run_parity(wl, par, meta["steps"], check_every=10, out_of_place=False)
+
+
+def test_out_of_place_step_writes_solvent_in_cell_order():
+    """After an out-of-place step the solvent storage holds the previous
+    storage's particles in the order of the step's cell lists (solvent before
+    sites in each cell)."""
+    wl, par, _ = W.config(0)
+    g = gpu_system(wl, par, prec="f64")
+    g.body_forces()
+    g.step(2)
+    tag_before = g.tag.cpu().numpy().copy()
+    g.step(1)
+    cs, perm, _ = g.bins()
+    sol = perm[perm < g.N]
+    assert np.array_equal(g.tag.cpu().numpy(), tag_before[sol])
+    for c in range(g.C):  # solvent first within each cell
+        seg = perm[cs[c]:cs[c + 1]]
+        kinds = seg >= g.N
+        assert np.all(kinds[:-1] <= kinds[1:])
+    # repeating the last collide + stream pass from its inputs gives the same bits
+    before = g.download()[0]
+    g.recollide_last()
+    assert_same(oracle_like(before), g.download()[0], ("x", "v"), "recollide")
+
+
+class oracle_like:
+    def __init__(self, d):
+        self.__dict__.update(d)
+
+
 def test_storage_reorder_keeps_results_bit_exact():
     """Reordering the solvent storage (with identity tags) changes nothing."""
     wl, par, _ = W.config(0)
     say("reorder every 3 steps")
-    o, g = run_parity(wl, par, 30, reorder_every=3)
+    o, g = run_parity(wl, par, 30, reorder_every=3, out_of_place=False)
     tag = g.tag.cpu().numpy()
     assert not np.array_equal(tag, np.arange(len(tag)))  # storage really was permuted
     assert np.array_equal(np.sort(tag), np.arange(len(tag)))
@@ -231,28 +266,33 @@ def test_batched_replicas_match_each_replica_alone():
     assert_same(os_[2], g2.download()[0], where="replica 2 alone")
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("out_of_place", [True, False])
+def test_graph_replay_matches_eager(out_of_place):
     wl, par, _ = W.config(0)
-    say("graph")
-    ge = gpu_system(wl, par, prec="f64")
-    gg = gpu_system(wl, par, prec="f64")
+    say("graph out_of_place=%s" % out_of_place)
+    ge = gpu_system(wl, par, prec="f64", out_of_place=out_of_place)
+    gg = gpu_system(wl, par, prec="f64", out_of_place=out_of_place)
     for g in (ge, gg):
         g.body_forces()
+    nsteps, every = (6, 0) if out_of_place else (5, 2)
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
-        gg.graph(5, reorder_every=2)
+        gg.graph(nsteps, reorder_every=every)
         for rep in range(4):
             gg.graph_launch()
             torch.cuda.synchronize()
-            for i in range(5):
+            for i in range(nsteps):
                 ge.step(1)
-                if (i + 1) % 2 == 0:
+                if every and (i + 1) % every == 0:
                     ge.reorder()
             torch.cuda.synchronize()
             a, b = ge.download()[0], gg.download()[0]
             for k in STATE_KEYS:
                 assert np.array_equal(a[k], b[k]), (rep, k)
+            # storage order within a cell follows atomic arrival order, so only
+            # the state in identity order is unique; the tags stay a permutation
+            assert np.array_equal(np.sort(gg.tag.cpu().numpy()), np.arange(gg.N))
         gg.release_graph()
 
 
@@ -300,7 +340,11 @@ def fp32_one_step(wl, par, warm=3):
     g.advance()
     s1 = g.download()[0]
     nt = o.N + o.S
-    cell32 = cells_of(gcs, gperm, nt)
+    # perm holds storage indices; solvent storage k holds identity tag[k]
+    cell_st = cells_of(gcs, gperm, nt)
+    tag = g.tag.cpu().numpy().astype(np.int64)
+    cell32 = cell_st.copy()
+    cell32[tag] = cell_st[:o.N]
     bad_cells = np.unique(np.concatenate([cell64[cell32 != cell64], cell32[cell32 != cell64]]))
     bad = np.isin(cell64, bad_cells) | np.isin(cell32, bad_cells)
     v64 = np.concatenate([o.v, o.vs], axis=1)[:, ~bad]
