@@ -264,10 +264,14 @@ TileCfg tile_config(const mpcd_sys *s)
 
 struct Layout {
     size_t status, shift, counts, partial, cell_start, site_start, cellid, slot, perm, draws, site_d, vpre, rtmp,
-        total;
+        grid_count, grid_body, total;
+    uint32_t grid_mask;
 };
 
 constexpr int SCAN_T = 1024, SCAN_V = 4, SCAN_TILE = SCAN_T * SCAN_V;
+
+// Slots per bucket of the body-centre grid.
+constexpr int GRID_K = 8;
 
 // Binning and reorder chunks: BIN_T threads x BIN_ITEMS entries per block.
 constexpr int BIN_T = 256, BIN_ITEMS = 4, BIN_CHUNK = BIN_T * BIN_ITEMS;
@@ -299,6 +303,13 @@ Layout layout_of(const mpcd_sys *s)
     // reorder staging: positions and velocities (prec) and tags of the solvent
     const size_t es = s->prec == MPCD_F64 ? sizeof(double) : sizeof(float);
     L.rtmp = take(6 * es * (size_t)s->n_solvent + sizeof(int32_t) * (size_t)s->n_solvent);
+    // hashed grid of body centres for the WCA neighbour search: a power of two
+    // >= 4 B buckets of GRID_K slots
+    uint64_t G = 64;
+    while (G < 4 * (uint64_t)s->n_bodies) G <<= 1;
+    L.grid_mask = (uint32_t)(G - 1);
+    L.grid_count = take(sizeof(int32_t) * (size_t)G);
+    L.grid_body = take(sizeof(int32_t) * (size_t)G * GRID_K);
     L.total = off;
     return L;
 }
@@ -1500,7 +1511,7 @@ template <typename Real>
 __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT, int thermalize, uint64_t seed,
                                                  const uint64_t *d_step, const Real *x, Real *xs, Real *vs,
                                                  double *site_d, double *vpre, unsigned long long *counts,
-                                                 int32_t *cellid,
+                                                 int32_t *grid_count, int64_t grid_n, int32_t *cellid,
                                                  int32_t *slot, double *shift_out, uint32_t *status)
 {
     __shared__ double bsh[6];
@@ -1509,6 +1520,10 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
     const uint64_t step = *d_step;
     uint32_t st = 0;
     if (blockIdx.x == 0) draw_shifts(s, seed, step, shift_out);
+    // clear the body-centre grid for this step's insertions (after the drift)
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; grid_count && q < grid_n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        grid_count[q] = 0;
     if ((int64_t)blockIdx.x < s.B) {
         const int64_t b = blockIdx.x;
         if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0))
@@ -1597,6 +1612,65 @@ __device__ __forceinline__ void nosquish(int k, double delta, double Ik, double 
 }
 
 // Impulse (J, K), half kick with the stored F, T, drift, NO_SQUISH rotation.
+// ---- hashed grid of body centres (WCA neighbour search) -------------------
+//
+// Per system, ng = floor(0.999 L / rc) cells per axis (at least 1), so a cell
+// is wider than the cutoff rc and every partner within rc of a body lies in one
+// of the 27 cells around it (cells repeat when ng < 3).  Cells hash into a
+// power-of-two table of GRID_K-slot buckets.  A bucket can also hold bodies of
+// other cells or systems; the lookup filters by system and distance and visits
+// each bucket once, so it finds exactly the partners of the all-pairs loop.
+
+struct BodyGrid {
+    int32_t *count;  // nullptr: no grid
+    int32_t *body;
+    uint32_t mask;
+    double rc;
+};
+
+__device__ __forceinline__ void grid_geometry(const SysDev &s, int r, double rc, int ng[3], double cw[3])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double L = (double)s.ncell[3 * r + k] * s.a;
+        int n = (int)floor((0.999 * L) / rc);
+        n = n < 1 ? 1 : n;
+        ng[k] = n;
+        cw[k] = L / (double)n;
+    }
+}
+
+__device__ __forceinline__ int grid_axis(double x, double w, int n)
+{
+    int c = (int)floor(x / w);
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+__device__ __forceinline__ uint32_t grid_hash(int r, int cx, int cy, int cz, uint32_t mask)
+{
+    return (((uint32_t)r * 73856093u) ^ ((uint32_t)cx * 19349663u) ^ ((uint32_t)cy * 83492791u) ^
+            ((uint32_t)cz * 2654435761u)) & mask;
+}
+
+__device__ void grid_insert(const SysDev &s, const BodyDev &bd, const BodyGrid &g, int64_t b)
+{
+    const int r = find_sys(s.body_off, s.nsys, b);
+    int ng[3];
+    double cw[3];
+    grid_geometry(s, r, g.rc, ng, cw);
+    const int64_t B = s.B;
+    const uint32_t h = grid_hash(r, grid_axis(bd.pos[b], cw[0], ng[0]), grid_axis(bd.pos[B + b], cw[1], ng[1]),
+                                 grid_axis(bd.pos[2 * B + b], cw[2], ng[2]), g.mask);
+    const int slot = atomicAdd(&g.count[h], 1);
+    if (slot < GRID_K) g.body[(size_t)h * GRID_K + slot] = (int32_t)b;
+}
+
+__global__ void k_grid_insert(SysDev s, BodyDev bd, BodyGrid g)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < s.B) grid_insert(s, bd, g, b);
+}
+
 __device__ void body_first_update(const SysDev &s, const BodyDev &bd, int64_t b, const double *Jb,
                                   const double *Kb, double dt, uint32_t &st)
 {
@@ -1670,7 +1744,7 @@ __global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double
 template <typename Real>
 __global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd, const Real *vs, const double *site_d,
                                                            const double *vpre, double *J, double *K, double dt,
-                                                           uint32_t *status)
+                                                           BodyGrid grid, uint32_t *status)
 {
     __shared__ double sh[6 * SH_PAD];
     __shared__ double jk[6];
@@ -1685,24 +1759,34 @@ __global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd,
 #pragma unroll
         for (int k = 0; k < 3; ++k) { J[k * s.B + b] = jk[k]; K[k * s.B + b] = jk[3 + k]; }
         body_first_update(s, bd, b, jk, jk + 3, dt, st);
+        if (grid.count) grid_insert(s, bd, grid, b);
         flag(status, st);
     }
 }
 
-// Core-shifted WCA between body centres, Eq. (1).  One wave per body: lanes
-// evaluate partners in parallel; lanes 0..2 add the x, y, z components of the
-// interacting partners in ascending partner index (the order of a sequential
-// host loop).  With kick != 0 the second half kick follows in the same lane
+// Core-shifted WCA between body centres, Eq. (1).  One wave per body.  With
+// the body-centre grid, lanes evaluate the bodies of the 27 surrounding
+// buckets and lane 0 adds the interacting partners' contributions in ascending
+// partner index; without it (or when a bucket overflowed) lanes sweep all
+// bodies of the system and lanes 0..2 add the x, y, z components in ascending
+// partner index.  Either way the sums follow a sequential host loop over
+// partners.  With kick != 0 the second half kick follows in the same lane
 // (it needs only this body's new force); with advance_step != NULL block 0
 // then advances the step counter (last kernel of a step).
 constexpr int FRC_T = 64;
 
-__global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, double dt, int kick,
-                                                       uint64_t *advance_step, uint32_t *status)
+__global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid, double dt,
+                                                       int kick, uint64_t *advance_step, uint32_t *status)
 {
+    constexpr int NCAND = 27 * GRID_K;
     __shared__ double sf[3][FRC_T + 1];
     __shared__ int shit[FRC_T];
     __shared__ double fsh[3];
+    __shared__ uint32_t s_h[27];
+    __shared__ int s_n[27], s_pre[28];
+    __shared__ int s_ovf, s_nhit;
+    __shared__ int hj[NCAND];
+    __shared__ double hc[3][NCAND];
     const int64_t i = blockIdx.x;
     if (advance_step && i == 0 && threadIdx.x == 0) *advance_step = *advance_step + 1;
     if (i >= s.B) return;
@@ -1721,7 +1805,110 @@ __global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpc
             Ri[k] = bd.pos[k * B + i];
         }
         const int64_t jb = s.body_off[r], je = s.body_off[r + 1];
-        for (int64_t j0 = jb; j0 < je; j0 += FRC_T) {
+        // grid path: the 27 buckets around this body, each once
+        bool use_grid = grid.count != nullptr;
+        if (use_grid) {
+            int ng[3];
+            double cw[3];
+            grid_geometry(s, r, grid.rc, ng, cw);
+            if (t == 0) {
+                s_ovf = 0;
+                s_nhit = 0;
+            }
+            if (t < 27) {
+                const int d[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+                int nc[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    int c = grid_axis(Ri[k], cw[k], ng[k]) + d[k];
+                    c = c < 0 ? c + ng[k] : (c >= ng[k] ? c - ng[k] : c);
+                    nc[k] = c;
+                }
+                s_h[t] = grid_hash(r, nc[0], nc[1], nc[2], grid.mask);
+            }
+            __syncthreads();
+            if (t < 27) {
+                const uint32_t h = s_h[t];
+                bool dup = false;
+                for (int u = 0; u < t; ++u) dup = dup || (s_h[u] == h);
+                const int n = dup ? 0 : grid.count[h];
+                if (n > GRID_K) s_ovf = 1;
+                s_n[t] = n;
+            }
+            __syncthreads();
+            if (t == 0) {
+                int acc_n = 0;
+                for (int u = 0; u < 27; ++u) {
+                    s_pre[u] = acc_n;
+                    acc_n += s_n[u] < GRID_K ? s_n[u] : GRID_K;
+                }
+                s_pre[27] = acc_n;
+            }
+            __syncthreads();
+            use_grid = s_ovf == 0;  // a full bucket: fall back to all pairs
+        }
+        if (use_grid) {
+            const int total = s_pre[27];
+            for (int idx = t; idx < total; idx += FRC_T) {
+                int u = 0;
+                while (u < 26 && s_pre[u + 1] <= idx) ++u;
+                const int64_t j = grid.body[(size_t)s_h[u] * GRID_K + (idx - s_pre[u])];
+                if (j == i || j < jb || j >= je) continue;
+                double dr[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    double d = Ri[k] - bd.pos[k * B + j];
+                    if (d > 0.5 * Lb[k]) d = d - Lb[k];
+                    else if (d < -0.5 * Lb[k]) d = d + Lb[k];
+                    dr[k] = d;
+                }
+                const double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
+                if (!(r2 <= rc2)) continue;
+                const double rr = sqrt(r2);
+                const double sh = rr - wca.delta;
+                if (!(sh > 0.0)) {
+                    st |= ST_NONFINITE;
+                    continue;
+                }
+                const double is = wca.sigma / sh;
+                const double is2 = is * is;
+                const double is6 = (is2 * is2) * is2;
+                const double is12 = is6 * is6;
+                const double fr = ((24.0 * wca.eps) * (2.0 * is12 - is6)) / sh;
+                const double fo = fr / rr;
+                const int pos = atomicAdd(&s_nhit, 1);
+                hj[pos] = (int)j;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) hc[k][pos] = fo * dr[k];
+            }
+            __syncthreads();
+            if (t == 0) {
+                // partners in ascending index, then the sequential sums
+                const int nh = s_nhit;
+                for (int a = 1; a < nh; ++a) {
+                    const int jk = hj[a];
+                    const double c0 = hc[0][a], c1 = hc[1][a], c2 = hc[2][a];
+                    int q = a;
+                    while (q > 0 && hj[q - 1] > jk) {
+                        hj[q] = hj[q - 1];
+                        hc[0][q] = hc[0][q - 1]; hc[1][q] = hc[1][q - 1]; hc[2][q] = hc[2][q - 1];
+                        --q;
+                    }
+                    hj[q] = jk;
+                    hc[0][q] = c0; hc[1][q] = c1; hc[2][q] = c2;
+                }
+                double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+                for (int a = 0; a < nh; ++a) {
+                    f0 = f0 + hc[0][a];
+                    f1 = f1 + hc[1][a];
+                    f2 = f2 + hc[2][a];
+                }
+                sf[0][0] = f0; sf[1][0] = f1; sf[2][0] = f2;
+            }
+            __syncthreads();
+            if (t < 3) f = sf[t][0];
+        }
+        for (int64_t j0 = jb; !use_grid && j0 < je; j0 += FRC_T) {
             const int64_t j = j0 + t;
             int hit = 0;
             double c[3] = {0.0, 0.0, 0.0};
@@ -2067,9 +2254,35 @@ static void launch_thermalize(const Ctx &c, hipStream_t st, const mpcd_bodies *b
 }
 
 // Thermalization + site binning + solvent binning in one launch.
-static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, double kT, int thermalize,
-                        uint64_t seed, const uint64_t *d_step, const void *x, void *xs, void *vs)
+static BodyGrid body_grid(const Ctx &c, const mpcd_wca &wca)
 {
+    BodyGrid g;
+    const bool on = wca.mode == 1 && c.sys->n_bodies > 0;
+    g.count = on ? at<int32_t>(c.ws, c.L.grid_count) : nullptr;
+    g.body = on ? at<int32_t>(c.ws, c.L.grid_body) : nullptr;
+    g.mask = c.L.grid_mask;
+    g.rc = wca.delta + 0x1.1f59ac3c7d6c0p+0 * wca.sigma;
+    return g;
+}
+
+// Standalone entry points: rebuild the body-centre grid from the current
+// positions (the fused step clears it in k_prep and fills it after the drift).
+static void launch_body_grid(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca)
+{
+    const BodyGrid g = body_grid(c, wca);
+    if (!g.count) return;
+    const int64_t G = (int64_t)c.L.grid_mask + 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(G, 256)), dim3(256), 0, st, g.count, G, 0);
+    hipLaunchKernelGGL(k_grid_insert, dim3(grid_for(c.sys->n_bodies, 64)), dim3(64), 0, st, c.sd,
+                       make_bodydev(bodies), g);
+}
+
+static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, double kT, int thermalize,
+                        uint64_t seed, const uint64_t *d_step, const void *x, void *xs, void *vs,
+                        const mpcd_wca &wca)
+{
+    const BodyGrid grid = body_grid(c, wca);
+    const int64_t grid_n = grid.count ? (int64_t)c.L.grid_mask + 1 : 0;
     const int64_t N = c.sys->n_solvent;
     const int64_t nb = (c.sys->n_sites > 0) ? c.sys->n_bodies : 0;
     const int64_t nchunks = (N + BIN_CHUNK - 1) / BIN_CHUNK;
@@ -2084,12 +2297,12 @@ static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies,
     double *shift = at<double>(c.ws, c.L.shift);
     if (c.sys->prec == MPCD_F64)
         hipLaunchKernelGGL(k_prep<double>, g, dim3(BODY_T), 0, st, sd, bd, kT, thermalize, seed, d_step,
-                           (const double *)x, (double *)xs, (double *)vs, site_d, vpre, counts, cellid, slot, shift,
-                           c.status);
+                           (const double *)x, (double *)xs, (double *)vs, site_d, vpre, counts, grid.count, grid_n,
+                           cellid, slot, shift, c.status);
     else
         hipLaunchKernelGGL(k_prep<float>, g, dim3(BODY_T), 0, st, sd, bd, kT, thermalize, seed, d_step,
-                           (const float *)x, (float *)xs, (float *)vs, site_d, vpre, counts, cellid, slot, shift,
-                           c.status);
+                           (const float *)x, (float *)xs, (float *)vs, site_d, vpre, counts, grid.count, grid_n,
+                           cellid, slot, shift, c.status);
 }
 
 // Scatter fused with the per-cell draws in one launch.
@@ -2104,17 +2317,18 @@ static void launch_scatter_draws(const Ctx &c, hipStream_t st, const CollideArgs
 }
 
 static void launch_transfer_first(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const void *vs, double *J,
-                                  double *K, double dt)
+                                  double *K, double dt, const mpcd_wca &wca)
 {
+    const BodyGrid grid = body_grid(c, wca);
     if (c.sys->n_bodies == 0) return;
     const BodyDev bd = make_bodydev(bodies);
     const dim3 gb((unsigned)c.sys->n_bodies);
     if (c.sys->prec == MPCD_F64)
         hipLaunchKernelGGL(k_transfer_first<double>, gb, dim3(BODY_T), 0, st, c.sd, bd, (const double *)vs,
-                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, c.status);
+                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, c.status);
     else
         hipLaunchKernelGGL(k_transfer_first<float>, gb, dim3(BODY_T), 0, st, c.sd, bd, (const float *)vs,
-                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, c.status);
+                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, c.status);
 }
 
 static void launch_forces(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca, double dt,
@@ -2122,7 +2336,7 @@ static void launch_forces(const Ctx &c, hipStream_t st, const mpcd_bodies *bodie
 {
     if (c.sys->n_bodies == 0) return;
     hipLaunchKernelGGL(k_body_forces, dim3((unsigned)c.sys->n_bodies), dim3(FRC_T), 0, st, c.sd,
-                       make_bodydev(bodies), wca, dt, kick, advance, c.status);
+                       make_bodydev(bodies), wca, body_grid(c, wca), dt, kick, advance, c.status);
 }
 
 static void launch_reorder(const Ctx &c, hipStream_t st, void *x, void *v, int32_t *tag)
@@ -2314,7 +2528,9 @@ int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, co
     TRY(check_ws(sys, ws, ws_bytes));
     TRY(check_bodies(sys, bodies));
     TRY(wca_check(wca));
-    launch_forces(make_ctx(sys, ws), (hipStream_t)stream, bodies, *wca, 0.0, 0, nullptr);
+    const Ctx c = make_ctx(sys, ws);
+    launch_body_grid(c, (hipStream_t)stream, bodies, *wca);
+    launch_forces(c, (hipStream_t)stream, bodies, *wca, 0.0, 0, nullptr);
     return launch_check();
 }
 
@@ -2332,6 +2548,7 @@ int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies,
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_body_first, dim3(grid_for(sys->n_bodies, 64)), dim3(64), 0, st, c.sd, make_bodydev(bodies),
                        J, K, dt, c.status);
+    launch_body_grid(c, st, bodies, *wca);
     launch_forces(c, st, bodies, *wca, dt, 1, nullptr);
     return launch_check();
 }
@@ -2372,7 +2589,7 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
     const mpcd_params &p = a->par;
     const Ctx c = make_ctx(s, a->ws);
     hipStream_t st = (hipStream_t)stream;
-    launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs);
+    launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca);
     launch_scan(c, st);
     const CollideArgs A = collide_args(c, a->tag, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed, a->d_step, p.dt,
                                        nullptr);
@@ -2386,7 +2603,7 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a->d_step);
         return launch_check();
     }
-    launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt);
+    launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt, p.wca);
     launch_forces(c, st, &a->bodies, p.wca, p.dt, 1, a->d_step);
     return launch_check();
 }

@@ -296,6 +296,38 @@ def test_graph_replay_matches_eager(out_of_place):
         gg.release_graph()
 
 
+def point_bodies(ncell, centres, seed):
+    """Bodies of one unit-mass site each at the given centres (no solvent)."""
+    rng = np.random.default_rng(seed)
+    tpl = W.rigid_template(np.zeros((1, 3)), 1.0)
+    q = np.tile([1.0, 0.0, 0.0, 0.0], (len(centres), 1))
+    return W.make_system(ncell, 0, [tpl] * len(centres), centres, q, rng)
+
+
+@pytest.mark.parametrize("case", ["many", "crowded"])
+def test_wca_forces_neighbour_grid_bit_exact(case):
+    """Body-centre WCA forces through the hashed neighbour grid equal the
+    oracle's all-pairs loop: 2000 random point bodies (many partners per
+    body), and 30 bodies crowded into one grid cell (a bucket overflows and
+    the kernel falls back to all pairs)."""
+    rng = np.random.default_rng(12)
+    if case == "many":
+        ncell, centres = (20, 20, 20), rng.random((2000, 3)) * 20.0
+    else:
+        ncell = (3, 3, 3)
+        centres = np.concatenate([0.2 + 1.1 * rng.random((30, 3)), 1.6 + 1.3 * rng.random((10, 3))])
+    wl = point_bodies(ncell, centres, 13)
+    par = W.srd_params(13, wca=W.wca_spheres(sigma=1.0))
+    o = oracle.OracleSystem(wl, par)
+    g = gpu_system(wl, par, prec="f64")
+    o.body_forces()
+    g.body_forces()
+    say("wca grid %s: %d bodies" % (case, g.B))
+    assert_same(o, g.download()[0], ("F", "T"), "forces")
+    assert np.count_nonzero(o.F) > 0
+    assert g.status() == 0
+
+
 def test_full_size_suspension_bit_exact_few_steps():
     """60^3 cells, 1.08M solvent, 191 spheres x 200 sites, WCA: the benchmark
     workload, checked bit for bit over 3 steps."""
