@@ -170,56 +170,67 @@ __device__ inline uint32_t site_normals(uint64_t seed, uint64_t step, uint64_t s
 }
 
 // Uniform random unit vector: accept (x1,x2) inside the unit disk,
-// n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1-2t).
-__device__ inline uint32_t cell_axis(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
-                                     double n[3])
+// n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1-2t).  One call's words: pairs
+// (w0, w1) then (w2, w3).
+__device__ __forceinline__ bool axis_from_words(const Words &w, double n[3])
 {
-    for (int call = 0; call < RNG_MAX_CALLS; ++call) {
-        const Words w = rng_draw(seed, RNG_AXIS, step, cell, replica, (uint64_t)call);
 #pragma unroll
-        for (int pair = 0; pair < 2; ++pair) {
-            const double x1 = 2.0 * unit53(w.w[2 * pair]) - 1.0;
-            const double x2 = 2.0 * unit53(w.w[2 * pair + 1]) - 1.0;
-            const double t = x1 * x1 + x2 * x2;
-            if (t > 0.0 && t < 1.0) {
-                const double r = sqrt(1.0 - t);
-                n[0] = (2.0 * x1) * r;
-                n[1] = (2.0 * x2) * r;
-                n[2] = 1.0 - 2.0 * t;
-                return 0;
-            }
+    for (int pair = 0; pair < 2; ++pair) {
+        const double x1 = 2.0 * unit53(w.w[2 * pair]) - 1.0;
+        const double x2 = 2.0 * unit53(w.w[2 * pair + 1]) - 1.0;
+        const double t = x1 * x1 + x2 * x2;
+        if (t > 0.0 && t < 1.0) {
+            const double r = sqrt(1.0 - t);
+            n[0] = (2.0 * x1) * r;
+            n[1] = (2.0 * x2) * r;
+            n[2] = 1.0 - 2.0 * t;
+            return true;
         }
+    }
+    return false;
+}
+
+__device__ inline uint32_t cell_axis(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
+                                     double n[3], int call0 = 0)
+{
+    for (int call = call0; call < RNG_MAX_CALLS; ++call) {
+        const Words w = rng_draw(seed, RNG_AXIS, step, cell, replica, (uint64_t)call);
+        if (axis_from_words(w, n)) return 0;
     }
     n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
     return ST_RNGLOOP;
 }
 
+// One Marsaglia-Tsang iteration (d = k - 1/3, c = 1/sqrt(9d)) on one call's
+// words: a polar normal from (w0, w1), the uniform w2.
+__device__ __forceinline__ bool gamma_from_words(const Words &w, double d, double c, double *g)
+{
+    const double x1 = 2.0 * unit53(w.w[0]) - 1.0;
+    const double x2 = 2.0 * unit53(w.w[1]) - 1.0;
+    const double t = x1 * x1 + x2 * x2;
+    if (!(t > 0.0 && t < 1.0)) return false;
+    const double z = x1 * sqrt((-2.0 * det_log(t)) / t);
+    double v = 1.0 + c * z;
+    if (v <= 0.0) return false;
+    v = (v * v) * v;
+    const double u = unit53(w.w[2]);
+    const double z2 = z * z;
+    if (u < 1.0 - 0.0331 * (z2 * z2) || det_log(u) < (0.5 * z) * z + d * ((1.0 - v) + det_log(v))) {
+        *g = d * v;
+        return true;
+    }
+    return false;
+}
+
 // Gamma(shape k >= 1) variate by Marsaglia-Tsang; iteration i uses call i.
 __device__ inline uint32_t gamma_variate(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
-                                         double k, double *g)
+                                         double k, double *g, int call0 = 0)
 {
     const double d = k - 1.0 / 3.0;
     const double c = 1.0 / sqrt(9.0 * d);
-    for (int call = 0; call < RNG_MAX_CALLS; ++call) {
+    for (int call = call0; call < RNG_MAX_CALLS; ++call) {
         const Words w = rng_draw(seed, RNG_THERMO, step, cell, replica, (uint64_t)call);
-        const double x1 = 2.0 * unit53(w.w[0]) - 1.0;
-        const double x2 = 2.0 * unit53(w.w[1]) - 1.0;
-        const double t = x1 * x1 + x2 * x2;
-        if (!(t > 0.0 && t < 1.0)) continue;
-        const double z = x1 * sqrt((-2.0 * det_log(t)) / t);
-        double v = 1.0 + c * z;
-        if (v <= 0.0) continue;
-        v = (v * v) * v;
-        const double u = unit53(w.w[2]);
-        const double z2 = z * z;
-        if (u < 1.0 - 0.0331 * (z2 * z2)) {
-            *g = d * v;
-            return 0;
-        }
-        if (det_log(u) < (0.5 * z) * z + d * ((1.0 - v) + det_log(v))) {
-            *g = d * v;
-            return 0;
-        }
+        if (gamma_from_words(w, d, c, g)) return 0;
     }
     *g = d;
     return ST_RNGLOOP;

@@ -1104,7 +1104,7 @@ __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
     L.idx = o; o += align16(sizeof(int) * (size_t)cap);
     L.cl = o; o += align16(sizeof(uint16_t) * (size_t)cap);
     L.v = o; o += align16((f64 ? 8 : 4) * 3 * (size_t)cap);
-    L.keyacc = o; o += align16(f64 ? sizeof(uint64_t) * (size_t)cap : 0);
+    L.keyacc = o; o += align16(f64 ? sizeof(uint64_t) * (size_t)cap : sizeof(long long) * 5 * (size_t)cpb);
     L.par = o; o += align16(f64 ? sizeof(double) * 13 * (size_t)cpb : sizeof(float) * 12 * (size_t)cpb);
     L.r = o; o += align16(sizeof(int) * (size_t)cpb);
     L.ss = o; o += align16(sizeof(int) * (size_t)cpb);
@@ -1148,11 +1148,19 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
     const int64_t N = s.N, S = s.S;
     const bool out = O.v != nullptr;
 
-    // phase 0: the tile's cell ranges; this lane's cell system and draws
+    // phase 0: the tile's cell ranges and slot -> cell map; this lane's cell
+    // system and draws; FP32: clear the cell's fixed-point accumulators
+    unsigned long long *s_acc = (unsigned long long *)(smem + Lo.keyacc);
     for (int c = t; c <= nc; c += TILE_T) s_cs[c] = A.cell_start[c0 + c] - m0;
     double nax[3] = {0.0, 0.0, 1.0}, gvar = 0.0;
     if (t < nc) {
         const int64_t gc = c0 + t;
+        const int cb0 = A.cell_start[gc] - m0, ce0 = A.cell_start[gc + 1] - m0;
+        for (int i = cb0; i < ce0; ++i) s_cl[i] = (uint16_t)t;
+        if constexpr (!F64) {
+#pragma unroll
+            for (int z = 0; z < 5; ++z) s_acc[5 * t + z] = 0ull;
+        }
         s_r[t] = find_sys(s.cell_off, s.nsys, gc);
         if (out) s_ss[t] = A.site_start[gc];
         read_axis(A, gc, nax);
@@ -1186,7 +1194,6 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
         }
     }
     const int cb = (t < nc) ? s_cs[t] : 0, ce = (t < nc) ? s_cs[t + 1] : 0;
-    for (int i = cb; i < ce; ++i) s_cl[i] = (uint16_t)t;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int i = t + j * TILE_T;
@@ -1194,7 +1201,18 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
             const int32_t k = kk[j];
             s_idx[i] = k;
             s_v[i] = va[j][0]; s_v[cap + i] = va[j][1]; s_v[2 * cap + i] = va[j][2];
-            if constexpr (F64) s_key[i] = ((uint64_t)ident(A, k) << 32) | (uint32_t)i;
+            if constexpr (F64) {
+                s_key[i] = ((uint64_t)ident(A, k) << 32) | (uint32_t)i;
+            } else {
+                // exact int64 fixed-point terms, summed per cell with LDS
+                // atomics (integer sums: the order does not matter)
+                long long w[5];
+                fixed_terms(k < N ? s.m : A.site_m[k - N], (float)va[j][0], (float)va[j][1], (float)va[j][2], w,
+                            st);
+                unsigned long long *acc = s_acc + 5 * (int)s_cl[i];
+#pragma unroll
+                for (int z = 0; z < 5; ++z) atomicAdd(acc + z, (unsigned long long)w[z]);
+            }
         }
     }
     __syncthreads();
@@ -1246,16 +1264,9 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
 #pragma unroll
                     for (int j = 0; j < 3; ++j) par[4 + 3 * i + j] = R.R[i][j];
             } else {
-                // exact int64 fixed-point sums over the cell's contiguous members
-                long long q[5] = {0, 0, 0, 0, 0};
-                for (int i = b; i < e; ++i) {
-                    const int32_t k = s_idx[i];
-                    long long w[5];
-                    fixed_terms(k < N ? s.m : A.site_m[k - N], (float)s_v[i], (float)s_v[cap + i],
-                                (float)s_v[2 * cap + i], w, st);
+                long long q[5];
 #pragma unroll
-                    for (int z = 0; z < 5; ++z) q[z] += w[z];
-                }
+                for (int z = 0; z < 5; ++z) q[z] = (long long)s_acc[5 * t + z];
                 float *par = (float *)(smem + Lo.par) + 12 * t;
                 const double Md = (double)q[0];
                 const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
