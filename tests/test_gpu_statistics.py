@@ -1,0 +1,165 @@
+"""FP32 against FP64 on ensemble observables (GPU).
+
+The FP32 form (FP32 solvent and sites, exact int64 fixed-point cell sums, FP64
+bodies) must reproduce the plain FP64 form's physics: solvent temperature, the
+shear viscosity (shear-wave decay, Sec. II.A; eta_0 = 3.96 at 5 particles per
+cell), the translational and rotational temperature of rigid colloids
+(equipartition, Sec. III.A) and their diffusivity (mean squared displacement,
+Eq. (14)).  Both forms start from the same seeded state and draw the same
+random numbers; rounding makes the trajectories decorrelate, so each pair of
+estimates is compared within its combined statistical error (replica spread or
+block averages), and each estimate against its closed form where there is one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2604_14307_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def gpu_system(*a, **k):
+    from paper_2604_14307_amd.sim import GPUSystem
+    return GPUSystem(*a, **k)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def block_error(x, nblocks=20):
+    means = [b.mean() for b in np.array_split(np.asarray(x), nblocks)]
+    return float(np.std(means, ddof=1) / math.sqrt(nblocks))
+
+
+def lhat_bodyframe(q, p):
+    """Body-frame angular momentum 1/2 p . P_k q of the quaternion momentum."""
+    P1 = np.stack([-q[1], q[0], q[3], -q[2]])
+    P2 = np.stack([-q[2], -q[3], q[0], q[1]])
+    P3 = np.stack([-q[3], q[2], -q[1], q[0]])
+    return 0.5 * np.stack([(p * P1).sum(0), (p * P2).sum(0), (p * P3).sum(0)])
+
+
+# ---------------------------------------------------------------------------
+
+def shear_wave_run(prec, nrep=16, nz=30, nxy=12, nsteps=450, A=0.5):
+    k = 2.0 * math.pi / nz
+    systems = []
+    for r in range(nrep):
+        rng = np.random.default_rng(500 + r)
+        wl = W.make_system((nxy, nxy, nz), 5, [], [], np.zeros((0, 4)), rng)
+        wl["v"][0] += A * np.sin(k * wl["x"][2])
+        systems.append(wl)
+    g = gpu_system(systems, W.srd_params(77, kT_cell=1.0), prec=prec)
+    seg = torch.tensor(np.repeat(np.arange(nrep), np.diff(g.solv_off_h)), device=g.device)
+    amps = np.empty((nsteps, nrep))
+    for s in range(nsteps):
+        z = g.x[2].double()
+        vx = g.v[0].double()
+        w = vx * torch.sin(k * z)
+        acc = torch.zeros(nrep, dtype=torch.float64, device=g.device).index_add_(0, seg, w)
+        amps[s] = (2.0 / np.diff(g.solv_off_h)) * acc.cpu().numpy()
+        g.step(1)
+    assert g.status() == 0
+    return amps, k
+
+
+def fit_nu(amps, k):
+    """Kinematic viscosity from the decay of the replica-mean amplitude, with a
+    jackknife error over replicas."""
+    t = 0.1 * np.arange(amps.shape[0])
+
+    def nu_of(a):
+        m = a.mean(1)
+        sel = m > 0.12
+        return -np.polyfit(t[sel], np.log(m[sel]), 1)[0] / k ** 2
+
+    nu = nu_of(amps)
+    n = amps.shape[1]
+    jk = np.array([nu_of(np.delete(amps, r, axis=1)) for r in range(n)])
+    err = math.sqrt((n - 1) / n * np.sum((jk - jk.mean()) ** 2))
+    return nu, err
+
+
+def test_fp32_viscosity_agrees_with_fp64_and_paper():
+    a64, k = shear_wave_run("f64")
+    a32, _ = shear_wave_run("f32")
+    nu64, e64 = fit_nu(a64, k)
+    nu32, e32 = fit_nu(a32, k)
+    say("eta FP64 %.4f +- %.4f, FP32 %.4f +- %.4f" % (5 * nu64, 5 * e64, 5 * nu32, 5 * e32))
+    assert abs(nu32 - nu64) < 4.0 * math.hypot(e32, e64) + 1e-3
+    for nu, e in ((nu64, e64), (nu32, e32)):
+        # eta_0 = 3.96 (closed form; it neglects correlations at the ~3% level)
+        assert abs(5.0 * nu - 3.96) < 4.0 * 5.0 * e + 0.15
+
+
+# ---------------------------------------------------------------------------
+
+def colloid_run(prec, nrep=192, edge=12, nsteps=3000, warm=200, every=10):
+    systems = []
+    tpl = W.sphere_template(2.0, 100, 5.0)
+    for r in range(nrep):
+        rng = np.random.default_rng([31, r])
+        c = 0.5 * edge
+        systems.append(W.make_system((edge, edge, edge), 5, [tpl], [(c, c, c)],
+                                     W.random_quaternions(rng, 1), rng))
+    g = gpu_system(systems, W.srd_params(31, kT_cell=1.0), prec=prec)
+    g.body_forces()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    L = float(edge)
+    pos, ET, ER, TS = [], [], [], []
+    M = g.mass.cpu().numpy()
+    I = g.inertia.cpu().numpy()
+    with torch.cuda.stream(side):
+        g.step(warm)
+        g.graph(every)
+        for s in range(nsteps // every):
+            g.graph_launch()
+            R = g.pos.cpu().numpy() + L * g.image.cpu().numpy()
+            P = g.mom.cpu().numpy()
+            Lh = lhat_bodyframe(g.quat.cpu().numpy(), g.angmom.cpu().numpy())
+            pos.append(R)
+            ET.append(0.5 * np.sum(P * P, 0) / M)
+            ER.append(0.5 * np.sum(Lh * Lh / I, 0))
+            v = g.v.double()
+            TS.append(float((v * v).sum() / (3 * g.N)))
+        g.release_graph()
+    assert g.status() == 0
+    return np.array(pos), np.array(ET), np.array(ER), np.array(TS), g
+
+
+def msd_slope(pos, dt_sample, lag0, lag1):
+    """Per-replica D from the slope of the time-origin-averaged MSD between lag0
+    and lag1 samples (Eq. (14): D = slope / 6)."""
+    n = pos.shape[0]
+    lags = np.arange(lag0, lag1 + 1, max(1, (lag1 - lag0) // 8))
+    msd = np.array([np.mean(np.sum((pos[l:] - pos[:n - l]) ** 2, axis=1), axis=0) for l in lags])
+    t = lags * dt_sample
+    return np.array([np.polyfit(t, msd[:, r], 1)[0] / 6.0 for r in range(pos.shape[2])])
+
+
+def test_fp32_colloid_temperature_and_diffusivity_agree_with_fp64():
+    res = {}
+    for prec in ("f64", "f32"):
+        pos, ET, ER, TS, g = colloid_run(prec)
+        Mtot = g.N / g.nsys * 1.0 + float(g.mass[0])
+        D = msd_slope(pos, 1.0, 30, 90)  # samples every 10 steps = 1 tau; lags 30..90 tau
+        res[prec] = dict(ET=ET.mean(), eET=block_error(ET.mean(1)), ER=ER.mean(), eER=block_error(ER.mean(1)),
+                         TS=TS.mean(), eTS=block_error(TS), D=D.mean(), eD=D.std(ddof=1) / math.sqrt(len(D)),
+                         eT=1.5 * (1.0 - float(g.mass[0]) / Mtot))
+        r = res[prec]
+        say("%s: E_T %.4f +- %.4f (expect %.4f), E_R %.4f +- %.4f, solvent kT %.5f +- %.5f, D %.5f +- %.5f"
+            % (prec, r["ET"], r["eET"], r["eT"], r["ER"], r["eER"], r["TS"], r["eTS"], r["D"], r["eD"]))
+    a, b = res["f64"], res["f32"]
+    for key in ("ET", "ER", "TS", "D"):
+        assert abs(a[key] - b[key]) < 4.0 * math.hypot(a["e" + key], b["e" + key]) + 1e-4, key
+    for r in (a, b):
+        assert abs(r["ET"] - r["eT"]) < 4.0 * r["eET"] + 0.02
+        assert abs(r["ER"] - 1.5) < 4.0 * r["eER"] + 0.02
+        assert abs(r["TS"] - 1.0) < 4.0 * r["eTS"] + 2e-3
+        assert r["D"] > 0.0
