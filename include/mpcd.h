@@ -70,6 +70,7 @@ enum {
 #define MPCD_FLAG_FIXOVF 4u    /* FP32 path: fixed-point cell sum overflow     */
 #define MPCD_FLAG_RNGLOOP 8u   /* a rejection sampler used all 64 Philox calls */
 #define MPCD_FLAG_BINERR 16u   /* inconsistent binning counts (particles dropped) */
+#define MPCD_FLAG_REACH 32u    /* WCA mode 2: a site lies beyond mpcd_wca.reach  */
 
 /* Geometry and sizes of nsys independent periodic boxes of cubic cells. */
 typedef struct {
@@ -105,10 +106,17 @@ typedef struct {
     const double *site_m;     /* [S] site masses                                */
 } mpcd_bodies;
 
-/* Colloid repulsion, Eq. (1): core-shifted WCA between body centres. */
+/* Colloid repulsion, Eq. (1): core-shifted WCA u(r; eps, sigma, delta), cut
+ * at delta + 2^(1/6) sigma.  Mode 1: between body centres (forces only).
+ * Mode 2: between surface sites of different bodies; the force on body b is
+ * the sum of its sites' forces and its torque the sum of d_j x f_j (f_j summed
+ * over the other bodies in ascending index and their sites in ascending
+ * index; F and T in site order).  `reach` (mode 2) bounds |d_j| over all
+ * sites; a site found farther from its body centre sets MPCD_FLAG_REACH. */
 typedef struct {
-    int32_t mode;        /* 0 off, 1 between body centres                      */
+    int32_t mode;        /* 0 off, 1 body centres, 2 sites of different bodies */
     double eps, sigma, delta;
+    double reach;        /* mode 2: max distance of a site from its body centre */
 } mpcd_wca;
 
 /* Scalars of one step. */

@@ -97,6 +97,10 @@ def lib():
         L.orc_sites_to_body.argtypes = [sysp, dp, dp]
         L.orc_body_forces.restype = C.c_uint32
         L.orc_body_forces.argtypes = [sysp, parp]
+        L.orc_site_wca_bodies.restype = C.c_uint32
+        L.orc_site_wca_bodies.argtypes = [sysp, parp, C.POINTER(i64), i64, dp, dp]
+        L.orc_wca_energy.restype = C.c_double
+        L.orc_wca_energy.argtypes = [sysp, parp]
         L.orc_body_integrate.restype = C.c_uint32
         L.orc_body_integrate.argtypes = [sysp, parp, dp, dp]
         L.orc_stream.restype = C.c_uint32
@@ -255,6 +259,19 @@ class OracleSystem:
 
     def body_forces(self):
         return lib().orc_body_forces(C.byref(self._sys), C.byref(self.par))
+
+    def site_wca_bodies(self, idx):
+        """Mode 2 force and torque ([3][n] each) of the listed bodies only."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        F = np.zeros((3, max(len(idx), 1)))
+        T = np.zeros((3, max(len(idx), 1)))
+        flags = lib().orc_site_wca_bodies(C.byref(self._sys), C.byref(self.par), _p(idx, C.c_int64), len(idx),
+                                          _p(F), _p(T))
+        return F[:, :len(idx)].copy(), T[:, :len(idx)].copy(), flags
+
+    def wca_energy(self):
+        """Total WCA potential energy of the current body poses, Eq. (1)."""
+        return lib().orc_wca_energy(C.byref(self._sys), C.byref(self.par))
 
     def body_integrate(self, J, K):
         J = np.ascontiguousarray(J, dtype=np.float64)

@@ -385,7 +385,7 @@ typedef struct {
     uint64_t seed;
     uint64_t replica;
     int32_t thermalize;  /* 1: Eq. (7); 0: naive scheme (rigid velocities only) */
-    int32_t wca_mode;    /* 0 off, 1 between body centres */
+    int32_t wca_mode;    /* 0 off, 1 between body centres, 2 between sites of different bodies */
     double eps, sigma, delta;
 } orc_par;
 
@@ -620,43 +620,194 @@ uint32_t orc_sites_to_body(const orc_sys *s, double *J, double *K)
 /* Colloid forces: core-shifted WCA between body centres, Eq. (1), minimum    */
 /* image, summed over partners in ascending index.  Central forces exert no   */
 /* torque.                                                                    */
+/* Core-shifted WCA of Eq. (1) at separation dr (|dr|^2 = r2 within the
+ * cutoff): adds the force on the first particle, -u'(r) dr / r, to f.
+ * Returns ORC_NONFINITE (and adds nothing) when r <= delta. */
+static uint32_t wca_pair(const orc_par *par, const double dr[3], double r2, double f[3])
+{
+    double r = sqrt(r2);
+    double sh = r - par->delta;
+    if (!(sh > 0.0)) return ORC_NONFINITE;
+    double is = par->sigma / sh;
+    double is2 = is * is;
+    double is6 = (is2 * is2) * is2;
+    double is12 = is6 * is6;
+    double fr = ((24.0 * par->eps) * (2.0 * is12 - is6)) / sh;
+    double fo = fr / r;
+    for (int k = 0; k < 3; ++k) f[k] = f[k] + fo * dr[k];
+    return 0;
+}
+
+/* Space-frame site offsets d_j = A(q_b) dhat_j and unwrapped site positions
+ * R_b + d_j of every site (arrays [3S]). */
+static void site_frames(const orc_sys *s, double *off, double *pos)
+{
+    int64_t B = s->B, S = s->S;
+    for (int64_t b = 0; b < B; ++b) {
+        double q[4], A[3][3];
+        for (int r = 0; r < 4; ++r) q[r] = s->q[r * B + b];
+        quat_to_mat(q, A);
+        for (int64_t j = s->site_off[b]; j < s->site_off[b + 1]; ++j) {
+            double dh[3] = {s->dhat[j], s->dhat[S + j], s->dhat[2 * S + j]}, d[3];
+            mat_vec(A, dh, d);
+            for (int k = 0; k < 3; ++k) {
+                off[k * S + j] = d[k];
+                pos[k * S + j] = s->R[k * B + b] + d[k];
+            }
+        }
+    }
+}
+
+/* Minimum image of a site-site separation: t - L rint(t / L). */
+static double min_image(double t, double L) { return t - L * rint(t / L); }
+
+/* Site-site WCA force and torque of body i (mode 2): for each of its sites j
+ * in order, f_j sums the pair forces of the sites of every other body (bodies
+ * in ascending index, their sites in ascending index); then F = sum_j f_j,
+ * T = sum_j d_j x f_j. */
+static uint32_t site_wca_body(const orc_sys *s, const orc_par *par, const double *off, const double *pos,
+                              int64_t i, double rc2, double F[3], double T[3])
+{
+    uint32_t flags = 0;
+    int64_t B = s->B, S = s->S;
+    for (int k = 0; k < 3; ++k) { F[k] = 0.0; T[k] = 0.0; }
+    for (int64_t j = s->site_off[i]; j < s->site_off[i + 1]; ++j) {
+        double f[3] = {0.0, 0.0, 0.0};
+        for (int64_t b = 0; b < B; ++b) {
+            if (b == i) continue;
+            for (int64_t k2 = s->site_off[b]; k2 < s->site_off[b + 1]; ++k2) {
+                double dr[3];
+                for (int k = 0; k < 3; ++k) dr[k] = min_image(pos[k * S + j] - pos[k * S + k2], box_len(s, k));
+                double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
+                if (!(r2 <= rc2)) continue;
+                flags |= wca_pair(par, dr, r2, f);
+            }
+        }
+        double d[3] = {off[j], off[S + j], off[2 * S + j]}, c[3];
+        cross3(d, f, c);
+        for (int k = 0; k < 3; ++k) {
+            F[k] = F[k] + f[k];
+            T[k] = T[k] + c[k];
+        }
+    }
+    return flags;
+}
+
+/* Colloid forces and torques.  Mode 1: WCA between body centres (Sec. II.B),
+ * partners in ascending index.  Mode 2: WCA between sites of different
+ * bodies; the force on site j is summed over the other bodies in ascending
+ * index and their sites in ascending index, then F = sum_j f_j and
+ * T = sum_j d_j x f_j in site order. */
 uint32_t orc_body_forces(orc_sys *s, const orc_par *par)
 {
     uint32_t flags = 0;
-    int64_t B = s->B;
+    int64_t B = s->B, S = s->S;
     for (int64_t i = 0; i < B; ++i)
         for (int k = 0; k < 3; ++k) { s->F[k * B + i] = 0.0; s->T[k * B + i] = 0.0; }
-    if (par->wca_mode != 1) return 0;
+    if (par->wca_mode != 1 && par->wca_mode != 2) return 0;
     double rc = par->delta + 0x1.1f59ac3c7d6c0p+0 * par->sigma;
     double rc2 = rc * rc;
-    for (int64_t i = 0; i < B; ++i) {
-        double f[3] = {0.0, 0.0, 0.0};
-        for (int64_t j = 0; j < B; ++j) {
-            if (j == i) continue;
-            double dr[3];
-            for (int k = 0; k < 3; ++k) {
-                double L = box_len(s, k);
-                double t = s->R[k * B + i] - s->R[k * B + j];
-                if (t > 0.5 * L) t = t - L;
-                else if (t < -0.5 * L) t = t + L;
-                dr[k] = t;
+    if (par->wca_mode == 1) {
+        for (int64_t i = 0; i < B; ++i) {
+            double f[3] = {0.0, 0.0, 0.0};
+            for (int64_t j = 0; j < B; ++j) {
+                if (j == i) continue;
+                double dr[3];
+                for (int k = 0; k < 3; ++k) {
+                    double L = box_len(s, k);
+                    double t = s->R[k * B + i] - s->R[k * B + j];
+                    if (t > 0.5 * L) t = t - L;
+                    else if (t < -0.5 * L) t = t + L;
+                    dr[k] = t;
+                }
+                double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
+                if (!(r2 <= rc2)) continue;
+                flags |= wca_pair(par, dr, r2, f);
             }
-            double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
-            if (!(r2 <= rc2)) continue;
-            double r = sqrt(r2);
-            double sh = r - par->delta;
-            if (!(sh > 0.0)) { flags |= ORC_NONFINITE; continue; }
-            double is = par->sigma / sh;
-            double is2 = is * is;
-            double is6 = (is2 * is2) * is2;
-            double is12 = is6 * is6;
-            double fr = ((24.0 * par->eps) * (2.0 * is12 - is6)) / sh;
-            double fo = fr / r;
-            for (int k = 0; k < 3; ++k) f[k] = f[k] + fo * dr[k];
+            for (int k = 0; k < 3; ++k) s->F[k * B + i] = f[k];
         }
-        for (int k = 0; k < 3; ++k) s->F[k * B + i] = f[k];
+        return flags;
     }
+    double *off = (double *)malloc(sizeof(double) * 3 * (size_t)(S > 0 ? S : 1));
+    double *pos = (double *)malloc(sizeof(double) * 3 * (size_t)(S > 0 ? S : 1));
+    site_frames(s, off, pos);
+    for (int64_t i = 0; i < B; ++i) {
+        double F[3], T[3];
+        flags |= site_wca_body(s, par, off, pos, i, rc2, F, T);
+        for (int k = 0; k < 3; ++k) {
+            s->F[k * B + i] = F[k];
+            s->T[k * B + i] = T[k];
+        }
+    }
+    free(off);
+    free(pos);
     return flags;
+}
+
+/* Mode 2 force and torque of the n listed bodies only (the same sums as
+ * orc_body_forces; F, T are [3][n]). */
+uint32_t orc_site_wca_bodies(const orc_sys *s, const orc_par *par, const int64_t *idx, int64_t n, double *F,
+                             double *T)
+{
+    uint32_t flags = 0;
+    int64_t S = s->S;
+    double rc = par->delta + 0x1.1f59ac3c7d6c0p+0 * par->sigma;
+    double rc2 = rc * rc;
+    double *off = (double *)malloc(sizeof(double) * 3 * (size_t)(S > 0 ? S : 1));
+    double *pos = (double *)malloc(sizeof(double) * 3 * (size_t)(S > 0 ? S : 1));
+    site_frames(s, off, pos);
+    for (int64_t u = 0; u < n; ++u) {
+        double Fi[3], Ti[3];
+        flags |= site_wca_body(s, par, off, pos, idx[u], rc2, Fi, Ti);
+        for (int k = 0; k < 3; ++k) {
+            F[k * n + u] = Fi[k];
+            T[k * n + u] = Ti[k];
+        }
+    }
+    free(off);
+    free(pos);
+    return flags;
+}
+
+/* Total WCA potential energy, Eq. (1), summed over interacting pairs (body
+ * centres in mode 1, sites of different bodies in mode 2).  Used to check
+ * forces and torques as derivatives of the potential. */
+double orc_wca_energy(const orc_sys *s, const orc_par *par)
+{
+    int64_t B = s->B, S = s->S;
+    double rc = par->delta + 0x1.1f59ac3c7d6c0p+0 * par->sigma;
+    double U = 0.0;
+    double *off = NULL, *pos = NULL;
+    if (par->wca_mode == 2) {
+        off = (double *)malloc(sizeof(double) * 3 * (size_t)(S > 0 ? S : 1));
+        pos = (double *)malloc(sizeof(double) * 3 * (size_t)(S > 0 ? S : 1));
+        site_frames(s, off, pos);
+    }
+    for (int64_t i = 0; i < B; ++i)
+        for (int64_t b = i + 1; b < B; ++b) {
+            int64_t n1 = par->wca_mode == 2 ? s->site_off[i + 1] - s->site_off[i] : 1;
+            int64_t n2 = par->wca_mode == 2 ? s->site_off[b + 1] - s->site_off[b] : 1;
+            for (int64_t u = 0; u < n1; ++u)
+                for (int64_t w = 0; w < n2; ++w) {
+                    double r2 = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        double L = box_len(s, k);
+                        double t = par->wca_mode == 2
+                                       ? pos[k * S + s->site_off[i] + u] - pos[k * S + s->site_off[b] + w]
+                                       : s->R[k * B + i] - s->R[k * B + b];
+                        t = t - L * rint(t / L);
+                        r2 += t * t;
+                    }
+                    double r = sqrt(r2);
+                    if (r > rc || r <= par->delta) continue;
+                    double x = par->sigma / (r - par->delta);
+                    double x6 = pow(x, 6.0);
+                    U += 4.0 * par->eps * (x6 * x6 - x6) + par->eps;
+                }
+        }
+    free(off);
+    free(pos);
+    return U;
 }
 
 /* One NO_SQUISH free rotation about body axis k for time delta. */

@@ -264,7 +264,7 @@ TileCfg tile_config(const mpcd_sys *s)
 
 struct Layout {
     size_t status, shift, counts, partial, cell_start, site_start, cellid, slot, perm, draws, site_d, vpre, rtmp,
-        grid_count, grid_body, total;
+        grid_count, grid_body, wpos, woff, total;
     uint32_t grid_mask;
 };
 
@@ -310,6 +310,9 @@ Layout layout_of(const mpcd_sys *s)
     L.grid_mask = (uint32_t)(G - 1);
     L.grid_count = take(sizeof(int32_t) * (size_t)G);
     L.grid_body = take(sizeof(int32_t) * (size_t)G * GRID_K);
+    // site frames for the site-site WCA (offsets and unwrapped positions)
+    L.wpos = take(sizeof(double) * 3 * (size_t)s->n_sites);
+    L.woff = take(sizeof(double) * 3 * (size_t)s->n_sites);
     L.total = off;
     return L;
 }
@@ -1682,8 +1685,54 @@ __global__ void k_grid_insert(SysDev s, BodyDev bd, BodyGrid g)
     if (b < s.B) grid_insert(s, bd, g, b);
 }
 
+// ---- site-site WCA (mode 2) ----------------------------------------------
+//
+// Space-frame offsets d_j = A(q) dhat_j and unwrapped positions R + d_j of a
+// body's sites at the force evaluation, written by the whole block.  A site
+// farther than `reach` from its centre is flagged (the neighbour search
+// relies on the bound).
+struct SiteFrames {
+    double *pos, *off;  // [3S] each; nullptr: not mode 2
+    double reach;
+};
+
+__device__ void site_frames_body(const SysDev &s, const BodyDev &bd, int64_t b, const double pose[7],
+                                 const SiteFrames &fr, uint32_t &st)
+{
+    const int64_t S = s.S;
+    double A[3][3];
+    quat_matrix(pose, A);
+    const double lim = fr.reach * fr.reach;
+    for (int64_t j = bd.site_off[b] + threadIdx.x; j < bd.site_off[b + 1]; j += blockDim.x) {
+        const double dh[3] = {bd.site_d[j], bd.site_d[S + j], bd.site_d[2 * S + j]};
+        double d[3];
+        matvec(A, dh, d);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            fr.off[k * S + j] = d[k];
+            fr.pos[k * S + j] = pose[4 + k] + d[k];
+        }
+        if (!((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2] <= lim)) st |= ST_REACH;
+    }
+}
+
+__global__ __launch_bounds__(BODY_T) void k_site_frames(SysDev s, BodyDev bd, SiteFrames fr, uint32_t *status)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= s.B) return;
+    const int64_t B = s.B;
+    double pose[7];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pose[i] = bd.quat[i * B + b];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pose[4 + k] = bd.pos[k * B + b];
+    uint32_t st = 0;
+    site_frames_body(s, bd, b, pose, fr, st);
+    flag(status, st);
+}
+
 __device__ void body_first_update(const SysDev &s, const BodyDev &bd, int64_t b, const double *Jb,
-                                  const double *Kb, double dt, uint32_t &st)
+                                  const double *Kb, double dt, uint32_t &st, double *pose_out = nullptr)
 {
     const int64_t B = s.B;
     const int r = find_sys(s.body_off, s.nsys, b);
@@ -1733,6 +1782,12 @@ __device__ void body_first_update(const SysDev &s, const BodyDev &bd, int64_t b,
     nosquish(3, hdt, I3, q, p);
 #pragma unroll
     for (int i = 0; i < 4; ++i) { bd.quat[i * B + b] = q[i]; bd.angmom[i * B + b] = p[i]; }
+    if (pose_out) {  // new q (4) and R (3) for the rest of the block
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pose_out[i] = q[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pose_out[4 + k] = bd.pos[k * B + b];
+    }
 }
 
 __global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double *K, double dt,
@@ -1755,10 +1810,11 @@ __global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double
 template <typename Real>
 __global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd, const Real *vs, const double *site_d,
                                                            const double *vpre, double *J, double *K, double dt,
-                                                           BodyGrid grid, uint32_t *status)
+                                                           BodyGrid grid, SiteFrames fr, uint32_t *status)
 {
     __shared__ double sh[6 * SH_PAD];
     __shared__ double jk[6];
+    __shared__ double pose[7];
     const int64_t b = blockIdx.x;
     if (b >= s.B) return;
     const double acc = transfer_sums<Real>(bd, s.S, b, vs, site_d, vpre, sh);
@@ -1769,8 +1825,14 @@ __global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd,
         uint32_t st = 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) { J[k * s.B + b] = jk[k]; K[k * s.B + b] = jk[3 + k]; }
-        body_first_update(s, bd, b, jk, jk + 3, dt, st);
+        body_first_update(s, bd, b, jk, jk + 3, dt, st, pose);
         if (grid.count) grid_insert(s, bd, grid, b);
+        flag(status, st);
+    }
+    if (fr.pos) {
+        __syncthreads();
+        uint32_t st = 0;
+        site_frames_body(s, bd, b, pose, fr, st);
         flag(status, st);
     }
 }
@@ -1987,6 +2049,199 @@ __global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpc
         qmul_pure(q, h3, dq);
 #pragma unroll
         for (int k = 0; k < 4; ++k) bd.angmom[k * B + i] = bd.angmom[k * B + i] + dt * dq[k];
+    }
+    flag(status, st);
+}
+
+
+// Site-site WCA (mode 2), one block per body.  The neighbour bodies (centres
+// within 2 reach + rc, from the 27 surrounding buckets of a grid whose cells
+// are at least that wide) are listed in ascending index; without the grid, or
+// when a bucket overflowed, every body of the system is a candidate in
+// ascending index.  Lane t takes site j of the chunk: f_j sums the pair forces
+// of the candidates' sites within the cutoff, in ascending body and site index
+// (a candidate whose centre is farther than reach + rc from the site cannot
+// contribute and is skipped).  Lanes 0..5 then add f_j and d_j x f_j in site
+// order.  With kick != 0 the second half kick follows; with advance_step set,
+// block 0 advances the step counter.
+__device__ __forceinline__ double min_image(double t, double L) { return t - L * rint(t / L); }
+
+__global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid,
+                                                        SiteFrames fr, double dt, int kick, uint64_t *advance_step,
+                                                        uint32_t *status)
+{
+    constexpr int NCAND = 27 * GRID_K;
+    __shared__ uint32_t s_h[27];
+    __shared__ int s_n[27], s_pre[28];
+    __shared__ int s_ovf, s_nnb;
+    __shared__ int nb[NCAND];
+    __shared__ double sh[6 * SH_PAD];
+    __shared__ double fT[6];
+    const int64_t i = blockIdx.x;
+    if (advance_step && i == 0 && threadIdx.x == 0) *advance_step = *advance_step + 1;
+    if (i >= s.B) return;
+    const int t = threadIdx.x;
+    const int64_t B = s.B, S = s.S;
+    uint32_t st = 0;
+    const int r = find_sys(s.body_off, s.nsys, i);
+    const double rc = wca.delta + 0x1.1f59ac3c7d6c0p+0 * wca.sigma;
+    const double rc2 = rc * rc;
+    double Lb[3], Ri[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Lb[k] = (double)s.ncell[3 * r + k] * s.a;
+        Ri[k] = bd.pos[k * B + i];
+    }
+    const int64_t jb = s.body_off[r], je = s.body_off[r + 1];
+    // centre-distance bounds with a margin far above rounding
+    const double reach_b = 2.0 * wca.reach + rc, cut_b = (reach_b * reach_b) * (1.0 + 1e-9) + 1e-12;
+    const double reach_s = wca.reach + rc, cut_s = (reach_s * reach_s) * (1.0 + 1e-9) + 1e-12;
+    bool use_grid = grid.count != nullptr;
+    if (use_grid) {
+        int ng[3];
+        double cw[3];
+        grid_geometry(s, r, grid.rc, ng, cw);
+        if (t == 0) {
+            s_ovf = 0;
+            s_nnb = 0;
+        }
+        if (t < 27) {
+            const int d[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+            int nc[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                int c = grid_axis(Ri[k], cw[k], ng[k]) + d[k];
+                c = c < 0 ? c + ng[k] : (c >= ng[k] ? c - ng[k] : c);
+                nc[k] = c;
+            }
+            s_h[t] = grid_hash(r, nc[0], nc[1], nc[2], grid.mask);
+        }
+        __syncthreads();
+        if (t < 27) {
+            const uint32_t h = s_h[t];
+            bool dup = false;
+            for (int u = 0; u < t; ++u) dup = dup || (s_h[u] == h);
+            const int n = dup ? 0 : grid.count[h];
+            if (n > GRID_K) s_ovf = 1;
+            s_n[t] = n;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int acc_n = 0;
+            for (int u = 0; u < 27; ++u) {
+                s_pre[u] = acc_n;
+                acc_n += s_n[u] < GRID_K ? s_n[u] : GRID_K;
+            }
+            s_pre[27] = acc_n;
+        }
+        __syncthreads();
+        use_grid = s_ovf == 0;
+        if (use_grid) {
+            for (int idx = t; idx < s_pre[27]; idx += BODY_T) {
+                int u = 0;
+                while (u < 26 && s_pre[u + 1] <= idx) ++u;
+                const int64_t j = grid.body[(size_t)s_h[u] * GRID_K + (idx - s_pre[u])];
+                if (j == i || j < jb || j >= je) continue;
+                double d2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double d = min_image(Ri[k] - bd.pos[k * B + j], Lb[k]);
+                    d2 = d2 + d * d;
+                }
+                if (d2 <= cut_b) nb[atomicAdd(&s_nnb, 1)] = (int)j;
+            }
+            __syncthreads();
+            if (t == 0) {
+                const int n = s_nnb;
+                for (int a = 1; a < n; ++a) {
+                    const int v = nb[a];
+                    int q = a;
+                    while (q > 0 && nb[q - 1] > v) {
+                        nb[q] = nb[q - 1];
+                        --q;
+                    }
+                    nb[q] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int ncand = use_grid ? s_nnb : (int)(je - jb);
+    const int64_t j0 = bd.site_off[i], j1 = bd.site_off[i + 1];
+    double acc = 0.0;
+    for (int64_t c0 = j0; c0 < j1; c0 += BODY_T) {
+        const int64_t j = c0 + t;
+        if (j < j1) {
+            const double pj[3] = {fr.pos[j], fr.pos[S + j], fr.pos[2 * S + j]};
+            double f[3] = {0.0, 0.0, 0.0};
+            for (int q = 0; q < ncand; ++q) {
+                const int64_t b2 = use_grid ? (int64_t)nb[q] : jb + q;
+                if (b2 == i) continue;
+                double d2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double d = min_image(pj[k] - bd.pos[k * B + b2], Lb[k]);
+                    d2 = d2 + d * d;
+                }
+                if (!(d2 <= cut_s)) continue;
+                for (int64_t k2 = bd.site_off[b2]; k2 < bd.site_off[b2 + 1]; ++k2) {
+                    double dr[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) dr[k] = min_image(pj[k] - fr.pos[k * S + k2], Lb[k]);
+                    const double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
+                    if (!(r2 <= rc2)) continue;
+                    const double rr = sqrt(r2);
+                    const double shf = rr - wca.delta;
+                    if (!(shf > 0.0)) {
+                        st |= ST_NONFINITE;
+                        continue;
+                    }
+                    const double is = wca.sigma / shf;
+                    const double is2 = is * is;
+                    const double is6 = (is2 * is2) * is2;
+                    const double is12 = is6 * is6;
+                    const double frr = ((24.0 * wca.eps) * (2.0 * is12 - is6)) / shf;
+                    const double fo = frr / rr;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) f[k] = f[k] + fo * dr[k];
+                }
+            }
+            const double d[3] = {fr.off[j], fr.off[S + j], fr.off[2 * S + j]};
+            double c[3];
+            cross3(d, f, c);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) { sh[k * SH_PAD + t] = f[k]; sh[(3 + k) * SH_PAD + t] = c[k]; }
+        }
+        __syncthreads();
+        ordered_add(sh, (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T), acc);
+        __syncthreads();
+    }
+    if (t < 6) fT[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            bd.force[k * B + i] = fT[k];
+            bd.torque[k * B + i] = fT[3 + k];
+        }
+        if (kick) {
+            const double hdt = 0.5 * dt;
+            double q[4], A[3][3], v3[3], h3[3], dq[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = bd.quat[k * B + i];
+            quat_matrix(q, A);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double Pk = bd.mom[k * B + i] + hdt * fT[k];
+                if (!(Pk - Pk == 0.0)) st |= ST_NONFINITE;
+                bd.mom[k * B + i] = Pk;
+                v3[k] = fT[3 + k];
+            }
+            matTvec(A, v3, h3);
+            qmul_pure(q, h3, dq);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bd.angmom[k * B + i] = bd.angmom[k * B + i] + dt * dq[k];
+        }
     }
     flag(status, st);
 }
@@ -2268,18 +2523,33 @@ static void launch_thermalize(const Ctx &c, hipStream_t st, const mpcd_bodies *b
 static BodyGrid body_grid(const Ctx &c, const mpcd_wca &wca)
 {
     BodyGrid g;
-    const bool on = wca.mode == 1 && c.sys->n_bodies > 0;
+    const bool on = (wca.mode == 1 || wca.mode == 2) && c.sys->n_bodies > 0;
     g.count = on ? at<int32_t>(c.ws, c.L.grid_count) : nullptr;
     g.body = on ? at<int32_t>(c.ws, c.L.grid_body) : nullptr;
     g.mask = c.L.grid_mask;
-    g.rc = wca.delta + 0x1.1f59ac3c7d6c0p+0 * wca.sigma;
+    const double rc = wca.delta + 0x1.1f59ac3c7d6c0p+0 * wca.sigma;
+    g.rc = wca.mode == 2 ? 2.0 * wca.reach + rc : rc;  // centre distance within which bodies interact
     return g;
+}
+
+static SiteFrames site_frames(const Ctx &c, const mpcd_wca &wca)
+{
+    SiteFrames f;
+    const bool on = wca.mode == 2 && c.sys->n_sites > 0;
+    f.pos = on ? at<double>(c.ws, c.L.wpos) : nullptr;
+    f.off = on ? at<double>(c.ws, c.L.woff) : nullptr;
+    f.reach = wca.reach;
+    return f;
 }
 
 // Standalone entry points: rebuild the body-centre grid from the current
 // positions (the fused step clears it in k_prep and fills it after the drift).
 static void launch_body_grid(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca)
 {
+    const SiteFrames fr = site_frames(c, wca);
+    if (fr.pos)
+        hipLaunchKernelGGL(k_site_frames, dim3((unsigned)c.sys->n_bodies), dim3(BODY_T), 0, st, c.sd,
+                           make_bodydev(bodies), fr, c.status);
     const BodyGrid g = body_grid(c, wca);
     if (!g.count) return;
     const int64_t G = (int64_t)c.L.grid_mask + 1;
@@ -2331,23 +2601,29 @@ static void launch_transfer_first(const Ctx &c, hipStream_t st, const mpcd_bodie
                                   double *K, double dt, const mpcd_wca &wca)
 {
     const BodyGrid grid = body_grid(c, wca);
+    const SiteFrames fr = site_frames(c, wca);
     if (c.sys->n_bodies == 0) return;
     const BodyDev bd = make_bodydev(bodies);
     const dim3 gb((unsigned)c.sys->n_bodies);
     if (c.sys->prec == MPCD_F64)
         hipLaunchKernelGGL(k_transfer_first<double>, gb, dim3(BODY_T), 0, st, c.sd, bd, (const double *)vs,
-                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, c.status);
+                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, fr, c.status);
     else
         hipLaunchKernelGGL(k_transfer_first<float>, gb, dim3(BODY_T), 0, st, c.sd, bd, (const float *)vs,
-                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, c.status);
+                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, fr, c.status);
 }
 
 static void launch_forces(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca, double dt,
                           int kick, uint64_t *advance)
 {
     if (c.sys->n_bodies == 0) return;
-    hipLaunchKernelGGL(k_body_forces, dim3((unsigned)c.sys->n_bodies), dim3(FRC_T), 0, st, c.sd,
-                       make_bodydev(bodies), wca, body_grid(c, wca), dt, kick, advance, c.status);
+    if (wca.mode == 2)
+        hipLaunchKernelGGL(k_site_forces, dim3((unsigned)c.sys->n_bodies), dim3(BODY_T), 0, st, c.sd,
+                           make_bodydev(bodies), wca, body_grid(c, wca), site_frames(c, wca), dt, kick, advance,
+                           c.status);
+    else
+        hipLaunchKernelGGL(k_body_forces, dim3((unsigned)c.sys->n_bodies), dim3(FRC_T), 0, st, c.sd,
+                           make_bodydev(bodies), wca, body_grid(c, wca), dt, kick, advance, c.status);
 }
 
 static void launch_reorder(const Ctx &c, hipStream_t st, void *x, void *v, int32_t *tag)
@@ -2527,8 +2803,9 @@ int sites_to_body(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, 
 
 static int wca_check(const mpcd_wca *wca)
 {
-    if (!wca || (wca->mode != 0 && wca->mode != 1)) return MPCD_EINVAL;
-    if (wca->mode == 1 && !(wca->sigma > 0.0 && wca->eps >= 0.0 && wca->delta >= 0.0)) return MPCD_EINVAL;
+    if (!wca || wca->mode < 0 || wca->mode > 2) return MPCD_EINVAL;
+    if (wca->mode != 0 && !(wca->sigma > 0.0 && wca->eps >= 0.0 && wca->delta >= 0.0)) return MPCD_EINVAL;
+    if (wca->mode == 2 && !(wca->reach >= 0.0 && wca->reach < 1e300)) return MPCD_EINVAL;
     return MPCD_OK;
 }
 

@@ -120,8 +120,12 @@ class GPUSystem:
             mass=_ptr(self.mass), inertia=_ptr(self.inertia), site_off=_ptr(self.site_off),
             site_body=_ptr(self.site_body), site_d=_ptr(self.site_d), site_m=_ptr(self.site_m))
         w = self.params.get("wca", {"mode": 0})
+        # site-site WCA: bound on a site's distance from its body centre
+        dh = [np.asarray(s["dhat"]) for s in systems if np.asarray(s["dhat"]).size]
+        reach = max(float(np.sqrt((d ** 2).sum(0)).max()) for d in dh) * (1.0 + 1e-9) if dh else 0.0
         self.cwca = L.MpcdWca(mode=int(w.get("mode", 0)), eps=float(w.get("eps", 0.0)),
-                              sigma=float(w.get("sigma", 0.0)), delta=float(w.get("delta", 0.0)))
+                              sigma=float(w.get("sigma", 0.0)), delta=float(w.get("delta", 0.0)),
+                              reach=float(w.get("reach", reach)))
         self.fuse_stream = bool(fuse_stream)
         L.check(self.lib.mpcd_ws_init(self.stream, C.byref(self.csys), _ptr(self.ws), self.ws_bytes),
                 "mpcd_ws_init")

@@ -142,6 +142,49 @@ def rsa_positions(rng, box, n: int, dmin: float, max_tries: int = 200000000) -> 
     return pts
 
 
+def rsa_positions_radii(rng, box, radii, max_tries: int = 200000000) -> np.ndarray:
+    """Random sequential addition of spheres of the given radii (no two closer
+    than the sum of their radii, minimum image), in the given order."""
+    box = np.asarray(box, dtype=np.float64)
+    radii = np.asarray(radii, dtype=np.float64)
+    n = len(radii)
+    cw_min = 2.0 * float(radii.max()) if n else 1.0
+    ng = np.maximum(1, np.floor(box / cw_min).astype(int))
+    cw = box / ng
+    grid: dict = {}
+    pts = np.zeros((n, 3))
+    tries = 0
+    for i in range(n):
+        while True:
+            tries += 1
+            if tries > max_tries:
+                raise RuntimeError("random sequential addition did not converge")
+            p = rng.random(3) * box
+            g = np.floor(p / cw).astype(int) % ng
+            ok = True
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dz in (-1, 0, 1):
+                        key = ((g[0] + dx) % ng[0], (g[1] + dy) % ng[1], (g[2] + dz) % ng[2])
+                        for j in grid.get(key, ()):
+                            dr = p - pts[j]
+                            dr -= box * np.round(dr / box)
+                            if dr @ dr < (radii[i] + radii[j]) ** 2:
+                                ok = False
+                                break
+                        if not ok:
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if ok:
+                pts[i] = p
+                grid.setdefault((g[0], g[1], g[2]), []).append(i)
+                break
+    return pts
+
+
 # ---------------------------------------------------------------------------
 # Systems
 
@@ -241,6 +284,32 @@ def wca_spheres(sigma=6.0, eps=1.0, delta=0.0):
     return {"mode": 1, "eps": eps, "sigma": sigma, "delta": delta}
 
 
+def wca_sites(sigma=1.0, eps=1.0, delta=0.0):
+    """WCA between surface sites of different bodies."""
+    return {"mode": 2, "eps": eps, "sigma": sigma, "delta": delta}
+
+
+def shapes(ncell, density, ncube, nrod, ndumb, site_mass=5.0, seed=5, kT=1.0):
+    """Mixed suspension of cubes (edge 4, 150 sites), rods (length 10, radius 1,
+    180 sites) and dumbbells (two radius-1.5 spheres 4 apart, 160 sites),
+    placed by random sequential addition of their bounding spheres, random
+    orientations, shapes interleaved."""
+    rng = np.random.default_rng(seed)
+    kinds = [rigid_template(cube_surface(4.0, 5), site_mass), rigid_template(rod_surface(10.0, 1.0, 18, 10), site_mass),
+             rigid_template(dumbbell_surface(1.5, 4.0, 80), site_mass)]
+    counts = [ncube, nrod, ndumb]
+    order = []
+    for i in range(max(counts)):
+        for k in range(3):
+            if i < counts[k]:
+                order.append(k)
+    tpls = [kinds[k] for k in order]
+    radii = [float(np.sqrt((t[0] ** 2).sum(1)).max()) for t in tpls]
+    centres = rsa_positions_radii(rng, np.array(ncell, dtype=np.float64), radii) if tpls else np.zeros((0, 3))
+    quats = random_quaternions(rng, len(tpls))
+    return make_system(ncell, density, tpls, centres, quats, rng, kT=kT)
+
+
 def config(i: int, kT_cell: float = 1.0):
     """Return (workload, params, meta) for named workload i.
 
@@ -248,6 +317,8 @@ def config(i: int, kT_cell: float = 1.0):
     1  suspension: 60^3 cells, 5/cell, 191 spheres r=3 (200 sites), WCA sigma=6; seed 2
     2  large suspension: 200^3 cells, 10/cell, spheres r=3 at volume fraction 0.3; seed 3
     3  batched: 512 cubic boxes, edge U{12..24}, 5/cell, one sphere r=2 each; seed 4
+    4  complex shapes: 128^3 cells, 10/cell, 667 cubes + 667 rods + 666 dumbbells,
+       site-site WCA sigma=1; seed 5
     """
     if i == 0:
         wl = single_sphere((10, 10, 10), 5, 2.0, 100, 5.0, centre=(5.0, 5.0, 5.0), seed=1)
@@ -265,6 +336,10 @@ def config(i: int, kT_cell: float = 1.0):
             name="large suspension 200^3 cells, 80M solvent, %d spheres x 200 sites" % nb, steps=200)
     if i == 3:
         return batched_replicas(512, seed=4, kT_cell=kT_cell)
+    if i == 4:
+        wl = shapes((128, 128, 128), 10, 667, 667, 666, seed=5)
+        return wl, srd_params(5, kT_cell=kT_cell, wca=wca_sites()), dict(
+            name="complex shapes 128^3 cells, 21M solvent, 667 cubes + 667 rods + 666 dumbbells", steps=500)
     raise ValueError("unknown workload %d" % i)
 
 

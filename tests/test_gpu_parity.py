@@ -328,6 +328,56 @@ def test_wca_forces_neighbour_grid_bit_exact(case):
     assert g.status() == 0
 
 
+def test_site_wca_mixed_shapes_bit_exact():
+    """Cubes, rods and dumbbells with WCA between sites of different bodies
+    (forces and torques), full steps against the oracle."""
+    wl = W.shapes((24, 24, 24), 3, 4, 4, 4, seed=51)
+    par = W.srd_params(51, kT_cell=1.0, wca=W.wca_sites(sigma=1.0))
+    say("site WCA shapes 24^3")
+    o, g = run_parity(wl, par, 12, check_every=4)
+    assert np.count_nonzero(o.T) > 0
+
+
+def test_site_wca_crowded_bodies_fall_back_to_all_pairs():
+    """Small shapes packed so a grid bucket overflows: every body of the
+    system becomes a candidate, with the same sums."""
+    rng = np.random.default_rng(52)
+    cube = np.array([[x, y, z] for x in (-0.5, 0.5) for y in (-0.5, 0.5) for z in (-0.5, 0.5)])
+    tpl = W.rigid_template(cube, 1.0)
+    centres = np.concatenate([0.5 + 2.5 * rng.random((30, 3)), 6.0 + 3.0 * rng.random((10, 3))])
+    wl = W.make_system((10, 10, 10), 0, [tpl] * 40, centres, W.random_quaternions(rng, 40), rng)
+    par = W.srd_params(52, wca=W.wca_sites(sigma=0.7))
+    o = oracle.OracleSystem(wl, par)
+    g = gpu_system(wl, par, prec="f64")
+    o.body_forces()
+    g.body_forces()
+    say("site WCA crowded")
+    assert_same(o, g.download()[0], ("F", "T"), "forces")
+    assert np.count_nonzero(o.T) > 0
+    assert g.status() == 0
+
+
+def test_site_wca_full_size_shapes_sampled():
+    """128^3 cells, 21M solvent, 2000 cubes, rods and dumbbells (326,670 sites):
+    after one FP32 step, the FP64 site-site forces and torques of sampled bodies
+    equal the oracle's at the same body poses."""
+    wl, par, _ = W.config(4)
+    say("complex shapes full size")
+    g = gpu_system(wl, par, prec="f32")
+    del wl["x"], wl["v"]
+    g.body_forces()
+    g.step(1)
+    assert g.status() == 0
+    gd = g.download()[0]
+    wl2 = dict(wl, x=np.zeros((3, 0)), v=np.zeros((3, 0)), R=gd["R"], q=gd["q"])
+    o = oracle.OracleSystem(wl2, par)
+    idx = np.array([0, 1, 2, 777, 1333, 1999])
+    F, T, fl = o.site_wca_bodies(idx)
+    assert fl == 0
+    assert np.array_equal(F, gd["F"][:, idx]) and np.array_equal(T, gd["T"][:, idx])
+    assert np.count_nonzero(gd["F"]) > 0
+
+
 def test_full_size_suspension_bit_exact_few_steps():
     """60^3 cells, 1.08M solvent, 191 spheres x 200 sites, WCA: the benchmark
     workload, checked bit for bit over 3 steps."""

@@ -350,6 +350,96 @@ def test_wca_collision_conserves_energy_and_momentum():
     assert np.all(o.img == 0)
 
 
+def wca_sites(sigma=1.0, eps=1.0, delta=0.0):
+    return {"mode": 2, "eps": eps, "sigma": sigma, "delta": delta}
+
+
+def shape_bodies(ncell, centres, quats, seed):
+    """Small rigid shapes (dumbbells of 2 x 6 sites, 8-site cubes, 4-site rods)."""
+    rng = np.random.default_rng(seed)
+    cube = np.array([[x, y, z] for x in (-0.7, 0.7) for y in (-0.7, 0.7) for z in (-0.7, 0.7)])
+    rod = np.array([[0.0, 0.0, z] for z in (-1.5, -0.5, 0.5, 1.5)])
+    dumb = np.concatenate([W.fibonacci_sphere(6, 0.6) + [0, 0, 1.2], W.fibonacci_sphere(6, 0.6) - [0, 0, 1.2]])
+    shapes = [W.rigid_template(x, 1.0) for x in (dumb, cube, rod)]
+    tpls = [shapes[b % 3] for b in range(len(centres))]
+    return W.make_system(ncell, 0, tpls, centres, quats, rng)
+
+
+def test_site_wca_reduces_to_centre_wca_for_one_central_site():
+    """Bodies of one site at the centre: site-site WCA is body-centre WCA."""
+    rng = np.random.default_rng(41)
+    centres = rng.random((40, 3)) * 8.0
+    tpl = W.rigid_template(np.zeros((1, 3)), 1.0)
+    wl = W.make_system((8, 8, 8), 0, [tpl] * 40, centres, np.tile([1.0, 0, 0, 0], (40, 1)), rng)
+    o1 = oracle.OracleSystem(wl, params(wca=W.wca_spheres(sigma=1.0)))
+    o2 = oracle.OracleSystem(wl, params(wca=wca_sites(sigma=1.0)))
+    assert o1.body_forces() == 0 and o2.body_forces() == 0
+    assert np.count_nonzero(o1.F) > 0
+    assert np.array_equal(o1.F, o2.F)
+    assert np.all(o2.T == 0.0)
+
+
+def rot_quat(axis, ang):
+    axis = np.asarray(axis, float) / np.linalg.norm(axis)
+    return np.concatenate([[math.cos(ang / 2)], math.sin(ang / 2) * axis])
+
+
+def qmul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def test_site_wca_force_and_torque_are_minus_gradients():
+    """F_i = -dU/dR_i and T_i . e = -dU/dtheta for a rotation of body i by
+    theta about the space-frame axis e, with U the total site-site energy of
+    Eq. (1)."""
+    rng = np.random.default_rng(42)
+    centres = np.array([[5.0, 5.0, 5.0], [6.6, 5.4, 5.2], [5.3, 6.7, 4.6], [4.1, 4.3, 6.3]])
+    wl = shape_bodies((10, 10, 10), centres, W.random_quaternions(rng, 4), 43)
+    o = oracle.OracleSystem(wl, params(wca=wca_sites(sigma=0.8)))
+    assert o.body_forces() == 0
+    F, T = o.F.copy(), o.T.copy()
+    assert np.count_nonzero(F) >= 6
+    F2, T2, fl = o.site_wca_bodies([2, 0])  # the per-body entry gives the same sums
+    assert fl == 0 and np.array_equal(F2, F[:, [2, 0]]) and np.array_equal(T2, T[:, [2, 0]])
+    h = 1e-6
+    for i in range(4):
+        for k in range(3):
+            R0 = o.R[k, i]
+            o.R[k, i] = R0 + h
+            up = o.wca_energy()
+            o.R[k, i] = R0 - h
+            um = o.wca_energy()
+            o.R[k, i] = R0
+            assert math.isclose(F[k, i], -(up - um) / (2 * h), rel_tol=1e-5, abs_tol=1e-6), (i, k)
+        q0 = o.q[:, i].copy()
+        for k in range(3):
+            e = np.eye(3)[k]
+            o.q[:, i] = qmul(rot_quat(e, h), q0)
+            up = o.wca_energy()
+            o.q[:, i] = qmul(rot_quat(e, -h), q0)
+            um = o.wca_energy()
+            o.q[:, i] = q0
+            assert math.isclose(T[k, i], -(up - um) / (2 * h), rel_tol=1e-5, abs_tol=1e-6), (i, k)
+
+
+def test_site_wca_obeys_newtons_third_law():
+    """Sum of forces and of total torques about the origin vanish (bodies away
+    from the periodic boundaries)."""
+    rng = np.random.default_rng(44)
+    centres = 8.0 + 4.0 * rng.random((12, 3))
+    wl = shape_bodies((20, 20, 20), centres, W.random_quaternions(rng, 12), 45)
+    o = oracle.OracleSystem(wl, params(wca=wca_sites(sigma=1.0)))
+    assert o.body_forces() == 0
+    scale = np.abs(o.F).max()
+    assert scale > 0
+    assert np.allclose(o.F.sum(1), 0.0, atol=1e-12 * scale * 12)
+    Ltot = np.cross(o.R.T, o.F.T).sum(0) + o.T.sum(1)
+    assert np.allclose(Ltot, 0.0, atol=1e-11 * scale * 12 * 20)
+
+
 # ---------------------------------------------------------------------------
 # Failure detection
 
