@@ -328,13 +328,31 @@ def test_wca_forces_neighbour_grid_bit_exact(case):
     assert g.status() == 0
 
 
+def small_shapes(ncell, density, centres, seed):
+    """Dumbbells (2 x 6 sites), 8-site cubes and 4-site rods, unit site mass."""
+    rng = np.random.default_rng(seed)
+    cube = np.array([[x, y, z] for x in (-0.7, 0.7) for y in (-0.7, 0.7) for z in (-0.7, 0.7)])
+    rod = np.array([[0.0, 0.0, z] for z in (-1.5, -0.5, 0.5, 1.5)])
+    dumb = np.concatenate([W.fibonacci_sphere(6, 0.6) + [0, 0, 1.2], W.fibonacci_sphere(6, 0.6) - [0, 0, 1.2]])
+    kinds = [W.rigid_template(x, 1.0) for x in (dumb, cube, rod)]
+    tpls = [kinds[b % 3] for b in range(len(centres))]
+    return W.make_system(ncell, density, tpls, centres, W.random_quaternions(rng, len(centres)), rng)
+
+
 def test_site_wca_mixed_shapes_bit_exact():
-    """Cubes, rods and dumbbells with WCA between sites of different bodies
-    (forces and torques), full steps against the oracle."""
-    wl = W.shapes((24, 24, 24), 3, 4, 4, 4, seed=51)
-    par = W.srd_params(51, kT_cell=1.0, wca=W.wca_sites(sigma=1.0))
-    say("site WCA shapes 24^3")
-    o, g = run_parity(wl, par, 12, check_every=4)
+    """Cubes, rods and dumbbells in contact, WCA between sites of different
+    bodies (forces and torques), full steps against the oracle.  The layout
+    (random sequential addition of radius-1.3 spheres, seed 74) keeps bodies in
+    contact over the run without violent overlaps."""
+    rng = np.random.default_rng(74)
+    centres = W.rsa_positions_radii(rng, np.array([10.0, 10.0, 10.0]), np.full(10, 1.3))
+    wl = small_shapes((10, 10, 10), 3, centres, 74)
+    par = W.srd_params(74, kT_cell=1.0, wca=W.wca_sites(sigma=0.8))
+    o0 = oracle.OracleSystem(wl, par)
+    o0.body_forces()
+    assert np.count_nonzero(o0.T) >= 6  # the bodies interact from the start
+    say("site WCA shapes 10^3")
+    o, g = run_parity(wl, par, 12, check_every=3)
     assert np.count_nonzero(o.T) > 0
 
 
