@@ -71,6 +71,8 @@ enum {
 #define MPCD_FLAG_RNGLOOP 8u   /* a rejection sampler used all 64 Philox calls */
 #define MPCD_FLAG_BINERR 16u   /* inconsistent binning counts (particles dropped) */
 #define MPCD_FLAG_REACH 32u    /* WCA mode 2: a site lies beyond mpcd_wca.reach  */
+#define MPCD_FLAG_CROWD 64u    /* FP64: a cell above 16384 members was not collided
+                                  (its canonical ordering is quadratic)          */
 
 /* Geometry and sizes of nsys independent periodic boxes of cubic cells. */
 typedef struct {

@@ -18,7 +18,7 @@ enum : uint64_t { RNG_SHIFT = 0, RNG_AXIS = 1, RNG_THERMO = 2, RNG_SITE = 3 };
 constexpr int RNG_MAX_CALLS = 64;
 
 constexpr uint32_t ST_NONFINITE = 1u, ST_ESCAPE = 2u, ST_FIXOVF = 4u, ST_RNGLOOP = 8u, ST_BINERR = 16u,
-                   ST_REACH = 32u;
+                   ST_REACH = 32u, ST_CROWD = 64u;
 
 struct Words {
     uint64_t w[4];

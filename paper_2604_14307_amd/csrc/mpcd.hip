@@ -947,6 +947,14 @@ __device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double
     const int64_t N = s.N, S = s.S;
     if (!cell_out_prepare<double>(A, gc, v, O, st)) return;
     const MemberVel<double> vel{v, vs, O.v, N, S, A.site_start[gc]};
+    // the canonical ordering below is quadratic in the members: a cell far
+    // beyond any physical occupancy (a corrupted state) is streamed, not collided
+    constexpr int MAX_CELL_F64 = 1 << 14;
+    if (n > MAX_CELL_F64) {
+        st |= ST_CROWD;
+        cell_stream_global<double>(A, gc, vel, x, O, st);
+        return;
+    }
     // identity key in the high word, permutation position in the low word
     auto key_at = [&](int i) -> uint64_t { return ((uint64_t)ident(A, A.perm[i]) << 32) | (uint32_t)i; };
     auto mass = [&](int32_t k) -> double { return k < N ? s.m : A.site_m[k - N]; };

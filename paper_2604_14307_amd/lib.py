@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpcd.so")
 
 MPCD_F64, MPCD_F32 = 0, 1
-FLAG_NONFINITE, FLAG_ESCAPE, FLAG_FIXOVF, FLAG_RNGLOOP, FLAG_BINERR, FLAG_REACH = 1, 2, 4, 8, 16, 32
+FLAG_NONFINITE, FLAG_ESCAPE, FLAG_FIXOVF, FLAG_RNGLOOP, FLAG_BINERR, FLAG_REACH, FLAG_CROWD = 1, 2, 4, 8, 16, 32, 64
 
 EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mpcd_stream", "mpcd_bin", "mpcd_collide",
            "mpcd_cell_draws", "mpcd_collide_drawn",

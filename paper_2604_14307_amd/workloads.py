@@ -289,11 +289,62 @@ def wca_sites(sigma=1.0, eps=1.0, delta=0.0):
     return {"mode": 2, "eps": eps, "sigma": sigma, "delta": delta}
 
 
-def shapes(ncell, density, ncube, nrod, ndumb, site_mass=5.0, seed=5, kT=1.0):
+def quat_matrix(q) -> np.ndarray:
+    """Body-to-space rotation of the unit quaternion (w, x, y, z) (placement only)."""
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def rsa_bodies(rng, box, tpls, quats, gap, max_tries: int = 1000000) -> np.ndarray:
+    """Random sequential addition of oriented rigid bodies: a trial centre is
+    accepted when every site keeps at least `gap` from every site of the bodies
+    already placed (minimum image); bounding spheres may interpenetrate."""
+    box = np.asarray(box, dtype=np.float64)
+    n = len(tpls)
+    sites = [tpls[b][0] @ quat_matrix(quats[b]).T for b in range(n)]
+    radii = np.array([float(np.sqrt((x ** 2).sum(1)).max()) if len(x) else 0.0 for x in sites])
+    reach = 2.0 * float(radii.max()) + gap if n else 1.0
+    ng = np.maximum(1, np.floor(box / reach).astype(int))
+    cw = box / ng
+    grid: dict = {}
+    pts = np.zeros((n, 3))
+    for i in range(n):
+        for _ in range(max_tries):
+            p = rng.random(3) * box
+            g = np.floor(p / cw).astype(int) % ng
+            ok = True
+            keys = {((g[0] + dx) % ng[0], (g[1] + dy) % ng[1], (g[2] + dz) % ng[2])
+                    for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)}
+            for key in keys:
+                for j in grid.get(key, ()):
+                    dc = p - pts[j]
+                    dc -= box * np.round(dc / box)
+                    if dc @ dc >= (radii[i] + radii[j] + gap) ** 2:
+                        continue
+                    d = (sites[i][:, None, :] + dc) - sites[j][None, :, :]
+                    d -= box * np.round(d / box)
+                    if ((d * d).sum(2) < gap * gap).any():
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if ok:
+                pts[i] = p
+                grid.setdefault((g[0], g[1], g[2]), []).append(i)
+                break
+        else:
+            raise RuntimeError("random sequential addition did not converge")
+    return pts
+
+
+def shapes(ncell, density, ncube, nrod, ndumb, site_mass=5.0, seed=5, kT=1.0, gap=2.0 ** (1.0 / 6.0)):
     """Mixed suspension of cubes (edge 4, 150 sites), rods (length 10, radius 1,
-    180 sites) and dumbbells (two radius-1.5 spheres 4 apart, 160 sites),
-    placed by random sequential addition of their bounding spheres, random
-    orientations, shapes interleaved."""
+    180 sites) and dumbbells (two radius-1.5 spheres 4 apart, 160 sites), shapes
+    interleaved, random orientations, placed without overlap: no two sites of
+    different bodies closer than `gap` (the site-site WCA cutoff for sigma = 1),
+    so no body starts inside another's repulsion."""
     rng = np.random.default_rng(seed)
     kinds = [rigid_template(cube_surface(4.0, 5), site_mass), rigid_template(rod_surface(10.0, 1.0, 18, 10), site_mass),
              rigid_template(dumbbell_surface(1.5, 4.0, 80), site_mass)]
@@ -304,9 +355,8 @@ def shapes(ncell, density, ncube, nrod, ndumb, site_mass=5.0, seed=5, kT=1.0):
             if i < counts[k]:
                 order.append(k)
     tpls = [kinds[k] for k in order]
-    radii = [float(np.sqrt((t[0] ** 2).sum(1)).max()) for t in tpls]
-    centres = rsa_positions_radii(rng, np.array(ncell, dtype=np.float64), radii) if tpls else np.zeros((0, 3))
     quats = random_quaternions(rng, len(tpls))
+    centres = rsa_bodies(rng, np.array(ncell, dtype=np.float64), tpls, quats, gap) if tpls else np.zeros((0, 3))
     return make_system(ncell, density, tpls, centres, quats, rng, kT=kT)
 
 

@@ -376,24 +376,27 @@ def test_site_wca_crowded_bodies_fall_back_to_all_pairs():
 
 
 def test_site_wca_full_size_shapes_sampled():
-    """128^3 cells, 21M solvent, 2000 cubes, rods and dumbbells (326,670 sites):
-    after one FP32 step, the FP64 site-site forces and torques of sampled bodies
-    equal the oracle's at the same body poses."""
+    """128^3 cells, 21M solvent, 2000 cubes, rods and dumbbells (326,670 sites,
+    placed without overlap): after 40 FP32 steps the FP64 site-site forces and
+    torques of sampled bodies (some in contact) equal the oracle's at the same
+    body poses."""
     wl, par, _ = W.config(4)
     say("complex shapes full size")
     g = gpu_system(wl, par, prec="f32")
     del wl["x"], wl["v"]
     g.body_forces()
-    g.step(1)
+    g.step(40)
     assert g.status() == 0
     gd = g.download()[0]
+    touching = np.flatnonzero(np.abs(gd["F"]).sum(0) > 0)
+    say("%d bodies in contact" % len(touching))
+    assert len(touching) >= 4
+    idx = np.unique(np.concatenate([[0, 1999], touching[:: max(1, len(touching) // 6)][:6]]))
     wl2 = dict(wl, x=np.zeros((3, 0)), v=np.zeros((3, 0)), R=gd["R"], q=gd["q"])
     o = oracle.OracleSystem(wl2, par)
-    idx = np.array([0, 1, 2, 777, 1333, 1999])
     F, T, fl = o.site_wca_bodies(idx)
     assert fl == 0
     assert np.array_equal(F, gd["F"][:, idx]) and np.array_equal(T, gd["T"][:, idx])
-    assert np.count_nonzero(gd["F"]) > 0
 
 
 def test_full_size_suspension_bit_exact_few_steps():
