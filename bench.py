@@ -207,7 +207,7 @@ def main():
                    "form": "FP32 solvent/sites + int64 fixed-point cell sums + FP64 bodies; "
                            "HIP graph replays of the step"},
         "ms_per_step_median_replay": r32["ms_step_median"],
-        "roofline": {"bound": "hbm", "kernel": "k_collide_tiled<float,4> (collide + stream)",
+        "roofline": {"bound": "hbm", "kernel": "k_collide_tiled_f32 (collide + stream)",
                      "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                      "traffic": measured_traffic(), "avg_launch_us": r32["collide_ms"] * 1e3,
                      "algorithmic_bytes_per_launch": collide_bytes(N, S, 4)},

@@ -390,32 +390,6 @@ inline unsigned xcd_grid(int64_t ntiles)
     return (unsigned)(per * NXCD);
 }
 
-// Per-cell random draws: the collision axis and, with the thermostat, the
-// Gamma(3(n-1)/2) variate for the cell's member count n, stored as
-// draws[0..2][C] and draws[3][C].  Cells with fewer than two members draw
-// nothing.  (Philox4x64 is a long chain of quarter-rate 64-bit multiplies, so
-// the draws run in high-occupancy kernels rather than inside the collision.)
-__device__ __forceinline__ void draw_cell(const SysDev &s, uint64_t seed, double kT_cell, uint64_t step, int64_t gc,
-                                          int n, int mode, double *draws, uint32_t &st)
-{
-    const int64_t C = s.C;
-    const int r = find_sys(s.cell_off, s.nsys, gc);
-    const uint64_t cl = (uint64_t)(gc - s.cell_off[r]);
-    const uint64_t rep = s.replica0 + (uint64_t)r;
-    if (mode & 1) {
-        double nax[3];
-        st |= cell_axis(seed, step, cl, rep, nax);
-        draws[gc] = nax[0];
-        draws[C + gc] = nax[1];
-        draws[2 * C + gc] = nax[2];
-    }
-    if ((mode & 2) && kT_cell > 0.0 && n >= 2) {
-        double g;
-        st |= gamma_variate(seed, step, cl, rep, 0.5 * (double)(3 * (n - 1)), &g);
-        draws[3 * C + gc] = g;
-    }
-}
-
 // Binning: atomic counting sort by cell.
 //  1. k_bin_count: cell of every particle and its slot in the cell.  A block
 //     covers BIN_T * BIN_ITEMS consecutive particles; each wave keeps the
@@ -803,29 +777,126 @@ __device__ __forceinline__ uint32_t ident(const CollideArgs &A, int32_t k)
 // variates (needs this step's cell counts); 3: both.  Extra axis draws for
 // cells with fewer than two members are harmless: each draw is a pure
 // function of (seed, step, cell).
-__global__ void k_cell_draws(CollideArgs A, double *draws, int mode)
+// Per-cell random draws: the collision axis and, with the thermostat, the
+// Gamma(3(n-1)/2) variate for the cell's member count n, stored as
+// draws[0..2][C] and draws[3][C] (cells with fewer than two members draw no
+// gamma variate).  Philox4x64 is a long chain of quarter-rate 64-bit
+// multiplies, so the draws run in their own blocks rather than inside the
+// collision.
+//
+// Lane g of nlanes takes cells g, g + nlanes, ...; each loop iteration makes
+// one Philox call for the lane's current draw (the axis, then, with mode & 2,
+// the thermostat gamma variate) and moves on as soon as it is accepted, so
+// the axis and gamma rejections of a wave share one loop.  Each cell uses
+// calls 0, 1, ... of its own streams in order, exactly as cell_axis and
+// gamma_variate do.  One cell per lane measured best: the Philox call is a
+// long dependent chain, and longer queues per lane leave too few waves to
+// hide it.
+struct DrawLane {
+    int64_t cell;
+    uint64_t cl, rep;
+    int phase;  // 0 axis, 1 gamma
+    int call;
+    bool want_axis, want_gamma;
+    double gd, gc;  // Marsaglia-Tsang d and c
+};
+
+__device__ __forceinline__ void draw_lane_start(const CollideArgs &A, int mode, DrawLane &L)
 {
     const SysDev &s = A.s;
-    uint32_t st = 0;
-    const uint64_t step = *A.d_step;
-    for (int64_t gc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gc < s.C; gc += (int64_t)gridDim.x * blockDim.x) {
-        const int n = (mode & 2) ? A.cell_start[gc + 1] - A.cell_start[gc] : 0;
-        draw_cell(s, A.seed, A.kT_cell, step, gc, n, mode, draws, st);
+    const int r = find_sys(s.cell_off, s.nsys, L.cell);
+    L.cl = (uint64_t)(L.cell - s.cell_off[r]);
+    L.rep = s.replica0 + (uint64_t)r;
+    L.call = 0;
+    L.want_axis = (mode & 1) != 0;
+    const int n = (mode & 2) ? A.cell_start[L.cell + 1] - A.cell_start[L.cell] : 0;
+    L.want_gamma = (mode & 2) && A.kT_cell > 0.0 && n >= 2;
+    if (L.want_gamma) {
+        const double k = 0.5 * (double)(3 * (n - 1));
+        L.gd = k - 1.0 / 3.0;
+        L.gc = 1.0 / sqrt(9.0 * L.gd);
     }
+    L.phase = L.want_axis ? 0 : 1;
+}
+
+__device__ void draw_cells(const CollideArgs &A, double *draws, int mode, int64_t g, int64_t nlanes, uint32_t &st)
+{
+    const SysDev &s = A.s;
+    const int64_t C = s.C;
+    const uint64_t step = *A.d_step;
+    DrawLane L;
+    L.cell = g;
+    if (L.cell < C) draw_lane_start(A, mode, L);
+    while (L.cell < C) {
+        bool done = false;
+        if (L.phase == 0 || L.want_gamma) {
+            const Words w = rng_draw(A.seed, L.phase == 0 ? RNG_AXIS : RNG_THERMO, step, L.cl, L.rep,
+                                     (uint64_t)L.call);
+            L.call += 1;
+            if (L.phase == 0) {
+                double nax[3];
+                bool ok = axis_from_words(w, nax);
+                if (!ok && L.call == RNG_MAX_CALLS) {
+                    nax[0] = 0.0; nax[1] = 0.0; nax[2] = 1.0;
+                    st |= ST_RNGLOOP;
+                    ok = true;
+                }
+                if (ok) {
+                    draws[L.cell] = nax[0];
+                    draws[C + L.cell] = nax[1];
+                    draws[2 * C + L.cell] = nax[2];
+                    L.phase = 1;
+                    L.call = 0;
+                    done = !L.want_gamma;
+                }
+            } else {
+                double gv;
+                bool ok = gamma_from_words(w, L.gd, L.gc, &gv);
+                if (!ok && L.call == RNG_MAX_CALLS) {
+                    gv = L.gd;
+                    st |= ST_RNGLOOP;
+                    ok = true;
+                }
+                if (ok) {
+                    draws[3 * C + L.cell] = gv;
+                    done = true;
+                }
+            }
+        } else {
+            done = true;  // no draw wanted for this cell
+        }
+        if (done) {
+            L.cell += nlanes;
+            if (L.cell < C) draw_lane_start(A, mode, L);
+        }
+    }
+}
+
+// Standalone per-cell draws.  mode 1: the axis of every cell (independent of
+// the binning); 2: the gamma variates (needs this step's cell counts); 3:
+// both.  Extra axis draws for cells with fewer than two members are harmless:
+// each draw is a pure function of (seed, step, cell).
+constexpr int DRAW_CELLS_PER_LANE = 1;
+
+__global__ __launch_bounds__(BIN_T) void k_cell_draws(CollideArgs A, double *draws, int mode)
+{
+    uint32_t st = 0;
+    draw_cells(A, draws, mode, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, st);
     flag(A.status, st);
 }
 
-// Scatter (blocks [0, nscatter)) fused with the per-cell draws (the other
-// blocks): independent work, one launch; the draws' ALU work overlaps the
-// scatter's memory traffic.
+// Per-cell draws (blocks [0, ndraw)) fused with the scatter (the other
+// blocks): independent work, one launch.  The draw blocks come first so their
+// ALU work starts early and overlaps the scatter's memory traffic.
 __global__ __launch_bounds__(BIN_T) void k_scatter_draws(int64_t NT, const int32_t *cellid, const int32_t *slot,
-                                                         int32_t *perm, int nscatter, CollideArgs A, double *draws)
+                                                         int32_t *perm, int ndraw, CollideArgs A, double *draws)
 {
     uint32_t st = 0;
-    if ((int)blockIdx.x < nscatter) {
+    if ((int)blockIdx.x >= ndraw) {
+        const int64_t b = (int64_t)blockIdx.x - ndraw;
 #pragma unroll
         for (int j = 0; j < BIN_ITEMS; ++j) {
-            const int64_t k = (int64_t)blockIdx.x * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
+            const int64_t k = b * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
             if (k < NT) {
                 const int64_t pos = perm_pos(A.cell_start, A.site_start, A.s.N, k, cellid[k], slot[k]);
                 if (pos >= 0 && pos < NT) perm[pos] = (int32_t)k;
@@ -833,11 +904,7 @@ __global__ __launch_bounds__(BIN_T) void k_scatter_draws(int64_t NT, const int32
             }
         }
     } else {
-        const SysDev &s = A.s;
-        const uint64_t step = *A.d_step;
-        const int64_t stride = (int64_t)(gridDim.x - nscatter) * blockDim.x;
-        for (int64_t gc = (int64_t)(blockIdx.x - nscatter) * blockDim.x + threadIdx.x; gc < s.C; gc += stride)
-            draw_cell(s, A.seed, A.kT_cell, step, gc, A.cell_start[gc + 1] - A.cell_start[gc], 3, draws, st);
+        draw_cells(A, draws, 3, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)ndraw * blockDim.x, st);
     }
     flag(A.status, st);
 }
@@ -1112,9 +1179,10 @@ __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
     TileLayout L;
     size_t o = 0;
     L.cs = o; o += align16(sizeof(int) * (size_t)(cpb + 1));
-    L.idx = o; o += align16(sizeof(int) * (size_t)cap);
+    // member indices and velocities are staged for the FP64 canonical sums only
+    L.idx = o; o += align16(f64 ? sizeof(int) * (size_t)cap : 0);
     L.cl = o; o += align16(sizeof(uint16_t) * (size_t)cap);
-    L.v = o; o += align16((f64 ? 8 : 4) * 3 * (size_t)cap);
+    L.v = o; o += align16(f64 ? 8 * 3 * (size_t)cap : 0);
     L.keyacc = o; o += align16(f64 ? sizeof(uint64_t) * (size_t)cap : sizeof(long long) * 5 * (size_t)cpb);
     L.par = o; o += align16(f64 ? sizeof(double) * 13 * (size_t)cpb : sizeof(float) * 12 * (size_t)cpb);
     L.r = o; o += align16(sizeof(int) * (size_t)cpb);
@@ -1125,8 +1193,8 @@ __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
 
 
 template <typename Real, int ITEMS>
-__global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg T, Real *v, Real *vs, Real *xstream,
-                                                          SolvOut<Real> O)
+__device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg &T, Real *v, Real *vs, Real *xstream,
+                                             const SolvOut<Real> &O)
 {
     constexpr bool F64 = sizeof(Real) == 8;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1210,9 +1278,9 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
         const int i = t + j * TILE_T;
         if (i < nm) {
             const int32_t k = kk[j];
-            s_idx[i] = k;
-            s_v[i] = va[j][0]; s_v[cap + i] = va[j][1]; s_v[2 * cap + i] = va[j][2];
             if constexpr (F64) {
+                s_idx[i] = k;
+                s_v[i] = va[j][0]; s_v[cap + i] = va[j][1]; s_v[2 * cap + i] = va[j][2];
                 s_key[i] = ((uint64_t)ident(A, k) << 32) | (uint32_t)i;
             } else {
                 // exact int64 fixed-point terms, summed per cell with LDS
@@ -1359,6 +1427,21 @@ __global__ __launch_bounds__(TILE_T) void k_collide_tiled(CollideArgs A, TileCfg
         }
     }
     flag(A.status, st);
+}
+
+// FP32 kernel: at most 80 VGPRs (six waves per SIMD to hide the gather
+// latency; measured faster than five).  FP64 keeps the compiler's allocation
+// (a cap spills).
+__global__ __launch_bounds__(TILE_T) __attribute__((amdgpu_waves_per_eu(6))) void k_collide_tiled_f32(
+    CollideArgs A, TileCfg T, float *v, float *vs, float *xstream, SolvOut<float> O)
+{
+    collide_tile<float, ITEMS_F32>(A, T, v, vs, xstream, O);
+}
+
+__global__ __launch_bounds__(TILE_T) void k_collide_tiled_f64(CollideArgs A, TileCfg T, double *v, double *vs,
+                                                              double *xstream, SolvOut<double> O)
+{
+    collide_tile<double, ITEMS_F64>(A, T, v, vs, xstream, O);
 }
 
 // ---------------------------------------------------------------------------
@@ -2485,10 +2568,16 @@ static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bod
     return A;
 }
 
+static unsigned draw_blocks(int64_t C)
+{
+    const int64_t lanes = (C + DRAW_CELLS_PER_LANE - 1) / DRAW_CELLS_PER_LANE;
+    return grid_for(lanes > 0 ? lanes : 1, BIN_T);
+}
+
 static void launch_draws(const Ctx &c, hipStream_t st, const CollideArgs &A, int mode)
 {
     if (mode == 2 && !(A.kT_cell > 0.0)) return;
-    hipLaunchKernelGGL(k_cell_draws, dim3(grid_for(c.sys->n_cells, 256)), dim3(256), 0, st, A,
+    hipLaunchKernelGGL(k_cell_draws, dim3(draw_blocks(c.sys->n_cells)), dim3(BIN_T), 0, st, A,
                        at<double>(c.ws, c.L.draws), mode);
 }
 
@@ -2503,12 +2592,12 @@ static void launch_collide(const Ctx &c, hipStream_t st, const CollideArgs &A, v
     const size_t lds = tile_layout(f64, T.cpb, T.cap).end;
     if (f64) {
         const SolvOut<double> O{(double *)x_out, (double *)v_out, tag_out};
-        hipLaunchKernelGGL((k_collide_tiled<double, ITEMS_F64>), grid, dim3(TILE_T), lds, st, A, T, (double *)v,
-                           (double *)vs, (double *)x_stream, O);
+        hipLaunchKernelGGL(k_collide_tiled_f64, grid, dim3(TILE_T), lds, st, A, T, (double *)v, (double *)vs,
+                           (double *)x_stream, O);
     } else {
         const SolvOut<float> O{(float *)x_out, (float *)v_out, tag_out};
-        hipLaunchKernelGGL((k_collide_tiled<float, ITEMS_F32>), grid, dim3(TILE_T), lds, st, A, T, (float *)v,
-                           (float *)vs, (float *)x_stream, O);
+        hipLaunchKernelGGL(k_collide_tiled_f32, grid, dim3(TILE_T), lds, st, A, T, (float *)v, (float *)vs,
+                           (float *)x_stream, O);
     }
 }
 
@@ -2599,9 +2688,9 @@ static void launch_scatter_draws(const Ctx &c, hipStream_t st, const CollideArgs
 {
     const int64_t NT = c.sys->n_solvent + c.sys->n_sites;
     const int nsc = (int)((NT + BIN_CHUNK - 1) / BIN_CHUNK);
-    const int ndr = (int)grid_for(c.sys->n_cells, BIN_T, 8192);
+    const int ndr = (int)draw_blocks(c.sys->n_cells);
     hipLaunchKernelGGL(k_scatter_draws, dim3((unsigned)(nsc + ndr)), dim3(BIN_T), 0, st, NT,
-                       at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot), at<int32_t>(c.ws, c.L.perm), nsc,
+                       at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot), at<int32_t>(c.ws, c.L.perm), ndr,
                        A, at<double>(c.ws, c.L.draws));
 }
 
