@@ -131,6 +131,13 @@ typedef struct {
     int32_t thermalize;  /* 1: Eq. (7) thermalization; 0: rigid velocities only */
     int32_t fuse_stream; /* 1: stream the solvent inside mpcd_collide          */
     mpcd_wca wca;
+    /* Forced flow (sedimentation, Sec. III.B): every body feels the constant
+     * force f_ext at its centre, and every solvent particle the constant
+     * acceleration g, streamed as x + v dt + h with h = (dt/2)(g dt), then
+     * v + g dt.  Choosing g = -B f_ext / (N m) makes the system force free.
+     * All zero: no forcing. */
+    double g[3];
+    double f_ext[3];
 } mpcd_params;
 
 /* All buffers of one step (for mpcd_step and graph capture). */
@@ -178,9 +185,11 @@ int mpcd_workspace_offsets(const mpcd_sys *sys, int64_t out[8]);
 /* Zero the counters and the status word of a fresh workspace. */
 int mpcd_ws_init(void *stream, const mpcd_sys *sys, void *ws, size_t ws_bytes);
 
-/* Ballistic streaming, Sec. II.A: x <- wrap(x + v dt) per component, one
- * periodic correction.  x, v: [3N] (prec). */
-int mpcd_stream(void *stream, const mpcd_sys *sys, void *x, const void *v, double dt,
+/* Streaming, Sec. II.A: x <- wrap(x + v dt) per component, one periodic
+ * correction.  g (host, 3 doubles, or NULL): a constant acceleration (forced
+ * flow, Sec. III.B), x <- wrap((x + v dt) + (dt/2)(g dt)), v <- v + g dt.
+ * x, v: [3N] (prec); v is written only when g is non-zero. */
+int mpcd_stream(void *stream, const mpcd_sys *sys, void *x, void *v, double dt, const double *g,
                 void *ws, size_t ws_bytes);
 
 /* Random grid shift and cell binning, Sec. II.A.  Shift s in [-a/2, a/2)^3 per
@@ -244,12 +253,14 @@ int sites_to_body(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, 
  * axes 3,2,1,2,3 for dt/2, dt/2, dt, dt/2, dt/2; new F, T from Eq. (1); half
  * kick.  J, K may be NULL (no impulse). */
 int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const double *J,
-                   const double *K, const mpcd_wca *wca, double dt, void *ws, size_t ws_bytes);
+                   const double *K, const mpcd_wca *wca, const double *f_ext, double dt, void *ws,
+                   size_t ws_bytes);
 
 /* Evaluate F, T at the current positions (Eq. (1)); call once before the first
- * step so the first half kick uses the right force. */
+ * step so the first half kick uses the right force.  f_ext (host, 3 doubles,
+ * or NULL): a constant force added at every body centre (Sec. III.B). */
 int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca,
-                void *ws, size_t ws_bytes);
+                const double *f_ext, void *ws, size_t ws_bytes);
 
 /* Storage reorder: permute the solvent (x, v and identity tags, [3N], [3N],
  * [N]) into the order of the last mpcd_bin (grouped by cell), so that the

@@ -57,7 +57,8 @@ class OrcPar(C.Structure):
                 ("kT", C.c_double), ("kT_cell", C.c_double),
                 ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("thermalize", C.c_int32), ("wca_mode", C.c_int32),
-                ("eps", C.c_double), ("sigma", C.c_double), ("delta", C.c_double)]
+                ("eps", C.c_double), ("sigma", C.c_double), ("delta", C.c_double),
+                ("g", C.c_double * 3), ("f_ext", C.c_double * 3)]
 
 
 def lib():
@@ -103,6 +104,8 @@ def lib():
         L.orc_wca_energy.argtypes = [sysp, parp]
         L.orc_body_integrate.restype = C.c_uint32
         L.orc_body_integrate.argtypes = [sysp, parp, dp, dp]
+        L.orc_stream_forced.restype = C.c_uint32
+        L.orc_stream_forced.argtypes = [sysp, C.c_double, dp]
         L.orc_stream.restype = C.c_uint32
         L.orc_stream.argtypes = [sysp, C.c_double]
         L.orc_step.restype = C.c_uint32
@@ -175,7 +178,9 @@ def make_par(p: dict, replica: int = 0) -> OrcPar:
                   kT_cell=p["kT_cell"], seed=p["seed"], replica=replica,
                   thermalize=int(p.get("thermalize", 1)), wca_mode=int(wca.get("mode", 0)),
                   eps=float(wca.get("eps", 0.0)), sigma=float(wca.get("sigma", 0.0)),
-                  delta=float(wca.get("delta", 0.0)))
+                  delta=float(wca.get("delta", 0.0)),
+                  g=(C.c_double * 3)(*[float(a) for a in p.get("g", (0.0, 0.0, 0.0))]),
+                  f_ext=(C.c_double * 3)(*[float(a) for a in p.get("f_ext", (0.0, 0.0, 0.0))]))
 
 
 class OracleSystem:
@@ -280,8 +285,12 @@ class OracleSystem:
             J = np.zeros((3, 1)); K = np.zeros((3, 1))
         return lib().orc_body_integrate(C.byref(self._sys), C.byref(self.par), _p(J), _p(K))
 
-    def stream(self, dt=None):
-        return lib().orc_stream(C.byref(self._sys), self.par.dt if dt is None else dt)
+    def stream(self, dt=None, g=None):
+        dt = self.par.dt if dt is None else dt
+        if g is None:
+            return lib().orc_stream(C.byref(self._sys), dt)
+        gg = np.ascontiguousarray(g, dtype=np.float64)
+        return lib().orc_stream_forced(C.byref(self._sys), dt, _p(gg))
 
     def step(self, step):
         return lib().orc_step(C.byref(self._sys), C.byref(self.par), step)

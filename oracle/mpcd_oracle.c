@@ -387,7 +387,11 @@ typedef struct {
     int32_t thermalize;  /* 1: Eq. (7); 0: naive scheme (rigid velocities only) */
     int32_t wca_mode;    /* 0 off, 1 between body centres, 2 between sites of different bodies */
     double eps, sigma, delta;
+    double g[3];         /* constant acceleration of every solvent particle      */
+    double f_ext[3];     /* constant force on every body, at its centre          */
 } orc_par;
+
+static int forced(const double a[3]) { return a[0] != 0.0 || a[1] != 0.0 || a[2] != 0.0; }
 
 static double box_len(const orc_sys *s, int k) { return (double)s->n[k] * s->a; }
 
@@ -698,13 +702,26 @@ static uint32_t site_wca_body(const orc_sys *s, const orc_par *par, const double
  * bodies; the force on site j is summed over the other bodies in ascending
  * index and their sites in ascending index, then F = sum_j f_j and
  * T = sum_j d_j x f_j in site order. */
+static uint32_t wca_forces(orc_sys *s, const orc_par *par);
+
 uint32_t orc_body_forces(orc_sys *s, const orc_par *par)
 {
     uint32_t flags = 0;
-    int64_t B = s->B, S = s->S;
+    int64_t B = s->B;
     for (int64_t i = 0; i < B; ++i)
         for (int k = 0; k < 3; ++k) { s->F[k * B + i] = 0.0; s->T[k * B + i] = 0.0; }
-    if (par->wca_mode != 1 && par->wca_mode != 2) return 0;
+    if (par->wca_mode == 1 || par->wca_mode == 2) flags = wca_forces(s, par);
+    /* a constant external force at the body centre (no torque), Sec. III.B */
+    if (forced(par->f_ext))
+        for (int64_t i = 0; i < B; ++i)
+            for (int k = 0; k < 3; ++k) s->F[k * B + i] = s->F[k * B + i] + par->f_ext[k];
+    return flags;
+}
+
+static uint32_t wca_forces(orc_sys *s, const orc_par *par)
+{
+    uint32_t flags = 0;
+    int64_t B = s->B, S = s->S;
     double rc = par->delta + 0x1.1f59ac3c7d6c0p+0 * par->sigma;
     double rc2 = rc * rc;
     if (par->wca_mode == 1) {
@@ -887,17 +904,33 @@ uint32_t orc_body_integrate(orc_sys *s, const orc_par *par, const double *J, con
 
 /* ------------------------------------------------------------------------- */
 /* (a7) Ballistic streaming of the solvent with periodic wrap (Sec. II.A).    */
-uint32_t orc_stream(orc_sys *s, double dt)
+/* With a constant acceleration g (forced flow, Sec. III.B), Newton's
+ * equations over dt give x + v dt + g dt^2 / 2 and v + g dt, evaluated as
+ * (x + v dt) + h with h = (dt / 2)(g dt), then v + g dt. */
+uint32_t orc_stream_forced(orc_sys *s, double dt, const double g[3])
 {
     uint32_t flags = 0;
+    int on = forced(g);
     for (int k = 0; k < 3; ++k) {
         double L = box_len(s, k);
+        double gdt = g[k] * dt;
+        double h = (0.5 * dt) * gdt;
         for (int64_t i = 0; i < s->N; ++i) {
             double y = s->x[k * s->N + i] + s->v[k * s->N + i] * dt;
+            if (on) {
+                y = y + h;
+                s->v[k * s->N + i] = s->v[k * s->N + i] + gdt;
+            }
             s->x[k * s->N + i] = wrap1(y, L, &flags);
         }
     }
     return flags;
+}
+
+uint32_t orc_stream(orc_sys *s, double dt)
+{
+    const double zero[3] = {0.0, 0.0, 0.0};
+    return orc_stream_forced(s, dt, zero);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -920,7 +953,7 @@ uint32_t orc_step(orc_sys *s, const orc_par *par, uint64_t step)
     flags |= orc_bin(s, shift, cell, cell_start, members);
     flags |= orc_collide(s, par, step, cell_start, members, NULL);
     flags |= orc_sites_to_body(s, J, K);
-    flags |= orc_stream(s, par->dt);
+    flags |= orc_stream_forced(s, par->dt, par->g);
     flags |= orc_body_integrate(s, par, J, K);
 
     free(cell); free(cell_start); free(members); free(J); free(K);

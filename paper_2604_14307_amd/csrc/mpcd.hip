@@ -344,8 +344,40 @@ __global__ void k_advance(uint64_t *d_step)
 // ---------------------------------------------------------------------------
 // (a7) streaming
 
+// Constant solvent acceleration g over one streaming interval (forced flow,
+// Sec. III.B): x + v dt + h with h = (dt / 2)(g dt), then v + g dt.
+struct Forcing {
+    double gdt[3], h[3];
+    int on;
+};
+
+Forcing make_forcing(const double *g, double dt)
+{
+    Forcing F;
+    F.on = g && (g[0] != 0.0 || g[1] != 0.0 || g[2] != 0.0);
+    for (int k = 0; k < 3; ++k) {
+        F.gdt[k] = F.on ? g[k] * dt : 0.0;
+        F.h[k] = (0.5 * dt) * F.gdt[k];
+    }
+    return F;
+}
+
+// A constant force at every body centre (no torque).
+struct ExtForce {
+    double f[3];
+    int on;
+};
+
+ExtForce make_ext(const double *f)
+{
+    ExtForce E;
+    E.on = f && (f[0] != 0.0 || f[1] != 0.0 || f[2] != 0.0);
+    for (int k = 0; k < 3; ++k) E.f[k] = E.on ? f[k] : 0.0;
+    return E;
+}
+
 template <typename Real>
-__global__ void k_stream(SysDev s, Real *x, const Real *v, double dt, uint32_t *status)
+__global__ void k_stream(SysDev s, Real *x, Real *v, double dt, Forcing F, uint32_t *status)
 {
     uint32_t st = 0;
     const Real dtr = (Real)dt;
@@ -355,7 +387,11 @@ __global__ void k_stream(SysDev s, Real *x, const Real *v, double dt, uint32_t *
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const Real L = (Real)((double)s.ncell[3 * r + k] * s.a);
-            const Real y = x[k * s.N + i] + v[k * s.N + i] * dtr;
+            Real y = x[k * s.N + i] + v[k * s.N + i] * dtr;
+            if (F.on) {
+                y = y + (Real)F.h[k];
+                v[k * s.N + i] = v[k * s.N + i] + (Real)F.gdt[k];
+            }
             x[k * s.N + i] = Prec<Real>::wrap(y, L, st);
         }
     }
@@ -764,6 +800,7 @@ struct CollideArgs {
     const uint64_t *d_step;
     uint32_t *status;
     uint64_t *advance_step;  // when set, block 0 advances the step counter (graph schedule)
+    Forcing F;               // solvent acceleration applied by the fused streaming
 };
 
 // Identity order key of particle k: solvent tag (or index), sites N_total + j.
@@ -1000,7 +1037,12 @@ __device__ void cell_stream_global(const CollideArgs &A, int64_t gc, const Membe
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
-            xd[d * N] = RealOps<Real>::wrap(x[d * N + k] + vel(i, k, d) * dtr, L, st);
+            Real y = x[d * N + k] + vel(i, k, d) * dtr;
+            if (A.F.on) {
+                y = y + (Real)A.F.h[d];
+                vel(i, k, d) = vel(i, k, d) + (Real)A.F.gdt[d];
+            }
+            xd[d * N] = RealOps<Real>::wrap(y, L, st);
         }
     }
 }
@@ -1413,8 +1455,14 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
-                O.x[d * N + dst] = RealOps<Real>::wrap(xo[j][d] + vn[d] * dtr, L, st);
-                O.v[d * N + dst] = vn[d];
+                Real y = xo[j][d] + vn[d] * dtr;
+                Real vo = vn[d];
+                if (A.F.on) {
+                    y = y + (Real)A.F.h[d];
+                    vo = vo + (Real)A.F.gdt[d];
+                }
+                O.x[d * N + dst] = RealOps<Real>::wrap(y, L, st);
+                O.v[d * N + dst] = vo;
             }
             O.tag[dst] = tg[j];
         } else if (xstream) {
@@ -1422,7 +1470,12 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
-                xstream[d * N + k] = RealOps<Real>::wrap(xo[j][d] + vn[d] * dtr, L, st);
+                Real y = xo[j][d] + vn[d] * dtr;
+                if (A.F.on) {
+                    y = y + (Real)A.F.h[d];
+                    v[d * N + k] = vn[d] + (Real)A.F.gdt[d];
+                }
+                xstream[d * N + k] = RealOps<Real>::wrap(y, L, st);
             }
         }
     }
@@ -1939,8 +1992,8 @@ __global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd,
 // then advances the step counter (last kernel of a step).
 constexpr int FRC_T = 64;
 
-__global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid, double dt,
-                                                       int kick, uint64_t *advance_step, uint32_t *status)
+__global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid, ExtForce E,
+                                                       double dt, int kick, uint64_t *advance_step, uint32_t *status)
 {
     constexpr int NCAND = 27 * GRID_K;
     __shared__ double sf[3][FRC_T + 1];
@@ -2117,6 +2170,7 @@ __global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpc
         }
     }
     if (t < 3) {
+        if (E.on) f = f + E.f[t];  // external force at the centre
         fsh[t] = f;
         bd.force[t * B + i] = f;
         bd.torque[t * B + i] = 0.0;
@@ -2158,8 +2212,8 @@ __global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpc
 __device__ __forceinline__ double min_image(double t, double L) { return t - L * rint(t / L); }
 
 __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid,
-                                                        SiteFrames fr, double dt, int kick, uint64_t *advance_step,
-                                                        uint32_t *status)
+                                                        SiteFrames fr, ExtForce E, double dt, int kick,
+                                                        uint64_t *advance_step, uint32_t *status)
 {
     constexpr int NCAND = 27 * GRID_K;
     __shared__ uint32_t s_h[27];
@@ -2307,7 +2361,7 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
         ordered_add(sh, (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T), acc);
         __syncthreads();
     }
-    if (t < 6) fT[t] = acc;
+    if (t < 6) fT[t] = (E.on && t < 3) ? acc + E.f[t] : acc;  // external force at the centre
     __syncthreads();
     if (t == 0) {
 #pragma unroll
@@ -2458,7 +2512,7 @@ int mpcd_ws_init(void *stream, const mpcd_sys *sys, void *ws, size_t ws_bytes)
     return launch_check();
 }
 
-int mpcd_stream(void *stream, const mpcd_sys *sys, void *x, const void *v, double dt, void *ws,
+int mpcd_stream(void *stream, const mpcd_sys *sys, void *x, void *v, double dt, const double *g, void *ws,
                 size_t ws_bytes)
 {
     TRY(check_sys(sys));
@@ -2469,12 +2523,13 @@ int mpcd_stream(void *stream, const mpcd_sys *sys, void *x, const void *v, doubl
     const Layout L = layout_of(sys);
     const SysDev sd = make_sysdev(sys);
     hipStream_t st = (hipStream_t)stream;
-    const unsigned g = grid_for(sys->n_solvent, 256);
+    const unsigned gr = grid_for(sys->n_solvent, 256);
+    const Forcing F = make_forcing(g, dt);
     if (sys->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_stream<double>, dim3(g), dim3(256), 0, st, sd, (double *)x, (const double *)v, dt,
+        hipLaunchKernelGGL(k_stream<double>, dim3(gr), dim3(256), 0, st, sd, (double *)x, (double *)v, dt, F,
                            at<uint32_t>(ws, L.status));
     else
-        hipLaunchKernelGGL(k_stream<float>, dim3(g), dim3(256), 0, st, sd, (float *)x, (const float *)v, dt,
+        hipLaunchKernelGGL(k_stream<float>, dim3(gr), dim3(256), 0, st, sd, (float *)x, (float *)v, dt, F,
                            at<uint32_t>(ws, L.status));
     return launch_check();
 }
@@ -2565,6 +2620,7 @@ static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bod
     A.d_step = d_step;
     A.status = c.status;
     A.advance_step = advance;
+    A.F = make_forcing(nullptr, dt);
     return A;
 }
 
@@ -2710,17 +2766,18 @@ static void launch_transfer_first(const Ctx &c, hipStream_t st, const mpcd_bodie
                            at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, fr, c.status);
 }
 
-static void launch_forces(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca, double dt,
-                          int kick, uint64_t *advance)
+static void launch_forces(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca,
+                          const double *f_ext, double dt, int kick, uint64_t *advance)
 {
+    const ExtForce E = make_ext(f_ext);
     if (c.sys->n_bodies == 0) return;
     if (wca.mode == 2)
         hipLaunchKernelGGL(k_site_forces, dim3((unsigned)c.sys->n_bodies), dim3(BODY_T), 0, st, c.sd,
-                           make_bodydev(bodies), wca, body_grid(c, wca), site_frames(c, wca), dt, kick, advance,
+                           make_bodydev(bodies), wca, body_grid(c, wca), site_frames(c, wca), E, dt, kick, advance,
                            c.status);
     else
         hipLaunchKernelGGL(k_body_forces, dim3((unsigned)c.sys->n_bodies), dim3(FRC_T), 0, st, c.sd,
-                           make_bodydev(bodies), wca, body_grid(c, wca), dt, kick, advance, c.status);
+                           make_bodydev(bodies), wca, body_grid(c, wca), E, dt, kick, advance, c.status);
 }
 
 static void launch_reorder(const Ctx &c, hipStream_t st, void *x, void *v, int32_t *tag)
@@ -2906,8 +2963,8 @@ static int wca_check(const mpcd_wca *wca)
     return MPCD_OK;
 }
 
-int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca, void *ws,
-                size_t ws_bytes)
+int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca,
+                const double *f_ext, void *ws, size_t ws_bytes)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
@@ -2915,12 +2972,13 @@ int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, co
     TRY(wca_check(wca));
     const Ctx c = make_ctx(sys, ws);
     launch_body_grid(c, (hipStream_t)stream, bodies, *wca);
-    launch_forces(c, (hipStream_t)stream, bodies, *wca, 0.0, 0, nullptr);
+    launch_forces(c, (hipStream_t)stream, bodies, *wca, f_ext, 0.0, 0, nullptr);
     return launch_check();
 }
 
 int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const double *J,
-                   const double *K, const mpcd_wca *wca, double dt, void *ws, size_t ws_bytes)
+                   const double *K, const mpcd_wca *wca, const double *f_ext, double dt, void *ws,
+                   size_t ws_bytes)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
@@ -2934,7 +2992,7 @@ int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies,
     hipLaunchKernelGGL(k_body_first, dim3(grid_for(sys->n_bodies, 64)), dim3(64), 0, st, c.sd, make_bodydev(bodies),
                        J, K, dt, c.status);
     launch_body_grid(c, st, bodies, *wca);
-    launch_forces(c, st, bodies, *wca, dt, 1, nullptr);
+    launch_forces(c, st, bodies, *wca, f_ext, dt, 1, nullptr);
     return launch_check();
 }
 
@@ -2976,20 +3034,21 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
     hipStream_t st = (hipStream_t)stream;
     launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca);
     launch_scan(c, st);
-    const CollideArgs A = collide_args(c, a->tag, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed, a->d_step, p.dt,
-                                       nullptr);
+    CollideArgs A = collide_args(c, a->tag, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed, a->d_step, p.dt,
+                                 nullptr);
+    if (p.fuse_stream) A.F = make_forcing(p.g, p.dt);
     launch_scatter_draws(c, st, A);
     if (a->v_out)
         launch_collide(c, st, A, a->v, a->vs, a->x, a->x_out, a->v_out, a->tag_out);
     else
         launch_collide(c, st, A, a->v, a->vs, p.fuse_stream ? a->x : nullptr);
-    if (!p.fuse_stream) TRY(mpcd_stream(stream, s, a->x, a->v, p.dt, a->ws, a->ws_bytes));
+    if (!p.fuse_stream) TRY(mpcd_stream(stream, s, a->x, a->v, p.dt, p.g, a->ws, a->ws_bytes));
     if (s->n_bodies == 0) {
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a->d_step);
         return launch_check();
     }
     launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt, p.wca);
-    launch_forces(c, st, &a->bodies, p.wca, p.dt, 1, a->d_step);
+    launch_forces(c, st, &a->bodies, p.wca, p.f_ext, p.dt, 1, a->d_step);
     return launch_check();
 }
 

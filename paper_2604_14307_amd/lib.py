@@ -46,7 +46,7 @@ class MpcdWca(C.Structure):
 class MpcdParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("cos_a", C.c_double), ("sin_a", C.c_double), ("kT", C.c_double),
                 ("kT_cell", C.c_double), ("seed", C.c_uint64), ("thermalize", C.c_int32),
-                ("fuse_stream", C.c_int32), ("wca", MpcdWca)]
+                ("fuse_stream", C.c_int32), ("wca", MpcdWca), ("g", C.c_double * 3), ("f_ext", C.c_double * 3)]
 
 
 class MpcdStepArgs(C.Structure):
@@ -77,15 +77,15 @@ def load(path: str = LIB_PATH):
         "mpcd_workspace_bytes": (sz, [sp]),
         "mpcd_workspace_offsets": (C.c_int, [sp, C.POINTER(C.c_int64)]),
         "mpcd_ws_init": (C.c_int, [vp, sp, vp, sz]),
-        "mpcd_stream": (C.c_int, [vp, sp, vp, vp, dbl, vp, sz]),
+        "mpcd_stream": (C.c_int, [vp, sp, vp, vp, dbl, C.POINTER(dbl), vp, sz]),
         "mpcd_bin": (C.c_int, [vp, sp, vp, vp, bp, u64, vp, vp, sz]),
         "mpcd_collide": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, u64, vp, vp, sz, vp, dbl]),
         "mpcd_cell_draws": (C.c_int, [vp, sp, dbl, u64, vp, vp, sz]),
         "mpcd_collide_drawn": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, vp, vp, sz, vp, dbl, vp, vp, vp]),
         "sites_thermalize": (C.c_int, [vp, sp, bp, dbl, i32, u64, vp, vp, vp, vp, sz]),
         "sites_to_body": (C.c_int, [vp, sp, bp, vp, vp, sz, vp, vp]),
-        "body_integrate": (C.c_int, [vp, sp, bp, vp, vp, wp, dbl, vp, sz]),
-        "body_forces": (C.c_int, [vp, sp, bp, wp, vp, sz]),
+        "body_integrate": (C.c_int, [vp, sp, bp, vp, vp, wp, C.POINTER(dbl), dbl, vp, sz]),
+        "body_forces": (C.c_int, [vp, sp, bp, wp, C.POINTER(dbl), vp, sz]),
         "mpcd_advance_step": (C.c_int, [vp, vp]),
         "mpcd_step": (C.c_int, [vp, C.POINTER(MpcdStepArgs)]),
         "mpcd_reorder": (C.c_int, [vp, sp, vp, vp, vp, vp, sz]),

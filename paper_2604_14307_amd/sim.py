@@ -143,7 +143,8 @@ class GPUSystem:
         p = self.params
         par = L.MpcdParams(dt=p["dt"], cos_a=p["cos_a"], sin_a=p["sin_a"], kT=p["kT"], kT_cell=p["kT_cell"],
                            seed=p["seed"], thermalize=int(p.get("thermalize", 1)),
-                           fuse_stream=int(self.fuse_stream), wca=self.cwca)
+                           fuse_stream=int(self.fuse_stream), wca=self.cwca, g=self._vec("g"),
+                           f_ext=self._vec("f_ext"))
         out = self.out_of_place
         self._args = L.MpcdStepArgs(sys=C.pointer(self.csys), bodies=self.cbodies, x=_ptr(self.x), v=_ptr(self.v),
                                     tag=_ptr(self.tag), xs=_ptr(self.xs), vs=_ptr(self.vs), J=_ptr(self.J),
@@ -153,6 +154,15 @@ class GPUSystem:
                                     v_out=_ptr(self.v2) if out else C.c_void_p(0),
                                     tag_out=_ptr(self.tag2) if out else C.c_void_p(0))
         return self._args
+
+    def _vec(self, key):
+        return (C.c_double * 3)(*[float(a) for a in self.params.get(key, (0.0, 0.0, 0.0))])
+
+    def _vec_ptr(self, key):
+        v = self.params.get(key)
+        if v is None or not any(float(a) != 0.0 for a in v):
+            return None
+        return self._vec(key)
 
     def _swap(self):
         self.x, self.x2 = self.x2, self.x
@@ -201,17 +211,20 @@ class GPUSystem:
 
     def body_forces(self):
         L.check(self.lib.body_forces(self.stream, C.byref(self.csys), C.byref(self.cbodies),
-                                     C.byref(self.cwca), _ptr(self.ws), self.ws_bytes), "body_forces")
+                                     C.byref(self.cwca), self._vec_ptr("f_ext"), _ptr(self.ws), self.ws_bytes),
+                "body_forces")
 
     def body_integrate(self, impulse: bool = True):
         L.check(self.lib.body_integrate(self.stream, C.byref(self.csys), C.byref(self.cbodies),
                                         _ptr(self.J) if impulse else C.c_void_p(0),
                                         _ptr(self.K) if impulse else C.c_void_p(0), C.byref(self.cwca),
-                                        self.params["dt"], _ptr(self.ws), self.ws_bytes), "body_integrate")
+                                        self._vec_ptr("f_ext"), self.params["dt"], _ptr(self.ws), self.ws_bytes),
+                "body_integrate")
 
     def stream_solvent(self):
         L.check(self.lib.mpcd_stream(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.v),
-                                     self.params["dt"], _ptr(self.ws), self.ws_bytes), "mpcd_stream")
+                                     self.params["dt"], self._vec_ptr("g"), _ptr(self.ws), self.ws_bytes),
+                "mpcd_stream")
 
     def advance(self):
         L.check(self.lib.mpcd_advance_step(self.stream, _ptr(self.d_step)), "mpcd_advance_step")

@@ -284,6 +284,21 @@ def wca_spheres(sigma=6.0, eps=1.0, delta=0.0):
     return {"mode": 1, "eps": eps, "sigma": sigma, "delta": delta}
 
 
+def sedimentation(params: dict, systems, force=(0.5, 0.0, 0.0)) -> dict:
+    """Forced-flow parameters (Sec. III.B): the constant force `force` at every
+    body centre and the balancing solvent acceleration g = -B F / (N m), so the
+    whole system is force free.  Several systems must share B / N."""
+    if isinstance(systems, dict):
+        systems = [systems]
+    F = np.asarray(force, dtype=np.float64)
+    ratios = {(len(s["M"]), s["x"].shape[1], float(s["m"])) for s in systems}
+    B, N, m = next(iter(ratios))
+    if any(b * N != B * n for b, n, _ in ratios):
+        raise ValueError("systems with different body/solvent ratios need different accelerations")
+    g = -B * F / (N * m) if N else np.zeros(3)
+    return dict(params, f_ext=tuple(float(a) for a in F), g=tuple(float(a) for a in g))
+
+
 def wca_sites(sigma=1.0, eps=1.0, delta=0.0):
     """WCA between surface sites of different bodies."""
     return {"mode": 2, "eps": eps, "sigma": sigma, "delta": delta}

@@ -61,7 +61,7 @@ def test_invalid_sizes_are_rejected(bad):
 def test_invalid_pointers_rejected_before_any_launch():
     L = lib.load()
     s = sys_desc()  # device arrays left NULL
-    assert L.mpcd_stream(None, C.byref(s), None, None, 0.1, None, 0) == -1
+    assert L.mpcd_stream(None, C.byref(s), None, None, 0.1, None, None, 0) == -1
     assert L.mpcd_advance_step(None, None) == -1
     assert L.mpcd_graph_destroy(None) == -1
     f = C.c_uint32(0)

@@ -399,6 +399,25 @@ def test_site_wca_full_size_shapes_sampled():
     assert np.array_equal(F, gd["F"][:, idx]) and np.array_equal(T, gd["T"][:, idx])
 
 
+@pytest.mark.parametrize("form", ["out_of_place", "in_place", "unfused"])
+def test_forced_flow_bit_exact(form):
+    """Sedimentation forcing (Sec. III.B): a constant force on every body and
+    the balancing solvent acceleration, in every streaming form."""
+    wl = W.suspension((12, 12, 12), 5, 4, 2.0, 60, 5.0, seed=63)
+    par = W.sedimentation(W.srd_params(63, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0)), wl, (0.5, 0.1, -0.2))
+    say("forced flow %s" % form)
+    run_parity(wl, par, 20, fuse=(form != "unfused"), out_of_place=(form == "out_of_place"), check_every=5)
+
+
+def test_forced_flow_with_site_wca_bit_exact():
+    rng = np.random.default_rng(74)
+    centres = W.rsa_positions_radii(rng, np.array([10.0, 10.0, 10.0]), np.full(10, 1.3))
+    wl = small_shapes((10, 10, 10), 3, centres, 74)
+    par = W.sedimentation(W.srd_params(74, kT_cell=1.0, wca=W.wca_sites(sigma=0.8)), wl, (0.0, 0.0, 0.3))
+    say("forced flow, site WCA")
+    run_parity(wl, par, 8, check_every=4)
+
+
 def test_full_size_suspension_bit_exact_few_steps():
     """60^3 cells, 1.08M solvent, 191 spheres x 200 sites, WCA: the benchmark
     workload, checked bit for bit over 3 steps."""

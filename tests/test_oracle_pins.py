@@ -35,8 +35,13 @@ def tiny_system(ncell, xs, vs, bodies=(), m=1.0):
                 sm=np.concatenate(sm) if B else np.zeros(0))
 
 
-def params(kT_cell=0.0, thermalize=1, seed=3, **kw):
-    return W.srd_params(seed, kT_cell=kT_cell, thermalize=thermalize, **kw)
+def params(kT_cell=0.0, thermalize=1, seed=3, g=None, f_ext=None, **kw):
+    p = W.srd_params(seed, kT_cell=kT_cell, thermalize=thermalize, **kw)
+    if g is not None:
+        p["g"] = tuple(g)
+    if f_ext is not None:
+        p["f_ext"] = tuple(f_ext)
+    return p
 
 
 # ---------------------------------------------------------------------------
@@ -438,6 +443,58 @@ def test_site_wca_obeys_newtons_third_law():
     assert np.allclose(o.F.sum(1), 0.0, atol=1e-12 * scale * 12)
     Ltot = np.cross(o.R.T, o.F.T).sum(0) + o.T.sum(1)
     assert np.allclose(Ltot, 0.0, atol=1e-11 * scale * 12 * 20)
+
+
+# ---------------------------------------------------------------------------
+# Forced flow (Sec. III.B)
+
+def test_forced_streaming_follows_constant_acceleration():
+    """One particle per cell (no collisions): x(t) = x0 + v0 t + g t^2 / 2 and
+    v(t) = v0 + g t, step after step."""
+    xs = [[2.5, 2.5, 2.5], [6.5, 6.5, 6.5]]
+    vs = [[0.3, -0.2, 0.1], [-0.1, 0.05, 0.2]]
+    wl = tiny_system((40, 40, 40), xs, vs)
+    g = np.array([0.01, -0.02, 0.005])
+    o = oracle.OracleSystem(wl, params(g=tuple(g)))
+    x0, v0 = o.x.copy(), o.v.copy()
+    for n in range(50):
+        assert o.step(n) == 0
+    t = 50 * 0.1
+    assert np.allclose(o.x, x0 + v0 * t + 0.5 * g[:, None] * t * t, rtol=0, atol=1e-12)
+    assert np.allclose(o.v, v0 + g[:, None] * t, rtol=0, atol=1e-13)
+
+
+def test_body_under_external_force_gains_momentum_F_t():
+    """A lone body whose sites only collide with each other: collisions conserve
+    the body's momentum, so P(t) = P0 + F t."""
+    wl = W.single_sphere((10, 10, 10), 0, 2.0, 60, 5.0, seed=61)
+    F = np.array([0.5, -0.25, 0.1])
+    o = oracle.OracleSystem(wl, params(kT_cell=1.0, f_ext=tuple(F)))
+    o.body_forces()
+    P0 = o.P[:, 0].copy()
+    for n in range(40):
+        assert o.step(n) == 0
+    assert np.allclose(o.P[:, 0], P0 + F * 40 * 0.1, rtol=0, atol=1e-10)
+
+
+def test_forcing_changes_total_momentum_by_the_applied_impulse():
+    """Body force alone: total momentum grows by B F t exactly.  With the
+    balancing solvent acceleration g = -B F / (N m) it is conserved."""
+    wl = W.suspension((10, 10, 10), 5, 2, 1.5, 40, 5.0, seed=62)
+    base = params(kT_cell=1.0, wca=W.wca_spheres(sigma=3.0))
+    F = (0.5, -0.2, 0.0)
+    for balanced in (False, True):
+        par = W.sedimentation(base, wl, F)
+        if not balanced:
+            par["g"] = (0.0, 0.0, 0.0)
+        o = oracle.OracleSystem(wl, par)
+        o.body_forces()
+        P0 = o.m * o.v.sum(1) + o.P.sum(1)
+        for n in range(60):
+            assert o.step(n) == 0
+        dP = o.m * o.v.sum(1) + o.P.sum(1) - P0
+        expect = np.zeros(3) if balanced else 2 * np.array(F) * 60 * 0.1
+        assert np.allclose(dP, expect, rtol=0, atol=1e-9), (balanced, dP)
 
 
 # ---------------------------------------------------------------------------
