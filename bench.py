@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--large", action="store_true", help="also run the 200^3-cell, 80M-solvent suspension (FP32)")
+    ap.add_argument("--shapes", action="store_true",
+                    help="also run the 128^3 complex-shape suspension (site-site WCA), FP32 and FP64")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -234,6 +236,14 @@ def main():
         out["large"] = dict(summary(rl), workload=lmeta["name"], collide_us=rl["collide_ms"] * 1e3,
                             collide_GBs=collide_bytes(rl["N"], rl["S"], 4) / (rl["collide_ms"] * 1e-3) / 1e9)
         del lw
+    if args.shapes:
+        sw, spar, smeta = W.config(4, kT_cell=1.0)
+        out["shapes"] = {"workload": smeta["name"]}
+        for prec in ("f32", "f64"):
+            log("complex shapes %s: 50 timed steps" % prec)
+            rs = run_gpu(sw, spar, prec, 50, 6, 5, 0)
+            out["shapes"][prec] = summary(rs)
+        del sw
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:
