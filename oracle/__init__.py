@@ -313,3 +313,85 @@ class OracleSystem:
     def state(self):
         return {k: getattr(self, k).copy() for k in
                 ("x", "v", "R", "img", "q", "P", "p", "F", "T", "xs", "vs", "vpre", "d")}
+
+
+# ---------------------------------------------------------------------------
+# Harmonic-bond comparator (Sec. II.B.1)
+
+class OrcHarm(C.Structure):
+    _fields_ = [("B", C.c_int64), ("xc", C.POINTER(C.c_double)), ("vc", C.POINTER(C.c_double)),
+                ("imgc", C.POINTER(C.c_int32)), ("imgs", C.POINTER(C.c_int32)),
+                ("mc", C.c_double), ("kb", C.c_double),
+                ("site_off", C.POINTER(C.c_int64)), ("site_body", C.POINTER(C.c_int32)),
+                ("adj_off", C.POINTER(C.c_int64)), ("adj", C.POINTER(C.c_int32)),
+                ("adj_r0", C.POINTER(C.c_double)), ("rc0", C.POINTER(C.c_double)),
+                ("fs", C.POINTER(C.c_double)), ("fc", C.POINTER(C.c_double))]
+
+
+def _harm_lib():
+    L = lib()
+    if not hasattr(L, "_harm_ready"):
+        sysp, parp, hp = C.POINTER(OrcSys), C.POINTER(OrcPar), C.POINTER(OrcHarm)
+        L.orc_harm_forces.restype = C.c_uint32
+        L.orc_harm_forces.argtypes = [sysp, hp, parp]
+        L.orc_harm_md.restype = C.c_uint32
+        L.orc_harm_md.argtypes = [sysp, hp, parp, C.c_double, C.c_int64]
+        L.orc_harm_step.restype = C.c_uint32
+        L.orc_harm_step.argtypes = [sysp, hp, parp, C.c_uint64, C.c_double, C.c_int64]
+        L.orc_harm_energy.restype = C.c_double
+        L.orc_harm_energy.argtypes = [sysp, hp, parp]
+        L._harm_ready = True
+    return L
+
+
+class HarmonicOracle:
+    """The harmonic-bond model of one system (see workloads.harmonic_from_rigid),
+    advanced by the C oracle: solvent x, v; surface sites xs, vs (they collide);
+    centre sites xc, vc; forces fs, fc."""
+
+    def __init__(self, hw: dict, params: dict, replica: int = 0):
+        f64 = lambda a: np.ascontiguousarray(np.array(a, dtype=np.float64, copy=True))
+        self.ncell = tuple(int(n) for n in hw["ncell"])
+        self.a, self.m = float(hw["a"]), float(hw["m"])
+        self.x, self.v = f64(hw["x"]), f64(hw["v"])
+        self.xs, self.vs, self.sm = f64(hw["xs"]), f64(hw["vs"]), f64(hw["sm"])
+        self.xc, self.vc = f64(hw["xc"]), f64(hw["vc"])
+        self.imgs = np.ascontiguousarray(np.array(hw["imgs"], dtype=np.int32, copy=True))
+        self.imgc = np.ascontiguousarray(np.array(hw["imgc"], dtype=np.int32, copy=True))
+        self.site_off = np.ascontiguousarray(np.array(hw["site_off"], dtype=np.int64))
+        self.site_body = np.ascontiguousarray(np.array(hw["site_body"], dtype=np.int32))
+        self.adj_off = np.ascontiguousarray(np.array(hw["adj_off"], dtype=np.int64))
+        self.adj = np.ascontiguousarray(np.array(hw["adj"], dtype=np.int32))
+        self.adj_r0, self.rc0 = f64(hw["adj_r0"]), f64(hw["rc0"])
+        self.N, self.S, self.B = self.x.shape[1], self.xs.shape[1], self.xc.shape[1]
+        self.fs, self.fc = np.zeros((3, self.S)), np.zeros((3, self.B))
+        self._dummy = np.zeros(8)
+        self._zero_off = np.zeros(1, dtype=np.int64)
+        self._zero_i = np.zeros(3, dtype=np.int32)
+        self._vpre, self._d = np.zeros((3, self.S)), np.zeros((3, self.S))
+        self.par = make_par(params, replica)
+        d = self._dummy
+        self._sys = OrcSys(n=(C.c_int32 * 3)(*self.ncell), a=self.a, N=self.N, m=self.m,
+                           x=_p(self.x), v=_p(self.v), B=0, R=_p(d), img=_p(self._zero_i, C.c_int32),
+                           q=_p(d), P=_p(d), p=_p(d), F=_p(d), T=_p(d), M=_p(d), I=_p(d), S=self.S,
+                           site_off=_p(self._zero_off, C.c_int64), dhat=_p(self._d), sm=_p(self.sm),
+                           xs=_p(self.xs), vs=_p(self.vs), vpre=_p(self._vpre), d=_p(self._d))
+        self._h = OrcHarm(B=self.B, xc=_p(self.xc), vc=_p(self.vc), imgc=_p(self.imgc, C.c_int32),
+                          imgs=_p(self.imgs, C.c_int32), mc=float(hw["mc"]), kb=float(hw["kb"]),
+                          site_off=_p(self.site_off, C.c_int64), site_body=_p(self.site_body, C.c_int32),
+                          adj_off=_p(self.adj_off, C.c_int64), adj=_p(self.adj, C.c_int32),
+                          adj_r0=_p(self.adj_r0), rc0=_p(self.rc0), fs=_p(self.fs), fc=_p(self.fc))
+        self.mc = float(hw["mc"])
+
+    def forces(self):
+        return _harm_lib().orc_harm_forces(C.byref(self._sys), C.byref(self._h), C.byref(self.par))
+
+    def md(self, dt, nsub):
+        return _harm_lib().orc_harm_md(C.byref(self._sys), C.byref(self._h), C.byref(self.par), dt, nsub)
+
+    def step(self, step, dt_md, nsub):
+        return _harm_lib().orc_harm_step(C.byref(self._sys), C.byref(self._h), C.byref(self.par), step, dt_md,
+                                         nsub)
+
+    def energy(self):
+        return _harm_lib().orc_harm_energy(C.byref(self._sys), C.byref(self._h), C.byref(self.par))

@@ -934,6 +934,189 @@ uint32_t orc_stream(orc_sys *s, double dt)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Harmonic-bond comparator (Sec. II.B.1).  Each colloid is a centre site plus */
+/* surface sites; every surface site is bonded to its nearest surface         */
+/* neighbours and to the centre by u_b = (k_b / 2)(r - r_b)^2, Eq. (2).  All  */
+/* sites move by velocity Verlet with a small step; the surface sites collide */
+/* like heavy solvent (the orc_sys site arrays xs, vs, sm, with B = 0); the   */
+/* centre sites carry the colloid WCA of Eq. (1) and do not collide.          */
+typedef struct {
+    int64_t B;               /* colloids (one centre site each) */
+    double *xc, *vc;         /* [3B] centre sites (wrapped), velocities */
+    int32_t *imgc, *imgs;    /* [3B], [3S] periodic images */
+    double mc;               /* centre site mass */
+    double kb;               /* spring constant */
+    const int64_t *site_off; /* [B+1] surface sites of colloid b */
+    const int32_t *site_body;/* [S] colloid of each surface site */
+    const int64_t *adj_off;  /* [S+1] bonds of surface site j to other surface sites */
+    const int32_t *adj;      /* partner (ascending within each site's range) */
+    const double *adj_r0;    /* rest length of each bond */
+    const double *rc0;       /* [S] rest length of the bond of site j to its centre */
+    double *fs, *fc;         /* [3S], [3B] forces at the current positions */
+} orc_harm;
+
+/* Force on the first end of a bond with separation d = x_1 - x_2 (minimum
+ * image): -k_b (r - r0) d / r, added to f. */
+static void bond_add(double kb, double r0, const double d[3], double f[3])
+{
+    double r = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+    double fo = (-kb * (r - r0)) / r;
+    for (int k = 0; k < 3; ++k) f[k] = f[k] + fo * d[k];
+}
+
+/* Forces on every site: a surface site sums its surface bonds in ascending
+ * partner index, then its centre bond; a centre sums its bonds in site order,
+ * then the WCA of Eq. (1) with the other centres in ascending index. */
+uint32_t orc_harm_forces(const orc_sys *s, orc_harm *h, const orc_par *par)
+{
+    uint32_t flags = 0;
+    int64_t S = s->S, B = h->B;
+    for (int64_t j = 0; j < S; ++j) {
+        double f[3] = {0.0, 0.0, 0.0}, d[3];
+        for (int64_t e = h->adj_off[j]; e < h->adj_off[j + 1]; ++e) {
+            int64_t k2 = h->adj[e];
+            for (int k = 0; k < 3; ++k) d[k] = min_image(s->xs[k * S + j] - s->xs[k * S + k2], box_len(s, k));
+            bond_add(h->kb, h->adj_r0[e], d, f);
+        }
+        int64_t b = h->site_body[j];
+        for (int k = 0; k < 3; ++k) d[k] = min_image(s->xs[k * S + j] - h->xc[k * B + b], box_len(s, k));
+        bond_add(h->kb, h->rc0[j], d, f);
+        for (int k = 0; k < 3; ++k) h->fs[k * S + j] = f[k];
+    }
+    double rc = par->delta + 0x1.1f59ac3c7d6c0p+0 * par->sigma;
+    double rc2 = rc * rc;
+    for (int64_t b = 0; b < B; ++b) {
+        double f[3] = {0.0, 0.0, 0.0}, d[3];
+        for (int64_t j = h->site_off[b]; j < h->site_off[b + 1]; ++j) {
+            for (int k = 0; k < 3; ++k) d[k] = min_image(h->xc[k * B + b] - s->xs[k * S + j], box_len(s, k));
+            bond_add(h->kb, h->rc0[j], d, f);
+        }
+        if (par->wca_mode == 1)
+            for (int64_t b2 = 0; b2 < B; ++b2) {
+                if (b2 == b) continue;
+                double dr[3];
+                for (int k = 0; k < 3; ++k) {
+                    double L = box_len(s, k);
+                    double t = h->xc[k * B + b] - h->xc[k * B + b2];
+                    if (t > 0.5 * L) t = t - L;
+                    else if (t < -0.5 * L) t = t + L;
+                    dr[k] = t;
+                }
+                double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
+                if (!(r2 <= rc2)) continue;
+                flags |= wca_pair(par, dr, r2, f);
+            }
+        for (int k = 0; k < 3; ++k) h->fc[k * B + b] = f[k];
+    }
+    return flags;
+}
+
+/* Velocity Verlet for all sites, nsub steps of dt: v += (dt/2)(f/m),
+ * x += v dt (wrapped, image counted), new forces, v += (dt/2)(f/m). */
+uint32_t orc_harm_md(orc_sys *s, orc_harm *h, const orc_par *par, double dt, int64_t nsub)
+{
+    uint32_t flags = 0;
+    int64_t S = s->S, B = h->B;
+    double hdt = 0.5 * dt;
+    for (int64_t n = 0; n < nsub; ++n) {
+        for (int k = 0; k < 3; ++k) {
+            double L = box_len(s, k);
+            for (int64_t j = 0; j < S; ++j) {
+                double v = s->vs[k * S + j] + hdt * (h->fs[k * S + j] / s->sm[j]);
+                s->vs[k * S + j] = v;
+                double y = s->xs[k * S + j] + v * dt;
+                if (y >= L) { y = y - L; h->imgs[k * S + j] += 1; }
+                else if (y < 0.0) { y = y + L; h->imgs[k * S + j] -= 1; }
+                if (!(y >= 0.0 && y <= L)) flags |= (y != y) ? ORC_NONFINITE : ORC_ESCAPE;
+                s->xs[k * S + j] = y;
+            }
+            for (int64_t b = 0; b < B; ++b) {
+                double v = h->vc[k * B + b] + hdt * (h->fc[k * B + b] / h->mc);
+                h->vc[k * B + b] = v;
+                double y = h->xc[k * B + b] + v * dt;
+                if (y >= L) { y = y - L; h->imgc[k * B + b] += 1; }
+                else if (y < 0.0) { y = y + L; h->imgc[k * B + b] -= 1; }
+                if (!(y >= 0.0 && y <= L)) flags |= (y != y) ? ORC_NONFINITE : ORC_ESCAPE;
+                h->xc[k * B + b] = y;
+            }
+        }
+        flags |= orc_harm_forces(s, h, par);
+        for (int k = 0; k < 3; ++k) {
+            for (int64_t j = 0; j < S; ++j) s->vs[k * S + j] = s->vs[k * S + j] + hdt * (h->fs[k * S + j] / s->sm[j]);
+            for (int64_t b = 0; b < B; ++b) h->vc[k * B + b] = h->vc[k * B + b] + hdt * (h->fc[k * B + b] / h->mc);
+        }
+    }
+    return flags;
+}
+
+/* Bond and WCA potential energy of the harmonic colloids. */
+double orc_harm_energy(const orc_sys *s, const orc_harm *h, const orc_par *par)
+{
+    int64_t S = s->S, B = h->B;
+    double U = 0.0;
+    for (int64_t j = 0; j < S; ++j) {
+        for (int64_t e = h->adj_off[j]; e < h->adj_off[j + 1]; ++e) {
+            int64_t k2 = h->adj[e];
+            if (k2 < j) continue; /* each bond once */
+            double r2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double t = min_image(s->xs[k * S + j] - s->xs[k * S + k2], box_len(s, k));
+                r2 += t * t;
+            }
+            double x = sqrt(r2) - h->adj_r0[e];
+            U += 0.5 * h->kb * x * x;
+        }
+        int64_t b = h->site_body[j];
+        double r2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double t = min_image(s->xs[k * S + j] - h->xc[k * B + b], box_len(s, k));
+            r2 += t * t;
+        }
+        double x = sqrt(r2) - h->rc0[j];
+        U += 0.5 * h->kb * x * x;
+    }
+    if (par->wca_mode == 1) {
+        double rc = par->delta + 0x1.1f59ac3c7d6c0p+0 * par->sigma;
+        for (int64_t i = 0; i < B; ++i)
+            for (int64_t b = i + 1; b < B; ++b) {
+                double r2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    double t = min_image(h->xc[k * B + i] - h->xc[k * B + b], box_len(s, k));
+                    r2 += t * t;
+                }
+                double r = sqrt(r2);
+                if (r > rc || r <= par->delta) continue;
+                double x6 = pow(par->sigma / (r - par->delta), 6.0);
+                U += 4.0 * par->eps * (x6 * x6 - x6) + par->eps;
+            }
+    }
+    return U;
+}
+
+/* One collision period of the harmonic model: shift, bin solvent and surface
+ * sites, collide (the sites as heavy solvent), stream the solvent over the
+ * period, then nsub velocity-Verlet steps of dt_md for the sites. */
+uint32_t orc_harm_step(orc_sys *s, orc_harm *h, const orc_par *par, uint64_t step, double dt_md, int64_t nsub)
+{
+    uint32_t flags = 0;
+    int64_t C = (int64_t)s->n[0] * s->n[1] * s->n[2];
+    int64_t NT = s->N + s->S;
+    double sh[3];
+    orc_shift(par->seed, step, par->replica, s->a, sh);
+    int32_t *cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(NT > 0 ? NT : 1));
+    int64_t *cs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
+    int64_t *mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)(NT > 0 ? NT : 1));
+    flags |= orc_bin(s, sh, cell, cs, mem);
+    flags |= orc_collide(s, par, step, cs, mem, NULL);
+    free(cell);
+    free(cs);
+    free(mem);
+    flags |= orc_stream_forced(s, par->dt, par->g);
+    flags |= orc_harm_md(s, h, par, dt_md, nsub);
+    return flags;
+}
+
+/* ------------------------------------------------------------------------- */
 /* One full step n: thermalize sites, shift, bin, collide, transfer to the    */
 /* bodies, stream the solvent, integrate the bodies.                          */
 uint32_t orc_step(orc_sys *s, const orc_par *par, uint64_t step)

@@ -299,6 +299,80 @@ def sedimentation(params: dict, systems, force=(0.5, 0.0, 0.0)) -> dict:
     return dict(params, f_ext=tuple(float(a) for a in F), g=tuple(float(a) for a in g))
 
 
+def harmonic_network(dhat: np.ndarray, nneigh: int = 3):
+    """Bonds of the harmonic-bond model (Sec. II.B.1) for one template: each
+    surface site to its nneigh nearest surface sites (the union of those
+    pairs) and to the centre; rest lengths rounded to three decimals, as in the
+    paper.  Returns (adjacency lists with rest lengths, centre rest lengths)."""
+    d = np.asarray(dhat, dtype=np.float64)
+    n = len(d)
+    dist = np.sqrt(((d[:, None, :] - d[None, :, :]) ** 2).sum(2))
+    np.fill_diagonal(dist, np.inf)
+    pairs = set()
+    for j in range(n):
+        for k in np.argsort(dist[j], kind="stable")[:nneigh]:
+            pairs.add((min(j, int(k)), max(j, int(k))))
+    adj = [[] for _ in range(n)]
+    for a, b in sorted(pairs):
+        r0 = round(float(dist[a, b]), 3)
+        adj[a].append((b, r0))
+        adj[b].append((a, r0))
+    adj = [sorted(x) for x in adj]
+    rc0 = np.round(np.sqrt((d * d).sum(1)), 3)
+    return adj, rc0
+
+
+def harmonic_from_rigid(wl: dict, kb: float = 5000.0, centre_mass=None, nneigh: int = 3) -> dict:
+    """The harmonic-bond model of a rigid workload: the same solvent, the same
+    colloids (site positions R + A(q) dhat, rigid-motion velocities
+    V + omega x d), a centre site per colloid (mass = site mass unless given),
+    and the bond network of harmonic_network."""
+    B = wl["M"].shape[0]
+    so = np.asarray(wl["site_off"], dtype=np.int64)
+    S = int(so[-1])
+    L = np.array(wl["ncell"], dtype=np.float64) * float(wl["a"])
+    xs = np.zeros((3, S)); vs = np.zeros((3, S))
+    xc = np.zeros((3, B)); vc = np.zeros((3, B))
+    site_body = np.zeros(S, dtype=np.int32)
+    adj_off, adj, adj_r0, rc0 = [0], [], [], np.zeros(S)
+    cache = {}
+    for b in range(B):
+        j0, j1 = int(so[b]), int(so[b + 1])
+        dh = wl["dhat"][:, j0:j1].T
+        A = quat_matrix(wl["q"][:, b])
+        d = dh @ A.T
+        V = wl["P"][:, b] / wl["M"][b]
+        q, p = wl["q"][:, b], wl["p"][:, b]
+        # body-frame angular momentum 1/2 p . P_k q, then omega = A (Lhat / I)
+        Lh = 0.5 * np.array([-p[0] * q[1] + p[1] * q[0] + p[2] * q[3] - p[3] * q[2],
+                             -p[0] * q[2] - p[1] * q[3] + p[2] * q[0] + p[3] * q[1],
+                             -p[0] * q[3] + p[1] * q[2] - p[2] * q[1] + p[3] * q[0]])
+        I = wl["I"][:, b]
+        w = A @ np.where(I > 0, Lh / np.where(I > 0, I, 1.0), 0.0)
+        xs[:, j0:j1] = ((wl["R"][:, b][None, :] + d) % L).T
+        vs[:, j0:j1] = (V[None, :] + np.cross(w[None, :], d)).T
+        xc[:, b] = wl["R"][:, b] % L
+        vc[:, b] = V
+        site_body[j0:j1] = b
+        key = dh.tobytes()
+        if key not in cache:
+            cache[key] = harmonic_network(dh, nneigh)
+        badj, brc0 = cache[key]
+        for jl in range(j1 - j0):
+            for k, r0 in badj[jl]:
+                adj.append(j0 + k)
+                adj_r0.append(r0)
+            adj_off.append(len(adj))
+        rc0[j0:j1] = brc0
+    sm = np.asarray(wl["sm"], dtype=np.float64)
+    mc = float(sm[0]) if centre_mass is None and S else float(centre_mass or 1.0)
+    return dict(ncell=wl["ncell"], a=wl["a"], m=wl["m"], x=wl["x"], v=wl["v"],
+                xs=xs, vs=vs, sm=sm.copy(), site_body=site_body, site_off=so.copy(),
+                xc=xc, vc=vc, mc=mc, kb=float(kb), adj_off=np.array(adj_off, dtype=np.int64),
+                adj=np.array(adj, dtype=np.int32), adj_r0=np.array(adj_r0), rc0=rc0,
+                imgs=np.zeros((3, S), dtype=np.int32), imgc=np.zeros((3, B), dtype=np.int32))
+
+
 def wca_sites(sigma=1.0, eps=1.0, delta=0.0):
     """WCA between surface sites of different bodies."""
     return {"mode": 2, "eps": eps, "sigma": sigma, "delta": delta}

@@ -498,6 +498,73 @@ def test_forcing_changes_total_momentum_by_the_applied_impulse():
 
 
 # ---------------------------------------------------------------------------
+# Harmonic-bond comparator (Sec. II.B.1)
+
+def harmonic_pair(seed=71, density=0):
+    """Two bonded spheres (40 sites each) close enough for their centre WCA."""
+    wl = W.suspension((12, 12, 12), density, 2, 1.5, 40, 5.0, seed=seed)
+    wl["R"][:, 0] = (4.0, 6.0, 6.0)
+    wl["R"][:, 1] = (7.9, 6.3, 6.1)
+    return W.harmonic_from_rigid(wl, kb=5000.0)
+
+
+def test_harmonic_forces_are_minus_gradient():
+    """Bond forces of Eq. (2) and the centre WCA of Eq. (1) are -dU/dx for
+    surface and centre sites (perturbed from rest so the bonds are loaded)."""
+    hw = harmonic_pair()
+    rng = np.random.default_rng(72)
+    hw["xs"] = hw["xs"] + 0.02 * rng.normal(size=hw["xs"].shape)
+    par = params(wca=W.wca_spheres(sigma=4.0))
+    o = oracle.HarmonicOracle(hw, par)
+    assert o.forces() == 0
+    assert np.abs(o.fc).max() > 1.0
+    h = 1e-6
+    for arr, f, idx in ((o.xs, o.fs, (0, 7, 45)), (o.xc, o.fc, (0, 1))):
+        for i in idx:
+            for k in range(3):
+                x0 = arr[k, i]
+                arr[k, i] = x0 + h
+                up = o.energy()
+                arr[k, i] = x0 - h
+                um = o.energy()
+                arr[k, i] = x0
+                assert math.isclose(f[k, i], -(up - um) / (2 * h), rel_tol=1e-5, abs_tol=1e-4), (i, k)
+
+
+def test_harmonic_model_conserves_energy_and_momentum():
+    """Without solvent and thermostat, collisions among the sites conserve
+    momentum and kinetic energy and velocity Verlet conserves energy to
+    O(dt^2): 20 collision periods of 50 steps of 0.002."""
+    hw = harmonic_pair()
+    o = oracle.HarmonicOracle(hw, params(kT_cell=0.0, wca=W.wca_spheres(sigma=4.0)))
+    assert o.forces() == 0
+
+    def energy():
+        return 0.5 * (o.sm * (o.vs ** 2)).sum() + 0.5 * o.mc * (o.vc ** 2).sum() + o.energy()
+
+    def momentum():
+        return (o.sm * o.vs).sum(1) + o.mc * o.vc.sum(1)
+    E0, P0 = energy(), momentum()
+    for n in range(20):
+        assert o.step(n, 0.002, 50) == 0
+    assert abs(energy() - E0) < 1e-3 * E0
+    assert np.allclose(momentum(), P0, rtol=0, atol=1e-9)
+
+
+def test_harmonic_model_with_solvent_conserves_momentum():
+    hw = harmonic_pair(seed=73, density=3)
+    o = oracle.HarmonicOracle(hw, params(kT_cell=1.0, wca=W.wca_spheres(sigma=4.0)))
+    assert o.forces() == 0
+
+    def momentum():
+        return o.m * o.v.sum(1) + (o.sm * o.vs).sum(1) + o.mc * o.vc.sum(1)
+    P0 = momentum()
+    for n in range(5):
+        assert o.step(n, 0.002, 50) == 0
+    assert np.allclose(momentum(), P0, rtol=0, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
 # Failure detection
 
 def test_escape_flag_for_too_fast_particle():
