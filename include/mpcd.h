@@ -262,6 +262,52 @@ int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies,
 int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca,
                 const double *f_ext, void *ws, size_t ws_bytes);
 
+/* Harmonic-bond comparator, Sec. II.B.1: a colloid is a centre site plus
+ * surface sites; each surface site is bonded to its nearest surface neighbours
+ * and to the centre by u_b = (k_b / 2)(r - r_b)^2, Eq. (2).  All sites move by
+ * velocity Verlet with a small step dt_md; the surface sites collide like
+ * heavy solvent (they are the "sites" of mpcd_sys, FP64 only), the centres
+ * carry the WCA of Eq. (1) (mode 1) and do not collide.  Forces: a surface
+ * site sums its surface bonds in stored (ascending partner) order, then its
+ * centre bond; a centre sums its bonds in site order, then the WCA partners in
+ * ascending index.  Bond vectors use the minimum image t - L rint(t / L).
+ * Positions ping-pong between the caller's arrays and the _alt arrays inside
+ * harm_md; after an (even) number of Verlet steps they are back in xs, xc. */
+typedef struct {
+    double *xs_alt;             /* [3S] second buffer of surface positions      */
+    double *xc, *xc_alt, *vc;   /* [3B] centre positions (two buffers), velocities */
+    double *fs, *fc;            /* [3S], [3B] forces at the current positions   */
+    int32_t *imgs, *imgc;       /* [3S], [3B] periodic image counters           */
+    double mc, kb;              /* centre mass, spring constant                 */
+    const int64_t *site_off;    /* [B+1] surface sites of each colloid          */
+    const int32_t *site_body;   /* [S] colloid of each surface site             */
+    const int64_t *adj_off;     /* [S+1] bonds of each surface site             */
+    const int32_t *adj;         /* bonded surface partner, ascending per site   */
+    const double *adj_r0;       /* rest length of each listed bond              */
+    const double *rc0;          /* [S] rest length of each centre bond          */
+    const double *site_m;       /* [S] surface site masses                      */
+} mpcd_harm;
+
+/* Forces on all sites at the positions xs (surface) and h->xc (centres). */
+int harm_forces(void *stream, const mpcd_sys *sys, const mpcd_harm *h, const double *xs,
+                const mpcd_wca *wca, void *ws, size_t ws_bytes);
+/* nsub (even, >= 2) velocity-Verlet steps of dt: v += (dt/2)(f/m), x += v dt
+ * (wrapped, images counted), new forces, v += (dt/2)(f/m).  Requires the
+ * forces of the current positions in h->fs, h->fc (harm_forces, or the last
+ * harm_md). */
+int harm_md(void *stream, const mpcd_sys *sys, const mpcd_harm *h, double *xs, double *vs,
+            const mpcd_wca *wca, double dt, int32_t nsub, void *ws, size_t ws_bytes);
+/* One collision period: grid shift and binning of solvent and surface sites,
+ * collision (surface sites as heavy solvent) fused with solvent streaming over
+ * par.dt (out of place when x_out.. are set), nsub Verlet steps of dt_md
+ * (nsub dt_md = par.dt in the paper's protocol), step counter + 1.  a->xs,
+ * a->vs are the surface sites (double); a->bodies supplies site_body and
+ * site_m; par.thermalize must be 0 and par.fuse_stream 1. */
+int harm_step(void *stream, const mpcd_step_args *a, const mpcd_harm *h, double dt_md, int32_t nsub);
+/* A HIP graph of nperiods harm_step calls (even when out of place). */
+int harm_graph_create(void *stream, const mpcd_step_args *a, const mpcd_harm *h, double dt_md,
+                      int32_t nsub, int32_t nperiods, void **graph_exec);
+
 /* Storage reorder: permute the solvent (x, v and identity tags, [3N], [3N],
  * [N]) into the order of the last mpcd_bin (grouped by cell), so that the
  * gathers of the next steps stay local as the solvent diffuses.  Changes only

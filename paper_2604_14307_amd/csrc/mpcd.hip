@@ -2392,6 +2392,203 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
 }
 
 // ---------------------------------------------------------------------------
+// Harmonic-bond comparator (Sec. II.B.1): bonded surface and centre sites
+// moved by velocity Verlet.  One launch per Verlet step; blocks [0, nsb) take
+// one surface site per thread, the next B blocks one centre each.  Positions
+// are read from one buffer and written to the other, so every force of a step
+// sees the positions of that step.  Phase 0: first half kick and drift (forces
+// from the previous step); phase 1: new forces, second half kick of the
+// previous step, first half kick and drift of the next; phase 2: new forces
+// and the last second half kick; phase 3: forces only.
+
+struct HarmDev {
+    int64_t B, S;
+    const int64_t *site_off;
+    const int32_t *site_body;
+    const int64_t *adj_off;
+    const int32_t *adj;
+    const double *adj_r0, *rc0, *site_m;
+    double *vc, *fs, *fc;
+    int32_t *imgs, *imgc;
+    double mc, kb;
+};
+
+__device__ __forceinline__ void harm_bond(double kb, double r0, const double d[3], double f[3])
+{
+    const double r = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+    const double fo = (-kb * (r - r0)) / r;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] = f[k] + fo * d[k];
+}
+
+__device__ __forceinline__ void harm_drift(double &x, double v, double dt, double L, int32_t &img, uint32_t &st)
+{
+    double y = x + v * dt;
+    if (y >= L) { y = y - L; img += 1; }
+    else if (y < 0.0) { y = y + L; img -= 1; }
+    if (!(y >= 0.0 && y <= L)) st |= (y != y) ? ST_NONFINITE : ST_ESCAPE;
+    x = y;
+}
+
+__global__ __launch_bounds__(BODY_T) void k_harm_substep(SysDev s, HarmDev h, mpcd_wca wca, const double *xs_in,
+                                                         double *xs_out, double *vs, const double *xc_in,
+                                                         double *xc_out, double dt, int phase, int nsb,
+                                                         uint32_t *status)
+{
+    __shared__ double sh[3 * SH_PAD];
+    __shared__ int shit[BODY_T];
+    __shared__ double fsum[3];
+    const int t = threadIdx.x;
+    const int64_t S = h.S, B = h.B;
+    const double hdt = 0.5 * dt;
+    uint32_t st = 0;
+    if ((int)blockIdx.x < nsb) {
+        const int64_t j = (int64_t)blockIdx.x * BODY_T + t;
+        if (j >= S) return;
+        const int64_t b = h.site_body[j];
+        const int r = find_sys(s.body_off, s.nsys, b);
+        double Lb[3], xj[3], f[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Lb[k] = (double)s.ncell[3 * r + k] * s.a;
+            xj[k] = xs_in[k * S + j];
+        }
+        if (phase == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) f[k] = h.fs[k * S + j];
+        } else {  // phases 1, 2, 3: forces at the input positions
+            double d[3];
+            for (int64_t e = h.adj_off[j]; e < h.adj_off[j + 1]; ++e) {
+                const int64_t k2 = h.adj[e];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) d[k] = min_image(xj[k] - xs_in[k * S + k2], Lb[k]);
+                harm_bond(h.kb, h.adj_r0[e], d, f);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d[k] = min_image(xj[k] - xc_in[k * B + b], Lb[k]);
+            harm_bond(h.kb, h.rc0[j], d, f);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) h.fs[k * S + j] = f[k];
+        }
+        if (phase == 3) return;
+        const double m = h.site_m[j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double v = vs[k * S + j];
+            if (phase >= 1) v = v + hdt * (f[k] / m);
+            if (phase <= 1) {
+                v = v + hdt * (f[k] / m);
+                double x = xj[k];
+                harm_drift(x, v, dt, Lb[k], h.imgs[k * S + j], st);
+                xs_out[k * S + j] = x;
+            }
+            vs[k * S + j] = v;
+        }
+        flag(status, st);
+        return;
+    }
+    const int64_t b = (int64_t)blockIdx.x - nsb;
+    if (b >= B) return;
+    const int r = find_sys(s.body_off, s.nsys, b);
+    double Lb[3], xb[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Lb[k] = (double)s.ncell[3 * r + k] * s.a;
+        xb[k] = xc_in[k * B + b];
+    }
+    double f = 0.0;  // component t (lanes 0..2)
+    if (phase >= 1) {
+        // bonds to the centre, in site order
+        const int64_t j0 = h.site_off[b], j1 = h.site_off[b + 1];
+        for (int64_t c0 = j0; c0 < j1; c0 += BODY_T) {
+            const int64_t j = c0 + t;
+            if (j < j1) {
+                double d[3], fj[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) d[k] = min_image(xb[k] - xs_in[k * S + j], Lb[k]);
+                harm_bond(h.kb, h.rc0[j], d, fj);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sh[k * SH_PAD + t] = fj[k];
+            }
+            __syncthreads();
+            if (t < 3) {
+                const int cnt = (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T);
+                for (int i = 0; i < cnt; ++i) f = f + sh[t * SH_PAD + i];
+            }
+            __syncthreads();
+        }
+        // WCA of Eq. (1) with the other centres, ascending index
+        if (wca.mode == 1) {
+            const double rc = wca.delta + 0x1.1f59ac3c7d6c0p+0 * wca.sigma;
+            const double rc2 = rc * rc;
+            const int64_t jb = s.body_off[r], je = s.body_off[r + 1];
+            for (int64_t c0 = jb; c0 < je; c0 += BODY_T) {
+                const int64_t b2 = c0 + t;
+                int hit = 0;
+                double c[3] = {0.0, 0.0, 0.0};
+                if (b2 < je && b2 != b) {
+                    double dr[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        double d = xb[k] - xc_in[k * B + b2];
+                        if (d > 0.5 * Lb[k]) d = d - Lb[k];
+                        else if (d < -0.5 * Lb[k]) d = d + Lb[k];
+                        dr[k] = d;
+                    }
+                    const double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
+                    if (r2 <= rc2) {
+                        const double rr = sqrt(r2);
+                        const double shf = rr - wca.delta;
+                        if (shf > 0.0) {
+                            const double is = wca.sigma / shf;
+                            const double is2 = is * is;
+                            const double is6 = (is2 * is2) * is2;
+                            const double is12 = is6 * is6;
+                            const double fr = ((24.0 * wca.eps) * (2.0 * is12 - is6)) / shf;
+                            const double fo = fr / rr;
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) c[k] = fo * dr[k];
+                            hit = 1;
+                        } else {
+                            st |= ST_NONFINITE;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sh[k * SH_PAD + t] = c[k];
+                shit[t] = hit;
+                __syncthreads();
+                if (t < 3) {
+                    const int cnt = (int)((je - c0) < BODY_T ? (je - c0) : BODY_T);
+                    for (int i = 0; i < cnt; ++i)
+                        if (shit[i]) f = f + sh[t * SH_PAD + i];
+                }
+                __syncthreads();
+            }
+        }
+        if (t < 3) h.fc[t * B + b] = f;
+    } else if (t < 3) {
+        f = h.fc[t * B + b];
+    }
+    if (t < 3) fsum[t] = f;
+    __syncthreads();
+    if (t < 3 && phase != 3) {
+        const int k = t;
+        double v = h.vc[k * B + b];
+        const double fk = fsum[k];
+        if (phase >= 1) v = v + hdt * (fk / h.mc);
+        if (phase <= 1) {
+            v = v + hdt * (fk / h.mc);
+            double x = xb[k];
+            harm_drift(x, v, dt, Lb[k], h.imgc[k * B + b], st);
+            xc_out[k * B + b] = x;
+        }
+        h.vc[k * B + b] = v;
+    }
+    flag(status, st);
+}
+
+// ---------------------------------------------------------------------------
 // Host-side validation and launch helpers
 
 thread_local int g_last_hip = 0;
@@ -3095,6 +3292,130 @@ int mpcd_graph_destroy(void *graph_exec)
 {
     if (!graph_exec) return MPCD_EINVAL;
     return hip_check(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
+}
+
+// ---- harmonic-bond comparator ----
+
+static HarmDev make_harmdev(const mpcd_sys *sys, const mpcd_harm *h)
+{
+    HarmDev d;
+    d.B = sys->n_bodies;
+    d.S = sys->n_sites;
+    d.site_off = h->site_off;
+    d.site_body = h->site_body;
+    d.adj_off = h->adj_off;
+    d.adj = h->adj;
+    d.adj_r0 = h->adj_r0;
+    d.rc0 = h->rc0;
+    d.site_m = h->site_m;
+    d.vc = h->vc;
+    d.fs = h->fs;
+    d.fc = h->fc;
+    d.imgs = h->imgs;
+    d.imgc = h->imgc;
+    d.mc = h->mc;
+    d.kb = h->kb;
+    return d;
+}
+
+static int harm_checks(const mpcd_sys *sys, const mpcd_harm *h, const double *xs, const mpcd_wca *wca, void *ws,
+                       size_t ws_bytes)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    TRY(wca_check(wca));
+    if (!h || sys->prec != MPCD_F64) return h ? MPCD_ENOTSUP : MPCD_EINVAL;
+    if (wca->mode == 2) return MPCD_ENOTSUP;
+    const int64_t S = sys->n_sites, B = sys->n_bodies;
+    if (!ok_arr(xs, S, 8) || !ok_arr(h->xs_alt, S, 8) || !ok_arr(h->xc, B, 8) || !ok_arr(h->xc_alt, B, 8) ||
+        !ok_arr(h->vc, B, 8) || !ok_arr(h->fs, S, 8) || !ok_arr(h->fc, B, 8) || !ok_arr(h->imgs, S, 4) ||
+        !ok_arr(h->imgc, B, 4) || !ok_arr(h->site_off, B + 1, 8) || !ok_arr(h->site_body, S, 4) ||
+        !ok_arr(h->adj_off, S + 1, 8) || !ok_arr(h->rc0, S, 8) || !ok_arr(h->site_m, S, 8))
+        return MPCD_EINVAL;
+    if (!(h->mc > 0.0) || !(h->kb >= 0.0)) return MPCD_EINVAL;
+    return MPCD_OK;
+}
+
+static void launch_harm(const Ctx &c, hipStream_t st, const mpcd_harm *h, const mpcd_wca &wca, const double *xs_in,
+                        double *xs_out, double *vs, const double *xc_in, double *xc_out, double dt, int phase)
+{
+    const int64_t S = c.sys->n_sites, B = c.sys->n_bodies;
+    const int nsb = (int)((S + BODY_T - 1) / BODY_T);
+    if (nsb + B == 0) return;
+    hipLaunchKernelGGL(k_harm_substep, dim3((unsigned)(nsb + B)), dim3(BODY_T), 0, st, c.sd, make_harmdev(c.sys, h),
+                       wca, xs_in, xs_out, vs, xc_in, xc_out, dt, phase, nsb, c.status);
+}
+
+int harm_forces(void *stream, const mpcd_sys *sys, const mpcd_harm *h, const double *xs, const mpcd_wca *wca,
+                void *ws, size_t ws_bytes)
+{
+    TRY(harm_checks(sys, h, xs, wca, ws, ws_bytes));
+    launch_harm(make_ctx(sys, ws), (hipStream_t)stream, h, *wca, xs, nullptr, nullptr, h->xc, nullptr, 1.0, 3);
+    return launch_check();
+}
+
+int harm_md(void *stream, const mpcd_sys *sys, const mpcd_harm *h, double *xs, double *vs, const mpcd_wca *wca,
+            double dt, int32_t nsub, void *ws, size_t ws_bytes)
+{
+    TRY(harm_checks(sys, h, xs, wca, ws, ws_bytes));
+    if (!ok_arr(vs, sys->n_sites, 8) || !(dt > 0.0) || nsub < 2 || (nsub & 1)) return MPCD_EINVAL;
+    const Ctx c = make_ctx(sys, ws);
+    hipStream_t st = (hipStream_t)stream;
+    double *xsb[2] = {xs, h->xs_alt}, *xcb[2] = {h->xc, h->xc_alt};
+    launch_harm(c, st, h, *wca, xsb[0], xsb[1], vs, xcb[0], xcb[1], dt, 0);
+    for (int i = 1; i < nsub; ++i)
+        launch_harm(c, st, h, *wca, xsb[i & 1], xsb[(i + 1) & 1], vs, xcb[i & 1], xcb[(i + 1) & 1], dt, 1);
+    launch_harm(c, st, h, *wca, xsb[0], nullptr, vs, xcb[0], nullptr, dt, 2);
+    return launch_check();
+}
+
+// One collision period of the harmonic model: bin solvent and surface sites,
+// per-cell draws, collision (the surface sites as heavy solvent) fused with the
+// solvent streaming, nsub Verlet steps of dt_md for the sites, step counter.
+int harm_step(void *stream, const mpcd_step_args *a, const mpcd_harm *h, double dt_md, int32_t nsub)
+{
+    if (!a || !a->sys) return MPCD_EINVAL;
+    const mpcd_sys *s = a->sys;
+    const mpcd_params &p = a->par;
+    TRY(harm_checks(s, h, (const double *)a->xs, &p.wca, a->ws, a->ws_bytes));
+    if (!p.fuse_stream || p.thermalize) return MPCD_ENOTSUP;
+    TRY(out_checks(s, a->v, a->tag, a->x, a->x_out, a->v_out, a->tag_out));
+    TRY(mpcd_bin(stream, s, a->x, a->xs, &a->bodies, p.seed, a->d_step, a->ws, a->ws_bytes));
+    TRY(mpcd_cell_draws(stream, s, p.kT_cell, p.seed, a->d_step, a->ws, a->ws_bytes));
+    TRY(mpcd_collide_drawn(stream, s, a->v, a->tag, a->vs, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, a->d_step,
+                           a->ws, a->ws_bytes, a->x, p.dt, a->x_out, a->v_out, a->tag_out));
+    TRY(harm_md(stream, s, h, (double *)a->xs, (double *)a->vs, &p.wca, dt_md, nsub, a->ws, a->ws_bytes));
+    return mpcd_advance_step(stream, a->d_step);
+}
+
+int harm_graph_create(void *stream, const mpcd_step_args *args, const mpcd_harm *h, double dt_md, int32_t nsub,
+                      int32_t nperiods, void **graph_exec)
+{
+    if (!stream || !args || !h || nperiods < 1 || !graph_exec) return MPCD_EINVAL;
+    if (args->v_out && ((nperiods & 1) || !args->tag)) return MPCD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    mpcd_step_args swapped = *args;
+    if (args->v_out) {
+        swapped.x = args->x_out;
+        swapped.v = args->v_out;
+        swapped.tag = args->tag_out;
+        swapped.x_out = args->x;
+        swapped.v_out = args->v;
+        swapped.tag_out = (int32_t *)args->tag;
+    }
+    TRY(hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)));
+    int rc = MPCD_OK;
+    for (int i = 0; i < nperiods && rc == MPCD_OK; ++i)
+        rc = harm_step(stream, (args->v_out && (i & 1)) ? &swapped : args, h, dt_md, nsub);
+    hipGraph_t graph = nullptr;
+    const int rc_end = hip_check(hipStreamEndCapture(st, &graph));
+    if (rc == MPCD_OK) rc = rc_end;
+    hipGraphExec_t exec = nullptr;
+    if (rc == MPCD_OK) rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    if (graph) (void)hipGraphDestroy(graph);
+    TRY(rc);
+    *graph_exec = (void *)exec;
+    return MPCD_OK;
 }
 
 int mpcd_status(void *stream, const void *ws, size_t ws_bytes, uint32_t *flags)

@@ -20,7 +20,8 @@ EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mp
            "mpcd_cell_draws", "mpcd_collide_drawn",
            "sites_thermalize", "sites_to_body", "body_integrate", "body_forces",
            "mpcd_advance_step", "mpcd_step", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
-           "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error")
+           "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error",
+           "harm_forces", "harm_md", "harm_step", "harm_graph_create")
 
 vp = C.c_void_p
 
@@ -54,6 +55,13 @@ class MpcdStepArgs(C.Structure):
                 ("xs", vp), ("vs", vp), ("J", vp), ("K", vp), ("d_step", vp), ("ws", vp),
                 ("ws_bytes", C.c_size_t), ("par", MpcdParams), ("reorder_every", C.c_int32),
                 ("x_out", vp), ("v_out", vp), ("tag_out", vp)]
+
+
+class MpcdHarm(C.Structure):
+    _fields_ = [("xs_alt", vp), ("xc", vp), ("xc_alt", vp), ("vc", vp), ("fs", vp), ("fc", vp),
+                ("imgs", vp), ("imgc", vp), ("mc", C.c_double), ("kb", C.c_double),
+                ("site_off", vp), ("site_body", vp), ("adj_off", vp), ("adj", vp), ("adj_r0", vp),
+                ("rc0", vp), ("site_m", vp)]
 
 
 _lib = None
@@ -94,6 +102,11 @@ def load(path: str = LIB_PATH):
         "mpcd_graph_destroy": (C.c_int, [vp]),
         "mpcd_status": (C.c_int, [vp, vp, sz, C.POINTER(C.c_uint32)]),
         "mpcd_last_hip_error": (C.c_int, []),
+        "harm_forces": (C.c_int, [vp, sp, C.POINTER(MpcdHarm), vp, wp, vp, sz]),
+        "harm_md": (C.c_int, [vp, sp, C.POINTER(MpcdHarm), vp, vp, wp, dbl, i32, vp, sz]),
+        "harm_step": (C.c_int, [vp, C.POINTER(MpcdStepArgs), C.POINTER(MpcdHarm), dbl, i32]),
+        "harm_graph_create": (C.c_int, [vp, C.POINTER(MpcdStepArgs), C.POINTER(MpcdHarm), dbl, i32, i32,
+                                        C.POINTER(vp)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -325,3 +325,122 @@ class GPUSystem:
                             T=g["torque"][:, b0:b1], xs=g["xs"][:, s0:s1].astype(np.float64),
                             vs=g["vs"][:, s0:s1].astype(np.float64), J=g["J"][:, b0:b1], K=g["K"][:, b0:b1]))
         return out
+
+
+class HarmonicGPU:
+    """Device state of the harmonic-bond comparator (one system; see
+    workloads.harmonic_from_rigid), FP64, out-of-place solvent."""
+
+    def __init__(self, hw: dict, params: dict, device: str = "cuda:0"):
+        self.lib = L.load()
+        dev = self.device = torch.device(device)
+        self.params = dict(params)
+        f64 = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+        i32 = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.int32), device=dev)
+        i64 = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.int64), device=dev)
+        ncell = np.array(hw["ncell"], dtype=np.int32)
+        self.N, self.S, self.B = hw["x"].shape[1], hw["xs"].shape[1], hw["xc"].shape[1]
+        self.C = int(np.prod(ncell))
+        self.ncell = i32(ncell)
+        self.solv_off = i64([0, self.N])
+        self.cell_off = i64([0, self.C])
+        self.body_off = i64([0, self.B])
+        self.x, self.v = f64(hw["x"]), f64(hw["v"])
+        self.x2, self.v2 = torch.empty_like(self.x), torch.empty_like(self.v)
+        self.tag = torch.arange(self.N, dtype=torch.int32, device=dev)
+        self.tag2 = torch.empty_like(self.tag)
+        self.xs, self.vs = f64(hw["xs"]), f64(hw["vs"])
+        self.xs_alt = torch.empty_like(self.xs)
+        self.xc, self.vc = f64(hw["xc"]), f64(hw["vc"])
+        self.xc_alt = torch.empty_like(self.xc)
+        self.fs, self.fc = torch.zeros_like(self.xs), torch.zeros_like(self.xc)
+        self.imgs, self.imgc = i32(hw["imgs"]), i32(hw["imgc"])
+        self.site_off, self.site_body = i64(hw["site_off"]), i32(hw["site_body"])
+        self.adj_off, self.adj, self.adj_r0 = i64(hw["adj_off"]), i32(hw["adj"]), f64(hw["adj_r0"])
+        self.rc0, self.site_m = f64(hw["rc0"]), f64(hw["sm"])
+        self.d_step = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.csys = L.MpcdSys(nsys=1, prec=L.MPCD_F64, a=float(hw["a"]), m_solvent=float(hw["m"]), n_solvent=self.N,
+                              n_sites=self.S, n_bodies=self.B, n_cells=self.C, replica0=0,
+                              ncell=_ptr(self.ncell), solv_off=_ptr(self.solv_off), cell_off=_ptr(self.cell_off),
+                              body_off=_ptr(self.body_off))
+        self.ws_bytes = int(self.lib.mpcd_workspace_bytes(C.byref(self.csys)))
+        if self.ws_bytes == 0:
+            raise L.MpcdError("invalid system description")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.ch = L.MpcdHarm(xs_alt=_ptr(self.xs_alt), xc=_ptr(self.xc), xc_alt=_ptr(self.xc_alt), vc=_ptr(self.vc),
+                             fs=_ptr(self.fs), fc=_ptr(self.fc), imgs=_ptr(self.imgs), imgc=_ptr(self.imgc),
+                             mc=float(hw["mc"]), kb=float(hw["kb"]), site_off=_ptr(self.site_off),
+                             site_body=_ptr(self.site_body), adj_off=_ptr(self.adj_off), adj=_ptr(self.adj),
+                             adj_r0=_ptr(self.adj_r0), rc0=_ptr(self.rc0), site_m=_ptr(self.site_m))
+        self.cbodies = L.MpcdBodies(site_off=_ptr(self.site_off), site_body=_ptr(self.site_body),
+                                    site_m=_ptr(self.site_m))
+        w = self.params.get("wca", {"mode": 0})
+        self.cwca = L.MpcdWca(mode=int(w.get("mode", 0)), eps=float(w.get("eps", 0.0)),
+                              sigma=float(w.get("sigma", 0.0)), delta=float(w.get("delta", 0.0)), reach=0.0)
+        L.check(self.lib.mpcd_ws_init(self.stream, C.byref(self.csys), _ptr(self.ws), self.ws_bytes), "mpcd_ws_init")
+        self._graph = None
+
+    @property
+    def stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forces(self):
+        L.check(self.lib.harm_forces(self.stream, C.byref(self.csys), C.byref(self.ch), _ptr(self.xs),
+                                     C.byref(self.cwca), _ptr(self.ws), self.ws_bytes), "harm_forces")
+
+    def args(self) -> L.MpcdStepArgs:
+        p = self.params
+        par = L.MpcdParams(dt=p["dt"], cos_a=p["cos_a"], sin_a=p["sin_a"], kT=p["kT"], kT_cell=p["kT_cell"],
+                           seed=p["seed"], thermalize=0, fuse_stream=1, wca=self.cwca)
+        self._args = L.MpcdStepArgs(sys=C.pointer(self.csys), bodies=self.cbodies, x=_ptr(self.x), v=_ptr(self.v),
+                                    tag=_ptr(self.tag), xs=_ptr(self.xs), vs=_ptr(self.vs), d_step=_ptr(self.d_step),
+                                    ws=_ptr(self.ws), ws_bytes=self.ws_bytes, par=par, x_out=_ptr(self.x2),
+                                    v_out=_ptr(self.v2), tag_out=_ptr(self.tag2))
+        return self._args
+
+    def step(self, dt_md: float, nsub: int, n: int = 1):
+        for _ in range(n):
+            a = self.args()
+            L.check(self.lib.harm_step(self.stream, C.byref(a), C.byref(self.ch), float(dt_md), int(nsub)),
+                    "harm_step")
+            self.x, self.x2 = self.x2, self.x
+            self.v, self.v2 = self.v2, self.v
+            self.tag, self.tag2 = self.tag2, self.tag
+
+    def graph(self, dt_md: float, nsub: int, nperiods: int):
+        if nperiods % 2:
+            raise ValueError("out-of-place graphs capture an even number of periods")
+        self.release_graph()
+        a = self.args()
+        h = C.c_void_p(0)
+        L.check(self.lib.harm_graph_create(self.stream, C.byref(a), C.byref(self.ch), float(dt_md), int(nsub),
+                                           int(nperiods), C.byref(h)), "harm_graph_create")
+        self._graph = h
+        self._graph_args = a
+        return h
+
+    def graph_launch(self):
+        L.check(self.lib.mpcd_graph_launch(self.stream, self._graph), "mpcd_graph_launch")
+
+    def release_graph(self):
+        if self._graph is not None:
+            self.lib.mpcd_graph_destroy(self._graph)
+            self._graph = None
+
+    def status(self) -> int:
+        f = C.c_uint32(0)
+        L.check(self.lib.mpcd_status(self.stream, _ptr(self.ws), self.ws_bytes, C.byref(f)), "mpcd_status")
+        return int(f.value)
+
+    def download(self):
+        torch.cuda.synchronize(self.device)
+        tag = self.tag.cpu().numpy().astype(np.int64)
+        out = {}
+        for k in ("x", "v"):
+            a = getattr(self, k).cpu().numpy()
+            b = np.empty_like(a)
+            b[:, tag] = a
+            out[k] = b
+        for k in ("xs", "vs", "xc", "vc", "fs", "fc", "imgs", "imgc"):
+            out[k] = getattr(self, k).cpu().numpy()
+        return out

@@ -492,3 +492,69 @@ def test_fp32_full_size_within_1e5():
     say("fp32 full size rel err %.3e, excluded %d of %d" % (rel, nbad, nt))
     assert rel <= 1e-5
     assert nbad <= 0.001 * nt
+
+
+# ---------------------------------------------------------------------------
+# Harmonic-bond comparator (Sec. II.B.1)
+
+def harmonic_gpu(*a, **k):
+    from paper_2604_14307_amd.sim import HarmonicGPU
+    return HarmonicGPU(*a, **k)
+
+
+HARM_KEYS = ("x", "v", "xs", "vs", "xc", "vc", "fs", "fc", "imgs", "imgc")
+
+
+def harmonic_parity(hw, par, nper, nsub=50, dt_md=0.002):
+    o = oracle.HarmonicOracle(hw, par)
+    g = harmonic_gpu(hw, par)
+    assert o.forces() == 0
+    g.forces()
+    assert_same(o, g.download(), ("fs", "fc"), "harmonic forces")
+    for n in range(nper):
+        assert o.step(n, dt_md, nsub) == 0
+        g.step(dt_md, nsub)
+        assert_same(o, g.download(), HARM_KEYS, "harmonic period %d" % n)
+    assert g.status() == 0
+    return o, g
+
+
+def test_harmonic_single_sphere_bit_exact():
+    wl, par, _ = W.config(0, kT_cell=1.0)
+    say("harmonic single sphere")
+    harmonic_parity(W.harmonic_from_rigid(wl), dict(par, thermalize=0), 6)
+
+
+def test_harmonic_spheres_in_contact_bit_exact():
+    wl = W.suspension((12, 12, 12), 3, 2, 1.5, 40, 5.0, seed=75)
+    wl["R"][:, 0] = (4.0, 6.0, 6.0)
+    wl["R"][:, 1] = (7.9, 6.3, 6.1)
+    par = dict(W.srd_params(75, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0)), thermalize=0)
+    say("harmonic spheres in contact")
+    o, g = harmonic_parity(W.harmonic_from_rigid(wl), par, 4)
+    assert np.abs(o.fc).max() > 0
+
+
+def test_harmonic_graph_matches_eager():
+    wl, par, _ = W.config(0, kT_cell=1.0)
+    hw, par = W.harmonic_from_rigid(wl), dict(par, thermalize=0)
+    ge, gg = harmonic_gpu(hw, par), harmonic_gpu(hw, par)
+    ge.forces()
+    gg.forces()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        gg.graph(0.002, 50, 2)
+        for rep in range(3):
+            gg.graph_launch()
+            ge.step(0.002, 50, 2)
+            a, b = ge.download(), gg.download()
+            for k in HARM_KEYS:
+                assert np.array_equal(a[k], b[k]), (rep, k)
+        gg.release_graph()
+
+
+def test_harmonic_full_size_one_period_bit_exact():
+    wl, par, _ = W.config(1, kT_cell=1.0)
+    say("harmonic 60^3")
+    harmonic_parity(W.harmonic_from_rigid(wl), dict(par, thermalize=0), 1)
