@@ -136,6 +136,49 @@ def copy_calibration(nbytes=1 << 30):
     log("copy calibration: 3 copies and 3 scale-by-one passes of %d bytes" % nbytes)
 
 
+def run_harmonic(wl, par, dt_md, nsub, periods, repeats):
+    """Time per collision period of the harmonic-bond comparator (FP64)."""
+    import torch
+    from paper_2604_14307_amd import workloads as W
+    from paper_2604_14307_amd.sim import HarmonicGPU
+
+    g = HarmonicGPU(W.harmonic_from_rigid(wl), dict(par, thermalize=0), device="cuda:0")
+    g.forces()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g.step(dt_md, nsub, 2)
+        g.graph(dt_md, nsub, periods)
+        g.graph_launch()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(repeats):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(side)
+            g.graph_launch()
+            b.record(side)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b) / periods)
+        g.release_graph()
+        flags = g.status()
+    if flags != 0:
+        raise SystemExit("device status flags %d in the harmonic run" % flags)
+    return statistics.median(ms)
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s, %d logical CPUs visible" % (model, os.cpu_count() or 0)
+
+
 def cpu_baseline(wl, par, steps):
     import oracle
     o = oracle.OracleSystem(wl, par)
@@ -168,6 +211,8 @@ def main():
     ap.add_argument("--shapes", action="store_true",
                     help="also run the 128^3 complex-shape suspension (site-site WCA), FP32 and FP64")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-harmonic", action="store_true",
+                    help="skip the rigid-vs-harmonic time per tau on the paper's benchmark geometry")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this implementation drives a single MI355X "
@@ -244,6 +289,23 @@ def main():
             rs = run_gpu(sw, spar, prec, 50, 6, 5, 0)
             out["shapes"][prec] = summary(rs)
         del sw
+    if not args.no_harmonic:
+        hw, hpar, hmeta = W.paper_benchmark(0.1)
+        res_h = {"workload": hmeta["name"],
+                 "protocol": "rigid: one step per collision, dt = 0.1; harmonic: collision every 0.1 tau, "
+                             "50 velocity-Verlet steps of 0.002 between collisions (Sec. II.B.1)"}
+        for prec in ("f64", "f32"):
+            log("paper geometry, rigid %s: 20 timed steps" % prec)
+            rr = run_gpu(hw, hpar, prec, 20, 6, 2, 0)
+            res_h["rigid_%s_ms_per_tau" % prec] = rr["ms_step"] * 10.0
+        log("paper geometry, harmonic FP64: 10 timed collision periods")
+        hper = run_harmonic(hw, hpar, 0.002, 50, 10, 3)
+        res_h["harmonic_f64_ms_per_tau"] = hper * 10.0
+        res_h["speedup_rigid_f64_vs_harmonic_f64"] = res_h["harmonic_f64_ms_per_tau"] / res_h["rigid_f64_ms_per_tau"]
+        res_h["speedup_rigid_f32_vs_harmonic_f64"] = res_h["harmonic_f64_ms_per_tau"] / res_h["rigid_f32_ms_per_tau"]
+        res_h["paper"] = "rigid (dt 0.1) vs harmonic (dt 0.002): nearly an order of magnitude, 1x A100, HOOMD-blue"
+        out["rigid_vs_harmonic"] = res_h
+        del hw
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:
@@ -251,7 +313,8 @@ def main():
         rate, secs = cpu_baseline(wl, par, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
                                "sample": "%d steps of the same 60^3 suspension (FP64 C oracle, one thread, %.1f s)"
-                                         % (args.cpu_steps, secs)}
+                                         % (args.cpu_steps, secs),
+                               "host": host_cpu()}
     print(json.dumps(out), flush=True)
 
 

@@ -2436,8 +2436,8 @@ __global__ __launch_bounds__(BODY_T) void k_harm_substep(SysDev s, HarmDev h, mp
                                                          uint32_t *status)
 {
     __shared__ double sh[3 * SH_PAD];
-    __shared__ int shit[BODY_T];
     __shared__ double fsum[3];
+    __shared__ int s_nhit;
     const int t = threadIdx.x;
     const int64_t S = h.S, B = h.B;
     const double hdt = 0.5 * dt;
@@ -2554,15 +2554,16 @@ __global__ __launch_bounds__(BODY_T) void k_harm_substep(SysDev s, HarmDev h, mp
                         }
                     }
                 }
+                // compact the interacting partners, keeping ascending order
+                const int pos = block_exclusive_scan<BODY_T>(hit, &s_nhit);
+                const int nhit = s_nhit;
+                if (hit) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) sh[k * SH_PAD + t] = c[k];
-                shit[t] = hit;
-                __syncthreads();
-                if (t < 3) {
-                    const int cnt = (int)((je - c0) < BODY_T ? (je - c0) : BODY_T);
-                    for (int i = 0; i < cnt; ++i)
-                        if (shit[i]) f = f + sh[t * SH_PAD + i];
+                    for (int k = 0; k < 3; ++k) sh[k * SH_PAD + pos] = c[k];
                 }
+                __syncthreads();
+                if (t < 3)
+                    for (int i = 0; i < nhit; ++i) f = f + sh[t * SH_PAD + i];
                 __syncthreads();
             }
         }

@@ -482,6 +482,19 @@ def config(i: int, kT_cell: float = 1.0):
     raise ValueError("unknown workload %d" % i)
 
 
+def paper_benchmark(phi=0.1, seed=6, kT_cell=1.0):
+    """The geometry of the paper's rigid-vs-harmonic benchmark (Sec. III.C):
+    a cubic box of edge 120, 5 solvent per cell, colloids of diameter 6 at
+    volume fraction phi (B = round(phi V / (4/3 pi 3^3))), 162 surface sites of
+    mass 5 each (a Fibonacci lattice stands in for the subdivided icosahedron),
+    WCA between centres with sigma = 1, Delta = 5 (Eq. (1))."""
+    nb = int(round(phi * 120 ** 3 / (4.0 / 3.0 * math.pi * 27.0)))
+    wl = suspension((120, 120, 120), 5, nb, 3.0, 162, 5.0, seed=seed)
+    par = srd_params(seed, kT_cell=kT_cell, wca=wca_spheres(sigma=1.0, eps=1.0, delta=5.0))
+    return wl, par, dict(name="paper benchmark geometry: 120^3 cells, 5/cell (8.64M solvent), phi=%g "
+                              "(%d spheres, d=6, 162 sites), WCA sigma=1 Delta=5" % (phi, nb))
+
+
 def batched_replicas(nrep=512, seed=4, lo=12, hi=24, density=5, kT_cell=1.0):
     """Independent cubic boxes with integer edges drawn uniformly from lo..hi."""
     rng = np.random.default_rng(seed)
