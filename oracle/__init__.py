@@ -274,6 +274,24 @@ class OracleSystem:
                                           _p(F), _p(T))
         return F[:, :len(idx)].copy(), T[:, :len(idx)].copy(), flags
 
+    def rnemd(self, y0, y1, dy, target, npairs, dp=0.0, tag=None):
+        """One reverse nonequilibrium exchange (Sec. III.B); returns the updated
+        momentum accumulator and the number of pairs swapped."""
+        L = lib()
+        if not hasattr(L, "_rnemd_ready"):
+            L.orc_rnemd.restype = C.c_uint32
+            L.orc_rnemd.argtypes = [C.POINTER(OrcSys), C.POINTER(C.c_int32), C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+            L._rnemd_ready = True
+        acc = C.c_double(dp)
+        ns = C.c_int64(0)
+        tg = None
+        if tag is not None:
+            self._tag = np.ascontiguousarray(tag, dtype=np.int32)
+            tg = _p(self._tag, C.c_int32)
+        L.orc_rnemd(C.byref(self._sys), tg, y0, y1, dy, target, npairs, C.byref(acc), C.byref(ns))
+        return acc.value, ns.value
+
     def wca_energy(self):
         """Total WCA potential energy of the current body poses, Eq. (1)."""
         return lib().orc_wca_energy(C.byref(self._sys), C.byref(self.par))

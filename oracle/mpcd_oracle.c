@@ -1117,6 +1117,62 @@ uint32_t orc_harm_step(orc_sys *s, orc_harm *h, const orc_par *par, uint64_t ste
 }
 
 /* ------------------------------------------------------------------------- */
+/* Reverse nonequilibrium shear (Sec. III.B, viscosity).  The solvent in the  */
+/* lower slab y0 <= y < y0 + dy whose v_x is closest to +target and in the     */
+/* upper slab y1 <= y < y1 + dy closest to -target are ranked by |v_x -+      */
+/* target| (ties: lower identity first); the first min(npairs, n_lower,       */
+/* n_upper) of each list exchange v_x pairwise.  *dp accumulates the          */
+/* x-momentum moved from the lower to the upper slab, m (v_lower - v_upper)   */
+/* per pair, in rank order.  tag (optional) gives the identities.            */
+typedef struct {
+    double key;
+    int64_t id, k;
+} rn_item;
+
+static int rn_cmp(const void *a, const void *b)
+{
+    const rn_item *x = (const rn_item *)a, *y = (const rn_item *)b;
+    if (x->key < y->key) return -1;
+    if (x->key > y->key) return 1;
+    return (x->id < y->id) ? -1 : (x->id > y->id);
+}
+
+uint32_t orc_rnemd(orc_sys *s, const int32_t *tag, double y0, double y1, double dy, double target,
+                   int64_t npairs, double *dp, int64_t *nswapped)
+{
+    int64_t N = s->N;
+    rn_item *lo = (rn_item *)malloc(sizeof(rn_item) * (size_t)(N > 0 ? N : 1));
+    rn_item *up = (rn_item *)malloc(sizeof(rn_item) * (size_t)(N > 0 ? N : 1));
+    int64_t nl = 0, nu = 0;
+    for (int64_t k = 0; k < N; ++k) {
+        double y = s->x[N + k], vx = s->v[k];
+        int64_t id = tag ? (int64_t)tag[k] : k;
+        if (y >= y0 && y < y0 + dy) {
+            lo[nl].key = fabs(vx - target); lo[nl].id = id; lo[nl].k = k; ++nl;
+        } else if (y >= y1 && y < y1 + dy) {
+            up[nu].key = fabs(vx + target); up[nu].id = id; up[nu].k = k; ++nu;
+        }
+    }
+    qsort(lo, (size_t)nl, sizeof(rn_item), rn_cmp);
+    qsort(up, (size_t)nu, sizeof(rn_item), rn_cmp);
+    int64_t np = npairs;
+    if (nl < np) np = nl;
+    if (nu < np) np = nu;
+    double acc = *dp;
+    for (int64_t i = 0; i < np; ++i) {
+        double vl = s->v[lo[i].k], vu = s->v[up[i].k];
+        acc = acc + s->m * (vl - vu);
+        s->v[lo[i].k] = vu;
+        s->v[up[i].k] = vl;
+    }
+    *dp = acc;
+    *nswapped = np;
+    free(lo);
+    free(up);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* One full step n: thermalize sites, shift, bin, collide, transfer to the    */
 /* bodies, stream the solvent, integrate the bodies.                          */
 uint32_t orc_step(orc_sys *s, const orc_par *par, uint64_t step)

@@ -498,6 +498,45 @@ def test_forcing_changes_total_momentum_by_the_applied_impulse():
 
 
 # ---------------------------------------------------------------------------
+# Reverse nonequilibrium shear (Sec. III.B)
+
+def test_rnemd_swaps_ranked_pairs_by_hand():
+    """Lower slab y in [0, 1): v_x closest to +0.5 first; upper slab y in
+    [5, 6): closest to -0.5 first; ties by identity; two pairs swap v_x."""
+    xs = [[1.0, 0.2, 3.0], [2.0, 0.7, 3.0], [3.0, 0.9, 3.0], [4.0, 0.1, 3.0],   # lower slab
+          [1.0, 5.5, 3.0], [2.0, 5.1, 3.0], [3.0, 5.9, 3.0],                  # upper slab
+          [1.0, 3.0, 3.0]]                                                    # neither
+    vx = [0.6, 0.4, 0.5, -1.0, -0.45, -0.7, -0.1, 0.5]
+    vs = [[v, 0.1 * i, -0.2] for i, v in enumerate(vx)]
+    wl = tiny_system((10, 10, 10), xs, vs)
+    o = oracle.OracleSystem(wl, params())
+    v0 = o.v.copy()
+    dp, n = o.rnemd(0.0, 5.0, 1.0, 0.5, 2)
+    # lower ranks: id 2 (key 0), then ids 0 and 1 tie at 0.1 -> id 0; upper: id 4 (0.05), id 5 (0.2)
+    assert n == 2
+    exp = v0[0].copy()
+    exp[2], exp[4] = v0[0, 4], v0[0, 2]
+    exp[0], exp[5] = v0[0, 5], v0[0, 0]
+    assert np.array_equal(o.v[0], exp)
+    assert np.array_equal(o.v[1:], v0[1:])
+    assert dp == (0.0 + (0.5 - -0.45)) + (0.6 - -0.7)
+
+
+def test_rnemd_pairs_limited_by_smaller_slab_and_conserving():
+    rng = np.random.default_rng(81)
+    wl = W.make_system((6, 12, 6), 5, [], [], np.zeros((0, 4)), rng)
+    o = oracle.OracleSystem(wl, params())
+    p0, e0 = o.v.sum(1), (o.v ** 2).sum()
+    dp, n = o.rnemd(0.0, 6.0, 1.0, 0.5, 10 ** 6)
+    inl = (o.x[1] >= 0) & (o.x[1] < 1)
+    inu = (o.x[1] >= 6) & (o.x[1] < 7)
+    assert n == min(inl.sum(), inu.sum())
+    assert np.allclose(o.v.sum(1), p0, rtol=0, atol=1e-12)
+    assert math.isclose((o.v ** 2).sum(), e0, rel_tol=1e-14)
+    assert dp > 0
+
+
+# ---------------------------------------------------------------------------
 # Harmonic-bond comparator (Sec. II.B.1)
 
 def harmonic_pair(seed=71, density=0):
