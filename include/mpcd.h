@@ -165,6 +165,10 @@ typedef struct {
      * tag (tag must then be non-NULL). */
     void *x_out, *v_out;   /* [3N] (prec)                                        */
     int32_t *tag_out;      /* [N]                                                */
+    /* Optional reverse nonequilibrium exchange after the step (NULL: none):
+     * see mpcd_rnemd_exchange; rnemd_dp is its device accumulator. */
+    const struct mpcd_rnemd_s *rnemd;
+    double *rnemd_dp;
 } mpcd_step_args;
 
 /* Workspace bytes for sys (host-side sizes only).  The workspace holds the cell
@@ -182,7 +186,9 @@ size_t mpcd_workspace_bytes(const mpcd_sys *sys);
  * out[7] site velocities entering the collision [3S] (double). */
 int mpcd_workspace_offsets(const mpcd_sys *sys, int64_t out[8]);
 
-/* Zero the counters and the status word of a fresh workspace. */
+/* Zero the cell counters, the reverse nonequilibrium exchange's histograms
+ * and control words and the status word of a fresh workspace (any prior
+ * contents); every other region is written before it is read. */
 int mpcd_ws_init(void *stream, const mpcd_sys *sys, void *ws, size_t ws_bytes);
 
 /* Streaming, Sec. II.A: x <- wrap(x + v dt) per component, one periodic
@@ -261,6 +267,23 @@ int body_integrate(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies,
  * or NULL): a constant force added at every body centre (Sec. III.B). */
 int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, const mpcd_wca *wca,
                 const double *f_ext, void *ws, size_t ws_bytes);
+
+/* Reverse nonequilibrium shear, Sec. III.B (viscosity): the solvent in the
+ * lower slab y0 <= y < y0 + dy is ranked by |v_x - target| and in the upper slab
+ * y1 <= y < y1 + dy by |v_x + target| (ties: lower identity first); the first
+ * min(npairs, n_lower, n_upper) of each exchange v_x pairwise, and *dp (device
+ * double) accumulates the moved momentum m (v_lower - v_upper), in rank order.
+ * One system (nsys == 1); npairs <= 1024; at most 4096 candidates per slab
+ * within the ranking bins (more set MPCD_FLAG_BINERR).  x, v: [3N] (prec);
+ * tag: [N] identities or NULL (index). */
+typedef struct mpcd_rnemd_s {
+    double y0, y1, dy;     /* slab lower edges and width                         */
+    double target;         /* |target velocity| (0.5 in the paper)               */
+    int32_t npairs;        /* pairs per exchange (100 in the paper)              */
+} mpcd_rnemd;
+
+int mpcd_rnemd_exchange(void *stream, const mpcd_sys *sys, const void *x, void *v, const int32_t *tag,
+                        const mpcd_rnemd *r, double *dp, void *ws, size_t ws_bytes);
 
 /* Harmonic-bond comparator, Sec. II.B.1: a colloid is a centre site plus
  * surface sites; each surface site is bonded to its nearest surface neighbours

@@ -264,7 +264,7 @@ TileCfg tile_config(const mpcd_sys *s)
 
 struct Layout {
     size_t status, shift, counts, partial, cell_start, site_start, cellid, slot, perm, draws, site_d, vpre, rtmp,
-        grid_count, grid_body, wpos, woff, total;
+        grid_count, grid_body, wpos, woff, rn_hist, rn_ctl, rn_key, rn_id, rn_k, total;
     uint32_t grid_mask;
 };
 
@@ -272,6 +272,11 @@ constexpr int SCAN_T = 1024, SCAN_V = 4, SCAN_TILE = SCAN_T * SCAN_V;
 
 // Slots per bucket of the body-centre grid.
 constexpr int GRID_K = 8;
+
+// Reverse nonequilibrium exchange: key histogram bins over [0, RN_KMAX) (the
+// last bin also takes larger keys), candidate capacity per slab, pair limit.
+constexpr int RN_BINS = 4096, RN_CAP = 4096, RN_MAXPAIRS = 1024;
+constexpr double RN_KMAX = 0.4096;
 
 // Binning and reorder chunks: BIN_T threads x BIN_ITEMS entries per block.
 constexpr int BIN_T = 256, BIN_ITEMS = 4, BIN_CHUNK = BIN_T * BIN_ITEMS;
@@ -313,6 +318,13 @@ Layout layout_of(const mpcd_sys *s)
     // site frames for the site-site WCA (offsets and unwrapped positions)
     L.wpos = take(sizeof(double) * 3 * (size_t)s->n_sites);
     L.woff = take(sizeof(double) * 3 * (size_t)s->n_sites);
+    // reverse nonequilibrium exchange: key histograms, control words and
+    // candidate lists of the two slabs
+    L.rn_hist = take(sizeof(int32_t) * 2 * RN_BINS);
+    L.rn_ctl = take(sizeof(int32_t) * 16);
+    L.rn_key = take(sizeof(double) * 2 * RN_CAP);
+    L.rn_id = take(sizeof(int32_t) * 2 * RN_CAP);
+    L.rn_k = take(sizeof(int32_t) * 2 * RN_CAP);
     L.total = off;
     return L;
 }
@@ -2590,6 +2602,179 @@ __global__ __launch_bounds__(BODY_T) void k_harm_substep(SysDev s, HarmDev h, mp
 }
 
 // ---------------------------------------------------------------------------
+// Reverse nonequilibrium shear (Sec. III.B, viscosity).  Solvent in the lower
+// slab y0 <= y < y0 + dy is ranked by |v_x - target|, in the upper slab
+// y1 <= y < y1 + dy by |v_x + target| (ties: lower identity first); the first
+// np = min(npairs, n_lower, n_upper) of each exchange v_x pairwise.
+//  1. k_rn_hist: per slab, member count and a histogram of key bins.
+//  2. k_rn_thresh (one block): per slab, the smallest bin by which np members
+//     have accumulated; every member of the top np lies in a bin <= it.
+//  3. k_rn_collect: the members in those bins (a superset of the top np).
+//  4. k_rn_swap (one block): bitonic sort of each candidate list by (key,
+//     identity), pairwise exchange of the first np, the moved momentum
+//     m (v_lower - v_upper) added in rank order, counters cleared.
+// ctl words: [0..1] members, [2..3] threshold bins, [4..5] candidates, [6] np.
+
+struct RnArgs {
+    double y0, y1, dy, target, m;
+    int npairs;
+    int32_t *hist, *ctl, *id, *kk;
+    double *key;
+};
+
+template <typename Real>
+__device__ __forceinline__ int rn_slab(const RnArgs &R, const Real *x, const Real *v, int64_t N, int64_t k,
+                                       double &key)
+{
+    const double y = (double)x[N + k];
+    const double vx = (double)v[k];
+    if (y >= R.y0 && y < R.y0 + R.dy) {
+        key = fabs(vx - R.target);
+        return 0;
+    }
+    if (y >= R.y1 && y < R.y1 + R.dy) {
+        key = fabs(vx + R.target);
+        return 1;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int rn_bin(double key)
+{
+    const double b = key * ((double)RN_BINS / RN_KMAX);
+    return b < (double)(RN_BINS - 1) ? (int)b : RN_BINS - 1;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_rn_hist(RnArgs R, const Real *x, const Real *v, int64_t N)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
+        double key;
+        const int sl = rn_slab(R, x, v, N, k, key);
+        if (sl >= 0) {
+            atomicAdd(&R.hist[sl * RN_BINS + rn_bin(key)], 1);
+            atomicAdd(&R.ctl[sl], 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rn_thresh(RnArgs R)
+{
+    const int t = threadIdx.x;
+    if (t < 2) {
+        int np = R.npairs;
+        if (R.ctl[0] < np) np = R.ctl[0];
+        if (R.ctl[1] < np) np = R.ctl[1];
+        if (np < 0) np = 0;
+        int cum = 0, b = 0;
+        const int32_t *h = R.hist + t * RN_BINS;
+        while (b < RN_BINS - 1 && cum + h[b] < np) cum += h[b++];
+        R.ctl[2 + t] = (np == 0) ? -1 : b;
+        if (t == 0) R.ctl[6] = np;
+    }
+    __syncthreads();
+    for (int i = t; i < 2 * RN_BINS; i += blockDim.x) R.hist[i] = 0;  // ready for the next exchange
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_rn_collect(RnArgs R, const Real *x, const Real *v, const int32_t *tag,
+                                                    int64_t N, uint32_t *status)
+{
+    uint32_t st = 0;
+    const int th0 = R.ctl[2], th1 = R.ctl[3];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
+        double key;
+        const int sl = rn_slab(R, x, v, N, k, key);
+        if (sl < 0 || rn_bin(key) > (sl ? th1 : th0)) continue;
+        const int pos = atomicAdd(&R.ctl[4 + sl], 1);
+        if (pos >= 0 && pos < RN_CAP) {
+            R.key[sl * RN_CAP + pos] = key;
+            R.id[sl * RN_CAP + pos] = tag ? tag[k] : (int32_t)k;
+            R.kk[sl * RN_CAP + pos] = (int32_t)k;
+        } else {
+            st |= ST_BINERR;
+        }
+    }
+    flag(status, st);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_rn_swap(RnArgs R, Real *v, int64_t N, double *dp, uint32_t *status)
+{
+    __shared__ double sk[RN_CAP];
+    __shared__ int32_t sid[RN_CAP], sk2[RN_CAP];
+    __shared__ int32_t low_k[RN_MAXPAIRS];
+    const int t = threadIdx.x;
+    // pairs to swap: never more than either slab's stored candidates
+    int nc[2];
+    for (int sl = 0; sl < 2; ++sl) {
+        const int n = R.ctl[4 + sl];
+        nc[sl] = n < 0 ? 0 : (n > RN_CAP ? RN_CAP : n);
+    }
+    int np = R.ctl[6];
+    const bool short_list = np > nc[0] || np > nc[1];
+    if (np > nc[0]) np = nc[0];
+    if (np > nc[1]) np = nc[1];
+    if (np > RN_MAXPAIRS) np = RN_MAXPAIRS;
+    if (np < 0) np = 0;
+    for (int sl = 0; sl < 2; ++sl) {
+        const int n = nc[sl];
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int i = t; i < P; i += blockDim.x) {
+            if (i < n) {
+                sk[i] = R.key[sl * RN_CAP + i];
+                sid[i] = R.id[sl * RN_CAP + i];
+                sk2[i] = R.kk[sl * RN_CAP + i];
+            } else {
+                sk[i] = __builtin_inf();
+                sid[i] = 0x7fffffff;
+                sk2[i] = -1;
+            }
+        }
+        __syncthreads();
+        for (int size = 2; size <= P; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = t; i < P; i += blockDim.x) {
+                    const int j = i ^ stride;
+                    if (j > i) {
+                        const bool up = (i & size) == 0;
+                        const bool gt = sk[i] > sk[j] || (sk[i] == sk[j] && sid[i] > sid[j]);
+                        if (gt == up) {
+                            const double a = sk[i]; sk[i] = sk[j]; sk[j] = a;
+                            const int32_t b = sid[i]; sid[i] = sid[j]; sid[j] = b;
+                            const int32_t c = sk2[i]; sk2[i] = sk2[j]; sk2[j] = c;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        if (sl == 0) {
+            for (int i = t; i < np; i += blockDim.x) low_k[i] = sk2[i];
+            __syncthreads();
+        }
+    }
+    if (t == 0) {
+        uint32_t st = short_list ? ST_BINERR : 0u;
+        double acc = *dp;
+        for (int i = 0; i < np; ++i) {
+            const int32_t kl = low_k[i], ku = sk2[i];
+            if (kl < 0 || kl >= N || ku < 0 || ku >= N) {
+                st |= ST_BINERR;
+                continue;
+            }
+            const Real vl = v[kl], vu = v[ku];
+            acc = acc + R.m * ((double)vl - (double)vu);
+            v[kl] = vu;
+            v[ku] = vl;
+        }
+        *dp = acc;
+        flag(status, st);
+    }
+    if (t < 16) R.ctl[t] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Host-side validation and launch helpers
 
 thread_local int g_last_hip = 0;
@@ -2707,6 +2892,11 @@ int mpcd_ws_init(void *stream, const mpcd_sys *sys, void *ws, size_t ws_bytes)
                        at<int32_t>(ws, L.counts), 2 * sys->n_cells, 0);
     if (NT > 0)  // the permutation holds valid particle indices from the start
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NT, 256)), dim3(256), 0, st, at<int32_t>(ws, L.perm), NT, 0);
+    // the exchange's histograms and control words start at zero; each exchange
+    // leaves them at zero for the next
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * RN_BINS, 256)), dim3(256), 0, st, at<int32_t>(ws, L.rn_hist),
+                       (int64_t)(2 * RN_BINS), 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, at<int32_t>(ws, L.rn_ctl), (int64_t)16, 0);
     return launch_check();
 }
 
@@ -3201,6 +3391,58 @@ int mpcd_advance_step(void *stream, uint64_t *d_step)
     return launch_check();
 }
 
+// ---- reverse nonequilibrium exchange ----
+
+static int rnemd_checks(const mpcd_sys *sys, const void *x, const void *v, const int32_t *tag, const mpcd_rnemd *r,
+                        const double *dp, void *ws, size_t ws_bytes)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    if (!r || !dp || !aligned(dp, 8)) return MPCD_EINVAL;
+    if (sys->nsys != 1) return MPCD_ENOTSUP;
+    if (!ok_arr(x, sys->n_solvent, esize(sys)) || !ok_arr(v, sys->n_solvent, esize(sys))) return MPCD_EINVAL;
+    if (tag && !aligned(tag, 4)) return MPCD_EINVAL;
+    if (!(r->dy > 0.0) || r->npairs < 0 || r->npairs > RN_MAXPAIRS) return MPCD_EINVAL;
+    return MPCD_OK;
+}
+
+static void launch_rnemd(const Ctx &c, hipStream_t st, const void *x, void *v, const int32_t *tag,
+                         const mpcd_rnemd *r, double *dp)
+{
+    const int64_t N = c.sys->n_solvent;
+    if (N == 0 || r->npairs == 0) return;
+    RnArgs R;
+    R.y0 = r->y0; R.y1 = r->y1; R.dy = r->dy; R.target = r->target; R.m = c.sys->m_solvent;
+    R.npairs = r->npairs;
+    R.hist = at<int32_t>(c.ws, c.L.rn_hist);
+    R.ctl = at<int32_t>(c.ws, c.L.rn_ctl);
+    R.key = at<double>(c.ws, c.L.rn_key);
+    R.id = at<int32_t>(c.ws, c.L.rn_id);
+    R.kk = at<int32_t>(c.ws, c.L.rn_k);
+    const unsigned g = grid_for(N, 256, 8192);
+    if (c.sys->prec == MPCD_F64) {
+        hipLaunchKernelGGL(k_rn_hist<double>, dim3(g), dim3(256), 0, st, R, (const double *)x, (const double *)v, N);
+        hipLaunchKernelGGL(k_rn_thresh, dim3(1), dim3(256), 0, st, R);
+        hipLaunchKernelGGL(k_rn_collect<double>, dim3(g), dim3(256), 0, st, R, (const double *)x, (const double *)v,
+                           tag, N, c.status);
+        hipLaunchKernelGGL(k_rn_swap<double>, dim3(1), dim3(1024), 0, st, R, (double *)v, N, dp, c.status);
+    } else {
+        hipLaunchKernelGGL(k_rn_hist<float>, dim3(g), dim3(256), 0, st, R, (const float *)x, (const float *)v, N);
+        hipLaunchKernelGGL(k_rn_thresh, dim3(1), dim3(256), 0, st, R);
+        hipLaunchKernelGGL(k_rn_collect<float>, dim3(g), dim3(256), 0, st, R, (const float *)x, (const float *)v,
+                           tag, N, c.status);
+        hipLaunchKernelGGL(k_rn_swap<float>, dim3(1), dim3(1024), 0, st, R, (float *)v, N, dp, c.status);
+    }
+}
+
+int mpcd_rnemd_exchange(void *stream, const mpcd_sys *sys, const void *x, void *v, const int32_t *tag,
+                        const mpcd_rnemd *r, double *dp, void *ws, size_t ws_bytes)
+{
+    TRY(rnemd_checks(sys, x, v, tag, r, dp, ws, ws_bytes));
+    launch_rnemd(make_ctx(sys, ws), (hipStream_t)stream, x, v, tag, r, dp);
+    return launch_check();
+}
+
 static int step_checks(const mpcd_step_args *a)
 {
     if (!a || !a->sys) return MPCD_EINVAL;
@@ -3215,7 +3457,20 @@ static int step_checks(const mpcd_step_args *a)
     if (a->reorder_every < 0 || (a->reorder_every > 0 && !ok_arr(a->tag, s->n_solvent, 4))) return MPCD_EINVAL;
     TRY(out_checks(s, a->v, a->tag, a->x, a->x_out, a->v_out, a->tag_out));
     if (a->v_out && !p.fuse_stream) return MPCD_ENOTSUP;
+    if (a->rnemd)
+        TRY(rnemd_checks(s, a->v_out ? a->x_out : a->x, a->v_out ? a->v_out : a->v, a->tag, a->rnemd, a->rnemd_dp,
+                         a->ws, a->ws_bytes));
     return MPCD_OK;
+}
+
+// Reverse nonequilibrium exchange at the end of a step, on the new solvent.
+static void step_rnemd(const Ctx &c, hipStream_t st, const mpcd_step_args *a)
+{
+    if (!a->rnemd) return;
+    if (a->v_out)
+        launch_rnemd(c, st, a->x_out, a->v_out, a->tag_out, a->rnemd, a->rnemd_dp);
+    else
+        launch_rnemd(c, st, a->x, a->v, a->tag, a->rnemd, a->rnemd_dp);
 }
 
 // One step: [thermalize + site binning | solvent binning] (one launch), scan,
@@ -3243,10 +3498,12 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
     if (!p.fuse_stream) TRY(mpcd_stream(stream, s, a->x, a->v, p.dt, p.g, a->ws, a->ws_bytes));
     if (s->n_bodies == 0) {
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a->d_step);
+        step_rnemd(c, st, a);
         return launch_check();
     }
     launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt, p.wca);
     launch_forces(c, st, &a->bodies, p.wca, p.f_ext, p.dt, 1, a->d_step);
+    step_rnemd(c, st, a);
     return launch_check();
 }
 

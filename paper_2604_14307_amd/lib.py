@@ -21,7 +21,7 @@ EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mp
            "sites_thermalize", "sites_to_body", "body_integrate", "body_forces",
            "mpcd_advance_step", "mpcd_step", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
            "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error",
-           "harm_forces", "harm_md", "harm_step", "harm_graph_create")
+           "harm_forces", "harm_md", "harm_step", "harm_graph_create", "mpcd_rnemd_exchange")
 
 vp = C.c_void_p
 
@@ -50,11 +50,17 @@ class MpcdParams(C.Structure):
                 ("fuse_stream", C.c_int32), ("wca", MpcdWca), ("g", C.c_double * 3), ("f_ext", C.c_double * 3)]
 
 
+class MpcdRnemd(C.Structure):
+    _fields_ = [("y0", C.c_double), ("y1", C.c_double), ("dy", C.c_double), ("target", C.c_double),
+                ("npairs", C.c_int32)]
+
+
 class MpcdStepArgs(C.Structure):
     _fields_ = [("sys", C.POINTER(MpcdSys)), ("bodies", MpcdBodies), ("x", vp), ("v", vp), ("tag", vp),
                 ("xs", vp), ("vs", vp), ("J", vp), ("K", vp), ("d_step", vp), ("ws", vp),
                 ("ws_bytes", C.c_size_t), ("par", MpcdParams), ("reorder_every", C.c_int32),
-                ("x_out", vp), ("v_out", vp), ("tag_out", vp)]
+                ("x_out", vp), ("v_out", vp), ("tag_out", vp), ("rnemd", C.POINTER(MpcdRnemd)),
+                ("rnemd_dp", vp)]
 
 
 class MpcdHarm(C.Structure):
@@ -102,6 +108,7 @@ def load(path: str = LIB_PATH):
         "mpcd_graph_destroy": (C.c_int, [vp]),
         "mpcd_status": (C.c_int, [vp, vp, sz, C.POINTER(C.c_uint32)]),
         "mpcd_last_hip_error": (C.c_int, []),
+        "mpcd_rnemd_exchange": (C.c_int, [vp, sp, vp, vp, vp, C.POINTER(MpcdRnemd), vp, vp, sz]),
         "harm_forces": (C.c_int, [vp, sp, C.POINTER(MpcdHarm), vp, wp, vp, sz]),
         "harm_md": (C.c_int, [vp, sp, C.POINTER(MpcdHarm), vp, vp, wp, dbl, i32, vp, sz]),
         "harm_step": (C.c_int, [vp, C.POINTER(MpcdStepArgs), C.POINTER(MpcdHarm), dbl, i32]),

@@ -127,14 +127,20 @@ class GPUSystem:
                               sigma=float(w.get("sigma", 0.0)), delta=float(w.get("delta", 0.0)),
                               reach=float(w.get("reach", reach)))
         self.fuse_stream = bool(fuse_stream)
-        L.check(self.lib.mpcd_ws_init(self.stream, C.byref(self.csys), _ptr(self.ws), self.ws_bytes),
-                "mpcd_ws_init")
+        # optional reverse nonequilibrium exchange after every step
+        self.rnemd = None
+        self.rnemd_dp = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.ws_init()
         self._graph = None
 
     # ------------------------------------------------------------------
     @property
     def stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def ws_init(self):
+        L.check(self.lib.mpcd_ws_init(self.stream, C.byref(self.csys), _ptr(self.ws), self.ws_bytes),
+                "mpcd_ws_init")
 
     def set_step(self, n: int):
         self.d_step.fill_(int(n))
@@ -152,8 +158,21 @@ class GPUSystem:
                                     ws_bytes=self.ws_bytes, par=par, reorder_every=int(reorder_every),
                                     x_out=_ptr(self.x2) if out else C.c_void_p(0),
                                     v_out=_ptr(self.v2) if out else C.c_void_p(0),
-                                    tag_out=_ptr(self.tag2) if out else C.c_void_p(0))
+                                    tag_out=_ptr(self.tag2) if out else C.c_void_p(0),
+                                    rnemd=C.pointer(self.rnemd) if self.rnemd is not None else None,
+                                    rnemd_dp=_ptr(self.rnemd_dp))
         return self._args
+
+    def set_rnemd(self, y0, y1, dy=1.0, target=0.5, npairs=100):
+        """Exchange after every step (Sec. III.B); None-like npairs=0 turns it off."""
+        self.rnemd = L.MpcdRnemd(y0=float(y0), y1=float(y1), dy=float(dy), target=float(target),
+                                 npairs=int(npairs)) if npairs else None
+
+    def rnemd_exchange(self, y0, y1, dy=1.0, target=0.5, npairs=100):
+        r = L.MpcdRnemd(y0=float(y0), y1=float(y1), dy=float(dy), target=float(target), npairs=int(npairs))
+        L.check(self.lib.mpcd_rnemd_exchange(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.v),
+                                             _ptr(self.tag), C.byref(r), _ptr(self.rnemd_dp), _ptr(self.ws),
+                                             self.ws_bytes), "mpcd_rnemd_exchange")
 
     def _vec(self, key):
         return (C.c_double * 3)(*[float(a) for a in self.params.get(key, (0.0, 0.0, 0.0))])

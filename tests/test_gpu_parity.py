@@ -558,3 +558,86 @@ def test_harmonic_full_size_one_period_bit_exact():
     wl, par, _ = W.config(1, kT_cell=1.0)
     say("harmonic 60^3")
     harmonic_parity(W.harmonic_from_rigid(wl), dict(par, thermalize=0), 1)
+
+
+# ---------------------------------------------------------------------------
+# Reverse nonequilibrium shear (Sec. III.B)
+
+@pytest.mark.parametrize("bodies", [False, True])
+def test_rnemd_exchange_bit_exact(bodies):
+    if bodies:
+        wl = W.suspension((8, 16, 8), 5, 2, 1.5, 40, 5.0, seed=82)
+        par = W.srd_params(82, kT_cell=1.0, wca=W.wca_spheres(sigma=3.0))
+    else:
+        wl = W.make_system((8, 16, 8), 5, [], [], np.zeros((0, 4)), np.random.default_rng(83))
+        par = W.srd_params(83, kT_cell=1.0)
+    o = oracle.OracleSystem(wl, par)
+    g = gpu_system(wl, par, prec="f64")
+    o.body_forces()
+    g.body_forces()
+    g.set_rnemd(0.0, 8.0, 1.0, 0.5, 12)
+    dp = 0.0
+    say("rnemd bodies=%s" % bodies)
+    for n in range(30):
+        assert o.step(n) == 0
+        dp, ns = o.rnemd(0.0, 8.0, 1.0, 0.5, 12, dp)
+        assert ns == 12
+        g.step(1)
+        if n % 5 == 4:
+            assert_same(o, g.download()[0], ("x", "v", "P", "p"), "rnemd step %d" % n)
+            assert float(g.rnemd_dp.cpu()[0]) == dp
+    assert g.status() == 0
+
+
+# The exchange's state occupies the end of the workspace: key-bin histograms
+# (2 x 4096 int32), 16 control words (padded to 256 bytes), then the candidate
+# keys, identities and indices (2 x 4096 each).
+RN_TAIL = 2 * 4096 * 4 + 256 + 2 * 4096 * 8 + 2 * 4096 * 4 + 2 * 4096 * 4
+
+
+def test_rnemd_from_dirty_workspace():
+    """A workspace with arbitrary prior contents: initialisation must leave the
+    exchange's histograms and counters at zero, and the exchange then matches
+    the oracle bit for bit."""
+    wl = W.make_system((8, 16, 8), 5, [], [], np.zeros((0, 4)), np.random.default_rng(85))
+    par = W.srd_params(85, kT_cell=1.0)
+    o = oracle.OracleSystem(wl, par)
+    g = gpu_system(wl, par, prec="f64")
+    assert g.ws_bytes == g.ws.numel() and g.ws_bytes > RN_TAIL
+    g.ws[g.ws_bytes - RN_TAIL:].fill_(0xFF)
+    g.ws_init()
+    tail = g.ws[g.ws_bytes - RN_TAIL:].cpu().numpy()
+    state = tail[:2 * 4096 * 4 + 64].view(np.int32)
+    assert not state.any(), "exchange state not cleared by initialisation"
+    g.set_rnemd(0.0, 8.0, 1.0, 0.5, 16)
+    dp = 0.0
+    for n in range(8):
+        assert o.step(n) == 0
+        dp, ns = o.rnemd(0.0, 8.0, 1.0, 0.5, 16, dp)
+        g.step(1)
+    assert_same(o, g.download()[0], ("x", "v"), "dirty workspace")
+    assert float(g.rnemd_dp.cpu()[0]) == dp
+    assert g.status() == 0
+
+
+@pytest.mark.parametrize("exchange", [False, True])
+def test_solvent_graph_matches_eager(exchange):
+    wl = W.make_system((8, 16, 8), 5, [], [], np.zeros((0, 4)), np.random.default_rng(84))
+    par = W.srd_params(84, kT_cell=1.0)
+    say("solvent graph exchange=%s" % exchange)
+    ge, gg = gpu_system(wl, par, prec="f64"), gpu_system(wl, par, prec="f64")
+    for g in (ge, gg):
+        if exchange:
+            g.set_rnemd(0.0, 8.0, 1.0, 0.5, 20)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        gg.graph(6)
+        for rep in range(3):
+            gg.graph_launch()
+            ge.step(6)
+            a, b = ge.download()[0], gg.download()[0]
+            assert np.array_equal(a["v"], b["v"]) and np.array_equal(a["x"], b["x"])
+            assert float(ge.rnemd_dp.cpu()[0]) == float(gg.rnemd_dp.cpu()[0])
+        gg.release_graph()
+    assert ge.status() == 0 and gg.status() == 0

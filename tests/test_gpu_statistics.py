@@ -163,3 +163,49 @@ def test_fp32_colloid_temperature_and_diffusivity_agree_with_fp64():
         assert abs(r["ER"] - 1.5) < 4.0 * r["eER"] + 0.02
         assert abs(r["TS"] - 1.0) < 4.0 * r["eTS"] + 2e-3
         assert r["D"] > 0.0
+
+
+# ---------------------------------------------------------------------------
+
+def rnemd_viscosity(prec, nx=16, ny=32, warm=4000, prod=4000, every=10, npairs=10):
+    """Pure solvent, exchange slabs at y in [0, 1) and [ny/2, ny/2 + 1) every
+    step (Sec. III.B): eta = (dp/dt) / (2 A) / (du/dy), with the shear rate
+    from a linear fit of the mass-averaged u_x(y) between the slabs, using
+    the symmetry of the profile."""
+    wl = W.make_system((nx, ny, nx), 5, [], [], np.zeros((0, 4)), np.random.default_rng(91))
+    g = gpu_system(wl, W.srd_params(91, kT_cell=1.0), prec=prec)
+    g.set_rnemd(0.0, ny / 2.0, 1.0, 0.5, npairs)
+    side = torch.cuda.Stream()
+    prof = np.zeros(ny)
+    with torch.cuda.stream(side):
+        g.step(warm)
+        dp0 = float(g.rnemd_dp.cpu()[0])
+        g.graph(every)
+        ns = 0
+        for _ in range(prod // every):
+            g.graph_launch()
+            yb = g.x[1].double().floor().long().clamp_(0, ny - 1)
+            acc = torch.zeros(ny, dtype=torch.float64, device=g.device).index_add_(0, yb, g.v[0].double())
+            cnt = torch.bincount(yb, minlength=ny).double()
+            prof += (acc / cnt).cpu().numpy()
+            ns += 1
+        g.release_graph()
+        dp1 = float(g.rnemd_dp.cpu()[0])
+    assert g.status() == 0
+    prof /= ns
+    # lower slab at y = 0.5 drives u_x toward +..., upper at ny/2 + 0.5; fold the two halves
+    y = np.arange(ny) + 0.5
+    half = ny // 2
+    sel = np.arange(2, half - 1)
+    u = 0.5 * (prof[sel] - prof[(half + sel) % ny])
+    slope = np.polyfit(y[sel], u, 1)[0]
+    rate = (dp1 - dp0) / (prod * 0.1)
+    return abs(rate / (2.0 * nx * nx) / slope)
+
+
+def test_rnemd_viscosity_matches_paper_fp32_and_fp64():
+    e64 = rnemd_viscosity("f64")
+    e32 = rnemd_viscosity("f32")
+    say("RNEMD viscosity FP64 %.3f, FP32 %.3f (paper 3.96)" % (e64, e32))
+    for e in (e64, e32):
+        assert abs(e - 3.96) < 0.35, e
