@@ -74,12 +74,14 @@ def measured_traffic():
         return None
 
 
-def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps):
+def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None):
     import torch
     from paper_2604_14307_amd.sim import GPUSystem
 
     g = GPUSystem(systems, par, prec=prec, device="cuda:0")
     g.body_forces()
+    if rnemd is not None:
+        g.set_rnemd(*rnemd)
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
     per = max(2, 2 * (steps // (2 * repeats)))  # out-of-place graphs hold an even number of steps
@@ -213,6 +215,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-harmonic", action="store_true",
                     help="skip the rigid-vs-harmonic time per tau on the paper's benchmark geometry")
+    ap.add_argument("--no-rnemd", action="store_true",
+                    help="skip the step time with the reverse nonequilibrium exchange appended")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this implementation drives a single MI355X "
@@ -306,6 +310,26 @@ def main():
         res_h["paper"] = "rigid (dt 0.1) vs harmonic (dt 0.002): nearly an order of magnitude, 1x A100, HOOMD-blue"
         out["rigid_vs_harmonic"] = res_h
         del hw
+    if not args.no_rnemd:
+        # slabs of width 1 at y = 0 and y = 30, up to 100 pairs per step (Sec. III.B)
+        rn = (0.0, 30.0, 1.0, 0.5, 100)
+        res_rn = {"workload": "the headline suspension with the exchange after every step: slabs y in [0, 1) "
+                              "and [30, 31), target |v_x| = 0.5, 100 pairs"}
+        for prec in (("f32",) if args.no_fp64 else ("f32", "f64")):
+            log("suspension 60^3 %s with the exchange: 100 timed steps" % prec)
+            rr = run_gpu(wl, par, prec, 100, 6, 2, 0, rnemd=rn)
+            res_rn["%s_ms_per_step" % prec] = rr["ms_step"]
+            res_rn["%s_overhead" % prec] = rr["ms_step"] / res[prec]["ms_step"] - 1.0
+        vw, vpar, vmeta, vrn = W.paper_viscosity(0.1)
+        pv = {"workload": vmeta["name"]}
+        for label, rn_v in (("plain", None), ("exchange", vrn)):
+            log("paper viscosity geometry FP32, %s: 40 timed steps" % label)
+            rv = run_gpu(vw, vpar, "f32", 40, 4, 2, 0, rnemd=rn_v)
+            pv["f32_%s_ms_per_step" % label] = rv["ms_step"]
+        pv["f32_overhead"] = pv["f32_exchange_ms_per_step"] / pv["f32_plain_ms_per_step"] - 1.0
+        res_rn["paper_geometry"] = pv
+        del vw
+        out["rnemd"] = res_rn
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:

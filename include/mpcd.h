@@ -273,9 +273,12 @@ int body_forces(void *stream, const mpcd_sys *sys, const mpcd_bodies *bodies, co
  * y1 <= y < y1 + dy by |v_x + target| (ties: lower identity first); the first
  * min(npairs, n_lower, n_upper) of each exchange v_x pairwise, and *dp (device
  * double) accumulates the moved momentum m (v_lower - v_upper), in rank order.
- * One system (nsys == 1); npairs <= 1024; at most 4096 candidates per slab
- * within the ranking bins (more set MPCD_FLAG_BINERR).  x, v: [3N] (prec);
- * tag: [N] identities or NULL (index). */
+ * One system (nsys == 1); npairs <= 1024.  The ranking reads the members
+ * whose key lies in the key bins (width 1e-4 below 0.4096, then one bin for
+ * all larger keys) up to the bin of the last ranked member: at most 2048 per
+ * slab (more set MPCD_FLAG_BINERR, as in a slab whose ranked members reach the
+ * last bin when that bin is crowded).  x, v: [3N] (prec); tag: [N] distinct
+ * identities or NULL (index). */
 typedef struct mpcd_rnemd_s {
     double y0, y1, dy;     /* slab lower edges and width                         */
     double target;         /* |target velocity| (0.5 in the paper)               */

@@ -275,7 +275,7 @@ constexpr int GRID_K = 8;
 
 // Reverse nonequilibrium exchange: key histogram bins over [0, RN_KMAX) (the
 // last bin also takes larger keys), candidate capacity per slab, pair limit.
-constexpr int RN_BINS = 4096, RN_CAP = 4096, RN_MAXPAIRS = 1024;
+constexpr int RN_BINS = 4096, RN_CAP = 2048, RN_MAXPAIRS = 1024;
 constexpr double RN_KMAX = 0.4096;
 
 // Binning and reorder chunks: BIN_T threads x BIN_ITEMS entries per block.
@@ -2606,13 +2606,17 @@ __global__ __launch_bounds__(BODY_T) void k_harm_substep(SysDev s, HarmDev h, mp
 // slab y0 <= y < y0 + dy is ranked by |v_x - target|, in the upper slab
 // y1 <= y < y1 + dy by |v_x + target| (ties: lower identity first); the first
 // np = min(npairs, n_lower, n_upper) of each exchange v_x pairwise.
-//  1. k_rn_hist: per slab, member count and a histogram of key bins.
+//  1. k_rn_hist: per slab, member count (one atomic per block) and a
+//     histogram of key bins; the last bin holds every key >= RN_KMAX and is
+//     not counted, since a threshold never needs to look past it.
 //  2. k_rn_thresh (one block): per slab, the smallest bin by which np members
-//     have accumulated; every member of the top np lies in a bin <= it.
+//     have accumulated (a block prefix sum over the bins), else the last bin;
+//     every member of the top np lies in a bin <= it.
 //  3. k_rn_collect: the members in those bins (a superset of the top np).
-//  4. k_rn_swap (one block): bitonic sort of each candidate list by (key,
-//     identity), pairwise exchange of the first np, the moved momentum
-//     m (v_lower - v_upper) added in rank order, counters cleared.
+//  4. k_rn_swap (one block): rank of each candidate in the (key, identity)
+//     order, pairwise exchange of the first np (2 np distinct particles, one
+//     thread per pair), the moved momentum m (v_lower - v_upper) added in rank
+//     order, counters cleared.
 // ctl words: [0..1] members, [2..3] threshold bins, [4..5] candidates, [6] np.
 
 struct RnArgs {
@@ -2648,31 +2652,69 @@ __device__ __forceinline__ int rn_bin(double key)
 template <typename Real>
 __global__ __launch_bounds__(256) void k_rn_hist(RnArgs R, const Real *x, const Real *v, int64_t N)
 {
+    __shared__ int s_n[2];
+    if (threadIdx.x < 2) s_n[threadIdx.x] = 0;
+    __syncthreads();
+    int n0 = 0, n1 = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
         double key;
         const int sl = rn_slab(R, x, v, N, k, key);
-        if (sl >= 0) {
-            atomicAdd(&R.hist[sl * RN_BINS + rn_bin(key)], 1);
-            atomicAdd(&R.ctl[sl], 1);
-        }
+        if (sl < 0) continue;
+        const int b = rn_bin(key);
+        if (b < RN_BINS - 1) atomicAdd(&R.hist[sl * RN_BINS + b], 1);
+        n0 += sl == 0;
+        n1 += sl == 1;
     }
+    // slab counts: one global atomic per block and slab
+    if (n0) atomicAdd(&s_n[0], n0);
+    if (n1) atomicAdd(&s_n[1], n1);
+    __syncthreads();
+    if (threadIdx.x < 2 && s_n[threadIdx.x]) atomicAdd(&R.ctl[threadIdx.x], s_n[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void k_rn_thresh(RnArgs R)
 {
+    constexpr int PER = RN_BINS / 256;
+    static_assert(RN_BINS % 256 == 0, "bins per thread");
+    __shared__ int s_b[2], s_tot;
     const int t = threadIdx.x;
-    if (t < 2) {
-        int np = R.npairs;
-        if (R.ctl[0] < np) np = R.ctl[0];
-        if (R.ctl[1] < np) np = R.ctl[1];
-        if (np < 0) np = 0;
-        int cum = 0, b = 0;
-        const int32_t *h = R.hist + t * RN_BINS;
-        while (b < RN_BINS - 1 && cum + h[b] < np) cum += h[b++];
-        R.ctl[2 + t] = (np == 0) ? -1 : b;
-        if (t == 0) R.ctl[6] = np;
+    int np = R.npairs;
+    const int n0 = R.ctl[0], n1 = R.ctl[1];
+    if (n0 < np) np = n0;
+    if (n1 < np) np = n1;
+    if (np < 0) np = 0;
+    if (t < 2) s_b[t] = RN_BINS - 1;
+    int hv[2][PER], sum[2] = {0, 0};
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl)  // both slabs' bins in flight together
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            hv[sl][i] = R.hist[sl * RN_BINS + t * PER + i];
+            sum[sl] += hv[sl][i];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+        const int excl = block_exclusive_scan<256, int>(sum[sl], &s_tot);
+        // the one thread whose bins carry the prefix across np: its first bin
+        // by which np members have accumulated (else its last)
+        if (np > 0 && excl < np && excl + sum[sl] >= np) {
+            int cum = excl, b = PER - 1;
+            bool found = false;
+#pragma unroll
+            for (int i = 0; i < PER - 1; ++i) {
+                if (!found && cum + hv[sl][i] >= np) {
+                    b = i;
+                    found = true;
+                }
+                cum += hv[sl][i];
+            }
+            s_b[sl] = t * PER + b;
+        }
     }
     __syncthreads();
+    if (t < 2) R.ctl[2 + t] = (np == 0) ? -1 : s_b[t];
+    if (t == 0) R.ctl[6] = np;
     for (int i = t; i < 2 * RN_BINS; i += blockDim.x) R.hist[i] = 0;  // ready for the next exchange
 }
 
@@ -2701,9 +2743,10 @@ __global__ __launch_bounds__(256) void k_rn_collect(RnArgs R, const Real *x, con
 template <typename Real>
 __global__ __launch_bounds__(1024) void k_rn_swap(RnArgs R, Real *v, int64_t N, double *dp, uint32_t *status)
 {
-    __shared__ double sk[RN_CAP];
-    __shared__ int32_t sid[RN_CAP], sk2[RN_CAP];
-    __shared__ int32_t low_k[RN_MAXPAIRS];
+    __shared__ double sk[2][RN_CAP];
+    __shared__ int32_t sid[2][RN_CAP], skk[2][RN_CAP];
+    __shared__ int32_t sel[2][RN_MAXPAIRS];  // particle of rank r in each slab
+    __shared__ double s_dm[RN_MAXPAIRS];
     const int t = threadIdx.x;
     // pairs to swap: never more than either slab's stored candidates
     int nc[2];
@@ -2717,59 +2760,74 @@ __global__ __launch_bounds__(1024) void k_rn_swap(RnArgs R, Real *v, int64_t N, 
     if (np > nc[1]) np = nc[1];
     if (np > RN_MAXPAIRS) np = RN_MAXPAIRS;
     if (np < 0) np = 0;
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int i = t; i < 2 * RN_MAXPAIRS; i += blockDim.x) sel[i / RN_MAXPAIRS][i % RN_MAXPAIRS] = -1;
+    // both candidate lists in one round trip, not waiting for the counts
+    // (entries past a list's count are never read)
+    for (int i = t; i < 2 * RN_CAP; i += blockDim.x) {
+        const int sl = i / RN_CAP, j = i % RN_CAP;
+        sk[sl][j] = R.key[i];
+        sid[sl][j] = R.id[i];
+        skk[sl][j] = R.kk[i];
+    }
+    __syncthreads();
+    // rank in the (key, identity) order = number of candidates before it, both
+    // slabs at once; the threads of a wave read the same entry j together (an
+    // LDS broadcast)
+    for (int q = t; q < nc[0] + nc[1]; q += blockDim.x) {
+        const int sl = q < nc[0] ? 0 : 1;
+        const int i = sl ? q - nc[0] : q;
         const int n = nc[sl];
-        int P = 1;
-        while (P < n) P <<= 1;
-        for (int i = t; i < P; i += blockDim.x) {
-            if (i < n) {
-                sk[i] = R.key[sl * RN_CAP + i];
-                sid[i] = R.id[sl * RN_CAP + i];
-                sk2[i] = R.kk[sl * RN_CAP + i];
-            } else {
-                sk[i] = __builtin_inf();
-                sid[i] = 0x7fffffff;
-                sk2[i] = -1;
-            }
-        }
-        __syncthreads();
-        for (int size = 2; size <= P; size <<= 1)
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int i = t; i < P; i += blockDim.x) {
-                    const int j = i ^ stride;
-                    if (j > i) {
-                        const bool up = (i & size) == 0;
-                        const bool gt = sk[i] > sk[j] || (sk[i] == sk[j] && sid[i] > sid[j]);
-                        if (gt == up) {
-                            const double a = sk[i]; sk[i] = sk[j]; sk[j] = a;
-                            const int32_t b = sid[i]; sid[i] = sid[j]; sid[j] = b;
-                            const int32_t c = sk2[i]; sk2[i] = sk2[j]; sk2[j] = c;
-                        }
-                    }
+        const double *sks = sk[sl];
+        const int32_t *sis = sid[sl];
+        {
+            const double ki = sks[i];
+            const int32_t ii = sis[i];
+            int r = 0, j = 0;
+            for (; j + 8 <= n; j += 8) {  // eight reads in flight per wait
+                double kj[8];
+                int32_t ij[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    kj[u] = sks[j + u];
+                    ij[u] = sis[j + u];
                 }
-                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < 8; ++u) r += (int)((kj[u] < ki) | ((kj[u] == ki) & (ij[u] < ii)));
             }
-        if (sl == 0) {
-            for (int i = t; i < np; i += blockDim.x) low_k[i] = sk2[i];
-            __syncthreads();
+            for (; j < n; ++j) r += (int)((sks[j] < ki) | ((sks[j] == ki) & (sis[j] < ii)));
+            if (r < np) sel[sl][r] = skk[sl][i];
         }
     }
-    if (t == 0) {
-        uint32_t st = short_list ? ST_BINERR : 0u;
-        double acc = *dp;
-        for (int i = 0; i < np; ++i) {
-            const int32_t kl = low_k[i], ku = sk2[i];
-            if (kl < 0 || kl >= N || ku < 0 || ku >= N) {
-                st |= ST_BINERR;
-                continue;
-            }
-            const Real vl = v[kl], vu = v[ku];
-            acc = acc + R.m * ((double)vl - (double)vu);
-            v[kl] = vu;
-            v[ku] = vl;
+    __syncthreads();
+    // the 2 np particles are distinct (a particle is in one slab at most, and
+    // once in its slab's list): one thread per pair
+    uint32_t st = (t == 0 && short_list) ? ST_BINERR : 0u;
+    for (int i = t; i < np; i += blockDim.x) {
+        const int32_t kl = sel[0][i], ku = sel[1][i];
+        if (kl < 0 || kl >= N || ku < 0 || ku >= N) {
+            st |= ST_BINERR;
+            s_dm[i] = 0.0;
+            continue;
         }
+        const Real vl = v[kl], vu = v[ku];
+        v[kl] = vu;
+        v[ku] = vl;
+        s_dm[i] = R.m * ((double)vl - (double)vu);
+    }
+    flag(status, st);
+    __syncthreads();
+    if (t == 0) {
+        double acc = *dp;
+        int i = 0;
+        for (; i + 8 <= np; i += 8) {  // rank order; the reads batched
+            double d[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) d[u] = s_dm[i + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = acc + d[u];
+        }
+        for (; i < np; ++i) acc = acc + s_dm[i];
         *dp = acc;
-        flag(status, st);
     }
     if (t < 16) R.ctl[t] = 0;
 }

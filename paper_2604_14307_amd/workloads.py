@@ -495,6 +495,27 @@ def paper_benchmark(phi=0.1, seed=6, kT_cell=1.0):
                               "(%d spheres, d=6, 162 sites), WCA sigma=1 Delta=5" % (phi, nb))
 
 
+def paper_viscosity(phi=0.1, edge=120, seed=7, kT_cell=1.0):
+    """The geometry of the paper's reverse nonequilibrium viscosity runs
+    (Sec. III.B): a cubic suspension of edge `edge` (RSA spheres of diameter 6,
+    162 surface sites of mass 5, WCA sigma = 1, Delta = 5) duplicated along y,
+    so the box is edge x 2 edge x edge with 5 solvent per cell, and the
+    exchange slabs (width 1) at y = 0 and y = edge.  Returns (workload,
+    params, meta, exchange) with exchange = (y0, y1, dy, target, npairs)."""
+    rng = np.random.default_rng(seed)
+    nb = int(round(phi * edge ** 3 / (4.0 / 3.0 * math.pi * 27.0)))
+    half = rsa_positions(rng, np.array([edge, edge, edge], dtype=np.float64), nb, 6.0) if nb else np.zeros((0, 3))
+    centres = np.concatenate([half, half + np.array([0.0, float(edge), 0.0])]) if nb else half
+    tpl = sphere_template(3.0, 162, 5.0)
+    quats = random_quaternions(rng, len(centres))
+    wl = make_system((edge, 2 * edge, edge), 5, [tpl] * len(centres), centres, quats, rng)
+    par = srd_params(seed, kT_cell=kT_cell, wca=wca_spheres(sigma=1.0, eps=1.0, delta=5.0))
+    meta = dict(name="paper viscosity geometry: %d x %d x %d cells, 5/cell (%d solvent), phi=%g "
+                     "(%d spheres, d=6, 162 sites), WCA sigma=1 Delta=5; slabs y=0 and y=%d, 100 pairs"
+                     % (edge, 2 * edge, edge, wl["x"].shape[1], phi, len(centres), edge))
+    return wl, par, meta, (0.0, float(edge), 1.0, 0.5, 100)
+
+
 def batched_replicas(nrep=512, seed=4, lo=12, hi=24, density=5, kT_cell=1.0):
     """Independent cubic boxes with integer edges drawn uniformly from lo..hi."""
     rng = np.random.default_rng(seed)

@@ -591,8 +591,8 @@ def test_rnemd_exchange_bit_exact(bodies):
 
 # The exchange's state occupies the end of the workspace: key-bin histograms
 # (2 x 4096 int32), 16 control words (padded to 256 bytes), then the candidate
-# keys, identities and indices (2 x 4096 each).
-RN_TAIL = 2 * 4096 * 4 + 256 + 2 * 4096 * 8 + 2 * 4096 * 4 + 2 * 4096 * 4
+# keys, identities and indices (2 x 2048 each).
+RN_TAIL = 2 * 4096 * 4 + 256 + 2 * 2048 * 8 + 2 * 2048 * 4 + 2 * 2048 * 4
 
 
 def test_rnemd_from_dirty_workspace():

@@ -209,3 +209,70 @@ def test_rnemd_viscosity_matches_paper_fp32_and_fp64():
     say("RNEMD viscosity FP64 %.3f, FP32 %.3f (paper 3.96)" % (e64, e32))
     for e in (e64, e32):
         assert abs(e - 3.96) < 0.35, e
+
+
+def suspension_viscosity(prec, phi=0.1, n=30, warm=10000, prod=20000, every=100, npairs=6, nblocks=10):
+    """Suspension shear viscosity by the reverse nonequilibrium protocol of
+    Sec. III.B in a box doubled along y (n x 2n x n): slabs of width 1 at y = 0
+    and y = n, exchanges every step, mass-averaged velocity of solvent and
+    colloids in bins of width 0.5, shear rate from the folded profile, and
+    eta = (dp/dt) / (2 A gamma_dot).  npairs scales the paper's 100 pairs per
+    120^2 slab to this slab area.  Returns (eta, block error, shear rate)."""
+    nb = int(round(phi * 2 * n ** 3 / (4.0 / 3.0 * math.pi * 27.0)))
+    wl = W.suspension((n, 2 * n, n), 5, nb, 3.0, 162, 5.0, seed=95)
+    par = W.srd_params(95, kT_cell=1.0, wca=W.wca_spheres(sigma=1.0, eps=1.0, delta=5.0))
+    g = gpu_system(wl, par, prec=prec)
+    g.body_forces()
+    g.set_rnemd(0.0, float(n), 1.0, 0.5, npairs)
+    nbins = 4 * n
+    m = float(wl["m"])
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    per_block = prod // every // nblocks
+    mom_b = np.zeros((nblocks, nbins))
+    dp = []
+    with torch.cuda.stream(side):
+        g.graph(every)
+        for _ in range(warm // every):
+            g.graph_launch()
+        dp.append(float(g.rnemd_dp.cpu()[0]))
+        for b in range(nblocks):
+            for _ in range(per_block):
+                g.graph_launch()
+                yb = (2.0 * g.x[1].double()).floor().long().clamp_(0, nbins - 1)
+                mom = torch.zeros(nbins, dtype=torch.float64, device=g.device).index_add_(0, yb, m * g.v[0].double())
+                mass = m * torch.bincount(yb, minlength=nbins).double()
+                Yb = (2.0 * g.pos[1]).floor().long().clamp_(0, nbins - 1)
+                mom.index_add_(0, Yb, g.mom[0])
+                mass.index_add_(0, Yb, g.mass)
+                mom_b[b] += (mom / mass).cpu().numpy()
+            dp.append(float(g.rnemd_dp.cpu()[0]))
+        g.release_graph()
+    assert g.status() == 0
+    y = 0.25 + 0.5 * np.arange(nbins)
+    half = nbins // 2
+    sel = np.nonzero((y > 2.5) & (y < n - 1.5))[0]
+    A = float(n * n)
+    tb = per_block * every * 0.1
+
+    def eta_of(prof, rate):
+        u = 0.5 * (prof[sel] - prof[sel + half])
+        slope = np.polyfit(y[sel], u, 1)[0]
+        return abs(rate / (2.0 * A * slope)), abs(slope)
+
+    etas = [eta_of(mom_b[b] / per_block, (dp[b + 1] - dp[b]) / tb)[0] for b in range(nblocks)]
+    eta, rate = eta_of(mom_b.sum(0) / (per_block * nblocks), (dp[-1] - dp[0]) / (tb * nblocks))
+    return eta, block_error(np.array(etas), nblocks), rate
+
+
+def test_suspension_viscosity_fp32_matches_fp64():
+    res = {prec: suspension_viscosity(prec) for prec in ("f64", "f32")}
+    for prec, (eta, err, rate) in res.items():
+        say("%s: suspension (phi 0.1) eta %.3f +- %.3f, eta/eta_0 %.3f, shear rate %.4f"
+            % (prec, eta, err, eta / 3.96, rate))
+    (e64, s64, _), (e32, s32, _) = res["f64"], res["f32"]
+    assert abs(e64 - e32) < 4.0 * math.hypot(s64, s32) + 0.02
+    for eta, err, _ in res.values():
+        # hard spheres at phi = 0.1: eta / eta_0 = 1 + 2.5 phi + O(phi^2) ~ 1.3; the
+        # band allows for the hydrodynamic radius of the discrete-particle shell
+        assert 1.1 < eta / 3.96 < 1.7, eta
