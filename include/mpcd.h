@@ -177,11 +177,21 @@ typedef struct {
  * mpcd_ws_init before the first step. */
 size_t mpcd_workspace_bytes(const mpcd_sys *sys);
 
+/* Cell storage order.  The cell lists (cell_start, the permutation) and the
+ * out-of-place solvent hold a system's cells in brick order: bricks of
+ * 8 x 8 x 4 cells (narrower at the far faces), bricks x-fastest, the cells of
+ * a brick x-fastest; systems follow each other.  pos (host, [sum of the
+ * systems' cell counts]) receives, for every cell in canonical order (system,
+ * then (j_z n_y + j_y) n_x + j_x), its global storage position.  ncell: host
+ * [3*nsys].  Host only; no device work. */
+int mpcd_cell_order(int32_t nsys, const int32_t *ncell, int64_t *pos);
+
 /* Byte offsets inside the workspace (for inspection by tests and tools):
  * out[0] status word (uint32), out[1] grid shifts [3*nsys] (double),
- * out[2] cell_start [n_cells+1] (int32), out[3] permutation [N+S] (int32,
- * particles grouped by global cell, solvent before sites within a cell),
- * out[4] cell of each particle (int32),
+ * out[2] cell_start [n_cells+1] (int32, cells in storage order, see
+ * mpcd_cell_order), out[3] permutation [N+S] (int32, particles grouped by
+ * cell, solvent before sites within a cell), out[4] storage position of
+ * each particle's cell (int32),
  * out[5] slot within the cell (int32), out[6] site offsets d_j [3S] (double),
  * out[7] site velocities entering the collision [3S] (double). */
 int mpcd_workspace_offsets(const mpcd_sys *sys, int64_t out[8]);

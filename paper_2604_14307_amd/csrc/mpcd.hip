@@ -79,6 +79,16 @@ BodyDev make_bodydev(const mpcd_bodies *b)
 }
 
 // Largest r in [0, nsys) with off[r] <= i.
+__device__ __forceinline__ int find_sys_in(const int64_t *off, int lo, int hi, int64_t i)
+{
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ int find_sys(const int64_t *off, int nsys, int64_t i)
 {
     int lo = 0, hi = nsys - 1;
@@ -280,6 +290,8 @@ constexpr double RN_KMAX = 0.4096;
 
 // Binning and reorder chunks: BIN_T threads x BIN_ITEMS entries per block.
 constexpr int BIN_T = 256, BIN_ITEMS = 4, BIN_CHUNK = BIN_T * BIN_ITEMS;
+// Binning of the step's first kernel and of mpcd_bin: PREP_ITEMS per thread.
+constexpr int PREP_ITEMS = 8, PREP_CHUNK = BIN_T * PREP_ITEMS;
 
 Layout layout_of(const mpcd_sys *s)
 {
@@ -439,13 +451,12 @@ inline unsigned xcd_grid(int64_t ntiles)
 }
 
 // Binning: atomic counting sort by cell.
-//  1. k_bin_count: cell of every particle and its slot in the cell.  A block
-//     covers BIN_T * BIN_ITEMS consecutive particles; each wave keeps the
-//     atomics of its BIN_ITEMS groups of 64 in flight together, and lanes
-//     whose consecutive particles share a cell (storage ordered by cell) take
-//     their slots with one atomic per run.  Device-scope atomics are
-//     performed beyond the per-XCD L2s on MI355X, so their count and their
-//     spread over many addresses set the cost.
+//  1. k_bin_count (and the solvent blocks of k_prep): cell of every particle
+//     and its slot in the cell.  A block covers PREP_CHUNK consecutive
+//     particles, counts them per cell in an LDS hash table and takes one
+//     device-scope atomic per distinct cell (bin_chunk); with storage in
+//     brick order that is about 0.3 atomics per particle.  The sites of a
+//     body take one atomic per run of equal cells within a wave (run_slots).
 //     A cell's counter is 64 bits: solvent particles take slots from the low
 //     32 bits and sites from the high 32 bits, so one scan yields both.
 //  2. k_scan_reduce / k_scan_down: exclusive scan of the packed counters ->
@@ -481,6 +492,45 @@ struct BlockShift {
     }
 };
 
+// Storage order of a system's cells (the order of the cell lists and of the
+// out-of-place solvent): bricks of BRX x BRY x BRZ cells, narrower at the far
+// faces when the box is not a multiple, the bricks x-fastest and the cells of
+// a brick x-fastest.  Consecutive cells are then a compact region, so the
+// particles of a run of storage land in few cells of the next grid and the
+// binning aggregates their counts per block.  The canonical index
+// (jz n_y + j_y) n_x + j_x keys the random streams.
+constexpr int BRX = 8, BRY = 8, BRZ = 4;
+
+__host__ __device__ __forceinline__ int32_t brick_index(int nx, int ny, int nz, int jx, int jy, int jz)
+{
+    const int bz = jz / BRZ, lz = jz - bz * BRZ, ez = min(BRZ, nz - bz * BRZ);
+    const int by = jy / BRY, ly = jy - by * BRY, ey = min(BRY, ny - by * BRY);
+    const int bx = jx / BRX, lx = jx - bx * BRX, ex = min(BRX, nx - bx * BRX);
+    return bz * BRZ * ny * nx + ez * (by * BRY) * nx + ez * ey * (bx * BRX) + (lz * ey + ly) * ex + lx;
+}
+
+// Inverse of brick_index: the canonical local index of storage position q.
+__host__ __device__ __forceinline__ int32_t brick_canonical(int nx, int ny, int nz, int32_t q)
+{
+    const uint32_t slab = (uint32_t)(BRZ * ny * nx);
+    const int bz = (int)((uint32_t)q / slab);
+    uint32_t rem = (uint32_t)q - (uint32_t)bz * slab;
+    const int ez = min(BRZ, nz - bz * BRZ);
+    const uint32_t row = (uint32_t)(ez * BRY * nx);
+    const int by = (int)(rem / row);
+    rem -= (uint32_t)by * row;
+    const int ey = min(BRY, ny - by * BRY);
+    const uint32_t brick = (uint32_t)(ez * ey * BRX);
+    const int bx = (int)(rem / brick);
+    rem -= (uint32_t)bx * brick;
+    const int ex = min(BRX, nx - bx * BRX);
+    const int lz = (int)(rem / (uint32_t)(ey * ex));
+    rem -= (uint32_t)(lz * ey * ex);
+    const int ly = (int)(rem / (uint32_t)ex);
+    const int lx = (int)(rem - (uint32_t)(ly * ex));
+    return ((bz * BRZ + lz) * ny + (by * BRY + ly)) * nx + (bx * BRX + lx);
+}
+
 template <typename Real>
 __device__ __forceinline__ int32_t cell_of_pos(const SysDev &s, int r, Real p0, Real p1, Real p2, const double sh[3],
                                                uint32_t &st)
@@ -489,7 +539,7 @@ __device__ __forceinline__ int32_t cell_of_pos(const SysDev &s, int r, Real p0, 
     const int jx = axis_cell(p0, sh[0], s.a, nx, st);
     const int jy = axis_cell(p1, sh[1], s.a, ny, st);
     const int jz = axis_cell(p2, sh[2], s.a, nz, st);
-    return (int32_t)(s.cell_off[r] + ((int64_t)jz * ny + jy) * nx + jx);
+    return (int32_t)(s.cell_off[r] + brick_index(nx, ny, nz, jx, jy, jz));
 }
 
 // Slots for one group of 64 lanes: one atomic per run of equal cells.
@@ -513,25 +563,45 @@ __device__ __forceinline__ void run_slots(int32_t gc, bool site, unsigned long l
     }
 }
 
-// One chunk of BIN_CHUNK particles starting at kbase (< k1).
+// One chunk of PREP_CHUNK particles starting at kbase (< k1).  The block counts
+// its particles per (cell, kind) in an LDS hash table (each particle's rank
+// among its key's particles), then takes one global atomic per distinct key
+// for the key's base slot; slot = base + rank.  With cells in brick order a
+// chunk is a compact region and lands in about a third as many cells as it
+// has particles.
+constexpr int BIN_HT_BITS = 12, BIN_HT = 1 << BIN_HT_BITS;  // hash slots: at most half full
+static_assert(BIN_HT >= 2 * PREP_CHUNK, "hash load");
+constexpr uint32_t BIN_EMPTY = 0xffffffffu;
+
+struct BinLds {
+    uint32_t key[BIN_HT];
+    int32_t cnt[BIN_HT];  // particles per key, then the key's base slot
+};
+
 template <typename Real, bool SITES>
 __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const int32_t *site_body,
                           const BlockShift &bs, unsigned long long *counts, int32_t *cellid, int32_t *slot,
                           int64_t kbase,
-                          int64_t k1, uint32_t &st)
+                          int64_t k1, BinLds &H, uint32_t &st)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wbase = kbase + (threadIdx.x & ~63);
-    int32_t gc[BIN_ITEMS];
+    uint32_t *hkey = H.key;
+    int32_t *hcnt = H.cnt;
+    for (int i = threadIdx.x; i < BIN_HT; i += BIN_T) {
+        hkey[i] = BIN_EMPTY;
+        hcnt[i] = 0;
+    }
+    int32_t gc[PREP_ITEMS];
 #pragma unroll
-    for (int j = 0; j < BIN_ITEMS; ++j) {
-        const int64_t k = wbase + (int64_t)j * BIN_T + lane;
+    for (int j = 0; j < PREP_ITEMS; ++j) {
+        const int64_t k = kbase + (int64_t)j * BIN_T + threadIdx.x;
         gc[j] = -1;
         if (k < k1) {
             int r;
             Real p0, p1, p2;
             if (!SITES || k < s.N) {
-                r = find_sys(s.solv_off, s.nsys, k);
+                // the chunk's first and last systems, when known, bound the search
+                r = bs.ra < 0 ? find_sys(s.solv_off, s.nsys, k)
+                              : (bs.ra == bs.rb ? bs.ra : find_sys_in(s.solv_off, bs.ra, bs.rb, k));
                 p0 = x[k]; p1 = x[s.N + k]; p2 = x[2 * s.N + k];
             } else {
                 const int64_t q = k - s.N;
@@ -543,16 +613,39 @@ __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const 
             gc[j] = cell_of_pos<Real>(s, r, p0, p1, p2, sh, st);
         }
     }
-    int hl[BIN_ITEMS], base[BIN_ITEMS];
+    __syncthreads();
+    int hs[PREP_ITEMS], rank[PREP_ITEMS];
 #pragma unroll
-    for (int j = 0; j < BIN_ITEMS; ++j)
-        run_slots(gc[j], SITES && (wbase + (int64_t)j * BIN_T + lane) >= s.N, counts, hl[j], base[j]);
+    for (int j = 0; j < PREP_ITEMS; ++j) {
+        hs[j] = 0;
+        rank[j] = 0;
+        if (gc[j] < 0) continue;
+        const bool site = SITES && (kbase + (int64_t)j * BIN_T + threadIdx.x) >= s.N;
+        const uint32_t key = (uint32_t)gc[j] | (site ? 0x80000000u : 0u);
+        uint32_t h = (key * 2654435761u) >> (32 - BIN_HT_BITS);
+        while (true) {  // ends: fewer distinct keys than slots
+            const uint32_t old = atomicCAS(&hkey[h], BIN_EMPTY, key);
+            if (old == BIN_EMPTY || old == key) break;
+            h = (h + 1) & (BIN_HT - 1);
+        }
+        hs[j] = (int)h;
+        rank[j] = atomicAdd(&hcnt[h], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < BIN_HT; i += BIN_T) {
+        const uint32_t key = hkey[i];
+        if (key == BIN_EMPTY) continue;
+        const int sh = (key & 0x80000000u) ? 32 : 0;
+        const unsigned long long old =
+            atomicAdd(&counts[key & 0x7fffffffu], (unsigned long long)hcnt[i] << sh);
+        hcnt[i] = (int)((old >> sh) & 0xffffffffull);
+    }
+    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < BIN_ITEMS; ++j) {
-        const int b = __shfl(base[j], hl[j], 64);
-        const int64_t k = wbase + (int64_t)j * BIN_T + lane;
+    for (int j = 0; j < PREP_ITEMS; ++j) {
+        const int64_t k = kbase + (int64_t)j * BIN_T + threadIdx.x;
         if (k < k1) {
-            slot[k] = b + (lane - hl[j]);
+            slot[k] = hcnt[hs[j]] + rank[j];
             cellid[k] = gc[j];
         }
     }
@@ -573,10 +666,12 @@ __global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, co
                                                      unsigned long long *counts, int32_t *cellid, int32_t *slot,
                                                      uint32_t *status, int64_t k0, int64_t k1)
 {
+    __shared__ BinLds H;
     uint32_t st = 0;
     BlockShift bs;
     bs.arr = shift; bs.lds = nullptr; bs.ra = bs.rb = -1; bs.seed = 0; bs.step = 0;
-    bin_chunk<Real, true>(s, x, xs, site_body, bs, counts, cellid, slot, k0 + (int64_t)blockIdx.x * BIN_CHUNK, k1, st);
+    bin_chunk<Real, true>(s, x, xs, site_body, bs, counts, cellid, slot, k0 + (int64_t)blockIdx.x * PREP_CHUNK, k1, H,
+                          st);
     flag(status, st);
 }
 
@@ -854,7 +949,8 @@ __device__ __forceinline__ void draw_lane_start(const CollideArgs &A, int mode, 
 {
     const SysDev &s = A.s;
     const int r = find_sys(s.cell_off, s.nsys, L.cell);
-    L.cl = (uint64_t)(L.cell - s.cell_off[r]);
+    L.cl = (uint64_t)brick_canonical(s.ncell[3 * r], s.ncell[3 * r + 1], s.ncell[3 * r + 2],
+                                     (int32_t)(L.cell - s.cell_off[r]));
     L.rep = s.replica0 + (uint64_t)r;
     L.call = 0;
     L.want_axis = (mode & 1) != 0;
@@ -1675,7 +1771,7 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
 }
 
 // First kernel of a step: blocks [0, B) thermalize one body each and bin its
-// sites; the remaining blocks bin BIN_CHUNK solvent particles each.  Every
+// sites; the remaining blocks bin PREP_CHUNK solvent particles each.  Every
 // block draws the grid shifts it needs; block 0 also stores them.
 template <typename Real>
 __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT, int thermalize, uint64_t seed,
@@ -1686,7 +1782,10 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
 {
     __shared__ double bsh[6];
     __shared__ int bsr[2];
-    __shared__ ThermLds lds;
+    __shared__ union {  // a block either thermalizes a body or bins solvent
+        ThermLds th;
+        BinLds bin;
+    } lds;
     const uint64_t step = *d_step;
     uint32_t st = 0;
     if (blockIdx.x == 0) draw_shifts(s, seed, step, shift_out);
@@ -1699,13 +1798,13 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
         if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0))
             shift_of(s, seed, step, find_sys(s.body_off, s.nsys, b), bsh);
         thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid, slot,
-                              lds, st);
+                              lds.th, st);
     } else {
-        const int64_t kbase = ((int64_t)blockIdx.x - s.B) * BIN_CHUNK;
+        const int64_t kbase = ((int64_t)blockIdx.x - s.B) * PREP_CHUNK;
         const int64_t k1 = s.N;
         if (threadIdx.x == 0) {
             int ra, rb;
-            chunk_systems(s, nullptr, kbase, (kbase + BIN_CHUNK < k1) ? kbase + BIN_CHUNK : k1, ra, rb);
+            chunk_systems(s, nullptr, kbase, (kbase + PREP_CHUNK < k1) ? kbase + PREP_CHUNK : k1, ra, rb);
             bsr[0] = ra;
             bsr[1] = rb;
             shift_of(s, seed, step, ra, bsh);
@@ -1714,7 +1813,7 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
         __syncthreads();
         BlockShift bs;
         bs.arr = nullptr; bs.lds = bsh; bs.ra = bsr[0]; bs.rb = bsr[1]; bs.seed = seed; bs.step = step;
-        bin_chunk<Real, false>(s, x, nullptr, nullptr, bs, counts, cellid, slot, kbase, k1, st);
+        bin_chunk<Real, false>(s, x, nullptr, nullptr, bs, counts, cellid, slot, kbase, k1, lds.bin, st);
     }
     flag(status, st);
 }
@@ -2922,6 +3021,22 @@ size_t mpcd_workspace_bytes(const mpcd_sys *sys)
 
 int mpcd_last_hip_error(void) { return g_last_hip; }
 
+int mpcd_cell_order(int32_t nsys, const int32_t *ncell, int64_t *pos)
+{
+    if (nsys < 1 || !ncell || !pos) return MPCD_EINVAL;
+    int64_t off = 0;
+    for (int32_t r = 0; r < nsys; ++r) {
+        const int nx = ncell[3 * r], ny = ncell[3 * r + 1], nz = ncell[3 * r + 2];
+        if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz >= ((int64_t)1 << 31)) return MPCD_EINVAL;
+        for (int jz = 0; jz < nz; ++jz)
+            for (int jy = 0; jy < ny; ++jy)
+                for (int jx = 0; jx < nx; ++jx)
+                    pos[off + ((int64_t)jz * ny + jy) * nx + jx] = off + brick_index(nx, ny, nz, jx, jy, jz);
+        off += (int64_t)nx * ny * nz;
+    }
+    return MPCD_OK;
+}
+
 int mpcd_workspace_offsets(const mpcd_sys *sys, int64_t out[8])
 {
     TRY(check_sizes(sys));
@@ -3012,7 +3127,7 @@ static void launch_bin_count(const Ctx &c, hipStream_t st, const void *x, const 
                              int64_t k0, int64_t k1)
 {
     if (k1 <= k0) return;
-    const unsigned g = (unsigned)((k1 - k0 + BIN_CHUNK - 1) / BIN_CHUNK);
+    const unsigned g = (unsigned)((k1 - k0 + PREP_CHUNK - 1) / PREP_CHUNK);
     double *shift = at<double>(c.ws, c.L.shift);
     u64 *counts = at<u64>(c.ws, c.L.counts);
     int32_t *cellid = at<int32_t>(c.ws, c.L.cellid);
@@ -3165,7 +3280,7 @@ static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies,
     const int64_t grid_n = grid.count ? (int64_t)c.L.grid_mask + 1 : 0;
     const int64_t N = c.sys->n_solvent;
     const int64_t nb = (c.sys->n_sites > 0) ? c.sys->n_bodies : 0;
-    const int64_t nchunks = (N + BIN_CHUNK - 1) / BIN_CHUNK;
+    const int64_t nchunks = (N + PREP_CHUNK - 1) / PREP_CHUNK;
     const BodyDev bd = make_bodydev(bodies);
     SysDev sd = c.sd;
     if (nb == 0) sd.B = 0;  // no site work: every block bins solvent

@@ -21,7 +21,7 @@ EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mp
            "sites_thermalize", "sites_to_body", "body_integrate", "body_forces",
            "mpcd_advance_step", "mpcd_step", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
            "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error",
-           "harm_forces", "harm_md", "harm_step", "harm_graph_create", "mpcd_rnemd_exchange")
+           "harm_forces", "harm_md", "harm_step", "harm_graph_create", "mpcd_rnemd_exchange", "mpcd_cell_order")
 
 vp = C.c_void_p
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "mpcd_workspace_bytes": (sz, [sp]),
         "mpcd_workspace_offsets": (C.c_int, [sp, C.POINTER(C.c_int64)]),
+        "mpcd_cell_order": (C.c_int, [i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "mpcd_ws_init": (C.c_int, [vp, sp, vp, sz]),
         "mpcd_stream": (C.c_int, [vp, sp, vp, vp, dbl, C.POINTER(dbl), vp, sz]),
         "mpcd_bin": (C.c_int, [vp, sp, vp, vp, bp, u64, vp, vp, sz]),

@@ -311,11 +311,30 @@ class GPUSystem:
         nbytes = count * torch.tensor([], dtype=dtype).element_size()
         return self.ws[off:off + nbytes].view(dtype)
 
-    def bins(self):
+    def cell_order(self):
+        """Storage position of every cell, in canonical cell order (host)."""
+        if getattr(self, "_cell_order", None) is None:
+            nc = np.ascontiguousarray(self.ncell_h.reshape(-1), dtype=np.int32)
+            pos = np.empty(self.C, dtype=np.int64)
+            L.check(self.lib.mpcd_cell_order(self.nsys, nc.ctypes.data_as(C.POINTER(C.c_int32)),
+                                             pos.ctypes.data_as(C.POINTER(C.c_int64))), "mpcd_cell_order")
+            self._cell_order = pos
+        return self._cell_order
+
+    def bins(self, storage: bool = False):
+        """The last binning's cell lists: (cell_start [C+1], members [N+S], shifts).
+        Cells in canonical order (system, then (j_z n_y + j_y) n_x + j_x), or as
+        stored (storage=True)."""
         cs = self.ws_view("cell_start", torch.int32, self.C + 1).cpu().numpy().astype(np.int64)
         perm = self.ws_view("perm", torch.int32, self.N + self.S).cpu().numpy().astype(np.int64)
         shift = self.ws_view("shift", torch.float64, 3 * self.nsys).cpu().numpy().reshape(-1, 3)
-        return cs, perm, shift
+        if storage:
+            return cs, perm, shift
+        pos = self.cell_order()
+        cnt = cs[pos + 1] - cs[pos]
+        cc = np.concatenate([[0], np.cumsum(cnt)])
+        idx = np.repeat(cs[pos] - cc[:-1], cnt) + np.arange(cc[-1])
+        return cc, perm[idx], shift
 
     def site_state(self):
         d = self.ws_view("site_d", torch.float64, 3 * self.S).cpu().numpy().reshape(3, -1)

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2604_14307_amd import lib
@@ -66,3 +67,45 @@ def test_invalid_pointers_rejected_before_any_launch():
     assert L.mpcd_graph_destroy(None) == -1
     f = C.c_uint32(0)
     assert L.mpcd_status(None, None, 0, C.byref(f)) == -1
+
+
+def brick_enumeration(ncells, b=(8, 8, 4)):
+    """Storage position of every cell (canonical order), by enumerating the
+    bricks x-fastest and each brick's cells x-fastest."""
+    out, off = [], 0
+    for nx, ny, nz in ncells:
+        pos = np.empty(nx * ny * nz, dtype=np.int64)
+        q = off
+        for z0 in range(0, nz, b[2]):
+            for y0 in range(0, ny, b[1]):
+                for x0 in range(0, nx, b[0]):
+                    for jz in range(z0, min(z0 + b[2], nz)):
+                        for jy in range(y0, min(y0 + b[1], ny)):
+                            for jx in range(x0, min(x0 + b[0], nx)):
+                                pos[(jz * ny + jy) * nx + jx] = q
+                                q += 1
+        out.append(pos)
+        off += nx * ny * nz
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("ncells", [[(10, 10, 10)], [(7, 9, 11)], [(60, 60, 60)], [(1, 1, 1)],
+                                    [(12, 17, 24), (13, 13, 13), (3, 20, 5)]])
+def test_cell_order_is_the_brick_enumeration(ncells):
+    L = lib.load()
+    nc = np.ascontiguousarray(np.array(ncells, dtype=np.int32).reshape(-1))
+    C_tot = int(sum(a * b * c for a, b, c in ncells))
+    pos = np.empty(C_tot, dtype=np.int64)
+    rc = L.mpcd_cell_order(len(ncells), nc.ctypes.data_as(C.POINTER(C.c_int32)),
+                             pos.ctypes.data_as(C.POINTER(C.c_int64)))
+    assert rc == 0
+    assert np.array_equal(pos, brick_enumeration(ncells))
+
+
+def test_cell_order_rejects_bad_boxes():
+    L = lib.load()
+    pos = np.empty(8, dtype=np.int64)
+    for bad in ([2, 2, 0], [2, -1, 2]):
+        nc = np.array(bad, dtype=np.int32)
+        assert L.mpcd_cell_order(1, nc.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   pos.ctypes.data_as(C.POINTER(C.c_int64))) == -1

@@ -164,7 +164,7 @@ def test_out_of_place_step_writes_solvent_in_cell_order():
     g.step(2)
     tag_before = g.tag.cpu().numpy().copy()
     g.step(1)
-    cs, perm, _ = g.bins()
+    cs, perm, _ = g.bins(storage=True)
     sol = perm[perm < g.N]
     assert np.array_equal(g.tag.cpu().numpy(), tag_before[sol])
     for c in range(g.C):  # solvent first within each cell
