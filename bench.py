@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_14307_amd", "csrc", "mpcd.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_collide_tiled_f32_suspension60_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_f32_suspension60_traffic.txt")
 
 
 def log(msg):
@@ -55,9 +55,10 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(kernel):
     """HBM bytes per collide launch from the committed rocprofv3 counter summary,
-    or None when the kernel source has changed since the counters were taken."""
+    or None when it covers another kernel or the kernel source has changed
+    since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -66,7 +67,7 @@ def measured_traffic():
             if ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash() or vals.get("kernel") != kernel:
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -74,8 +75,19 @@ def measured_traffic():
         return None
 
 
-def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None):
+# Launch shapes: read from the committed cache of tuned shapes (one entry per
+# GPU architecture, precision and workload size); a workload missing from it
+# is tuned on the spot (untimed).  --retune tunes every workload again and
+# writes the cache given by --tune-cache.
+TUNE = {"on": True, "cache": os.path.join(ROOT, "paper_2604_14307_amd", "tuning_gfx950.json"), "write": None}
+
+
+def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None, tuning=None):
+    """Time graph replays of the step.  tuning: None = autotune the launch
+    shapes on this system first (untimed; unless disabled), else a fixed
+    (items, fill, draw_cells)."""
     import torch
+    from paper_2604_14307_amd import tune
     from paper_2604_14307_amd.sim import GPUSystem
 
     g = GPUSystem(systems, par, prec=prec, device="cuda:0")
@@ -88,6 +100,20 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None)
     with torch.cuda.stream(side):
         for i in range(warmup):  # eager warmup (also pages in the code objects)
             g.step(1)
+    tuned = None
+    if tuning is not None:
+        g.set_tuning(*tuning)
+    elif TUNE["on"]:
+        if TUNE["write"]:
+            tuned = tune.autotune(g, steps=min(20, per), repeats=3, cache_path=TUNE["write"], retune=True)
+        else:
+            tuned = tune.autotune(g, steps=min(20, per), repeats=3, cache_path=TUNE["cache"], write=False)
+        if tuned["cached"]:
+            log("  launch shape %s (tile %s) from the cache" % (tuned["tune"], tuned["tile"]))
+        else:
+            log("  launch shape %s (tile %s) tuned now: %.4f ms/step, default %.4f"
+                % (tuned["tune"], tuned["tile"], tuned["ms_per_step"], tuned["default_ms_per_step"]))
+    with torch.cuda.stream(side):
         g.graph(per)
         g.graph_launch()  # one untimed replay
         torch.cuda.synchronize()
@@ -120,7 +146,24 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None)
     ms = sum(seg)
     return dict(ms=ms, steps=total_steps, ms_step=ms / total_steps,
                 ms_step_median=statistics.median(seg) / per, collide_ms=kms,
-                rate=g.N * total_steps / (ms * 1e-3), N=g.N, S=g.S, B=g.B, C=g.C, nsys=g.nsys)
+                rate=g.N * total_steps / (ms * 1e-3), N=g.N, S=g.S, B=g.B, C=g.C, nsys=g.nsys,
+                tuning=tuning_record(g, tuned))
+
+
+def tuning_record(g, tuned):
+    t = g.tuning
+    rec = {"tune_items_fill_drawcells": [t.tile_items, t.tile_fill, t.draw_cells],
+           "tile_items_cells_cap_tiles": list(g.tile_shape())}
+    if tuned:
+        rec["source"] = "cache" if tuned["cached"] else "tuned in this run"
+        rec["default_ms_per_step_when_tuned"] = tuned["default_ms_per_step"]
+    return rec
+
+
+def collide_kernel_name(items, f64=False):
+    if f64:
+        return {1: "k_collide_tiled_f64_i1", 2: "k_collide_tiled_f64", 4: "k_collide_tiled_f64_i4"}[items]
+    return {2: "k_collide_tiled_f32_i2", 4: "k_collide_tiled_f32", 8: "k_collide_tiled_f32_i8"}[items]
 
 
 def copy_calibration(nbytes=1 << 30):
@@ -194,7 +237,7 @@ def cpu_baseline(wl, par, steps):
 def summary(r):
     return {"value": r["rate"], "ms_per_step": r["ms_step"], "ms_per_step_median_replay": r["ms_step_median"],
             "steps": r["steps"], "solvent": r["N"], "sites": r["S"], "bodies": r["B"], "cells": r["C"],
-            "systems": r["nsys"]}
+            "systems": r["nsys"], "tuning": r["tuning"]}
 
 
 def main():
@@ -215,6 +258,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-harmonic", action="store_true",
                     help="skip the rigid-vs-harmonic time per tau on the paper's benchmark geometry")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shapes (no cached or tuned shapes)")
+    ap.add_argument("--retune", metavar="PATH", default=None,
+                    help="tune every workload again (untimed) and write the shapes to this JSON cache")
     ap.add_argument("--no-rnemd", action="store_true",
                     help="skip the step time with the reverse nonequilibrium exchange appended")
     args = ap.parse_args()
@@ -225,6 +272,8 @@ def main():
         sys.exit(2)
     if args.steps < args.repeats:
         raise SystemExit("--steps must be at least --repeats")
+    TUNE["on"] = not args.no_tune
+    TUNE["write"] = args.retune
 
     from paper_2604_14307_amd import workloads as W
     wl, par, meta = W.config(1, kT_cell=1.0)
@@ -239,6 +288,7 @@ def main():
     r32 = res["f32"]
     N, S = r32["N"], r32["S"]
     ach = collide_bytes(N, S, 4) / (r32["collide_ms"] * 1e-3) / 1e9
+    kname = collide_kernel_name(r32["tuning"]["tile_items_cells_cap_tiles"][0])
     out = {
         "metric": "solvent particle-steps/s",
         "value": r32["rate"],
@@ -258,10 +308,11 @@ def main():
                    "form": "FP32 solvent/sites + int64 fixed-point cell sums + FP64 bodies; "
                            "HIP graph replays of the step"},
         "ms_per_step_median_replay": r32["ms_step_median"],
-        "roofline": {"bound": "hbm", "kernel": "k_collide_tiled_f32 (collide + stream)",
+        "roofline": {"bound": "hbm", "kernel": kname + " (collide + stream)",
                      "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                     "traffic": measured_traffic(), "avg_launch_us": r32["collide_ms"] * 1e3,
+                     "traffic": measured_traffic(kname), "avg_launch_us": r32["collide_ms"] * 1e3,
                      "algorithmic_bytes_per_launch": collide_bytes(N, S, 4)},
+        "tuning": r32["tuning"],
     }
     if "f64" in res:
         r64 = res["f64"]

@@ -121,6 +121,21 @@ typedef struct {
     double reach;        /* mode 2: max distance of a site from its body centre */
 } mpcd_wca;
 
+/* Launch shapes of the step (all zero: defaults).  They change how work is
+ * split over blocks, never the results: every choice gives the same bits.
+ * A collision tile is a block of 256 threads that owns consecutive cells and
+ * stages up to 256 * tile_items members in LDS; tile_items is 2, 4 or 8 for
+ * FP32 (default 4) and 1, 2 or 4 for FP64 (default 2).  tile_fill (10..100,
+ * default 70) is the percentage of that capacity an average tile may fill;
+ * it sets the cells per tile (a power of two, 8..256).  draw_cells (1..16,
+ * default 1) is the number of cells each lane of the per-cell draws takes.
+ * Out-of-range values: MPCD_EINVAL. */
+typedef struct {
+    int32_t tile_items;
+    int32_t tile_fill;
+    int32_t draw_cells;
+} mpcd_tune;
+
 /* Scalars of one step. */
 typedef struct {
     double dt;           /* step = collision period (0.1 tau in the paper)     */
@@ -138,6 +153,7 @@ typedef struct {
      * All zero: no forcing. */
     double g[3];
     double f_ext[3];
+    mpcd_tune tune;      /* launch shapes; zero: defaults                    */
 } mpcd_params;
 
 /* All buffers of one step (for mpcd_step and graph capture). */
@@ -185,6 +201,11 @@ size_t mpcd_workspace_bytes(const mpcd_sys *sys);
  * then (j_z n_y + j_y) n_x + j_x), its global storage position.  ncell: host
  * [3*nsys].  Host only; no device work. */
 int mpcd_cell_order(int32_t nsys, const int32_t *ncell, int64_t *pos);
+
+/* The collision tiles a tuning gives for sys (host only): out[0] items per
+ * thread, out[1] cells per tile, out[2] member capacity, out[3] tiles.
+ * tune may be NULL (defaults). */
+int mpcd_tile_shape(const mpcd_sys *sys, const mpcd_tune *tune, int32_t out[4]);
 
 /* Byte offsets inside the workspace (for inspection by tests and tools):
  * out[0] status word (uint32), out[1] grid shifts [3*nsys] (double),
@@ -239,13 +260,14 @@ int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag,
  * the same results as mpcd_collide.  With x_out, v_out, tag_out non-NULL
  * (all three) the solvent is collided and streamed out of place, as in
  * mpcd_step: x_stream (required) and v, tag are read and left unchanged, and
- * the new state goes to the outputs in cell order. */
+ * the new state goes to the outputs in cell order.  tune (host, may be NULL
+ * for the defaults) sets the collision tile shape, as in mpcd_params. */
 int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t seed,
                     const uint64_t *d_step, void *ws, size_t ws_bytes);
 int mpcd_collide_drawn(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream,
-                       double dt, void *x_out, void *v_out, int32_t *tag_out);
+                       double dt, void *x_out, void *v_out, int32_t *tag_out, const mpcd_tune *tune);
 
 /* Site positions and thermalized velocities, Eqs. (5) and (7).  Per body:
  * V = P/M, omega = A (Lhat / I) with Lhat_k = p . P_k q / 2; site offset

@@ -245,24 +245,35 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20)
 // Workspace layout (identical for every call with the same sizes)
 
 // Collision tiles: a block owns cpb consecutive cells (a power of two, at
-// most one per thread), sized so that a tile holds on average at most 70% of
-// the block's LDS member capacity (TILE_T * items).  Binning counts particles
-// per tile first, so the tile shape is fixed by the system sizes and precision.
+// most one per thread), sized so that a tile holds on average at most a
+// fraction `fill` of the block's LDS member capacity (TILE_T * items).  The
+// items per thread and the fill are launch-shape choices (mpcd_tune); they
+// change the split of work, never the results.
 constexpr int TILE_T = 256;
-constexpr int ITEMS_F64 = 2, ITEMS_F32 = 4;
+constexpr int ITEMS_F64 = 2, ITEMS_F32 = 4;  // defaults
 
 struct TileCfg {
-    int cpb, cpb_shift, cap, ntiles;
+    int items, cpb, cpb_shift, cap, ntiles;
 };
 
-TileCfg tile_config(const mpcd_sys *s)
+static bool tune_ok(const mpcd_tune &tu, bool f64)
+{
+    const int it = tu.tile_items;
+    const bool items_ok = it == 0 || (f64 ? (it == 1 || it == 2 || it == 4) : (it == 2 || it == 4 || it == 8));
+    return items_ok && (tu.tile_fill == 0 || (tu.tile_fill >= 10 && tu.tile_fill <= 100)) &&
+           tu.draw_cells >= 0 && tu.draw_cells <= 16;
+}
+
+TileCfg tile_config(const mpcd_sys *s, const mpcd_tune &tu)
 {
     TileCfg T;
     const bool f64 = s->prec == MPCD_F64;
-    T.cap = TILE_T * (f64 ? ITEMS_F64 : ITEMS_F32);
+    T.items = tu.tile_items ? tu.tile_items : (f64 ? ITEMS_F64 : ITEMS_F32);
+    T.cap = TILE_T * T.items;
+    const double fill = (tu.tile_fill ? tu.tile_fill : 70) / 100.0;
     const double per_cell = (double)(s->n_solvent + s->n_sites) / (double)s->n_cells;
     int cpb = TILE_T, sh = 8;
-    while (cpb > 8 && (double)cpb * per_cell > 0.7 * T.cap) {
+    while (cpb > 8 && (double)cpb * per_cell > fill * T.cap) {
         cpb >>= 1;
         --sh;
     }
@@ -274,7 +285,7 @@ TileCfg tile_config(const mpcd_sys *s)
 
 struct Layout {
     size_t status, shift, counts, partial, cell_start, site_start, cellid, slot, perm, draws, site_d, vpre, rtmp,
-        grid_count, grid_body, wpos, woff, rn_hist, rn_ctl, rn_key, rn_id, rn_k, total;
+        grid_count, grid_body, wpos, woff, rn_hist, rn_bcnt, rn_ctl, rn_key, rn_id, rn_k, total;
     uint32_t grid_mask;
 };
 
@@ -286,6 +297,7 @@ constexpr int GRID_K = 8;
 // Reverse nonequilibrium exchange: key histogram bins over [0, RN_KMAX) (the
 // last bin also takes larger keys), candidate capacity per slab, pair limit.
 constexpr int RN_BINS = 4096, RN_CAP = 2048, RN_MAXPAIRS = 1024;
+constexpr int RN_HBLOCKS = 1024;  // blocks of the histogram pass (grid-stride)
 constexpr double RN_KMAX = 0.4096;
 
 // Binning and reorder chunks: BIN_T threads x BIN_ITEMS entries per block.
@@ -333,6 +345,7 @@ Layout layout_of(const mpcd_sys *s)
     // reverse nonequilibrium exchange: key histograms, control words and
     // candidate lists of the two slabs
     L.rn_hist = take(sizeof(int32_t) * 2 * RN_BINS);
+    L.rn_bcnt = take(sizeof(int32_t) * 2 * RN_HBLOCKS);
     L.rn_ctl = take(sizeof(int32_t) * 16);
     L.rn_key = take(sizeof(double) * 2 * RN_CAP);
     L.rn_id = take(sizeof(int32_t) * 2 * RN_CAP);
@@ -1377,27 +1390,8 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     const int64_t N = s.N, S = s.S;
     const bool out = O.v != nullptr;
 
-    // phase 0: the tile's cell ranges and slot -> cell map; this lane's cell
-    // system and draws; FP32: clear the cell's fixed-point accumulators
-    unsigned long long *s_acc = (unsigned long long *)(smem + Lo.keyacc);
-    for (int c = t; c <= nc; c += TILE_T) s_cs[c] = A.cell_start[c0 + c] - m0;
-    double nax[3] = {0.0, 0.0, 1.0}, gvar = 0.0;
-    if (t < nc) {
-        const int64_t gc = c0 + t;
-        const int cb0 = A.cell_start[gc] - m0, ce0 = A.cell_start[gc + 1] - m0;
-        for (int i = cb0; i < ce0; ++i) s_cl[i] = (uint16_t)t;
-        if constexpr (!F64) {
-#pragma unroll
-            for (int z = 0; z < 5; ++z) s_acc[5 * t + z] = 0ull;
-        }
-        s_r[t] = find_sys(s.cell_off, s.nsys, gc);
-        if (out) s_ss[t] = A.site_start[gc];
-        read_axis(A, gc, nax);
-        if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
-    }
-    __syncthreads();
-
-    // phase 1: batched gathers of v (and x for the streaming); slot -> cell map
+    // the tile's member gathers (v, and x for the streaming) go out first: they
+    // need only the tile's member range, and they are in flight through phase 0
     int kk[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -1422,6 +1416,27 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
             }
         }
     }
+    // phase 0: the tile's cell ranges and slot -> cell map; this lane's cell
+    // system and draws; FP32: clear the cell's fixed-point accumulators
+    unsigned long long *s_acc = (unsigned long long *)(smem + Lo.keyacc);
+    for (int c = t; c <= nc; c += TILE_T) s_cs[c] = A.cell_start[c0 + c] - m0;
+    double nax[3] = {0.0, 0.0, 1.0}, gvar = 0.0;
+    if (t < nc) {
+        const int64_t gc = c0 + t;
+        const int cb0 = A.cell_start[gc] - m0, ce0 = A.cell_start[gc + 1] - m0;
+        for (int i = cb0; i < ce0; ++i) s_cl[i] = (uint16_t)t;
+        if constexpr (!F64) {
+#pragma unroll
+            for (int z = 0; z < 5; ++z) s_acc[5 * t + z] = 0ull;
+        }
+        s_r[t] = find_sys(s.cell_off, s.nsys, gc);
+        if (out) s_ss[t] = A.site_start[gc];
+        read_axis(A, gc, nax);
+        if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
+    }
+    __syncthreads();
+
+    // phase 1: fixed-point sums (FP32) or LDS staging (FP64); slot -> cell map
     const int cb = (t < nc) ? s_cs[t] : 0, ce = (t < nc) ? s_cs[t + 1] : 0;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -1590,19 +1605,44 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     flag(A.status, st);
 }
 
-// FP32 kernel: at most 80 VGPRs (six waves per SIMD to hide the gather
-// latency; measured faster than five).  FP64 keeps the compiler's allocation
-// (a cap spills).
+// One kernel per items-per-thread choice.  The FP32 default (4 items) is held
+// to 80 VGPRs (six waves per SIMD to hide the gather latency; measured faster
+// than five) and the 2-item form to 72 (seven waves); the 8-item form and FP64 keep the
+// compiler's allocation (a cap spills).
+__global__ __launch_bounds__(TILE_T) __attribute__((amdgpu_waves_per_eu(7))) void k_collide_tiled_f32_i2(
+    CollideArgs A, TileCfg T, float *v, float *vs, float *xstream, SolvOut<float> O)
+{
+    collide_tile<float, 2>(A, T, v, vs, xstream, O);
+}
+
 __global__ __launch_bounds__(TILE_T) __attribute__((amdgpu_waves_per_eu(6))) void k_collide_tiled_f32(
     CollideArgs A, TileCfg T, float *v, float *vs, float *xstream, SolvOut<float> O)
 {
-    collide_tile<float, ITEMS_F32>(A, T, v, vs, xstream, O);
+    collide_tile<float, 4>(A, T, v, vs, xstream, O);
+}
+
+__global__ __launch_bounds__(TILE_T) void k_collide_tiled_f32_i8(CollideArgs A, TileCfg T, float *v, float *vs,
+                                                                 float *xstream, SolvOut<float> O)
+{
+    collide_tile<float, 8>(A, T, v, vs, xstream, O);
+}
+
+__global__ __launch_bounds__(TILE_T) void k_collide_tiled_f64_i1(CollideArgs A, TileCfg T, double *v, double *vs,
+                                                                 double *xstream, SolvOut<double> O)
+{
+    collide_tile<double, 1>(A, T, v, vs, xstream, O);
 }
 
 __global__ __launch_bounds__(TILE_T) void k_collide_tiled_f64(CollideArgs A, TileCfg T, double *v, double *vs,
                                                               double *xstream, SolvOut<double> O)
 {
-    collide_tile<double, ITEMS_F64>(A, T, v, vs, xstream, O);
+    collide_tile<double, 2>(A, T, v, vs, xstream, O);
+}
+
+__global__ __launch_bounds__(TILE_T) void k_collide_tiled_f64_i4(CollideArgs A, TileCfg T, double *v, double *vs,
+                                                                 double *xstream, SolvOut<double> O)
+{
+    collide_tile<double, 4>(A, T, v, vs, xstream, O);
 }
 
 // ---------------------------------------------------------------------------
@@ -2705,7 +2745,7 @@ __global__ __launch_bounds__(BODY_T) void k_harm_substep(SysDev s, HarmDev h, mp
 // slab y0 <= y < y0 + dy is ranked by |v_x - target|, in the upper slab
 // y1 <= y < y1 + dy by |v_x + target| (ties: lower identity first); the first
 // np = min(npairs, n_lower, n_upper) of each exchange v_x pairwise.
-//  1. k_rn_hist: per slab, member count (one atomic per block) and a
+//  1. k_rn_hist: per slab, member count (each block stores its own) and a
 //     histogram of key bins; the last bin holds every key >= RN_KMAX and is
 //     not counted, since a threshold never needs to look past it.
 //  2. k_rn_thresh (one block): per slab, the smallest bin by which np members
@@ -2716,12 +2756,12 @@ __global__ __launch_bounds__(BODY_T) void k_harm_substep(SysDev s, HarmDev h, mp
 //     order, pairwise exchange of the first np (2 np distinct particles, one
 //     thread per pair), the moved momentum m (v_lower - v_upper) added in rank
 //     order, counters cleared.
-// ctl words: [0..1] members, [2..3] threshold bins, [4..5] candidates, [6] np.
+// ctl words: [2..3] threshold bins, [4..5] candidates, [6] np (others unused).
 
 struct RnArgs {
     double y0, y1, dy, target, m;
     int npairs;
-    int32_t *hist, *ctl, *id, *kk;
+    int32_t *hist, *bcnt, *ctl, *id, *kk;
     double *key;
 };
 
@@ -2764,34 +2804,43 @@ __global__ __launch_bounds__(256) void k_rn_hist(RnArgs R, const Real *x, const 
         n0 += sl == 0;
         n1 += sl == 1;
     }
-    // slab counts: one global atomic per block and slab
+    // slab counts: each block stores its own (a slab in brick order touches
+    // most blocks; one address per slab would serialize them)
     if (n0) atomicAdd(&s_n[0], n0);
     if (n1) atomicAdd(&s_n[1], n1);
     __syncthreads();
-    if (threadIdx.x < 2 && s_n[threadIdx.x]) atomicAdd(&R.ctl[threadIdx.x], s_n[threadIdx.x]);
+    if (threadIdx.x < 2) R.bcnt[threadIdx.x * RN_HBLOCKS + blockIdx.x] = s_n[threadIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_rn_thresh(RnArgs R)
 {
     constexpr int PER = RN_BINS / 256;
     static_assert(RN_BINS % 256 == 0, "bins per thread");
-    __shared__ int s_b[2], s_tot;
+    __shared__ int s_b[2], s_tot, s_n[2];
     const int t = threadIdx.x;
-    int np = R.npairs;
-    const int n0 = R.ctl[0], n1 = R.ctl[1];
-    if (n0 < np) np = n0;
-    if (n1 < np) np = n1;
-    if (np < 0) np = 0;
     if (t < 2) s_b[t] = RN_BINS - 1;
-    int hv[2][PER], sum[2] = {0, 0};
+    // both slabs' bins and the histogram blocks' member counts, in flight together
+    static_assert(RN_HBLOCKS % 256 == 0, "counts per thread");
+    int hv[2][PER], sum[2] = {0, 0}, c0 = 0, c1 = 0;
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl)  // both slabs' bins in flight together
+    for (int sl = 0; sl < 2; ++sl)
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             hv[sl][i] = R.hist[sl * RN_BINS + t * PER + i];
             sum[sl] += hv[sl][i];
         }
-    __syncthreads();
+#pragma unroll
+    for (int b = t; b < RN_HBLOCKS; b += 256) {
+        c0 += R.bcnt[b];
+        c1 += R.bcnt[RN_HBLOCKS + b];
+    }
+    (void)block_exclusive_scan<256, int>(c0, &s_n[0]);  // slab member counts
+    (void)block_exclusive_scan<256, int>(c1, &s_n[1]);
+    const int n0 = s_n[0], n1 = s_n[1];
+    int np = R.npairs;
+    if (n0 < np) np = n0;
+    if (n1 < np) np = n1;
+    if (np < 0) np = 0;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
         const int excl = block_exclusive_scan<256, int>(sum[sl], &s_tot);
@@ -3037,6 +3086,19 @@ int mpcd_cell_order(int32_t nsys, const int32_t *ncell, int64_t *pos)
     return MPCD_OK;
 }
 
+int mpcd_tile_shape(const mpcd_sys *sys, const mpcd_tune *tune, int32_t out[4])
+{
+    TRY(check_sizes(sys));
+    const mpcd_tune tu = tune ? *tune : mpcd_tune{0, 0, 0};
+    if (!out || !tune_ok(tu, sys->prec == MPCD_F64)) return MPCD_EINVAL;
+    const TileCfg T = tile_config(sys, tu);
+    out[0] = T.items;
+    out[1] = T.cpb;
+    out[2] = T.cap;
+    out[3] = T.ntiles;
+    return MPCD_OK;
+}
+
 int mpcd_workspace_offsets(const mpcd_sys *sys, int64_t out[8])
 {
     TRY(check_sizes(sys));
@@ -3104,12 +3166,14 @@ struct Ctx {
     Layout L;
     void *ws;
     uint32_t *status;
+    mpcd_tune tune;
 };
 
-static Ctx make_ctx(const mpcd_sys *sys, void *ws)
+static Ctx make_ctx(const mpcd_sys *sys, void *ws, const mpcd_tune *tune = nullptr)
 {
     Ctx c;
     c.sys = sys;
+    c.tune = tune ? *tune : mpcd_tune{0, 0, 0};
     c.sd = make_sysdev(sys);
     c.L = layout_of(sys);
     c.ws = ws;
@@ -3185,16 +3249,17 @@ static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bod
     return A;
 }
 
-static unsigned draw_blocks(int64_t C)
+static unsigned draw_blocks(int64_t C, const mpcd_tune &tu)
 {
-    const int64_t lanes = (C + DRAW_CELLS_PER_LANE - 1) / DRAW_CELLS_PER_LANE;
+    const int per = tu.draw_cells ? tu.draw_cells : DRAW_CELLS_PER_LANE;
+    const int64_t lanes = (C + per - 1) / per;
     return grid_for(lanes > 0 ? lanes : 1, BIN_T);
 }
 
 static void launch_draws(const Ctx &c, hipStream_t st, const CollideArgs &A, int mode)
 {
     if (mode == 2 && !(A.kT_cell > 0.0)) return;
-    hipLaunchKernelGGL(k_cell_draws, dim3(draw_blocks(c.sys->n_cells)), dim3(BIN_T), 0, st, A,
+    hipLaunchKernelGGL(k_cell_draws, dim3(draw_blocks(c.sys->n_cells, c.tune)), dim3(BIN_T), 0, st, A,
                        at<double>(c.ws, c.L.draws), mode);
 }
 
@@ -3204,17 +3269,17 @@ static void launch_collide(const Ctx &c, hipStream_t st, const CollideArgs &A, v
                            void *x_out = nullptr, void *v_out = nullptr, int32_t *tag_out = nullptr)
 {
     const bool f64 = c.sys->prec == MPCD_F64;
-    const TileCfg T = tile_config(c.sys);
+    const TileCfg T = tile_config(c.sys, c.tune);
     const dim3 grid(xcd_grid(T.ntiles));
     const size_t lds = tile_layout(f64, T.cpb, T.cap).end;
     if (f64) {
         const SolvOut<double> O{(double *)x_out, (double *)v_out, tag_out};
-        hipLaunchKernelGGL(k_collide_tiled_f64, grid, dim3(TILE_T), lds, st, A, T, (double *)v, (double *)vs,
-                           (double *)x_stream, O);
+        auto kern = T.items == 1 ? k_collide_tiled_f64_i1 : (T.items == 4 ? k_collide_tiled_f64_i4 : k_collide_tiled_f64);
+        hipLaunchKernelGGL(kern, grid, dim3(TILE_T), lds, st, A, T, (double *)v, (double *)vs, (double *)x_stream, O);
     } else {
         const SolvOut<float> O{(float *)x_out, (float *)v_out, tag_out};
-        hipLaunchKernelGGL(k_collide_tiled_f32, grid, dim3(TILE_T), lds, st, A, T, (float *)v, (float *)vs,
-                           (float *)x_stream, O);
+        auto kern = T.items == 2 ? k_collide_tiled_f32_i2 : (T.items == 8 ? k_collide_tiled_f32_i8 : k_collide_tiled_f32);
+        hipLaunchKernelGGL(kern, grid, dim3(TILE_T), lds, st, A, T, (float *)v, (float *)vs, (float *)x_stream, O);
     }
 }
 
@@ -3305,7 +3370,7 @@ static void launch_scatter_draws(const Ctx &c, hipStream_t st, const CollideArgs
 {
     const int64_t NT = c.sys->n_solvent + c.sys->n_sites;
     const int nsc = (int)((NT + BIN_CHUNK - 1) / BIN_CHUNK);
-    const int ndr = (int)draw_blocks(c.sys->n_cells);
+    const int ndr = (int)draw_blocks(c.sys->n_cells, c.tune);
     hipLaunchKernelGGL(k_scatter_draws, dim3((unsigned)(nsc + ndr)), dim3(BIN_T), 0, st, NT,
                        at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot), at<int32_t>(c.ws, c.L.perm), ndr,
                        A, at<double>(c.ws, c.L.draws));
@@ -3463,11 +3528,12 @@ int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t 
 int mpcd_collide_drawn(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt,
-                       void *x_out, void *v_out, int32_t *tag_out)
+                       void *x_out, void *v_out, int32_t *tag_out, const mpcd_tune *tune)
 {
     TRY(collide_checks(sys, v, tag, vs, bodies, d_step, ws, ws_bytes, x_stream, dt));
     TRY(out_checks(sys, v, tag, x_stream, x_out, v_out, tag_out));
-    const Ctx c = make_ctx(sys, ws);
+    if (tune && !tune_ok(*tune, sys->prec == MPCD_F64)) return MPCD_EINVAL;
+    const Ctx c = make_ctx(sys, ws, tune);
     const CollideArgs A = collide_args(c, tag, bodies, cos_a, sin_a, kT_cell, 0, d_step, dt, nullptr);
     launch_collide(c, (hipStream_t)stream, A, v, vs, x_stream, x_out, v_out, tag_out);
     return launch_check();
@@ -3588,19 +3654,22 @@ static void launch_rnemd(const Ctx &c, hipStream_t st, const void *x, void *v, c
     R.y0 = r->y0; R.y1 = r->y1; R.dy = r->dy; R.target = r->target; R.m = c.sys->m_solvent;
     R.npairs = r->npairs;
     R.hist = at<int32_t>(c.ws, c.L.rn_hist);
+    R.bcnt = at<int32_t>(c.ws, c.L.rn_bcnt);
     R.ctl = at<int32_t>(c.ws, c.L.rn_ctl);
     R.key = at<double>(c.ws, c.L.rn_key);
     R.id = at<int32_t>(c.ws, c.L.rn_id);
     R.kk = at<int32_t>(c.ws, c.L.rn_k);
     const unsigned g = grid_for(N, 256, 8192);
     if (c.sys->prec == MPCD_F64) {
-        hipLaunchKernelGGL(k_rn_hist<double>, dim3(g), dim3(256), 0, st, R, (const double *)x, (const double *)v, N);
+        hipLaunchKernelGGL(k_rn_hist<double>, dim3(RN_HBLOCKS), dim3(256), 0, st, R, (const double *)x,
+                           (const double *)v, N);
         hipLaunchKernelGGL(k_rn_thresh, dim3(1), dim3(256), 0, st, R);
         hipLaunchKernelGGL(k_rn_collect<double>, dim3(g), dim3(256), 0, st, R, (const double *)x, (const double *)v,
                            tag, N, c.status);
         hipLaunchKernelGGL(k_rn_swap<double>, dim3(1), dim3(1024), 0, st, R, (double *)v, N, dp, c.status);
     } else {
-        hipLaunchKernelGGL(k_rn_hist<float>, dim3(g), dim3(256), 0, st, R, (const float *)x, (const float *)v, N);
+        hipLaunchKernelGGL(k_rn_hist<float>, dim3(RN_HBLOCKS), dim3(256), 0, st, R, (const float *)x,
+                           (const float *)v, N);
         hipLaunchKernelGGL(k_rn_thresh, dim3(1), dim3(256), 0, st, R);
         hipLaunchKernelGGL(k_rn_collect<float>, dim3(g), dim3(256), 0, st, R, (const float *)x, (const float *)v,
                            tag, N, c.status);
@@ -3625,6 +3694,7 @@ static int step_checks(const mpcd_step_args *a)
     TRY(bin_checks(s, a->x, a->xs, &a->bodies, a->d_step, a->ws, a->ws_bytes));
     TRY(collide_checks(s, a->v, a->tag, a->vs, &a->bodies, a->d_step, a->ws, a->ws_bytes, a->x, p.dt));
     TRY(wca_check(&p.wca));
+    if (!tune_ok(p.tune, s->prec == MPCD_F64)) return MPCD_EINVAL;
     if (!(p.dt > 0.0)) return MPCD_EINVAL;
     if (!ok_arr(a->J, s->n_bodies, 8) || !ok_arr(a->K, s->n_bodies, 8)) return MPCD_EINVAL;
     if (a->reorder_every < 0 || (a->reorder_every > 0 && !ok_arr(a->tag, s->n_solvent, 4))) return MPCD_EINVAL;
@@ -3656,7 +3726,7 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
     TRY(step_checks(a));
     const mpcd_sys *s = a->sys;
     const mpcd_params &p = a->par;
-    const Ctx c = make_ctx(s, a->ws);
+    const Ctx c = make_ctx(s, a->ws, &p.tune);
     hipStream_t st = (hipStream_t)stream;
     launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca);
     launch_scan(c, st);
@@ -3814,7 +3884,7 @@ int harm_step(void *stream, const mpcd_step_args *a, const mpcd_harm *h, double 
     TRY(mpcd_bin(stream, s, a->x, a->xs, &a->bodies, p.seed, a->d_step, a->ws, a->ws_bytes));
     TRY(mpcd_cell_draws(stream, s, p.kT_cell, p.seed, a->d_step, a->ws, a->ws_bytes));
     TRY(mpcd_collide_drawn(stream, s, a->v, a->tag, a->vs, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, a->d_step,
-                           a->ws, a->ws_bytes, a->x, p.dt, a->x_out, a->v_out, a->tag_out));
+                           a->ws, a->ws_bytes, a->x, p.dt, a->x_out, a->v_out, a->tag_out, nullptr));
     TRY(harm_md(stream, s, h, (double *)a->xs, (double *)a->vs, &p.wca, dt_md, nsub, a->ws, a->ws_bytes));
     return mpcd_advance_step(stream, a->d_step);
 }

@@ -21,7 +21,8 @@ EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mp
            "sites_thermalize", "sites_to_body", "body_integrate", "body_forces",
            "mpcd_advance_step", "mpcd_step", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
            "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error",
-           "harm_forces", "harm_md", "harm_step", "harm_graph_create", "mpcd_rnemd_exchange", "mpcd_cell_order")
+           "harm_forces", "harm_md", "harm_step", "harm_graph_create", "mpcd_rnemd_exchange", "mpcd_cell_order",
+           "mpcd_tile_shape")
 
 vp = C.c_void_p
 
@@ -44,10 +45,15 @@ class MpcdWca(C.Structure):
                 ("reach", C.c_double)]
 
 
+class MpcdTune(C.Structure):
+    _fields_ = [("tile_items", C.c_int32), ("tile_fill", C.c_int32), ("draw_cells", C.c_int32)]
+
+
 class MpcdParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("cos_a", C.c_double), ("sin_a", C.c_double), ("kT", C.c_double),
                 ("kT_cell", C.c_double), ("seed", C.c_uint64), ("thermalize", C.c_int32),
-                ("fuse_stream", C.c_int32), ("wca", MpcdWca), ("g", C.c_double * 3), ("f_ext", C.c_double * 3)]
+                ("fuse_stream", C.c_int32), ("wca", MpcdWca), ("g", C.c_double * 3), ("f_ext", C.c_double * 3),
+                ("tune", MpcdTune)]
 
 
 class MpcdRnemd(C.Structure):
@@ -91,12 +97,14 @@ def load(path: str = LIB_PATH):
         "mpcd_workspace_bytes": (sz, [sp]),
         "mpcd_workspace_offsets": (C.c_int, [sp, C.POINTER(C.c_int64)]),
         "mpcd_cell_order": (C.c_int, [i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+        "mpcd_tile_shape": (C.c_int, [sp, C.POINTER(MpcdTune), C.POINTER(C.c_int32)]),
         "mpcd_ws_init": (C.c_int, [vp, sp, vp, sz]),
         "mpcd_stream": (C.c_int, [vp, sp, vp, vp, dbl, C.POINTER(dbl), vp, sz]),
         "mpcd_bin": (C.c_int, [vp, sp, vp, vp, bp, u64, vp, vp, sz]),
         "mpcd_collide": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, u64, vp, vp, sz, vp, dbl]),
         "mpcd_cell_draws": (C.c_int, [vp, sp, dbl, u64, vp, vp, sz]),
-        "mpcd_collide_drawn": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, vp, vp, sz, vp, dbl, vp, vp, vp]),
+        "mpcd_collide_drawn": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, vp, vp, sz, vp, dbl, vp, vp, vp,
+                                         C.POINTER(MpcdTune)]),
         "sites_thermalize": (C.c_int, [vp, sp, bp, dbl, i32, u64, vp, vp, vp, vp, sz]),
         "sites_to_body": (C.c_int, [vp, sp, bp, vp, vp, sz, vp, vp]),
         "body_integrate": (C.c_int, [vp, sp, bp, vp, vp, wp, C.POINTER(dbl), dbl, vp, sz]),

@@ -130,6 +130,8 @@ class GPUSystem:
         # optional reverse nonequilibrium exchange after every step
         self.rnemd = None
         self.rnemd_dp = torch.zeros(1, dtype=torch.float64, device=dev)
+        # launch shapes (zero: the library's defaults); results do not depend on them
+        self.tuning = L.MpcdTune(0, 0, 0)
         self.ws_init()
         self._graph = None
 
@@ -150,7 +152,7 @@ class GPUSystem:
         par = L.MpcdParams(dt=p["dt"], cos_a=p["cos_a"], sin_a=p["sin_a"], kT=p["kT"], kT_cell=p["kT_cell"],
                            seed=p["seed"], thermalize=int(p.get("thermalize", 1)),
                            fuse_stream=int(self.fuse_stream), wca=self.cwca, g=self._vec("g"),
-                           f_ext=self._vec("f_ext"))
+                           f_ext=self._vec("f_ext"), tune=self.tuning)
         out = self.out_of_place
         self._args = L.MpcdStepArgs(sys=C.pointer(self.csys), bodies=self.cbodies, x=_ptr(self.x), v=_ptr(self.v),
                                     tag=_ptr(self.tag), xs=_ptr(self.xs), vs=_ptr(self.vs), J=_ptr(self.J),
@@ -162,6 +164,35 @@ class GPUSystem:
                                     rnemd=C.pointer(self.rnemd) if self.rnemd is not None else None,
                                     rnemd_dp=_ptr(self.rnemd_dp))
         return self._args
+
+    def set_tuning(self, tile_items: int = 0, tile_fill: int = 0, draw_cells: int = 0):
+        """Launch shapes of the step (see mpcd_tune); 0 keeps a default."""
+        self.tuning = L.MpcdTune(int(tile_items), int(tile_fill), int(draw_cells))
+        self.tile_shape()  # validates
+
+    def tile_shape(self, tune=None):
+        """(items per thread, cells per tile, member capacity, tiles) of a tuning."""
+        out = (C.c_int32 * 4)()
+        t = self.tuning if tune is None else L.MpcdTune(*[int(a) for a in tune])
+        L.check(self.lib.mpcd_tile_shape(C.byref(self.csys), C.byref(t), out), "mpcd_tile_shape")
+        return tuple(out)
+
+    _STATE = ("x", "v", "tag", "xs", "vs", "pos", "image", "quat", "mom", "angmom", "force", "torque", "J", "K",
+              "d_step", "rnemd_dp")
+
+    def snapshot(self):
+        """Device copies of the whole simulation state (for timing runs).  Waits
+        for all work on the device first: steps may still run on another stream."""
+        torch.cuda.synchronize(self.device)
+        snap = {k: getattr(self, k).clone() for k in self._STATE}
+        torch.cuda.synchronize(self.device)
+        return snap
+
+    def restore(self, snap):
+        torch.cuda.synchronize(self.device)
+        for k in self._STATE:
+            getattr(self, k).copy_(snap[k])
+        torch.cuda.synchronize(self.device)
 
     def set_rnemd(self, y0, y1, dy=1.0, target=0.5, npairs=100):
         """Exchange after every step (Sec. III.B); None-like npairs=0 turns it off."""
@@ -220,7 +251,7 @@ class GPUSystem:
                                             _ptr(self.vs), C.byref(self.cbodies), p["cos_a"], p["sin_a"],
                                             p["kT_cell"], _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
                                             _ptr(self.x) if stream_x else C.c_void_p(0), p["dt"],
-                                            C.c_void_p(0), C.c_void_p(0), C.c_void_p(0)),
+                                            C.c_void_p(0), C.c_void_p(0), C.c_void_p(0), C.byref(self.tuning)),
                 "mpcd_collide_drawn")
 
     def sites_to_body(self):
@@ -269,7 +300,8 @@ class GPUSystem:
         L.check(self.lib.mpcd_collide_drawn(self.stream, C.byref(self.csys), _ptr(self.v2), _ptr(self.tag2),
                                             _ptr(self.vs), C.byref(self.cbodies), p["cos_a"], p["sin_a"],
                                             p["kT_cell"], _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
-                                            _ptr(self.x2), p["dt"], _ptr(self.x), _ptr(self.v), _ptr(self.tag)),
+                                            _ptr(self.x2), p["dt"], _ptr(self.x), _ptr(self.v), _ptr(self.tag),
+                                            C.byref(self.tuning)),
                 "mpcd_collide_drawn")
 
     def reorder(self):

@@ -109,3 +109,22 @@ def test_cell_order_rejects_bad_boxes():
         nc = np.array(bad, dtype=np.int32)
         assert L.mpcd_cell_order(1, nc.ctypes.data_as(C.POINTER(C.c_int32)),
                                    pos.ctypes.data_as(C.POINTER(C.c_int64))) == -1
+
+
+def test_tile_shape_follows_the_tuning():
+    L = lib.load()
+    s = sys_desc(prec=lib.MPCD_F32, n_solvent=1_080_000, n_sites=38_200, n_bodies=191, n_cells=216_000)
+    out = (C.c_int32 * 4)()
+    assert L.mpcd_tile_shape(C.byref(s), None, out) == 0
+    items, cpb, cap, ntiles = list(out)
+    # default: 4 items per thread, cells per tile the largest power of two whose
+    # average membership (5.18 per cell) stays within 70% of 1024
+    assert (items, cap) == (4, 1024) and cpb == 128 and ntiles == 216_000 // 128 + 1
+    t = lib.MpcdTune(8, 85, 2)
+    assert L.mpcd_tile_shape(C.byref(s), C.byref(t), out) == 0
+    assert list(out)[:3] == [8, 256, 2048]
+    for bad in ((3, 0, 0), (0, 5, 0), (0, 101, 0), (0, 0, 17), (1, 0, 0)):
+        assert L.mpcd_tile_shape(C.byref(s), C.byref(lib.MpcdTune(*bad)), out) == -1
+    s64 = sys_desc(prec=lib.MPCD_F64)
+    assert L.mpcd_tile_shape(C.byref(s64), C.byref(lib.MpcdTune(1, 0, 0)), out) == 0 and out[0] == 1
+    assert L.mpcd_tile_shape(C.byref(s64), C.byref(lib.MpcdTune(8, 0, 0)), out) == -1

@@ -590,9 +590,11 @@ def test_rnemd_exchange_bit_exact(bodies):
 
 
 # The exchange's state occupies the end of the workspace: key-bin histograms
-# (2 x 4096 int32), 16 control words (padded to 256 bytes), then the candidate
-# keys, identities and indices (2 x 2048 each).
-RN_TAIL = 2 * 4096 * 4 + 256 + 2 * 2048 * 8 + 2 * 2048 * 4 + 2 * 2048 * 4
+# (2 x 4096 int32), per-block member counts (2 x 1024 int32, rewritten by every
+# exchange), 16 control words (padded to 256 bytes), then the candidate keys,
+# identities and indices (2 x 2048 each).
+RN_HIST, RN_BCNT, RN_CTL = 2 * 4096 * 4, 2 * 1024 * 4, 256
+RN_TAIL = RN_HIST + RN_BCNT + RN_CTL + 2 * 2048 * 8 + 2 * 2048 * 4 + 2 * 2048 * 4
 
 
 def test_rnemd_from_dirty_workspace():
@@ -607,8 +609,9 @@ def test_rnemd_from_dirty_workspace():
     g.ws[g.ws_bytes - RN_TAIL:].fill_(0xFF)
     g.ws_init()
     tail = g.ws[g.ws_bytes - RN_TAIL:].cpu().numpy()
-    state = tail[:2 * 4096 * 4 + 64].view(np.int32)
-    assert not state.any(), "exchange state not cleared by initialisation"
+    hist = tail[:RN_HIST].view(np.int32)
+    ctl = tail[RN_HIST + RN_BCNT:RN_HIST + RN_BCNT + 64].view(np.int32)
+    assert not hist.any() and not ctl.any(), "exchange state not cleared by initialisation"
     g.set_rnemd(0.0, 8.0, 1.0, 0.5, 16)
     dp = 0.0
     for n in range(8):
@@ -641,3 +644,68 @@ def test_solvent_graph_matches_eager(exchange):
             assert float(ge.rnemd_dp.cpu()[0]) == float(gg.rnemd_dp.cpu()[0])
         gg.release_graph()
     assert ge.status() == 0 and gg.status() == 0
+
+
+# ---------------------------------------------------------------------------
+# Launch shapes change the split of work, never the results
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_launch_shape_gives_the_same_bits(prec):
+    wl = W.suspension((14, 18, 11), 5, 4, 2.0, 60, 5.0, seed=88)
+    par = W.srd_params(88, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
+    items = (1, 2, 4) if prec == "f64" else (2, 4, 8)
+    shapes = [(0, 0, 0)] + [(it, fill, dc) for it in items for fill, dc in ((10, 3), (55, 1), (100, 16))]
+    ref = None
+    for sh in shapes:
+        g = gpu_system(wl, par, prec=prec)
+        g.set_tuning(*sh)
+        say("shape %s %s -> tile %s" % (prec, sh, g.tile_shape()))
+        g.body_forces()
+        g.step(6)
+        st = g.download()[0]
+        assert g.status() == 0
+        if ref is None:
+            ref = st
+            continue
+        for k in ("x", "v", "xs", "vs", "R", "q", "P", "p", "F", "T"):
+            assert np.array_equal(ref[k], st[k]), (sh, k)
+
+
+def test_autotune_keeps_the_state_and_reuses_its_cache(tmp_path):
+    from paper_2604_14307_amd import tune
+    wl = W.suspension((16, 16, 16), 5, 4, 2.0, 60, 5.0, seed=89)
+    par = W.srd_params(89, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
+    g = gpu_system(wl, par, prec="f32")
+    g.body_forces()
+    g.step(2)
+    before = {k: v.cpu().clone() for k, v in g.snapshot().items()}
+    cache = str(tmp_path / "tune.json")
+    e = tune.autotune(g, steps=4, repeats=2, cache_path=cache)
+    after = g.snapshot()
+    for k in before:
+        assert torch.equal(before[k], after[k].cpu()), k
+    assert not e["cached"] and e["shapes_tried"] >= 6 and e["ms_per_step"] <= e["default_ms_per_step"]
+    assert tuple(g.tile_shape()) == tuple(e["tile"])
+    g2 = gpu_system(wl, par, prec="f32")
+    e2 = tune.autotune(g2, steps=4, cache_path=cache)
+    assert e2["cached"] and list(e2["tune"]) == list(e["tune"])
+    assert g.status() == 0
+
+
+def test_snapshot_waits_for_steps_on_another_stream():
+    """Steps queued on a side stream must be complete in a snapshot taken from
+    the default stream (the tuner snapshots after such warmup steps)."""
+    wl = W.make_system((12, 12, 12), 5, [], [], np.zeros((0, 4)), np.random.default_rng(90))
+    par = W.srd_params(90, kT_cell=1.0)
+    g = gpu_system(wl, par, prec="f32")
+    ref = gpu_system(wl, par, prec="f32")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g.step(40)
+    snap = g.snapshot()
+    ref.step(40)
+    torch.cuda.synchronize()
+    # storage order within a cell follows atomic arrival: compare by identity
+    a, b = torch.argsort(snap["tag"].long()), torch.argsort(ref.tag.long())
+    assert torch.equal(snap["tag"][a], ref.tag[b])
+    assert torch.equal(snap["v"][:, a], ref.v[:, b]) and torch.equal(snap["x"][:, a], ref.x[:, b])
