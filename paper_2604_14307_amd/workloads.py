@@ -41,6 +41,35 @@ def fibonacci_sphere(nsites: int, radius: float) -> np.ndarray:
     return radius * np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], axis=1)
 
 
+def icosphere(radius: float, frequency: int = 4) -> np.ndarray:
+    """Sites of a subdivided icosahedron projected onto a sphere: every face
+    split into frequency^2 triangles, 10 f^2 + 2 distinct vertices (162 for
+    f = 4, the discrete-particle sphere of the paper's single-particle runs)."""
+    g = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([[-1, g, 0], [1, g, 0], [-1, -g, 0], [1, -g, 0], [0, -1, g], [0, 1, g],
+                  [0, -1, -g], [0, 1, -g], [g, 0, -1], [g, 0, 1], [-g, 0, -1], [-g, 0, 1]], dtype=np.float64)
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    # faces: the vertex triples whose pairwise distances are all the edge length
+    d = np.linalg.norm(v[:, None] - v[None], axis=2)
+    edge = d[d > 1e-9].min()
+    adj = np.abs(d - edge) < 1e-9
+    faces = [(a, b, c) for a in range(12) for b in range(a + 1, 12) for c in range(b + 1, 12)
+             if adj[a, b] and adj[b, c] and adj[a, c]]
+    assert len(faces) == 20
+    pts = {}
+    f = int(frequency)
+    for a, b, c in faces:
+        for i in range(f + 1):
+            for j in range(f + 1 - i):
+                k = f - i - j
+                p = (i * v[a] + j * v[b] + k * v[c]) / f
+                p /= np.linalg.norm(p)
+                pts.setdefault(tuple(np.round(p, 12)), p)
+    out = np.array(list(pts.values()))
+    assert len(out) == 10 * f * f + 2
+    return radius * out
+
+
 def cube_surface(edge: float = 4.0, per_side: int = 5) -> np.ndarray:
     """per_side x per_side grid on each of the 6 faces of a cube (150 sites for 5)."""
     h = 0.5 * edge
@@ -514,6 +543,21 @@ def paper_viscosity(phi=0.1, edge=120, seed=7, kT_cell=1.0):
                      "(%d spheres, d=6, 162 sites), WCA sigma=1 Delta=5; slabs y=0 and y=%d, 100 pairs"
                      % (edge, 2 * edge, edge, wl["x"].shape[1], phi, len(centres), edge))
     return wl, par, meta, (0.0, float(edge), 1.0, 0.5, 100)
+
+
+def paper_single_sphere(edge=90, nrep=1, seed=12, kT_cell=1.0):
+    """The paper's single-particle validation (Sec. III.A): a cubic periodic box
+    of edge `edge`, 5 solvent per cell, one sphere of diameter 6 made of the 162
+    sites of a subdivided icosahedron (mass 5 each) at the box centre, randomly
+    oriented; nrep independent replicas advanced together."""
+    tpl = rigid_template(icosphere(3.0, 4), 5.0)
+    systems = []
+    for r in range(nrep):
+        rng = np.random.default_rng([seed, r])
+        c = 0.5 * edge
+        systems.append(make_system((edge, edge, edge), 5, [tpl], [(c, c, c)], random_quaternions(rng, 1), rng))
+    return systems, srd_params(seed, kT_cell=kT_cell), dict(
+        name="single sphere (162-site icosahedron, d=6) in %d^3 cells, 5/cell, %d replica(s)" % (edge, nrep))
 
 
 def batched_replicas(nrep=512, seed=4, lo=12, hi=24, density=5, kT_cell=1.0):
