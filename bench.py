@@ -152,7 +152,7 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None,
 
 def tuning_record(g, tuned):
     t = g.tuning
-    rec = {"tune_items_fill_drawcells": [t.tile_items, t.tile_fill, t.draw_cells],
+    rec = {"tune_items_fill_drawcells_inline": [t.tile_items, t.tile_fill, t.draw_cells, t.draws_inline],
            "tile_items_cells_cap_tiles": list(g.tile_shape())}
     if tuned:
         rec["source"] = "cache" if tuned["cached"] else "tuned in this run"
@@ -160,10 +160,18 @@ def tuning_record(g, tuned):
     return rec
 
 
-def collide_kernel_name(items, f64=False):
-    if f64:
-        return {1: "k_collide_tiled_f64_i1", 2: "k_collide_tiled_f64", 4: "k_collide_tiled_f64_i4"}[items]
-    return {2: "k_collide_tiled_f32_i2", 4: "k_collide_tiled_f32", 8: "k_collide_tiled_f32_i8"}[items]
+def collide_kernel_name(items, draws_inline=0, f64=False):
+    base = ({1: "k_collide_tiled_f64_i1", 2: "k_collide_tiled_f64", 4: "k_collide_tiled_f64_i4"} if f64 else
+            {2: "k_collide_tiled_f32_i2", 4: "k_collide_tiled_f32", 8: "k_collide_tiled_f32_i8"})[items]
+    return base + ("_d" if draws_inline else "")
+
+
+def step_bytes(N, S, prec_bytes):
+    """Algorithmic HBM bytes of one whole step: each solvent particle's x and v
+    read and written once, each site's position and velocity written by the
+    thermalization and its velocity read and written by the collision, its
+    offset, mass and pre-collision velocity read (bodies: negligible)."""
+    return N * 4 * 3 * prec_bytes + S * (4 * 3 * prec_bytes + 3 * 8 + 8 + 3 * 8)
 
 
 def copy_calibration(nbytes=1 << 30):
@@ -288,7 +296,8 @@ def main():
     r32 = res["f32"]
     N, S = r32["N"], r32["S"]
     ach = collide_bytes(N, S, 4) / (r32["collide_ms"] * 1e-3) / 1e9
-    kname = collide_kernel_name(r32["tuning"]["tile_items_cells_cap_tiles"][0])
+    kname = collide_kernel_name(r32["tuning"]["tile_items_cells_cap_tiles"][0],
+                                r32["tuning"]["tune_items_fill_drawcells_inline"][3])
     out = {
         "metric": "solvent particle-steps/s",
         "value": r32["rate"],
@@ -308,11 +317,14 @@ def main():
                    "form": "FP32 solvent/sites + int64 fixed-point cell sums + FP64 bodies; "
                            "HIP graph replays of the step"},
         "ms_per_step_median_replay": r32["ms_step_median"],
-        "roofline": {"bound": "hbm", "kernel": kname + " (collide + stream)",
+        "roofline": {"bound": "hbm", "kernel": kname + (" (collide + stream + per-cell draws)" if kname.endswith("_d")
+                                                        else " (collide + stream)"),
                      "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
                      "traffic": measured_traffic(kname), "avg_launch_us": r32["collide_ms"] * 1e3,
                      "algorithmic_bytes_per_launch": collide_bytes(N, S, 4)},
         "tuning": r32["tuning"],
+        # the whole step against the HBM peak: algorithmic bytes of a step / step time
+        "step_hbm_frac": step_bytes(N, S, 4) / (r32["ms_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS,
     }
     if "f64" in res:
         r64 = res["f64"]

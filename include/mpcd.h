@@ -129,11 +129,14 @@ typedef struct {
  * default 70) is the percentage of that capacity an average tile may fill;
  * it sets the cells per tile (a power of two, 8..256).  draw_cells (1..16,
  * default 1) is the number of cells each lane of the per-cell draws takes.
- * Out-of-range values: MPCD_EINVAL. */
+ * draws_inline (0 or 1): 1 makes the collision draw each cell's random axis
+ * and gamma variate itself, in place of a separate draws pass (the same
+ * values).  Out-of-range values: MPCD_EINVAL. */
 typedef struct {
     int32_t tile_items;
     int32_t tile_fill;
     int32_t draw_cells;
+    int32_t draws_inline;
 } mpcd_tune;
 
 /* Scalars of one step. */
@@ -261,13 +264,16 @@ int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag,
  * (all three) the solvent is collided and streamed out of place, as in
  * mpcd_step: x_stream (required) and v, tag are read and left unchanged, and
  * the new state goes to the outputs in cell order.  tune (host, may be NULL
- * for the defaults) sets the collision tile shape, as in mpcd_params. */
+ * for the defaults) sets the collision tile shape, as in mpcd_params; with
+ * tune->draws_inline the collision draws each cell's axis and gamma variate
+ * itself (from seed and *d_step) and mpcd_cell_draws is not needed. */
 int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t seed,
                     const uint64_t *d_step, void *ws, size_t ws_bytes);
 int mpcd_collide_drawn(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream,
-                       double dt, void *x_out, void *v_out, int32_t *tag_out, const mpcd_tune *tune);
+                       double dt, void *x_out, void *v_out, int32_t *tag_out, uint64_t seed,
+                       const mpcd_tune *tune);
 
 /* Site positions and thermalized velocities, Eqs. (5) and (7).  Per body:
  * V = P/M, omega = A (Lhat / I) with Lhat_k = p . P_k q / 2; site offset

@@ -261,7 +261,7 @@ static bool tune_ok(const mpcd_tune &tu, bool f64)
     const int it = tu.tile_items;
     const bool items_ok = it == 0 || (f64 ? (it == 1 || it == 2 || it == 4) : (it == 2 || it == 4 || it == 8));
     return items_ok && (tu.tile_fill == 0 || (tu.tile_fill >= 10 && tu.tile_fill <= 100)) &&
-           tu.draw_cells >= 0 && tu.draw_cells <= 16;
+           tu.draw_cells >= 0 && tu.draw_cells <= 16 && (tu.draws_inline == 0 || tu.draws_inline == 1);
 }
 
 TileCfg tile_config(const mpcd_sys *s, const mpcd_tune &tu)
@@ -921,6 +921,7 @@ struct CollideArgs {
     uint32_t *status;
     uint64_t *advance_step;  // when set, block 0 advances the step counter (graph schedule)
     Forcing F;               // solvent acceleration applied by the fused streaming
+    int inline_draws;        // 1: the collision draws each cell's axis and gamma itself
 };
 
 // Identity order key of particle k: solvent tag (or index), sites N_total + j.
@@ -1075,12 +1076,53 @@ __device__ __forceinline__ void read_axis(const CollideArgs &A, int64_t gc, doub
     nax[2] = A.draws[2 * C + gc];
 }
 
-// lambda = sqrt(kT_cell g / E) when E > 0 (cell thermostat), else 1.
-__device__ __forceinline__ double thermostat_factor(const CollideArgs &A, int64_t gc, double E)
+// lambda = sqrt(kT_cell g / E) when E > 0 (cell thermostat), else 1; g is the
+// cell's gamma variate.
+__device__ __forceinline__ double thermostat_factor(const CollideArgs &A, double g, double E)
 {
     if (!(E > 0.0)) return 1.0;
-    const double Enew = A.kT_cell * A.draws[3 * A.s.C + gc];
+    const double Enew = A.kT_cell * g;
     return sqrt(Enew / E);
+}
+
+// The cell's random axis and, with the thermostat, its gamma variate (n: the
+// cell's member count).  Read from the draws pass, or (A.inline_draws) drawn
+// here by the same calls of the cell's streams as the draws pass makes, so
+// the values are the same either way; inside the collision the ALU work of
+// the draws overlaps the tile's gathers.
+template <int INL = -1>  // 0 or 1: known at compile time; -1: A.inline_draws
+__device__ __forceinline__ void cell_axis_gamma(const CollideArgs &A, int64_t gc, int n, double nax[3],
+                                                double &gvar, uint32_t &st)
+{
+    const SysDev &s = A.s;
+    gvar = 0.0;
+    if (INL == 0 || (INL < 0 && !A.inline_draws)) {
+        read_axis(A, gc, nax);
+        if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
+        return;
+    }
+    const int r = find_sys(s.cell_off, s.nsys, gc);
+    const uint64_t cl = (uint64_t)brick_canonical(s.ncell[3 * r], s.ncell[3 * r + 1], s.ncell[3 * r + 2],
+                                                  (int32_t)(gc - s.cell_off[r]));
+    const uint64_t rep = s.replica0 + (uint64_t)r, step = *A.d_step;
+    bool ok = false;
+    for (int call = 0; call < RNG_MAX_CALLS && !ok; ++call)
+        ok = axis_from_words(rng_draw(A.seed, RNG_AXIS, step, cl, rep, (uint64_t)call), nax);
+    if (!ok) {
+        nax[0] = 0.0; nax[1] = 0.0; nax[2] = 1.0;
+        st |= ST_RNGLOOP;
+    }
+    if (A.kT_cell > 0.0 && n >= 2) {
+        const double k = 0.5 * (double)(3 * (n - 1));
+        const double gd = k - 1.0 / 3.0, gcc = 1.0 / sqrt(9.0 * gd);
+        ok = false;
+        for (int call = 0; call < RNG_MAX_CALLS && !ok; ++call)
+            ok = gamma_from_words(rng_draw(A.seed, RNG_THERMO, step, cl, rep, (uint64_t)call), gd, gcc, &gvar);
+        if (!ok) {
+            gvar = gd;
+            st |= ST_RNGLOOP;
+        }
+    }
 }
 
 // ---- fallback: one lane per cell, members read from global memory ----------
@@ -1168,6 +1210,7 @@ __device__ void cell_stream_global(const CollideArgs &A, int64_t gc, const Membe
     }
 }
 
+template <int INL>
 __device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double *v, double *vs, double *x,
                                         const SolvOut<double> &O, uint32_t &st)
 {
@@ -1212,8 +1255,8 @@ __device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double
             P2 = P2 + mk * vel(i, k, 2);
         });
         const double u[3] = {P0 / M, P1 / M, P2 / M};
-        double nax[3];
-        read_axis(A, gc, nax);
+        double nax[3], gvar;
+        cell_axis_gamma<INL>(A, gc, n, nax, gvar, st);
         const Rot R = rotation(nax, A.cos_a, A.sin_a);
         double lam = 1.0;
         if (A.kT_cell > 0.0) {
@@ -1222,7 +1265,7 @@ __device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double
                 const double d0 = vel(i, k, 0) - u[0], d1 = vel(i, k, 1) - u[1], d2 = vel(i, k, 2) - u[2];
                 Es = Es + mass(k) * ((d0 * d0 + d1 * d1) + d2 * d2);
             });
-            lam = thermostat_factor(A, gc, 0.5 * Es);
+            lam = thermostat_factor(A, gvar, 0.5 * Es);
         }
         for (int i = b; i < e; ++i) {
             const int32_t k = A.perm[i];
@@ -1262,19 +1305,20 @@ __device__ __forceinline__ void fixed_terms(double mk, float fv0, float fv1, flo
 
 // Per-cell FP32 collision parameters from exact fixed-point sums: u and
 // lambda R rounded to float.
-__device__ __forceinline__ void f32_cell_params(const CollideArgs &A, int64_t gc, const long long q[5], float uf[3],
-                                                float Rf[3][3])
+template <int INL>
+__device__ __forceinline__ void f32_cell_params(const CollideArgs &A, int64_t gc, int n, const long long q[5],
+                                                float uf[3], float Rf[3][3], uint32_t &st)
 {
     const double Md = (double)q[0];
     const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
-    double nax[3];
-    read_axis(A, gc, nax);
+    double nax[3], gvar;
+    cell_axis_gamma<INL>(A, gc, n, nax, gvar, st);
     const Rot R = rotation(nax, A.cos_a, A.sin_a);
     double lam = 1.0;
     if (A.kT_cell > 0.0) {
         const double P0 = (double)q[1] * 0x1p-32, P1 = (double)q[2] * 0x1p-32, P2 = (double)q[3] * 0x1p-32;
         const double E = 0.5 * ((double)q[4] * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
-        lam = thermostat_factor(A, gc, E);
+        lam = thermostat_factor(A, gvar, E);
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -1283,6 +1327,7 @@ __device__ __forceinline__ void f32_cell_params(const CollideArgs &A, int64_t gc
     uf[0] = (float)u0; uf[1] = (float)u1; uf[2] = (float)u2;
 }
 
+template <int INL>
 __device__ void collide_cell_f32_global(const CollideArgs &A, int64_t gc, float *v, float *vs, float *x,
                                         const SolvOut<float> &O, uint32_t &st)
 {
@@ -1302,7 +1347,7 @@ __device__ void collide_cell_f32_global(const CollideArgs &A, int64_t gc, float 
             for (int j = 0; j < 5; ++j) acc[j] += q[j];
         }
         float uf[3], Rf[3][3];
-        f32_cell_params(A, gc, acc, uf, Rf);
+        f32_cell_params<INL>(A, gc, n, acc, uf, Rf, st);
         for (int i = b; i < e; ++i) {
             const int32_t k = A.perm[i];
             const float dl[3] = {vel(i, k, 0) - uf[0], vel(i, k, 1) - uf[1], vel(i, k, 2) - uf[2]};
@@ -1355,7 +1400,7 @@ __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
 }
 
 
-template <typename Real, int ITEMS>
+template <typename Real, int ITEMS, int INL>
 __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg &T, Real *v, Real *vs, Real *xstream,
                                              const SolvOut<Real> &O)
 {
@@ -1372,8 +1417,8 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     uint32_t st = 0;
     if (nm > T.cap) {
         for (int c = t; c < nc; c += TILE_T) {
-            if constexpr (F64) collide_cell_f64_global(A, c0 + c, v, vs, xstream, O, st);
-            else collide_cell_f32_global(A, c0 + c, v, vs, xstream, O, st);
+            if constexpr (F64) collide_cell_f64_global<INL>(A, c0 + c, v, vs, xstream, O, st);
+            else collide_cell_f32_global<INL>(A, c0 + c, v, vs, xstream, O, st);
         }
         flag(A.status, st);
         return;
@@ -1425,14 +1470,13 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
         const int64_t gc = c0 + t;
         const int cb0 = A.cell_start[gc] - m0, ce0 = A.cell_start[gc + 1] - m0;
         for (int i = cb0; i < ce0; ++i) s_cl[i] = (uint16_t)t;
+        cell_axis_gamma<INL>(A, gc, ce0 - cb0, nax, gvar, st);
         if constexpr (!F64) {
 #pragma unroll
             for (int z = 0; z < 5; ++z) s_acc[5 * t + z] = 0ull;
         }
         s_r[t] = find_sys(s.cell_off, s.nsys, gc);
         if (out) s_ss[t] = A.site_start[gc];
-        read_axis(A, gc, nax);
-        if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
     }
     __syncthreads();
 
@@ -1605,45 +1649,30 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     flag(A.status, st);
 }
 
-// One kernel per items-per-thread choice.  The FP32 default (4 items) is held
-// to 80 VGPRs (six waves per SIMD to hide the gather latency; measured faster
-// than five) and the 2-item form to 72 (seven waves); the 8-item form and FP64 keep the
-// compiler's allocation (a cap spills).
-__global__ __launch_bounds__(TILE_T) __attribute__((amdgpu_waves_per_eu(7))) void k_collide_tiled_f32_i2(
-    CollideArgs A, TileCfg T, float *v, float *vs, float *xstream, SolvOut<float> O)
-{
-    collide_tile<float, 2>(A, T, v, vs, xstream, O);
-}
-
-__global__ __launch_bounds__(TILE_T) __attribute__((amdgpu_waves_per_eu(6))) void k_collide_tiled_f32(
-    CollideArgs A, TileCfg T, float *v, float *vs, float *xstream, SolvOut<float> O)
-{
-    collide_tile<float, 4>(A, T, v, vs, xstream, O);
-}
-
-__global__ __launch_bounds__(TILE_T) void k_collide_tiled_f32_i8(CollideArgs A, TileCfg T, float *v, float *vs,
-                                                                 float *xstream, SolvOut<float> O)
-{
-    collide_tile<float, 8>(A, T, v, vs, xstream, O);
-}
-
-__global__ __launch_bounds__(TILE_T) void k_collide_tiled_f64_i1(CollideArgs A, TileCfg T, double *v, double *vs,
-                                                                 double *xstream, SolvOut<double> O)
-{
-    collide_tile<double, 1>(A, T, v, vs, xstream, O);
-}
-
-__global__ __launch_bounds__(TILE_T) void k_collide_tiled_f64(CollideArgs A, TileCfg T, double *v, double *vs,
-                                                              double *xstream, SolvOut<double> O)
-{
-    collide_tile<double, 2>(A, T, v, vs, xstream, O);
-}
-
-__global__ __launch_bounds__(TILE_T) void k_collide_tiled_f64_i4(CollideArgs A, TileCfg T, double *v, double *vs,
-                                                                 double *xstream, SolvOut<double> O)
-{
-    collide_tile<double, 4>(A, T, v, vs, xstream, O);
-}
+// One kernel per items-per-thread choice, each with the draws read from the
+// draws pass or made inside (suffix _d).  The FP32 4-item form without draws
+// is held to 80 VGPRs (six waves per SIMD to hide the gather latency;
+// measured faster than five) and the 2-item form to 72 (seven waves); the
+// other forms keep the compiler's allocation (a cap spills).
+#define MPCD_COLLIDE_KERNEL(NAME, ATTR, REAL, ITEMS, INL)                                                      \
+    __global__ __launch_bounds__(TILE_T) ATTR void NAME(CollideArgs A, TileCfg T, REAL *v, REAL *vs,           \
+                                                        REAL *xstream, SolvOut<REAL> O)                       \
+    {                                                                                                          \
+        collide_tile<REAL, ITEMS, INL>(A, T, v, vs, xstream, O);                                              \
+    }
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i2, __attribute__((amdgpu_waves_per_eu(7))), float, 2, 0)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f32, __attribute__((amdgpu_waves_per_eu(6))), float, 4, 0)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i8, , float, 8, 0)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i2_d, , float, 2, 1)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_d, , float, 4, 1)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i8_d, , float, 8, 1)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i1, , double, 1, 0)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f64, , double, 2, 0)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i4, , double, 4, 0)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i1_d, , double, 1, 1)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_d, , double, 2, 1)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i4_d, , double, 4, 1)
+#undef MPCD_COLLIDE_KERNEL
 
 // ---------------------------------------------------------------------------
 // (a1) site thermalization, Eqs. (5) and (7): one block per body.
@@ -3089,7 +3118,7 @@ int mpcd_cell_order(int32_t nsys, const int32_t *ncell, int64_t *pos)
 int mpcd_tile_shape(const mpcd_sys *sys, const mpcd_tune *tune, int32_t out[4])
 {
     TRY(check_sizes(sys));
-    const mpcd_tune tu = tune ? *tune : mpcd_tune{0, 0, 0};
+    const mpcd_tune tu = tune ? *tune : mpcd_tune{0, 0, 0, 0};
     if (!out || !tune_ok(tu, sys->prec == MPCD_F64)) return MPCD_EINVAL;
     const TileCfg T = tile_config(sys, tu);
     out[0] = T.items;
@@ -3173,7 +3202,7 @@ static Ctx make_ctx(const mpcd_sys *sys, void *ws, const mpcd_tune *tune = nullp
 {
     Ctx c;
     c.sys = sys;
-    c.tune = tune ? *tune : mpcd_tune{0, 0, 0};
+    c.tune = tune ? *tune : mpcd_tune{0, 0, 0, 0};
     c.sd = make_sysdev(sys);
     c.L = layout_of(sys);
     c.ws = ws;
@@ -3246,6 +3275,7 @@ static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bod
     A.status = c.status;
     A.advance_step = advance;
     A.F = make_forcing(nullptr, dt);
+    A.inline_draws = 0;
     return A;
 }
 
@@ -3272,13 +3302,18 @@ static void launch_collide(const Ctx &c, hipStream_t st, const CollideArgs &A, v
     const TileCfg T = tile_config(c.sys, c.tune);
     const dim3 grid(xcd_grid(T.ntiles));
     const size_t lds = tile_layout(f64, T.cpb, T.cap).end;
+    const bool d = A.inline_draws != 0;
     if (f64) {
         const SolvOut<double> O{(double *)x_out, (double *)v_out, tag_out};
-        auto kern = T.items == 1 ? k_collide_tiled_f64_i1 : (T.items == 4 ? k_collide_tiled_f64_i4 : k_collide_tiled_f64);
+        auto kern = T.items == 1 ? (d ? k_collide_tiled_f64_i1_d : k_collide_tiled_f64_i1)
+                  : T.items == 4 ? (d ? k_collide_tiled_f64_i4_d : k_collide_tiled_f64_i4)
+                                 : (d ? k_collide_tiled_f64_d : k_collide_tiled_f64);
         hipLaunchKernelGGL(kern, grid, dim3(TILE_T), lds, st, A, T, (double *)v, (double *)vs, (double *)x_stream, O);
     } else {
         const SolvOut<float> O{(float *)x_out, (float *)v_out, tag_out};
-        auto kern = T.items == 2 ? k_collide_tiled_f32_i2 : (T.items == 8 ? k_collide_tiled_f32_i8 : k_collide_tiled_f32);
+        auto kern = T.items == 2 ? (d ? k_collide_tiled_f32_i2_d : k_collide_tiled_f32_i2)
+                  : T.items == 8 ? (d ? k_collide_tiled_f32_i8_d : k_collide_tiled_f32_i8)
+                                 : (d ? k_collide_tiled_f32_d : k_collide_tiled_f32);
         hipLaunchKernelGGL(kern, grid, dim3(TILE_T), lds, st, A, T, (float *)v, (float *)vs, (float *)x_stream, O);
     }
 }
@@ -3528,13 +3563,15 @@ int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t 
 int mpcd_collide_drawn(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag, void *vs,
                        const mpcd_bodies *bodies, double cos_a, double sin_a, double kT_cell,
                        const uint64_t *d_step, void *ws, size_t ws_bytes, void *x_stream, double dt,
-                       void *x_out, void *v_out, int32_t *tag_out, const mpcd_tune *tune)
+                       void *x_out, void *v_out, int32_t *tag_out, uint64_t seed, const mpcd_tune *tune)
 {
     TRY(collide_checks(sys, v, tag, vs, bodies, d_step, ws, ws_bytes, x_stream, dt));
     TRY(out_checks(sys, v, tag, x_stream, x_out, v_out, tag_out));
     if (tune && !tune_ok(*tune, sys->prec == MPCD_F64)) return MPCD_EINVAL;
     const Ctx c = make_ctx(sys, ws, tune);
-    const CollideArgs A = collide_args(c, tag, bodies, cos_a, sin_a, kT_cell, 0, d_step, dt, nullptr);
+    CollideArgs A = collide_args(c, tag, bodies, cos_a, sin_a, kT_cell, c.tune.draws_inline ? seed : 0, d_step, dt,
+                                 nullptr);
+    A.inline_draws = c.tune.draws_inline;
     launch_collide(c, (hipStream_t)stream, A, v, vs, x_stream, x_out, v_out, tag_out);
     return launch_check();
 }
@@ -3733,7 +3770,12 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
     CollideArgs A = collide_args(c, a->tag, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed, a->d_step, p.dt,
                                  nullptr);
     if (p.fuse_stream) A.F = make_forcing(p.g, p.dt);
-    launch_scatter_draws(c, st, A);
+    if (p.tune.draws_inline) {  // the collision draws; the scatter runs alone
+        A.inline_draws = 1;
+        launch_scatter(c, st);
+    } else {
+        launch_scatter_draws(c, st, A);
+    }
     if (a->v_out)
         launch_collide(c, st, A, a->v, a->vs, a->x, a->x_out, a->v_out, a->tag_out);
     else
@@ -3884,7 +3926,7 @@ int harm_step(void *stream, const mpcd_step_args *a, const mpcd_harm *h, double 
     TRY(mpcd_bin(stream, s, a->x, a->xs, &a->bodies, p.seed, a->d_step, a->ws, a->ws_bytes));
     TRY(mpcd_cell_draws(stream, s, p.kT_cell, p.seed, a->d_step, a->ws, a->ws_bytes));
     TRY(mpcd_collide_drawn(stream, s, a->v, a->tag, a->vs, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, a->d_step,
-                           a->ws, a->ws_bytes, a->x, p.dt, a->x_out, a->v_out, a->tag_out, nullptr));
+                           a->ws, a->ws_bytes, a->x, p.dt, a->x_out, a->v_out, a->tag_out, p.seed, nullptr));
     TRY(harm_md(stream, s, h, (double *)a->xs, (double *)a->vs, &p.wca, dt_md, nsub, a->ws, a->ws_bytes));
     return mpcd_advance_step(stream, a->d_step);
 }

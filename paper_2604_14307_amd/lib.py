@@ -46,7 +46,8 @@ class MpcdWca(C.Structure):
 
 
 class MpcdTune(C.Structure):
-    _fields_ = [("tile_items", C.c_int32), ("tile_fill", C.c_int32), ("draw_cells", C.c_int32)]
+    _fields_ = [("tile_items", C.c_int32), ("tile_fill", C.c_int32), ("draw_cells", C.c_int32),
+                ("draws_inline", C.c_int32)]
 
 
 class MpcdParams(C.Structure):
@@ -104,7 +105,7 @@ def load(path: str = LIB_PATH):
         "mpcd_collide": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, u64, vp, vp, sz, vp, dbl]),
         "mpcd_cell_draws": (C.c_int, [vp, sp, dbl, u64, vp, vp, sz]),
         "mpcd_collide_drawn": (C.c_int, [vp, sp, vp, vp, vp, bp, dbl, dbl, dbl, vp, vp, sz, vp, dbl, vp, vp, vp,
-                                         C.POINTER(MpcdTune)]),
+                                         u64, C.POINTER(MpcdTune)]),
         "sites_thermalize": (C.c_int, [vp, sp, bp, dbl, i32, u64, vp, vp, vp, vp, sz]),
         "sites_to_body": (C.c_int, [vp, sp, bp, vp, vp, sz, vp, vp]),
         "body_integrate": (C.c_int, [vp, sp, bp, vp, vp, wp, C.POINTER(dbl), dbl, vp, sz]),

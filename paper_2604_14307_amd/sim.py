@@ -131,7 +131,7 @@ class GPUSystem:
         self.rnemd = None
         self.rnemd_dp = torch.zeros(1, dtype=torch.float64, device=dev)
         # launch shapes (zero: the library's defaults); results do not depend on them
-        self.tuning = L.MpcdTune(0, 0, 0)
+        self.tuning = L.MpcdTune(0, 0, 0, 0)
         self.ws_init()
         self._graph = None
 
@@ -165,9 +165,9 @@ class GPUSystem:
                                     rnemd_dp=_ptr(self.rnemd_dp))
         return self._args
 
-    def set_tuning(self, tile_items: int = 0, tile_fill: int = 0, draw_cells: int = 0):
+    def set_tuning(self, tile_items: int = 0, tile_fill: int = 0, draw_cells: int = 0, draws_inline: int = 0):
         """Launch shapes of the step (see mpcd_tune); 0 keeps a default."""
-        self.tuning = L.MpcdTune(int(tile_items), int(tile_fill), int(draw_cells))
+        self.tuning = L.MpcdTune(int(tile_items), int(tile_fill), int(draw_cells), int(draws_inline))
         self.tile_shape()  # validates
 
     def tile_shape(self, tune=None):
@@ -251,7 +251,8 @@ class GPUSystem:
                                             _ptr(self.vs), C.byref(self.cbodies), p["cos_a"], p["sin_a"],
                                             p["kT_cell"], _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
                                             _ptr(self.x) if stream_x else C.c_void_p(0), p["dt"],
-                                            C.c_void_p(0), C.c_void_p(0), C.c_void_p(0), C.byref(self.tuning)),
+                                            C.c_void_p(0), C.c_void_p(0), C.c_void_p(0), p["seed"],
+                                            C.byref(self.tuning)),
                 "mpcd_collide_drawn")
 
     def sites_to_body(self):
@@ -301,7 +302,7 @@ class GPUSystem:
                                             _ptr(self.vs), C.byref(self.cbodies), p["cos_a"], p["sin_a"],
                                             p["kT_cell"], _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
                                             _ptr(self.x2), p["dt"], _ptr(self.x), _ptr(self.v), _ptr(self.tag),
-                                            C.byref(self.tuning)),
+                                            p["seed"], C.byref(self.tuning)),
                 "mpcd_collide_drawn")
 
     def reorder(self):

@@ -22,6 +22,7 @@ from . import lib as L
 FILLS = (40, 55, 70, 85)
 ITEMS = {"f32": (2, 4, 8), "f64": (1, 2, 4)}
 DRAW_CELLS = (1, 2)
+DRAWS_INLINE = (0, 1)
 
 
 def arch(device) -> str:
@@ -37,19 +38,21 @@ def workload_key(g) -> str:
 
 
 def candidates(g):
-    """Distinct shapes: tunings with the same tile shape and draw split are
-    the same launch.  The default (all zero) comes first."""
+    """Distinct shapes (items, fill, draw_cells, draws_inline): tunings with the
+    same tile shape and the same draws are the same launch (cells per lane do
+    not matter when the collision draws).  The default comes first."""
     seen, out = set(), []
     for items in ITEMS[prec_name(g)]:
         for fill in FILLS:
-            for dc in DRAW_CELLS:
-                shape = g.tile_shape((items, fill, dc))
-                key = (shape[0], shape[1], dc)
-                if key not in seen:
-                    seen.add(key)
-                    out.append((items, fill, dc))
-    d = g.tile_shape((0, 0, 0))
-    default = next(c for c in out if g.tile_shape(c)[:2] == d[:2] and c[2] == 1)
+            for inl in DRAWS_INLINE:
+                for dc in (DRAW_CELLS if not inl else (1,)):
+                    shape = g.tile_shape((items, fill, dc, inl))
+                    key = (shape[0], shape[1], dc, inl)
+                    if key not in seen:
+                        seen.add(key)
+                        out.append((items, fill, dc, inl))
+    d = g.tile_shape((0, 0, 0, 0))
+    default = next(c for c in out if g.tile_shape(c)[:2] == d[:2] and c[2] == 1 and c[3] == 0)
     out.remove(default)
     return [default] + out
 

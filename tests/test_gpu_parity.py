@@ -654,7 +654,8 @@ def test_every_launch_shape_gives_the_same_bits(prec):
     wl = W.suspension((14, 18, 11), 5, 4, 2.0, 60, 5.0, seed=88)
     par = W.srd_params(88, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
     items = (1, 2, 4) if prec == "f64" else (2, 4, 8)
-    shapes = [(0, 0, 0)] + [(it, fill, dc) for it in items for fill, dc in ((10, 3), (55, 1), (100, 16))]
+    shapes = [(0, 0, 0, 0)] + [(it, fill, dc, inl) for it in items
+                               for fill, dc, inl in ((10, 3, 0), (55, 1, 1), (100, 16, 0), (100, 1, 1))]
     ref = None
     for sh in shapes:
         g = gpu_system(wl, par, prec=prec)
