@@ -152,7 +152,8 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None,
 
 def tuning_record(g, tuned):
     t = g.tuning
-    rec = {"tune_items_fill_drawcells_inline": [t.tile_items, t.tile_fill, t.draw_cells, t.draws_inline],
+    rec = {"tune_items_fill_drawcells_inline_overlap": [t.tile_items, t.tile_fill, t.draw_cells, t.draws_inline,
+                                                         t.overlap],
            "tile_items_cells_cap_tiles": list(g.tile_shape())}
     if tuned:
         rec["source"] = "cache" if tuned["cached"] else "tuned in this run"
@@ -297,7 +298,7 @@ def main():
     N, S = r32["N"], r32["S"]
     ach = collide_bytes(N, S, 4) / (r32["collide_ms"] * 1e-3) / 1e9
     kname = collide_kernel_name(r32["tuning"]["tile_items_cells_cap_tiles"][0],
-                                r32["tuning"]["tune_items_fill_drawcells_inline"][3])
+                                r32["tuning"]["tune_items_fill_drawcells_inline_overlap"][3])
     out = {
         "metric": "solvent particle-steps/s",
         "value": r32["rate"],

@@ -131,12 +131,16 @@ typedef struct {
  * default 1) is the number of cells each lane of the per-cell draws takes.
  * draws_inline (0 or 1): 1 makes the collision draw each cell's random axis
  * and gamma variate itself, in place of a separate draws pass (the same
- * values).  Out-of-range values: MPCD_EINVAL. */
+ * values).  overlap (0 or 1): 1 lets mpcd_graph_create bin the solvent of
+ * each next step on a second stream beside the current step's body update
+ * (out-of-place steps with sites and no reorder; elsewhere ignored).
+ * Out-of-range values: MPCD_EINVAL. */
 typedef struct {
     int32_t tile_items;
     int32_t tile_fill;
     int32_t draw_cells;
     int32_t draws_inline;
+    int32_t overlap;
 } mpcd_tune;
 
 /* Scalars of one step. */

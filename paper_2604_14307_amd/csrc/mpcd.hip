@@ -261,7 +261,8 @@ static bool tune_ok(const mpcd_tune &tu, bool f64)
     const int it = tu.tile_items;
     const bool items_ok = it == 0 || (f64 ? (it == 1 || it == 2 || it == 4) : (it == 2 || it == 4 || it == 8));
     return items_ok && (tu.tile_fill == 0 || (tu.tile_fill >= 10 && tu.tile_fill <= 100)) &&
-           tu.draw_cells >= 0 && tu.draw_cells <= 16 && (tu.draws_inline == 0 || tu.draws_inline == 1);
+           tu.draw_cells >= 0 && tu.draw_cells <= 16 && (tu.draws_inline == 0 || tu.draws_inline == 1) &&
+           (tu.overlap == 0 || tu.overlap == 1);
 }
 
 TileCfg tile_config(const mpcd_sys *s, const mpcd_tune &tu)
@@ -285,7 +286,7 @@ TileCfg tile_config(const mpcd_sys *s, const mpcd_tune &tu)
 
 struct Layout {
     size_t status, shift, counts, partial, cell_start, site_start, cellid, slot, perm, draws, site_d, vpre, rtmp,
-        grid_count, grid_body, wpos, woff, rn_hist, rn_bcnt, rn_ctl, rn_key, rn_id, rn_k, total;
+        grid_count, grid_body, wpos, woff, step_next, rn_hist, rn_bcnt, rn_ctl, rn_key, rn_id, rn_k, total;
     uint32_t grid_mask;
 };
 
@@ -342,6 +343,9 @@ Layout layout_of(const mpcd_sys *s)
     // site frames for the site-site WCA (offsets and unwrapped positions)
     L.wpos = take(sizeof(double) * 3 * (size_t)s->n_sites);
     L.woff = take(sizeof(double) * 3 * (size_t)s->n_sites);
+    // the next step's index, stored by the collision for a binning of the next
+    // step that runs beside this step's body update
+    L.step_next = take(sizeof(uint64_t));
     // reverse nonequilibrium exchange: key histograms, control words and
     // candidate lists of the two slabs
     L.rn_hist = take(sizeof(int32_t) * 2 * RN_BINS);
@@ -920,6 +924,7 @@ struct CollideArgs {
     const uint64_t *d_step;
     uint32_t *status;
     uint64_t *advance_step;  // when set, block 0 advances the step counter (graph schedule)
+    uint64_t *step_next;     // when set, block 0 stores the step index + 1 there
     Forcing F;               // solvent acceleration applied by the fused streaming
     int inline_draws;        // 1: the collision draws each cell's axis and gamma itself
 };
@@ -1407,6 +1412,7 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     constexpr bool F64 = sizeof(Real) == 8;
     extern __shared__ __align__(16) unsigned char smem[];
     if (A.advance_step && blockIdx.x == 0 && threadIdx.x == 0) *A.advance_step = *A.advance_step + 1;
+    if (A.step_next && blockIdx.x == 0 && threadIdx.x == 0) *A.step_next = *A.d_step + 1;
     const int tile = tile_of_block(T.ntiles);
     if (tile >= T.ntiles) return;
     const SysDev &s = A.s;
@@ -1841,8 +1847,11 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
 
 // First kernel of a step: blocks [0, B) thermalize one body each and bin its
 // sites; the remaining blocks bin PREP_CHUNK solvent particles each.  Every
-// block draws the grid shifts it needs; block 0 also stores them.
-template <typename Real>
+// block draws the grid shifts it needs; block 0 also stores them.  PART 0 is
+// that whole kernel; PART 1 its body blocks (with the shift store and the
+// grid clearing) and PART 2 its solvent blocks, compiled without the body
+// code, for a schedule that bins the solvent on another stream.
+template <typename Real, int PART>
 __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT, int thermalize, uint64_t seed,
                                                  const uint64_t *d_step, const Real *x, Real *xs, Real *vs,
                                                  double *site_d, double *vpre, unsigned long long *counts,
@@ -1857,19 +1866,23 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
     } lds;
     const uint64_t step = *d_step;
     uint32_t st = 0;
-    if (blockIdx.x == 0) draw_shifts(s, seed, step, shift_out);
-    // clear the body-centre grid for this step's insertions (after the drift)
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; grid_count && q < grid_n;
-         q += (int64_t)gridDim.x * blockDim.x)
-        grid_count[q] = 0;
-    if ((int64_t)blockIdx.x < s.B) {
-        const int64_t b = blockIdx.x;
-        if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0))
-            shift_of(s, seed, step, find_sys(s.body_off, s.nsys, b), bsh);
-        thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid, slot,
-                              lds.th, st);
+    if constexpr (PART != 2) {
+        if (blockIdx.x == 0) draw_shifts(s, seed, step, shift_out);
+        // clear the body-centre grid for this step's insertions (after the drift)
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; grid_count && q < grid_n;
+             q += (int64_t)gridDim.x * blockDim.x)
+            grid_count[q] = 0;
+    }
+    if (PART == 1 || (PART == 0 && (int64_t)blockIdx.x < s.B)) {
+        if constexpr (PART != 2) {
+            const int64_t b = blockIdx.x;
+            if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0))
+                shift_of(s, seed, step, find_sys(s.body_off, s.nsys, b), bsh);
+            thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid,
+                                  slot, lds.th, st);
+        }
     } else {
-        const int64_t kbase = ((int64_t)blockIdx.x - s.B) * PREP_CHUNK;
+        const int64_t kbase = ((int64_t)blockIdx.x - (PART == 0 ? s.B : 0)) * PREP_CHUNK;
         const int64_t k1 = s.N;
         if (threadIdx.x == 0) {
             int ra, rb;
@@ -3118,7 +3131,7 @@ int mpcd_cell_order(int32_t nsys, const int32_t *ncell, int64_t *pos)
 int mpcd_tile_shape(const mpcd_sys *sys, const mpcd_tune *tune, int32_t out[4])
 {
     TRY(check_sizes(sys));
-    const mpcd_tune tu = tune ? *tune : mpcd_tune{0, 0, 0, 0};
+    const mpcd_tune tu = tune ? *tune : mpcd_tune{0, 0, 0, 0, 0};
     if (!out || !tune_ok(tu, sys->prec == MPCD_F64)) return MPCD_EINVAL;
     const TileCfg T = tile_config(sys, tu);
     out[0] = T.items;
@@ -3202,7 +3215,7 @@ static Ctx make_ctx(const mpcd_sys *sys, void *ws, const mpcd_tune *tune = nullp
 {
     Ctx c;
     c.sys = sys;
-    c.tune = tune ? *tune : mpcd_tune{0, 0, 0, 0};
+    c.tune = tune ? *tune : mpcd_tune{0, 0, 0, 0, 0};
     c.sd = make_sysdev(sys);
     c.L = layout_of(sys);
     c.ws = ws;
@@ -3274,6 +3287,7 @@ static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bod
     A.d_step = d_step;
     A.status = c.status;
     A.advance_step = advance;
+    A.step_next = nullptr;
     A.F = make_forcing(nullptr, dt);
     A.inline_draws = 0;
     return A;
@@ -3374,7 +3388,7 @@ static void launch_body_grid(const Ctx &c, hipStream_t st, const mpcd_bodies *bo
 
 static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, double kT, int thermalize,
                         uint64_t seed, const uint64_t *d_step, const void *x, void *xs, void *vs,
-                        const mpcd_wca &wca)
+                        const mpcd_wca &wca, int part = 0)
 {
     const BodyGrid grid = body_grid(c, wca);
     const int64_t grid_n = grid.count ? (int64_t)c.L.grid_mask + 1 : 0;
@@ -3384,20 +3398,28 @@ static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies,
     const BodyDev bd = make_bodydev(bodies);
     SysDev sd = c.sd;
     if (nb == 0) sd.B = 0;  // no site work: every block bins solvent
-    const dim3 g((unsigned)(nb + nchunks > 0 ? nb + nchunks : 1));
     double *site_d = at<double>(c.ws, c.L.site_d), *vpre = at<double>(c.ws, c.L.vpre);
     u64 *counts = at<u64>(c.ws, c.L.counts);
     int32_t *cellid = at<int32_t>(c.ws, c.L.cellid);
     int32_t *slot = at<int32_t>(c.ws, c.L.slot);
     double *shift = at<double>(c.ws, c.L.shift);
-    if (c.sys->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_prep<double>, g, dim3(BODY_T), 0, st, sd, bd, kT, thermalize, seed, d_step,
-                           (const double *)x, (double *)xs, (double *)vs, site_d, vpre, counts, grid.count, grid_n,
-                           cellid, slot, shift, c.status);
-    else
-        hipLaunchKernelGGL(k_prep<float>, g, dim3(BODY_T), 0, st, sd, bd, kT, thermalize, seed, d_step,
-                           (const float *)x, (float *)xs, (float *)vs, site_d, vpre, counts, grid.count, grid_n,
-                           cellid, slot, shift, c.status);
+    // part 1: the body blocks alone; part 2: the solvent blocks alone (both
+    // only with sites); otherwise the whole kernel
+    const int pk = (nb > 0 && (part == 1 || part == 2)) ? part : 0;
+    const int64_t nblocks = pk == 1 ? nb : pk == 2 ? nchunks : nb + nchunks;
+    if (nblocks <= 0 && pk != 0) return;
+    const dim3 g((unsigned)(nblocks > 0 ? nblocks : 1));
+    if (c.sys->prec == MPCD_F64) {
+        auto k = pk == 1 ? k_prep<double, 1> : pk == 2 ? k_prep<double, 2> : k_prep<double, 0>;
+        hipLaunchKernelGGL(k, g, dim3(BODY_T), 0, st, sd, bd, kT, thermalize, seed, d_step, (const double *)x,
+                           (double *)xs, (double *)vs, site_d, vpre, counts, grid.count, grid_n, cellid, slot, shift,
+                           c.status);
+    } else {
+        auto k = pk == 1 ? k_prep<float, 1> : pk == 2 ? k_prep<float, 2> : k_prep<float, 0>;
+        hipLaunchKernelGGL(k, g, dim3(BODY_T), 0, st, sd, bd, kT, thermalize, seed, d_step, (const float *)x,
+                           (float *)xs, (float *)vs, site_d, vpre, counts, grid.count, grid_n, cellid, slot, shift,
+                           c.status);
+    }
 }
 
 // Scatter fused with the per-cell draws in one launch.
@@ -3753,22 +3775,48 @@ static void step_rnemd(const Ctx &c, hipStream_t st, const mpcd_step_args *a)
         launch_rnemd(c, st, a->x, a->v, a->tag, a->rnemd, a->rnemd_dp);
 }
 
+// Overlap schedule of a captured run of out-of-place steps: the solvent of
+// step t+1 is binned on a second stream right after step t's collision
+// (it needs only the new solvent positions), beside step t's body update;
+// step t+1 then thermalizes and bins its sites alone and joins that binning
+// before its scan.  The early binning reads the step index t+1 that the
+// collision stored, not the counter that step t's force kernel advances.
+struct Overlap {
+    hipStream_t side;
+    hipEvent_t fork, join;
+    bool pre_binned;  // this step's solvent is binned already (on side, joined by `join`)
+    bool bin_next;    // bin the next step's solvent on side after this step's collision
+};
+
+static bool overlap_possible(const mpcd_step_args *a)
+{
+    return a->par.tune.overlap && a->v_out && a->reorder_every == 0 && a->sys->n_bodies > 0 &&
+           a->sys->n_sites > 0 && a->sys->n_solvent > 0;
+}
+
 // One step: [thermalize + site binning | solvent binning] (one launch), scan,
 // [scatter | per-cell draws] (one launch), collide + stream, transfer fused
 // with the first body half-step, forces fused with the second half kick and
 // the step-counter advance.  The same operations in the same order, per
 // particle, cell and body, as calling the entry points in sequence.
-int mpcd_step(void *stream, const mpcd_step_args *a)
+static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
 {
     TRY(step_checks(a));
     const mpcd_sys *s = a->sys;
     const mpcd_params &p = a->par;
     const Ctx c = make_ctx(s, a->ws, &p.tune);
     hipStream_t st = (hipStream_t)stream;
-    launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca);
+    if (ov && ov->pre_binned) {
+        launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca, 1);
+        TRY(hip_check(hipStreamWaitEvent(st, ov->join, 0)));
+    } else {
+        launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca);
+    }
     launch_scan(c, st);
     CollideArgs A = collide_args(c, a->tag, &a->bodies, p.cos_a, p.sin_a, p.kT_cell, p.seed, a->d_step, p.dt,
                                  nullptr);
+    uint64_t *step_next = at<uint64_t>(c.ws, c.L.step_next);
+    if (ov && ov->bin_next) A.step_next = step_next;
     if (p.fuse_stream) A.F = make_forcing(p.g, p.dt);
     if (p.tune.draws_inline) {  // the collision draws; the scatter runs alone
         A.inline_draws = 1;
@@ -3780,6 +3828,13 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
         launch_collide(c, st, A, a->v, a->vs, a->x, a->x_out, a->v_out, a->tag_out);
     else
         launch_collide(c, st, A, a->v, a->vs, p.fuse_stream ? a->x : nullptr);
+    if (ov && ov->bin_next) {  // next step's solvent binning beside this step's body update
+        TRY(hip_check(hipEventRecord(ov->fork, st)));
+        TRY(hip_check(hipStreamWaitEvent(ov->side, ov->fork, 0)));
+        launch_prep(c, ov->side, &a->bodies, p.kT, p.thermalize, p.seed, step_next, a->x_out, a->xs, a->vs, p.wca,
+                    2);
+        TRY(hip_check(hipEventRecord(ov->join, ov->side)));
+    }
     if (!p.fuse_stream) TRY(mpcd_stream(stream, s, a->x, a->v, p.dt, p.g, a->ws, a->ws_bytes));
     if (s->n_bodies == 0) {
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a->d_step);
@@ -3792,14 +3847,38 @@ int mpcd_step(void *stream, const mpcd_step_args *a)
     return launch_check();
 }
 
+int mpcd_step(void *stream, const mpcd_step_args *a) { return step_impl(stream, a, nullptr); }
+
 int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, void **graph_exec)
 {
     if (!stream || !args || nsteps < 1 || !graph_exec) return MPCD_EINVAL;
     TRY(step_checks(args));
     if (args->v_out && ((nsteps & 1) || !args->tag)) return MPCD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    TRY(hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)));
-    int rc = MPCD_OK;
+    Overlap ov{nullptr, nullptr, nullptr, false, false};
+    const bool overlap = nsteps >= 2 && overlap_possible(args);
+    if (overlap) {  // default-priority side stream and the two events, for the capture only
+        int rc0 = hip_check(hipStreamCreateWithFlags(&ov.side, hipStreamNonBlocking));
+        if (rc0 == MPCD_OK) rc0 = hip_check(hipEventCreateWithFlags(&ov.fork, hipEventDisableTiming));
+        if (rc0 == MPCD_OK) rc0 = hip_check(hipEventCreateWithFlags(&ov.join, hipEventDisableTiming));
+        if (rc0 != MPCD_OK) {
+            if (ov.join) (void)hipEventDestroy(ov.join);
+            if (ov.fork) (void)hipEventDestroy(ov.fork);
+            if (ov.side) (void)hipStreamDestroy(ov.side);
+            return rc0;
+        }
+    }
+    auto release = [&]() {
+        if (!overlap) return;
+        (void)hipEventDestroy(ov.join);
+        (void)hipEventDestroy(ov.fork);
+        (void)hipStreamDestroy(ov.side);
+    };
+    int rc = hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    if (rc != MPCD_OK) {
+        release();
+        return rc;
+    }
     mpcd_step_args swapped = *args;  // odd steps of the out-of-place form: outputs become inputs
     if (args->v_out) {
         swapped.x = args->x_out;
@@ -3810,7 +3889,9 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
         swapped.tag_out = (int32_t *)args->tag;
     }
     for (int i = 0; i < nsteps && rc == MPCD_OK; ++i) {
-        rc = mpcd_step(stream, (args->v_out && (i & 1)) ? &swapped : args);
+        ov.pre_binned = overlap && i > 0;
+        ov.bin_next = overlap && i + 1 < nsteps;
+        rc = step_impl(stream, (args->v_out && (i & 1)) ? &swapped : args, overlap ? &ov : nullptr);
         if (rc == MPCD_OK && !args->v_out && args->reorder_every > 0 && (i + 1) % args->reorder_every == 0)
             rc = mpcd_reorder(stream, args->sys, args->x, args->v, (int32_t *)args->tag, args->ws, args->ws_bytes);
     }
@@ -3820,6 +3901,7 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
     hipGraphExec_t exec = nullptr;
     if (rc == MPCD_OK) rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     if (graph) (void)hipGraphDestroy(graph);
+    release();
     TRY(rc);
     *graph_exec = (void *)exec;
     return MPCD_OK;

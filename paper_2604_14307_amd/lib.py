@@ -47,7 +47,7 @@ class MpcdWca(C.Structure):
 
 class MpcdTune(C.Structure):
     _fields_ = [("tile_items", C.c_int32), ("tile_fill", C.c_int32), ("draw_cells", C.c_int32),
-                ("draws_inline", C.c_int32)]
+                ("draws_inline", C.c_int32), ("overlap", C.c_int32)]
 
 
 class MpcdParams(C.Structure):

@@ -131,7 +131,7 @@ class GPUSystem:
         self.rnemd = None
         self.rnemd_dp = torch.zeros(1, dtype=torch.float64, device=dev)
         # launch shapes (zero: the library's defaults); results do not depend on them
-        self.tuning = L.MpcdTune(0, 0, 0, 0)
+        self.tuning = L.MpcdTune(0, 0, 0, 0, 0)
         self.ws_init()
         self._graph = None
 
@@ -165,9 +165,10 @@ class GPUSystem:
                                     rnemd_dp=_ptr(self.rnemd_dp))
         return self._args
 
-    def set_tuning(self, tile_items: int = 0, tile_fill: int = 0, draw_cells: int = 0, draws_inline: int = 0):
+    def set_tuning(self, tile_items: int = 0, tile_fill: int = 0, draw_cells: int = 0, draws_inline: int = 0,
+                   overlap: int = 0):
         """Launch shapes of the step (see mpcd_tune); 0 keeps a default."""
-        self.tuning = L.MpcdTune(int(tile_items), int(tile_fill), int(draw_cells), int(draws_inline))
+        self.tuning = L.MpcdTune(int(tile_items), int(tile_fill), int(draw_cells), int(draws_inline), int(overlap))
         self.tile_shape()  # validates
 
     def tile_shape(self, tune=None):

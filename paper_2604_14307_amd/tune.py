@@ -2,12 +2,15 @@
 
 The step's launch shapes (``mpcd_tune``: items per thread of a collision
 tile, the fill that sets the cells per tile, cells per lane of the per-cell
-draws) change how work is split over blocks, never the results.  The tuner
-times HIP-graph replays of a few steps of the caller's own system for each
-distinct shape, restores the state after every trial, keeps the fastest shape
-on the system and records it in a JSON cache keyed by the GPU architecture,
-the precision and the system sizes, so a later run on the same workload
-reuses it without timing.
+draws, draws inside the collision or in a pass of their own, and the overlap
+of each next step's solvent binning with the current step's body update in
+graphs) change how work is split over blocks and streams, never the results.
+The tuner times HIP-graph replays of a few steps of the caller's own system
+for each distinct collision shape, then the overlap on top of the fastest one
+(the two choices touch different kernels), restores the state after every
+trial, keeps the fastest shape on the system and records it in a JSON cache
+keyed by the GPU architecture, the precision and the system sizes, so a later
+run on the same workload reuses it without timing.
 """
 from __future__ import annotations
 
@@ -23,6 +26,7 @@ FILLS = (40, 55, 70, 85)
 ITEMS = {"f32": (2, 4, 8), "f64": (1, 2, 4)}
 DRAW_CELLS = (1, 2)
 DRAWS_INLINE = (0, 1)
+OVERLAP = (0, 1)
 
 
 def arch(device) -> str:
@@ -38,9 +42,10 @@ def workload_key(g) -> str:
 
 
 def candidates(g):
-    """Distinct shapes (items, fill, draw_cells, draws_inline): tunings with the
-    same tile shape and the same draws are the same launch (cells per lane do
-    not matter when the collision draws).  The default comes first."""
+    """Distinct collision shapes (items, fill, draw_cells, draws_inline, 0):
+    tunings with the same tile shape and the same draws are the same launch
+    (cells per lane do not matter when the collision draws).  The default
+    comes first."""
     seen, out = set(), []
     for items in ITEMS[prec_name(g)]:
         for fill in FILLS:
@@ -50,8 +55,8 @@ def candidates(g):
                     key = (shape[0], shape[1], dc, inl)
                     if key not in seen:
                         seen.add(key)
-                        out.append((items, fill, dc, inl))
-    d = g.tile_shape((0, 0, 0, 0))
+                        out.append((items, fill, dc, inl, 0))
+    d = g.tile_shape((0, 0, 0, 0, 0))
     default = next(c for c in out if g.tile_shape(c)[:2] == d[:2] and c[2] == 1 and c[3] == 0)
     out.remove(default)
     return [default] + out
@@ -85,7 +90,7 @@ def load_cache(path):
 def autotune(g, steps: int = 20, repeats: int = 3, cache_path: str | None = None, retune: bool = False,
              write: bool = True) -> dict:
     """Pick the fastest launch shape for system g and set it.  Returns
-    {"tune": (items, fill, draw_cells), "ms_per_step", "default_ms_per_step",
+    {"tune": (items, fill, draw_cells, draws_inline, overlap), "ms_per_step", "default_ms_per_step",
     "shapes_tried", "tile", "cached"}.  The simulation state is unchanged.  A
     shape cached for this workload is used as it is unless retune; a new
     result is written to cache_path when write."""
@@ -105,6 +110,12 @@ def autotune(g, steps: int = 20, repeats: int = 3, cache_path: str | None = None
     for cand in candidates(g):
         g.restore(snap)
         results.append((time_shape(g, cand, steps, repeats), cand))
+    if g.B > 0 and g.S > 0 and g.out_of_place and steps >= 2:  # the overlap needs sites and out-of-place graphs
+        best = min(results)[1]
+        for ov in OVERLAP[1:]:
+            g.restore(snap)
+            cand = best[:4] + (ov,)
+            results.append((time_shape(g, cand, steps, repeats), cand))
     g.restore(snap)
     torch.cuda.synchronize(g.device)
     if g.status() != 0:

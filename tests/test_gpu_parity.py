@@ -296,6 +296,38 @@ def test_graph_replay_matches_eager(out_of_place):
         gg.release_graph()
 
 
+@pytest.mark.parametrize("prec,exchange", [("f64", False), ("f32", False), ("f32", True)])
+def test_overlapped_graph_matches_eager(prec, exchange):
+    """Graphs that bin each next step's solvent on a second stream, beside the
+    current step's body update, give the state of the same steps run one by
+    one (bodies with sites, WCA, out of place; with the exchange appended)."""
+    wl = W.suspension((14, 18, 11), 5, 4, 2.0, 60, 5.0, seed=91)
+    par = W.srd_params(91, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
+    say("overlapped graph %s exchange=%s" % (prec, exchange))
+    ge, gg = gpu_system(wl, par, prec=prec), gpu_system(wl, par, prec=prec)
+    ge.set_tuning(0, 0, 0, 1, 0)
+    gg.set_tuning(0, 0, 0, 1, 1)
+    for g in (ge, gg):
+        g.body_forces()
+        if exchange:
+            g.set_rnemd(0.0, 9.0, 1.0, 0.5, 20)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        gg.graph(6)
+        for rep in range(3):
+            gg.graph_launch()
+            ge.step(6)
+            torch.cuda.synchronize()
+            a, b = ge.download()[0], gg.download()[0]
+            for k in STATE_KEYS:
+                assert np.array_equal(a[k], b[k]), (rep, k)
+            assert float(ge.rnemd_dp.cpu()[0]) == float(gg.rnemd_dp.cpu()[0])
+            assert int(ge.d_step.cpu()[0]) == int(gg.d_step.cpu()[0]) == 6 * (rep + 1)
+        gg.release_graph()
+    assert ge.status() == 0 and gg.status() == 0
+
+
 def point_bodies(ncell, centres, seed):
     """Bodies of one unit-mass site each at the given centres (no solvent)."""
     rng = np.random.default_rng(seed)
