@@ -286,11 +286,17 @@ TileCfg tile_config(const mpcd_sys *s, const mpcd_tune &tu)
 
 struct Layout {
     size_t status, shift, counts, partial, cell_start, site_start, cellid, slot, perm, draws, site_d, vpre, rtmp,
-        grid_count, grid_body, wpos, woff, step_next, rn_hist, rn_bcnt, rn_ctl, rn_key, rn_id, rn_k, total;
+        grid_count, grid_body, wpos, woff, step_next, scan_ctl, scan_d0, scan_d1, rn_hist, rn_bcnt, rn_ctl, rn_key,
+        rn_id, rn_k, total;
     uint32_t grid_mask;
 };
 
+// Scan blocks of SCAN_T threads, each thread SCAN_V counters (4 up to
+// SCAN_BIG_C cells, else 16: fewer tiles, fewer tickets on one address);
+// SCAN_TILE, the smaller tile, sizes the per-tile arrays.
 constexpr int SCAN_T = 1024, SCAN_V = 4, SCAN_TILE = SCAN_T * SCAN_V;
+constexpr int64_t SCAN_BIG_C = 1 << 19;
+constexpr int scan_v(int64_t C) { return C > SCAN_BIG_C ? 16 : 4; }
 
 // Slots per bucket of the body-centre grid.
 constexpr int GRID_K = 8;
@@ -346,6 +352,10 @@ Layout layout_of(const mpcd_sys *s)
     // the next step's index, stored by the collision for a binning of the next
     // step that runs beside this step's body update
     L.step_next = take(sizeof(uint64_t));
+    // single-pass scan: tile ticket counter and two descriptor words per tile
+    L.scan_ctl = take(sizeof(uint64_t));
+    L.scan_d0 = take(sizeof(uint64_t) * (size_t)nbc);
+    L.scan_d1 = take(sizeof(uint64_t) * (size_t)nbc);
     // reverse nonequilibrium exchange: key histograms, control words and
     // candidate lists of the two slabs
     L.rn_hist = take(sizeof(int32_t) * 2 * RN_BINS);
@@ -476,9 +486,10 @@ inline unsigned xcd_grid(int64_t ntiles)
 //     body take one atomic per run of equal cells within a wave (run_slots).
 //     A cell's counter is 64 bits: solvent particles take slots from the low
 //     32 bits and sites from the high 32 bits, so one scan yields both.
-//  2. k_scan_reduce / k_scan_down: exclusive scan of the packed counters ->
+//  2. k_scan: single-pass exclusive scan of the packed counters ->
 //     cell_start (all members) and site_start (sites in earlier cells); each
-//     block adds the earlier tile totals itself and clears the counters.
+//     block takes the earlier tiles' prefix by look-back and clears the
+//     counters.
 //  3. k_bin_scatter: perm[cell_start[cell] + slot] = particle, solvent first
 //     within each cell, then its sites.  A solvent particle at permutation
 //     position p of cell c is therefore solvent number p - site_start[c] in
@@ -726,59 +737,154 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *total)
 
 using u64 = unsigned long long;
 
-__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const u64 *counts, int64_t C, u64 *partial)
+// Single-pass exclusive scan of the packed cell counters (decoupled
+// look-back, Merrill & Garland 2016) into cell_start (solvent + sites) and
+// site_start (sites), clearing the counters for the next step.  Packed sums
+// cannot carry from the low half into the high half: the solvent total is
+// below 2^31.  A block takes its tile from a ticket counter, so every tile it
+// waits for belongs to a block that started before it; each block publishes
+// its tile's aggregate at once and its inclusive prefix when known.  A tile's
+// descriptor is two 64-bit words, each a 32-bit flag (launch generation,
+// ticket / tiles + 1, above a two-bit state) beside one 32-bit half of the
+// value, written and read with relaxed device-scope atomics: a reader takes
+// them only when both flags match the current generation and each other, so
+// no fence (and no cache write-back or invalidation) is needed, flags of
+// earlier launches read as not ready, and nothing is cleared between launches.
+// Wave 0 looks back over 64 earlier tiles at a time.  The waits end because
+// the tiles waited for publish without waiting; a spin limit turns a stall
+// into ST_BINERR instead of a hang.
+struct ScanWs {
+    u64 *ctl, *d0, *d1;
+};
+constexpr uint32_t SCAN_AGG = 1, SCAN_INCL = 2;
+constexpr int SCAN_SPIN_LIMIT = 1 << 22;
+
+__device__ __forceinline__ u64 load_relaxed(const u64 *p)
 {
-    __shared__ u64 tot;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
-    u64 v = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_V; ++i)
-        if (base + i < C) v += counts[base + i];
-    (void)block_exclusive_scan<SCAN_T, u64>(v, &tot);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Each block adds the totals of the earlier tiles itself, scans its tile of
-// packed counters into cell_start (solvent + sites) and site_start (sites)
-// and clears the counters for the next step.  Packed sums cannot carry from
-// the low half into the high half: the solvent total is below 2^31.
-__global__ __launch_bounds__(SCAN_T) void k_scan_down(u64 *counts, int64_t C, const u64 *partial,
-                                                      int32_t *cell_start, int32_t *site_start, int32_t total,
-                                                      int32_t total_sites)
+__device__ __forceinline__ void store_relaxed(u64 *p, u64 v)
 {
-    __shared__ u64 tot;
-    __shared__ u64 pre;
-    u64 carry = 0;
-    for (int64_t b0 = 0; b0 < (int64_t)blockIdx.x; b0 += SCAN_T) {
-        const int64_t i = b0 + threadIdx.x;
-        (void)block_exclusive_scan<SCAN_T, u64>(i < (int64_t)blockIdx.x ? partial[i] : 0ull, &tot);
-        carry += tot;
-    }
-    if (threadIdx.x == 0) pre = carry;
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void scan_publish(const ScanWs &W, int64_t j, uint32_t fl, u64 val)
+{
+    store_relaxed(&W.d0[j], ((u64)fl << 32) | (val & 0xffffffffull));
+    store_relaxed(&W.d1[j], ((u64)fl << 32) | (val >> 32));
+}
+
+template <int V>
+__global__ __launch_bounds__(SCAN_T) void k_scan(u64 *counts, int64_t C, int64_t ntiles, ScanWs W,
+                                                 int32_t *cell_start, int32_t *site_start, int32_t total,
+                                                 int32_t total_sites, uint32_t *status)
+{
+    __shared__ u64 s_ticket, tot, pre;
+    if (threadIdx.x == 0) s_ticket = atomicAdd((unsigned long long *)W.ctl, 1ull);
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_V;
-    u64 c[SCAN_V];
+    const u64 ticket = s_ticket;
+    const int64_t j = (int64_t)(ticket % (u64)ntiles);
+    const uint32_t gen = (uint32_t)((ticket / (u64)ntiles + 1) & 0x3fffffffull);
+    static_assert(V % 4 == 0, "vector loads and stores of a scan thread's counters");
+    const int64_t base = j * (int64_t)(SCAN_T * V) + (int64_t)threadIdx.x * V;
+    const bool full = base + V <= C;  // whole vectors (the arrays are 256-byte aligned)
+    u64 c[V];
     u64 v = 0;
+    if (full) {
+        const ulonglong2 *src = (const ulonglong2 *)(counts + base);
 #pragma unroll
-    for (int i = 0; i < SCAN_V; ++i) {
-        c[i] = (base + i < C) ? counts[base + i] : 0ull;
-        v += c[i];
-    }
-    u64 run = pre + block_exclusive_scan<SCAN_T, u64>(v, &tot);
-#pragma unroll
-    for (int i = 0; i < SCAN_V; ++i) {
-        if (base + i < C) {
-            const uint32_t ns = (uint32_t)(run & 0xffffffffull), nq = (uint32_t)(run >> 32);
-            cell_start[base + i] = (int32_t)(ns + nq);
-            site_start[base + i] = (int32_t)nq;
-            counts[base + i] = 0;
+        for (int i = 0; i < V / 2; ++i) {
+            const ulonglong2 w = src[i];
+            c[2 * i] = w.x;
+            c[2 * i + 1] = w.y;
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) c[i] = (base + i < C) ? counts[base + i] : 0ull;
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) v += c[i];
+    u64 run = block_exclusive_scan<SCAN_T, u64>(v, &tot);
+    const u64 agg = tot;
+    uint32_t st = 0;
+    if (threadIdx.x == 0) {
+        scan_publish(W, j, (gen << 2) | (j == 0 ? SCAN_INCL : SCAN_AGG), agg);
+        if (j == 0) pre = 0;
+    }
+    if (j > 0 && threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        u64 excl = 0;
+        int64_t look = j - 1;
+        int spins = 0;
+        while (true) {
+            const int64_t q = look - lane;  // lane 0: the nearest earlier tile
+            uint32_t state = SCAN_INCL;     // before tile 0 there is nothing: an inclusive zero
+            u64 val = 0;
+            if (q >= 0) {
+                const u64 w0 = load_relaxed(&W.d0[q]), w1 = load_relaxed(&W.d1[q]);
+                const uint32_t f0 = (uint32_t)(w0 >> 32), f1 = (uint32_t)(w1 >> 32);
+                state = (f0 == f1 && (f0 >> 2) == gen) ? (f0 & 3u) : 0u;
+                val = (w0 & 0xffffffffull) | (w1 << 32);
+            }
+            const unsigned long long incl_mask = __ballot(state == SCAN_INCL);
+            const int first = incl_mask ? __ffsll((long long)incl_mask) - 1 : 63;
+            const unsigned long long upto = (first == 63) ? ~0ull : ((2ull << first) - 1ull);
+            if (__ballot(state == 0u) & upto) {  // a tile this window needs has not published
+                if (++spins > SCAN_SPIN_LIMIT) {
+                    st |= ST_BINERR;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            if (lane > first) val = 0;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) val += __shfl_down(val, d, 64);
+            excl += __shfl(val, 0, 64);
+            if (incl_mask) break;
+            look -= 64;
+        }
+        if (lane == 0) {
+            scan_publish(W, j, (gen << 2) | SCAN_INCL, excl + agg);
+            pre = excl;
+        }
+    }
+    __syncthreads();
+    run += pre;
+    int32_t cs[V], ss[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        const uint32_t ns = (uint32_t)(run & 0xffffffffull), nq = (uint32_t)(run >> 32);
+        cs[i] = (int32_t)(ns + nq);
+        ss[i] = (int32_t)nq;
         run += c[i];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (full) {
+        int4 *dc = (int4 *)(cell_start + base), *ds = (int4 *)(site_start + base);
+        ulonglong2 *dz = (ulonglong2 *)(counts + base);
+#pragma unroll
+        for (int i = 0; i < V / 4; ++i) {
+            dc[i] = make_int4(cs[4 * i], cs[4 * i + 1], cs[4 * i + 2], cs[4 * i + 3]);
+            ds[i] = make_int4(ss[4 * i], ss[4 * i + 1], ss[4 * i + 2], ss[4 * i + 3]);
+        }
+#pragma unroll
+        for (int i = 0; i < V / 2; ++i) dz[i] = make_ulonglong2(0ull, 0ull);
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            if (base + i < C) {
+                cell_start[base + i] = cs[i];
+                site_start[base + i] = ss[i];
+                counts[base + i] = 0;
+            }
+        }
+    }
+    if (j == 0 && threadIdx.x == 0) {
         cell_start[C] = total;
         site_start[C] = total_sites;
     }
+    flag(status, st);
 }
 
 // Position of particle k (cell gc, slot within its kind) in the permutation:
@@ -3169,6 +3275,13 @@ int mpcd_ws_init(void *stream, const mpcd_sys *sys, void *ws, size_t ws_bytes)
                        at<int32_t>(ws, L.counts), 2 * sys->n_cells, 0);
     if (NT > 0)  // the permutation holds valid particle indices from the start
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(NT, 256)), dim3(256), 0, st, at<int32_t>(ws, L.perm), NT, 0);
+    // the scan's ticket counter and tile descriptors (state 0: not published)
+    const int64_t ntiles = (sys->n_cells + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, at<int32_t>(ws, L.scan_ctl), (int64_t)2, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * ntiles, 256)), dim3(256), 0, st, at<int32_t>(ws, L.scan_d0),
+                       2 * ntiles, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * ntiles, 256)), dim3(256), 0, st, at<int32_t>(ws, L.scan_d1),
+                       2 * ntiles, 0);
     // the exchange's histograms and control words start at zero; each exchange
     // leaves them at zero for the next
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * RN_BINS, 256)), dim3(256), 0, st, at<int32_t>(ws, L.rn_hist),
@@ -3249,12 +3362,13 @@ static void launch_bin_count(const Ctx &c, hipStream_t st, const void *x, const 
 static void launch_scan(const Ctx &c, hipStream_t st)
 {
     const int64_t NT = c.sys->n_solvent + c.sys->n_sites, C = c.sys->n_cells;
-    const int64_t nb = (C + SCAN_TILE - 1) / SCAN_TILE;
-    u64 *counts = at<u64>(c.ws, c.L.counts), *partial = at<u64>(c.ws, c.L.partial);
+    const int V = scan_v(C);
+    const int64_t nb = (C + (int64_t)SCAN_T * V - 1) / ((int64_t)SCAN_T * V);
+    u64 *counts = at<u64>(c.ws, c.L.counts);
     int32_t *cs = at<int32_t>(c.ws, c.L.cell_start), *ss = at<int32_t>(c.ws, c.L.site_start);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, partial, cs, ss, (int32_t)NT,
-                       (int32_t)c.sys->n_sites);
+    const ScanWs W{at<u64>(c.ws, c.L.scan_ctl), at<u64>(c.ws, c.L.scan_d0), at<u64>(c.ws, c.L.scan_d1)};
+    hipLaunchKernelGGL(V == 16 ? k_scan<16> : k_scan<4>, dim3((unsigned)nb), dim3(SCAN_T), 0, st, counts, C, nb, W,
+                       cs, ss, (int32_t)NT, (int32_t)c.sys->n_sites, c.status);
 }
 
 static void launch_scatter(const Ctx &c, hipStream_t st)

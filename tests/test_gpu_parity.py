@@ -154,6 +154,29 @@ def test_in_place_form_bit_exact():
     run_parity(wl, par, meta["steps"], check_every=10, out_of_place=False)
 
 
+def test_binning_of_many_cells_matches_the_oracle():
+    """Above 2^19 cells the scan takes 16 counters per thread (fewer, larger
+    tiles); two binnings in a row (the second scan reads the first one's tile
+    descriptors as stale) still give the oracle's cell lists."""
+    wl = W.make_system((96, 96, 64), 2, [], [], np.zeros((0, 4)), np.random.default_rng(93))
+    par = W.srd_params(93, kT_cell=1.0)
+    o = oracle.OracleSystem(wl, par)
+    g = gpu_system(wl, par, prec="f64")
+    assert g.C > 2 ** 19
+    for step in (5, 6):
+        say("many-cell binning, step %d" % step)
+        g.set_step(step)
+        cell, cs, mem, _ = o.bin(o.shift(step))
+        g.bin()
+        gcs, gperm, _ = g.bins()
+        assert np.array_equal(gcs, cs)
+        owner = np.repeat(np.arange(o.C), np.diff(cs))
+        a = np.lexsort((gperm, owner))
+        b = np.lexsort((mem, owner))
+        assert np.array_equal(gperm[a], mem[b])
+    assert g.status() == 0
+
+
 def test_out_of_place_step_writes_solvent_in_cell_order():
     """After an out-of-place step the solvent storage holds the previous
     storage's particles in the order of the step's cell lists (solvent before
