@@ -37,8 +37,11 @@
  *    do not depend on the other systems.
  *  - Random numbers: Philox4x64-10, key (seed, purpose), counter
  *    (step, entity, replica0 + system, call); purpose 0 grid shift (entity 0),
- *    1 collision axis (entity = cell index within its system), 2 thermostat
- *    (entity = cell), 3 site velocities (entity = site index within its system).
+ *    1 a cell's collision axis and thermostat Gamma variate (entity = cell
+ *    index within its system: a call's words as eight 32-bit halves, high
+ *    half first; axis attempts on halves (0,1) and (2,3), a variate attempt
+ *    on (4,5,6); calls until both are accepted), 3 site velocities (entity =
+ *    site index within its system).
  *  - Limits: total solvent + sites < 2^31; total cells < 2^31.
  *
  * Errors: 0 on success, else a negative code below; nothing is launched then.

@@ -88,6 +88,8 @@ def lib():
         L.orc_gamma.argtypes = [u64, u64, u64, u64, C.c_double, dp]
         L.orc_gamma_n.restype = C.c_uint32
         L.orc_gamma_n.argtypes = [u64, u64, u64, C.c_double, i64, dp]
+        L.orc_cell_draws_n.restype = C.c_uint32
+        L.orc_cell_draws_n.argtypes = [u64, u64, u64, C.c_double, i64, dp, dp]
         L.orc_sites_thermalize.restype = C.c_uint32
         L.orc_sites_thermalize.argtypes = [sysp, parp, u64, dp]
         L.orc_bin.restype = C.c_uint32
@@ -167,6 +169,14 @@ def gammas(seed, step, replica, k, n):
     g = np.zeros(n)
     flags = lib().orc_gamma_n(seed, step, replica, k, n, _p(g))
     return g, flags
+
+
+def cell_draws(seed, step, replica, k, n):
+    """Axis and Gamma(k) variate of cells 0..n-1 from their one stream each."""
+    ax = np.zeros((n, 3))
+    g = np.zeros(n)
+    flags = lib().orc_cell_draws_n(seed, step, replica, k, n, _p(ax), _p(g))
+    return ax, g, flags
 
 
 # ---------------------------------------------------------------------------

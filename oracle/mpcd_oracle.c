@@ -44,8 +44,7 @@
 
 /* Philox purposes (second key word). */
 #define PURPOSE_SHIFT 0u
-#define PURPOSE_AXIS 1u
-#define PURPOSE_THERMO 2u
+#define PURPOSE_CELL 1u /* a cell's collision axis and thermostat variate */
 #define PURPOSE_SITE 3u
 
 #define MAX_RNG_CALLS 64
@@ -215,63 +214,106 @@ uint32_t orc_site_normals(uint64_t seed, uint64_t step, uint64_t site, uint64_t 
     return 0;
 }
 
-/* Uniform random unit vector (Marsaglia 1972): accept (x1,x2) in the unit    */
-/* disk, n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1 - 2t).                        */
-uint32_t orc_cell_axis(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
-                       double n[3])
+/* The 32-bit halves of a call's four words, high half of each word first.   */
+static void halves(const uint64_t w[4], uint32_t h[8])
 {
-    for (uint64_t call = 0; call < MAX_RNG_CALLS; ++call) {
-        uint64_t w[4];
-        draw(seed, PURPOSE_AXIS, step, cell, replica, call, w);
-        for (int pair = 0; pair < 2; ++pair) {
-            double x1 = 2.0 * u53(w[2 * pair]) - 1.0;
-            double x2 = 2.0 * u53(w[2 * pair + 1]) - 1.0;
-            double t = x1 * x1 + x2 * x2;
-            if (t > 0.0 && t < 1.0) {
-                double r = sqrt(1.0 - t);
-                n[0] = (2.0 * x1) * r;
-                n[1] = (2.0 * x2) * r;
-                n[2] = 1.0 - 2.0 * t;
-                return 0;
-            }
-        }
+    for (int i = 0; i < 4; ++i) {
+        h[2 * i] = (uint32_t)(w[i] >> 32);
+        h[2 * i + 1] = (uint32_t)(w[i] & 0xffffffffu);
     }
-    n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
-    return ORC_RNGLOOP;
 }
 
-/* Gamma(shape k >= 1, scale 1) by Marsaglia and Tsang (2000).  Iteration i   */
-/* uses call i: a polar normal from (u0,u1) (second normal dropped) and the   */
-/* uniform u2.                                                                */
-uint32_t orc_gamma(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
-                   double k, double *g)
+/* A half as a uniform in (-1, 1) and in (0, 1): (h + 1/2) 2^-31 - 1 and      */
+/* (h + 1/2) 2^-32, both exact in double.                                     */
+static double sym_u32(uint32_t h) { return ((double)h + 0.5) * 0x1p-31 - 1.0; }
+static double unit_u32(uint32_t h) { return ((double)h + 0.5) * 0x1p-32; }
+
+/* One attempt at a uniform random unit vector (Marsaglia 1972): accept       */
+/* (x1, x2) inside the unit disk, n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1-2t). */
+static int axis_attempt(uint32_t h1, uint32_t h2, double n[3])
 {
-    double d = k - 1.0 / 3.0;
-    double c = 1.0 / sqrt(9.0 * d);
-    for (uint64_t call = 0; call < MAX_RNG_CALLS; ++call) {
-        uint64_t w[4];
-        draw(seed, PURPOSE_THERMO, step, cell, replica, call, w);
-        double x1 = 2.0 * u53(w[0]) - 1.0;
-        double x2 = 2.0 * u53(w[1]) - 1.0;
-        double t = x1 * x1 + x2 * x2;
-        if (!(t > 0.0 && t < 1.0)) continue;
-        double z = x1 * sqrt((-2.0 * orc_dlog(t)) / t);
-        double v = 1.0 + c * z;
-        if (v <= 0.0) continue;
-        v = (v * v) * v;
-        double u = u53(w[2]);
-        double z2 = z * z;
-        if (u < 1.0 - 0.0331 * (z2 * z2)) {
-            *g = d * v;
-            return 0;
-        }
-        if (orc_dlog(u) < (0.5 * z) * z + d * ((1.0 - v) + orc_dlog(v))) {
-            *g = d * v;
-            return 0;
-        }
+    double x1 = sym_u32(h1), x2 = sym_u32(h2);
+    double t = x1 * x1 + x2 * x2;
+    if (!(t > 0.0 && t < 1.0)) return 0;
+    double r = sqrt(1.0 - t);
+    n[0] = (2.0 * x1) * r;
+    n[1] = (2.0 * x2) * r;
+    n[2] = 1.0 - 2.0 * t;
+    return 1;
+}
+
+/* One attempt at Gamma(shape k >= 1, scale 1) by Marsaglia and Tsang (2000), */
+/* d = k - 1/3, c = 1/sqrt(9 d): a polar normal from (h1, h2) (the second     */
+/* normal dropped) and the uniform from h3.                                   */
+static int gamma_attempt(uint32_t h1, uint32_t h2, uint32_t h3, double d, double c, double *g)
+{
+    double x1 = sym_u32(h1), x2 = sym_u32(h2);
+    double t = x1 * x1 + x2 * x2;
+    if (!(t > 0.0 && t < 1.0)) return 0;
+    double z = x1 * sqrt((-2.0 * orc_dlog(t)) / t);
+    double v = 1.0 + c * z;
+    if (v <= 0.0) return 0;
+    v = (v * v) * v;
+    double u = unit_u32(h3);
+    double z2 = z * z;
+    if (u < 1.0 - 0.0331 * (z2 * z2)) {
+        *g = d * v;
+        return 1;
     }
-    *g = d;
-    return ORC_RNGLOOP;
+    if (orc_dlog(u) < (0.5 * z) * z + d * ((1.0 - v) + orc_dlog(v))) {
+        *g = d * v;
+        return 1;
+    }
+    return 0;
+}
+
+/* A cell's random collision axis and, when want_gamma, its thermostat        */
+/* Gamma(k) variate, both from the cell's one stream (purpose PURPOSE_CELL).  */
+/* Call i's eight halves: while the axis is pending, an attempt on halves     */
+/* (0, 1) and then one on (2, 3); while the variate is pending, an attempt on */
+/* (4, 5, 6).  Calls 0, 1, ... continue until both are accepted, so the axis  */
+/* is the same whether or not the variate is wanted.                          */
+uint32_t orc_cell_draws(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica, int want_gamma, double k,
+                        double n[3], double *g)
+{
+    int have_axis = 0, have_gamma = !want_gamma;
+    double d = 0.0, c = 0.0;
+    if (want_gamma) {
+        d = k - 1.0 / 3.0;
+        c = 1.0 / sqrt(9.0 * d);
+    }
+    *g = 0.0;
+    for (uint64_t call = 0; call < MAX_RNG_CALLS && !(have_axis && have_gamma); ++call) {
+        uint64_t w[4];
+        uint32_t h[8];
+        draw(seed, PURPOSE_CELL, step, cell, replica, call, w);
+        halves(w, h);
+        if (!have_axis) have_axis = axis_attempt(h[0], h[1], n) || axis_attempt(h[2], h[3], n);
+        if (!have_gamma) have_gamma = gamma_attempt(h[4], h[5], h[6], d, c, g);
+    }
+    uint32_t flags = 0;
+    if (!have_axis) {
+        n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+        flags |= ORC_RNGLOOP;
+    }
+    if (!have_gamma) {
+        *g = d;
+        flags |= ORC_RNGLOOP;
+    }
+    return flags;
+}
+
+/* The axis alone, and the variate alone, of a cell's draws.                  */
+uint32_t orc_cell_axis(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica, double n[3])
+{
+    double g;
+    return orc_cell_draws(seed, step, cell, replica, 0, 0.0, n, &g);
+}
+
+uint32_t orc_gamma(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica, double k, double *g)
+{
+    double n[3];
+    return orc_cell_draws(seed, step, cell, replica, 1, k, n, g);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -546,9 +588,16 @@ uint32_t orc_collide(orc_sys *s, const orc_par *par, uint64_t step, const int64_
         double u[3];
         for (int d = 0; d < 3; ++d) u[d] = Pc[d] / Mc;
 
-        double n[3];
-        if (axis_in) { n[0] = axis_in[c]; n[1] = axis_in[C + c]; n[2] = axis_in[2 * C + c]; }
-        else flags |= orc_cell_axis(par->seed, step, (uint64_t)c, par->replica, n);
+        /* the cell's axis and, with the thermostat, its Gamma(3(nc-1)/2)      */
+        /* variate, from the cell's one stream                                 */
+        double n[3], g = 0.0;
+        double shape = 0.5 * (double)(3 * (nc - 1));
+        if (axis_in) {
+            n[0] = axis_in[c]; n[1] = axis_in[C + c]; n[2] = axis_in[2 * C + c];
+            if (par->kT_cell > 0.0) flags |= orc_gamma(par->seed, step, (uint64_t)c, par->replica, shape, &g);
+        } else {
+            flags |= orc_cell_draws(par->seed, step, (uint64_t)c, par->replica, par->kT_cell > 0.0, shape, n, &g);
+        }
 
         /* R = cos(a) I + sin(a) [n]x + (1 - cos(a)) n n^T (right-hand rule) */
         double omc = 1.0 - ca, R[3][3];
@@ -574,9 +623,6 @@ uint32_t orc_collide(orc_sys *s, const orc_par *par, uint64_t step, const int64_
             }
             double E = 0.5 * Es;
             if (E > 0.0) {
-                double g;
-                double shape = 0.5 * (double)(3 * (nc - 1));
-                flags |= orc_gamma(par->seed, step, (uint64_t)c, par->replica, shape, &g);
                 double Enew = par->kT_cell * g;
                 lam = sqrt(Enew / E);
             }
@@ -1237,5 +1283,12 @@ uint32_t orc_gamma_n(uint64_t seed, uint64_t step, uint64_t replica, double k, i
 {
     uint32_t flags = 0;
     for (int64_t c = 0; c < n; ++c) flags |= orc_gamma(seed, step, (uint64_t)c, replica, k, &g[c]);
+    return flags;
+}
+
+uint32_t orc_cell_draws_n(uint64_t seed, uint64_t step, uint64_t replica, double k, int64_t n, double *ax, double *g)
+{
+    uint32_t flags = 0;
+    for (int64_t c = 0; c < n; ++c) flags |= orc_cell_draws(seed, step, (uint64_t)c, replica, 1, k, &ax[3 * c], &g[c]);
     return flags;
 }

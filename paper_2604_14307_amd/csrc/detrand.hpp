@@ -3,18 +3,19 @@
 // Counter-based random numbers (Philox4x64-10, Salmon et al., SC'11), a
 // project-written natural log (atanh series) and sin/cos (Taylor series after a
 // two-part pi/2 reduction), and the samplers built on them: the random grid
-// shift, Marsaglia-polar normals, the Marsaglia (1972) random unit axis and the
-// Marsaglia-Tsang (2000) gamma variate.  With contraction disabled
-// (-ffp-contract=off) every + - * / sqrt below is one correctly rounded IEEE
-// operation in the order written, so a host implementation of the same
-// definitions draws bit-identical numbers.
+// shift, Marsaglia-polar normals, and a cell's Marsaglia (1972) random unit
+// axis with its Marsaglia-Tsang (2000) gamma variate drawn from one stream.
+// With contraction disabled (-ffp-contract=off) every + - * / sqrt below is
+// one correctly rounded IEEE operation in the order written, so a host
+// implementation of the same definitions draws bit-identical numbers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace mpcd {
 
-enum : uint64_t { RNG_SHIFT = 0, RNG_AXIS = 1, RNG_THERMO = 2, RNG_SITE = 3 };
+// purposes of the streams (2, an earlier thermostat stream, is unused)
+enum : uint64_t { RNG_SHIFT = 0, RNG_CELL = 1, RNG_SITE = 3 };
 constexpr int RNG_MAX_CALLS = 64;
 
 constexpr uint32_t ST_NONFINITE = 1u, ST_ESCAPE = 2u, ST_FIXOVF = 4u, ST_RNGLOOP = 8u, ST_BINERR = 16u,
@@ -170,51 +171,45 @@ __device__ inline uint32_t site_normals(uint64_t seed, uint64_t step, uint64_t s
     return 0;
 }
 
-// Uniform random unit vector: accept (x1,x2) inside the unit disk,
-// n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1-2t).  One call's words: pairs
-// (w0, w1) then (w2, w3).
-__device__ __forceinline__ bool axis_from_words(const Words &w, double n[3])
+// 32-bit half i (0..7) of a call's words, the high half of each word first.
+__device__ __forceinline__ uint32_t half32(const Words &w, int i)
 {
-#pragma unroll
-    for (int pair = 0; pair < 2; ++pair) {
-        const double x1 = 2.0 * unit53(w.w[2 * pair]) - 1.0;
-        const double x2 = 2.0 * unit53(w.w[2 * pair + 1]) - 1.0;
-        const double t = x1 * x1 + x2 * x2;
-        if (t > 0.0 && t < 1.0) {
-            const double r = sqrt(1.0 - t);
-            n[0] = (2.0 * x1) * r;
-            n[1] = (2.0 * x2) * r;
-            n[2] = 1.0 - 2.0 * t;
-            return true;
-        }
-    }
-    return false;
+    return (i & 1) ? (uint32_t)w.w[i >> 1] : (uint32_t)(w.w[i >> 1] >> 32);
 }
 
-__device__ inline uint32_t cell_axis(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
-                                     double n[3], int call0 = 0)
+// (h + 1/2) 2^-31 - 1: exact, symmetric, in (-1, 1), never 0.
+__device__ __forceinline__ double sym32(uint32_t h) { return ((double)h + 0.5) * 0x1p-31 - 1.0; }
+
+// (h + 1/2) 2^-32: exact, in (0, 1).
+__device__ __forceinline__ double unit32(uint32_t h) { return ((double)h + 0.5) * 0x1p-32; }
+
+// Uniform random unit vector (Marsaglia 1972): accept (x1,x2) inside the unit
+// disk, n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1-2t).
+__device__ __forceinline__ bool axis_try(uint32_t h1, uint32_t h2, double n[3])
 {
-    for (int call = call0; call < RNG_MAX_CALLS; ++call) {
-        const Words w = rng_draw(seed, RNG_AXIS, step, cell, replica, (uint64_t)call);
-        if (axis_from_words(w, n)) return 0;
-    }
-    n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
-    return ST_RNGLOOP;
+    const double x1 = sym32(h1), x2 = sym32(h2);
+    const double t = x1 * x1 + x2 * x2;
+    if (!(t > 0.0 && t < 1.0)) return false;
+    const double r = sqrt(1.0 - t);
+    n[0] = (2.0 * x1) * r;
+    n[1] = (2.0 * x2) * r;
+    n[2] = 1.0 - 2.0 * t;
+    return true;
 }
 
-// One Marsaglia-Tsang iteration (d = k - 1/3, c = 1/sqrt(9d)) on one call's
-// words: a polar normal from (w0, w1), the uniform w2.
-__device__ __forceinline__ bool gamma_from_words(const Words &w, double d, double c, double *g)
+// One Marsaglia-Tsang (2000) iteration for Gamma(k), d = k - 1/3,
+// c = 1/sqrt(9d): a polar normal from (h1, h2) (the second normal dropped),
+// the uniform from h3.
+__device__ __forceinline__ bool gamma_try(uint32_t h1, uint32_t h2, uint32_t h3, double d, double c, double *g)
 {
-    const double x1 = 2.0 * unit53(w.w[0]) - 1.0;
-    const double x2 = 2.0 * unit53(w.w[1]) - 1.0;
+    const double x1 = sym32(h1), x2 = sym32(h2);
     const double t = x1 * x1 + x2 * x2;
     if (!(t > 0.0 && t < 1.0)) return false;
     const double z = x1 * sqrt((-2.0 * det_log(t)) / t);
     double v = 1.0 + c * z;
     if (v <= 0.0) return false;
     v = (v * v) * v;
-    const double u = unit53(w.w[2]);
+    const double u = unit32(h3);
     const double z2 = z * z;
     if (u < 1.0 - 0.0331 * (z2 * z2) || det_log(u) < (0.5 * z) * z + d * ((1.0 - v) + det_log(v))) {
         *g = d * v;
@@ -223,18 +218,59 @@ __device__ __forceinline__ bool gamma_from_words(const Words &w, double d, doubl
     return false;
 }
 
-// Gamma(shape k >= 1) variate by Marsaglia-Tsang; iteration i uses call i.
-__device__ inline uint32_t gamma_variate(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
-                                         double k, double *g, int call0 = 0)
+// A cell's random axis and (want_gamma) thermostat Gamma variate from its one
+// stream: each call's eight halves serve an axis attempt on (0,1) and one on
+// (2,3) while the axis is pending, and a Gamma attempt on (4,5,6) while the
+// variate is pending; calls go on until both are accepted.  The axis does not
+// depend on whether the variate is wanted.  State per call, for a caller that
+// interleaves calls of several cells: see cell_draw_call.
+struct CellDraw {
+    double n[3], g, d, c;
+    bool have_axis, have_gamma;
+};
+
+__device__ __forceinline__ void cell_draw_begin(CellDraw &D, bool want_gamma, double k)
 {
-    const double d = k - 1.0 / 3.0;
-    const double c = 1.0 / sqrt(9.0 * d);
-    for (int call = call0; call < RNG_MAX_CALLS; ++call) {
-        const Words w = rng_draw(seed, RNG_THERMO, step, cell, replica, (uint64_t)call);
-        if (gamma_from_words(w, d, c, g)) return 0;
+    D.have_axis = false;
+    D.have_gamma = !want_gamma;
+    D.g = 0.0;
+    if (want_gamma) {
+        D.d = k - 1.0 / 3.0;
+        D.c = 1.0 / sqrt(9.0 * D.d);
     }
-    *g = d;
-    return ST_RNGLOOP;
+}
+
+// One call's attempts; true when both draws are done.
+__device__ __forceinline__ bool cell_draw_call(CellDraw &D, const Words &w)
+{
+    if (!D.have_axis)
+        D.have_axis = axis_try(half32(w, 0), half32(w, 1), D.n) || axis_try(half32(w, 2), half32(w, 3), D.n);
+    if (!D.have_gamma) D.have_gamma = gamma_try(half32(w, 4), half32(w, 5), half32(w, 6), D.d, D.c, &D.g);
+    return D.have_axis && D.have_gamma;
+}
+
+// Fallbacks after RNG_MAX_CALLS calls without acceptance (flagged).
+__device__ __forceinline__ uint32_t cell_draw_end(CellDraw &D)
+{
+    uint32_t st = 0;
+    if (!D.have_axis) {
+        D.n[0] = 0.0; D.n[1] = 0.0; D.n[2] = 1.0;
+        st |= ST_RNGLOOP;
+    }
+    if (!D.have_gamma) {
+        D.g = D.d;
+        st |= ST_RNGLOOP;
+    }
+    return st;
+}
+
+__device__ inline uint32_t cell_draw(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica, bool want_gamma,
+                                     double k, CellDraw &D)
+{
+    cell_draw_begin(D, want_gamma, k);
+    for (int call = 0; call < RNG_MAX_CALLS; ++call)
+        if (cell_draw_call(D, rng_draw(seed, RNG_CELL, step, cell, replica, (uint64_t)call))) return 0;
+    return cell_draw_end(D);
 }
 
 }  // namespace mpcd

@@ -509,13 +509,15 @@ __device__ __forceinline__ void shift_of(const SysDev &s, uint64_t seed, uint64_
 struct BlockShift {
     const double *arr;
     const double *lds;  // [2][3]
-    int ra, rb;
+    const int *sys;     // [2]: ra, rb in LDS, or nullptr (systems unknown)
     uint64_t seed, step;
+    __device__ int ra() const { return sys ? sys[0] : -1; }
+    __device__ int rb() const { return sys ? sys[1] : -1; }
     __device__ void get(const SysDev &s, int r, double sh[3]) const
     {
         if (arr) { sh[0] = arr[3 * r]; sh[1] = arr[3 * r + 1]; sh[2] = arr[3 * r + 2]; }
-        else if (r == ra) { sh[0] = lds[0]; sh[1] = lds[1]; sh[2] = lds[2]; }
-        else if (r == rb) { sh[0] = lds[3]; sh[1] = lds[4]; sh[2] = lds[5]; }
+        else if (r == sys[0]) { sh[0] = lds[0]; sh[1] = lds[1]; sh[2] = lds[2]; }
+        else if (r == sys[1]) { sh[0] = lds[3]; sh[1] = lds[4]; sh[2] = lds[5]; }
         else shift_of(s, seed, step, r, sh);
     }
 };
@@ -606,11 +608,10 @@ struct BinLds {
     int32_t cnt[BIN_HT];  // particles per key, then the key's base slot
 };
 
-template <typename Real, bool SITES>
+template <typename Real, bool SITES, typename PreBarrier>
 __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const int32_t *site_body,
                           const BlockShift &bs, unsigned long long *counts, int32_t *cellid, int32_t *slot,
-                          int64_t kbase,
-                          int64_t k1, BinLds &H, uint32_t &st)
+                          int64_t kbase, int64_t k1, BinLds &H, uint32_t &st, PreBarrier pre_barrier)
 {
     uint32_t *hkey = H.key;
     int32_t *hcnt = H.cnt;
@@ -618,6 +619,25 @@ __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const 
         hkey[i] = BIN_EMPTY;
         hcnt[i] = 0;
     }
+    // positions first: their loads are in flight while the block draws its
+    // grid shifts (pre_barrier) and until the barrier
+    Real p[PREP_ITEMS][3];
+#pragma unroll
+    for (int j = 0; j < PREP_ITEMS; ++j) {
+        const int64_t k = kbase + (int64_t)j * BIN_T + threadIdx.x;
+        p[j][0] = p[j][1] = p[j][2] = (Real)0;
+        if (k < k1) {
+            if (!SITES || k < s.N) {
+                p[j][0] = x[k]; p[j][1] = x[s.N + k]; p[j][2] = x[2 * s.N + k];
+            } else {
+                const int64_t q = k - s.N;
+                p[j][0] = xs[q]; p[j][1] = xs[s.S + q]; p[j][2] = xs[2 * s.S + q];
+            }
+        }
+    }
+    pre_barrier();
+    __syncthreads();  // hash table cleared; the block's shifts and systems in LDS
+    const int ra = bs.ra(), rb = bs.rb();
     int32_t gc[PREP_ITEMS];
 #pragma unroll
     for (int j = 0; j < PREP_ITEMS; ++j) {
@@ -625,23 +645,15 @@ __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const 
         gc[j] = -1;
         if (k < k1) {
             int r;
-            Real p0, p1, p2;
-            if (!SITES || k < s.N) {
-                // the chunk's first and last systems, when known, bound the search
-                r = bs.ra < 0 ? find_sys(s.solv_off, s.nsys, k)
-                              : (bs.ra == bs.rb ? bs.ra : find_sys_in(s.solv_off, bs.ra, bs.rb, k));
-                p0 = x[k]; p1 = x[s.N + k]; p2 = x[2 * s.N + k];
-            } else {
-                const int64_t q = k - s.N;
-                r = find_sys(s.body_off, s.nsys, (int64_t)site_body[q]);
-                p0 = xs[q]; p1 = xs[s.S + q]; p2 = xs[2 * s.S + q];
-            }
+            if (!SITES || k < s.N)  // the chunk's first and last systems, when known, bound the search
+                r = ra < 0 ? find_sys(s.solv_off, s.nsys, k) : (ra == rb ? ra : find_sys_in(s.solv_off, ra, rb, k));
+            else
+                r = find_sys(s.body_off, s.nsys, (int64_t)site_body[k - s.N]);
             double sh[3];
             bs.get(s, r, sh);
-            gc[j] = cell_of_pos<Real>(s, r, p0, p1, p2, sh, st);
+            gc[j] = cell_of_pos<Real>(s, r, p[j][0], p[j][1], p[j][2], sh, st);
         }
     }
-    __syncthreads();
     int hs[PREP_ITEMS], rank[PREP_ITEMS];
 #pragma unroll
     for (int j = 0; j < PREP_ITEMS; ++j) {
@@ -660,13 +672,27 @@ __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const 
         rank[j] = atomicAdd(&hcnt[h], 1);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < BIN_HT; i += BIN_T) {
-        const uint32_t key = hkey[i];
-        if (key == BIN_EMPTY) continue;
-        const int sh = (key & 0x80000000u) ? 32 : 0;
-        const unsigned long long old =
-            atomicAdd(&counts[key & 0x7fffffffu], (unsigned long long)hcnt[i] << sh);
-        hcnt[i] = (int)((old >> sh) & 0xffffffffull);
+    // one device atomic per distinct key; unrolled with the returned bases in
+    // registers, so a lane's atomics are all in flight before it waits
+    constexpr int HT_PER_T = BIN_HT / BIN_T;
+    static_assert(BIN_HT % BIN_T == 0, "hash slots per thread");
+    unsigned long long old[HT_PER_T];
+    uint32_t keys[HT_PER_T];
+#pragma unroll
+    for (int it = 0; it < HT_PER_T; ++it) {
+        const int i = threadIdx.x + it * BIN_T;
+        keys[it] = hkey[i];
+        old[it] = 0ull;
+        if (keys[it] != BIN_EMPTY) {
+            const int sh = (keys[it] & 0x80000000u) ? 32 : 0;
+            old[it] = atomicAdd(&counts[keys[it] & 0x7fffffffu], (unsigned long long)hcnt[i] << sh);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < HT_PER_T; ++it) {
+        if (keys[it] == BIN_EMPTY) continue;
+        const int sh = (keys[it] & 0x80000000u) ? 32 : 0;
+        hcnt[threadIdx.x + it * BIN_T] = (int)((old[it] >> sh) & 0xffffffffull);
     }
     __syncthreads();
 #pragma unroll
@@ -679,15 +705,6 @@ __device__ void bin_chunk(const SysDev &s, const Real *x, const Real *xs, const 
     }
 }
 
-// Systems of the first and last particle of [k0, k1) (k1 > k0).
-__device__ __forceinline__ void chunk_systems(const SysDev &s, const int32_t *site_body, int64_t k0, int64_t k1,
-                                              int &ra, int &rb)
-{
-    ra = k0 < s.N ? find_sys(s.solv_off, s.nsys, k0) : find_sys(s.body_off, s.nsys, (int64_t)site_body[k0 - s.N]);
-    const int64_t kl = k1 - 1;
-    rb = kl < s.N ? find_sys(s.solv_off, s.nsys, kl) : find_sys(s.body_off, s.nsys, (int64_t)site_body[kl - s.N]);
-}
-
 template <typename Real>
 __global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, const Real *xs,
                                                      const int32_t *site_body, const double *shift,
@@ -697,9 +714,9 @@ __global__ __launch_bounds__(BIN_T) void k_bin_count(SysDev s, const Real *x, co
     __shared__ BinLds H;
     uint32_t st = 0;
     BlockShift bs;
-    bs.arr = shift; bs.lds = nullptr; bs.ra = bs.rb = -1; bs.seed = 0; bs.step = 0;
+    bs.arr = shift; bs.lds = nullptr; bs.sys = nullptr; bs.seed = 0; bs.step = 0;
     bin_chunk<Real, true>(s, x, xs, site_body, bs, counts, cellid, slot, k0 + (int64_t)blockIdx.x * PREP_CHUNK, k1, H,
-                          st);
+                          st, [] {});
     flag(status, st);
 }
 
@@ -1041,36 +1058,26 @@ __device__ __forceinline__ uint32_t ident(const CollideArgs &A, int32_t k)
     return (k < A.s.N && A.tag) ? (uint32_t)A.tag[k] : (uint32_t)k;
 }
 
-// Per-cell draws for the standalone collision entry point.
-// mode 1: the axis of every cell (independent of the binning); 2: the gamma
-// variates (needs this step's cell counts); 3: both.  Extra axis draws for
-// cells with fewer than two members are harmless: each draw is a pure
-// function of (seed, step, cell).
 // Per-cell random draws: the collision axis and, with the thermostat, the
 // Gamma(3(n-1)/2) variate for the cell's member count n, stored as
 // draws[0..2][C] and draws[3][C] (cells with fewer than two members draw no
-// gamma variate).  Philox4x64 is a long chain of quarter-rate 64-bit
-// multiplies, so the draws run in their own blocks rather than inside the
-// collision.
+// gamma variate).  Both come from the cell's one stream (cell_draw).
 //
 // Lane g of nlanes takes cells g, g + nlanes, ...; each loop iteration makes
-// one Philox call for the lane's current draw (the axis, then, with mode & 2,
-// the thermostat gamma variate) and moves on as soon as it is accepted, so
-// the axis and gamma rejections of a wave share one loop.  Each cell uses
-// calls 0, 1, ... of its own streams in order, exactly as cell_axis and
-// gamma_variate do.  One cell per lane measured best: the Philox call is a
-// long dependent chain, and longer queues per lane leave too few waves to
-// hide it.
+// one Philox call for the lane's current cell and moves on as soon as both
+// draws are accepted, so the rejections of a wave share one loop.  Each cell
+// uses calls 0, 1, ... of its stream in order, exactly as cell_draw does.
+// One cell per lane measured best: the Philox call is a long dependent chain,
+// and longer queues per lane leave too few waves to hide it.
 struct DrawLane {
     int64_t cell;
     uint64_t cl, rep;
-    int phase;  // 0 axis, 1 gamma
     int call;
-    bool want_axis, want_gamma;
-    double gd, gc;  // Marsaglia-Tsang d and c
+    bool want_gamma;
+    CellDraw D;
 };
 
-__device__ __forceinline__ void draw_lane_start(const CollideArgs &A, int mode, DrawLane &L)
+__device__ __forceinline__ void draw_lane_start(const CollideArgs &A, DrawLane &L)
 {
     const SysDev &s = A.s;
     const int r = find_sys(s.cell_off, s.nsys, L.cell);
@@ -1078,80 +1085,44 @@ __device__ __forceinline__ void draw_lane_start(const CollideArgs &A, int mode, 
                                      (int32_t)(L.cell - s.cell_off[r]));
     L.rep = s.replica0 + (uint64_t)r;
     L.call = 0;
-    L.want_axis = (mode & 1) != 0;
-    const int n = (mode & 2) ? A.cell_start[L.cell + 1] - A.cell_start[L.cell] : 0;
-    L.want_gamma = (mode & 2) && A.kT_cell > 0.0 && n >= 2;
-    if (L.want_gamma) {
-        const double k = 0.5 * (double)(3 * (n - 1));
-        L.gd = k - 1.0 / 3.0;
-        L.gc = 1.0 / sqrt(9.0 * L.gd);
-    }
-    L.phase = L.want_axis ? 0 : 1;
+    const int n = A.cell_start[L.cell + 1] - A.cell_start[L.cell];
+    L.want_gamma = A.kT_cell > 0.0 && n >= 2;
+    cell_draw_begin(L.D, L.want_gamma, 0.5 * (double)(3 * (n - 1)));
 }
 
-__device__ void draw_cells(const CollideArgs &A, double *draws, int mode, int64_t g, int64_t nlanes, uint32_t &st)
+__device__ void draw_cells(const CollideArgs &A, double *draws, int64_t g, int64_t nlanes, uint32_t &st)
 {
-    const SysDev &s = A.s;
-    const int64_t C = s.C;
+    const int64_t C = A.s.C;
     const uint64_t step = *A.d_step;
     DrawLane L;
     L.cell = g;
-    if (L.cell < C) draw_lane_start(A, mode, L);
+    if (L.cell < C) draw_lane_start(A, L);
     while (L.cell < C) {
-        bool done = false;
-        if (L.phase == 0 || L.want_gamma) {
-            const Words w = rng_draw(A.seed, L.phase == 0 ? RNG_AXIS : RNG_THERMO, step, L.cl, L.rep,
-                                     (uint64_t)L.call);
-            L.call += 1;
-            if (L.phase == 0) {
-                double nax[3];
-                bool ok = axis_from_words(w, nax);
-                if (!ok && L.call == RNG_MAX_CALLS) {
-                    nax[0] = 0.0; nax[1] = 0.0; nax[2] = 1.0;
-                    st |= ST_RNGLOOP;
-                    ok = true;
-                }
-                if (ok) {
-                    draws[L.cell] = nax[0];
-                    draws[C + L.cell] = nax[1];
-                    draws[2 * C + L.cell] = nax[2];
-                    L.phase = 1;
-                    L.call = 0;
-                    done = !L.want_gamma;
-                }
-            } else {
-                double gv;
-                bool ok = gamma_from_words(w, L.gd, L.gc, &gv);
-                if (!ok && L.call == RNG_MAX_CALLS) {
-                    gv = L.gd;
-                    st |= ST_RNGLOOP;
-                    ok = true;
-                }
-                if (ok) {
-                    draws[3 * C + L.cell] = gv;
-                    done = true;
-                }
-            }
-        } else {
-            done = true;  // no draw wanted for this cell
+        bool done = cell_draw_call(L.D, rng_draw(A.seed, RNG_CELL, step, L.cl, L.rep, (uint64_t)L.call));
+        L.call += 1;
+        if (!done && L.call == RNG_MAX_CALLS) {
+            st |= cell_draw_end(L.D);
+            done = true;
         }
         if (done) {
+            draws[L.cell] = L.D.n[0];
+            draws[C + L.cell] = L.D.n[1];
+            draws[2 * C + L.cell] = L.D.n[2];
+            if (L.want_gamma) draws[3 * C + L.cell] = L.D.g;
             L.cell += nlanes;
-            if (L.cell < C) draw_lane_start(A, mode, L);
+            if (L.cell < C) draw_lane_start(A, L);
         }
     }
 }
 
-// Standalone per-cell draws.  mode 1: the axis of every cell (independent of
-// the binning); 2: the gamma variates (needs this step's cell counts); 3:
-// both.  Extra axis draws for cells with fewer than two members are harmless:
-// each draw is a pure function of (seed, step, cell).
+// Standalone per-cell draws (axis and gamma variate of every cell; the gamma
+// variates need this step's cell counts).
 constexpr int DRAW_CELLS_PER_LANE = 1;
 
-__global__ __launch_bounds__(BIN_T) void k_cell_draws(CollideArgs A, double *draws, int mode)
+__global__ __launch_bounds__(BIN_T) void k_cell_draws(CollideArgs A, double *draws)
 {
     uint32_t st = 0;
-    draw_cells(A, draws, mode, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, st);
+    draw_cells(A, draws, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, st);
     flag(A.status, st);
 }
 
@@ -1174,7 +1145,7 @@ __global__ __launch_bounds__(BIN_T) void k_scatter_draws(int64_t NT, const int32
             }
         }
     } else {
-        draw_cells(A, draws, 3, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)ndraw * blockDim.x, st);
+        draw_cells(A, draws, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)ndraw * blockDim.x, st);
     }
     flag(A.status, st);
 }
@@ -1215,25 +1186,13 @@ __device__ __forceinline__ void cell_axis_gamma(const CollideArgs &A, int64_t gc
     const int r = find_sys(s.cell_off, s.nsys, gc);
     const uint64_t cl = (uint64_t)brick_canonical(s.ncell[3 * r], s.ncell[3 * r + 1], s.ncell[3 * r + 2],
                                                   (int32_t)(gc - s.cell_off[r]));
-    const uint64_t rep = s.replica0 + (uint64_t)r, step = *A.d_step;
-    bool ok = false;
-    for (int call = 0; call < RNG_MAX_CALLS && !ok; ++call)
-        ok = axis_from_words(rng_draw(A.seed, RNG_AXIS, step, cl, rep, (uint64_t)call), nax);
-    if (!ok) {
-        nax[0] = 0.0; nax[1] = 0.0; nax[2] = 1.0;
-        st |= ST_RNGLOOP;
-    }
-    if (A.kT_cell > 0.0 && n >= 2) {
-        const double k = 0.5 * (double)(3 * (n - 1));
-        const double gd = k - 1.0 / 3.0, gcc = 1.0 / sqrt(9.0 * gd);
-        ok = false;
-        for (int call = 0; call < RNG_MAX_CALLS && !ok; ++call)
-            ok = gamma_from_words(rng_draw(A.seed, RNG_THERMO, step, cl, rep, (uint64_t)call), gd, gcc, &gvar);
-        if (!ok) {
-            gvar = gd;
-            st |= ST_RNGLOOP;
-        }
-    }
+    CellDraw D;
+    st |= cell_draw(A.seed, *A.d_step, cl, s.replica0 + (uint64_t)r, A.kT_cell > 0.0 && n >= 2,
+                    0.5 * (double)(3 * (n - 1)), D);
+    nax[0] = D.n[0];
+    nax[1] = D.n[1];
+    nax[2] = D.n[2];
+    if (A.kT_cell > 0.0 && n >= 2) gvar = D.g;
 }
 
 // ---- fallback: one lane per cell, members read from global memory ----------
@@ -1764,8 +1723,10 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
 // One kernel per items-per-thread choice, each with the draws read from the
 // draws pass or made inside (suffix _d).  The FP32 4-item form without draws
 // is held to 80 VGPRs (six waves per SIMD to hide the gather latency;
-// measured faster than five) and the 2-item form to 72 (seven waves); the
-// other forms keep the compiler's allocation (a cap spills).
+// measured faster than five), the 2-item form to 72 (seven waves) and the
+// 8-item form with draws to 128 (four waves; the compiler's own choice, 129,
+// drops it to three); the other forms keep the compiler's allocation (a tighter
+// cap spills).
 #define MPCD_COLLIDE_KERNEL(NAME, ATTR, REAL, ITEMS, INL)                                                      \
     __global__ __launch_bounds__(TILE_T) ATTR void NAME(CollideArgs A, TileCfg T, REAL *v, REAL *vs,           \
                                                         REAL *xstream, SolvOut<REAL> O)                       \
@@ -1777,7 +1738,7 @@ MPCD_COLLIDE_KERNEL(k_collide_tiled_f32, __attribute__((amdgpu_waves_per_eu(6)))
 MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i8, , float, 8, 0)
 MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i2_d, , float, 2, 1)
 MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_d, , float, 4, 1)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i8_d, , float, 8, 1)
+MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i8_d, __attribute__((amdgpu_waves_per_eu(4))), float, 8, 1)
 MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i1, , double, 1, 0)
 MPCD_COLLIDE_KERNEL(k_collide_tiled_f64, , double, 2, 0)
 MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i4, , double, 4, 0)
@@ -1990,18 +1951,20 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
     } else {
         const int64_t kbase = ((int64_t)blockIdx.x - (PART == 0 ? s.B : 0)) * PREP_CHUNK;
         const int64_t k1 = s.N;
-        if (threadIdx.x == 0) {
-            int ra, rb;
-            chunk_systems(s, nullptr, kbase, (kbase + PREP_CHUNK < k1) ? kbase + PREP_CHUNK : k1, ra, rb);
-            bsr[0] = ra;
-            bsr[1] = rb;
-            shift_of(s, seed, step, ra, bsh);
-            if (rb != ra) shift_of(s, seed, step, rb, bsh + 3);
-        }
-        __syncthreads();
+        const int64_t kl = ((kbase + PREP_CHUNK < k1) ? kbase + PREP_CHUNK : k1) - 1;
         BlockShift bs;
-        bs.arr = nullptr; bs.lds = bsh; bs.ra = bsr[0]; bs.rb = bsr[1]; bs.seed = seed; bs.step = step;
-        bin_chunk<Real, false>(s, x, nullptr, nullptr, bs, counts, cellid, slot, kbase, k1, lds.bin, st);
+        bs.arr = nullptr; bs.lds = bsh; bs.sys = bsr; bs.seed = seed; bs.step = step;
+        // after the block's position loads are issued: thread 0 the system and
+        // shift of the chunk's first particle, thread 64 (another wave, in
+        // parallel) those of its last
+        bin_chunk<Real, false>(s, x, nullptr, nullptr, bs, counts, cellid, slot, kbase, k1, lds.bin, st, [&] {
+            if (threadIdx.x == 0 || threadIdx.x == 64) {
+                const int e = threadIdx.x == 0 ? 0 : 1;
+                const int r = find_sys(s.solv_off, s.nsys, e ? kl : kbase);
+                bsr[e] = r;
+                shift_of(s, seed, step, r, bsh + 3 * e);
+            }
+        });
     }
     flag(status, st);
 }
@@ -3414,11 +3377,10 @@ static unsigned draw_blocks(int64_t C, const mpcd_tune &tu)
     return grid_for(lanes > 0 ? lanes : 1, BIN_T);
 }
 
-static void launch_draws(const Ctx &c, hipStream_t st, const CollideArgs &A, int mode)
+static void launch_draws(const Ctx &c, hipStream_t st, const CollideArgs &A)
 {
-    if (mode == 2 && !(A.kT_cell > 0.0)) return;
     hipLaunchKernelGGL(k_cell_draws, dim3(draw_blocks(c.sys->n_cells, c.tune)), dim3(BIN_T), 0, st, A,
-                       at<double>(c.ws, c.L.draws), mode);
+                       at<double>(c.ws, c.L.draws));
 }
 
 // x_stream: positions streamed in place, or (out of place) read and streamed
@@ -3679,7 +3641,7 @@ int mpcd_collide(void *stream, const mpcd_sys *sys, void *v, const int32_t *tag,
     const Ctx c = make_ctx(sys, ws);
     hipStream_t st = (hipStream_t)stream;
     const CollideArgs A = collide_args(c, tag, bodies, cos_a, sin_a, kT_cell, seed, d_step, dt, nullptr);
-    launch_draws(c, st, A, 3);
+    launch_draws(c, st, A);
     launch_collide(c, st, A, v, vs, x_stream);
     return launch_check();
 }
@@ -3692,7 +3654,7 @@ int mpcd_cell_draws(void *stream, const mpcd_sys *sys, double kT_cell, uint64_t 
     if (!d_step) return MPCD_EINVAL;
     const Ctx c = make_ctx(sys, ws);
     const CollideArgs A = collide_args(c, nullptr, nullptr, 1.0, 0.0, kT_cell, seed, d_step, 1.0, nullptr);
-    launch_draws(c, (hipStream_t)stream, A, 3);
+    launch_draws(c, (hipStream_t)stream, A);
     return launch_check();
 }
 

@@ -99,6 +99,25 @@ def test_cell_axes_uniform_on_sphere():
     assert np.allclose(ax.T @ ax / len(ax), np.eye(3) / 3, atol=0.01)
 
 
+def test_cell_axis_and_gamma_share_a_stream_independently():
+    """A cell's axis and thermostat variate come from the same calls (axis
+    halves 0-3, variate halves 4-6): the axis is the same whether or not the
+    variate is drawn, each is the one drawn alone, and the two are
+    uncorrelated across cells."""
+    n, k = 20000, 6.0
+    ax, g, flags = oracle.cell_draws(23, 9, 1, k, n)
+    assert flags == 0
+    ax0, _ = oracle.cell_axes(23, 9, 1, n)
+    g0, _ = oracle.gammas(23, 9, 1, k, n)
+    assert np.array_equal(ax, ax0) and np.array_equal(g, g0)
+    lim = 4.0 / math.sqrt(n)
+    for comp in (ax[:, 0], ax[:, 1], ax[:, 2], ax[:, 2] ** 2):
+        assert abs(stats.spearmanr(comp, g)[0]) < lim
+    # drawn from 32-bit halves, both still follow their target distributions
+    assert stats.kstest(g, "gamma", args=(k,)).pvalue > 1e-3
+    assert stats.kstest(ax[:, 2], "uniform", args=(-1.0, 2.0)).pvalue > 1e-3
+
+
 @pytest.mark.parametrize("k", [1.5, 6.0, 13.5, 30.0])
 def test_gamma_sampler(k):
     g, flags = oracle.gammas(17, 4, 0, k, 30000)
