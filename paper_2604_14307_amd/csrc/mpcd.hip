@@ -100,6 +100,24 @@ __device__ __forceinline__ int find_sys(const int64_t *off, int nsys, int64_t i)
     return lo;
 }
 
+// find_sys by a whole wave (all 64 lanes take part, each gets the result):
+// each round the lanes probe 64 evenly spaced offsets of the remaining range,
+// so 512 systems take two dependent loads instead of nine.
+__device__ __forceinline__ int find_sys_wave(const int64_t *off, int nsys, int64_t i)
+{
+    const int lane = threadIdx.x & 63;
+    int lo = 0, n = nsys;  // off[lo] <= i, and i < off[lo + n] when lo + n < nsys
+    while (n > 1) {
+        const int stride = (n + 63) >> 6;
+        const int idx = lane * stride;
+        const unsigned long long m = __ballot(idx < n && off[lo + idx] <= i);
+        const int last = m ? 63 - __clzll(m) : 0;
+        lo += last * stride;
+        n = min(stride, n - last * stride);
+    }
+    return lo;
+}
+
 __device__ __forceinline__ void flag(uint32_t *status, uint32_t bits)
 {
     if (bits) atomicOr(status, bits);
@@ -1077,10 +1095,10 @@ struct DrawLane {
     CellDraw D;
 };
 
-__device__ __forceinline__ void draw_lane_start(const CollideArgs &A, DrawLane &L)
+__device__ __forceinline__ void draw_lane_start(const CollideArgs &A, DrawLane &L, int r_lo, int r_hi)
 {
     const SysDev &s = A.s;
-    const int r = find_sys(s.cell_off, s.nsys, L.cell);
+    const int r = r_lo == r_hi ? r_lo : find_sys_in(s.cell_off, r_lo, r_hi, L.cell);
     L.cl = (uint64_t)brick_canonical(s.ncell[3 * r], s.ncell[3 * r + 1], s.ncell[3 * r + 2],
                                      (int32_t)(L.cell - s.cell_off[r]));
     L.rep = s.replica0 + (uint64_t)r;
@@ -1096,7 +1114,15 @@ __device__ void draw_cells(const CollideArgs &A, double *draws, int64_t g, int64
     const uint64_t step = *A.d_step;
     DrawLane L;
     L.cell = g;
-    if (L.cell < C) draw_lane_start(A, L);
+    // the wave's first cells are consecutive: two wave-wide searches bound
+    // their systems (every lane of the wave is here)
+    const int64_t w0 = g - (threadIdx.x & 63);
+    int r_lo = 0, r_hi = 0;
+    if (w0 < C) {
+        r_lo = find_sys_wave(A.s.cell_off, A.s.nsys, w0);
+        r_hi = find_sys_wave(A.s.cell_off, A.s.nsys, (w0 + 63 < C) ? w0 + 63 : C - 1);
+    }
+    if (L.cell < C) draw_lane_start(A, L, r_lo, r_hi);
     while (L.cell < C) {
         bool done = cell_draw_call(L.D, rng_draw(A.seed, RNG_CELL, step, L.cl, L.rep, (uint64_t)L.call));
         L.call += 1;
@@ -1110,7 +1136,7 @@ __device__ void draw_cells(const CollideArgs &A, double *draws, int64_t g, int64
             draws[2 * C + L.cell] = L.D.n[2];
             if (L.want_gamma) draws[3 * C + L.cell] = L.D.g;
             L.cell += nlanes;
-            if (L.cell < C) draw_lane_start(A, L);
+            if (L.cell < C) draw_lane_start(A, L, 0, A.s.nsys - 1);
         }
     }
 }
@@ -1173,7 +1199,7 @@ __device__ __forceinline__ double thermostat_factor(const CollideArgs &A, double
 // the values are the same either way; inside the collision the ALU work of
 // the draws overlaps the tile's gathers.
 template <int INL = -1>  // 0 or 1: known at compile time; -1: A.inline_draws
-__device__ __forceinline__ void cell_axis_gamma(const CollideArgs &A, int64_t gc, int n, double nax[3],
+__device__ __forceinline__ void cell_axis_gamma(const CollideArgs &A, int64_t gc, int r, int n, double nax[3],
                                                 double &gvar, uint32_t &st)
 {
     const SysDev &s = A.s;
@@ -1183,7 +1209,6 @@ __device__ __forceinline__ void cell_axis_gamma(const CollideArgs &A, int64_t gc
         if (A.kT_cell > 0.0) gvar = A.draws[3 * s.C + gc];
         return;
     }
-    const int r = find_sys(s.cell_off, s.nsys, gc);
     const uint64_t cl = (uint64_t)brick_canonical(s.ncell[3 * r], s.ncell[3 * r + 1], s.ncell[3 * r + 2],
                                                   (int32_t)(gc - s.cell_off[r]));
     CellDraw D;
@@ -1326,7 +1351,7 @@ __device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double
         });
         const double u[3] = {P0 / M, P1 / M, P2 / M};
         double nax[3], gvar;
-        cell_axis_gamma<INL>(A, gc, n, nax, gvar, st);
+        cell_axis_gamma<INL>(A, gc, find_sys(A.s.cell_off, A.s.nsys, gc), n, nax, gvar, st);
         const Rot R = rotation(nax, A.cos_a, A.sin_a);
         double lam = 1.0;
         if (A.kT_cell > 0.0) {
@@ -1382,7 +1407,7 @@ __device__ __forceinline__ void f32_cell_params(const CollideArgs &A, int64_t gc
     const double Md = (double)q[0];
     const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
     double nax[3], gvar;
-    cell_axis_gamma<INL>(A, gc, n, nax, gvar, st);
+    cell_axis_gamma<INL>(A, gc, find_sys(A.s.cell_off, A.s.nsys, gc), n, nax, gvar, st);
     const Rot R = rotation(nax, A.cos_a, A.sin_a);
     double lam = 1.0;
     if (A.kT_cell > 0.0) {
@@ -1532,6 +1557,10 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
             }
         }
     }
+    // systems of the tile's first and last cells, found by each wave for
+    // itself (every lane is here); a cell's own search is bounded by them
+    const int tr0 = find_sys_wave(s.cell_off, s.nsys, c0);
+    const int tr1 = find_sys_wave(s.cell_off, s.nsys, c0 + nc - 1);
     // phase 0: the tile's cell ranges and slot -> cell map; this lane's cell
     // system and draws; FP32: clear the cell's fixed-point accumulators
     unsigned long long *s_acc = (unsigned long long *)(smem + Lo.keyacc);
@@ -1539,14 +1568,15 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     double nax[3] = {0.0, 0.0, 1.0}, gvar = 0.0;
     if (t < nc) {
         const int64_t gc = c0 + t;
+        const int r = tr0 == tr1 ? tr0 : find_sys_in(s.cell_off, tr0, tr1, gc);
         const int cb0 = A.cell_start[gc] - m0, ce0 = A.cell_start[gc + 1] - m0;
         for (int i = cb0; i < ce0; ++i) s_cl[i] = (uint16_t)t;
-        cell_axis_gamma<INL>(A, gc, ce0 - cb0, nax, gvar, st);
+        cell_axis_gamma<INL>(A, gc, r, ce0 - cb0, nax, gvar, st);
         if constexpr (!F64) {
 #pragma unroll
             for (int z = 0; z < 5; ++z) s_acc[5 * t + z] = 0ull;
         }
-        s_r[t] = find_sys(s.cell_off, s.nsys, gc);
+        s_r[t] = r;
         if (out) s_ss[t] = A.site_start[gc];
     }
     __syncthreads();
@@ -1802,7 +1832,7 @@ __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, d
     double *sh = lds.sh, *sacc = lds.sacc, *dvw = lds.dvw;
     const int t = threadIdx.x;
     const int64_t B = s.B, S = s.S;
-    const int r = find_sys(s.body_off, s.nsys, b);
+    const int r = find_sys_wave(s.body_off, s.nsys, b);  // called by whole blocks
     double q[4], A[3][3], R[3], Lbox[3];
 #pragma unroll
     for (int i = 0; i < 4; ++i) q[i] = bd.quat[i * B + b];
@@ -1943,8 +1973,8 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
     if (PART == 1 || (PART == 0 && (int64_t)blockIdx.x < s.B)) {
         if constexpr (PART != 2) {
             const int64_t b = blockIdx.x;
-            if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0))
-                shift_of(s, seed, step, find_sys(s.body_off, s.nsys, b), bsh);
+            const int rb = find_sys_wave(s.body_off, s.nsys, b);  // every lane of the block is here
+            if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0)) shift_of(s, seed, step, rb, bsh);
             thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid,
                                   slot, lds.th, st);
         }
@@ -1954,15 +1984,17 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
         const int64_t kl = ((kbase + PREP_CHUNK < k1) ? kbase + PREP_CHUNK : k1) - 1;
         BlockShift bs;
         bs.arr = nullptr; bs.lds = bsh; bs.sys = bsr; bs.seed = seed; bs.step = step;
-        // after the block's position loads are issued: thread 0 the system and
-        // shift of the chunk's first particle, thread 64 (another wave, in
-        // parallel) those of its last
+        // after the block's position loads are issued: wave 0 the system and
+        // shift of the chunk's first particle, wave 1 (in parallel) those of
+        // its last
         bin_chunk<Real, false>(s, x, nullptr, nullptr, bs, counts, cellid, slot, kbase, k1, lds.bin, st, [&] {
-            if (threadIdx.x == 0 || threadIdx.x == 64) {
-                const int e = threadIdx.x == 0 ? 0 : 1;
-                const int r = find_sys(s.solv_off, s.nsys, e ? kl : kbase);
-                bsr[e] = r;
-                shift_of(s, seed, step, r, bsh + 3 * e);
+            if (threadIdx.x < 128) {  // whole waves 0 and 1
+                const int e = threadIdx.x >> 6;
+                const int r = find_sys_wave(s.solv_off, s.nsys, e ? kl : kbase);
+                if ((threadIdx.x & 63) == 0) {
+                    bsr[e] = r;
+                    shift_of(s, seed, step, r, bsh + 3 * e);
+                }
             }
         });
     }
