@@ -228,33 +228,28 @@ static void halves(const uint64_t w[4], uint32_t h[8])
 static double sym_u32(uint32_t h) { return ((double)h + 0.5) * 0x1p-31 - 1.0; }
 static double unit_u32(uint32_t h) { return ((double)h + 0.5) * 0x1p-32; }
 
-/* One attempt at a uniform random unit vector (Marsaglia 1972): accept       */
-/* (x1, x2) inside the unit disk, n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1-2t). */
-static int axis_attempt(uint32_t h1, uint32_t h2, double n[3])
+#define TWO_PI 0x1.921fb54442d18p+2
+
+/* Uniform random unit vector without rejection (Archimedes' theorem: on the   */
+/* unit sphere z is uniform in (-1, 1) and the azimuth uniform in [0, 2 pi)).  */
+static void axis_from_halves(uint32_t hz, uint32_t hphi, double n[3])
 {
-    double x1 = sym_u32(h1), x2 = sym_u32(h2);
-    double t = x1 * x1 + x2 * x2;
-    if (!(t > 0.0 && t < 1.0)) return 0;
-    double r = sqrt(1.0 - t);
-    n[0] = (2.0 * x1) * r;
-    n[1] = (2.0 * x2) * r;
-    n[2] = 1.0 - 2.0 * t;
-    return 1;
+    double z = sym_u32(hz);
+    double r = sqrt(1.0 - z * z);
+    double sn, cs;
+    orc_dsincos(TWO_PI * unit_u32(hphi), &sn, &cs);
+    n[0] = r * cs;
+    n[1] = r * sn;
+    n[2] = z;
 }
 
-/* One attempt at Gamma(shape k >= 1, scale 1) by Marsaglia and Tsang (2000), */
-/* d = k - 1/3, c = 1/sqrt(9 d): a polar normal from (h1, h2) (the second     */
-/* normal dropped) and the uniform from h3.                                   */
-static int gamma_attempt(uint32_t h1, uint32_t h2, uint32_t h3, double d, double c, double *g)
+/* The Marsaglia-Tsang (2000) test for Gamma(shape k >= 1, scale 1) of the    */
+/* standard normal z with the uniform u; d = k - 1/3, c = 1/sqrt(9 d).         */
+static int mt_accept(double z, double u, double d, double c, double *g)
 {
-    double x1 = sym_u32(h1), x2 = sym_u32(h2);
-    double t = x1 * x1 + x2 * x2;
-    if (!(t > 0.0 && t < 1.0)) return 0;
-    double z = x1 * sqrt((-2.0 * orc_dlog(t)) / t);
     double v = 1.0 + c * z;
     if (v <= 0.0) return 0;
     v = (v * v) * v;
-    double u = unit_u32(h3);
     double z2 = z * z;
     if (u < 1.0 - 0.0331 * (z2 * z2)) {
         *g = d * v;
@@ -269,10 +264,12 @@ static int gamma_attempt(uint32_t h1, uint32_t h2, uint32_t h3, double d, double
 
 /* A cell's random collision axis and, when want_gamma, its thermostat        */
 /* Gamma(k) variate, both from the cell's one stream (purpose PURPOSE_CELL).  */
-/* Call i's eight halves: while the axis is pending, an attempt on halves     */
-/* (0, 1) and then one on (2, 3); while the variate is pending, an attempt on */
-/* (4, 5, 6).  Calls 0, 1, ... continue until both are accepted, so the axis  */
-/* is the same whether or not the variate is wanted.                          */
+/* Call 0's halves 0 and 1 give the axis.  While the variate is pending, call  */
+/* i's halves 2 and 3 give the Box-Muller (1958) pair                          */
+/* z1 = rho cos(2 pi u3), z2 = rho sin(2 pi u3), rho = sqrt(-2 ln u2), tested  */
+/* by Marsaglia-Tsang with the uniform of half 4 and then z2 with half 5;      */
+/* calls 0, 1, ... continue until one test accepts.  The axis is the same      */
+/* whether or not the variate is wanted.                                       */
 uint32_t orc_cell_draws(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica, int want_gamma, double k,
                         double n[3], double *g)
 {
@@ -288,14 +285,18 @@ uint32_t orc_cell_draws(uint64_t seed, uint64_t step, uint64_t cell, uint64_t re
         uint32_t h[8];
         draw(seed, PURPOSE_CELL, step, cell, replica, call, w);
         halves(w, h);
-        if (!have_axis) have_axis = axis_attempt(h[0], h[1], n) || axis_attempt(h[2], h[3], n);
-        if (!have_gamma) have_gamma = gamma_attempt(h[4], h[5], h[6], d, c, g);
+        if (!have_axis) {
+            axis_from_halves(h[0], h[1], n);
+            have_axis = 1;
+        }
+        if (!have_gamma) {
+            double rho = sqrt(-2.0 * orc_dlog(unit_u32(h[2])));
+            double sn, cs;
+            orc_dsincos(TWO_PI * unit_u32(h[3]), &sn, &cs);
+            have_gamma = mt_accept(rho * cs, unit_u32(h[4]), d, c, g) || mt_accept(rho * sn, unit_u32(h[5]), d, c, g);
+        }
     }
     uint32_t flags = 0;
-    if (!have_axis) {
-        n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
-        flags |= ORC_RNGLOOP;
-    }
     if (!have_gamma) {
         *g = d;
         flags |= ORC_RNGLOOP;

@@ -3,8 +3,9 @@
 // Counter-based random numbers (Philox4x64-10, Salmon et al., SC'11), a
 // project-written natural log (atanh series) and sin/cos (Taylor series after a
 // two-part pi/2 reduction), and the samplers built on them: the random grid
-// shift, Marsaglia-polar normals, and a cell's Marsaglia (1972) random unit
-// axis with its Marsaglia-Tsang (2000) gamma variate drawn from one stream.
+// shift, Marsaglia-polar normals for the site velocities, and a cell's random
+// unit axis (Archimedes) with its Marsaglia-Tsang (2000) gamma variate (on
+// Box-Muller normals) drawn from one stream.
 // With contraction disabled (-ffp-contract=off) every + - * / sqrt below is
 // one correctly rounded IEEE operation in the order written, so a host
 // implementation of the same definitions draws bit-identical numbers.
@@ -183,33 +184,29 @@ __device__ __forceinline__ double sym32(uint32_t h) { return ((double)h + 0.5) *
 // (h + 1/2) 2^-32: exact, in (0, 1).
 __device__ __forceinline__ double unit32(uint32_t h) { return ((double)h + 0.5) * 0x1p-32; }
 
-// Uniform random unit vector (Marsaglia 1972): accept (x1,x2) inside the unit
-// disk, n = (2 x1 sqrt(1-t), 2 x2 sqrt(1-t), 1-2t).
-__device__ __forceinline__ bool axis_try(uint32_t h1, uint32_t h2, double n[3])
+constexpr double TWO_PI = 0x1.921fb54442d18p+2;
+
+// Uniform random unit vector without rejection (Archimedes: on the unit sphere
+// z is uniform in (-1, 1) and the azimuth phi uniform in [0, 2 pi)):
+// n = (sqrt(1 - z^2) cos phi, sqrt(1 - z^2) sin phi, z).
+__device__ __forceinline__ void axis_from(uint32_t hz, uint32_t hphi, double n[3])
 {
-    const double x1 = sym32(h1), x2 = sym32(h2);
-    const double t = x1 * x1 + x2 * x2;
-    if (!(t > 0.0 && t < 1.0)) return false;
-    const double r = sqrt(1.0 - t);
-    n[0] = (2.0 * x1) * r;
-    n[1] = (2.0 * x2) * r;
-    n[2] = 1.0 - 2.0 * t;
-    return true;
+    const double z = sym32(hz);
+    const double r = sqrt(1.0 - z * z);
+    double sn, cs;
+    det_sincos(TWO_PI * unit32(hphi), &sn, &cs);
+    n[0] = r * cs;
+    n[1] = r * sn;
+    n[2] = z;
 }
 
-// One Marsaglia-Tsang (2000) iteration for Gamma(k), d = k - 1/3,
-// c = 1/sqrt(9d): a polar normal from (h1, h2) (the second normal dropped),
-// the uniform from h3.
-__device__ __forceinline__ bool gamma_try(uint32_t h1, uint32_t h2, uint32_t h3, double d, double c, double *g)
+// One Marsaglia-Tsang (2000) test for Gamma(k), d = k - 1/3, c = 1/sqrt(9d),
+// of the standard normal z with the uniform u.
+__device__ __forceinline__ bool mt_try(double z, double u, double d, double c, double *g)
 {
-    const double x1 = sym32(h1), x2 = sym32(h2);
-    const double t = x1 * x1 + x2 * x2;
-    if (!(t > 0.0 && t < 1.0)) return false;
-    const double z = x1 * sqrt((-2.0 * det_log(t)) / t);
     double v = 1.0 + c * z;
     if (v <= 0.0) return false;
     v = (v * v) * v;
-    const double u = unit32(h3);
     const double z2 = z * z;
     if (u < 1.0 - 0.0331 * (z2 * z2) || det_log(u) < (0.5 * z) * z + d * ((1.0 - v) + det_log(v))) {
         *g = d * v;
@@ -218,11 +215,24 @@ __device__ __forceinline__ bool gamma_try(uint32_t h1, uint32_t h2, uint32_t h3,
     return false;
 }
 
+// Two Marsaglia-Tsang tests on one call's halves: the Box-Muller (1958) pair
+// z1 = rho cos(2 pi u2), z2 = rho sin(2 pi u2), rho = sqrt(-2 ln u1), from
+// (h1, h2), tested with the uniforms from h3 and then h4.
+__device__ __forceinline__ bool gamma_try2(uint32_t h1, uint32_t h2, uint32_t h3, uint32_t h4, double d, double c,
+                                           double *g)
+{
+    const double rho = sqrt(-2.0 * det_log(unit32(h1)));
+    double sn, cs;
+    det_sincos(TWO_PI * unit32(h2), &sn, &cs);
+    return mt_try(rho * cs, unit32(h3), d, c, g) || mt_try(rho * sn, unit32(h4), d, c, g);
+}
+
 // A cell's random axis and (want_gamma) thermostat Gamma variate from its one
-// stream: each call's eight halves serve an axis attempt on (0,1) and one on
-// (2,3) while the axis is pending, and a Gamma attempt on (4,5,6) while the
-// variate is pending; calls go on until both are accepted.  The axis does not
-// depend on whether the variate is wanted.  State per call, for a caller that
+// stream.  Call 0's halves 0 and 1 give the axis (no rejection); while the
+// variate is pending, each call's halves 2-5 give two Marsaglia-Tsang tests;
+// calls go on until the variate is accepted.  The axis does not depend on
+// whether the variate is wanted.  Neither draw rejects often, so the lanes of
+// a wave rarely need a second call.  State per call, for a caller that
 // interleaves calls of several cells: see cell_draw_call.
 struct CellDraw {
     double n[3], g, d, c;
@@ -240,16 +250,19 @@ __device__ __forceinline__ void cell_draw_begin(CellDraw &D, bool want_gamma, do
     }
 }
 
-// One call's attempts; true when both draws are done.
+// One call's draws; true when both are done.
 __device__ __forceinline__ bool cell_draw_call(CellDraw &D, const Words &w)
 {
-    if (!D.have_axis)
-        D.have_axis = axis_try(half32(w, 0), half32(w, 1), D.n) || axis_try(half32(w, 2), half32(w, 3), D.n);
-    if (!D.have_gamma) D.have_gamma = gamma_try(half32(w, 4), half32(w, 5), half32(w, 6), D.d, D.c, &D.g);
+    if (!D.have_axis) {
+        axis_from(half32(w, 0), half32(w, 1), D.n);
+        D.have_axis = true;
+    }
+    if (!D.have_gamma)
+        D.have_gamma = gamma_try2(half32(w, 2), half32(w, 3), half32(w, 4), half32(w, 5), D.d, D.c, &D.g);
     return D.have_axis && D.have_gamma;
 }
 
-// Fallbacks after RNG_MAX_CALLS calls without acceptance (flagged).
+// Fallback after RNG_MAX_CALLS calls without acceptance (flagged).
 __device__ __forceinline__ uint32_t cell_draw_end(CellDraw &D)
 {
     uint32_t st = 0;
