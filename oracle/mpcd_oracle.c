@@ -84,7 +84,6 @@ static void draw(uint64_t seed, uint64_t purpose, uint64_t step, uint64_t entity
 }
 
 /* Uniform in [0,1) from the top 53 bits of a word. */
-static double u53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
 
 /* ------------------------------------------------------------------------- */
 /* Natural logarithm from the atanh series:                                   */
@@ -187,30 +186,28 @@ void orc_shift(uint64_t seed, uint64_t step, uint64_t replica, double a, double 
     }
 }
 
-/* Three standard normals for a site by the Marsaglia polar method; pairs     */
-/* (u0,u1) then (u2,u3) of successive calls; the spare normal is dropped.     */
+#define TWO_PI 0x1.921fb54442d18p+2
+
+/* (w >> 12 + 1/2) 2^-52: a uniform in (0, 1), exact in double.                */
+static double u52(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
+
+/* Three standard normals for a site by Box-Muller (1958): the pairs           */
+/* rho (cos 2 pi u1, sin 2 pi u1), rho = sqrt(-2 ln u0), from words (w0, w1)   */
+/* and (w2, w3) of call 0; the sine of the second pair is dropped.  Never      */
+/* rejects.                                                                    */
 uint32_t orc_site_normals(uint64_t seed, uint64_t step, uint64_t site, uint64_t replica,
                           double z[3])
 {
-    int have = 0;
-    for (uint64_t call = 0; call < MAX_RNG_CALLS && have < 3; ++call) {
-        uint64_t w[4];
-        draw(seed, PURPOSE_SITE, step, site, replica, call, w);
-        for (int pair = 0; pair < 2 && have < 3; ++pair) {
-            double x1 = 2.0 * u53(w[2 * pair]) - 1.0;
-            double x2 = 2.0 * u53(w[2 * pair + 1]) - 1.0;
-            double t = x1 * x1 + x2 * x2;
-            if (t > 0.0 && t < 1.0) {
-                double f = sqrt((-2.0 * orc_dlog(t)) / t);
-                z[have++] = x1 * f;
-                if (have < 3) z[have++] = x2 * f;
-            }
-        }
-    }
-    if (have < 3) {
-        while (have < 3) z[have++] = 0.0;
-        return ORC_RNGLOOP;
-    }
+    uint64_t w[4];
+    draw(seed, PURPOSE_SITE, step, site, replica, 0, w);
+    double sn, cs;
+    double rho1 = sqrt(-2.0 * orc_dlog(u52(w[0])));
+    orc_dsincos(TWO_PI * u52(w[1]), &sn, &cs);
+    z[0] = rho1 * cs;
+    z[1] = rho1 * sn;
+    double rho2 = sqrt(-2.0 * orc_dlog(u52(w[2])));
+    orc_dsincos(TWO_PI * u52(w[3]), &sn, &cs);
+    z[2] = rho2 * cs;
     return 0;
 }
 
@@ -227,8 +224,6 @@ static void halves(const uint64_t w[4], uint32_t h[8])
 /* (h + 1/2) 2^-32, both exact in double.                                     */
 static double sym_u32(uint32_t h) { return ((double)h + 0.5) * 0x1p-31 - 1.0; }
 static double unit_u32(uint32_t h) { return ((double)h + 0.5) * 0x1p-32; }
-
-#define TWO_PI 0x1.921fb54442d18p+2
 
 /* Uniform random unit vector without rejection (Archimedes' theorem: on the   */
 /* unit sphere z is uniform in (-1, 1) and the azimuth uniform in [0, 2 pi)).  */

@@ -3,7 +3,7 @@
 // Counter-based random numbers (Philox4x64-10, Salmon et al., SC'11), a
 // project-written natural log (atanh series) and sin/cos (Taylor series after a
 // two-part pi/2 reduction), and the samplers built on them: the random grid
-// shift, Marsaglia-polar normals for the site velocities, and a cell's random
+// shift, Box-Muller normals for the site velocities, and a cell's random
 // unit axis (Archimedes) with its Marsaglia-Tsang (2000) gamma variate (on
 // Box-Muller normals) drawn from one stream.
 // With contraction disabled (-ffp-contract=off) every + - * / sqrt below is
@@ -58,7 +58,6 @@ __device__ __forceinline__ Words rng_draw(uint64_t seed, uint64_t purpose, uint6
     return philox4x64(step, entity, replica, call, seed, purpose);
 }
 
-__device__ __forceinline__ double unit53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
 
 // ln x = e ln2 + 2 atanh(t), x = f 2^e with f in (sqrt(2)/2, sqrt(2)], t = (f-1)/(f+1).
 __device__ inline double det_log(double x)
@@ -140,35 +139,25 @@ __device__ __forceinline__ double shift_component(uint64_t w, double a)
     return (q * 0x1p-24) * a;
 }
 
-// Three standard normals (polar method; pairs (w0,w1) then (w2,w3) of
-// successive calls; the spare normal of the last pair is dropped).
-__device__ inline uint32_t site_normals(uint64_t seed, uint64_t step, uint64_t site, uint64_t replica,
-                                        double z[3])
+constexpr double TWO_PI = 0x1.921fb54442d18p+2;
+
+// (w >> 12 + 1/2) 2^-52: exact, in (0, 1).
+__device__ __forceinline__ double unit52(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
+
+// Three standard normals from one call without rejection: Box-Muller (1958)
+// pairs rho (cos, sin)(2 pi u) with rho = sqrt(-2 ln u'), from words
+// (w0, w1) and (w2, w3); the sine of the second pair is dropped.
+__device__ inline uint32_t site_normals(uint64_t seed, uint64_t step, uint64_t site, uint64_t replica, double z[3])
 {
-    int have = 0;
-    for (int call = 0; call < RNG_MAX_CALLS && have < 3; ++call) {
-        const Words w = rng_draw(seed, RNG_SITE, step, site, replica, (uint64_t)call);
-#pragma unroll
-        for (int pair = 0; pair < 2; ++pair) {
-            if (have >= 3) break;
-            const double x1 = 2.0 * unit53(w.w[2 * pair]) - 1.0;
-            const double x2 = 2.0 * unit53(w.w[2 * pair + 1]) - 1.0;
-            const double t = x1 * x1 + x2 * x2;
-            if (t > 0.0 && t < 1.0) {
-                const double f = sqrt((-2.0 * det_log(t)) / t);
-                z[have] = x1 * f;
-                have = have + 1;
-                if (have < 3) {
-                    z[have] = x2 * f;
-                    have = have + 1;
-                }
-            }
-        }
-    }
-    if (have < 3) {
-        for (int i = have; i < 3; ++i) z[i] = 0.0;
-        return ST_RNGLOOP;
-    }
+    const Words w = rng_draw(seed, RNG_SITE, step, site, replica, 0);
+    double sn, cs;
+    const double rho1 = sqrt(-2.0 * det_log(unit52(w.w[0])));
+    det_sincos(TWO_PI * unit52(w.w[1]), &sn, &cs);
+    z[0] = rho1 * cs;
+    z[1] = rho1 * sn;
+    const double rho2 = sqrt(-2.0 * det_log(unit52(w.w[2])));
+    det_sincos(TWO_PI * unit52(w.w[3]), &sn, &cs);
+    z[2] = rho2 * cs;
     return 0;
 }
 
@@ -183,8 +172,6 @@ __device__ __forceinline__ double sym32(uint32_t h) { return ((double)h + 0.5) *
 
 // (h + 1/2) 2^-32: exact, in (0, 1).
 __device__ __forceinline__ double unit32(uint32_t h) { return ((double)h + 0.5) * 0x1p-32; }
-
-constexpr double TWO_PI = 0x1.921fb54442d18p+2;
 
 // Uniform random unit vector without rejection (Archimedes: on the unit sphere
 // z is uniform in (-1, 1) and the azimuth phi uniform in [0, 2 pi)):
