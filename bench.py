@@ -35,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2604_14307_amd", "csrc", "mpcd.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_14307_amd", "csrc", f) for f in ("mpcd.hip", "detrand.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_f32_suspension60_traffic.txt")
 
 
@@ -51,8 +51,13 @@ def collide_bytes(N, S, prec_bytes):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """First 16 hex digits of the SHA-256 of the kernel sources (the HIP file
+    and the header of device primitives it includes), concatenated."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel):
