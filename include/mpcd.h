@@ -134,9 +134,11 @@ typedef struct {
  * default 1) is the number of cells each lane of the per-cell draws takes.
  * draws_inline (0 or 1): 1 makes the collision draw each cell's random axis
  * and gamma variate itself, in place of a separate draws pass (the same
- * values).  overlap (0 or 1): 1 lets mpcd_graph_create bin the solvent of
- * each next step on a second stream beside the current step's body update
- * (out-of-place steps with sites and no reorder; elsewhere ignored).
+ * values).  overlap (0, 1 or 2), for mpcd_graph_create (out-of-place steps
+ * with sites and no reorder; elsewhere ignored): 1 bins the solvent of each
+ * next step on a second stream beside the current step's body update; 2 runs
+ * each next step's first kernel inside the current step's force kernel
+ * (centre-centre WCA only).
  * Out-of-range values: MPCD_EINVAL. */
 typedef struct {
     int32_t tile_items;
@@ -392,6 +394,19 @@ int mpcd_advance_step(void *stream, uint64_t *d_step);
 
 /* One whole step (the sequence above), then mpcd_advance_step. */
 int mpcd_step(void *stream, const mpcd_step_args *args);
+
+/* The last kernel of step t fused with the first kernel of step t+1, as the
+ * fused graph schedule (tune.overlap = 2) runs it, for callers that schedule
+ * steps themselves: the body forces of Eq. (1) and the second half kick
+ * (Sec. II.B.2) with the step-counter advance, then each body's sites
+ * thermalized (Eq. 7) and binned, and the solvent x of args (the positions
+ * step t wrote: after an out-of-place step, the caller's current arrays)
+ * binned, for step t+1.  step_next: device uint64 holding t+1
+ * (read on the device; *d_step still holds t).  Step t+1 then continues from
+ * its scan, and its scatter must clear the body-centre grid (the fused graph
+ * schedule does both).  Needs bodies with sites and centre-centre or no WCA:
+ * otherwise MPCD_ENOTSUP. */
+int mpcd_forces_prep(void *stream, const mpcd_step_args *args, const uint64_t *step_next);
 
 /* Capture nsteps calls of mpcd_step into a HIP graph (stream must not be the
  * null stream); replay with mpcd_graph_launch; free with mpcd_graph_destroy. */

@@ -280,7 +280,7 @@ static bool tune_ok(const mpcd_tune &tu, bool f64)
     const bool items_ok = it == 0 || (f64 ? (it == 1 || it == 2 || it == 4) : (it == 2 || it == 4 || it == 8));
     return items_ok && (tu.tile_fill == 0 || (tu.tile_fill >= 10 && tu.tile_fill <= 100)) &&
            tu.draw_cells >= 0 && tu.draw_cells <= 16 && (tu.draws_inline == 0 || tu.draws_inline == 1) &&
-           (tu.overlap == 0 || tu.overlap == 1);
+           (tu.overlap >= 0 && tu.overlap <= 2);
 }
 
 TileCfg tile_config(const mpcd_sys *s, const mpcd_tune &tu)
@@ -933,11 +933,17 @@ __device__ __forceinline__ int64_t perm_pos(const int32_t *cell_start, const int
     return (int64_t)b + nsol + slot;
 }
 
+// grid_count (when set): the body-centre grid, cleared here for the step's
+// insertions when the step's first kernel did not run (fused schedule).
 __global__ __launch_bounds__(BIN_T) void k_bin_scatter(int64_t NT, int64_t N, const int32_t *cellid,
                                                        const int32_t *slot, const int32_t *cell_start,
-                                                       const int32_t *site_start, int32_t *perm, uint32_t *status)
+                                                       const int32_t *site_start, int32_t *perm, int32_t *grid_count,
+                                                       int64_t grid_n, uint32_t *status)
 {
     uint32_t st = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; grid_count && q < grid_n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        grid_count[q] = 0;
 #pragma unroll
     for (int j = 0; j < BIN_ITEMS; ++j) {
         const int64_t k = (int64_t)blockIdx.x * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
@@ -1156,9 +1162,13 @@ __global__ __launch_bounds__(BIN_T) void k_cell_draws(CollideArgs A, double *dra
 // blocks): independent work, one launch.  The draw blocks come first so their
 // ALU work starts early and overlaps the scatter's memory traffic.
 __global__ __launch_bounds__(BIN_T) void k_scatter_draws(int64_t NT, const int32_t *cellid, const int32_t *slot,
-                                                         int32_t *perm, int ndraw, CollideArgs A, double *draws)
+                                                         int32_t *perm, int ndraw, CollideArgs A, double *draws,
+                                                         int32_t *grid_count, int64_t grid_n)
 {
     uint32_t st = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; grid_count && q < grid_n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        grid_count[q] = 0;
     if ((int)blockIdx.x >= ndraw) {
         const int64_t b = (int64_t)blockIdx.x - ndraw;
 #pragma unroll
@@ -1942,6 +1952,46 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
     flag(status, st);
 }
 
+// Body role of the first kernel (a whole BODY_T block): body b's grid shift
+// into bsh, then its sites thermalized and binned for step `step`.
+template <typename Real>
+__device__ __forceinline__ void prep_body_block(const SysDev &s, const BodyDev &bd, int64_t b, double kT,
+                                                int thermalize, uint64_t seed, uint64_t step, Real *xs, Real *vs,
+                                                double *site_d, double *vpre, unsigned long long *counts,
+                                                int32_t *cellid, int32_t *slot, double *bsh, ThermLds &th,
+                                                uint32_t &st)
+{
+    const int rb = find_sys_wave(s.body_off, s.nsys, b);  // every lane of the block is here
+    if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0)) shift_of(s, seed, step, rb, bsh);
+    thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid, slot, th,
+                          st);
+}
+
+// Solvent role of the first kernel (a whole BODY_T block): bin the PREP_CHUNK
+// solvent particles from kbase for step `step`.  After the block's position
+// loads are issued, wave 0 finds the system and draws the shift of the
+// chunk's first particle and wave 1 (in parallel) those of its last.
+template <typename Real>
+__device__ __forceinline__ void prep_solvent_block(const SysDev &s, uint64_t seed, uint64_t step, const Real *x,
+                                                   unsigned long long *counts, int32_t *cellid, int32_t *slot,
+                                                   int64_t kbase, double *bsh, int *bsr, BinLds &bin, uint32_t &st)
+{
+    const int64_t k1 = s.N;
+    const int64_t kl = ((kbase + PREP_CHUNK < k1) ? kbase + PREP_CHUNK : k1) - 1;
+    BlockShift bs;
+    bs.arr = nullptr; bs.lds = bsh; bs.sys = bsr; bs.seed = seed; bs.step = step;
+    bin_chunk<Real, false>(s, x, nullptr, nullptr, bs, counts, cellid, slot, kbase, k1, bin, st, [&] {
+        if (threadIdx.x < 128) {  // whole waves 0 and 1
+            const int e = threadIdx.x >> 6;
+            const int r = find_sys_wave(s.solv_off, s.nsys, e ? kl : kbase);
+            if ((threadIdx.x & 63) == 0) {
+                bsr[e] = r;
+                shift_of(s, seed, step, r, bsh + 3 * e);
+            }
+        }
+    });
+}
+
 // First kernel of a step: blocks [0, B) thermalize one body each and bin its
 // sites; the remaining blocks bin PREP_CHUNK solvent particles each.  Every
 // block draws the grid shifts it needs; block 0 also stores them.  PART 0 is
@@ -1971,32 +2021,12 @@ __global__ __launch_bounds__(BODY_T) void k_prep(SysDev s, BodyDev bd, double kT
             grid_count[q] = 0;
     }
     if (PART == 1 || (PART == 0 && (int64_t)blockIdx.x < s.B)) {
-        if constexpr (PART != 2) {
-            const int64_t b = blockIdx.x;
-            const int rb = find_sys_wave(s.body_off, s.nsys, b);  // every lane of the block is here
-            if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0)) shift_of(s, seed, step, rb, bsh);
-            thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid,
-                                  slot, lds.th, st);
-        }
+        if constexpr (PART != 2)
+            prep_body_block<Real>(s, bd, blockIdx.x, kT, thermalize, seed, step, xs, vs, site_d, vpre, counts, cellid,
+                                  slot, bsh, lds.th, st);
     } else {
         const int64_t kbase = ((int64_t)blockIdx.x - (PART == 0 ? s.B : 0)) * PREP_CHUNK;
-        const int64_t k1 = s.N;
-        const int64_t kl = ((kbase + PREP_CHUNK < k1) ? kbase + PREP_CHUNK : k1) - 1;
-        BlockShift bs;
-        bs.arr = nullptr; bs.lds = bsh; bs.sys = bsr; bs.seed = seed; bs.step = step;
-        // after the block's position loads are issued: wave 0 the system and
-        // shift of the chunk's first particle, wave 1 (in parallel) those of
-        // its last
-        bin_chunk<Real, false>(s, x, nullptr, nullptr, bs, counts, cellid, slot, kbase, k1, lds.bin, st, [&] {
-            if (threadIdx.x < 128) {  // whole waves 0 and 1
-                const int e = threadIdx.x >> 6;
-                const int r = find_sys_wave(s.solv_off, s.nsys, e ? kl : kbase);
-                if ((threadIdx.x & 63) == 0) {
-                    bsr[e] = r;
-                    shift_of(s, seed, step, r, bsh + 3 * e);
-                }
-            }
-        });
+        prep_solvent_block<Real>(s, seed, step, x, counts, cellid, slot, kbase, bsh, bsr, lds.bin, st);
     }
     flag(status, st);
 }
@@ -2286,21 +2316,39 @@ __global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd,
 // then advances the step counter (last kernel of a step).
 constexpr int FRC_T = 64;
 
-__global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid, ExtForce E,
-                                                       double dt, int kick, uint64_t *advance_step, uint32_t *status)
+// LDS of the body forces for a block of NT threads.
+constexpr int FRC_NCAND = 27 * GRID_K;
+template <int NT> struct ForceLds {
+    double sf[3][NT + 1];
+    int shit[NT];
+    double fsh[3];
+    uint32_t s_h[27];
+    int s_n[27], s_pre[28];
+    int s_ovf, s_nhit;
+    int hj[FRC_NCAND];
+    double hc[3][FRC_NCAND];
+};
+
+// The forces (and kick) of body i = blockIdx.x < B by a block of NT threads.
+template <int NT>
+__device__ void body_forces_block(const SysDev &s, const BodyDev &bd, const mpcd_wca &wca, const BodyGrid &grid,
+                                  const ExtForce &E, double dt, int kick, uint64_t *advance_step, uint32_t *status,
+                                  ForceLds<NT> &Lf)
 {
-    constexpr int NCAND = 27 * GRID_K;
-    __shared__ double sf[3][FRC_T + 1];
-    __shared__ int shit[FRC_T];
-    __shared__ double fsh[3];
-    __shared__ uint32_t s_h[27];
-    __shared__ int s_n[27], s_pre[28];
-    __shared__ int s_ovf, s_nhit;
-    __shared__ int hj[NCAND];
-    __shared__ double hc[3][NCAND];
+    constexpr int NCAND = FRC_NCAND;
+    auto &sf = Lf.sf;
+    auto &shit = Lf.shit;
+    auto &fsh = Lf.fsh;
+    auto &s_h = Lf.s_h;
+    auto &s_n = Lf.s_n;
+    auto &s_pre = Lf.s_pre;
+    int &s_ovf = Lf.s_ovf;
+    int &s_nhit = Lf.s_nhit;
+    auto &hj = Lf.hj;
+    auto &hc = Lf.hc;
+    (void)NCAND;
     const int64_t i = blockIdx.x;
     if (advance_step && i == 0 && threadIdx.x == 0) *advance_step = *advance_step + 1;
-    if (i >= s.B) return;
     const int t = threadIdx.x;
     const int64_t B = s.B;
     uint32_t st = 0;
@@ -2360,7 +2408,7 @@ __global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpc
         }
         if (use_grid) {
             const int total = s_pre[27];
-            for (int idx = t; idx < total; idx += FRC_T) {
+            for (int idx = t; idx < total; idx += NT) {
                 int u = 0;
                 while (u < 26 && s_pre[u + 1] <= idx) ++u;
                 const int64_t j = grid.body[(size_t)s_h[u] * GRID_K + (idx - s_pre[u])];
@@ -2419,7 +2467,7 @@ __global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpc
             __syncthreads();
             if (t < 3) f = sf[t][0];
         }
-        for (int64_t j0 = jb; !use_grid && j0 < je; j0 += FRC_T) {
+        for (int64_t j0 = jb; !use_grid && j0 < je; j0 += NT) {
             const int64_t j = j0 + t;
             int hit = 0;
             double c[3] = {0.0, 0.0, 0.0};
@@ -2456,7 +2504,7 @@ __global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpc
             shit[t] = hit;
             __syncthreads();
             if (t < 3) {
-                const int cnt = (int)((je - j0) < FRC_T ? (je - j0) : FRC_T);
+                const int cnt = (int)((je - j0) < NT ? (je - j0) : NT);
                 for (int q = 0; q < cnt; ++q)
                     if (shit[q]) f = f + sf[t][q];
             }
@@ -2488,6 +2536,55 @@ __global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpc
         qmul_pure(q, h3, dq);
 #pragma unroll
         for (int k = 0; k < 4; ++k) bd.angmom[k * B + i] = bd.angmom[k * B + i] + dt * dq[k];
+    }
+    flag(status, st);
+}
+
+__global__ __launch_bounds__(FRC_T) void k_body_forces(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid, ExtForce E,
+                                                       double dt, int kick, uint64_t *advance_step, uint32_t *status)
+{
+    __shared__ ForceLds<FRC_T> Lf;
+    if ((int64_t)blockIdx.x >= s.B) {
+        if (advance_step && blockIdx.x == 0 && threadIdx.x == 0) *advance_step = *advance_step + 1;
+        return;
+    }
+    body_forces_block<FRC_T>(s, bd, wca, grid, E, dt, kick, advance_step, status, Lf);
+}
+
+// Last kernel of step t fused with the first kernel of step t+1 (a schedule
+// of captured steps): blocks [0, B) compute body b's centre forces and second
+// half kick (block 0 also advances the step counter), then thermalize body
+// b's sites for step t+1 and bin them; the other blocks bin PREP_CHUNK
+// particles each of the solvent step t wrote, for step t+1.  The index t+1
+// comes from step_next, stored by step t's collision (the counter advances in
+// this launch).  The body-centre grid is read here, so step t+1's scatter
+// clears it.  One LDS union serves the three roles.
+template <typename Real>
+__global__ __launch_bounds__(BODY_T) void k_forces_prep(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid,
+                                                        ExtForce E, double dt, uint64_t *advance_step, double kT,
+                                                        int thermalize, uint64_t seed, const uint64_t *step_next,
+                                                        const Real *x, Real *xs, Real *vs, double *site_d,
+                                                        double *vpre, unsigned long long *counts, int32_t *cellid,
+                                                        int32_t *slot, double *shift_out, uint32_t *status)
+{
+    __shared__ double bsh[6];
+    __shared__ int bsr[2];
+    __shared__ union {
+        ForceLds<BODY_T> f;
+        ThermLds th;
+        BinLds bin;
+    } lds;
+    uint32_t st = 0;
+    if ((int64_t)blockIdx.x < s.B) {
+        body_forces_block<BODY_T>(s, bd, wca, grid, E, dt, 1, advance_step, status, lds.f);
+        __syncthreads();  // the kick is stored (by thread 0, which reads it back); the LDS is free
+        const uint64_t step = *step_next;
+        if (blockIdx.x == 0) draw_shifts(s, seed, step, shift_out);
+        prep_body_block<Real>(s, bd, blockIdx.x, kT, thermalize, seed, step, xs, vs, site_d, vpre, counts, cellid,
+                              slot, bsh, lds.th, st);
+    } else {
+        prep_solvent_block<Real>(s, seed, *step_next, x, counts, cellid, slot, ((int64_t)blockIdx.x - s.B) * PREP_CHUNK,
+                                 bsh, bsr, lds.bin, st);
     }
     flag(status, st);
 }
@@ -3366,14 +3463,16 @@ static void launch_scan(const Ctx &c, hipStream_t st)
                        cs, ss, (int32_t)NT, (int32_t)c.sys->n_sites, c.status);
 }
 
-static void launch_scatter(const Ctx &c, hipStream_t st)
+// clear_grid: also clear the body-centre grid (a step whose first kernel ran
+// fused into the previous step's last).
+static void launch_scatter(const Ctx &c, hipStream_t st, int32_t *clear_grid = nullptr, int64_t grid_n = 0)
 {
     const int64_t NT = c.sys->n_solvent + c.sys->n_sites;
     if (NT == 0) return;
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((NT + BIN_CHUNK - 1) / BIN_CHUNK)), dim3(BIN_T), 0, st, NT,
                        c.sys->n_solvent, at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot),
                        at<int32_t>(c.ws, c.L.cell_start), at<int32_t>(c.ws, c.L.site_start),
-                       at<int32_t>(c.ws, c.L.perm), c.status);
+                       at<int32_t>(c.ws, c.L.perm), clear_grid, grid_n, c.status);
 }
 
 static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bodies *bodies, double cos_a,
@@ -3531,14 +3630,41 @@ static void launch_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies,
 }
 
 // Scatter fused with the per-cell draws in one launch.
-static void launch_scatter_draws(const Ctx &c, hipStream_t st, const CollideArgs &A)
+static void launch_scatter_draws(const Ctx &c, hipStream_t st, const CollideArgs &A, int32_t *clear_grid = nullptr,
+                                 int64_t grid_n = 0)
 {
     const int64_t NT = c.sys->n_solvent + c.sys->n_sites;
     const int nsc = (int)((NT + BIN_CHUNK - 1) / BIN_CHUNK);
     const int ndr = (int)draw_blocks(c.sys->n_cells, c.tune);
     hipLaunchKernelGGL(k_scatter_draws, dim3((unsigned)(nsc + ndr)), dim3(BIN_T), 0, st, NT,
                        at<int32_t>(c.ws, c.L.cellid), at<int32_t>(c.ws, c.L.slot), at<int32_t>(c.ws, c.L.perm), ndr,
-                       A, at<double>(c.ws, c.L.draws));
+                       A, at<double>(c.ws, c.L.draws), clear_grid, grid_n);
+}
+
+// Step t's forces and kick fused with step t+1's first kernel (k_forces_prep):
+// x is the solvent step t wrote, step_next the index t+1 stored by step t's
+// collision.
+static void launch_forces_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca,
+                               const double *f_ext, double dt, uint64_t *advance, double kT, int thermalize,
+                               uint64_t seed, const uint64_t *step_next, const void *x, void *xs, void *vs)
+{
+    const int64_t nchunks = (c.sys->n_solvent + PREP_CHUNK - 1) / PREP_CHUNK;
+    const dim3 g((unsigned)(c.sys->n_bodies + nchunks));
+    const BodyDev bd = make_bodydev(bodies);
+    const BodyGrid grid = body_grid(c, wca);
+    const ExtForce E = make_ext(f_ext);
+    double *site_d = at<double>(c.ws, c.L.site_d), *vpre = at<double>(c.ws, c.L.vpre);
+    u64 *counts = at<u64>(c.ws, c.L.counts);
+    int32_t *cellid = at<int32_t>(c.ws, c.L.cellid), *slot = at<int32_t>(c.ws, c.L.slot);
+    double *shift = at<double>(c.ws, c.L.shift);
+    if (c.sys->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_forces_prep<double>, g, dim3(BODY_T), 0, st, c.sd, bd, wca, grid, E, dt, advance, kT,
+                           thermalize, seed, step_next, (const double *)x, (double *)xs, (double *)vs, site_d, vpre,
+                           counts, cellid, slot, shift, c.status);
+    else
+        hipLaunchKernelGGL(k_forces_prep<float>, g, dim3(BODY_T), 0, st, c.sd, bd, wca, grid, E, dt, advance, kT,
+                           thermalize, seed, step_next, (const float *)x, (float *)xs, (float *)vs, site_d, vpre,
+                           counts, cellid, slot, shift, c.status);
 }
 
 static void launch_transfer_first(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const void *vs, double *J,
@@ -3889,17 +4015,28 @@ static void step_rnemd(const Ctx &c, hipStream_t st, const mpcd_step_args *a)
 // step t+1 then thermalizes and bins its sites alone and joins that binning
 // before its scan.  The early binning reads the step index t+1 that the
 // collision stored, not the counter that step t's force kernel advances.
+//
+// Schedule 2 (fused): step t's force kernel also runs step t+1's first kernel
+// (k_forces_prep: each body block computes its forces and kick, then
+// thermalizes and bins its sites for t+1; extra blocks bin the new solvent),
+// so step t+1 starts at its scan and its scatter clears the body-centre grid.
+// Centre-centre WCA only (site-site WCA has a force kernel of its own).
 struct Overlap {
+    int mode;         // 1: side stream; 2: fused into the force kernel
     hipStream_t side;
     hipEvent_t fork, join;
-    bool pre_binned;  // this step's solvent is binned already (on side, joined by `join`)
-    bool bin_next;    // bin the next step's solvent on side after this step's collision
+    bool pre_binned;  // this step's first kernel has run already (mode 1: its solvent part, joined by `join`)
+    bool bin_next;    // run the next step's first kernel (its solvent part with mode 1) during this step
 };
 
-static bool overlap_possible(const mpcd_step_args *a)
+static int overlap_mode(const mpcd_step_args *a)
 {
-    return a->par.tune.overlap && a->v_out && a->reorder_every == 0 && a->sys->n_bodies > 0 &&
-           a->sys->n_sites > 0 && a->sys->n_solvent > 0;
+    const int m = a->par.tune.overlap;
+    if (!m || !a->v_out || a->reorder_every != 0 || a->sys->n_bodies == 0 || a->sys->n_sites == 0 ||
+        a->sys->n_solvent == 0)
+        return 0;
+    if (m == 2 && a->par.wca.mode == 2) return 0;
+    return m;
 }
 
 // One step: [thermalize + site binning | solvent binning] (one launch), scan,
@@ -3914,9 +4051,12 @@ static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
     const mpcd_params &p = a->par;
     const Ctx c = make_ctx(s, a->ws, &p.tune);
     hipStream_t st = (hipStream_t)stream;
+    const bool fused_in = ov && ov->mode == 2 && ov->pre_binned;  // first kernel ran in the last step's
     if (ov && ov->pre_binned) {
-        launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca, 1);
-        TRY(hip_check(hipStreamWaitEvent(st, ov->join, 0)));
+        if (ov->mode == 1) {
+            launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca, 1);
+            TRY(hip_check(hipStreamWaitEvent(st, ov->join, 0)));
+        }
     } else {
         launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca);
     }
@@ -3926,17 +4066,20 @@ static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
     uint64_t *step_next = at<uint64_t>(c.ws, c.L.step_next);
     if (ov && ov->bin_next) A.step_next = step_next;
     if (p.fuse_stream) A.F = make_forcing(p.g, p.dt);
+    const BodyGrid grid = body_grid(c, p.wca);
+    int32_t *clear_grid = fused_in ? grid.count : nullptr;
+    const int64_t grid_n = clear_grid ? (int64_t)c.L.grid_mask + 1 : 0;
     if (p.tune.draws_inline) {  // the collision draws; the scatter runs alone
         A.inline_draws = 1;
-        launch_scatter(c, st);
+        launch_scatter(c, st, clear_grid, grid_n);
     } else {
-        launch_scatter_draws(c, st, A);
+        launch_scatter_draws(c, st, A, clear_grid, grid_n);
     }
     if (a->v_out)
         launch_collide(c, st, A, a->v, a->vs, a->x, a->x_out, a->v_out, a->tag_out);
     else
         launch_collide(c, st, A, a->v, a->vs, p.fuse_stream ? a->x : nullptr);
-    if (ov && ov->bin_next) {  // next step's solvent binning beside this step's body update
+    if (ov && ov->bin_next && ov->mode == 1) {  // next step's solvent binning beside this step's body update
         TRY(hip_check(hipEventRecord(ov->fork, st)));
         TRY(hip_check(hipStreamWaitEvent(ov->side, ov->fork, 0)));
         launch_prep(c, ov->side, &a->bodies, p.kT, p.thermalize, p.seed, step_next, a->x_out, a->xs, a->vs, p.wca,
@@ -3950,12 +4093,29 @@ static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
         return launch_check();
     }
     launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt, p.wca);
-    launch_forces(c, st, &a->bodies, p.wca, p.f_ext, p.dt, 1, a->d_step);
+    if (ov && ov->bin_next && ov->mode == 2)  // forces, kick and the next step's first kernel in one launch
+        launch_forces_prep(c, st, &a->bodies, p.wca, p.f_ext, p.dt, a->d_step, p.kT, p.thermalize, p.seed, step_next,
+                           a->x_out, a->xs, a->vs);
+    else
+        launch_forces(c, st, &a->bodies, p.wca, p.f_ext, p.dt, 1, a->d_step);
     step_rnemd(c, st, a);
     return launch_check();
 }
 
 int mpcd_step(void *stream, const mpcd_step_args *a) { return step_impl(stream, a, nullptr); }
+
+int mpcd_forces_prep(void *stream, const mpcd_step_args *a, const uint64_t *step_next)
+{
+    TRY(step_checks(a));
+    if (!ok_arr(step_next, 1, 8)) return MPCD_EINVAL;
+    const mpcd_sys *s = a->sys;
+    const mpcd_params &p = a->par;
+    if (s->n_bodies == 0 || s->n_sites == 0 || p.wca.mode == 2) return MPCD_ENOTSUP;
+    const Ctx c = make_ctx(s, a->ws, &p.tune);
+    launch_forces_prep(c, (hipStream_t)stream, &a->bodies, p.wca, p.f_ext, p.dt, a->d_step, p.kT, p.thermalize,
+                       p.seed, step_next, a->x, a->xs, a->vs);
+    return launch_check();
+}
 
 int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, void **graph_exec)
 {
@@ -3963,9 +4123,10 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
     TRY(step_checks(args));
     if (args->v_out && ((nsteps & 1) || !args->tag)) return MPCD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    Overlap ov{nullptr, nullptr, nullptr, false, false};
-    const bool overlap = nsteps >= 2 && overlap_possible(args);
-    if (overlap) {  // default-priority side stream and the two events, for the capture only
+    const int omode = nsteps >= 2 ? overlap_mode(args) : 0;
+    Overlap ov{omode, nullptr, nullptr, nullptr, false, false};
+    const bool overlap = omode != 0;
+    if (omode == 1) {  // default-priority side stream and the two events, for the capture only
         int rc0 = hip_check(hipStreamCreateWithFlags(&ov.side, hipStreamNonBlocking));
         if (rc0 == MPCD_OK) rc0 = hip_check(hipEventCreateWithFlags(&ov.fork, hipEventDisableTiming));
         if (rc0 == MPCD_OK) rc0 = hip_check(hipEventCreateWithFlags(&ov.join, hipEventDisableTiming));
@@ -3977,7 +4138,7 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
         }
     }
     auto release = [&]() {
-        if (!overlap) return;
+        if (omode != 1) return;
         (void)hipEventDestroy(ov.join);
         (void)hipEventDestroy(ov.fork);
         (void)hipStreamDestroy(ov.side);

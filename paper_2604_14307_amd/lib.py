@@ -19,7 +19,7 @@ FLAG_NONFINITE, FLAG_ESCAPE, FLAG_FIXOVF, FLAG_RNGLOOP, FLAG_BINERR, FLAG_REACH,
 EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mpcd_stream", "mpcd_bin", "mpcd_collide",
            "mpcd_cell_draws", "mpcd_collide_drawn",
            "sites_thermalize", "sites_to_body", "body_integrate", "body_forces",
-           "mpcd_advance_step", "mpcd_step", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
+           "mpcd_advance_step", "mpcd_step", "mpcd_forces_prep", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
            "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error",
            "harm_forces", "harm_md", "harm_step", "harm_graph_create", "mpcd_rnemd_exchange", "mpcd_cell_order",
            "mpcd_tile_shape")
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
         "body_forces": (C.c_int, [vp, sp, bp, wp, C.POINTER(dbl), vp, sz]),
         "mpcd_advance_step": (C.c_int, [vp, vp]),
         "mpcd_step": (C.c_int, [vp, C.POINTER(MpcdStepArgs)]),
+        "mpcd_forces_prep": (C.c_int, [vp, C.POINTER(MpcdStepArgs), vp]),
         "mpcd_reorder": (C.c_int, [vp, sp, vp, vp, vp, vp, sz]),
         "mpcd_graph_create": (C.c_int, [vp, C.POINTER(MpcdStepArgs), i32, C.POINTER(vp)]),
         "mpcd_graph_launch": (C.c_int, [vp, vp]),

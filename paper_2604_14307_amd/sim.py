@@ -288,6 +288,13 @@ class GPUSystem:
             if self.out_of_place:
                 self._swap()
 
+    def forces_prep(self, step_next):
+        """mpcd_forces_prep on the current state: body forces, kick and counter
+        advance, then the next step's site thermalization and binning of the
+        current solvent, for the step index held in step_next (device int64)."""
+        a = self.step_args()  # a.x: the solvent the last step wrote
+        L.check(self.lib.mpcd_forces_prep(self.stream, C.byref(a), _ptr(step_next)), "mpcd_forces_prep")
+
     def recollide_last(self, restore_sites: bool = True):
         """Repeat the last out-of-place step's collide + stream pass from its
         inputs into the current arrays.  The sites collide in place, so their

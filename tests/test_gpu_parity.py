@@ -322,17 +322,22 @@ def test_graph_replay_matches_eager(out_of_place):
         gg.release_graph()
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("prec,exchange", [("f64", False), ("f32", False), ("f32", True)])
-def test_overlapped_graph_matches_eager(prec, exchange):
-    """Graphs that bin each next step's solvent on a second stream, beside the
-    current step's body update, give the state of the same steps run one by
-    one (bodies with sites, WCA, out of place; with the exchange appended)."""
+def test_overlapped_graph_matches_eager(prec, exchange, mode):
+    """Graphs that run each next step's first kernel during the current step
+    (mode 1: its solvent binning on a second stream beside the body update;
+    mode 2: inside the force kernel) give the state of the same steps run one
+    by one (bodies with sites, WCA, out of place; with the exchange appended)."""
     wl = W.suspension((14, 18, 11), 5, 4, 2.0, 60, 5.0, seed=91)
     par = W.srd_params(91, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
-    say("overlapped graph %s exchange=%s" % (prec, exchange))
+    say("overlapped graph %s exchange=%s mode %d" % (prec, exchange, mode))
     ge, gg = gpu_system(wl, par, prec=prec), gpu_system(wl, par, prec=prec)
-    ge.set_tuning(0, 0, 0, 1, 0)
-    gg.set_tuning(0, 0, 0, 1, 1)
+    # both scatter kernels clear the body-centre grid in mode 2: the one fused
+    # with the draws pass (FP32 here) and the one without it
+    inl = 0 if (mode == 2 and prec == "f32") else 1
+    ge.set_tuning(0, 0, 0, inl, 0)
+    gg.set_tuning(0, 0, 0, inl, mode)
     for g in (ge, gg):
         g.body_forces()
         if exchange:
@@ -352,6 +357,44 @@ def test_overlapped_graph_matches_eager(prec, exchange):
             assert int(ge.d_step.cpu()[0]) == int(gg.d_step.cpu()[0]) == 6 * (rep + 1)
         gg.release_graph()
     assert ge.status() == 0 and gg.status() == 0
+
+
+def test_forces_prep_entry_point():
+    """mpcd_forces_prep after step t: the counter advances to t+1, and its
+    binning for t+1 (site positions and every particle's cell) equals that of
+    the separate entry points (sites_thermalize, mpcd_bin) at step t+1.
+    Bodies without sites, or with site-site WCA, are not supported."""
+    wl = W.suspension((14, 18, 11), 5, 4, 2.0, 60, 5.0, seed=92)
+    par = W.srd_params(92, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
+    ga, gb = gpu_system(wl, par, prec="f64"), gpu_system(wl, par, prec="f64")
+    for g in (ga, gb):
+        g.body_forces()
+        g.step(3)
+    t = int(ga.d_step.cpu()[0])
+    nxt = torch.tensor([t + 1], dtype=torch.int64, device="cuda")
+    ga.forces_prep(nxt)
+    assert int(ga.d_step.cpu()[0]) == t + 1
+    gb.set_step(t + 1)
+    gb.sites_thermalize()
+    gb.bin()
+    ca = ga.ws_view("cellid", torch.int32, ga.N + ga.S).cpu().numpy()
+    cb = gb.ws_view("cellid", torch.int32, gb.N + gb.S).cpu().numpy()
+    # the solvent's storage order within a cell follows atomic arrival, so the
+    # cells are compared by identity (tag); sites are stored in body order
+    ida, idb = np.empty(ga.N, np.int32), np.empty(gb.N, np.int32)
+    ida[ga.tag.cpu().numpy()] = ca[:ga.N]
+    idb[gb.tag.cpu().numpy()] = cb[:gb.N]
+    assert np.array_equal(ida, idb)
+    assert np.array_equal(ca[ga.N:], cb[gb.N:])
+    assert np.array_equal(ga.download()[0]["xs"], gb.download()[0]["xs"])
+    assert ga.status() == 0 and gb.status() == 0
+    # unsupported: pure solvent (no sites)
+    ws = W.make_system((8, 8, 8), 5, [], [], np.zeros((0, 4)), np.random.default_rng(93))
+    g0 = gpu_system(ws, W.srd_params(93, kT_cell=1.0), prec="f64")
+    import ctypes
+    a = g0.step_args()
+    enotsup = -4  # MPCD_ENOTSUP
+    assert g0.lib.mpcd_forces_prep(g0.stream, ctypes.byref(a), ctypes.c_void_p(nxt.data_ptr())) == enotsup
 
 
 def point_bodies(ncell, centres, seed):
