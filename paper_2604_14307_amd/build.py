@@ -11,10 +11,14 @@ LIB = os.path.join(HERE, "libmpcd.so")
 
 # -ffp-contract=off: every a*b+c stays a rounded multiply and a rounded add, so
 # the FP64 path reproduces a host evaluation bit for bit.  Packed FP32 ops are
-# disabled for all device code.
+# disabled for all device code.  The IR load/store vectorizer is off: it merges
+# the kernel-argument loads into a few wide scalar loads at kernel entry, which
+# keeps every argument live in SGPRs and spills them into VGPR lanes in the
+# larger kernels (each later use then costs a v_readlane).
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-ffp-contract=off", "-fno-fast-math",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-mllvm", "-amdgpu-load-store-vectorizer=false",
                "-Wno-unused-command-line-argument"]
 
 

@@ -1484,7 +1484,7 @@ __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(siz
 
 // LDS layout: offsets of s_cs, s_idx, s_cl, s_v, s_key|s_acc, s_par, s_r, end.
 struct TileLayout {
-    size_t cs, idx, cl, v, keyacc, par, r, ss, end;
+    size_t cs, idx, cl, v, keyacc, par, r, ss, len, end;
 };
 
 __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
@@ -1500,6 +1500,7 @@ __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
     L.par = o; o += align16(f64 ? sizeof(double) * 13 * (size_t)cpb : sizeof(float) * 12 * (size_t)cpb);
     L.r = o; o += align16(sizeof(int) * (size_t)cpb);
     L.ss = o; o += align16(sizeof(int) * (size_t)cpb);
+    L.len = o; o += align16((f64 ? 8 : 4) * 3 * (size_t)cpb);  // box edges of each cell's system
     L.end = o;
     return L;
 }
@@ -1538,6 +1539,7 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     uint64_t *s_key = (uint64_t *)(smem + Lo.keyacc);
     int *s_r = (int *)(smem + Lo.r);
     int *s_ss = (int *)(smem + Lo.ss);
+    Real *s_len = (Real *)(smem + Lo.len);
     const int64_t N = s.N, S = s.S;
     const bool out = O.v != nullptr;
 
@@ -1588,6 +1590,8 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
         }
         s_r[t] = r;
         if (out) s_ss[t] = A.site_start[gc];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s_len[3 * t + d] = (Real)((double)s.ncell[3 * r + d] * s.a);
     }
     __syncthreads();
 
@@ -1686,74 +1690,94 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     __syncthreads();
 
     // phase 3: rotate, stream, write back (solvent out of place: to its
-    // cell-order slot, every member whether or not its cell collided)
+    // cell-order slot, every member whether or not its cell collided).  The
+    // out-of-place and in-place forms are separate loops, so each keeps only
+    // its own pointers live.
     const Real dtr = (Real)A.dt;
+    const bool fon = A.F.on != 0;
+    Real fh[3], fg[3];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int i = t + j * TILE_T;
-        const int32_t k = kk[j];
-        if (i >= nm) continue;
-        const int c = s_cl[i];
-        Real vn[3] = {va[j][0], va[j][1], va[j][2]};
-        const bool moved = (s_cs[c + 1] - s_cs[c]) >= 2;
-        if (moved) {
-            if constexpr (F64) {
-                const double *par = (const double *)(smem + Lo.par) + 13 * c;
-                const double dl[3] = {vn[0] - par[0], vn[1] - par[1], vn[2] - par[2]};
+    for (int d = 0; d < 3; ++d) {
+        fh[d] = (Real)A.F.h[d];
+        fg[d] = (Real)A.F.gdt[d];
+    }
+    // collided velocity of item j (its cell c); writes a site's back
+    auto rotate = [&](int j, int c, Real vn[3]) {
+        vn[0] = va[j][0]; vn[1] = va[j][1]; vn[2] = va[j][2];
+        if ((s_cs[c + 1] - s_cs[c]) < 2) return;
+        if constexpr (F64) {
+            const double *par = (const double *)(smem + Lo.par) + 13 * c;
+            const double dl[3] = {vn[0] - par[0], vn[1] - par[1], vn[2] - par[2]};
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double rr = (par[4 + 3 * d] * dl[0] + par[5 + 3 * d] * dl[1]) + par[6 + 3 * d] * dl[2];
-                    vn[d] = par[d] + par[3] * rr;
-                    if (!(vn[d] - vn[d] == 0.0)) st |= ST_NONFINITE;
-                }
-            } else {
-                const float *par = (const float *)(smem + Lo.par) + 12 * c;
-                const float dl[3] = {vn[0] - par[0], vn[1] - par[1], vn[2] - par[2]};
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    vn[d] = par[d] + ((par[3 + 3 * d] * dl[0] + par[4 + 3 * d] * dl[1]) + par[5 + 3 * d] * dl[2]);
-                    if (!(vn[d] - vn[d] == 0.0f)) st |= ST_NONFINITE;
-                }
+            for (int d = 0; d < 3; ++d) {
+                const double rr = (par[4 + 3 * d] * dl[0] + par[5 + 3 * d] * dl[1]) + par[6 + 3 * d] * dl[2];
+                vn[d] = par[d] + par[3] * rr;
+                if (!(vn[d] - vn[d] == 0.0)) st |= ST_NONFINITE;
             }
-            if (k >= N) {
-                const int64_t q = k - N;
-                vs[q] = vn[0]; vs[S + q] = vn[1]; vs[2 * S + q] = vn[2];
-            } else if (!out) {
-                v[k] = vn[0]; v[N + k] = vn[1]; v[2 * N + k] = vn[2];
+        } else {
+            const float *par = (const float *)(smem + Lo.par) + 12 * c;
+            const float dl[3] = {vn[0] - par[0], vn[1] - par[1], vn[2] - par[2]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                vn[d] = par[d] + ((par[3 + 3 * d] * dl[0] + par[4 + 3 * d] * dl[1]) + par[5 + 3 * d] * dl[2]);
+                if (!(vn[d] - vn[d] == 0.0f)) st |= ST_NONFINITE;
             }
         }
-        if (k >= N) continue;
-        if (out) {
+        if (kk[j] >= N) {
+            const int64_t q = kk[j] - N;
+            vs[q] = vn[0]; vs[S + q] = vn[1]; vs[2 * S + q] = vn[2];
+        }
+    };
+    if (out) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int i = t + j * TILE_T;
+            if (i >= nm) continue;
+            const int c = s_cl[i];
+            Real vn[3];
+            rotate(j, c, vn);
+            if (kk[j] >= N) continue;
             const int64_t dst = (int64_t)(m0 + i) - s_ss[c];
             if (dst < 0 || dst >= N) {  // only with a corrupted permutation
                 st |= ST_BINERR;
                 continue;
             }
-            const int r = s_r[c];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
+                const Real L = s_len[3 * c + d];
                 Real y = xo[j][d] + vn[d] * dtr;
                 Real vo = vn[d];
-                if (A.F.on) {
-                    y = y + (Real)A.F.h[d];
-                    vo = vo + (Real)A.F.gdt[d];
+                if (fon) {
+                    y = y + fh[d];
+                    vo = vo + fg[d];
                 }
                 O.x[d * N + dst] = RealOps<Real>::wrap(y, L, st);
                 O.v[d * N + dst] = vo;
             }
             O.tag[dst] = tg[j];
-        } else if (xstream) {
-            const int r = s_r[c];
+        }
+    } else {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const Real L = (Real)((double)s.ncell[3 * r + d] * s.a);
-                Real y = xo[j][d] + vn[d] * dtr;
-                if (A.F.on) {
-                    y = y + (Real)A.F.h[d];
-                    v[d * N + k] = vn[d] + (Real)A.F.gdt[d];
+        for (int j = 0; j < ITEMS; ++j) {
+            const int i = t + j * TILE_T;
+            if (i >= nm) continue;
+            const int c = s_cl[i];
+            const int32_t k = kk[j];
+            Real vn[3];
+            rotate(j, c, vn);
+            if (k >= N) continue;
+            const bool moved = (s_cs[c + 1] - s_cs[c]) >= 2;
+            if (xstream) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const Real L = s_len[3 * c + d];
+                    Real y = xo[j][d] + vn[d] * dtr;
+                    if (fon) y = y + fh[d];
+                    xstream[d * N + k] = RealOps<Real>::wrap(y, L, st);
+                    if (moved || fon) v[d * N + k] = fon ? vn[d] + fg[d] : vn[d];
                 }
-                xstream[d * N + k] = RealOps<Real>::wrap(y, L, st);
+            } else if (moved) {
+                v[k] = vn[0]; v[N + k] = vn[1]; v[2 * N + k] = vn[2];
             }
         }
     }
