@@ -134,11 +134,13 @@ typedef struct {
  * default 1) is the number of cells each lane of the per-cell draws takes.
  * draws_inline (0 or 1): 1 makes the collision draw each cell's random axis
  * and gamma variate itself, in place of a separate draws pass (the same
- * values).  overlap (0, 1 or 2), for mpcd_graph_create (out-of-place steps
+ * values).  overlap (0..3), for mpcd_graph_create (out-of-place steps
  * with sites and no reorder; elsewhere ignored): 1 bins the solvent of each
  * next step on a second stream beside the current step's body update; 2 runs
  * each next step's first kernel inside the current step's force kernel
- * (centre-centre WCA only).
+ * (centre-centre WCA only); 3 is 2 with the next step's solvent binned by the
+ * current step's collision (the force kernel then thermalizes and bins the
+ * sites only).
  * Out-of-range values: MPCD_EINVAL. */
 typedef struct {
     int32_t tile_items;

@@ -32,6 +32,7 @@ namespace {
 struct SysDev {
     int32_t nsys;
     double a;
+    double inv_a;  // 1/a when a is a power of two (x/a == x*inv_a exactly, in FP32 too), else 0
     double m;
     int64_t N, S, B, C;
     uint64_t replica0;
@@ -54,6 +55,9 @@ SysDev make_sysdev(const mpcd_sys *s)
     SysDev d;
     d.nsys = s->nsys;
     d.a = s->a;
+    int e = 0;
+    const double f = frexp(s->a, &e);
+    d.inv_a = (f == 0.5 && s->a > 0x1p-120 && s->a < 0x1p120) ? ldexp(1.0, 1 - e) : 0.0;
     d.m = s->m_solvent;
     d.N = s->n_solvent;
     d.S = s->n_sites;
@@ -223,10 +227,12 @@ template <> struct Prec<float> {
 };
 
 // Cell index along one axis for the shifted grid: floor((x - s)/a) mod n.
-__device__ __forceinline__ int axis_cell(double x, double s, double a, int n, uint32_t &st)
+// inv_a != 0: a is a power of two and g * inv_a is the same correctly rounded
+// quotient as g / a (both round the exact value g 2^-k), without the division.
+__device__ __forceinline__ int axis_cell(double x, double s, double a, double inv_a, int n, uint32_t &st)
 {
     const double g = x - s;
-    const double jf = floor(g / a);
+    const double jf = floor(inv_a != 0.0 ? g * inv_a : g / a);
     if (!(jf >= -1.0 && jf <= (double)n)) {
         st |= (g != g) ? ST_NONFINITE : ST_ESCAPE;
         return 0;
@@ -237,10 +243,10 @@ __device__ __forceinline__ int axis_cell(double x, double s, double a, int n, ui
     return j;
 }
 
-__device__ __forceinline__ int axis_cell(float x, double s, double a, int n, uint32_t &st)
+__device__ __forceinline__ int axis_cell(float x, double s, double a, double inv_a, int n, uint32_t &st)
 {
     const float g = x - (float)s;
-    const float jf = floorf(g / (float)a);
+    const float jf = floorf(inv_a != 0.0 ? g * (float)inv_a : g / (float)a);
     if (!(jf >= -1.0f && jf <= (float)n)) {
         st |= (g != g) ? ST_NONFINITE : ST_ESCAPE;
         return 0;
@@ -280,7 +286,7 @@ static bool tune_ok(const mpcd_tune &tu, bool f64)
     const bool items_ok = it == 0 || (f64 ? (it == 1 || it == 2 || it == 4) : (it == 2 || it == 4 || it == 8));
     return items_ok && (tu.tile_fill == 0 || (tu.tile_fill >= 10 && tu.tile_fill <= 100)) &&
            tu.draw_cells >= 0 && tu.draw_cells <= 16 && (tu.draws_inline == 0 || tu.draws_inline == 1) &&
-           (tu.overlap >= 0 && tu.overlap <= 2);
+           (tu.overlap >= 0 && tu.overlap <= 3);
 }
 
 TileCfg tile_config(const mpcd_sys *s, const mpcd_tune &tu)
@@ -584,9 +590,9 @@ __device__ __forceinline__ int32_t cell_of_pos(const SysDev &s, int r, Real p0, 
                                                uint32_t &st)
 {
     const int nx = s.ncell[3 * r], ny = s.ncell[3 * r + 1], nz = s.ncell[3 * r + 2];
-    const int jx = axis_cell(p0, sh[0], s.a, nx, st);
-    const int jy = axis_cell(p1, sh[1], s.a, ny, st);
-    const int jz = axis_cell(p2, sh[2], s.a, nz, st);
+    const int jx = axis_cell(p0, sh[0], s.a, s.inv_a, nx, st);
+    const int jy = axis_cell(p1, sh[1], s.a, s.inv_a, ny, st);
+    const int jz = axis_cell(p2, sh[2], s.a, s.inv_a, nz, st);
     return (int32_t)(s.cell_off[r] + brick_index(nx, ny, nz, jx, jy, jz));
 }
 
@@ -1074,6 +1080,11 @@ struct CollideArgs {
     uint64_t *step_next;     // when set, block 0 stores the step index + 1 there
     Forcing F;               // solvent acceleration applied by the fused streaming
     int inline_draws;        // 1: the collision draws each cell's axis and gamma itself
+    // binning of the new solvent for the next step (kernels with BIN): packed
+    // per-cell counters (solvent in the low 32 bits) and the cell and slot of
+    // each new solvent particle
+    unsigned long long *bin_counts;
+    int32_t *bin_cellid, *bin_slot;
 };
 
 // Identity order key of particle k: solvent tag (or index), sites N_total + j.
@@ -1506,7 +1517,7 @@ __host__ __device__ inline TileLayout tile_layout(bool f64, int cpb, int cap)
 }
 
 
-template <typename Real, int ITEMS, int INL>
+template <typename Real, int ITEMS, int INL, bool BIN>
 __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg &T, Real *v, Real *vs, Real *xstream,
                                              const SolvOut<Real> &O)
 {
@@ -1527,6 +1538,28 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
             if constexpr (F64) collide_cell_f64_global<INL>(A, c0 + c, v, vs, xstream, O, st);
             else collide_cell_f32_global<INL>(A, c0 + c, v, vs, xstream, O, st);
         }
+        if constexpr (BIN) {
+            // the tile's new solvent is the contiguous range [q0, q1) of the
+            // output; bin it with one device atomic per particle (crowded
+            // tiles are rare)
+            __syncthreads();  // the block's stores of the new solvent are visible to it
+            const int64_t q0 = (int64_t)A.cell_start[c0] - A.site_start[c0];
+            const int64_t q1 = (int64_t)A.cell_start[c0 + nc] - A.site_start[c0 + nc];
+            const uint64_t step1 = *A.d_step + 1;
+            for (int64_t q = q0 + t; q < q1; q += TILE_T) {
+                if (q < 0 || q >= s.N) {
+                    st |= ST_BINERR;
+                    continue;
+                }
+                const int r = find_sys(s.solv_off, s.nsys, q);
+                double sh[3];
+                shift_of(s, A.seed, step1, r, sh);
+                const int32_t gc = cell_of_pos<Real>(s, r, O.x[q], O.x[s.N + q], O.x[2 * s.N + q], sh, st);
+                const unsigned long long old = atomicAdd(&A.bin_counts[gc], 1ull);
+                A.bin_slot[q] = (int32_t)(old & 0xffffffffull);
+                A.bin_cellid[q] = gc;
+            }
+        }
         flag(A.status, st);
         return;
     }
@@ -1540,6 +1573,7 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
     int *s_r = (int *)(smem + Lo.r);
     int *s_ss = (int *)(smem + Lo.ss);
     Real *s_len = (Real *)(smem + Lo.len);
+    double *s_shift = (double *)(smem + Lo.end);  // BIN: next-step shifts of systems tr0..tr1
     const int64_t N = s.N, S = s.S;
     const bool out = O.v != nullptr;
 
@@ -1592,6 +1626,11 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
         if (out) s_ss[t] = A.site_start[gc];
 #pragma unroll
         for (int d = 0; d < 3; ++d) s_len[3 * t + d] = (Real)((double)s.ncell[3 * r + d] * s.a);
+    }
+    if constexpr (BIN) {  // next-step shift of system tr0 + l by lane TILE_T - 1 - l (a tile has
+                          // at least one cell per system, so at most TILE_T systems)
+        const int l = TILE_T - 1 - t;
+        if (l <= tr1 - tr0 && l < T.cpb) shift_of(s, A.seed, *A.d_step + 1, tr0 + l, s_shift + 3 * l);
     }
     __syncthreads();
 
@@ -1728,6 +1767,10 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
             vs[q] = vn[0]; vs[S + q] = vn[1]; vs[2 * S + q] = vn[2];
         }
     };
+    // BIN: the next-step cell of each new solvent particle and its output index
+    int32_t gcs[BIN ? ITEMS : 1], dsts[BIN ? ITEMS : 1];
+#pragma unroll
+    for (int j = 0; j < (BIN ? ITEMS : 1); ++j) gcs[j] = dsts[j] = -1;
     if (out) {
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
@@ -1742,6 +1785,7 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
                 st |= ST_BINERR;
                 continue;
             }
+            Real yw[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const Real L = s_len[3 * c + d];
@@ -1751,10 +1795,73 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
                     y = y + fh[d];
                     vo = vo + fg[d];
                 }
-                O.x[d * N + dst] = RealOps<Real>::wrap(y, L, st);
+                yw[d] = RealOps<Real>::wrap(y, L, st);
+                O.x[d * N + dst] = yw[d];
                 O.v[d * N + dst] = vo;
             }
             O.tag[dst] = tg[j];
+            if constexpr (BIN) {
+                const int r = s_r[c];
+                if (r - tr0 >= T.cpb) {  // only with systems of no cells
+                    st |= ST_BINERR;
+                    continue;
+                }
+                const double *sh = s_shift + 3 * (r - tr0);
+                const double shv[3] = {sh[0], sh[1], sh[2]};
+                gcs[j] = cell_of_pos<Real>(s, r, yw[0], yw[1], yw[2], shv, st);
+                dsts[j] = (int32_t)dst;
+            }
+        }
+        if constexpr (BIN) {
+            // phase 4: count the new solvent per next-step cell in an LDS hash
+            // table (over the tile's LDS, free now), one device atomic per
+            // distinct cell for its base slot; slot = base + rank in the block
+            constexpr int HT = TILE_T * ITEMS, HT_BITS = ITEMS == 1 ? 8 : ITEMS == 2 ? 9 : ITEMS == 4 ? 10 : 11;
+            static_assert((1 << HT_BITS) == HT, "hash size");
+            uint32_t *hkey = (uint32_t *)smem;
+            int32_t *hcnt = (int32_t *)(smem + sizeof(uint32_t) * HT);
+            __syncthreads();  // phase 3's LDS reads are done
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                hkey[t + it * TILE_T] = BIN_EMPTY;
+                hcnt[t + it * TILE_T] = 0;
+            }
+            __syncthreads();
+            int hs[ITEMS], rk[ITEMS];
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                hs[j] = rk[j] = 0;
+                if (gcs[j] < 0) continue;
+                const uint32_t key = (uint32_t)gcs[j];
+                uint32_t h = (key * 2654435761u) >> (32 - HT_BITS);
+                while (true) {  // ends: at most HT members, so fewer distinct keys than slots
+                    const uint32_t old = atomicCAS(&hkey[h], BIN_EMPTY, key);
+                    if (old == BIN_EMPTY || old == key) break;
+                    h = (h + 1) & (HT - 1);
+                }
+                hs[j] = (int)h;
+                rk[j] = atomicAdd(&hcnt[h], 1);
+            }
+            __syncthreads();
+            unsigned long long base[ITEMS];
+            uint32_t keys[ITEMS];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                const int i = t + it * TILE_T;
+                keys[it] = hkey[i];
+                base[it] = 0ull;
+                if (keys[it] != BIN_EMPTY) base[it] = atomicAdd(&A.bin_counts[keys[it]], (unsigned long long)hcnt[i]);
+            }
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (keys[it] != BIN_EMPTY) hcnt[t + it * TILE_T] = (int32_t)(base[it] & 0xffffffffull);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                if (gcs[j] < 0) continue;
+                A.bin_slot[dsts[j]] = hcnt[hs[j]] + rk[j];
+                A.bin_cellid[dsts[j]] = gcs[j];
+            }
         }
     } else {
 #pragma unroll
@@ -1785,30 +1892,35 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
 }
 
 // One kernel per items-per-thread choice, each with the draws read from the
-// draws pass or made inside (suffix _d).  The FP32 4-item form without draws
-// is held to 80 VGPRs (six waves per SIMD to hide the gather latency;
+// draws pass or made inside (suffix _d), and each of those with the binning of
+// the new solvent for the next step (suffix _b).  The FP32 4-item form without
+// draws is held to 80 VGPRs (six waves per SIMD to hide the gather latency;
 // measured faster than five), the 2-item form to 72 (seven waves) and the
 // 8-item form with draws to 128 (four waves; the compiler's own choice, 129,
 // drops it to three); the other forms keep the compiler's allocation (a tighter
 // cap spills).
-#define MPCD_COLLIDE_KERNEL(NAME, ATTR, REAL, ITEMS, INL)                                                      \
+#define MPCD_COLLIDE_KERNEL(NAME, ATTR, REAL, ITEMS, INL, BIN)                                                 \
     __global__ __launch_bounds__(TILE_T) ATTR void NAME(CollideArgs A, TileCfg T, REAL *v, REAL *vs,           \
                                                         REAL *xstream, SolvOut<REAL> O)                       \
     {                                                                                                          \
-        collide_tile<REAL, ITEMS, INL>(A, T, v, vs, xstream, O);                                              \
+        collide_tile<REAL, ITEMS, INL, BIN>(A, T, v, vs, xstream, O);                                         \
     }
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i2, __attribute__((amdgpu_waves_per_eu(7))), float, 2, 0)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f32, __attribute__((amdgpu_waves_per_eu(6))), float, 4, 0)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i8, , float, 8, 0)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i2_d, , float, 2, 1)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_d, , float, 4, 1)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f32_i8_d, __attribute__((amdgpu_waves_per_eu(4))), float, 8, 1)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i1, , double, 1, 0)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f64, , double, 2, 0)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i4, , double, 4, 0)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i1_d, , double, 1, 1)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_d, , double, 2, 1)
-MPCD_COLLIDE_KERNEL(k_collide_tiled_f64_i4_d, , double, 4, 1)
+#define MPCD_COLLIDE_PAIR(NAME, ATTR, REAL, ITEMS, INL)                                                        \
+    MPCD_COLLIDE_KERNEL(NAME, ATTR, REAL, ITEMS, INL, false)                                                   \
+    MPCD_COLLIDE_KERNEL(NAME##_b, ATTR, REAL, ITEMS, INL, true)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f32_i2, __attribute__((amdgpu_waves_per_eu(7))), float, 2, 0)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f32, __attribute__((amdgpu_waves_per_eu(6))), float, 4, 0)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f32_i8, , float, 8, 0)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f32_i2_d, , float, 2, 1)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f32_d, , float, 4, 1)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f32_i8_d, __attribute__((amdgpu_waves_per_eu(4))), float, 8, 1)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f64_i1, , double, 1, 0)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f64, , double, 2, 0)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f64_i4, , double, 4, 0)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f64_i1_d, , double, 1, 1)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f64_d, , double, 2, 1)
+MPCD_COLLIDE_PAIR(k_collide_tiled_f64_i4_d, , double, 4, 1)
+#undef MPCD_COLLIDE_PAIR
 #undef MPCD_COLLIDE_KERNEL
 
 // ---------------------------------------------------------------------------
@@ -3522,6 +3634,9 @@ static CollideArgs collide_args(const Ctx &c, const int32_t *tag, const mpcd_bod
     A.step_next = nullptr;
     A.F = make_forcing(nullptr, dt);
     A.inline_draws = 0;
+    A.bin_counts = nullptr;
+    A.bin_cellid = nullptr;
+    A.bin_slot = nullptr;
     return A;
 }
 
@@ -3540,25 +3655,38 @@ static void launch_draws(const Ctx &c, hipStream_t st, const CollideArgs &A)
 
 // x_stream: positions streamed in place, or (out of place) read and streamed
 // into x_out.  v_out == nullptr: in place.
+// A.bin_counts set (out of place only): the kernel also bins the new solvent
+// for the next step; its LDS then also holds the tile's hash table.
 static void launch_collide(const Ctx &c, hipStream_t st, const CollideArgs &A, void *v, void *vs, void *x_stream,
                            void *x_out = nullptr, void *v_out = nullptr, int32_t *tag_out = nullptr)
 {
     const bool f64 = c.sys->prec == MPCD_F64;
     const TileCfg T = tile_config(c.sys, c.tune);
     const dim3 grid(xcd_grid(T.ntiles));
-    const size_t lds = tile_layout(f64, T.cpb, T.cap).end;
+    const bool b = A.bin_counts != nullptr && v_out != nullptr;
+    size_t lds = tile_layout(f64, T.cpb, T.cap).end;
+    if (b) {  // + the next-step shifts of the tile's systems; the hash table overlays the tile
+        lds += sizeof(double) * 3 * (size_t)T.cpb;
+        if (lds < 8 * (size_t)T.cap) lds = 8 * (size_t)T.cap;
+    }
     const bool d = A.inline_draws != 0;
     if (f64) {
         const SolvOut<double> O{(double *)x_out, (double *)v_out, tag_out};
-        auto kern = T.items == 1 ? (d ? k_collide_tiled_f64_i1_d : k_collide_tiled_f64_i1)
-                  : T.items == 4 ? (d ? k_collide_tiled_f64_i4_d : k_collide_tiled_f64_i4)
-                                 : (d ? k_collide_tiled_f64_d : k_collide_tiled_f64);
+        auto kern = T.items == 1 ? (b ? (d ? k_collide_tiled_f64_i1_d_b : k_collide_tiled_f64_i1_b)
+                                      : (d ? k_collide_tiled_f64_i1_d : k_collide_tiled_f64_i1))
+                  : T.items == 4 ? (b ? (d ? k_collide_tiled_f64_i4_d_b : k_collide_tiled_f64_i4_b)
+                                      : (d ? k_collide_tiled_f64_i4_d : k_collide_tiled_f64_i4))
+                                 : (b ? (d ? k_collide_tiled_f64_d_b : k_collide_tiled_f64_b)
+                                      : (d ? k_collide_tiled_f64_d : k_collide_tiled_f64));
         hipLaunchKernelGGL(kern, grid, dim3(TILE_T), lds, st, A, T, (double *)v, (double *)vs, (double *)x_stream, O);
     } else {
         const SolvOut<float> O{(float *)x_out, (float *)v_out, tag_out};
-        auto kern = T.items == 2 ? (d ? k_collide_tiled_f32_i2_d : k_collide_tiled_f32_i2)
-                  : T.items == 8 ? (d ? k_collide_tiled_f32_i8_d : k_collide_tiled_f32_i8)
-                                 : (d ? k_collide_tiled_f32_d : k_collide_tiled_f32);
+        auto kern = T.items == 2 ? (b ? (d ? k_collide_tiled_f32_i2_d_b : k_collide_tiled_f32_i2_b)
+                                      : (d ? k_collide_tiled_f32_i2_d : k_collide_tiled_f32_i2))
+                  : T.items == 8 ? (b ? (d ? k_collide_tiled_f32_i8_d_b : k_collide_tiled_f32_i8_b)
+                                      : (d ? k_collide_tiled_f32_i8_d : k_collide_tiled_f32_i8))
+                                 : (b ? (d ? k_collide_tiled_f32_d_b : k_collide_tiled_f32_b)
+                                      : (d ? k_collide_tiled_f32_d : k_collide_tiled_f32));
         hipLaunchKernelGGL(kern, grid, dim3(TILE_T), lds, st, A, T, (float *)v, (float *)vs, (float *)x_stream, O);
     }
 }
@@ -3670,9 +3798,11 @@ static void launch_scatter_draws(const Ctx &c, hipStream_t st, const CollideArgs
 // collision.
 static void launch_forces_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca,
                                const double *f_ext, double dt, uint64_t *advance, double kT, int thermalize,
-                               uint64_t seed, const uint64_t *step_next, const void *x, void *xs, void *vs)
+                               uint64_t seed, const uint64_t *step_next, const void *x, void *xs, void *vs,
+                               bool solvent = true)
 {
-    const int64_t nchunks = (c.sys->n_solvent + PREP_CHUNK - 1) / PREP_CHUNK;
+    // solvent == false: the collision has binned the new solvent already
+    const int64_t nchunks = solvent ? (c.sys->n_solvent + PREP_CHUNK - 1) / PREP_CHUNK : 0;
     const dim3 g((unsigned)(c.sys->n_bodies + nchunks));
     const BodyDev bd = make_bodydev(bodies);
     const BodyGrid grid = body_grid(c, wca);
@@ -4045,8 +4175,12 @@ static void step_rnemd(const Ctx &c, hipStream_t st, const mpcd_step_args *a)
 // thermalizes and bins its sites for t+1; extra blocks bin the new solvent),
 // so step t+1 starts at its scan and its scatter clears the body-centre grid.
 // Centre-centre WCA only (site-site WCA has a force kernel of its own).
+//
+// Schedule 3: as schedule 2, but step t's collision bins the new solvent for
+// t+1 itself (it holds the new positions in registers), so the fused force
+// kernel runs its body blocks only.
 struct Overlap {
-    int mode;         // 1: side stream; 2: fused into the force kernel
+    int mode;         // 1: side stream; 2: fused into the force kernel; 3: 2 with the solvent binned by the collision
     hipStream_t side;
     hipEvent_t fork, join;
     bool pre_binned;  // this step's first kernel has run already (mode 1: its solvent part, joined by `join`)
@@ -4059,7 +4193,7 @@ static int overlap_mode(const mpcd_step_args *a)
     if (!m || !a->v_out || a->reorder_every != 0 || a->sys->n_bodies == 0 || a->sys->n_sites == 0 ||
         a->sys->n_solvent == 0)
         return 0;
-    if (m == 2 && a->par.wca.mode == 2) return 0;
+    if (m >= 2 && a->par.wca.mode == 2) return 0;
     return m;
 }
 
@@ -4075,7 +4209,7 @@ static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
     const mpcd_params &p = a->par;
     const Ctx c = make_ctx(s, a->ws, &p.tune);
     hipStream_t st = (hipStream_t)stream;
-    const bool fused_in = ov && ov->mode == 2 && ov->pre_binned;  // first kernel ran in the last step's
+    const bool fused_in = ov && ov->mode >= 2 && ov->pre_binned;  // first kernel ran in the last step's
     if (ov && ov->pre_binned) {
         if (ov->mode == 1) {
             launch_prep(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->x, a->xs, a->vs, p.wca, 1);
@@ -4089,6 +4223,11 @@ static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
                                  nullptr);
     uint64_t *step_next = at<uint64_t>(c.ws, c.L.step_next);
     if (ov && ov->bin_next) A.step_next = step_next;
+    if (ov && ov->bin_next && ov->mode == 3) {  // the collision bins the new solvent for the next step
+        A.bin_counts = at<u64>(c.ws, c.L.counts);
+        A.bin_cellid = at<int32_t>(c.ws, c.L.cellid);
+        A.bin_slot = at<int32_t>(c.ws, c.L.slot);
+    }
     if (p.fuse_stream) A.F = make_forcing(p.g, p.dt);
     const BodyGrid grid = body_grid(c, p.wca);
     int32_t *clear_grid = fused_in ? grid.count : nullptr;
@@ -4117,9 +4256,9 @@ static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
         return launch_check();
     }
     launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt, p.wca);
-    if (ov && ov->bin_next && ov->mode == 2)  // forces, kick and the next step's first kernel in one launch
+    if (ov && ov->bin_next && ov->mode >= 2)  // forces, kick and the next step's first kernel in one launch
         launch_forces_prep(c, st, &a->bodies, p.wca, p.f_ext, p.dt, a->d_step, p.kT, p.thermalize, p.seed, step_next,
-                           a->x_out, a->xs, a->vs);
+                           a->x_out, a->xs, a->vs, ov->mode == 2);
     else
         launch_forces(c, st, &a->bodies, p.wca, p.f_ext, p.dt, 1, a->d_step);
     step_rnemd(c, st, a);

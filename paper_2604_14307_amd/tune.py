@@ -26,7 +26,7 @@ FILLS = (40, 55, 70, 85)
 ITEMS = {"f32": (2, 4, 8), "f64": (1, 2, 4)}
 DRAW_CELLS = (1, 2)
 DRAWS_INLINE = (0, 1)
-OVERLAP = (0, 1, 2)
+OVERLAP = (0, 1, 2, 3)
 
 
 def arch(device) -> str:

@@ -123,7 +123,7 @@ def test_tile_shape_follows_the_tuning():
     t = lib.MpcdTune(8, 85, 2)
     assert L.mpcd_tile_shape(C.byref(s), C.byref(t), out) == 0
     assert list(out)[:3] == [8, 256, 2048]
-    for bad in ((3, 0, 0), (0, 5, 0), (0, 101, 0), (0, 0, 17), (1, 0, 0), (0, 0, 0, 2), (0, 0, 0, 0, 3)):
+    for bad in ((3, 0, 0), (0, 5, 0), (0, 101, 0), (0, 0, 17), (1, 0, 0), (0, 0, 0, 2), (0, 0, 0, 0, 4)):
         assert L.mpcd_tile_shape(C.byref(s), C.byref(lib.MpcdTune(*bad)), out) == -1
     s64 = sys_desc(prec=lib.MPCD_F64)
     assert L.mpcd_tile_shape(C.byref(s64), C.byref(lib.MpcdTune(1, 0, 0)), out) == 0 and out[0] == 1

@@ -322,22 +322,27 @@ def test_graph_replay_matches_eager(out_of_place):
         gg.release_graph()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode,items,fill", [(1, 0, 0), (2, 0, 0), (3, 0, 0), (3, 1, 100)])
 @pytest.mark.parametrize("prec,exchange", [("f64", False), ("f32", False), ("f32", True)])
-def test_overlapped_graph_matches_eager(prec, exchange, mode):
+def test_overlapped_graph_matches_eager(prec, exchange, mode, items, fill):
     """Graphs that run each next step's first kernel during the current step
     (mode 1: its solvent binning on a second stream beside the body update;
-    mode 2: inside the force kernel) give the state of the same steps run one
-    by one (bodies with sites, WCA, out of place; with the exchange appended)."""
-    wl = W.suspension((14, 18, 11), 5, 4, 2.0, 60, 5.0, seed=91)
+    mode 2: inside the force kernel; mode 3: the solvent binned by the
+    collision, the sites in the force kernel) give the state of the same steps
+    run one by one (bodies with sites, WCA, out of place; with the exchange
+    appended).  The full-capacity tiles (fill 100) overflow often, so the
+    collision's per-cell fallback bins its tiles too."""
+    # density 8: the full-capacity tiles hold 8 cells' worth on average
+    wl = W.suspension((14, 18, 11), 8 if fill else 5, 4, 2.0, 60, 5.0, seed=91)
     par = W.srd_params(91, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
-    say("overlapped graph %s exchange=%s mode %d" % (prec, exchange, mode))
+    say("overlapped graph %s exchange=%s mode %d items %d fill %d" % (prec, exchange, mode, items, fill))
     ge, gg = gpu_system(wl, par, prec=prec), gpu_system(wl, par, prec=prec)
-    # both scatter kernels clear the body-centre grid in mode 2: the one fused
-    # with the draws pass (FP32 here) and the one without it
-    inl = 0 if (mode == 2 and prec == "f32") else 1
-    ge.set_tuning(0, 0, 0, inl, 0)
-    gg.set_tuning(0, 0, 0, inl, mode)
+    # both scatter kernels clear the body-centre grid in modes 2 and 3: the one
+    # fused with the draws pass (FP32 here) and the one without it
+    inl = 0 if (mode >= 2 and prec == "f32") else 1
+    it = (2 if prec == "f32" else 1) if items else 0
+    ge.set_tuning(it, fill, 0, inl, 0)
+    gg.set_tuning(it, fill, 0, inl, mode)
     for g in (ge, gg):
         g.body_forces()
         if exchange:
