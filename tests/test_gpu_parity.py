@@ -534,6 +534,49 @@ def test_full_size_suspension_bit_exact_few_steps():
     run_parity(wl, par, 3)
 
 
+@pytest.mark.parametrize("ci,prec", [(1, "f64"), (1, "f32"), (3, "f32")])
+def test_full_size_in_the_bench_launch_configuration(ci, prec):
+    """The benchmark workloads (the 60^3 suspension; the 512 batched
+    replicas, 17.4M solvent) run the way the bench times them: the committed
+    tuned launch shape and schedule for the workload, steps as replays of a
+    captured HIP graph on a side stream.  FP64: bit for bit against the oracle
+    after 4 steps.  FP32: bit for bit against 4 eager steps of the same shape
+    (the schedules change the order of launches, never the arithmetic)."""
+    import os
+    from paper_2604_14307_amd import tune
+    wl, par = W.config(ci)[:2]
+    cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2604_14307_amd",
+                         "tuning_gfx950.json")
+    g = gpu_system(wl, par, prec=prec)
+    g.body_forces()
+    e = tune.autotune(g, cache_path=cache, write=False)
+    assert e["cached"]
+    say("full size workload %d %s, tuned shape %s" % (ci, prec, list(e["tune"])))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g.graph(2)
+        g.graph_launch()
+        g.graph_launch()
+        torch.cuda.synchronize()
+        g.release_graph()
+    assert g.status() == 0
+    if prec == "f64":
+        o = oracle.OracleSystem(wl, par)
+        o.body_forces()
+        for n in range(4):
+            assert o.step(n) == 0
+        assert_same(o, g.download()[0], where="graph of the tuned shape")
+    else:
+        ge = gpu_system(wl, par, prec=prec)
+        ge.set_tuning(*(list(e["tune"][:4]) + [0]))
+        ge.body_forces()
+        ge.step(4)
+        a, b = ge.download()[0], g.download()[0]
+        for k in STATE_KEYS:
+            assert np.array_equal(a[k], b[k]), k
+        assert ge.status() == 0
+
+
 # ---------------------------------------------------------------------------
 # FP32 form
 
