@@ -2,12 +2,14 @@
 
 The step's launch shapes (``mpcd_tune``: items per thread of a collision
 tile, the fill that sets the cells per tile, cells per lane of the per-cell
-draws, draws inside the collision or in a pass of their own, and the overlap
-of each next step's solvent binning with the current step's body update in
-graphs) change how work is split over blocks and streams, never the results.
+draws, draws inside the collision or in a pass of their own, and the schedule
+of each next step's first kernel in graphs: on a second stream beside the body
+update, inside the force kernel, or with the solvent binned by the collision)
+change how work is split over blocks and streams, never the results.
 The tuner times HIP-graph replays of a few steps of the caller's own system
-for each distinct collision shape, then the overlap on top of the fastest one
-(the two choices touch different kernels), restores the state after every
+for each distinct collision shape, then each schedule on top of the fastest
+shape (a schedule changes the kernels around the collision's own work, and its
+cost ranks the same across shapes), restores the state after every
 trial, keeps the fastest shape on the system and records it in a JSON cache
 keyed by the GPU architecture, the precision and the system sizes, so a later
 run on the same workload reuses it without timing.
