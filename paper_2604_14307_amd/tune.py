@@ -8,8 +8,7 @@ update, inside the force kernel, or with the solvent binned by the collision)
 change how work is split over blocks and streams, never the results.
 The tuner times HIP-graph replays of a few steps of the caller's own system
 for each distinct collision shape, then each schedule on top of the fastest
-shape (a schedule changes the kernels around the collision's own work, and its
-cost ranks the same across shapes), restores the state after every
+shape only (which bounds the tuning time), restores the state after every
 trial, keeps the fastest shape on the system and records it in a JSON cache
 keyed by the GPU architecture, the precision and the system sizes, so a later
 run on the same workload reuses it without timing.
