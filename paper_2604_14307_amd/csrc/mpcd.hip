@@ -928,15 +928,51 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(u64 *counts, int64_t C, int64_t
     flag(status, st);
 }
 
-// Position of particle k (cell gc, slot within its kind) in the permutation:
-// solvent first, then the cell's sites.
-__device__ __forceinline__ int64_t perm_pos(const int32_t *cell_start, const int32_t *site_start, int64_t N,
-                                            int64_t k, int32_t gc, int32_t slot)
+// The scatter of BIN_ITEMS entries per thread, k = kb + j BIN_T + t, each to
+// its position in the permutation: its cell's start plus its slot, the
+// solvent first and then the cell's sites.  Every entry's cell and slot loads
+// are issued before the first dependent load (its cell's start), so a thread
+// waits for two round trips, not two per entry.
+__device__ __forceinline__ void scatter_items(int64_t kb, int64_t NT, int64_t N, const int32_t *cellid,
+                                              const int32_t *slot, const int32_t *cell_start,
+                                              const int32_t *site_start, int32_t *perm, uint32_t &st)
 {
-    const int32_t b = cell_start[gc];
-    if (k < N) return (int64_t)b + slot;
-    const int32_t nsol = (cell_start[gc + 1] - b) - (site_start[gc + 1] - site_start[gc]);
-    return (int64_t)b + nsol + slot;
+    int32_t gc[BIN_ITEMS], sl[BIN_ITEMS], b[BIN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int64_t k = kb + (int64_t)j * BIN_T + threadIdx.x;
+        gc[j] = -1;
+        sl[j] = 0;
+        if (k < NT) {
+            gc[j] = cellid[k];
+            sl[j] = slot[k];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) b[j] = gc[j] >= 0 ? cell_start[gc[j]] : 0;
+    // every position before the first store (a store would otherwise count
+    // in the waits for the later entries' loads)
+    int64_t pos[BIN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j) {
+        const int64_t k = kb + (int64_t)j * BIN_T + threadIdx.x;
+        pos[j] = -1;
+        if (k >= NT) continue;
+        if (gc[j] < 0) {  // only with a corrupted binning
+            st |= ST_BINERR;
+            continue;
+        }
+        pos[j] = (int64_t)b[j] + sl[j];
+        if (k >= N)  // sites follow the cell's solvent
+            pos[j] += (cell_start[gc[j] + 1] - b[j]) - (site_start[gc[j] + 1] - site_start[gc[j]]);
+        if (pos[j] < 0 || pos[j] >= NT) {
+            st |= ST_BINERR;
+            pos[j] = -1;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < BIN_ITEMS; ++j)
+        if (pos[j] >= 0) perm[pos[j]] = (int32_t)(kb + (int64_t)j * BIN_T + threadIdx.x);
 }
 
 // grid_count (when set): the body-centre grid, cleared here for the step's
@@ -950,15 +986,7 @@ __global__ __launch_bounds__(BIN_T) void k_bin_scatter(int64_t NT, int64_t N, co
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; grid_count && q < grid_n;
          q += (int64_t)gridDim.x * blockDim.x)
         grid_count[q] = 0;
-#pragma unroll
-    for (int j = 0; j < BIN_ITEMS; ++j) {
-        const int64_t k = (int64_t)blockIdx.x * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
-        if (k < NT) {
-            const int64_t pos = perm_pos(cell_start, site_start, N, k, cellid[k], slot[k]);
-            if (pos >= 0 && pos < NT) perm[pos] = (int32_t)k;
-            else st |= ST_BINERR;
-        }
-    }
+    scatter_items((int64_t)blockIdx.x * BIN_CHUNK, NT, N, cellid, slot, cell_start, site_start, perm, st);
     flag(status, st);
 }
 
@@ -1181,12 +1209,18 @@ __global__ __launch_bounds__(BIN_T) void k_scatter_draws(int64_t NT, const int32
          q += (int64_t)gridDim.x * blockDim.x)
         grid_count[q] = 0;
     if ((int)blockIdx.x >= ndraw) {
+        // one entry after the other here: issuing all loads first (scatter_items)
+        // measured slower beside the draw blocks of this launch
         const int64_t b = (int64_t)blockIdx.x - ndraw;
 #pragma unroll
         for (int j = 0; j < BIN_ITEMS; ++j) {
             const int64_t k = b * BIN_CHUNK + (int64_t)j * BIN_T + threadIdx.x;
             if (k < NT) {
-                const int64_t pos = perm_pos(A.cell_start, A.site_start, A.s.N, k, cellid[k], slot[k]);
+                const int32_t gc = cellid[k];
+                const int32_t c0 = A.cell_start[gc];
+                int64_t pos = (int64_t)c0 + slot[k];
+                if (k >= A.s.N)  // sites follow the cell's solvent
+                    pos += (A.cell_start[gc + 1] - c0) - (A.site_start[gc + 1] - A.site_start[gc]);
                 if (pos >= 0 && pos < NT) perm[pos] = (int32_t)k;
                 else st |= ST_BINERR;
             }
