@@ -7,8 +7,8 @@ of each next step's first kernel in graphs: on a second stream beside the body
 update, inside the force kernel, or with the solvent binned by the collision)
 change how work is split over blocks and streams, never the results.
 The tuner times HIP-graph replays of a few steps of the caller's own system
-for each distinct collision shape, then each schedule on top of the fastest
-shape only (which bounds the tuning time), restores the state after every
+for each distinct collision shape, then each schedule on top of the two
+fastest shapes (which bounds the tuning time), restores the state after every
 trial, keeps the fastest shape on the system and records it in a JSON cache
 keyed by the GPU architecture, the precision and the system sizes, so a later
 run on the same workload reuses it without timing.
@@ -28,6 +28,7 @@ ITEMS = {"f32": (2, 4, 8), "f64": (1, 2, 4)}
 DRAW_CELLS = (1, 2)
 DRAWS_INLINE = (0, 1)
 OVERLAP = (0, 1, 2, 3)
+SCHEDULE_SHAPES = 2
 
 
 def arch(device) -> str:
@@ -111,12 +112,14 @@ def autotune(g, steps: int = 20, repeats: int = 3, cache_path: str | None = None
     for cand in candidates(g):
         g.restore(snap)
         results.append((time_shape(g, cand, steps, repeats), cand))
-    if g.B > 0 and g.S > 0 and g.out_of_place and steps >= 2:  # the overlap needs sites and out-of-place graphs
-        best = min(results)[1]
-        for ov in OVERLAP[1:]:
-            g.restore(snap)
-            cand = best[:4] + (ov,)
-            results.append((time_shape(g, cand, steps, repeats), cand))
+    if g.B > 0 and g.S > 0 and g.out_of_place and steps >= 2:  # the schedules need sites and out-of-place graphs
+        # each schedule on the SCHEDULE_SHAPES fastest shapes: a schedule moves
+        # work into or out of the collision, which can reorder close shapes
+        for _, best in sorted(results)[:SCHEDULE_SHAPES]:
+            for ov in OVERLAP[1:]:
+                g.restore(snap)
+                cand = best[:4] + (ov,)
+                results.append((time_shape(g, cand, steps, repeats), cand))
     g.restore(snap)
     torch.cuda.synchronize(g.device)
     if g.status() != 0:
