@@ -38,10 +38,16 @@
  *  - Random numbers: Philox4x64-10, key (seed, purpose), counter
  *    (step, entity, replica0 + system, call); purpose 0 grid shift (entity 0),
  *    1 a cell's collision axis and thermostat Gamma variate (entity = cell
- *    index within its system: a call's words as eight 32-bit halves, high
- *    half first; axis attempts on halves (0,1) and (2,3), a variate attempt
- *    on (4,5,6); calls until both are accepted), 3 site velocities (entity =
- *    site index within its system).
+ *    index within its system; a call's four words read as eight 32-bit
+ *    halves, high half first.  The axis comes from call 0 without rejection:
+ *    half 0 gives z uniform in (-1, 1), half 1 the azimuth phi (Archimedes),
+ *    n = (sqrt(1-z^2) cos phi, sqrt(1-z^2) sin phi, z).  While the variate is
+ *    pending, each call's halves 2 and 3 give a Box-Muller normal pair and
+ *    halves 4 and 5 the uniforms of two Marsaglia-Tsang tests, the cosine
+ *    normal first; calls continue until one test accepts, at most 64),
+ *    3 site velocities (entity = site index within its system; one call,
+ *    Box-Muller pairs from words (0, 1) and (2, 3), the second pair's sine
+ *    dropped).
  *  - Limits: total solvent + sites < 2^31; total cells < 2^31.
  *
  * Errors: 0 on success, else a negative code below; nothing is launched then.

@@ -83,8 +83,6 @@ static void draw(uint64_t seed, uint64_t purpose, uint64_t step, uint64_t entity
     orc_philox(ctr, key, w);
 }
 
-/* Uniform in [0,1) from the top 53 bits of a word. */
-
 /* ------------------------------------------------------------------------- */
 /* Natural logarithm from the atanh series:                                   */
 /*   x = f 2^e, f in (sqrt2/2, sqrt2],  ln x = e ln2 + 2 atanh((f-1)/(f+1)).  */

@@ -100,9 +100,10 @@ def test_cell_axes_uniform_on_sphere():
 
 
 def test_cell_axis_and_gamma_share_a_stream_independently():
-    """A cell's axis and thermostat variate come from the same calls (axis
-    halves 0-3, variate halves 4-6): the axis is the same whether or not the
-    variate is drawn, each is the one drawn alone, and the two are
+    """A cell's axis and thermostat variate come from the same calls (the
+    axis from call 0's halves 0 and 1, the variate's normal pair and test
+    uniforms from halves 2-5 of each call): the axis is the same whether or
+    not the variate is drawn, each is the one drawn alone, and the two are
     uncorrelated across cells."""
     n, k = 20000, 6.0
     ax, g, flags = oracle.cell_draws(23, 9, 1, k, n)
