@@ -1,25 +1,28 @@
 #!/usr/bin/env python
 """Throughput of the MPCD + rigid-body step on one MI355X.
 
-Headline workload: hard-sphere suspension, 60^3 cells (a = 1, periodic), 5
-solvent per cell (1,080,000 solvent), 191 rigid spheres of radius 3 with 200
-Fibonacci surface sites each (volume fraction 0.1), WCA between body centres
-(sigma 6, eps = kT), SRD 130 degrees, dt = 0.1, kT = 1 with the cell
-thermostat; synthetic seeded inputs (random sequential addition,
-Maxwell-Boltzmann velocities).
+Headline workload: 512 independent periodic replicas advanced together, cubic
+boxes with edges drawn uniformly from 12..24 cells (a = 1), 5 solvent per cell
+(17,376,750 solvent in all), one rigid sphere of radius 2 with 100 Fibonacci
+surface sites in each; SRD 130 degrees, dt = 0.1, kT = 1 with the cell
+thermostat; a random stream per replica; synthetic seeded inputs
+(Maxwell-Boltzmann velocities).  The headline value is the batched FP32 form
+(FP32 solvent/sites, exact int64 fixed-point cell sums, FP64 bodies); the
+plain FP64 form runs on the same workload beside it, with the ratio.
 
 One step = site thermalization, grid shift + counting sort, SRD collision
 (fused with solvent streaming), momentum transfer, rigid-body update.  Inputs
-are resident in HBM; the timed region replays a HIP graph of the steps.  The
-headline value is the FP32 form (FP32 solvent/sites, exact int64 fixed-point
-cell sums, FP64 bodies); the plain FP64 form is measured alongside, and both
-forms are also run on 512 independent replicas of uneven box size advanced
-together (the batched form).
+are resident in HBM; the timed region replays a HIP graph of the steps.
 
-The solvent is double-buffered: every step writes it out of place in cell
-order.  The dominant kernel (the fused collide + stream pass) is timed on its
-own with HIP events on its stream: back-to-back launches of mpcd_collide_drawn
-repeating the last step's pass (its inputs, cell lists and draws).
+The other workloads run after the headline, each with the roofline of its
+dominant kernel: the 60^3 hard-sphere suspension (1.08M solvent, 191 spheres),
+the 200^3 suspension at volume fraction 0.3 (80M solvent, 21,221 spheres) and
+the 128^3 complex-shape suspension (21M solvent, 2,000 cubes, rods and
+dumbbells with site-site WCA), each in FP32 and FP64.
+
+The dominant kernel is timed on its own with HIP events on its stream:
+back-to-back launches of mpcd_collide_drawn repeating the last step's collide
++ stream pass (its inputs, cell lists and draws).
 
 Prints one JSON line (N = 1).
 """
@@ -36,9 +39,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_14307_amd", "csrc", f) for f in ("mpcd.hip", "detrand.hpp")]
-# committed rocprofv3 counter summaries of the 60^3 FP32 kernels, by kernel family
-TRAFFIC_FILES = {"collide": os.path.join(ROOT, "profiles", "collide_f32_suspension60_traffic.txt"),
-                 "forces_prep": os.path.join(ROOT, "profiles", "forces_prep_f32_suspension60_traffic.txt")}
+# committed rocprofv3 counter summaries: profiles/<kernel>_<workload>_traffic.txt
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
@@ -62,11 +64,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when it covers another kernel or the kernel source has
-    changed since the counters were taken."""
-    path = TRAFFIC_FILES["forces_prep" if "forces_prep" in kernel else "collide"]
+def measured_traffic(kernel, wtag):
+    """HBM bytes per launch of `kernel` on workload `wtag` from the committed
+    rocprofv3 counter summary, or None when there is none, it covers another
+    kernel or the kernel source has changed since the counters were taken."""
+    path = os.path.join(PROFILES, "%s_%s_traffic.txt" % (kernel, wtag))
     if not os.path.exists(path):
         return None
     vals = {}
@@ -85,9 +87,10 @@ def measured_traffic(kernel):
 
 # Launch shapes: read from the committed cache of tuned shapes (one entry per
 # GPU architecture, precision and workload size); a workload missing from it
-# is tuned on the spot (untimed).  --retune tunes every workload again and
-# writes the cache given by --tune-cache.
-TUNE = {"on": True, "cache": os.path.join(ROOT, "paper_2604_14307_amd", "tuning_gfx950.json"), "write": None}
+# is tuned on the spot (untimed) and, with --tune-out, recorded in that file.
+# --retune tunes every workload again and writes the cache file it names.
+TUNE = {"on": True, "cache": os.path.join(ROOT, "paper_2604_14307_amd", "tuning_gfx950.json"), "write": None,
+        "out": None}
 
 
 def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None, tuning=None):
@@ -104,7 +107,12 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None,
         g.set_rnemd(*rnemd)
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
-    per = max(2, 2 * (steps // (2 * repeats)))  # out-of-place graphs hold an even number of steps
+    # out-of-place graphs hold an even number of steps: split the K timed
+    # steps into the most replays (at most `repeats`) of equal even length
+    if steps < 2 or steps % 2:
+        raise SystemExit("out-of-place graphs step in pairs: the number of timed steps must be even")
+    repeats = max(r for r in range(1, repeats + 1) if steps % r == 0 and (steps // r) % 2 == 0)
+    per = steps // repeats
     with torch.cuda.stream(side):
         for i in range(warmup):  # eager warmup (also pages in the code objects)
             g.step(1)
@@ -121,6 +129,11 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None,
         else:
             log("  launch shape %s (tile %s) tuned now: %.4f ms/step, default %.4f"
                 % (tuned["tune"], tuned["tile"], tuned["ms_per_step"], tuned["default_ms_per_step"]))
+            if TUNE["out"]:  # keep the new entry (merged into that file)
+                cache = tune.load_cache(TUNE["out"])
+                cache[tune.workload_key(g)] = {k: v for k, v in tuned.items() if k != "cached"}
+                with open(TUNE["out"], "w") as f:
+                    json.dump(cache, f, indent=1, sort_keys=True)
     with torch.cuda.stream(side):
         g.graph(per)
         g.graph_launch()  # one untimed replay
@@ -262,14 +275,17 @@ def host_cpu():
     return "%s, %d logical CPUs visible" % (model, os.cpu_count() or 0)
 
 
-def cpu_baseline(wl, par, steps):
+def cpu_baseline(systems, par, steps):
+    """The oracle as it stands, one thread: `steps` steps of every system."""
     import oracle
-    o = oracle.OracleSystem(wl, par)
-    o.body_forces()
+    os_ = [oracle.OracleSystem(wl, par, replica=r) for r, wl in enumerate(systems)]
+    for o in os_:
+        o.body_forces()
     t0 = time.perf_counter()
-    o.run(0, steps)
+    for o in os_:
+        o.run(0, steps)
     dt = time.perf_counter() - t0
-    return o.N * steps / dt, dt
+    return sum(o.N for o in os_) * steps / dt, dt
 
 
 def summary(r):
@@ -278,21 +294,50 @@ def summary(r):
             "systems": r["nsys"], "tuning": r["tuning"]}
 
 
+WORKLOADS = {1: "suspension60", 2: "suspension200", 3: "batched512", 4: "shapes128"}
+
+
+def roofline(r, prec_bytes, wtag):
+    """Roofline object of the run's dominant kernel: the collide + stream pass
+    (or the fused force + next-binning kernel when that launch is longer),
+    timed live; algorithmic bytes per launch over its average duration."""
+    N, S = r["N"], r["S"]
+    kname = collide_kernel_name(r["tuning"]["tile_items_cells_cap_tiles"][0],
+                                r["tuning"]["tune_items_fill_drawcells_inline_overlap"][3], prec_bytes == 8)
+    kern, ms, nbytes = kname, r["collide_ms"], collide_bytes(N, S, prec_bytes)
+    label = kname + (" (collide + stream + per-cell draws)" if kname.endswith("_d") else " (collide + stream)")
+    fp_ms = r.get("forces_prep_ms")
+    if fp_ms and fp_ms > ms:
+        kern, ms, nbytes = "k_forces_prep", fp_ms, forces_prep_bytes(N, S, prec_bytes)
+        label = kern + " (body forces + kick, then the next step's site thermalization and binning)"
+    ach = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": label, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(kern, wtag), "avg_launch_us": ms * 1e3,
+            "algorithmic_bytes_per_launch": nbytes}
+
+
+def form_summary(r, prec_bytes, wtag):
+    out = summary(r)
+    out["roofline"] = roofline(r, prec_bytes, wtag)
+    out["step_hbm_frac"] = step_bytes(r["N"], r["S"], prec_bytes) / (r["ms_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=25)
+    ap.add_argument("--steps", type=int, default=100, help="timed steps of the headline (batched FP32) form")
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--repeats", type=int, default=5, help="graph replays the K timed steps are split into")
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--batched-steps", type=int, default=150)
-    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--other-steps", type=int, default=40, help="timed steps of every other workload")
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="oracle steps over all replicas of the headline workload for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--large", action="store_true", help="also run the 200^3-cell, 80M-solvent suspension (FP32)")
-    ap.add_argument("--shapes", action="store_true",
-                    help="also run the 128^3 complex-shape suspension (site-site WCA), FP32 and FP64")
+    ap.add_argument("--only-headline", action="store_true", help="skip every other workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the 200^3-cell, 80M-solvent suspension")
+    ap.add_argument("--no-shapes", action="store_true", help="skip the 128^3 complex-shape suspension")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-harmonic", action="store_true",
                     help="skip the rigid-vs-harmonic time per tau on the paper's benchmark geometry")
@@ -302,6 +347,8 @@ def main():
                     help="tune every workload again (untimed) and write the shapes to this JSON cache")
     ap.add_argument("--no-rnemd", action="store_true",
                     help="skip the step time with the reverse nonequilibrium exchange appended")
+    ap.add_argument("--tune-out", metavar="PATH", default=None,
+                    help="record the shapes of workloads tuned on the spot (missing from the cache) in this JSON file")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this implementation drives a single MI355X "
@@ -312,31 +359,22 @@ def main():
         raise SystemExit("--steps must be at least --repeats")
     TUNE["on"] = not args.no_tune
     TUNE["write"] = args.retune
+    TUNE["out"] = args.tune_out
+    precs = ("f32",) if args.no_fp64 else ("f32", "f64")
 
     from paper_2604_14307_amd import workloads as W
-    wl, par, meta = W.config(1, kT_cell=1.0)
+    bsys, bpar, bmeta = W.config(3, kT_cell=1.0)
     res = {}
-    for prec in (("f32",) if args.no_fp64 else ("f32", "f64")):
-        log("suspension 60^3 %s: warmup %d, %d timed steps in %d replays" % (prec, args.warmup, args.steps,
-                                                                            args.repeats))
-        res[prec] = run_gpu(wl, par, prec, args.steps, args.warmup, args.repeats, args.kernel_reps)
+    for prec in precs:
+        log("batched replicas %s: warmup %d, %d timed steps in %d replays" % (prec, args.warmup, args.steps,
+                                                                             args.repeats))
+        res[prec] = run_gpu(bsys, bpar, prec, args.steps, args.warmup, args.repeats, args.kernel_reps)
         r = res[prec]
-        log("%s: %.4f ms/step (median replay %.4f), collide %.2f us" % (prec, r["ms_step"], r["ms_step_median"],
-                                                                        r["collide_ms"] * 1e3))
+        log("batched %s: %.4f ms/step (median replay %.4f), collide %.2f us" % (prec, r["ms_step"],
+                                                                               r["ms_step_median"],
+                                                                               r["collide_ms"] * 1e3))
     r32 = res["f32"]
     N, S = r32["N"], r32["S"]
-    ach = collide_bytes(N, S, 4) / (r32["collide_ms"] * 1e-3) / 1e9
-    # the roofline follows the longer launch of the two big kernels of the step
-    fp_ms = r32.get("forces_prep_ms")
-    if fp_ms and fp_ms > r32["collide_ms"]:
-        rl_kernel, rl_ms, rl_bytes = "k_forces_prep<float>", fp_ms, forces_prep_bytes(N, S, 4)
-        rl_label = rl_kernel + " (body forces + kick, then the next step's site thermalization and binning)"
-    else:
-        rl_kernel, rl_ms, rl_bytes = None, r32["collide_ms"], collide_bytes(N, S, 4)
-        rl_label = None
-    rl_ach = rl_bytes / (rl_ms * 1e-3) / 1e9
-    kname = collide_kernel_name(r32["tuning"]["tile_items_cells_cap_tiles"][0],
-                                r32["tuning"]["tune_items_fill_drawcells_inline_overlap"][3])
     out = {
         "metric": "solvent particle-steps/s",
         "value": r32["rate"],
@@ -350,56 +388,35 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "hard-sphere suspension: 60^3 cells, 1,080,000 solvent, 191 rigid spheres "
-                               "r=3 x 200 sites, WCA sigma=6, SRD 130 deg, dt=0.1, kT=1, cell thermostat",
-                   "solvent": N, "sites": S, "bodies": r32["B"], "cells": r32["C"],
+        "config": {"workload": "batched replicas: 512 periodic boxes, edges uniform in 12..24 cells, 5 solvent "
+                               "per cell (17,376,750 solvent), one rigid sphere r=2 x 100 sites each, SRD 130 deg, "
+                               "dt=0.1, kT=1, cell thermostat, a random stream per replica",
+                   "systems": r32["nsys"], "solvent": N, "sites": S, "bodies": r32["B"], "cells": r32["C"],
                    "form": "FP32 solvent/sites + int64 fixed-point cell sums + FP64 bodies; "
                            "HIP graph replays of the step"},
         "ms_per_step_median_replay": r32["ms_step_median"],
-        "roofline": {"bound": "hbm",
-                     "kernel": rl_label or (kname + (" (collide + stream + per-cell draws)" if kname.endswith("_d")
-                                                     else " (collide + stream)")),
-                     "achieved": rl_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": rl_ach / PEAK_HBM_GBS,
-                     "traffic": measured_traffic(rl_kernel or kname), "avg_launch_us": rl_ms * 1e3,
-                     "algorithmic_bytes_per_launch": rl_bytes},
-        "collide": {"kernel": kname, "avg_launch_us": r32["collide_ms"] * 1e3, "achieved_GBs": ach,
-                    "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(kname),
-                    "algorithmic_bytes_per_launch": collide_bytes(N, S, 4)},
+        "roofline": roofline(r32, 4, WORKLOADS[3]),
         "tuning": r32["tuning"],
         # the whole step against the HBM peak: algorithmic bytes of a step / step time
         "step_hbm_frac": step_bytes(N, S, 4) / (r32["ms_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS,
     }
     if "f64" in res:
-        r64 = res["f64"]
-        a64 = collide_bytes(N, S, 8) / (r64["collide_ms"] * 1e-3) / 1e9
-        out["fp64"] = dict(summary(r64), speedup_fp32_vs_fp64=r32["rate"] / r64["rate"],
-                           collide_us=r64["collide_ms"] * 1e3, collide_GBs=a64)
-    if not args.no_batched:
-        bsys, bpar, bmeta = W.config(3, kT_cell=1.0)
-        out["batched"] = {"workload": bmeta["name"]}
-        for prec in (("f32",) if args.no_fp64 else ("f32", "f64")):
-            log("batched replicas %s: %d timed steps" % (prec, args.batched_steps))
-            rb = run_gpu(bsys, bpar, prec, args.batched_steps, 10, 3, 0)
-            log("batched %s: %.4f ms/step" % (prec, rb["ms_step"]))
-            out["batched"][prec] = summary(rb)
-        if "f64" in out["batched"]:
-            out["batched"]["speedup_fp32_vs_fp64"] = out["batched"]["f32"]["value"] / out["batched"]["f64"]["value"]
-    if args.large:
-        lw, lpar, lmeta = W.config(2, kT_cell=1.0)
-        log("large suspension FP32: 50 timed steps")
-        rl = run_gpu(lw, lpar, "f32", 50, 5, 5, 5)
-        out["large"] = dict(summary(rl), workload=lmeta["name"], collide_us=rl["collide_ms"] * 1e3,
-                            collide_GBs=collide_bytes(rl["N"], rl["S"], 4) / (rl["collide_ms"] * 1e-3) / 1e9)
-        del lw
-    if args.shapes:
-        sw, spar, smeta = W.config(4, kT_cell=1.0)
-        out["shapes"] = {"workload": smeta["name"]}
-        for prec in ("f32", "f64"):
-            log("complex shapes %s: 50 timed steps" % prec)
-            rs = run_gpu(sw, spar, prec, 50, 6, 5, 0)
-            out["shapes"][prec] = summary(rs)
-        del sw
-    if not args.no_harmonic:
+        out["fp64"] = dict(form_summary(res["f64"], 8, WORKLOADS[3]),
+                           speedup_batched_fp32_vs_plain_fp64=r32["rate"] / res["f64"]["rate"])
+    others = [] if args.only_headline else [1] + ([] if args.no_large else [2]) + ([] if args.no_shapes else [4])
+    for ci in others:
+        wl, par, meta = W.config(ci, kT_cell=1.0)
+        block = {"workload": meta["name"]}
+        for prec in precs:
+            log("%s %s: %d timed steps" % (WORKLOADS[ci], prec, args.other_steps))
+            rr = run_gpu(wl, par, prec, args.other_steps, 4, 2, args.kernel_reps)
+            log("%s %s: %.4f ms/step, collide %.2f us" % (WORKLOADS[ci], prec, rr["ms_step"], rr["collide_ms"] * 1e3))
+            block[prec] = form_summary(rr, 4 if prec == "f32" else 8, WORKLOADS[ci])
+        if "f64" in block:
+            block["speedup_fp32_vs_fp64"] = block["f32"]["value"] / block["f64"]["value"]
+        out[WORKLOADS[ci]] = block
+        del wl
+    if not args.no_harmonic and not args.only_headline:
         hw, hpar, hmeta = W.paper_benchmark(0.1)
         res_h = {"workload": hmeta["name"],
                  "protocol": "rigid: one step per collision, dt = 0.1; harmonic: collision every 0.1 tau, "
@@ -416,16 +433,7 @@ def main():
         res_h["paper"] = "rigid (dt 0.1) vs harmonic (dt 0.002): nearly an order of magnitude, 1x A100, HOOMD-blue"
         out["rigid_vs_harmonic"] = res_h
         del hw
-    if not args.no_rnemd:
-        # slabs of width 1 at y = 0 and y = 30, up to 100 pairs per step (Sec. III.B)
-        rn = (0.0, 30.0, 1.0, 0.5, 100)
-        res_rn = {"workload": "the headline suspension with the exchange after every step: slabs y in [0, 1) "
-                              "and [30, 31), target |v_x| = 0.5, 100 pairs"}
-        for prec in (("f32",) if args.no_fp64 else ("f32", "f64")):
-            log("suspension 60^3 %s with the exchange: 100 timed steps" % prec)
-            rr = run_gpu(wl, par, prec, 100, 6, 2, 0, rnemd=rn)
-            res_rn["%s_ms_per_step" % prec] = rr["ms_step"]
-            res_rn["%s_overhead" % prec] = rr["ms_step"] / res[prec]["ms_step"] - 1.0
+    if not args.no_rnemd and not args.only_headline:
         vw, vpar, vmeta, vrn = W.paper_viscosity(0.1)
         pv = {"workload": vmeta["name"]}
         for label, rn_v in (("plain", None), ("exchange", vrn)):
@@ -433,17 +441,16 @@ def main():
             rv = run_gpu(vw, vpar, "f32", 40, 4, 2, 0, rnemd=rn_v)
             pv["f32_%s_ms_per_step" % label] = rv["ms_step"]
         pv["f32_overhead"] = pv["f32_exchange_ms_per_step"] / pv["f32_plain_ms_per_step"] - 1.0
-        res_rn["paper_geometry"] = pv
+        out["rnemd"] = {"paper_geometry": pv}
         del vw
-        out["rnemd"] = res_rn
     if args.copy_calibration:
         copy_calibration()
     if not args.no_cpu_baseline:
-        log("oracle on the host: %d steps" % args.cpu_steps)
-        rate, secs = cpu_baseline(wl, par, args.cpu_steps)
+        log("oracle on the host: %d steps of all %d replicas" % (args.cpu_steps, len(bsys)))
+        rate, secs = cpu_baseline(bsys, bpar, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d steps of the same 60^3 suspension (FP64 C oracle, one thread, %.1f s)"
-                                         % (args.cpu_steps, secs),
+                               "sample": "%d steps of all 512 replicas of the headline workload (FP64 C oracle, "
+                                         "one thread, %.1f s)" % (args.cpu_steps, secs),
                                "host": host_cpu()}
     print(json.dumps(out), flush=True)
 

@@ -134,40 +134,67 @@ def random_quaternions(rng, n: int) -> np.ndarray:
 
 
 def rsa_positions(rng, box, n: int, dmin: float, max_tries: int = 200000000) -> np.ndarray:
-    """Random sequential addition of n points, minimum-image distance >= dmin."""
+    """Random sequential addition of n points, minimum-image distance >= dmin.
+
+    Candidates are drawn in batches and tested against the points accepted
+    before the batch with array operations; the survivors are then accepted in
+    draw order against the batch's own earlier acceptances.  The points and
+    the generator's state afterwards are those of drawing and testing one
+    candidate at a time (the unused tail of the last batch is given back by
+    rewinding the generator and advancing it past the consumed draws)."""
     box = np.asarray(box, dtype=np.float64)
     ng = np.maximum(1, np.floor(box / dmin).astype(int))
     cw = box / ng
-    grid: dict = {}
+    kcap = 16  # points per grid cell: cells are at least dmin wide, fewer than 2 dmin
+    slots = np.full((int(ng[0]), int(ng[1]), int(ng[2]), kcap), -1, dtype=np.int64)
+    fill = np.zeros((int(ng[0]), int(ng[1]), int(ng[2])), dtype=np.int64)
+    offs = np.array([(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)])
     pts = np.zeros((n, 3))
-    placed, tries = 0, 0
+    d2min = dmin * dmin
+    state0 = rng.bit_generator.state
+    consumed, placed, tries, batch = 0, 0, 0, 16
     while placed < n:
-        tries += 1
+        cand = rng.random((batch, 3)) * box
+        g = np.floor(cand / cw).astype(int) % ng
+        nb = (g[:, None, :] + offs[None, :, :]) % ng
+        # (candidate, accepted point) pairs in the 27 neighbouring grid cells
+        fc = ((nb[..., 0] * ng[1] + nb[..., 1]) * ng[2] + nb[..., 2]).ravel()
+        f = fill.ravel()[fc]
+        rows = np.repeat(np.arange(len(fc)), f)
+        first_of = np.repeat(np.cumsum(f) - f, f)
+        pj = slots.reshape(-1)[fc[rows] * kcap + (np.arange(len(rows)) - first_of)]
+        ci = rows // len(offs)
+        dr = cand[ci] - pts[pj]
+        dr -= box * np.round(dr / box)
+        conflict = np.zeros(batch, dtype=bool)
+        conflict[ci[(dr * dr).sum(-1) < d2min]] = True
+        first = placed
+        used = batch
+        for i in np.flatnonzero(~conflict):
+            if first < placed:  # against the points accepted earlier in this batch
+                dq = cand[i] - pts[first:placed]
+                dq -= box * np.round(dq / box)
+                if ((dq * dq).sum(-1) < d2min).any():
+                    continue
+            gi = tuple(g[i])
+            if fill[gi] >= kcap:
+                raise RuntimeError("random sequential addition: grid cell over capacity")
+            slots[gi + (fill[gi],)] = placed
+            fill[gi] += 1
+            pts[placed] = cand[i]
+            placed += 1
+            if placed == n:
+                used = int(i) + 1
+                break
+        tries += used
+        consumed += 3 * used
         if tries > max_tries:
             raise RuntimeError("random sequential addition did not converge")
-        p = rng.random(3) * box
-        g = np.floor(p / cw).astype(int) % ng
-        ok = True
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    key = ((g[0] + dx) % ng[0], (g[1] + dy) % ng[1], (g[2] + dz) % ng[2])
-                    for j in grid.get(key, ()):
-                        dr = p - pts[j]
-                        dr -= box * np.round(dr / box)
-                        if dr @ dr < dmin * dmin:
-                            ok = False
-                            break
-                    if not ok:
-                        break
-                if not ok:
-                    break
-            if not ok:
-                break
-        if ok:
-            pts[placed] = p
-            grid.setdefault((g[0], g[1], g[2]), []).append(placed)
-            placed += 1
+        # about 32 acceptances per batch
+        rate = max(placed - first, 1) / used
+        batch = int(min(8192, max(16, 32.0 / rate)))
+    rng.bit_generator.state = state0
+    rng.bit_generator.advance(consumed)
     return pts
 
 
@@ -236,15 +263,20 @@ def make_system(ncell, density, templates, centres, quats, rng, kT: float = 1.0,
     L = np.array(ncell, dtype=np.float64) * a
     C = ncell[0] * ncell[1] * ncell[2]
     N = int(round(density * C)) if n_solvent is None else int(n_solvent)
-    x = rng.random((N, 3)) * L
+    if sort_solvent and N > 0:
+        # uniform positions stored by cell: every particle's cell is drawn
+        # uniformly, the cells are laid out in order (a counting sort of the
+        # draws), and each particle takes a uniform offset within its cell
+        cnt = np.bincount(rng.integers(0, C, N), minlength=C)
+        cid = np.repeat(np.arange(C, dtype=np.int64), cnt)
+        j = np.stack([cid % ncell[0], (cid // ncell[0]) % ncell[1], cid // (ncell[0] * ncell[1])], axis=1)
+        del cid, cnt
+        x = (j + rng.random((N, 3))) * a
+        del j
+    else:
+        x = rng.random((N, 3)) * L
     x = np.minimum(x, np.nextafter(L, 0))
     v = rng.normal(0.0, math.sqrt(kT / m), size=(N, 3))
-    if sort_solvent and N > 0:
-        j = np.floor(x / a).astype(np.int64)
-        j = np.minimum(j, np.array(ncell) - 1)
-        cid = (j[:, 2] * ncell[1] + j[:, 1]) * ncell[0] + j[:, 0]
-        order = np.argsort(cid, kind="stable")
-        x, v = x[order], v[order]
 
     B = len(templates)
     R = np.zeros((3, B)); q = np.zeros((4, B)); P = np.zeros((3, B)); p = np.zeros((4, B))

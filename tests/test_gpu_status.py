@@ -1,0 +1,118 @@
+"""The device status bits: each anomaly the kernels detect sets its sticky bit
+and the call still returns normally (no fault, no hang).
+
+Every case here stays within bounds by construction: a non-finite or
+out-of-box coordinate is binned into cell 0 of its system and flagged, a
+fixed-point overflow contributes nothing to its cell's sums and is flagged, and
+a site beyond the stated reach only narrows the neighbour search.  Each test
+runs one step (or one force evaluation) and reads the flags.  Where the oracle
+defines the same anomaly (a NaN, an escape), the GPU result is also compared
+with it bit for bit, NaNs included.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_14307_amd import lib as L
+from paper_2604_14307_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+STATE_KEYS = ("x", "v", "R", "img", "q", "P", "p", "F", "T", "xs", "vs")
+
+
+def gpu_system(*a, **k):
+    from paper_2604_14307_amd.sim import GPUSystem
+    return GPUSystem(*a, **k)
+
+
+def far_particle(wl, min_dist=4.5, lo=None):
+    """Index of a solvent particle far from the single sphere at the box centre
+    (so its cell holds no site), optionally with x >= lo."""
+    c = np.asarray(wl["R"])[:, 0]
+    d = np.linalg.norm(wl["x"] - c[:, None], axis=0)
+    ok = d > min_dist
+    if lo is not None:
+        ok &= wl["x"][0] >= lo
+    return int(np.flatnonzero(ok)[0])
+
+
+def with_velocity(wl, i, vel):
+    wl = dict(wl)
+    wl["v"] = wl["v"].copy()
+    wl["v"][:, i] = vel
+    return wl
+
+
+def same_as_oracle(o, gd):
+    for k in STATE_KEYS:
+        a, b = getattr(o, k), gd[k]
+        assert np.array_equal(a, b, equal_nan=True), k
+
+
+def test_nonfinite_velocity_sets_nonfinite():
+    wl, par, _ = W.config(0)
+    i = far_particle(wl)
+    wl = with_velocity(wl, i, (np.nan, 0.0, 0.0))
+    g = gpu_system(wl, par, prec="f64")
+    g.body_forces()
+    g.step(1)
+    flags = g.status()
+    assert flags & L.FLAG_NONFINITE
+    o = oracle.OracleSystem(wl, par)
+    o.body_forces()
+    assert o.step(0) & oracle.NONFINITE
+    gd = g.download()[0]
+    same_as_oracle(o, gd)
+    # the NaN reached its cell's members and nothing else
+    bad = ~np.isfinite(gd["v"]).all(0)
+    assert 2 <= bad.sum() <= 40
+    assert np.isfinite(gd["vs"]).all() and np.isfinite(gd["P"]).all()
+
+
+def test_escaping_particle_sets_escape():
+    """|v dt| larger than the box: one periodic correction leaves the particle
+    outside [0, L); the step flags it (and the next binning would put it in
+    cell 0), as the oracle does."""
+    wl, par, _ = W.config(0)
+    i = far_particle(wl, lo=6.0)
+    wl = with_velocity(wl, i, (150.0, 0.0, 0.0))  # moves 15 cells in a step of a 10-cell box
+    g = gpu_system(wl, par, prec="f64")
+    g.body_forces()
+    g.step(1)
+    flags = g.status()
+    assert flags & L.FLAG_ESCAPE
+    assert not flags & L.FLAG_NONFINITE
+    o = oracle.OracleSystem(wl, par)
+    o.body_forces()
+    assert o.step(0) & oracle.ESCAPE
+    same_as_oracle(o, g.download()[0])
+    g.step(1)  # the escaped particle is binned into cell 0 and flagged again
+    assert g.status() & L.FLAG_ESCAPE
+
+
+def test_fixed_point_overflow_sets_fixovf():
+    """FP32: a velocity with m v 2^32 beyond the int64 fixed-point range adds
+    nothing to its cell's sums and sets FIXOVF; the step completes."""
+    wl, par, _ = W.config(0)
+    i = far_particle(wl)
+    wl = with_velocity(wl, i, (2.0e9, 0.0, 0.0))
+    g = gpu_system(wl, par, prec="f32")
+    g.body_forces()
+    g.step(1)
+    flags = g.status()
+    assert flags & L.FLAG_FIXOVF
+    gd = g.download()[0]
+    assert np.isfinite(gd["v"]).all() and np.isfinite(gd["P"]).all()
+
+
+def test_site_beyond_reach_sets_reach():
+    """Site-site WCA relies on a bound on the sites' distance from their body
+    centre; a site found beyond it sets REACH."""
+    wl = W.shapes((16, 16, 16), 2, 1, 1, 1, seed=31)
+    par = W.srd_params(31, kT_cell=1.0, wca=dict(W.wca_sites(), reach=1.0))  # the rod reaches 5
+    g = gpu_system(wl, par, prec="f64")
+    g.body_forces()
+    assert g.status() & L.FLAG_REACH
