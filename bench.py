@@ -93,15 +93,16 @@ TUNE = {"on": True, "cache": os.path.join(ROOT, "paper_2604_14307_amd", "tuning_
         "out": None}
 
 
-def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None, tuning=None):
+def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None, tuning=None, layout="dense"):
     """Time graph replays of the step.  tuning: None = autotune the launch
     shapes on this system first (untimed; unless disabled), else a fixed
-    (items, fill, draw_cells)."""
+    (items, fill, draw_cells).  layout "binned": the binned solvent layout
+    (no tunable shapes)."""
     import torch
     from paper_2604_14307_amd import tune
     from paper_2604_14307_amd.sim import GPUSystem
 
-    g = GPUSystem(systems, par, prec=prec, device="cuda:0")
+    g = GPUSystem(systems, par, prec=prec, device="cuda:0", layout=layout)
     g.body_forces()
     if rnemd is not None:
         g.set_rnemd(*rnemd)
@@ -117,7 +118,9 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None,
         for i in range(warmup):  # eager warmup (also pages in the code objects)
             g.step(1)
     tuned = None
-    if tuning is not None:
+    if layout == "binned":
+        pass
+    elif tuning is not None:
         g.set_tuning(*tuning)
     elif TUNE["on"]:
         if TUNE["write"]:
@@ -147,7 +150,20 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None,
         seg = [ev[r].elapsed_time(ev[r + 1]) for r in range(repeats)]
         kms = None
         fpms = None
-        if kernel_reps > 0:
+        if kernel_reps > 0 and layout == "binned":
+            # the current step's sites listed once, then back-to-back launches
+            # of the brick collision of that step (its inputs are left
+            # unchanged; each launch first clears the next step's region fills)
+            g.graph_launch()
+            g.binned_sites()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(side)
+            for _ in range(kernel_reps):
+                g.binned_collide()
+            b.record(side)
+            torch.cuda.synchronize()
+            kms = a.elapsed_time(b) / kernel_reps
+        elif kernel_reps > 0:
             # keep the GPU busy with one more replay while the host enqueues the
             # back-to-back launches, so launch latency is not counted; each
             # launch repeats the last step's collide + stream pass (same inputs,
@@ -181,10 +197,14 @@ def run_gpu(systems, par, prec, steps, warmup, repeats, kernel_reps, rnemd=None,
     return dict(ms=ms, steps=total_steps, ms_step=ms / total_steps,
                 ms_step_median=statistics.median(seg) / per, collide_ms=kms, forces_prep_ms=fpms,
                 rate=g.N * total_steps / (ms * 1e-3), N=g.N, S=g.S, B=g.B, C=g.C, nsys=g.nsys,
-                tuning=tuning_record(g, tuned))
+                tuning=tuning_record(g, tuned), layout=layout)
 
 
 def tuning_record(g, tuned):
+    if g.binned is not None:
+        b = g.binned
+        return {"layout": "binned", "bricks": int(b.nbricks), "capacity": int(b.capacity),
+                "members_per_thread": int(b.items)}
     t = g.tuning
     rec = {"tune_items_fill_drawcells_inline_overlap": [t.tile_items, t.tile_fill, t.draw_cells, t.draws_inline,
                                                          t.overlap],
@@ -297,11 +317,25 @@ def summary(r):
 WORKLOADS = {1: "suspension60", 2: "suspension200", 3: "batched512", 4: "shapes128"}
 
 
+def brick_bytes(N, S):
+    """Algorithmic bytes of one brick collision (FP32): each solvent
+    particle's position and velocity read and written once; each site's
+    position and velocity read, its mass read and its velocity written."""
+    return N * 4 * 3 * 4 + S * (3 * 4 + 3 * 4 + 8 + 3 * 4)
+
+
 def roofline(r, prec_bytes, wtag):
     """Roofline object of the run's dominant kernel: the collide + stream pass
     (or the fused force + next-binning kernel when that launch is longer),
     timed live; algorithmic bytes per launch over its average duration."""
     N, S = r["N"], r["S"]
+    if r.get("layout") == "binned":
+        kern, ms, nbytes = "k_brick_collide_f32", r["collide_ms"], brick_bytes(N, S)
+        ach = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "kernel": kern + " (binned layout: collide + stream + bin for the next step)",
+                "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                "traffic": measured_traffic(kern, wtag), "avg_launch_us": ms * 1e3,
+                "algorithmic_bytes_per_launch": nbytes}
     kname = collide_kernel_name(r["tuning"]["tile_items_cells_cap_tiles"][0],
                                 r["tuning"]["tune_items_fill_drawcells_inline_overlap"][3], prec_bytes == 8)
     kern, ms, nbytes = kname, r["collide_ms"], collide_bytes(N, S, prec_bytes)
@@ -335,6 +369,7 @@ def main():
                     help="oracle steps over all replicas of the headline workload for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-binned", action="store_true", help="skip the binned solvent layout (headline: dense)")
     ap.add_argument("--only-headline", action="store_true", help="skip every other workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 200^3-cell, 80M-solvent suspension")
     ap.add_argument("--no-shapes", action="store_true", help="skip the 128^3 complex-shape suspension")
@@ -360,20 +395,25 @@ def main():
     TUNE["on"] = not args.no_tune
     TUNE["write"] = args.retune
     TUNE["out"] = args.tune_out
-    precs = ("f32",) if args.no_fp64 else ("f32", "f64")
+    # forms: (name, precision, solvent layout); the headline is the first
+    forms = [("f32_binned", "f32", "binned"), ("f32", "f32", "dense")] + ([] if args.no_fp64 else
+                                                                        [("f64", "f64", "dense")])
+    if args.no_binned:
+        forms = forms[1:]
 
     from paper_2604_14307_amd import workloads as W
     bsys, bpar, bmeta = W.config(3, kT_cell=1.0)
     res = {}
-    for prec in precs:
-        log("batched replicas %s: warmup %d, %d timed steps in %d replays" % (prec, args.warmup, args.steps,
-                                                                             args.repeats))
-        res[prec] = run_gpu(bsys, bpar, prec, args.steps, args.warmup, args.repeats, args.kernel_reps)
-        r = res[prec]
-        log("batched %s: %.4f ms/step (median replay %.4f), collide %.2f us" % (prec, r["ms_step"],
-                                                                               r["ms_step_median"],
-                                                                               r["collide_ms"] * 1e3))
-    r32 = res["f32"]
+    for name, prec, layout in forms:
+        log("batched replicas %s: warmup %d, %d timed steps in at most %d replays" % (name, args.warmup, args.steps,
+                                                                                     args.repeats))
+        res[name] = run_gpu(bsys, bpar, prec, args.steps, args.warmup, args.repeats, args.kernel_reps,
+                            layout=layout)
+        r = res[name]
+        log("batched %s: %.4f ms/step (median replay %.4f), dominant kernel %.2f us"
+            % (name, r["ms_step"], r["ms_step_median"], r["collide_ms"] * 1e3))
+    head = forms[0][0]
+    r32 = res[head]
     N, S = r32["N"], r32["S"]
     out = {
         "metric": "solvent particle-steps/s",
@@ -392,28 +432,30 @@ def main():
                                "per cell (17,376,750 solvent), one rigid sphere r=2 x 100 sites each, SRD 130 deg, "
                                "dt=0.1, kT=1, cell thermostat, a random stream per replica",
                    "systems": r32["nsys"], "solvent": N, "sites": S, "bodies": r32["B"], "cells": r32["C"],
-                   "form": "FP32 solvent/sites + int64 fixed-point cell sums + FP64 bodies; "
-                           "HIP graph replays of the step"},
+                   "form": "FP32 solvent/sites + int64 fixed-point cell sums + FP64 bodies; %s solvent layout; "
+                           "HIP graph replays of the step" % r32["layout"]},
         "ms_per_step_median_replay": r32["ms_step_median"],
         "roofline": roofline(r32, 4, WORKLOADS[3]),
         "tuning": r32["tuning"],
         # the whole step against the HBM peak: algorithmic bytes of a step / step time
         "step_hbm_frac": step_bytes(N, S, 4) / (r32["ms_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS,
     }
+    for name, prec, layout in forms[1:]:
+        out[name] = form_summary(res[name], 4 if prec == "f32" else 8, WORKLOADS[3])
     if "f64" in res:
-        out["fp64"] = dict(form_summary(res["f64"], 8, WORKLOADS[3]),
-                           speedup_batched_fp32_vs_plain_fp64=r32["rate"] / res["f64"]["rate"])
+        out["speedup_batched_fp32_vs_plain_fp64"] = r32["rate"] / res["f64"]["rate"]
     others = [] if args.only_headline else [1] + ([] if args.no_large else [2]) + ([] if args.no_shapes else [4])
     for ci in others:
         wl, par, meta = W.config(ci, kT_cell=1.0)
         block = {"workload": meta["name"]}
-        for prec in precs:
-            log("%s %s: %d timed steps" % (WORKLOADS[ci], prec, args.other_steps))
-            rr = run_gpu(wl, par, prec, args.other_steps, 4, 2, args.kernel_reps)
-            log("%s %s: %.4f ms/step, collide %.2f us" % (WORKLOADS[ci], prec, rr["ms_step"], rr["collide_ms"] * 1e3))
-            block[prec] = form_summary(rr, 4 if prec == "f32" else 8, WORKLOADS[ci])
+        for name, prec, layout in forms:
+            log("%s %s: %d timed steps" % (WORKLOADS[ci], name, args.other_steps))
+            rr = run_gpu(wl, par, prec, args.other_steps, 4, 2, args.kernel_reps, layout=layout)
+            log("%s %s: %.4f ms/step, dominant kernel %.2f us" % (WORKLOADS[ci], name, rr["ms_step"],
+                                                                 rr["collide_ms"] * 1e3))
+            block[name] = form_summary(rr, 4 if prec == "f32" else 8, WORKLOADS[ci])
         if "f64" in block:
-            block["speedup_fp32_vs_fp64"] = block["f32"]["value"] / block["f64"]["value"]
+            block["speedup_fp32_vs_fp64"] = block[forms[0][0]]["value"] / block["f64"]["value"]
         out[WORKLOADS[ci]] = block
         del wl
     if not args.no_harmonic and not args.only_headline:
@@ -421,15 +463,17 @@ def main():
         res_h = {"workload": hmeta["name"],
                  "protocol": "rigid: one step per collision, dt = 0.1; harmonic: collision every 0.1 tau, "
                              "50 velocity-Verlet steps of 0.002 between collisions (Sec. II.B.1)"}
-        for prec in ("f64", "f32"):
-            log("paper geometry, rigid %s: 20 timed steps" % prec)
-            rr = run_gpu(hw, hpar, prec, 20, 6, 2, 0)
-            res_h["rigid_%s_ms_per_tau" % prec] = rr["ms_step"] * 10.0
+        for name, prec, layout in (("f64", "f64", "dense"), ("f32", "f32", "dense"), ("f32_binned", "f32", "binned")):
+            log("paper geometry, rigid %s: 20 timed steps" % name)
+            rr = run_gpu(hw, hpar, prec, 20, 6, 2, 0, layout=layout)
+            res_h["rigid_%s_ms_per_tau" % name] = rr["ms_step"] * 10.0
         log("paper geometry, harmonic FP64: 10 timed collision periods")
         hper = run_harmonic(hw, hpar, 0.002, 50, 10, 3)
         res_h["harmonic_f64_ms_per_tau"] = hper * 10.0
         res_h["speedup_rigid_f64_vs_harmonic_f64"] = res_h["harmonic_f64_ms_per_tau"] / res_h["rigid_f64_ms_per_tau"]
         res_h["speedup_rigid_f32_vs_harmonic_f64"] = res_h["harmonic_f64_ms_per_tau"] / res_h["rigid_f32_ms_per_tau"]
+        res_h["speedup_rigid_f32_binned_vs_harmonic_f64"] = (res_h["harmonic_f64_ms_per_tau"]
+                                                            / res_h["rigid_f32_binned_ms_per_tau"])
         res_h["paper"] = "rigid (dt 0.1) vs harmonic (dt 0.002): nearly an order of magnitude, 1x A100, HOOMD-blue"
         out["rigid_vs_harmonic"] = res_h
         del hw

@@ -205,7 +205,96 @@ typedef struct {
      * see mpcd_rnemd_exchange; rnemd_dp is its device accumulator. */
     const struct mpcd_rnemd_s *rnemd;
     double *rnemd_dp;
+    /* Binned solvent layout (NULL: the dense layout above).  When set, x, v,
+     * tag and x_out, v_out, tag_out are binned solvent arrays of
+     * binned->capacity slots each ([3][capacity], [3][capacity],
+     * [capacity]); see mpcd_binned_layout. */
+    const struct mpcd_binned_s *binned;
 } mpcd_step_args;
+
+/* Binned solvent layout, a storage form of the solvent in which one step of
+ * the collision (Sec. II.A) reads and writes each solvent particle once.
+ *
+ * Each system's cells are grouped into bricks of up to 8 x 8 x 4 cells
+ * (smaller bricks for denser systems; narrower at the far faces of the box).
+ * The solvent arrays hold one region of fixed capacity per brick: on a step
+ * with index t, a solvent particle is stored in the region of the brick of
+ * its cell on step t's shifted grid, in no particular order within the
+ * region.  The step collides each brick's particles and sites in one block
+ * and writes each new solvent particle straight into the region of its brick
+ * on step t+1's grid, so the binned arrays are double-buffered (x, v, tag ->
+ * x_out, v_out, tag_out, swapped by the caller after every step, as in the
+ * out-of-place dense form).  Region fills are kept in the binned workspace
+ * per step parity (the parity of *d_step), which is why the caller's swap
+ * must follow every step.  A region whose capacity (mean occupancy + 6
+ * standard deviations + 16) is exceeded spills into a shared list of 8192
+ * entries; beyond that MPCD_FLAG_BINERR is set and the state is invalid.
+ * The surface sites are listed per brick by the thermalization of the same
+ * step (sites beyond a brick's list spill into a second shared list).
+ * Results are identical to the dense form's in identity order (the same
+ * per-cell sums, draws and rounding).  FP32 only: other precisions return
+ * MPCD_ENOTSUP from the step; no reverse nonequilibrium exchange.
+ *
+ * Host fields are filled by mpcd_binned_layout; ws and ws_bytes are the
+ * caller's device buffer for the brick tables, fills, site lists and
+ * overflow lists (allocated by the caller, >= 256-byte aligned). */
+typedef struct mpcd_binned_s {
+    void *ws;            /* device: binned workspace                          */
+    size_t ws_bytes;     /* bytes of ws (>= the ws_bytes the layout reports)  */
+    int64_t nbricks;     /* host: bricks over all systems                     */
+    int64_t capacity;    /* host: slots of one set of binned solvent arrays   */
+    int64_t site_slots;  /* host: site list entries over all bricks           */
+    int32_t items;       /* host: members per thread of a brick block         */
+} mpcd_binned;
+
+/* Plan of the binned layout (host only; no device work).  ncell: host
+ * [3*nsys] cells per axis of each system; solv_off, site_off_sys: host
+ * [nsys+1] offsets of each system's solvent and sites.  Fills every field of
+ * *out except ws (out->ws_bytes: the bytes the binned workspace needs).
+ * MPCD_EINVAL for inconsistent sizes or a system too dense for a brick. */
+int mpcd_binned_layout(const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_off,
+                       const int64_t *site_off_sys, mpcd_binned *out);
+
+/* Write the brick tables of the layout into b->ws and clear its fills and
+ * overflow counters.  The host arrays are those given to mpcd_binned_layout.
+ * Synchronous (a blocking copy of the tables); call once before the first
+ * pack. */
+int mpcd_binned_init(void *stream, const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_off,
+                     const int64_t *site_off_sys, const mpcd_binned *b);
+
+/* Dense solvent (x, v: [3N] prec, tag: [N] identities or NULL = index) into
+ * the binned arrays xb, vb, tagb for the step *d_step (its grid shift, Sec.
+ * II.A).  Clears that step parity's fills first. */
+int mpcd_binned_pack(void *stream, const mpcd_sys *sys, const void *x, const void *v, const int32_t *tag, void *xb,
+                     void *vb, int32_t *tagb, uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes,
+                     const mpcd_binned *b);
+
+/* Binned solvent of the step *d_step back to dense arrays in identity order:
+ * x[:, id], v[:, id] of the particle with identity id, tag[id] = id.  The
+ * binned arrays and fills are left unchanged. */
+int mpcd_binned_unpack(void *stream, const mpcd_sys *sys, const void *xb, const void *vb, const int32_t *tagb, void *x,
+                       void *v, int32_t *tag, const uint64_t *d_step, void *ws, size_t ws_bytes,
+                       const mpcd_binned *b);
+
+/* The first kernel of a step of the binned layout on its own: the sites of
+ * step *d_step placed and thermalized (Eqs. (5) and (7), as sites_thermalize)
+ * and listed in the bricks of their cells on that step's grid (Sec. II.A),
+ * after clearing the site lists.  Followed by mpcd_binned_collide it gives
+ * the step's collision; mpcd_step runs both itself (with clear lists), so do
+ * not call it before mpcd_step.  args as for mpcd_step, with args->binned
+ * set; MPCD_EINVAL without it. */
+int mpcd_binned_sites(void *stream, const mpcd_step_args *args);
+
+/* The collision of one step of the binned layout alone (Sec. II.A, with the
+ * sites as heavy solvent, Sec. II.B.2): collide, stream and bin the solvent
+ * of step *d_step from x, v, tag into x_out, v_out, tag_out (the next step's
+ * regions, whose fills it clears first), and write the sites' new velocities
+ * in place.  It needs that step's sites thermalized and listed (as mpcd_step
+ * does first) and leaves the input fills, the site lists and the step counter
+ * unchanged, so it can be launched again on the same input (the sites then
+ * enter with the velocities it wrote).  args as for mpcd_step, with
+ * args->binned set; MPCD_EINVAL without it. */
+int mpcd_binned_collide(void *stream, const mpcd_step_args *args);
 
 /* Workspace bytes for sys (host-side sizes only).  The workspace holds the cell
  * counts and starts, the per-particle cell/slot/permutation, the per-step grid

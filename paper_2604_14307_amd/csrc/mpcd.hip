@@ -19,6 +19,10 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "../../include/mpcd.h"
 #include "detrand.hpp"
 
@@ -1968,6 +1972,108 @@ MPCD_COLLIDE_PAIR(k_collide_tiled_f64_i4_d, , double, 4, 1)
 // lanes then write v_j = (V - Vt) + (omega - omega_t) x d_j + vt_j.
 // Block 0 also draws the step's grid shifts.
 
+// ---------------------------------------------------------------------------
+// Binned solvent layout: definitions shared by the site binning (inside the
+// thermalization) and the brick kernels further below.
+//
+// Each system's cells are grouped into bricks of BX x BY x BZ cells (powers of
+// two, chosen per system from its density; narrower at the far faces).  The
+// solvent arrays hold one region of fixed capacity per brick, and a step's
+// solvent lies in the region of the brick of its cell on that step's shifted
+// grid.  The surface sites of each brick are listed in the brick's site slots
+// (filled by the thermalization of the same step).  A region or site list that
+// overflows spills into a shared overflow list.  Region fills are counted per
+// step parity: the step with index t reads the counts of parity t & 1 and its
+// writers count into parity (t + 1) & 1.
+struct BrickInfo {
+    int64_t off;      // first slot of the brick's solvent region
+    int32_t cap;      // region capacity
+    int32_t sys;      // system of the brick
+    int32_t soff;     // first site slot
+    int16_t scap;     // site slot capacity
+    int16_t org[3];   // first cell of the brick within its system
+    uint8_t dim[3];   // cells along each axis
+    uint8_t pad;
+};
+static_assert(sizeof(BrickInfo) == 32, "brick table entry");
+
+constexpr int BIN_OVF_CAP = 8192;  // solvent overflow entries per parity
+// control words of the binned workspace
+enum { BC_OVF0 = 1, BC_OVF1 = 2, BC_SOVF = 3, BC_WORDS = 16 };
+
+struct BinnedDev {
+    const BrickInfo *brick;  // [nbricks]
+    const int32_t *sys_bb;   // [nsys + 1] first brick of each system
+    const int32_t *sys_bg;   // [6 nsys] log2 of the brick extent (3), bricks per axis (3)
+    int32_t *cnt;            // [2 nbricks] solvent per region, by step parity
+    int32_t *scnt;           // [nbricks] sites per brick
+    int32_t *sslot;          // site slots: site index
+    int32_t *ctrl;           // [BC_WORDS]
+    int32_t *ovf_dest;       // [2 BIN_OVF_CAP] overflow entries: destination brick,
+    int32_t *ovf_tag;        // [2 BIN_OVF_CAP] identity,
+    void *ovf_xv;            // [2][6][BIN_OVF_CAP] position and velocity (prec)
+    int32_t *sovf;           // [2 sovf_cap]: (brick, site) pairs
+    int64_t nbricks, cap;    // bricks; slots of one set of solvent arrays
+    int32_t sovf_cap;
+};
+
+// Cell coordinates of a position on a shifted grid (as the binning computes
+// them) and the brick of that cell; returns the brick index.
+template <typename Real>
+__device__ __forceinline__ int32_t brick_of_pos(const SysDev &s, const BinnedDev &bn, int r, Real p0, Real p1, Real p2,
+                                                const double sh[3], int j[3], uint32_t &st)
+{
+    const int nx = s.ncell[3 * r], ny = s.ncell[3 * r + 1], nz = s.ncell[3 * r + 2];
+    j[0] = axis_cell(p0, sh[0], s.a, s.inv_a, nx, st);
+    j[1] = axis_cell(p1, sh[1], s.a, s.inv_a, ny, st);
+    j[2] = axis_cell(p2, sh[2], s.a, s.inv_a, nz, st);
+    const int32_t *g = bn.sys_bg + 6 * r;
+    return bn.sys_bb[r] + ((j[2] >> g[2]) * g[4] + (j[1] >> g[1])) * g[3] + (j[0] >> g[0]);
+}
+
+// Site binning of the binned layout inside the thermalization: the site's
+// brick on the step's grid, one device atomic per run of equal bricks within
+// a wave, a slot in the brick's site list or, when that is full, an entry of
+// the site overflow list.
+struct BrickSiteBin {
+    BinnedDev bn;
+};
+
+template <typename Real>
+__device__ __forceinline__ void brick_bin_site(const SysDev &s, const BrickSiteBin &bb, int r, bool valid, int64_t j,
+                                               const Real xr[3], const double *bsh, uint32_t &st)
+{
+    const BinnedDev &bn = bb.bn;
+    int jc[3];
+    const double sh[3] = {bsh[0], bsh[1], bsh[2]};
+    const int32_t b = valid ? brick_of_pos<Real>(s, bn, r, xr[0], xr[1], xr[2], sh, jc, st) : -1;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int32_t prev = __shfl_up(b, 1, 64);
+    const bool head = (lane == 0) || (prev != b);
+    const unsigned long long heads = __ballot(head);
+    const int hl = 63 - __clzll(heads & le);
+    const unsigned long long above = heads & ~le;
+    const int nh = above ? (__ffsll((long long)above) - 1) : 64;
+    int base = 0;
+    if (head && b >= 0) base = atomicAdd(&bn.scnt[b], nh - hl);
+    base = __shfl(base, hl, 64);
+    if (b < 0) return;
+    const int rank = base + (lane - hl);
+    const BrickInfo bi = bn.brick[b];
+    if (rank < bi.scap) {
+        bn.sslot[bi.soff + rank] = (int32_t)j;
+    } else {
+        const int e = atomicAdd(&bn.ctrl[BC_SOVF], 1);
+        if (e < bn.sovf_cap) {
+            bn.sovf[2 * e] = b;
+            bn.sovf[2 * e + 1] = (int32_t)j;
+        } else {
+            st |= ST_BINERR;
+        }
+    }
+}
+
 constexpr int WAVE = 64;
 constexpr int BODY_T = 256;
 static_assert(BODY_T == BIN_T, "k_prep bins solvent with BODY_T-thread blocks");
@@ -2006,8 +2112,7 @@ template <typename Real>
 __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, double kT, int thermalize,
                                 uint64_t seed, uint64_t step, Real *xs, Real *vs, double *site_d, double *vpre,
                                 const double *bsh, unsigned long long *counts, int32_t *cellid, int32_t *slot,
-                                ThermLds &lds,
-                                uint32_t &st)
+                                const BrickSiteBin *bbin, ThermLds &lds, uint32_t &st)
 {
     double *sh = lds.sh, *sacc = lds.sacc, *dvw = lds.dvw;
     const int t = threadIdx.x;
@@ -2064,6 +2169,8 @@ __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, d
                 slot[s.N + j] = bb + ((threadIdx.x & 63) - hl);
                 cellid[s.N + j] = gc;
             }
+        } else if (bbin) {  // binned layout: the brick's site list (all lanes take part)
+            brick_bin_site<Real>(s, *bbin, r, j < j1, j, xr, bsh, st);
         }
         ordered_add(sh, (int)((j1 - c0) < BODY_T ? (j1 - c0) : BODY_T), acc);
         __syncthreads();
@@ -2118,7 +2225,7 @@ __global__ __launch_bounds__(BODY_T) void k_thermalize(SysDev s, BodyDev bd, dou
     if (b >= s.B) return;
     uint32_t st = 0;
     thermalize_body<Real>(s, bd, b, kT, thermalize, seed, *d_step, xs, vs, site_d, vpre, nullptr, nullptr, nullptr,
-                          nullptr, lds, st);
+                          nullptr, nullptr, lds, st);
     flag(status, st);
 }
 
@@ -2133,8 +2240,8 @@ __device__ __forceinline__ void prep_body_block(const SysDev &s, const BodyDev &
 {
     const int rb = find_sys_wave(s.body_off, s.nsys, b);  // every lane of the block is here
     if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0)) shift_of(s, seed, step, rb, bsh);
-    thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid, slot, th,
-                          st);
+    thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, counts, cellid, slot, nullptr,
+                          th, st);
 }
 
 // Solvent role of the first kernel (a whole BODY_T block): bin the PREP_CHUNK
@@ -2445,11 +2552,32 @@ __global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double
 
 // Momentum transfer fused with the first half of the body update (one block
 // per body); J and K are also written out.
+// After the brick collision of step t (the step index is still t): clear
+// that step's region fills, the site counts and the input overflow counters,
+// ready for step t + 1's site binning and step t + 1's writers (which count
+// into this parity).  The brick kernel only reads them, so it can be
+// launched again on the same input.
+__device__ __forceinline__ void binned_finish(const BinnedDev &bn, uint64_t step)
+{
+    const int par = (int)(step & 1);
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn.nbricks; q += nt) {
+        bn.cnt[(int64_t)par * bn.nbricks + q] = 0;
+        bn.scnt[q] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        bn.ctrl[BC_OVF0 + par] = 0;
+        bn.ctrl[BC_SOVF] = 0;
+    }
+}
+
 template <typename Real>
 __global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd, const Real *vs, const double *site_d,
                                                            const double *vpre, double *J, double *K, double dt,
-                                                           BodyGrid grid, SiteFrames fr, uint32_t *status)
+                                                           BodyGrid grid, SiteFrames fr, uint32_t *status,
+                                                           BinnedDev bn, const uint64_t *d_step)
 {
+    if (d_step) binned_finish(bn, *d_step);  // binned layout: the brick collision's fills are spent
     __shared__ double sh[6 * SH_PAD];
     __shared__ double jk[6];
     __shared__ double pose[7];
@@ -3438,6 +3566,545 @@ int check_ws(const mpcd_sys *s, const void *ws, size_t ws_bytes)
     return MPCD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Binned step: one block per brick.
+//
+// The block loads its brick's members in one coalesced sweep: the region's
+// solvent (position, velocity, identity), the sites listed for the brick and
+// any overflow entries addressed to it, kept in registers (ITEMS per thread).
+// Each member's cell on this step's grid is local to the brick, so the cell
+// sums are complete in LDS (FP32: exact int64 fixed-point sums with LDS
+// atomics).  One lane per cell draws the cell's axis and thermostat variate
+// and forms u and lambda R; every member is rotated, the sites' velocities are
+// written back to the site arrays, and the solvent is streamed and written
+// straight into the region of its brick on the NEXT step's grid: the block
+// counts its members per destination brick in LDS, takes one device atomic
+// per distinct destination for the base slot, and writes each member at base
+// + rank.  The solvent therefore crosses HBM once per step (read and written
+// once), with no cell lists, scan, scatter or permutation.  A brick with more
+// members than the block holds in registers takes a two-pass path (sums, then
+// a second load to rotate and write).
+constexpr int BRICK_T = 512;     // threads of a brick block
+constexpr int BRICK_MAXC = 256;  // cells per brick at most (one lane per cell)
+constexpr int DEST_HT = 64;      // destination-brick hash slots per block
+constexpr int BRICK_OVL = 512;   // overflow entries per brick and kind a block takes
+constexpr int BRICK_ITEMS_F32 = 4;
+
+template <typename Real> struct BrickArgs {
+    SysDev s;
+    BinnedDev bn;
+    const Real *x, *v;  // binned solvent of this step: [3][cap] each
+    const int32_t *tag; // [cap]
+    Real *xo, *vo;      // binned solvent of the next step
+    int32_t *tago;
+    Real *xs, *vs;      // sites [3][S]
+    const double *site_m;
+    double cos_a, sin_a, kT_cell, dt;
+    uint64_t seed;
+    const uint64_t *d_step;
+    uint64_t *step_next;  // when set, block 0 stores the step index + 1 there
+    double *shift_out;    // when set, block 0 stores the step's grid shifts there
+    int32_t *grid_clear;  // body-centre grid cleared for this step's insertions
+    int64_t grid_n;
+    Forcing F;
+    uint32_t *status;
+};
+
+struct BrickLds32 {
+    unsigned long long acc[5 * BRICK_MAXC];
+    int cnt[BRICK_MAXC];
+    float par[12 * BRICK_MAXC];
+    int32_t dkey[DEST_HT], dcnt[DEST_HT], dcap[DEST_HT];
+    int64_t doff[DEST_HT];
+    int32_t lovf[BRICK_OVL], lsovf[BRICK_OVL];
+    double sh[3], sh1[3];
+    int hdr[8];
+};
+
+// Member i of the brick: region solvent, listed sites, then overflow solvent
+// and overflow sites; id is the solvent identity, or -(site + 1).
+template <typename Real>
+__device__ __forceinline__ bool brick_member(const BrickArgs<Real> &A, const BrickInfo &bi, int par_in, int i,
+                                             const int *hdr, const int32_t *lovf, const int32_t *lsovf, Real p[3],
+                                             Real w[3], int32_t &id, uint32_t &st)
+{
+    const int64_t cap = A.bn.cap, S = A.s.S;
+    const int nreg = hdr[0], nsite = hdr[1], novf = hdr[2];
+    int64_t j = -1;
+    if (i < nreg) {
+        const int64_t q = bi.off + i;
+        p[0] = A.x[q]; p[1] = A.x[cap + q]; p[2] = A.x[2 * cap + q];
+        w[0] = A.v[q]; w[1] = A.v[cap + q]; w[2] = A.v[2 * cap + q];
+        id = A.tag[q];
+        return true;
+    }
+    if (i < nreg + nsite) {
+        j = A.bn.sslot[bi.soff + (i - nreg)];
+    } else if (i < nreg + nsite + novf) {
+        const int64_t e = (int64_t)par_in * BIN_OVF_CAP + lovf[i - nreg - nsite];
+        const Real *o = (const Real *)A.bn.ovf_xv + (int64_t)par_in * 6 * BIN_OVF_CAP;
+        const int64_t k = lovf[i - nreg - nsite];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            p[d] = o[d * BIN_OVF_CAP + k];
+            w[d] = o[(3 + d) * BIN_OVF_CAP + k];
+        }
+        id = A.bn.ovf_tag[e];
+        return true;
+    } else {
+        j = A.bn.sovf[2 * lsovf[i - nreg - nsite - novf] + 1];
+    }
+    if (j < 0 || j >= S) {
+        st |= ST_BINERR;
+        return false;
+    }
+    p[0] = A.xs[j]; p[1] = A.xs[S + j]; p[2] = A.xs[2 * S + j];
+    w[0] = A.vs[j]; w[1] = A.vs[S + j]; w[2] = A.vs[2 * S + j];
+    id = -(int32_t)j - 1;
+    return true;
+}
+
+// Local cell of a member on this step's grid (-1 and BINERR when the member is
+// not in this brick: only with a corrupted state).
+template <typename Real>
+__device__ __forceinline__ int brick_local_cell(const SysDev &s, const BinnedDev &bn, const BrickInfo &bi, int64_t b,
+                                                const Real p[3], const double *sh, uint32_t &st)
+{
+    int jc[3];
+    const double shv[3] = {sh[0], sh[1], sh[2]};
+    const int32_t bb = brick_of_pos<Real>(s, bn, bi.sys, p[0], p[1], p[2], shv, jc, st);
+    if (bb != b) {
+        st |= ST_BINERR;
+        return -1;
+    }
+    return ((jc[2] - bi.org[2]) * bi.dim[1] + (jc[1] - bi.org[1])) * bi.dim[0] + (jc[0] - bi.org[0]);
+}
+
+// Per-cell FP32 parameters from the exact fixed-point sums (u and lambda R
+// rounded to float), the draws made here from the cell's stream.
+__device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const BrickInfo &bi, int c, int n,
+                                                      const unsigned long long *acc, double ca, double sa,
+                                                      double kT_cell, uint64_t seed, uint64_t step, float *par,
+                                                      uint32_t &st)
+{
+    const int r = bi.sys;
+    const int cx = c % bi.dim[0], cy = (c / bi.dim[0]) % bi.dim[1], cz = c / (bi.dim[0] * bi.dim[1]);
+    const int nx = s.ncell[3 * r], ny = s.ncell[3 * r + 1];
+    const uint64_t cl = (uint64_t)(((int64_t)(bi.org[2] + cz) * ny + (bi.org[1] + cy)) * nx + (bi.org[0] + cx));
+    CellDraw D;
+    st |= cell_draw(seed, step, cl, s.replica0 + (uint64_t)r, kT_cell > 0.0, 0.5 * (double)(3 * (n - 1)), D);
+    long long q[5];
+#pragma unroll
+    for (int z = 0; z < 5; ++z) q[z] = (long long)acc[5 * c + z];
+    const Rot R = rotation(D.n, ca, sa);
+    const double Md = (double)q[0];
+    const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
+    double lam = 1.0;
+    if (kT_cell > 0.0) {
+        const double P0 = (double)q[1] * 0x1p-32, P1 = (double)q[2] * 0x1p-32, P2 = (double)q[3] * 0x1p-32;
+        const double E = 0.5 * ((double)q[4] * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
+        if (E > 0.0) lam = sqrt((kT_cell * D.g) / E);
+    }
+    par[0] = (float)u0; par[1] = (float)u1; par[2] = (float)u2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) par[3 + 3 * i + j] = (float)(lam * R.R[i][j]);
+}
+
+// Rotation of one FP32 member about its cell's mean velocity (cells of fewer
+// than two members are left alone).
+__device__ __forceinline__ void brick_rotate_f32(const float *par, float w[3], uint32_t &st)
+{
+    const float dl[3] = {w[0] - par[0], w[1] - par[1], w[2] - par[2]};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        w[d] = par[d] + ((par[3 + 3 * d] * dl[0] + par[4 + 3 * d] * dl[1]) + par[5 + 3 * d] * dl[2]);
+        if (!(w[d] - w[d] == 0.0f)) st |= ST_NONFINITE;
+    }
+}
+
+// Streaming of a solvent member (position and velocity in place) and its
+// brick on the next step's grid.
+template <typename Real>
+__device__ __forceinline__ int32_t brick_stream(const BrickArgs<Real> &A, int r, const Real L[3], Real p[3], Real w[3],
+                                                const double *sh1, uint32_t &st)
+{
+    const Real dtr = (Real)A.dt;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        Real y = p[d] + w[d] * dtr;
+        if (A.F.on) {
+            y = y + (Real)A.F.h[d];
+            w[d] = w[d] + (Real)A.F.gdt[d];
+        }
+        p[d] = Prec<Real>::wrap(y, L[d], st);
+    }
+    int jc[3];
+    const double shv[3] = {sh1[0], sh1[1], sh1[2]};
+    return brick_of_pos<Real>(A.s, A.bn, r, p[0], p[1], p[2], shv, jc, st);
+}
+
+// Write one new solvent member into slot `slot` of brick b's region of the
+// output, or into the overflow list when the region is full.
+template <typename Real>
+__device__ __forceinline__ void brick_put(const BrickArgs<Real> &A, int par_out, int32_t b, int64_t off, int32_t cap,
+                                          int32_t slot, const Real p[3], const Real w[3], int32_t id, uint32_t &st)
+{
+    const int64_t C = A.bn.cap;
+    if (slot < cap) {
+        const int64_t q = off + slot;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            A.xo[d * C + q] = p[d];
+            A.vo[d * C + q] = w[d];
+        }
+        A.tago[q] = id;
+        return;
+    }
+    const int e = atomicAdd(&A.bn.ctrl[BC_OVF0 + par_out], 1);
+    if (e >= BIN_OVF_CAP) {
+        st |= ST_BINERR;
+        return;
+    }
+    Real *o = (Real *)A.bn.ovf_xv + (int64_t)par_out * 6 * BIN_OVF_CAP;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        o[d * BIN_OVF_CAP + e] = p[d];
+        o[(3 + d) * BIN_OVF_CAP + e] = w[d];
+    }
+    A.bn.ovf_tag[(int64_t)par_out * BIN_OVF_CAP + e] = id;
+    A.bn.ovf_dest[(int64_t)par_out * BIN_OVF_CAP + e] = b;
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) void k_brick_collide_f32(BrickArgs<float> A)
+{
+    __shared__ BrickLds32 L;
+    const int t = threadIdx.x;
+    const SysDev &s = A.s;
+    const BinnedDev &bn = A.bn;
+    const uint64_t step = *A.d_step;
+    const int par_in = (int)(step & 1), par_out = par_in ^ 1;
+    uint32_t st = 0;
+    if (blockIdx.x == 0) {
+        if (t == 0 && A.step_next) *A.step_next = step + 1;
+        if (A.shift_out) draw_shifts(s, A.seed, step, A.shift_out);
+    }
+    for (int64_t q = (int64_t)blockIdx.x * BRICK_T + t; A.grid_clear && q < A.grid_n; q += (int64_t)gridDim.x * BRICK_T)
+        A.grid_clear[q] = 0;
+    const int64_t b = tile_of_block((int)bn.nbricks);
+    if (b < bn.nbricks) {
+        const BrickInfo bi = bn.brick[b];
+        const int r = bi.sys;
+        const int ncb = bi.dim[0] * bi.dim[1] * bi.dim[2];
+        if (t == 0) {
+            const int nr = bn.cnt[(int64_t)par_in * bn.nbricks + b], ns = bn.scnt[b];
+            L.hdr[0] = min(nr, bi.cap);
+            L.hdr[1] = min(ns, bi.scap);
+            L.hdr[2] = 0;
+            L.hdr[3] = 0;
+            L.hdr[4] = min(bn.ctrl[BC_OVF0 + par_in], BIN_OVF_CAP);
+            L.hdr[5] = min(bn.ctrl[BC_SOVF], bn.sovf_cap);
+        }
+        if (t == 64) shift_of(s, A.seed, step, r, L.sh);
+        if (t == 128) shift_of(s, A.seed, step + 1, r, L.sh1);
+        for (int c = t; c < ncb; c += BRICK_T) {
+            L.cnt[c] = 0;
+#pragma unroll
+            for (int z = 0; z < 5; ++z) L.acc[5 * c + z] = 0ull;
+        }
+        if (t < DEST_HT) {
+            L.dkey[t] = -1;
+            L.dcnt[t] = 0;
+        }
+        __syncthreads();
+        // overflow entries addressed to this brick (the lists are nearly always empty)
+        for (int e = t; e < L.hdr[4]; e += BRICK_T)
+            if (bn.ovf_dest[(int64_t)par_in * BIN_OVF_CAP + e] == (int32_t)b) {
+                const int k = atomicAdd(&L.hdr[2], 1);
+                if (k < BRICK_OVL) L.lovf[k] = e;
+            }
+        for (int e = t; e < L.hdr[5]; e += BRICK_T)
+            if (bn.sovf[2 * e] == (int32_t)b) {
+                const int k = atomicAdd(&L.hdr[3], 1);
+                if (k < BRICK_OVL) L.lsovf[k] = e;
+            }
+        __syncthreads();
+        if (L.hdr[2] > BRICK_OVL || L.hdr[3] > BRICK_OVL) {
+            st |= ST_BINERR;
+            __syncthreads();
+            if (t == 0) {
+                L.hdr[2] = min(L.hdr[2], BRICK_OVL);
+                L.hdr[3] = min(L.hdr[3], BRICK_OVL);
+            }
+            __syncthreads();
+        }
+        const int nmem = L.hdr[0] + L.hdr[1] + L.hdr[2] + L.hdr[3];
+        const float Lb[3] = {(float)((double)s.ncell[3 * r] * s.a), (float)((double)s.ncell[3 * r + 1] * s.a),
+                             (float)((double)s.ncell[3 * r + 2] * s.a)};
+        if (nmem <= ITEMS * BRICK_T) {
+            float p[ITEMS][3], w[ITEMS][3];
+            int32_t id[ITEMS];
+            int lc[ITEMS];
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const int i = t + k * BRICK_T;
+                lc[k] = -1;
+                id[k] = 0;
+                if (i < nmem && brick_member<float>(A, bi, par_in, i, L.hdr, L.lovf, L.lsovf, p[k], w[k], id[k], st))
+                    lc[k] = 0;
+            }
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                if (lc[k] < 0) continue;
+                lc[k] = brick_local_cell<float>(s, bn, bi, b, p[k], L.sh, st);
+                if (lc[k] < 0) continue;
+                const double mk = id[k] >= 0 ? s.m : A.site_m[-(int64_t)id[k] - 1];
+                long long q[5];
+                fixed_terms(mk, w[k][0], w[k][1], w[k][2], q, st);
+                unsigned long long *acc = L.acc + 5 * lc[k];
+#pragma unroll
+                for (int z = 0; z < 5; ++z) atomicAdd(acc + z, (unsigned long long)q[z]);
+                atomicAdd(&L.cnt[lc[k]], 1);
+            }
+            __syncthreads();
+            for (int c = t; c < ncb; c += BRICK_T)
+                if (L.cnt[c] >= 2)
+                    brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, A.cos_a, A.sin_a, A.kT_cell, A.seed, step,
+                                          L.par + 12 * c, st);
+            __syncthreads();
+            int32_t dst[ITEMS], hs[ITEMS], rk[ITEMS];
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                dst[k] = -1;
+                hs[k] = -1;
+                rk[k] = 0;
+                if (lc[k] < 0) continue;
+                if (L.cnt[lc[k]] >= 2) brick_rotate_f32(L.par + 12 * lc[k], w[k], st);
+                if (id[k] < 0) {  // a site: its new velocity back to the site arrays
+                    const int64_t j = -(int64_t)id[k] - 1, S = s.S;
+                    A.vs[j] = w[k][0]; A.vs[S + j] = w[k][1]; A.vs[2 * S + j] = w[k][2];
+                    continue;
+                }
+                dst[k] = brick_stream<float>(A, r, Lb, p[k], w[k], L.sh1, st);
+                // count per destination brick in LDS (linear probing; a full
+                // table sends the member to its own device atomic)
+                uint32_t h = ((uint32_t)dst[k] * 2654435761u) >> (32 - 6);
+                for (int probe = 0; probe < DEST_HT; ++probe) {
+                    const int32_t old = atomicCAS(&L.dkey[h], -1, dst[k]);
+                    if (old == -1 || old == dst[k]) {
+                        hs[k] = (int)h;
+                        rk[k] = atomicAdd(&L.dcnt[h], 1);
+                        break;
+                    }
+                    h = (h + 1) & (DEST_HT - 1);
+                }
+            }
+            __syncthreads();
+            if (t < DEST_HT && L.dkey[t] >= 0) {  // one device atomic per destination brick
+                const int32_t db = L.dkey[t];
+                const BrickInfo di = bn.brick[db];
+                L.doff[t] = di.off;
+                L.dcap[t] = di.cap;
+                L.dcnt[t] = atomicAdd(&bn.cnt[(int64_t)par_out * bn.nbricks + db], L.dcnt[t]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                if (dst[k] < 0) continue;
+                if (hs[k] >= 0) {
+                    brick_put<float>(A, par_out, dst[k], L.doff[hs[k]], L.dcap[hs[k]], L.dcnt[hs[k]] + rk[k], p[k],
+                                     w[k], id[k], st);
+                } else {
+                    const BrickInfo di = bn.brick[dst[k]];
+                    const int slot = atomicAdd(&bn.cnt[(int64_t)par_out * bn.nbricks + dst[k]], 1);
+                    brick_put<float>(A, par_out, dst[k], di.off, di.cap, slot, p[k], w[k], id[k], st);
+                }
+            }
+        } else {
+            // more members than the block holds: sums over chunks of the
+            // member list, then a second load of each member to rotate it
+            for (int i = t; i < nmem; i += BRICK_T) {
+                float p[3], w[3];
+                int32_t id;
+                if (!brick_member<float>(A, bi, par_in, i, L.hdr, L.lovf, L.lsovf, p, w, id, st)) continue;
+                const int c = brick_local_cell<float>(s, bn, bi, b, p, L.sh, st);
+                if (c < 0) continue;
+                const double mk = id >= 0 ? s.m : A.site_m[-(int64_t)id - 1];
+                long long q[5];
+                fixed_terms(mk, w[0], w[1], w[2], q, st);
+#pragma unroll
+                for (int z = 0; z < 5; ++z) atomicAdd(L.acc + 5 * c + z, (unsigned long long)q[z]);
+                atomicAdd(&L.cnt[c], 1);
+            }
+            __syncthreads();
+            for (int c = t; c < ncb; c += BRICK_T)
+                if (L.cnt[c] >= 2)
+                    brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, A.cos_a, A.sin_a, A.kT_cell, A.seed, step,
+                                          L.par + 12 * c, st);
+            __syncthreads();
+            // second load: each member is read again before its own write (a
+            // site appears once in a brick's list)
+            for (int i = t; i < nmem; i += BRICK_T) {
+                float p[3], w[3];
+                int32_t id;
+                if (!brick_member<float>(A, bi, par_in, i, L.hdr, L.lovf, L.lsovf, p, w, id, st)) continue;
+                const int c = brick_local_cell<float>(s, bn, bi, b, p, L.sh, st);
+                if (c < 0) continue;
+                if (L.cnt[c] >= 2) brick_rotate_f32(L.par + 12 * c, w, st);
+                if (id < 0) {
+                    const int64_t j = -(int64_t)id - 1, S = s.S;
+                    A.vs[j] = w[0]; A.vs[S + j] = w[1]; A.vs[2 * S + j] = w[2];
+                    continue;
+                }
+                const int32_t db = brick_stream<float>(A, r, Lb, p, w, L.sh1, st);
+                const BrickInfo di = bn.brick[db];
+                const int slot = atomicAdd(&bn.cnt[(int64_t)par_out * bn.nbricks + db], 1);
+                brick_put<float>(A, par_out, db, di.off, di.cap, slot, p, w, id, st);
+            }
+        }
+    }
+    flag(A.status, st);
+}
+
+__global__ void k_binned_finish(BinnedDev bn, const uint64_t *d_step) { binned_finish(bn, *d_step); }
+
+// The site lists cleared, for a site listing launched on its own.
+__global__ void k_binned_clear_sites(BinnedDev bn)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn.nbricks; q += (int64_t)gridDim.x * blockDim.x)
+        bn.scnt[q] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) bn.ctrl[BC_SOVF] = 0;
+}
+
+// The next step's fills and output overflow counter cleared, for a brick
+// collision launched on its own (the step sequence has them clear already).
+__global__ void k_binned_clear_out(BinnedDev bn, const uint64_t *d_step)
+{
+    const int par = (int)((*d_step + 1) & 1);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn.nbricks; q += (int64_t)gridDim.x * blockDim.x)
+        bn.cnt[(int64_t)par * bn.nbricks + q] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) bn.ctrl[BC_OVF0 + par] = 0;
+}
+
+
+// Thermalization of each body's sites for the step and their binning into the
+// bricks' site lists (binned layout); one block per body.
+template <typename Real>
+__global__ __launch_bounds__(BODY_T) void k_therm_bin(SysDev s, BodyDev bd, BrickSiteBin bb, double kT, int thermalize,
+                                                      uint64_t seed, const uint64_t *d_step, Real *xs, Real *vs,
+                                                      double *site_d, double *vpre, uint32_t *status)
+{
+    __shared__ double bsh[3];
+    __shared__ ThermLds lds;
+    const int64_t b = blockIdx.x;
+    if (b >= s.B) return;
+    uint32_t st = 0;
+    const uint64_t step = *d_step;
+    const int r = find_sys_wave(s.body_off, s.nsys, b);  // every lane of the block is here
+    if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0)) shift_of(s, seed, step, r, bsh);
+    thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, nullptr, nullptr, nullptr,
+                          &bb, lds, st);
+    flag(status, st);
+}
+
+// Step t's body forces, second half kick and step-counter advance, then the
+// same block thermalizes its body's sites for step t + 1 and bins them into
+// the bricks' site lists (binned layout, graph schedule).
+template <typename Real>
+__global__ __launch_bounds__(BODY_T) void k_forces_therm_bin(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid,
+                                                             ExtForce E, double dt, uint64_t *advance_step,
+                                                             BrickSiteBin bb, double kT, int thermalize, uint64_t seed,
+                                                             const uint64_t *step_next, Real *xs, Real *vs,
+                                                             double *site_d, double *vpre, uint32_t *status)
+{
+    __shared__ double bsh[3];
+    __shared__ union {
+        ForceLds<BODY_T> f;
+        ThermLds th;
+    } lds;
+    if ((int64_t)blockIdx.x >= s.B) return;
+    body_forces_block<BODY_T>(s, bd, wca, grid, E, dt, 1, advance_step, status, lds.f);
+    __syncthreads();  // the kick is stored; the LDS is free
+    const uint64_t step = *step_next;
+    uint32_t st = 0;
+    const int r = find_sys_wave(s.body_off, s.nsys, blockIdx.x);
+    if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0)) shift_of(s, seed, step, r, bsh);
+    thermalize_body<Real>(s, bd, blockIdx.x, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, nullptr, nullptr,
+                          nullptr, &bb, lds.th, st);
+    flag(status, st);
+}
+
+// Dense solvent (x[3][N], v[3][N], identities) into the regions of the bricks
+// of its cells on the grid of the step *d_step.
+template <typename Real>
+__global__ void k_binned_pack(SysDev s, BinnedDev bn, uint64_t seed, const uint64_t *d_step, const Real *x,
+                              const Real *v, const int32_t *tag, Real *xb, Real *vb, int32_t *tagb, uint32_t *status)
+{
+    uint32_t st = 0;
+    const uint64_t step = *d_step;
+    const int par = (int)(step & 1);
+    BrickArgs<Real> A;
+    A.bn = bn;
+    A.xo = xb;
+    A.vo = vb;
+    A.tago = tagb;
+    const int64_t N = s.N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = find_sys(s.solv_off, s.nsys, i);
+        double sh[3];
+        shift_of(s, seed, step, r, sh);
+        const Real p[3] = {x[i], x[N + i], x[2 * N + i]}, w[3] = {v[i], v[N + i], v[2 * N + i]};
+        int jc[3];
+        const int32_t b = brick_of_pos<Real>(s, bn, r, p[0], p[1], p[2], sh, jc, st);
+        const BrickInfo bi = bn.brick[b];
+        const int slot = atomicAdd(&bn.cnt[(int64_t)par * bn.nbricks + b], 1);
+        brick_put<Real>(A, par, b, bi.off, bi.cap, slot, p, w, tag ? tag[i] : (int32_t)i, st);
+    }
+    flag(status, st);
+}
+
+// Binned solvent of the step *d_step back to dense arrays in identity order
+// (x[:, id] = the member's position, tag[id] = id).
+template <typename Real>
+__global__ void k_binned_unpack(SysDev s, BinnedDev bn, const uint64_t *d_step, const Real *xb, const Real *vb,
+                                const int32_t *tagb, Real *x, Real *v, int32_t *tag, uint32_t *status)
+{
+    uint32_t st = 0;
+    const int par = (int)(*d_step & 1);
+    const int64_t N = s.N, C = bn.cap;
+    auto put = [&](int32_t id, const Real p[3], const Real w[3]) {
+        if (id < 0 || id >= N) {
+            st |= ST_BINERR;
+            return;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            x[d * N + id] = p[d];
+            v[d * N + id] = w[d];
+        }
+        tag[id] = id;
+    };
+    for (int64_t b = blockIdx.x; b < bn.nbricks; b += gridDim.x) {
+        const BrickInfo bi = bn.brick[b];
+        const int n = min(bn.cnt[(int64_t)par * bn.nbricks + b], bi.cap);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int64_t q = bi.off + i;
+            const Real p[3] = {xb[q], xb[C + q], xb[2 * C + q]}, w[3] = {vb[q], vb[C + q], vb[2 * C + q]};
+            put(tagb[q], p, w);
+        }
+    }
+    const int novf = min(bn.ctrl[BC_OVF0 + par], BIN_OVF_CAP);
+    const Real *o = (const Real *)bn.ovf_xv + (int64_t)par * 6 * BIN_OVF_CAP;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < novf; e += (int64_t)gridDim.x * blockDim.x) {
+        const Real p[3] = {o[e], o[BIN_OVF_CAP + e], o[2 * BIN_OVF_CAP + e]};
+        const Real w[3] = {o[3 * BIN_OVF_CAP + e], o[4 * BIN_OVF_CAP + e], o[5 * BIN_OVF_CAP + e]};
+        put(bn.ovf_tag[(int64_t)par * BIN_OVF_CAP + e], p, w);
+    }
+    flag(status, st);
+}
+
 size_t esize(const mpcd_sys *s) { return s->prec == MPCD_F64 ? sizeof(double) : sizeof(float); }
 
 bool ok_arr(const void *p, int64_t n, size_t elem)
@@ -3464,6 +4131,168 @@ int check_bodies(const mpcd_sys *s, const mpcd_bodies *b)
         int _rc = (x);                 \
         if (_rc != MPCD_OK) return _rc; \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// Binned layout: host-side plan of the bricks, regions and site lists
+
+// Brick shapes, log2 of the extent along x, y, z, largest first (256 .. 8 cells).
+constexpr int BRICK_SHAPES[6][3] = {{3, 3, 2}, {3, 2, 2}, {2, 2, 2}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
+
+// Region capacity for mu expected members: mu + 6 sqrt(mu) + 16 (a Poisson
+// count exceeds it with probability below 1e-9); site list capacity: the
+// brick's cells + 64, at most the system's sites.
+int64_t region_cap(double mu) { return (int64_t)ceil(mu + 6.0 * sqrt(mu)) + 16; }
+int64_t site_cap(int64_t ncb, int64_t S_r) { return ncb + 64 < S_r ? ncb + 64 : S_r; }
+
+// Members a brick block holds in registers (FP32) or LDS (FP64).
+int brick_block_members(int prec) { return prec == MPCD_F64 ? 1024 : BRICK_T * BRICK_ITEMS_F32; }
+
+int32_t sovf_cap_of(const mpcd_sys *sys)
+{
+    const int64_t sc = sys->n_sites / 4 > 1024 ? sys->n_sites / 4 : 1024;
+    return (int32_t)(sc < ((int64_t)1 << 22) ? sc : ((int64_t)1 << 22));
+}
+
+struct BinnedPlan {
+    int64_t nbricks = 0, cap = 0, sslots = 0;
+    int32_t sovf_cap = 0;
+    std::vector<BrickInfo> brick;
+    std::vector<int32_t> sys_bb, sys_bg;
+};
+
+// tables == false: sizes only.
+int binned_plan(const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_off, const int64_t *site_off_sys,
+                bool tables, BinnedPlan &P)
+{
+    if (check_sizes(sys) != MPCD_OK || !ncell || !solv_off || !site_off_sys) return MPCD_EINVAL;
+    const int nsys = sys->nsys;
+    if (solv_off[0] != 0 || solv_off[nsys] != sys->n_solvent || site_off_sys[0] != 0 ||
+        site_off_sys[nsys] != sys->n_sites)
+        return MPCD_EINVAL;
+    const int target = brick_block_members(sys->prec) - 64;  // room for overflow entries
+    int64_t C = 0;
+    if (tables) {
+        P.sys_bb.assign(nsys + 1, 0);
+        P.sys_bg.assign(6 * (size_t)nsys, 0);
+        P.brick.clear();
+    }
+    for (int r = 0; r < nsys; ++r) {
+        const int n[3] = {ncell[3 * r], ncell[3 * r + 1], ncell[3 * r + 2]};
+        if (n[0] < 1 || n[1] < 1 || n[2] < 1 || n[0] > 32767 || n[1] > 32767 || n[2] > 32767) return MPCD_EINVAL;
+        const int64_t Cr = (int64_t)n[0] * n[1] * n[2];
+        const int64_t Nr = solv_off[r + 1] - solv_off[r], Sr = site_off_sys[r + 1] - site_off_sys[r];
+        if (Nr < 0 || Sr < 0) return MPCD_EINVAL;
+        C += Cr;
+        const double rho = (double)Nr / (double)Cr;
+        int k = 0;
+        for (; k < 6; ++k) {
+            const int64_t ncb = (int64_t)1 << (BRICK_SHAPES[k][0] + BRICK_SHAPES[k][1] + BRICK_SHAPES[k][2]);
+            if (region_cap(rho * (double)ncb) + site_cap(ncb, Sr) <= target) break;
+        }
+        if (k == 6) return MPCD_EINVAL;  // denser than a brick block can hold
+        const int lg[3] = {BRICK_SHAPES[k][0], BRICK_SHAPES[k][1], BRICK_SHAPES[k][2]};
+        int nb[3];
+        for (int d = 0; d < 3; ++d) nb[d] = (n[d] + (1 << lg[d]) - 1) >> lg[d];
+        if (tables) {
+            P.sys_bb[r] = (int32_t)P.nbricks;
+            for (int d = 0; d < 3; ++d) {
+                P.sys_bg[6 * r + d] = lg[d];
+                P.sys_bg[6 * r + 3 + d] = nb[d];
+            }
+        }
+        for (int bz = 0; bz < nb[2]; ++bz)
+            for (int by = 0; by < nb[1]; ++by)
+                for (int bx = 0; bx < nb[0]; ++bx) {
+                    const int o[3] = {bx << lg[0], by << lg[1], bz << lg[2]};
+                    int dim[3];
+                    for (int d = 0; d < 3; ++d) dim[d] = std::min(1 << lg[d], n[d] - o[d]);
+                    const int64_t ncb = (int64_t)dim[0] * dim[1] * dim[2];
+                    const int64_t cs = region_cap(rho * (double)ncb), ct = site_cap(ncb, Sr);
+                    if (tables) {
+                        BrickInfo bi;
+                        bi.off = P.cap;
+                        bi.cap = (int32_t)cs;
+                        bi.sys = r;
+                        bi.soff = (int32_t)P.sslots;
+                        bi.scap = (int16_t)ct;
+                        bi.pad = 0;
+                        for (int d = 0; d < 3; ++d) {
+                            bi.org[d] = (int16_t)o[d];
+                            bi.dim[d] = (uint8_t)dim[d];
+                        }
+                        P.brick.push_back(bi);
+                    }
+                    P.nbricks += 1;
+                    P.cap += cs;
+                    P.sslots += ct;
+                }
+        if (tables) P.sys_bb[r + 1] = (int32_t)P.nbricks;
+    }
+    if (C != sys->n_cells) return MPCD_EINVAL;
+    if (P.cap >= ((int64_t)1 << 31) || P.sslots >= ((int64_t)1 << 31) || P.nbricks >= ((int64_t)1 << 30))
+        return MPCD_EINVAL;
+    P.sovf_cap = sovf_cap_of(sys);
+    return MPCD_OK;
+}
+
+struct BinnedLayout {
+    size_t ctrl, brick, sys_bb, sys_bg, cnt, scnt, sslot, ovf_dest, ovf_tag, ovf_xv, sovf, total;
+};
+
+BinnedLayout binned_layout(const mpcd_sys *sys, int64_t nbricks, int64_t sslots, int32_t sovf_cap)
+{
+    BinnedLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    L.ctrl = take(sizeof(int32_t) * BC_WORDS);
+    L.brick = take(sizeof(BrickInfo) * (size_t)nbricks);
+    L.sys_bb = take(sizeof(int32_t) * (size_t)(sys->nsys + 1));
+    L.sys_bg = take(sizeof(int32_t) * 6 * (size_t)sys->nsys);
+    L.cnt = take(sizeof(int32_t) * 2 * (size_t)nbricks);
+    L.scnt = take(sizeof(int32_t) * (size_t)nbricks);
+    L.sslot = take(sizeof(int32_t) * (size_t)(sslots > 0 ? sslots : 1));
+    L.ovf_dest = take(sizeof(int32_t) * 2 * BIN_OVF_CAP);
+    L.ovf_tag = take(sizeof(int32_t) * 2 * BIN_OVF_CAP);
+    L.ovf_xv = take(esize(sys) * 12 * BIN_OVF_CAP);
+    L.sovf = take(sizeof(int32_t) * 2 * (size_t)sovf_cap);
+    L.total = off;
+    return L;
+}
+
+int check_binned(const mpcd_sys *sys, const mpcd_binned *b)
+{
+    if (!b || !b->ws || !aligned(b->ws, 256) || b->nbricks < 1 || b->capacity < 0 || b->site_slots < 0)
+        return MPCD_EINVAL;
+    if (b->ws_bytes < binned_layout(sys, b->nbricks, b->site_slots, sovf_cap_of(sys)).total) return MPCD_EWORKSPACE;
+    return MPCD_OK;
+}
+
+BinnedDev binned_dev(const mpcd_sys *sys, const mpcd_binned *b)
+{
+    const BinnedLayout L = binned_layout(sys, b->nbricks, b->site_slots, sovf_cap_of(sys));
+    BinnedDev d;
+    char *w = (char *)b->ws;
+    d.ctrl = (int32_t *)(w + L.ctrl);
+    d.brick = (const BrickInfo *)(w + L.brick);
+    d.sys_bb = (const int32_t *)(w + L.sys_bb);
+    d.sys_bg = (const int32_t *)(w + L.sys_bg);
+    d.cnt = (int32_t *)(w + L.cnt);
+    d.scnt = (int32_t *)(w + L.scnt);
+    d.sslot = (int32_t *)(w + L.sslot);
+    d.ovf_dest = (int32_t *)(w + L.ovf_dest);
+    d.ovf_tag = (int32_t *)(w + L.ovf_tag);
+    d.ovf_xv = (void *)(w + L.ovf_xv);
+    d.sovf = (int32_t *)(w + L.sovf);
+    d.nbricks = b->nbricks;
+    d.cap = b->capacity;
+    d.sovf_cap = sovf_cap_of(sys);
+    return d;
+}
+
 
 }  // namespace
 
@@ -3855,20 +4684,28 @@ static void launch_forces_prep(const Ctx &c, hipStream_t st, const mpcd_bodies *
                            counts, cellid, slot, shift, c.status);
 }
 
+// binned, d_step: also clear the binned layout's spent fills (binned_finish).
 static void launch_transfer_first(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const void *vs, double *J,
-                                  double *K, double dt, const mpcd_wca &wca)
+                                  double *K, double dt, const mpcd_wca &wca, const mpcd_binned *binned = nullptr,
+                                  const uint64_t *d_step = nullptr)
 {
     const BodyGrid grid = body_grid(c, wca);
     const SiteFrames fr = site_frames(c, wca);
     if (c.sys->n_bodies == 0) return;
     const BodyDev bd = make_bodydev(bodies);
+    BinnedDev bn;
+    memset(&bn, 0, sizeof bn);
+    if (binned) bn = binned_dev(c.sys, binned);
+    const uint64_t *ds = binned ? d_step : nullptr;
     const dim3 gb((unsigned)c.sys->n_bodies);
     if (c.sys->prec == MPCD_F64)
         hipLaunchKernelGGL(k_transfer_first<double>, gb, dim3(BODY_T), 0, st, c.sd, bd, (const double *)vs,
-                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, fr, c.status);
+                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, fr, c.status, bn,
+                           ds);
     else
         hipLaunchKernelGGL(k_transfer_first<float>, gb, dim3(BODY_T), 0, st, c.sd, bd, (const float *)vs,
-                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, fr, c.status);
+                           at<double>(c.ws, c.L.site_d), at<double>(c.ws, c.L.vpre), J, K, dt, grid, fr, c.status, bn,
+                           ds);
 }
 
 static void launch_forces(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca,
@@ -3915,6 +4752,84 @@ static void launch_reorder(const Ctx &c, hipStream_t st, void *x, void *v, int32
 
 // ---------------------------------------------------------------------------
 // Entry points
+
+// ---- binned layout launches ----
+
+static BrickSiteBin brick_site_bin(const Ctx &c, const mpcd_binned *b)
+{
+    BrickSiteBin bb;
+    bb.bn = binned_dev(c.sys, b);
+    return bb;
+}
+
+static void launch_therm_bin(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, double kT, int thermalize,
+                             uint64_t seed, const uint64_t *d_step, void *xs, void *vs, const mpcd_binned *b)
+{
+    if (c.sys->n_bodies == 0 || c.sys->n_sites == 0) return;
+    const BodyDev bd = make_bodydev(bodies);
+    double *site_d = at<double>(c.ws, c.L.site_d), *vpre = at<double>(c.ws, c.L.vpre);
+    const dim3 g((unsigned)c.sys->n_bodies);
+    if (c.sys->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_therm_bin<double>, g, dim3(BODY_T), 0, st, c.sd, bd, brick_site_bin(c, b), kT,
+                           thermalize, seed, d_step, (double *)xs, (double *)vs, site_d, vpre, c.status);
+    else
+        hipLaunchKernelGGL(k_therm_bin<float>, g, dim3(BODY_T), 0, st, c.sd, bd, brick_site_bin(c, b), kT, thermalize,
+                           seed, d_step, (float *)xs, (float *)vs, site_d, vpre, c.status);
+}
+
+static void launch_forces_therm_bin(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca,
+                                    const double *f_ext, double dt, uint64_t *advance, double kT, int thermalize,
+                                    uint64_t seed, const uint64_t *step_next, void *xs, void *vs,
+                                    const mpcd_binned *b)
+{
+    const BodyDev bd = make_bodydev(bodies);
+    const BodyGrid grid = body_grid(c, wca);
+    const ExtForce E = make_ext(f_ext);
+    double *site_d = at<double>(c.ws, c.L.site_d), *vpre = at<double>(c.ws, c.L.vpre);
+    const dim3 g((unsigned)c.sys->n_bodies);
+    if (c.sys->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_forces_therm_bin<double>, g, dim3(BODY_T), 0, st, c.sd, bd, wca, grid, E, dt, advance,
+                           brick_site_bin(c, b), kT, thermalize, seed, step_next, (double *)xs, (double *)vs, site_d,
+                           vpre, c.status);
+    else
+        hipLaunchKernelGGL(k_forces_therm_bin<float>, g, dim3(BODY_T), 0, st, c.sd, bd, wca, grid, E, dt, advance,
+                           brick_site_bin(c, b), kT, thermalize, seed, step_next, (float *)xs, (float *)vs, site_d,
+                           vpre, c.status);
+}
+
+// The brick collision of the binned layout (FP32).  step_next: when set,
+// block 0 stores the step index + 1 there.
+static void launch_brick_collide(const Ctx &c, hipStream_t st, const mpcd_step_args *a, uint64_t *step_next)
+{
+    const mpcd_params &p = a->par;
+    BrickArgs<float> A;
+    A.s = c.sd;
+    A.bn = binned_dev(c.sys, a->binned);
+    A.x = (const float *)a->x;
+    A.v = (const float *)a->v;
+    A.tag = a->tag;
+    A.xo = (float *)a->x_out;
+    A.vo = (float *)a->v_out;
+    A.tago = a->tag_out;
+    A.xs = (float *)a->xs;
+    A.vs = (float *)a->vs;
+    A.site_m = a->bodies.site_m;
+    A.cos_a = p.cos_a;
+    A.sin_a = p.sin_a;
+    A.kT_cell = p.kT_cell;
+    A.dt = p.dt;
+    A.seed = p.seed;
+    A.d_step = a->d_step;
+    A.step_next = step_next;
+    A.shift_out = at<double>(c.ws, c.L.shift);
+    const BodyGrid grid = body_grid(c, p.wca);
+    A.grid_clear = grid.count;
+    A.grid_n = grid.count ? (int64_t)c.L.grid_mask + 1 : 0;
+    A.F = make_forcing(p.g, p.dt);
+    A.status = c.status;
+    hipLaunchKernelGGL(k_brick_collide_f32<BRICK_ITEMS_F32>, dim3(xcd_grid(a->binned->nbricks)), dim3(BRICK_T), 0, st,
+                       A);
+}
 
 static int bin_checks(const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
                       const uint64_t *d_step, void *ws, size_t ws_bytes)
@@ -4181,6 +5096,11 @@ static int step_checks(const mpcd_step_args *a)
     if (a->reorder_every < 0 || (a->reorder_every > 0 && !ok_arr(a->tag, s->n_solvent, 4))) return MPCD_EINVAL;
     TRY(out_checks(s, a->v, a->tag, a->x, a->x_out, a->v_out, a->tag_out));
     if (a->v_out && !p.fuse_stream) return MPCD_ENOTSUP;
+    if (a->binned) {
+        TRY(check_binned(s, a->binned));
+        if (s->prec != MPCD_F32 || a->rnemd) return MPCD_ENOTSUP;
+        if (!a->x_out || !a->v_out || !a->tag_out || !a->tag || a->reorder_every != 0) return MPCD_EINVAL;
+    }
     if (a->rnemd)
         TRY(rnemd_checks(s, a->v_out ? a->x_out : a->x, a->v_out ? a->v_out : a->v, a->tag, a->rnemd, a->rnemd_dp,
                          a->ws, a->ws_bytes));
@@ -4236,9 +5156,41 @@ static int overlap_mode(const mpcd_step_args *a)
 // with the first body half-step, forces fused with the second half kick and
 // the step-counter advance.  The same operations in the same order, per
 // particle, cell and body, as calling the entry points in sequence.
+// One step of the binned layout: [thermalize + site binning], the brick
+// collision (collide, stream, bin the new solvent for the next step),
+// transfer fused with the first body half-step, forces fused with the second
+// half kick and the step-counter advance (in graphs also with the next step's
+// thermalization and site binning).
+static int step_binned(void *stream, const mpcd_step_args *a, const Overlap *ov)
+{
+    const mpcd_sys *s = a->sys;
+    const mpcd_params &p = a->par;
+    const Ctx c = make_ctx(s, a->ws, &p.tune);
+    hipStream_t st = (hipStream_t)stream;
+    if (!(ov && ov->pre_binned))
+        launch_therm_bin(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->xs, a->vs, a->binned);
+    uint64_t *step_next = at<uint64_t>(c.ws, c.L.step_next);
+    const bool next = ov && ov->bin_next;
+    launch_brick_collide(c, st, a, next ? step_next : nullptr);
+    if (s->n_bodies == 0) {
+        const BinnedDev bn = binned_dev(s, a->binned);
+        hipLaunchKernelGGL(k_binned_finish, dim3(grid_for(bn.nbricks, 256)), dim3(256), 0, st, bn, a->d_step);
+        hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a->d_step);
+        return launch_check();
+    }
+    launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt, p.wca, a->binned, a->d_step);
+    if (next)
+        launch_forces_therm_bin(c, st, &a->bodies, p.wca, p.f_ext, p.dt, a->d_step, p.kT, p.thermalize, p.seed,
+                                step_next, a->xs, a->vs, a->binned);
+    else
+        launch_forces(c, st, &a->bodies, p.wca, p.f_ext, p.dt, 1, a->d_step);
+    return launch_check();
+}
+
 static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
 {
     TRY(step_checks(a));
+    if (a->binned) return step_binned(stream, a, ov);
     const mpcd_sys *s = a->sys;
     const mpcd_params &p = a->par;
     const Ctx c = make_ctx(s, a->ws, &p.tune);
@@ -4320,7 +5272,12 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
     TRY(step_checks(args));
     if (args->v_out && ((nsteps & 1) || !args->tag)) return MPCD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    const int omode = nsteps >= 2 ? overlap_mode(args) : 0;
+    // the binned layout fuses each next step's thermalization and site
+    // binning into the force kernel (bodies with sites, no site-site WCA)
+    const mpcd_sys *gs = args->sys;
+    const int omode = nsteps < 2 ? 0
+                      : args->binned ? ((gs->n_bodies > 0 && gs->n_sites > 0 && args->par.wca.mode != 2) ? 2 : 0)
+                                     : overlap_mode(args);
     Overlap ov{omode, nullptr, nullptr, nullptr, false, false};
     const bool overlap = omode != 0;
     if (omode == 1) {  // default-priority side stream and the two events, for the capture only
@@ -4517,6 +5474,123 @@ int mpcd_status(void *stream, const void *ws, size_t ws_bytes, uint32_t *flags)
     TRY(hip_check(hipStreamSynchronize((hipStream_t)stream)));
     *flags = h;
     return MPCD_OK;
+}
+
+int mpcd_binned_sites(void *stream, const mpcd_step_args *a)
+{
+    TRY(step_checks(a));
+    if (!a->binned) return MPCD_EINVAL;
+    const mpcd_params &p = a->par;
+    const Ctx c = make_ctx(a->sys, a->ws, &p.tune);
+    hipStream_t st = (hipStream_t)stream;
+    const BinnedDev bn = binned_dev(a->sys, a->binned);
+    hipLaunchKernelGGL(k_binned_clear_sites, dim3(grid_for(bn.nbricks, 256)), dim3(256), 0, st, bn);
+    launch_therm_bin(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->xs, a->vs, a->binned);
+    return launch_check();
+}
+
+int mpcd_binned_collide(void *stream, const mpcd_step_args *a)
+{
+    TRY(step_checks(a));
+    if (!a->binned) return MPCD_EINVAL;
+    const Ctx c = make_ctx(a->sys, a->ws, &a->par.tune);
+    hipStream_t st = (hipStream_t)stream;
+    const BinnedDev bn = binned_dev(a->sys, a->binned);
+    hipLaunchKernelGGL(k_binned_clear_out, dim3(grid_for(bn.nbricks, 256)), dim3(256), 0, st, bn, a->d_step);
+    launch_brick_collide(c, st, a, nullptr);
+    return launch_check();
+}
+
+int mpcd_binned_layout(const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_off, const int64_t *site_off_sys,
+                       mpcd_binned *out)
+{
+    if (!out) return MPCD_EINVAL;
+    BinnedPlan P;
+    TRY(binned_plan(sys, ncell, solv_off, site_off_sys, false, P));
+    out->nbricks = P.nbricks;
+    out->capacity = P.cap;
+    out->site_slots = P.sslots;
+    out->items = sys->prec == MPCD_F64 ? 0 : BRICK_ITEMS_F32;
+    out->ws_bytes = binned_layout(sys, P.nbricks, P.sslots, P.sovf_cap).total;
+    return MPCD_OK;
+}
+
+int mpcd_binned_init(void *stream, const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_off,
+                     const int64_t *site_off_sys, const mpcd_binned *b)
+{
+    BinnedPlan P;
+    TRY(binned_plan(sys, ncell, solv_off, site_off_sys, true, P));
+    TRY(check_binned(sys, b));
+    if (P.nbricks != b->nbricks || P.cap != b->capacity || P.sslots != b->site_slots) return MPCD_EINVAL;
+    const BinnedLayout L = binned_layout(sys, P.nbricks, P.sslots, P.sovf_cap);
+    char *w = (char *)b->ws;
+    hipStream_t st = (hipStream_t)stream;
+    // every launch before this copy has finished; the copy blocks until done
+    TRY(hip_check(hipStreamSynchronize(st)));
+    TRY(hip_check(hipMemcpy(w + L.brick, P.brick.data(), sizeof(BrickInfo) * P.brick.size(), hipMemcpyHostToDevice)));
+    TRY(hip_check(hipMemcpy(w + L.sys_bb, P.sys_bb.data(), sizeof(int32_t) * P.sys_bb.size(), hipMemcpyHostToDevice)));
+    TRY(hip_check(hipMemcpy(w + L.sys_bg, P.sys_bg.data(), sizeof(int32_t) * P.sys_bg.size(), hipMemcpyHostToDevice)));
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (int32_t *)(w + L.ctrl), (int64_t)BC_WORDS, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(3 * P.nbricks, 256)), dim3(256), 0, st, (int32_t *)(w + L.cnt),
+                       3 * P.nbricks, 0);  // both parities' fills and the site counts (adjacent)
+    return launch_check();
+}
+
+int mpcd_binned_pack(void *stream, const mpcd_sys *sys, const void *x, const void *v, const int32_t *tag, void *xb,
+                     void *vb, int32_t *tagb, uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes,
+                     const mpcd_binned *b)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    TRY(check_binned(sys, b));
+    const size_t es = esize(sys);
+    const int64_t N = sys->n_solvent;
+    if (!ok_arr(x, N, es) || !ok_arr(v, N, es) || !ok_arr(tag, 0, 4) || !ok_arr(xb, b->capacity, es) ||
+        !ok_arr(vb, b->capacity, es) || !ok_arr(tagb, b->capacity, 4) || !d_step)
+        return MPCD_EINVAL;
+    const BinnedDev bn = binned_dev(sys, b);
+    const SysDev sd = make_sysdev(sys);
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *status = at<uint32_t>(ws, layout_of(sys).status);
+    // clear both parities' fills and overflow counters: the step parity is read on the device
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * bn.nbricks, 256)), dim3(256), 0, st, bn.cnt, 2 * bn.nbricks, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, bn.ctrl + BC_OVF0, (int64_t)2, 0);
+    if (N > 0) {
+        const unsigned g = grid_for(N, 256, 1 << 16);
+        if (sys->prec == MPCD_F64)
+            hipLaunchKernelGGL(k_binned_pack<double>, dim3(g), dim3(256), 0, st, sd, bn, seed, d_step,
+                               (const double *)x, (const double *)v, tag, (double *)xb, (double *)vb, tagb, status);
+        else
+            hipLaunchKernelGGL(k_binned_pack<float>, dim3(g), dim3(256), 0, st, sd, bn, seed, d_step,
+                               (const float *)x, (const float *)v, tag, (float *)xb, (float *)vb, tagb, status);
+    }
+    return launch_check();
+}
+
+int mpcd_binned_unpack(void *stream, const mpcd_sys *sys, const void *xb, const void *vb, const int32_t *tagb, void *x,
+                       void *v, int32_t *tag, const uint64_t *d_step, void *ws, size_t ws_bytes, const mpcd_binned *b)
+{
+    TRY(check_sys(sys));
+    TRY(check_ws(sys, ws, ws_bytes));
+    TRY(check_binned(sys, b));
+    const size_t es = esize(sys);
+    const int64_t N = sys->n_solvent;
+    if (!ok_arr(x, N, es) || !ok_arr(v, N, es) || !ok_arr(tag, N, 4) || !ok_arr(xb, b->capacity, es) ||
+        !ok_arr(vb, b->capacity, es) || !ok_arr(tagb, b->capacity, 4) || !d_step)
+        return MPCD_EINVAL;
+    if (N == 0) return MPCD_OK;
+    const BinnedDev bn = binned_dev(sys, b);
+    const SysDev sd = make_sysdev(sys);
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *status = at<uint32_t>(ws, layout_of(sys).status);
+    const unsigned g = (unsigned)std::min<int64_t>(bn.nbricks, 1 << 16);
+    if (sys->prec == MPCD_F64)
+        hipLaunchKernelGGL(k_binned_unpack<double>, dim3(g), dim3(256), 0, st, sd, bn, d_step, (const double *)xb,
+                           (const double *)vb, tagb, (double *)x, (double *)v, tag, status);
+    else
+        hipLaunchKernelGGL(k_binned_unpack<float>, dim3(g), dim3(256), 0, st, sd, bn, d_step, (const float *)xb,
+                           (const float *)vb, tagb, (float *)x, (float *)v, tag, status);
+    return launch_check();
 }
 
 }  // extern "C"

@@ -22,7 +22,8 @@ EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mp
            "mpcd_advance_step", "mpcd_step", "mpcd_forces_prep", "mpcd_reorder", "mpcd_graph_create", "mpcd_graph_launch",
            "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error",
            "harm_forces", "harm_md", "harm_step", "harm_graph_create", "mpcd_rnemd_exchange", "mpcd_cell_order",
-           "mpcd_tile_shape")
+           "mpcd_tile_shape", "mpcd_binned_layout", "mpcd_binned_init", "mpcd_binned_pack", "mpcd_binned_unpack",
+           "mpcd_binned_collide", "mpcd_binned_sites")
 
 vp = C.c_void_p
 
@@ -62,12 +63,17 @@ class MpcdRnemd(C.Structure):
                 ("npairs", C.c_int32)]
 
 
+class MpcdBinned(C.Structure):
+    _fields_ = [("ws", vp), ("ws_bytes", C.c_size_t), ("nbricks", C.c_int64), ("capacity", C.c_int64),
+                ("site_slots", C.c_int64), ("items", C.c_int32)]
+
+
 class MpcdStepArgs(C.Structure):
     _fields_ = [("sys", C.POINTER(MpcdSys)), ("bodies", MpcdBodies), ("x", vp), ("v", vp), ("tag", vp),
                 ("xs", vp), ("vs", vp), ("J", vp), ("K", vp), ("d_step", vp), ("ws", vp),
                 ("ws_bytes", C.c_size_t), ("par", MpcdParams), ("reorder_every", C.c_int32),
                 ("x_out", vp), ("v_out", vp), ("tag_out", vp), ("rnemd", C.POINTER(MpcdRnemd)),
-                ("rnemd_dp", vp)]
+                ("rnemd_dp", vp), ("binned", C.POINTER(MpcdBinned))]
 
 
 class MpcdHarm(C.Structure):
@@ -125,6 +131,14 @@ def load(path: str = LIB_PATH):
         "harm_step": (C.c_int, [vp, C.POINTER(MpcdStepArgs), C.POINTER(MpcdHarm), dbl, i32]),
         "harm_graph_create": (C.c_int, [vp, C.POINTER(MpcdStepArgs), C.POINTER(MpcdHarm), dbl, i32, i32,
                                         C.POINTER(vp)]),
+        "mpcd_binned_layout": (C.c_int, [sp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                         C.POINTER(MpcdBinned)]),
+        "mpcd_binned_init": (C.c_int, [vp, sp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                       C.POINTER(MpcdBinned)]),
+        "mpcd_binned_pack": (C.c_int, [vp, sp, vp, vp, vp, vp, vp, vp, u64, vp, vp, sz, C.POINTER(MpcdBinned)]),
+        "mpcd_binned_unpack": (C.c_int, [vp, sp, vp, vp, vp, vp, vp, vp, vp, vp, sz, C.POINTER(MpcdBinned)]),
+        "mpcd_binned_collide": (C.c_int, [vp, C.POINTER(MpcdStepArgs)]),
+        "mpcd_binned_sites": (C.c_int, [vp, C.POINTER(MpcdStepArgs)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -22,7 +22,8 @@ def _ptr(t):
 
 class GPUSystem:
     def __init__(self, systems, params: dict, prec: str = "f64", replica0: int = 0,
-                 device: str = "cuda:0", fuse_stream: bool = True, out_of_place: bool = True):
+                 device: str = "cuda:0", fuse_stream: bool = True, out_of_place: bool = True,
+                 layout: str = "dense"):
         self.lib = L.load()
         if isinstance(systems, dict):
             systems = [systems]
@@ -134,6 +135,60 @@ class GPUSystem:
         self.tuning = L.MpcdTune(0, 0, 0, 0, 0)
         self.ws_init()
         self._graph = None
+        self._state = self._STATE
+        self.layout = layout
+        self.binned = None
+        if layout == "binned":
+            self._setup_binned()
+        elif layout != "dense":
+            raise ValueError("layout must be 'dense' or 'binned'")
+
+    def _host_offsets(self):
+        nc = np.ascontiguousarray(self.ncell_h.reshape(-1), dtype=np.int32)
+        so = np.ascontiguousarray(self.solv_off_h, dtype=np.int64)
+        ss = np.ascontiguousarray(self.site_sys_off_h, dtype=np.int64)
+        return nc, so, ss, (nc.ctypes.data_as(C.POINTER(C.c_int32)), so.ctypes.data_as(C.POINTER(C.c_int64)),
+                            ss.ctypes.data_as(C.POINTER(C.c_int64)))
+
+    def _setup_binned(self):
+        """The binned solvent layout (see mpcd_binned_layout): solvent in
+        per-brick regions of the step's grid, double-buffered."""
+        if not self.out_of_place:
+            raise ValueError("the binned layout steps out of place")
+        nc, so, ss, hp = self._host_offsets()
+        b = L.MpcdBinned()
+        L.check(self.lib.mpcd_binned_layout(C.byref(self.csys), *hp, C.byref(b)), "mpcd_binned_layout")
+        self.bws = torch.empty(int(b.ws_bytes), dtype=torch.uint8, device=self.device)
+        b.ws = _ptr(self.bws)
+        self.binned = b
+        L.check(self.lib.mpcd_binned_init(self.stream, C.byref(self.csys), *hp, C.byref(b)), "mpcd_binned_init")
+        cap = int(b.capacity)
+        xd, vd, td = self.x, self.v, self.tag
+        self.x = torch.zeros((3, cap), dtype=self.real, device=self.device)
+        self.v = torch.zeros((3, cap), dtype=self.real, device=self.device)
+        self.tag = torch.full((cap,), -1, dtype=torch.int32, device=self.device)
+        self.x2, self.v2, self.tag2 = torch.zeros_like(self.x), torch.zeros_like(self.v), torch.full_like(self.tag, -1)
+        self._pack(xd, vd, td)
+        self._state = self._STATE + ("bws",)
+
+    def _pack(self, xd, vd, td):
+        L.check(self.lib.mpcd_binned_pack(self.stream, C.byref(self.csys), _ptr(xd), _ptr(vd), _ptr(td), _ptr(self.x),
+                                          _ptr(self.v), _ptr(self.tag), self.params["seed"], _ptr(self.d_step),
+                                          _ptr(self.ws), self.ws_bytes, C.byref(self.binned)), "mpcd_binned_pack")
+
+    def dense_solvent(self):
+        """(x [3,N], v [3,N], tag [N]) of the current solvent as device tensors:
+        the arrays themselves (dense layout) or, for the binned layout, a copy
+        in identity order."""
+        if self.binned is None:
+            return self.x, self.v, self.tag
+        xd = torch.empty((3, self.N), dtype=self.real, device=self.device)
+        vd = torch.empty((3, self.N), dtype=self.real, device=self.device)
+        td = torch.empty((self.N,), dtype=torch.int32, device=self.device)
+        L.check(self.lib.mpcd_binned_unpack(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.v),
+                                            _ptr(self.tag), _ptr(xd), _ptr(vd), _ptr(td), _ptr(self.d_step),
+                                            _ptr(self.ws), self.ws_bytes, C.byref(self.binned)), "mpcd_binned_unpack")
+        return xd, vd, td
 
     # ------------------------------------------------------------------
     @property
@@ -145,7 +200,13 @@ class GPUSystem:
                 "mpcd_ws_init")
 
     def set_step(self, n: int):
+        if self.binned is None:
+            self.d_step.fill_(int(n))
+            return
+        # the binned solvent lies in the bricks of its step's grid: repack
+        xd, vd, td = self.dense_solvent()
         self.d_step.fill_(int(n))
+        self._pack(xd, vd, td)
 
     def step_args(self, reorder_every: int = 0) -> L.MpcdStepArgs:
         p = self.params
@@ -162,7 +223,8 @@ class GPUSystem:
                                     v_out=_ptr(self.v2) if out else C.c_void_p(0),
                                     tag_out=_ptr(self.tag2) if out else C.c_void_p(0),
                                     rnemd=C.pointer(self.rnemd) if self.rnemd is not None else None,
-                                    rnemd_dp=_ptr(self.rnemd_dp))
+                                    rnemd_dp=_ptr(self.rnemd_dp),
+                                    binned=C.pointer(self.binned) if self.binned is not None else None)
         return self._args
 
     def set_tuning(self, tile_items: int = 0, tile_fill: int = 0, draw_cells: int = 0, draws_inline: int = 0,
@@ -185,13 +247,13 @@ class GPUSystem:
         """Device copies of the whole simulation state (for timing runs).  Waits
         for all work on the device first: steps may still run on another stream."""
         torch.cuda.synchronize(self.device)
-        snap = {k: getattr(self, k).clone() for k in self._STATE}
+        snap = {k: getattr(self, k).clone() for k in self._state}
         torch.cuda.synchronize(self.device)
         return snap
 
     def restore(self, snap):
         torch.cuda.synchronize(self.device)
-        for k in self._STATE:
+        for k in self._state:
             getattr(self, k).copy_(snap[k])
         torch.cuda.synchronize(self.device)
 
@@ -295,6 +357,15 @@ class GPUSystem:
         a = self.step_args()  # a.x: the solvent the last step wrote
         L.check(self.lib.mpcd_forces_prep(self.stream, C.byref(a), _ptr(step_next)), "mpcd_forces_prep")
 
+    def binned_sites(self):
+        """mpcd_binned_sites: the current step's sites thermalized and listed."""
+        L.check(self.lib.mpcd_binned_sites(self.stream, C.byref(self.step_args())), "mpcd_binned_sites")
+
+    def binned_collide(self):
+        """mpcd_binned_collide: the current step's brick collision into the
+        other set of arrays (repeatable; the state is not advanced)."""
+        L.check(self.lib.mpcd_binned_collide(self.stream, C.byref(self.step_args())), "mpcd_binned_collide")
+
     def recollide_last(self, restore_sites: bool = True):
         """Repeat the last out-of-place step's collide + stream pass from its
         inputs into the current arrays.  The sites collide in place, so their
@@ -386,9 +457,12 @@ class GPUSystem:
         """Per-system dicts of numpy float64 arrays in the oracle's layout."""
         torch.cuda.synchronize(self.device)
         g = {k: getattr(self, k).detach().cpu().numpy() for k in
-             ("x", "v", "pos", "image", "quat", "mom", "angmom", "force", "torque", "xs", "vs", "J", "K")}
+             ("pos", "image", "quat", "mom", "angmom", "force", "torque", "xs", "vs", "J", "K")}
+        xd, vd, td = self.dense_solvent()
+        torch.cuda.synchronize(self.device)
+        g["x"], g["v"] = xd.cpu().numpy(), vd.cpu().numpy()
         # solvent back into identity order
-        tag = self.tag.cpu().numpy().astype(np.int64)
+        tag = td.cpu().numpy().astype(np.int64)
         for k in ("x", "v"):
             a = np.empty_like(g[k])
             a[:, tag] = g[k]

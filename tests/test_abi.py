@@ -128,3 +128,47 @@ def test_tile_shape_follows_the_tuning():
     s64 = sys_desc(prec=lib.MPCD_F64)
     assert L.mpcd_tile_shape(C.byref(s64), C.byref(lib.MpcdTune(1, 0, 0)), out) == 0 and out[0] == 1
     assert L.mpcd_tile_shape(C.byref(s64), C.byref(lib.MpcdTune(8, 0, 0)), out) == -1
+
+
+def binned_layout(systems, prec=None):
+    """mpcd_binned_layout of workload dicts (host only)."""
+    L = lib.load()
+    prec = lib.MPCD_F32 if prec is None else prec
+    nc = np.array([s["ncell"] for s in systems], dtype=np.int32).reshape(-1)
+    Ns = [s["x"].shape[1] for s in systems]
+    Ss = [len(s["sm"]) for s in systems]
+    so = np.concatenate([[0], np.cumsum(Ns)]).astype(np.int64)
+    ss = np.concatenate([[0], np.cumsum(Ss)]).astype(np.int64)
+    C_ = int(sum(int(np.prod(s["ncell"])) for s in systems))
+    s = sys_desc(nsys=len(systems), prec=prec, n_solvent=int(so[-1]), n_sites=int(ss[-1]),
+                 n_bodies=sum(len(x["M"]) for x in systems), n_cells=C_)
+    b = lib.MpcdBinned()
+    rc = L.mpcd_binned_layout(C.byref(s), nc.ctypes.data_as(C.POINTER(C.c_int32)),
+                              so.ctypes.data_as(C.POINTER(C.c_int64)), ss.ctypes.data_as(C.POINTER(C.c_int64)),
+                              C.byref(b))
+    return rc, b, int(so[-1])
+
+
+def test_binned_layout_plan():
+    from paper_2604_14307_amd import workloads as W
+    systems = W.batched_replicas(nrep=8, seed=4)[0]
+    rc, b, N = binned_layout(systems)
+    assert rc == 0
+    # bricks of 8 x 8 x 4 cells at 5 per cell: region capacity 1280 + 6 sigma + 16 per full brick
+    ncells = [int(np.prod(s["ncell"])) for s in systems]
+    assert b.nbricks >= sum(c // 256 for c in ncells)
+    assert N < b.capacity < 1.35 * N + 64 * b.nbricks
+    assert b.items == 4 and b.ws_bytes > 0 and b.site_slots > 0
+    # a denser system gets smaller bricks, not more members per block
+    wl = W.make_system((16, 16, 16), 10, [], np.zeros((0, 3)), np.zeros((0, 4)), np.random.default_rng(1))
+    rc, b10, N10 = binned_layout([wl])
+    assert rc == 0 and b10.nbricks == 32  # 128-cell bricks
+    # inconsistent offsets are rejected
+    s = sys_desc(prec=lib.MPCD_F32)
+    nc = np.array([10, 10, 10], dtype=np.int32)
+    so = np.array([0, 4999], dtype=np.int64)
+    ss = np.array([0, 100], dtype=np.int64)
+    bb = lib.MpcdBinned()
+    assert lib.load().mpcd_binned_layout(C.byref(s), nc.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         so.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         ss.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(bb)) == -1  # MPCD_EINVAL

@@ -14,7 +14,7 @@ compared with the CPU oracle:
   error (solvent and sites together, Sec. II.A), and within stated max-abs
   bounds per observable; particles in cells whose membership differs because
   FP32 rounding of x - s moved a member across a cell boundary are excluded
-  and counted.
+  and counted, and so are bodies with a site in such a cell.
 * FP64, the 512 batched replicas: bit for bit against each replica's oracle
   after four steps of graph replays.
 """
@@ -90,6 +90,14 @@ def oracle_step(wl, state, par, r, step):
     return o, cell.astype(np.int64)
 
 
+def lhat(q, p):
+    """Body-frame angular momentum Lhat_k = p . P_k q / 2 (Miller et al.)."""
+    P1 = np.stack([-q[1], q[0], q[3], -q[2]])
+    P2 = np.stack([-q[2], -q[3], q[0], q[1]])
+    P3 = np.stack([-q[3], q[2], -q[1], q[0]])
+    return 0.5 * np.stack([(p * P1).sum(0), (p * P2).sum(0), (p * P3).sum(0)])
+
+
 class ErrorTally:
     """Accumulates the error of one FP32 step over systems."""
 
@@ -97,7 +105,8 @@ class ErrorTally:
         self.num = self.den = 0.0
         self.excluded = self.total = 0
         self.maxabs = dict.fromkeys(MAXABS, 0.0)
-        self.body_rel = 0.0
+        self.body_rel = self.body_L = 0.0
+        self.bodies_excluded = self.bodies_total = 0
         self.kT = par["kT"]
 
     def add(self, o, cell64, s1, cell32, m_solvent):
@@ -126,14 +135,24 @@ class ErrorTally:
             sig = np.sqrt(self.kT / o.sm)[None, :]
             self.maxabs["v_site"] = max(self.maxabs["v_site"], float((np.abs(s1["vs"] - o.vs) / sig)[:, gt].max()))
         if o.B:
-            scale = np.sqrt(self.kT * o.M)[None, :]
-            self.body_rel = max(self.body_rel, float((np.abs(s1["P"] - o.P) / scale).max()))
+            # bodies whose sites all collided in good cells (a flipped cell
+            # changes a site's impulse at order one)
+            ok = np.array([gt[o.site_off[b]:o.site_off[b + 1]].all() for b in range(o.B)])
+            self.bodies_excluded += int((~ok).sum())
+            self.bodies_total += o.B
+            if ok.any():
+                scale = np.sqrt(self.kT * o.M)[None, :]
+                self.body_rel = max(self.body_rel, float((np.abs(s1["P"] - o.P) / scale)[:, ok].max()))
+                Lg = lhat(s1["q"], s1["p"])
+                sL = np.sqrt(self.kT * np.where(o.I > 0.0, o.I, 1.0))
+                self.body_L = max(self.body_L, float((np.abs(Lg - o.body_angmom_bodyframe()) / sL)[:, ok].max()))
 
     def report(self, label):
         rel = math.sqrt(self.num / self.den)
-        say("%s: rel L2 %.3e, excluded %d of %d, max-abs %s, body P %.2e sqrt(kT M)"
-            % (label, rel, self.excluded, self.total,
-               ", ".join("%s %.2e" % kv for kv in sorted(self.maxabs.items())), self.body_rel))
+        say("%s: rel L2 %.3e, excluded %d of %d, max-abs %s; bodies (%d of %d excluded): P %.2e sqrt(kT M), "
+            "Lhat %.2e sqrt(kT I)" % (label, rel, self.excluded, self.total,
+                                      ", ".join("%s %.2e" % kv for kv in sorted(self.maxabs.items())),
+                                      self.bodies_excluded, self.bodies_total, self.body_rel, self.body_L))
         return rel
 
 
@@ -192,7 +211,9 @@ def test_fp32_bench_form_within_1e5_of_fp64_oracle(ci):
         assert tally.excluded <= 1e-3 * tally.total
         for k, bound in MAXABS.items():
             assert tally.maxabs[k] <= bound, (label, k, tally.maxabs[k])
+        assert tally.bodies_excluded <= 0.05 * tally.bodies_total
         assert tally.body_rel <= 1e-5, (label, tally.body_rel)
+        assert tally.body_L <= 1e-5, (label, tally.body_L)
 
 
 def test_fp64_batched_bench_form_bit_exact():

@@ -73,12 +73,15 @@ def test_nonfinite_velocity_sets_nonfinite():
 
 
 def test_escaping_particle_sets_escape():
-    """|v dt| larger than the box: one periodic correction leaves the particle
-    outside [0, L); the step flags it (and the next binning would put it in
-    cell 0), as the oracle does."""
+    """|v dt| larger than the box: one periodic correction leaves the particles
+    of that cell outside [0, L); the step flags it (and the next binning puts
+    them in cell 0), as the oracle does."""
     wl, par, _ = W.config(0)
     i = far_particle(wl, lo=6.0)
-    wl = with_velocity(wl, i, (150.0, 0.0, 0.0))  # moves 15 cells in a step of a 10-cell box
+    # the cell's mean velocity alone (about 1000 / 5 along x) carries every
+    # member about two box lengths in a step of a 10-cell box, whatever the
+    # rotation and the thermostat do to the relative velocities
+    wl = with_velocity(wl, i, (1000.0, 0.0, 0.0))
     g = gpu_system(wl, par, prec="f64")
     g.body_forces()
     g.step(1)
