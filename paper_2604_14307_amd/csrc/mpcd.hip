@@ -5531,8 +5531,10 @@ int mpcd_binned_init(void *stream, const mpcd_sys *sys, const int32_t *ncell, co
     TRY(hip_check(hipMemcpy(w + L.sys_bb, P.sys_bb.data(), sizeof(int32_t) * P.sys_bb.size(), hipMemcpyHostToDevice)));
     TRY(hip_check(hipMemcpy(w + L.sys_bg, P.sys_bg.data(), sizeof(int32_t) * P.sys_bg.size(), hipMemcpyHostToDevice)));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (int32_t *)(w + L.ctrl), (int64_t)BC_WORDS, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(3 * P.nbricks, 256)), dim3(256), 0, st, (int32_t *)(w + L.cnt),
-                       3 * P.nbricks, 0);  // both parities' fills and the site counts (adjacent)
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * P.nbricks, 256)), dim3(256), 0, st, (int32_t *)(w + L.cnt),
+                       2 * P.nbricks, 0);  // both parities' fills
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(P.nbricks, 256)), dim3(256), 0, st, (int32_t *)(w + L.scnt),
+                       P.nbricks, 0);  // the site counts
     return launch_check();
 }
 

@@ -182,9 +182,10 @@ class GPUSystem:
         in identity order."""
         if self.binned is None:
             return self.x, self.v, self.tag
-        xd = torch.empty((3, self.N), dtype=self.real, device=self.device)
-        vd = torch.empty((3, self.N), dtype=self.real, device=self.device)
-        td = torch.empty((self.N,), dtype=torch.int32, device=self.device)
+        # a particle missing from the binned arrays would stay NaN (tag -1)
+        xd = torch.full((3, self.N), float("nan"), dtype=self.real, device=self.device)
+        vd = torch.full((3, self.N), float("nan"), dtype=self.real, device=self.device)
+        td = torch.full((self.N,), -1, dtype=torch.int32, device=self.device)
         L.check(self.lib.mpcd_binned_unpack(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.v),
                                             _ptr(self.tag), _ptr(xd), _ptr(vd), _ptr(td), _ptr(self.d_step),
                                             _ptr(self.ws), self.ws_bytes, C.byref(self.binned)), "mpcd_binned_unpack")

@@ -65,8 +65,9 @@ def dense_and_binned(systems, par, nsteps, graph=False, check_every=1):
             gd.step(1)
             gb.step(1)
             if (n + 1) % check_every == 0 or n == nsteps - 1:
+                assert gb.status() == 0, "step %d" % n
                 assert_same_states(gd.download(), gb.download(), "step %d" % n)
-    assert gd.status() == 0
+    assert gd.status() == 0 and gb.status() == 0
     return gd, gb
 
 
