@@ -264,6 +264,43 @@ __device__ __forceinline__ uint32_t cell_draw_end(CellDraw &D)
     return st;
 }
 
+// cell_draw in two parts, for a caller that knows the cell's member count
+// only later: cell_draw_pre takes call 0 and forms everything of it that does
+// not depend on the count (the axis, the Box-Muller pair and the two test
+// uniforms); cell_draw_post runs the Marsaglia-Tsang tests on them and, when
+// both reject, continues with calls 1, 2, ... exactly as cell_draw does.  The
+// pair gives cell_draw's values bit for bit.
+struct CellDrawPre {
+    double n[3], z1, z2, u1, u2;
+};
+
+__device__ inline void cell_draw_pre(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica, CellDrawPre &P)
+{
+    const Words w = rng_draw(seed, RNG_CELL, step, cell, replica, 0);
+    axis_from(half32(w, 0), half32(w, 1), P.n);
+    const double rho = sqrt(-2.0 * det_log(unit32(half32(w, 2))));
+    double sn, cs;
+    det_sincos(TWO_PI * unit32(half32(w, 3)), &sn, &cs);
+    P.z1 = rho * cs;
+    P.z2 = rho * sn;
+    P.u1 = unit32(half32(w, 4));
+    P.u2 = unit32(half32(w, 5));
+}
+
+__device__ inline uint32_t cell_draw_post(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
+                                          const CellDrawPre &P, bool want_gamma, double k, CellDraw &D)
+{
+    cell_draw_begin(D, want_gamma, k);
+    D.n[0] = P.n[0];
+    D.n[1] = P.n[1];
+    D.n[2] = P.n[2];
+    D.have_axis = true;
+    if (!D.have_gamma) D.have_gamma = mt_try(P.z1, P.u1, D.d, D.c, &D.g) || mt_try(P.z2, P.u2, D.d, D.c, &D.g);
+    for (int call = 1; !D.have_gamma && call < RNG_MAX_CALLS; ++call)
+        cell_draw_call(D, rng_draw(seed, RNG_CELL, step, cell, replica, (uint64_t)call));
+    return D.have_gamma ? 0u : cell_draw_end(D);
+}
+
 __device__ inline uint32_t cell_draw(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica, bool want_gamma,
                                      double k, CellDraw &D)
 {

@@ -1978,15 +1978,19 @@ MPCD_COLLIDE_PAIR(k_collide_tiled_f64_i4_d, , double, 4, 1)
 //
 // Each system's cells are grouped into bricks of BX x BY x BZ cells (powers of
 // two, chosen per system from its density; narrower at the far faces).  The
-// solvent arrays hold one region of fixed capacity per brick, and a step's
-// solvent lies in the region of the brick of its cell on that step's shifted
-// grid.  The surface sites of each brick are listed in the brick's site slots
-// (filled by the thermalization of the same step).  A region or site list that
-// overflows spills into a shared overflow list.  Region fills are counted per
-// step parity: the step with index t reads the counts of parity t & 1 and its
-// writers count into parity (t + 1) & 1.
+// solvent arrays hold one region per brick, and a step's solvent lies in the
+// region of the brick of its cell on that step's shifted grid.  A region is
+// split into NCLS sub-regions, one per brick that can write into it: the
+// brick itself and its neighbours one brick away along each axis (periodic),
+// the "class" of the writer.  Each sub-region therefore has one writer per
+// step, which stores its fill with a plain store (no device atomics).  A
+// particle that moves farther than a neighbouring brick, or finds its
+// sub-region full, spills into a shared overflow list.  Fills are kept per
+// step parity: the step with index t reads the fills of parity t & 1 and
+// writes parity (t + 1) & 1.  The surface sites of each brick are listed in
+// the brick's site slots by the thermalization of the same step.
 struct BrickInfo {
-    int64_t off;      // first slot of the brick's solvent region
+    int64_t off;      // first slot of the brick's region (its NCLS sub-regions follow)
     int32_t cap;      // region capacity
     int32_t sys;      // system of the brick
     int32_t soff;     // first site slot
@@ -1997,15 +2001,17 @@ struct BrickInfo {
 };
 static_assert(sizeof(BrickInfo) == 32, "brick table entry");
 
+constexpr int NCLS = 27;           // writer classes of a region
 constexpr int BIN_OVF_CAP = 8192;  // solvent overflow entries per parity
 // control words of the binned workspace
 enum { BC_OVF0 = 1, BC_OVF1 = 2, BC_SOVF = 3, BC_WORDS = 16 };
 
 struct BinnedDev {
     const BrickInfo *brick;  // [nbricks]
+    const int32_t *subpre;   // [nbricks][NCLS + 1] first slot of each sub-region within the region
     const int32_t *sys_bb;   // [nsys + 1] first brick of each system
     const int32_t *sys_bg;   // [6 nsys] log2 of the brick extent (3), bricks per axis (3)
-    int32_t *cnt;            // [2 nbricks] solvent per region, by step parity
+    int32_t *cnt;            // [2][nbricks][NCLS] sub-region fills, by step parity
     int32_t *scnt;           // [nbricks] sites per brick
     int32_t *sslot;          // site slots: site index
     int32_t *ctrl;           // [BC_WORDS]
@@ -2016,6 +2022,28 @@ struct BinnedDev {
     int64_t nbricks, cap;    // bricks; slots of one set of solvent arrays
     int32_t sovf_cap;
 };
+
+// Writer class of a region along one axis of nb (periodic) bricks: 0 when the
+// writing brick bs is the region's brick bd, 1 when bs = bd + 1, 2 when
+// bs = bd - 1 (distinct from 1 only for nb >= 3), -1 otherwise.  The class of
+// a region is cx + 3 cy + 9 cz.
+__host__ __device__ __forceinline__ int class_code(int bs, int bd, int nb)
+{
+    int d = bs - bd;
+    if (d < 0) d += nb;
+    if (d == 0) return 0;
+    if (d == 1) return 1;
+    if (d == nb - 1) return 2;
+    return -1;
+}
+
+__host__ __device__ __forceinline__ bool code_valid(int c, int nb) { return c == 0 || (c == 1 && nb >= 2) || (c == 2 && nb >= 3); }
+
+// The region a writing brick at coordinate bs fills with code c (the inverse of class_code).
+__host__ __device__ __forceinline__ int code_dst(int bs, int c, int nb)
+{
+    return c == 0 ? bs : c == 1 ? (bs + nb - 1) % nb : (bs + 1) % nb;
+}
 
 // Cell coordinates of a position on a shifted grid (as the binning computes
 // them) and the brick of that cell; returns the brick index.
@@ -2552,19 +2580,17 @@ __global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double
 
 // Momentum transfer fused with the first half of the body update (one block
 // per body); J and K are also written out.
-// After the brick collision of step t (the step index is still t): clear
-// that step's region fills, the site counts and the input overflow counters,
-// ready for step t + 1's site binning and step t + 1's writers (which count
-// into this parity).  The brick kernel only reads them, so it can be
-// launched again on the same input.
+// After the brick collision of step t (the step index is still t): clear the
+// site counts and the overflow counters that step read, ready for step t+1's
+// site binning and for step t+1's writers (which count into this parity's
+// overflow list).  The sub-region fills need no clearing: every valid
+// sub-region is stored by its writer every step.  The brick kernel only reads
+// these, so it can be launched again on the same input.
 __device__ __forceinline__ void binned_finish(const BinnedDev &bn, uint64_t step)
 {
     const int par = (int)(step & 1);
     const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn.nbricks; q += nt) {
-        bn.cnt[(int64_t)par * bn.nbricks + q] = 0;
-        bn.scnt[q] = 0;
-    }
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn.nbricks; q += nt) bn.scnt[q] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         bn.ctrl[BC_OVF0 + par] = 0;
         bn.ctrl[BC_SOVF] = 0;
@@ -3569,24 +3595,25 @@ int check_ws(const mpcd_sys *s, const void *ws, size_t ws_bytes)
 // ---------------------------------------------------------------------------
 // Binned step: one block per brick.
 //
-// The block loads its brick's members in one coalesced sweep: the region's
-// solvent (position, velocity, identity), the sites listed for the brick and
-// any overflow entries addressed to it, kept in registers (ITEMS per thread).
+// The block loads its brick's members in one sweep: the solvent of the
+// region's sub-regions (position, velocity, identity), the sites listed for
+// the brick and any overflow entries addressed to it, kept in registers
+// (ITEMS per thread).  While those loads are in flight, one lane per cell
+// takes the cell's first random call (axis, Box-Muller pair, test uniforms).
 // Each member's cell on this step's grid is local to the brick, so the cell
 // sums are complete in LDS (FP32: exact int64 fixed-point sums with LDS
-// atomics).  One lane per cell draws the cell's axis and thermostat variate
-// and forms u and lambda R; every member is rotated, the sites' velocities are
-// written back to the site arrays, and the solvent is streamed and written
-// straight into the region of its brick on the NEXT step's grid: the block
-// counts its members per destination brick in LDS, takes one device atomic
-// per distinct destination for the base slot, and writes each member at base
-// + rank.  The solvent therefore crosses HBM once per step (read and written
-// once), with no cell lists, scan, scatter or permutation.  A brick with more
-// members than the block holds in registers takes a two-pass path (sums, then
-// a second load to rotate and write).
+// atomics).  One lane per cell then finishes the thermostat variate from its
+// member count and forms u and lambda R; every member is rotated, the sites'
+// velocities are written back to the site arrays, and the solvent is
+// streamed and written straight into the region of its brick on the NEXT
+// step's grid, in the sub-region of this brick's class there, at the rank
+// an LDS counter gives it.  The block stores the fill of each sub-region it
+// writes.  The solvent therefore crosses HBM once per step (read and written
+// once), with no cell lists, scan, scatter, permutation or device atomics.
+// A brick with more members than the block holds in registers takes a
+// two-pass path (sums, then a second load to rotate and write).
 constexpr int BRICK_T = 512;     // threads of a brick block
 constexpr int BRICK_MAXC = 256;  // cells per brick at most (one lane per cell)
-constexpr int DEST_HT = 64;      // destination-brick hash slots per block
 constexpr int BRICK_OVL = 512;   // overflow entries per brick and kind a block takes
 constexpr int BRICK_ITEMS_F32 = 4;
 
@@ -3614,25 +3641,35 @@ struct BrickLds32 {
     unsigned long long acc[5 * BRICK_MAXC];
     int cnt[BRICK_MAXC];
     float par[12 * BRICK_MAXC];
-    int32_t dkey[DEST_HT], dcnt[DEST_HT], dcap[DEST_HT];
-    int64_t doff[DEST_HT];
+    CellDrawPre pre[BRICK_MAXC];
+    int cin[NCLS], cpre[NCLS + 1];  // input sub-region fills and their prefix
+    int32_t csub[NCLS + 1];         // this brick's sub-region offsets
+    int wcnt[NCLS];                 // members written per class of this brick
+    int32_t wdst[NCLS], wcap[NCLS]; // the region written with each class, its sub-region capacity
+    int64_t woff[NCLS];             // and its first slot
     int32_t lovf[BRICK_OVL], lsovf[BRICK_OVL];
     double sh[3], sh1[3];
-    int hdr[8];
+    int hdr[8];  // region members, sites, overflow solvent, overflow sites, their list lengths
 };
 
-// Member i of the brick: region solvent, listed sites, then overflow solvent
-// and overflow sites; id is the solvent identity, or -(site + 1).
+// Member i of the brick: region solvent (sub-region by sub-region), listed
+// sites, then overflow solvent and overflow sites; id is the solvent identity,
+// or -(site + 1).
 template <typename Real>
 __device__ __forceinline__ bool brick_member(const BrickArgs<Real> &A, const BrickInfo &bi, int par_in, int i,
-                                             const int *hdr, const int32_t *lovf, const int32_t *lsovf, Real p[3],
-                                             Real w[3], int32_t &id, uint32_t &st)
+                                             const BrickLds32 &L, Real p[3], Real w[3], int32_t &id, uint32_t &st)
 {
     const int64_t cap = A.bn.cap, S = A.s.S;
-    const int nreg = hdr[0], nsite = hdr[1], novf = hdr[2];
+    const int nreg = L.hdr[0], nsite = L.hdr[1], novf = L.hdr[2];
     int64_t j = -1;
     if (i < nreg) {
-        const int64_t q = bi.off + i;
+        int lo = 0, hi = NCLS - 1;  // the last sub-region c with cpre[c] <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.cpre[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t q = bi.off + L.csub[lo] + (i - L.cpre[lo]);
         p[0] = A.x[q]; p[1] = A.x[cap + q]; p[2] = A.x[2 * cap + q];
         w[0] = A.v[q]; w[1] = A.v[cap + q]; w[2] = A.v[2 * cap + q];
         id = A.tag[q];
@@ -3641,18 +3678,17 @@ __device__ __forceinline__ bool brick_member(const BrickArgs<Real> &A, const Bri
     if (i < nreg + nsite) {
         j = A.bn.sslot[bi.soff + (i - nreg)];
     } else if (i < nreg + nsite + novf) {
-        const int64_t e = (int64_t)par_in * BIN_OVF_CAP + lovf[i - nreg - nsite];
+        const int64_t k = L.lovf[i - nreg - nsite];
         const Real *o = (const Real *)A.bn.ovf_xv + (int64_t)par_in * 6 * BIN_OVF_CAP;
-        const int64_t k = lovf[i - nreg - nsite];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             p[d] = o[d * BIN_OVF_CAP + k];
             w[d] = o[(3 + d) * BIN_OVF_CAP + k];
         }
-        id = A.bn.ovf_tag[e];
+        id = A.bn.ovf_tag[(int64_t)par_in * BIN_OVF_CAP + k];
         return true;
     } else {
-        j = A.bn.sovf[2 * lsovf[i - nreg - nsite - novf] + 1];
+        j = A.bn.sovf[2 * L.lsovf[i - nreg - nsite - novf] + 1];
     }
     if (j < 0 || j >= S) {
         st |= ST_BINERR;
@@ -3680,19 +3716,25 @@ __device__ __forceinline__ int brick_local_cell(const SysDev &s, const BinnedDev
     return ((jc[2] - bi.org[2]) * bi.dim[1] + (jc[1] - bi.org[1])) * bi.dim[0] + (jc[0] - bi.org[0]);
 }
 
-// Per-cell FP32 parameters from the exact fixed-point sums (u and lambda R
-// rounded to float), the draws made here from the cell's stream.
-__device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const BrickInfo &bi, int c, int n,
-                                                      const unsigned long long *acc, double ca, double sa,
-                                                      double kT_cell, uint64_t seed, uint64_t step, float *par,
-                                                      uint32_t &st)
+// The canonical index (within its system) of cell c of a brick.
+__device__ __forceinline__ uint64_t brick_cell_canonical(const SysDev &s, const BrickInfo &bi, int c)
 {
     const int r = bi.sys;
     const int cx = c % bi.dim[0], cy = (c / bi.dim[0]) % bi.dim[1], cz = c / (bi.dim[0] * bi.dim[1]);
     const int nx = s.ncell[3 * r], ny = s.ncell[3 * r + 1];
-    const uint64_t cl = (uint64_t)(((int64_t)(bi.org[2] + cz) * ny + (bi.org[1] + cy)) * nx + (bi.org[0] + cx));
+    return (uint64_t)(((int64_t)(bi.org[2] + cz) * ny + (bi.org[1] + cy)) * nx + (bi.org[0] + cx));
+}
+
+// Per-cell FP32 parameters from the exact fixed-point sums (u and lambda R
+// rounded to float), the draws finished from the cell's first call.
+__device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const BrickInfo &bi, int c, int n,
+                                                      const unsigned long long *acc, const CellDrawPre &P, double ca,
+                                                      double sa, double kT_cell, uint64_t seed, uint64_t step,
+                                                      float *par, uint32_t &st)
+{
     CellDraw D;
-    st |= cell_draw(seed, step, cl, s.replica0 + (uint64_t)r, kT_cell > 0.0, 0.5 * (double)(3 * (n - 1)), D);
+    st |= cell_draw_post(seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)bi.sys, P, kT_cell > 0.0,
+                         0.5 * (double)(3 * (n - 1)), D);
     long long q[5];
 #pragma unroll
     for (int z = 0; z < 5; ++z) q[z] = (long long)acc[5 * c + z];
@@ -3724,11 +3766,12 @@ __device__ __forceinline__ void brick_rotate_f32(const float *par, float w[3], u
     }
 }
 
-// Streaming of a solvent member (position and velocity in place) and its
-// brick on the next step's grid.
+// Streaming of a solvent member (position and velocity in place) and the
+// class of this brick in the region of its brick on the next step's grid (-1
+// beyond the neighbouring bricks; *dst receives that brick).
 template <typename Real>
-__device__ __forceinline__ int32_t brick_stream(const BrickArgs<Real> &A, int r, const Real L[3], Real p[3], Real w[3],
-                                                const double *sh1, uint32_t &st)
+__device__ __forceinline__ int brick_stream(const BrickArgs<Real> &A, const BrickInfo &bi, const Real L[3], Real p[3],
+                                            Real w[3], const double *sh1, int32_t *dst, uint32_t &st)
 {
     const Real dtr = (Real)A.dt;
 #pragma unroll
@@ -3742,11 +3785,21 @@ __device__ __forceinline__ int32_t brick_stream(const BrickArgs<Real> &A, int r,
     }
     int jc[3];
     const double shv[3] = {sh1[0], sh1[1], sh1[2]};
-    return brick_of_pos<Real>(A.s, A.bn, r, p[0], p[1], p[2], shv, jc, st);
+    *dst = brick_of_pos<Real>(A.s, A.bn, bi.sys, p[0], p[1], p[2], shv, jc, st);
+    const int32_t *g = A.bn.sys_bg + 6 * bi.sys;
+    int cls = 0, mul = 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int c = class_code(bi.org[d] >> g[d], jc[d] >> g[d], g[3 + d]);
+        if (c < 0) return -1;
+        cls += c * mul;
+        mul *= 3;
+    }
+    return cls;
 }
 
-// Write one new solvent member into slot `slot` of brick b's region of the
-// output, or into the overflow list when the region is full.
+// Write one new solvent member into slot `slot` of the sub-region at `off` (of
+// capacity `cap`) of the output, or into the overflow list for brick b.
 template <typename Real>
 __device__ __forceinline__ void brick_put(const BrickArgs<Real> &A, int par_out, int32_t b, int64_t off, int32_t cap,
                                           int32_t slot, const Real p[3], const Real w[3], int32_t id, uint32_t &st)
@@ -3777,6 +3830,20 @@ __device__ __forceinline__ void brick_put(const BrickArgs<Real> &A, int par_out,
     A.bn.ovf_dest[(int64_t)par_out * BIN_OVF_CAP + e] = b;
 }
 
+// A streamed solvent member into its class's sub-region of the next step's
+// region (rank from the block's LDS counter), or the overflow list.
+template <typename Real>
+__device__ __forceinline__ void brick_emit(const BrickArgs<Real> &A, BrickLds32 &L, int par_out, int cls, int32_t dst,
+                                           const Real p[3], const Real w[3], int32_t id, uint32_t &st)
+{
+    if (cls < 0) {
+        brick_put<Real>(A, par_out, dst, 0, 0, 0, p, w, id, st);  // beyond the neighbouring bricks
+        return;
+    }
+    const int rank = atomicAdd(&L.wcnt[cls], 1);
+    brick_put<Real>(A, par_out, dst, L.woff[cls], L.wcap[cls], rank, p, w, id, st);
+}
+
 template <int ITEMS>
 __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) void k_brick_collide_f32(BrickArgs<float> A)
 {
@@ -3798,27 +3865,57 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
         const BrickInfo bi = bn.brick[b];
         const int r = bi.sys;
         const int ncb = bi.dim[0] * bi.dim[1] * bi.dim[2];
-        if (t == 0) {
-            const int nr = bn.cnt[(int64_t)par_in * bn.nbricks + b], ns = bn.scnt[b];
-            L.hdr[0] = min(nr, bi.cap);
-            L.hdr[1] = min(ns, bi.scap);
+        const int32_t *g = bn.sys_bg + 6 * r;
+        if (t < NCLS) {
+            // input fills of the valid sub-regions; the region each class of
+            // this brick writes, with its first slot and capacity
+            const int c3[3] = {t % 3, (t / 3) % 3, t / 9};
+            const bool valid = code_valid(c3[0], g[3]) && code_valid(c3[1], g[4]) && code_valid(c3[2], g[5]);
+            const int32_t *sp = bn.subpre + b * (NCLS + 1);
+            const int s0 = sp[t], s1 = sp[t + 1];
+            L.csub[t] = s0;
+            if (t == NCLS - 1) L.csub[NCLS] = s1;
+            L.cin[t] = valid ? min(bn.cnt[((int64_t)par_in * bn.nbricks + b) * NCLS + t], s1 - s0) : 0;
+            L.wcnt[t] = 0;
+            int32_t db = -1;
+            if (valid) {
+                int bc[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) bc[d] = code_dst(bi.org[d] >> g[d], c3[d], g[3 + d]);
+                db = bn.sys_bb[r] + (bc[2] * g[4] + bc[1]) * g[3] + bc[0];
+                const int32_t *dp = bn.subpre + (int64_t)db * (NCLS + 1);
+                L.woff[t] = bn.brick[db].off + dp[t];
+                L.wcap[t] = dp[t + 1] - dp[t];
+            } else {
+                L.woff[t] = 0;
+                L.wcap[t] = 0;
+            }
+            L.wdst[t] = db;
+        }
+        if (t == 64) {
+            L.hdr[1] = min(bn.scnt[b], (int)bi.scap);
             L.hdr[2] = 0;
             L.hdr[3] = 0;
             L.hdr[4] = min(bn.ctrl[BC_OVF0 + par_in], BIN_OVF_CAP);
             L.hdr[5] = min(bn.ctrl[BC_SOVF], bn.sovf_cap);
         }
-        if (t == 64) shift_of(s, A.seed, step, r, L.sh);
-        if (t == 128) shift_of(s, A.seed, step + 1, r, L.sh1);
+        if (t == 128) shift_of(s, A.seed, step, r, L.sh);
+        if (t == 192) shift_of(s, A.seed, step + 1, r, L.sh1);
         for (int c = t; c < ncb; c += BRICK_T) {
             L.cnt[c] = 0;
 #pragma unroll
             for (int z = 0; z < 5; ++z) L.acc[5 * c + z] = 0ull;
         }
-        if (t < DEST_HT) {
-            L.dkey[t] = -1;
-            L.dcnt[t] = 0;
-        }
         __syncthreads();
+        if (t == 0) {
+            int a = 0;
+            for (int c = 0; c < NCLS; ++c) {
+                L.cpre[c] = a;
+                a += L.cin[c];
+            }
+            L.cpre[NCLS] = a;
+            L.hdr[0] = a;
+        }
         // overflow entries addressed to this brick (the lists are nearly always empty)
         for (int e = t; e < L.hdr[4]; e += BRICK_T)
             if (bn.ovf_dest[(int64_t)par_in * BIN_OVF_CAP + e] == (int32_t)b) {
@@ -3852,9 +3949,11 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 const int i = t + k * BRICK_T;
                 lc[k] = -1;
                 id[k] = 0;
-                if (i < nmem && brick_member<float>(A, bi, par_in, i, L.hdr, L.lovf, L.lsovf, p[k], w[k], id[k], st))
-                    lc[k] = 0;
+                if (i < nmem && brick_member<float>(A, bi, par_in, i, L, p[k], w[k], id[k], st)) lc[k] = 0;
             }
+            // the cells' first random calls while the member loads are in flight
+            for (int c = t; c < ncb; c += BRICK_T)
+                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.pre[c]);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
@@ -3871,15 +3970,11 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
             __syncthreads();
             for (int c = t; c < ncb; c += BRICK_T)
                 if (L.cnt[c] >= 2)
-                    brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, A.cos_a, A.sin_a, A.kT_cell, A.seed, step,
-                                          L.par + 12 * c, st);
+                    brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, L.pre[c], A.cos_a, A.sin_a, A.kT_cell, A.seed,
+                                          step, L.par + 12 * c, st);
             __syncthreads();
-            int32_t dst[ITEMS], hs[ITEMS], rk[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
-                dst[k] = -1;
-                hs[k] = -1;
-                rk[k] = 0;
                 if (lc[k] < 0) continue;
                 if (L.cnt[lc[k]] >= 2) brick_rotate_f32(L.par + 12 * lc[k], w[k], st);
                 if (id[k] < 0) {  // a site: its new velocity back to the site arrays
@@ -3887,48 +3982,19 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                     A.vs[j] = w[k][0]; A.vs[S + j] = w[k][1]; A.vs[2 * S + j] = w[k][2];
                     continue;
                 }
-                dst[k] = brick_stream<float>(A, r, Lb, p[k], w[k], L.sh1, st);
-                // count per destination brick in LDS (linear probing; a full
-                // table sends the member to its own device atomic)
-                uint32_t h = ((uint32_t)dst[k] * 2654435761u) >> (32 - 6);
-                for (int probe = 0; probe < DEST_HT; ++probe) {
-                    const int32_t old = atomicCAS(&L.dkey[h], -1, dst[k]);
-                    if (old == -1 || old == dst[k]) {
-                        hs[k] = (int)h;
-                        rk[k] = atomicAdd(&L.dcnt[h], 1);
-                        break;
-                    }
-                    h = (h + 1) & (DEST_HT - 1);
-                }
-            }
-            __syncthreads();
-            if (t < DEST_HT && L.dkey[t] >= 0) {  // one device atomic per destination brick
-                const int32_t db = L.dkey[t];
-                const BrickInfo di = bn.brick[db];
-                L.doff[t] = di.off;
-                L.dcap[t] = di.cap;
-                L.dcnt[t] = atomicAdd(&bn.cnt[(int64_t)par_out * bn.nbricks + db], L.dcnt[t]);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < ITEMS; ++k) {
-                if (dst[k] < 0) continue;
-                if (hs[k] >= 0) {
-                    brick_put<float>(A, par_out, dst[k], L.doff[hs[k]], L.dcap[hs[k]], L.dcnt[hs[k]] + rk[k], p[k],
-                                     w[k], id[k], st);
-                } else {
-                    const BrickInfo di = bn.brick[dst[k]];
-                    const int slot = atomicAdd(&bn.cnt[(int64_t)par_out * bn.nbricks + dst[k]], 1);
-                    brick_put<float>(A, par_out, dst[k], di.off, di.cap, slot, p[k], w[k], id[k], st);
-                }
+                int32_t dst;
+                const int cls = brick_stream<float>(A, bi, Lb, p[k], w[k], L.sh1, &dst, st);
+                brick_emit<float>(A, L, par_out, cls, dst, p[k], w[k], id[k], st);
             }
         } else {
             // more members than the block holds: sums over chunks of the
             // member list, then a second load of each member to rotate it
+            for (int c = t; c < ncb; c += BRICK_T)
+                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.pre[c]);
             for (int i = t; i < nmem; i += BRICK_T) {
                 float p[3], w[3];
                 int32_t id;
-                if (!brick_member<float>(A, bi, par_in, i, L.hdr, L.lovf, L.lsovf, p, w, id, st)) continue;
+                if (!brick_member<float>(A, bi, par_in, i, L, p, w, id, st)) continue;
                 const int c = brick_local_cell<float>(s, bn, bi, b, p, L.sh, st);
                 if (c < 0) continue;
                 const double mk = id >= 0 ? s.m : A.site_m[-(int64_t)id - 1];
@@ -3941,15 +4007,15 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
             __syncthreads();
             for (int c = t; c < ncb; c += BRICK_T)
                 if (L.cnt[c] >= 2)
-                    brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, A.cos_a, A.sin_a, A.kT_cell, A.seed, step,
-                                          L.par + 12 * c, st);
+                    brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, L.pre[c], A.cos_a, A.sin_a, A.kT_cell, A.seed,
+                                          step, L.par + 12 * c, st);
             __syncthreads();
             // second load: each member is read again before its own write (a
             // site appears once in a brick's list)
             for (int i = t; i < nmem; i += BRICK_T) {
                 float p[3], w[3];
                 int32_t id;
-                if (!brick_member<float>(A, bi, par_in, i, L.hdr, L.lovf, L.lsovf, p, w, id, st)) continue;
+                if (!brick_member<float>(A, bi, par_in, i, L, p, w, id, st)) continue;
                 const int c = brick_local_cell<float>(s, bn, bi, b, p, L.sh, st);
                 if (c < 0) continue;
                 if (L.cnt[c] >= 2) brick_rotate_f32(L.par + 12 * c, w, st);
@@ -3958,12 +4024,15 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                     A.vs[j] = w[0]; A.vs[S + j] = w[1]; A.vs[2 * S + j] = w[2];
                     continue;
                 }
-                const int32_t db = brick_stream<float>(A, r, Lb, p, w, L.sh1, st);
-                const BrickInfo di = bn.brick[db];
-                const int slot = atomicAdd(&bn.cnt[(int64_t)par_out * bn.nbricks + db], 1);
-                brick_put<float>(A, par_out, db, di.off, di.cap, slot, p, w, id, st);
+                int32_t dst;
+                const int cls = brick_stream<float>(A, bi, Lb, p, w, L.sh1, &dst, st);
+                brick_emit<float>(A, L, par_out, cls, dst, p, w, id, st);
             }
         }
+        __syncthreads();
+        // the fill of every sub-region this brick writes (zero included)
+        if (t < NCLS && L.wdst[t] >= 0)
+            bn.cnt[((int64_t)par_out * bn.nbricks + L.wdst[t]) * NCLS + t] = L.wcnt[t];
     }
     flag(A.status, st);
 }
@@ -3978,16 +4047,12 @@ __global__ void k_binned_clear_sites(BinnedDev bn)
     if (blockIdx.x == 0 && threadIdx.x == 0) bn.ctrl[BC_SOVF] = 0;
 }
 
-// The next step's fills and output overflow counter cleared, for a brick
-// collision launched on its own (the step sequence has them clear already).
+// The output overflow counter cleared, for a brick collision launched on its
+// own (in the step sequence it is clear already).
 __global__ void k_binned_clear_out(BinnedDev bn, const uint64_t *d_step)
 {
-    const int par = (int)((*d_step + 1) & 1);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn.nbricks; q += (int64_t)gridDim.x * blockDim.x)
-        bn.cnt[(int64_t)par * bn.nbricks + q] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) bn.ctrl[BC_OVF0 + par] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) bn.ctrl[BC_OVF0 + (int)((*d_step + 1) & 1)] = 0;
 }
-
 
 // Thermalization of each body's sites for the step and their binning into the
 // bricks' site lists (binned layout); one block per body.
@@ -4059,8 +4124,9 @@ __global__ void k_binned_pack(SysDev s, BinnedDev bn, uint64_t seed, const uint6
         int jc[3];
         const int32_t b = brick_of_pos<Real>(s, bn, r, p[0], p[1], p[2], sh, jc, st);
         const BrickInfo bi = bn.brick[b];
-        const int slot = atomicAdd(&bn.cnt[(int64_t)par * bn.nbricks + b], 1);
-        brick_put<Real>(A, par, b, bi.off, bi.cap, slot, p, w, tag ? tag[i] : (int32_t)i, st);
+        const int32_t *sp = bn.subpre + (int64_t)b * (NCLS + 1);  // class 0: the brick's own sub-region
+        const int slot = atomicAdd(&bn.cnt[((int64_t)par * bn.nbricks + b) * NCLS], 1);
+        brick_put<Real>(A, par, b, bi.off + sp[0], sp[1] - sp[0], slot, p, w, tag ? tag[i] : (int32_t)i, st);
     }
     flag(status, st);
 }
@@ -4088,11 +4154,14 @@ __global__ void k_binned_unpack(SysDev s, BinnedDev bn, const uint64_t *d_step, 
     };
     for (int64_t b = blockIdx.x; b < bn.nbricks; b += gridDim.x) {
         const BrickInfo bi = bn.brick[b];
-        const int n = min(bn.cnt[(int64_t)par * bn.nbricks + b], bi.cap);
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const int64_t q = bi.off + i;
-            const Real p[3] = {xb[q], xb[C + q], xb[2 * C + q]}, w[3] = {vb[q], vb[C + q], vb[2 * C + q]};
-            put(tagb[q], p, w);
+        const int32_t *sp = bn.subpre + b * (NCLS + 1);
+        for (int c = 0; c < NCLS; ++c) {  // fills of sub-regions without a writer stay zero
+            const int n = min(bn.cnt[((int64_t)par * bn.nbricks + b) * NCLS + c], sp[c + 1] - sp[c]);
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int64_t q = bi.off + sp[c] + i;
+                const Real p[3] = {xb[q], xb[C + q], xb[2 * C + q]}, w[3] = {vb[q], vb[C + q], vb[2 * C + q]};
+                put(tagb[q], p, w);
+            }
         }
     }
     const int novf = min(bn.ctrl[BC_OVF0 + par], BIN_OVF_CAP);
@@ -4138,9 +4207,14 @@ int check_bodies(const mpcd_sys *s, const mpcd_bodies *b)
 // Brick shapes, log2 of the extent along x, y, z, largest first (256 .. 8 cells).
 constexpr int BRICK_SHAPES[6][3] = {{3, 3, 2}, {3, 2, 2}, {2, 2, 2}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
 
-// Region capacity for mu expected members: mu + 6 sqrt(mu) + 16 (a Poisson
-// count exceeds it with probability below 1e-9); site list capacity: the
-// brick's cells + 64, at most the system's sites.
+// Sub-region capacity for mu expected members: mu + 6 sqrt(mu) + 16 (a
+// Poisson count exceeds it with probability below 1e-9); site list capacity:
+// the brick's cells + 64, at most the system's sites.  The brick's own class
+// expects the whole brick; a neighbour's class the solvent of a layer of
+// depth SUBREGION_DEPTH cells along each axis where the two bricks differ (a
+// step's shift change moves cell boundaries by less than one cell, and
+// streaming moves a particle by |v| dt, about 0.1 cells at kT = 1).
+constexpr double SUBREGION_DEPTH = 1.25;
 int64_t region_cap(double mu) { return (int64_t)ceil(mu + 6.0 * sqrt(mu)) + 16; }
 int64_t site_cap(int64_t ncb, int64_t S_r) { return ncb + 64 < S_r ? ncb + 64 : S_r; }
 
@@ -4157,7 +4231,7 @@ struct BinnedPlan {
     int64_t nbricks = 0, cap = 0, sslots = 0;
     int32_t sovf_cap = 0;
     std::vector<BrickInfo> brick;
-    std::vector<int32_t> sys_bb, sys_bg;
+    std::vector<int32_t> subpre, sys_bb, sys_bg;
 };
 
 // tables == false: sizes only.
@@ -4175,6 +4249,7 @@ int binned_plan(const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_o
         P.sys_bb.assign(nsys + 1, 0);
         P.sys_bg.assign(6 * (size_t)nsys, 0);
         P.brick.clear();
+        P.subpre.clear();
     }
     for (int r = 0; r < nsys; ++r) {
         const int n[3] = {ncell[3 * r], ncell[3 * r + 1], ncell[3 * r + 2]};
@@ -4207,8 +4282,24 @@ int binned_plan(const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_o
                     int dim[3];
                     for (int d = 0; d < 3; ++d) dim[d] = std::min(1 << lg[d], n[d] - o[d]);
                     const int64_t ncb = (int64_t)dim[0] * dim[1] * dim[2];
-                    const int64_t cs = region_cap(rho * (double)ncb), ct = site_cap(ncb, Sr);
+                    // sub-regions: one per writer class with a distinct writer
+                    int64_t cs = 0;
+                    int32_t pre[NCLS + 1];
+                    for (int c = 0; c < NCLS; ++c) {
+                        const int c3[3] = {c % 3, (c / 3) % 3, c / 9};
+                        double vol = 1.0;
+                        bool valid = true;
+                        for (int d = 0; d < 3; ++d) {
+                            valid = valid && code_valid(c3[d], nb[d]);
+                            vol *= c3[d] == 0 ? (double)dim[d] : SUBREGION_DEPTH;
+                        }
+                        pre[c] = (int32_t)cs;
+                        if (valid) cs += region_cap(rho * vol);
+                    }
+                    pre[NCLS] = (int32_t)cs;
+                    const int64_t ct = site_cap(ncb, Sr);
                     if (tables) {
+                        P.subpre.insert(P.subpre.end(), pre, pre + NCLS + 1);
                         BrickInfo bi;
                         bi.off = P.cap;
                         bi.cap = (int32_t)cs;
@@ -4236,7 +4327,7 @@ int binned_plan(const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_o
 }
 
 struct BinnedLayout {
-    size_t ctrl, brick, sys_bb, sys_bg, cnt, scnt, sslot, ovf_dest, ovf_tag, ovf_xv, sovf, total;
+    size_t ctrl, brick, subpre, sys_bb, sys_bg, cnt, scnt, sslot, ovf_dest, ovf_tag, ovf_xv, sovf, total;
 };
 
 BinnedLayout binned_layout(const mpcd_sys *sys, int64_t nbricks, int64_t sslots, int32_t sovf_cap)
@@ -4250,9 +4341,10 @@ BinnedLayout binned_layout(const mpcd_sys *sys, int64_t nbricks, int64_t sslots,
     };
     L.ctrl = take(sizeof(int32_t) * BC_WORDS);
     L.brick = take(sizeof(BrickInfo) * (size_t)nbricks);
+    L.subpre = take(sizeof(int32_t) * (NCLS + 1) * (size_t)nbricks);
     L.sys_bb = take(sizeof(int32_t) * (size_t)(sys->nsys + 1));
     L.sys_bg = take(sizeof(int32_t) * 6 * (size_t)sys->nsys);
-    L.cnt = take(sizeof(int32_t) * 2 * (size_t)nbricks);
+    L.cnt = take(sizeof(int32_t) * 2 * NCLS * (size_t)nbricks);
     L.scnt = take(sizeof(int32_t) * (size_t)nbricks);
     L.sslot = take(sizeof(int32_t) * (size_t)(sslots > 0 ? sslots : 1));
     L.ovf_dest = take(sizeof(int32_t) * 2 * BIN_OVF_CAP);
@@ -4278,6 +4370,7 @@ BinnedDev binned_dev(const mpcd_sys *sys, const mpcd_binned *b)
     char *w = (char *)b->ws;
     d.ctrl = (int32_t *)(w + L.ctrl);
     d.brick = (const BrickInfo *)(w + L.brick);
+    d.subpre = (const int32_t *)(w + L.subpre);
     d.sys_bb = (const int32_t *)(w + L.sys_bb);
     d.sys_bg = (const int32_t *)(w + L.sys_bg);
     d.cnt = (int32_t *)(w + L.cnt);
@@ -5528,11 +5621,12 @@ int mpcd_binned_init(void *stream, const mpcd_sys *sys, const int32_t *ncell, co
     // every launch before this copy has finished; the copy blocks until done
     TRY(hip_check(hipStreamSynchronize(st)));
     TRY(hip_check(hipMemcpy(w + L.brick, P.brick.data(), sizeof(BrickInfo) * P.brick.size(), hipMemcpyHostToDevice)));
+    TRY(hip_check(hipMemcpy(w + L.subpre, P.subpre.data(), sizeof(int32_t) * P.subpre.size(), hipMemcpyHostToDevice)));
     TRY(hip_check(hipMemcpy(w + L.sys_bb, P.sys_bb.data(), sizeof(int32_t) * P.sys_bb.size(), hipMemcpyHostToDevice)));
     TRY(hip_check(hipMemcpy(w + L.sys_bg, P.sys_bg.data(), sizeof(int32_t) * P.sys_bg.size(), hipMemcpyHostToDevice)));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (int32_t *)(w + L.ctrl), (int64_t)BC_WORDS, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * P.nbricks, 256)), dim3(256), 0, st, (int32_t *)(w + L.cnt),
-                       2 * P.nbricks, 0);  // both parities' fills
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * NCLS * P.nbricks, 256)), dim3(256), 0, st,
+                       (int32_t *)(w + L.cnt), 2 * NCLS * P.nbricks, 0);  // both parities' fills
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(P.nbricks, 256)), dim3(256), 0, st, (int32_t *)(w + L.scnt),
                        P.nbricks, 0);  // the site counts
     return launch_check();
@@ -5555,7 +5649,8 @@ int mpcd_binned_pack(void *stream, const mpcd_sys *sys, const void *x, const voi
     hipStream_t st = (hipStream_t)stream;
     uint32_t *status = at<uint32_t>(ws, layout_of(sys).status);
     // clear both parities' fills and overflow counters: the step parity is read on the device
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * bn.nbricks, 256)), dim3(256), 0, st, bn.cnt, 2 * bn.nbricks, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * NCLS * bn.nbricks, 256)), dim3(256), 0, st, bn.cnt,
+                       2 * NCLS * bn.nbricks, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, bn.ctrl + BC_OVF0, (int64_t)2, 0);
     if (N > 0) {
         const unsigned g = grid_for(N, 256, 1 << 16);
