@@ -1436,9 +1436,17 @@ __device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double
     cell_stream_global<double>(A, gc, vel, x, O, st);
 }
 
-constexpr double FIX_SCALE = 0x1p32, FIX_LIM = 0x1p62;
+// FP32 form: per-member fixed-point terms m, m v (3) and m |v|^2, each formed
+// in double and rounded once to the nearest multiple of 2^-32 (ties to even)
+// into int64, so that the per-cell sums are exact and independent of order.
+// The fine unit matters for the thermostat: a cell's relative kinetic energy
+// is the difference of two sums, and in a cell of nearly equal velocities it
+// is small.  A member whose term reaches 2^62 units adds nothing and sets
+// FIXOVF.
+constexpr double FIX_SCALE = 0x1p32, FIX_UNIT = 0x1p-32, FIX_LIM = 0x1p62;
 
-// FP32 fixed-point contributions of one particle: m, m v (3), m |v|^2.
+__device__ __forceinline__ long long fix_round(double a) { return __double2ll_rn(a); }
+
 __device__ __forceinline__ void fixed_terms(double mk, float fv0, float fv1, float fv2, long long q[5],
                                             uint32_t &st)
 {
@@ -1450,11 +1458,20 @@ __device__ __forceinline__ void fixed_terms(double mk, float fv0, float fv1, flo
         q[0] = q[1] = q[2] = q[3] = q[4] = 0;
         return;
     }
-    q[0] = __double2ll_rn(mk * FIX_SCALE);
-    q[1] = __double2ll_rn(a0);
-    q[2] = __double2ll_rn(a1);
-    q[3] = __double2ll_rn(a2);
-    q[4] = __double2ll_rn(ak);
+    q[0] = fix_round(mk * FIX_SCALE);
+    q[1] = fix_round(a0);
+    q[2] = fix_round(a1);
+    q[3] = fix_round(a2);
+    q[4] = fix_round(ak);
+}
+
+// Relative kinetic energy of a cell, 1/2 (sum m |v|^2 - |sum m v|^2 / sum m),
+// from its fixed-point sums.
+__device__ __forceinline__ double fixed_energy(const long long q[5])
+{
+    const double Mu = (double)q[0] * FIX_UNIT;
+    const double P0 = (double)q[1] * FIX_UNIT, P1 = (double)q[2] * FIX_UNIT, P2 = (double)q[3] * FIX_UNIT;
+    return 0.5 * ((double)q[4] * FIX_UNIT - ((P0 * P0 + P1 * P1) + P2 * P2) / Mu);
 }
 
 // Per-cell FP32 collision parameters from exact fixed-point sums: u and
@@ -1470,8 +1487,7 @@ __device__ __forceinline__ void f32_cell_params(const CollideArgs &A, int64_t gc
     const Rot R = rotation(nax, A.cos_a, A.sin_a);
     double lam = 1.0;
     if (A.kT_cell > 0.0) {
-        const double P0 = (double)q[1] * 0x1p-32, P1 = (double)q[2] * 0x1p-32, P2 = (double)q[3] * 0x1p-32;
-        const double E = 0.5 * ((double)q[4] * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
+        const double E = fixed_energy(q);
         lam = thermostat_factor(A, gvar, E);
     }
 #pragma unroll
@@ -1752,8 +1768,7 @@ __device__ __forceinline__ void collide_tile(const CollideArgs &A, const TileCfg
                 const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
                 double lam = 1.0;
                 if (A.kT_cell > 0.0) {
-                    const double P0 = (double)q[1] * 0x1p-32, P1 = (double)q[2] * 0x1p-32, P2 = (double)q[3] * 0x1p-32;
-                    const double E = 0.5 * ((double)q[4] * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
+                    const double E = fixed_energy(q);
                     if (E > 0.0) lam = sqrt((A.kT_cell * gvar) / E);
                 }
                 par[0] = (float)u0; par[1] = (float)u1; par[2] = (float)u2;
@@ -3663,11 +3678,15 @@ __device__ __forceinline__ bool brick_member(const BrickArgs<Real> &A, const Bri
     const int nreg = L.hdr[0], nsite = L.hdr[1], novf = L.hdr[2];
     int64_t j = -1;
     if (i < nreg) {
-        int lo = 0, hi = NCLS - 1;  // the last sub-region c with cpre[c] <= i
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.cpre[mid] <= i) lo = mid;
-            else hi = mid - 1;
+        int lo = 0;  // the last sub-region c with cpre[c] <= i: most members are the brick's own (class 0)
+        if (i >= L.cpre[1]) {
+            int hi = NCLS - 1;
+            lo = 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.cpre[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
         }
         const int64_t q = bi.off + L.csub[lo] + (i - L.cpre[lo]);
         p[0] = A.x[q]; p[1] = A.x[cap + q]; p[2] = A.x[2 * cap + q];
@@ -3743,8 +3762,7 @@ __device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const Bri
     const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
     double lam = 1.0;
     if (kT_cell > 0.0) {
-        const double P0 = (double)q[1] * 0x1p-32, P1 = (double)q[2] * 0x1p-32, P2 = (double)q[3] * 0x1p-32;
-        const double E = 0.5 * ((double)q[4] * 0x1p-32 - ((P0 * P0 + P1 * P1) + P2 * P2) / (Md * 0x1p-32));
+        const double E = fixed_energy(q);
         if (E > 0.0) lam = sqrt((kT_cell * D.g) / E);
     }
     par[0] = (float)u0; par[1] = (float)u1; par[2] = (float)u2;
@@ -3844,6 +3862,32 @@ __device__ __forceinline__ void brick_emit(const BrickArgs<Real> &A, BrickLds32 
     brick_put<Real>(A, par_out, dst, L.woff[cls], L.wcap[cls], rank, p, w, id, st);
 }
 
+// Lanes 0..NCLS-1: the region written with each class of this brick (the
+// class of a writer one brick below along an axis is 1 there, one above 2),
+// its first slot and its capacity; classes without a distinct region get none.
+__device__ __forceinline__ void brick_writer_info(const BinnedDev &bn, const BrickInfo &bi, int64_t b,
+                                                  const int32_t *g, BrickLds32 &L)
+{
+    const int t = threadIdx.x;
+    if (t >= NCLS) return;
+    const int c3[3] = {t % 3, (t / 3) % 3, t / 9};
+    const bool valid = code_valid(c3[0], g[3]) && code_valid(c3[1], g[4]) && code_valid(c3[2], g[5]);
+    int32_t db = -1;
+    L.woff[t] = 0;
+    L.wcap[t] = 0;
+    if (valid) {
+        int bc[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) bc[d] = code_dst(bi.org[d] >> g[d], c3[d], g[3 + d]);
+        db = bn.sys_bb[bi.sys] + (bc[2] * g[4] + bc[1]) * g[3] + bc[0];
+        const int32_t *dp = bn.subpre + (int64_t)db * (NCLS + 1);
+        L.woff[t] = bn.brick[db].off + dp[t];
+        L.wcap[t] = dp[t + 1] - dp[t];
+    }
+    L.wdst[t] = db;
+    (void)b;
+}
+
 template <int ITEMS>
 __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) void k_brick_collide_f32(BrickArgs<float> A)
 {
@@ -3867,30 +3911,13 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
         const int ncb = bi.dim[0] * bi.dim[1] * bi.dim[2];
         const int32_t *g = bn.sys_bg + 6 * r;
         if (t < NCLS) {
-            // input fills of the valid sub-regions; the region each class of
-            // this brick writes, with its first slot and capacity
-            const int c3[3] = {t % 3, (t / 3) % 3, t / 9};
-            const bool valid = code_valid(c3[0], g[3]) && code_valid(c3[1], g[4]) && code_valid(c3[2], g[5]);
+            // input fills (a sub-region without a writer has capacity 0)
             const int32_t *sp = bn.subpre + b * (NCLS + 1);
             const int s0 = sp[t], s1 = sp[t + 1];
             L.csub[t] = s0;
             if (t == NCLS - 1) L.csub[NCLS] = s1;
-            L.cin[t] = valid ? min(bn.cnt[((int64_t)par_in * bn.nbricks + b) * NCLS + t], s1 - s0) : 0;
+            L.cin[t] = min(bn.cnt[((int64_t)par_in * bn.nbricks + b) * NCLS + t], s1 - s0);
             L.wcnt[t] = 0;
-            int32_t db = -1;
-            if (valid) {
-                int bc[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) bc[d] = code_dst(bi.org[d] >> g[d], c3[d], g[3 + d]);
-                db = bn.sys_bb[r] + (bc[2] * g[4] + bc[1]) * g[3] + bc[0];
-                const int32_t *dp = bn.subpre + (int64_t)db * (NCLS + 1);
-                L.woff[t] = bn.brick[db].off + dp[t];
-                L.wcap[t] = dp[t + 1] - dp[t];
-            } else {
-                L.woff[t] = 0;
-                L.wcap[t] = 0;
-            }
-            L.wdst[t] = db;
         }
         if (t == 64) {
             L.hdr[1] = min(bn.scnt[b], (int)bi.scap);
@@ -3907,14 +3934,16 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
             for (int z = 0; z < 5; ++z) L.acc[5 * c + z] = 0ull;
         }
         __syncthreads();
-        if (t == 0) {
-            int a = 0;
-            for (int c = 0; c < NCLS; ++c) {
-                L.cpre[c] = a;
-                a += L.cin[c];
+        if (t < 64) {  // exclusive prefix of the input fills (wave 0)
+            const int v = t < NCLS ? L.cin[t] : 0;
+            int a = v;
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) {
+                const int u = __shfl_up(a, o, 64);
+                if ((t & 63) >= o) a += u;
             }
-            L.cpre[NCLS] = a;
-            L.hdr[0] = a;
+            if (t <= NCLS) L.cpre[t] = a - v;
+            if (t == NCLS - 1) L.hdr[0] = a;
         }
         // overflow entries addressed to this brick (the lists are nearly always empty)
         for (int e = t; e < L.hdr[4]; e += BRICK_T)
@@ -3951,9 +3980,11 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 id[k] = 0;
                 if (i < nmem && brick_member<float>(A, bi, par_in, i, L, p[k], w[k], id[k], st)) lc[k] = 0;
             }
-            // the cells' first random calls while the member loads are in flight
+            // the cells' first random calls and the regions this brick writes,
+            // while the member loads are in flight
             for (int c = t; c < ncb; c += BRICK_T)
                 cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.pre[c]);
+            brick_writer_info(bn, bi, b, g, L);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
@@ -3991,6 +4022,7 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
             // member list, then a second load of each member to rotate it
             for (int c = t; c < ncb; c += BRICK_T)
                 cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.pre[c]);
+            brick_writer_info(bn, bi, b, g, L);
             for (int i = t; i < nmem; i += BRICK_T) {
                 float p[3], w[3];
                 int32_t id;

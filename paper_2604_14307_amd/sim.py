@@ -142,6 +142,9 @@ class GPUSystem:
             self._setup_binned()
         elif layout != "dense":
             raise ValueError("layout must be 'dense' or 'binned'")
+        # the uploads, initialisation and packing ran on the current stream:
+        # wait for them, so that the system can be stepped on any stream
+        torch.cuda.synchronize(self.device)
 
     def _host_offsets(self):
         nc = np.ascontiguousarray(self.ncell_h.reshape(-1), dtype=np.int32)

@@ -173,6 +173,7 @@ def test_fp32_bench_form_within_1e5_of_fp64_oracle(ci):
     systems = wls if isinstance(wls, list) else [wls]
     g, e = tuned_system(systems, par, "f32")
     say("FP32 bench form, workload %d (%s), tuned shape %s" % (ci, meta["name"], list(e["tune"])))
+    torch.cuda.synchronize()  # the set-up work ran on the default stream
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         g.graph(2)
@@ -223,6 +224,7 @@ def test_fp64_batched_bench_form_bit_exact():
     systems, par, meta = W.config(3)
     g, e = tuned_system(systems, par, "f64")
     say("FP64 batched bench form, tuned shape %s" % list(e["tune"]))
+    torch.cuda.synchronize()  # the set-up work ran on the default stream
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         g.graph(2)

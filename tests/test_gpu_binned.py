@@ -50,6 +50,7 @@ def dense_and_binned(systems, par, nsteps, graph=False, check_every=1):
         g.body_forces()
     assert_same_states(gd.download(), gb.download(), "initial")
     if graph:
+        torch.cuda.synchronize()  # the set-up work ran on the default stream
         side = torch.cuda.Stream()
         with torch.cuda.stream(side):
             gb.graph(2)

@@ -552,6 +552,7 @@ def test_full_size_in_the_bench_launch_configuration(ci, prec):
     e = tune.autotune(g, cache_path=cache, write=False)
     assert e["cached"]
     say("full size workload %d %s, tuned shape %s" % (ci, prec, list(e["tune"])))
+    torch.cuda.synchronize()  # the set-up work ran on the default stream
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         g.graph(2)
@@ -851,6 +852,7 @@ def test_snapshot_waits_for_steps_on_another_stream():
     par = W.srd_params(90, kT_cell=1.0)
     g = gpu_system(wl, par, prec="f32")
     ref = gpu_system(wl, par, prec="f32")
+    torch.cuda.synchronize()  # the set-up work ran on the default stream
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         g.step(40)
