@@ -432,6 +432,24 @@ typedef struct mpcd_rnemd_s {
 int mpcd_rnemd_exchange(void *stream, const mpcd_sys *sys, const void *x, void *v, const int32_t *tag,
                         const mpcd_rnemd *r, double *dp, void *ws, size_t ws_bytes);
 
+/* The same exchange with no allocation and no workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Its buffers (histogram, control
+ * words, candidate lists) are one static device array of
+ * MPCD_RNEMD_SCRATCH_BYTES per GPU, held from the first call on that GPU
+ * until the process ends; the call allocates nothing and calls no allocating
+ * library routine.  Arguments, limits (nsys == 1, npairs <= 1024) and results
+ * are those of mpcd_rnemd_exchange, bit for bit; status (device, 4-byte
+ * aligned) receives the flags ORed in (MPCD_FLAG_BINERR as above), where
+ * mpcd_rnemd_exchange uses the workspace's status word.  The stream must
+ * belong to the current device (else MPCD_EINVAL).  Every call on a GPU uses
+ * that GPU's one array: calls that overlap on one GPU (other streams, other
+ * host threads) race and must be serialised by the caller.  Each call clears
+ * what must start at zero itself; the array keeps the last call's lists. */
+#define MPCD_RNEMD_SCRATCH_BYTES 106752
+int mpcd_rnemd_exchange_noalloc(void *stream, const mpcd_sys *sys, const void *x, void *v, const int32_t *tag,
+                                const mpcd_rnemd *r, double *dp, uint32_t *status);
+
 /* Harmonic-bond comparator, Sec. II.B.1: a colloid is a centre site plus
  * surface sites; each surface site is bonded to its nearest surface neighbours
  * and to the centre by u_b = (k_b / 2)(r - r_b)^2, Eq. (2).  All sites move by

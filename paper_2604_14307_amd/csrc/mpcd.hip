@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mpcd.h"
@@ -5166,36 +5167,80 @@ static int rnemd_checks(const mpcd_sys *sys, const void *x, const void *v, const
     return MPCD_OK;
 }
 
+// The exchange's four kernels on the buffers in R (histogram and control
+// words zero on entry; both are left zero), flags ORed into *status.
+static void launch_rnemd_on(RnArgs R, hipStream_t st, const mpcd_sys *sys, const void *x, void *v,
+                            const int32_t *tag, const mpcd_rnemd *r, double *dp, uint32_t *status)
+{
+    const int64_t N = sys->n_solvent;
+    if (N == 0 || r->npairs == 0) return;
+    R.y0 = r->y0; R.y1 = r->y1; R.dy = r->dy; R.target = r->target; R.m = sys->m_solvent;
+    R.npairs = r->npairs;
+    const unsigned g = grid_for(N, 256, 8192);
+    if (sys->prec == MPCD_F64) {
+        hipLaunchKernelGGL(k_rn_hist<double>, dim3(RN_HBLOCKS), dim3(256), 0, st, R, (const double *)x,
+                           (const double *)v, N);
+        hipLaunchKernelGGL(k_rn_thresh, dim3(1), dim3(256), 0, st, R);
+        hipLaunchKernelGGL(k_rn_collect<double>, dim3(g), dim3(256), 0, st, R, (const double *)x, (const double *)v,
+                           tag, N, status);
+        hipLaunchKernelGGL(k_rn_swap<double>, dim3(1), dim3(1024), 0, st, R, (double *)v, N, dp, status);
+    } else {
+        hipLaunchKernelGGL(k_rn_hist<float>, dim3(RN_HBLOCKS), dim3(256), 0, st, R, (const float *)x,
+                           (const float *)v, N);
+        hipLaunchKernelGGL(k_rn_thresh, dim3(1), dim3(256), 0, st, R);
+        hipLaunchKernelGGL(k_rn_collect<float>, dim3(g), dim3(256), 0, st, R, (const float *)x, (const float *)v,
+                           tag, N, status);
+        hipLaunchKernelGGL(k_rn_swap<float>, dim3(1), dim3(1024), 0, st, R, (float *)v, N, dp, status);
+    }
+}
+
 static void launch_rnemd(const Ctx &c, hipStream_t st, const void *x, void *v, const int32_t *tag,
                          const mpcd_rnemd *r, double *dp)
 {
-    const int64_t N = c.sys->n_solvent;
-    if (N == 0 || r->npairs == 0) return;
     RnArgs R;
-    R.y0 = r->y0; R.y1 = r->y1; R.dy = r->dy; R.target = r->target; R.m = c.sys->m_solvent;
-    R.npairs = r->npairs;
     R.hist = at<int32_t>(c.ws, c.L.rn_hist);
     R.bcnt = at<int32_t>(c.ws, c.L.rn_bcnt);
     R.ctl = at<int32_t>(c.ws, c.L.rn_ctl);
     R.key = at<double>(c.ws, c.L.rn_key);
     R.id = at<int32_t>(c.ws, c.L.rn_id);
     R.kk = at<int32_t>(c.ws, c.L.rn_k);
-    const unsigned g = grid_for(N, 256, 8192);
-    if (c.sys->prec == MPCD_F64) {
-        hipLaunchKernelGGL(k_rn_hist<double>, dim3(RN_HBLOCKS), dim3(256), 0, st, R, (const double *)x,
-                           (const double *)v, N);
-        hipLaunchKernelGGL(k_rn_thresh, dim3(1), dim3(256), 0, st, R);
-        hipLaunchKernelGGL(k_rn_collect<double>, dim3(g), dim3(256), 0, st, R, (const double *)x, (const double *)v,
-                           tag, N, c.status);
-        hipLaunchKernelGGL(k_rn_swap<double>, dim3(1), dim3(1024), 0, st, R, (double *)v, N, dp, c.status);
-    } else {
-        hipLaunchKernelGGL(k_rn_hist<float>, dim3(RN_HBLOCKS), dim3(256), 0, st, R, (const float *)x,
-                           (const float *)v, N);
-        hipLaunchKernelGGL(k_rn_thresh, dim3(1), dim3(256), 0, st, R);
-        hipLaunchKernelGGL(k_rn_collect<float>, dim3(g), dim3(256), 0, st, R, (const float *)x, (const float *)v,
-                           tag, N, c.status);
-        hipLaunchKernelGGL(k_rn_swap<float>, dim3(1), dim3(1024), 0, st, R, (float *)v, N, dp, c.status);
+    launch_rnemd_on(R, st, c.sys, x, v, tag, r, dp, c.status);
+}
+
+// ---------------------------------------------------------------------------
+// The exchange without allocation: its buffers live in one static device
+// array per GPU (the control words and histogram first, cleared by every
+// call, then the block counts and the candidate lists, which every call
+// writes before it reads them).  Each device's copy of the array sits at its
+// own address, looked up once per device with that device current; host code
+// uses only that address, never the array's name.
+constexpr size_t RNS_CTL = 0, RNS_HIST = 256, RNS_BCNT = RNS_HIST + sizeof(int32_t) * 2 * RN_BINS,
+                 RNS_KEY = RNS_BCNT + sizeof(int32_t) * 2 * RN_HBLOCKS, RNS_ID = RNS_KEY + sizeof(double) * 2 * RN_CAP,
+                 RNS_K = RNS_ID + sizeof(int32_t) * 2 * RN_CAP, RNS_BYTES = RNS_K + sizeof(int32_t) * 2 * RN_CAP;
+static_assert(RNS_BYTES == MPCD_RNEMD_SCRATCH_BYTES, "the exchange's static scratch size");
+static_assert(RNS_HIST % 256 == 0 && RNS_BCNT % 256 == 0 && RNS_KEY % 256 == 0 && RNS_ID % 256 == 0 &&
+                  RNS_K % 256 == 0, "256-byte aligned parts");
+
+static __device__ __align__(256) unsigned char scratch[RNS_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[SCRATCH_MAX_DEVICES];
+
+// The device address of this device's scratch array (looked up on the first
+// call per device, with the device current).
+static int scratch_on_device(int dev, void **out)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return MPCD_ENOTSUP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        TRY(hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))));
+        if (!ptr) return MPCD_EHIP;
+        g_scratch[dev] = ptr;
     }
+    *out = g_scratch[dev];
+    return MPCD_OK;
 }
 
 int mpcd_rnemd_exchange(void *stream, const mpcd_sys *sys, const void *x, void *v, const int32_t *tag,
@@ -5203,6 +5248,42 @@ int mpcd_rnemd_exchange(void *stream, const mpcd_sys *sys, const void *x, void *
 {
     TRY(rnemd_checks(sys, x, v, tag, r, dp, ws, ws_bytes));
     launch_rnemd(make_ctx(sys, ws), (hipStream_t)stream, x, v, tag, r, dp);
+    return launch_check();
+}
+
+int mpcd_rnemd_exchange_noalloc(void *stream, const mpcd_sys *sys, const void *x, void *v, const int32_t *tag,
+                                const mpcd_rnemd *r, double *dp, uint32_t *status)
+{
+    TRY(check_sys(sys));
+    if (!r || !dp || !aligned(dp, 8) || !status || !aligned(status, 4)) return MPCD_EINVAL;
+    if (sys->nsys != 1) return MPCD_ENOTSUP;
+    if (!ok_arr(x, sys->n_solvent, esize(sys)) || !ok_arr(v, sys->n_solvent, esize(sys))) return MPCD_EINVAL;
+    if (tag && !aligned(tag, 4)) return MPCD_EINVAL;
+    // the scratch holds the lists of npairs <= RN_MAXPAIRS ranked members
+    if (!(r->dy > 0.0) || r->npairs < 0 || r->npairs > RN_MAXPAIRS) return MPCD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    TRY(hip_check(hipGetDevice(&dev)));
+    if (st) {  // the stream must belong to the current device (the array is per device)
+        int sdev = -1;
+        TRY(hip_check(hipStreamGetDevice(st, &sdev)));
+        if (sdev != dev) return MPCD_EINVAL;
+    }
+    void *ptr = nullptr;
+    TRY(scratch_on_device(dev, &ptr));
+    char *w = (char *)ptr;
+    if (sys->n_solvent == 0 || r->npairs == 0) return MPCD_OK;
+    // control words and histogram start at zero (a fill kernel, not a memset node)
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)(RNS_BCNT / 4), 256)), dim3(256), 0, st, (int32_t *)w,
+                       (int64_t)(RNS_BCNT / 4), 0);
+    RnArgs R;
+    R.ctl = (int32_t *)(w + RNS_CTL);
+    R.hist = (int32_t *)(w + RNS_HIST);
+    R.bcnt = (int32_t *)(w + RNS_BCNT);
+    R.key = (double *)(w + RNS_KEY);
+    R.id = (int32_t *)(w + RNS_ID);
+    R.kk = (int32_t *)(w + RNS_K);
+    launch_rnemd_on(R, st, sys, x, v, tag, r, dp, status);
     return launch_check();
 }
 

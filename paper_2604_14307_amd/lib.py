@@ -23,7 +23,7 @@ EXPORTS = ("mpcd_workspace_bytes", "mpcd_workspace_offsets", "mpcd_ws_init", "mp
            "mpcd_graph_destroy", "mpcd_status", "mpcd_last_hip_error",
            "harm_forces", "harm_md", "harm_step", "harm_graph_create", "mpcd_rnemd_exchange", "mpcd_cell_order",
            "mpcd_tile_shape", "mpcd_binned_layout", "mpcd_binned_init", "mpcd_binned_pack", "mpcd_binned_unpack",
-           "mpcd_binned_collide", "mpcd_binned_sites")
+           "mpcd_binned_collide", "mpcd_binned_sites", "mpcd_rnemd_exchange_noalloc")
 
 vp = C.c_void_p
 
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
         "mpcd_status": (C.c_int, [vp, vp, sz, C.POINTER(C.c_uint32)]),
         "mpcd_last_hip_error": (C.c_int, []),
         "mpcd_rnemd_exchange": (C.c_int, [vp, sp, vp, vp, vp, C.POINTER(MpcdRnemd), vp, vp, sz]),
+        "mpcd_rnemd_exchange_noalloc": (C.c_int, [vp, sp, vp, vp, vp, C.POINTER(MpcdRnemd), vp, vp]),
         "harm_forces": (C.c_int, [vp, sp, C.POINTER(MpcdHarm), vp, wp, vp, sz]),
         "harm_md": (C.c_int, [vp, sp, C.POINTER(MpcdHarm), vp, vp, wp, dbl, i32, vp, sz]),
         "harm_step": (C.c_int, [vp, C.POINTER(MpcdStepArgs), C.POINTER(MpcdHarm), dbl, i32]),
