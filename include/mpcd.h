@@ -205,10 +205,10 @@ typedef struct {
      * see mpcd_rnemd_exchange; rnemd_dp is its device accumulator. */
     const struct mpcd_rnemd_s *rnemd;
     double *rnemd_dp;
-    /* Binned solvent layout (NULL: the dense layout above).  When set, x, v,
-     * tag and x_out, v_out, tag_out are binned solvent arrays of
-     * binned->capacity slots each ([3][capacity], [3][capacity],
-     * [capacity]); see mpcd_binned_layout. */
+    /* Binned solvent layout (NULL: the dense layout above).  When set, x and
+     * x_out are the solvent record arrays of this step and the next
+     * (binned->capacity records each, 16-byte aligned, see
+     * mpcd_binned_layout), and v, tag, v_out, tag_out must be NULL. */
     const struct mpcd_binned_s *binned;
 } mpcd_step_args;
 
@@ -217,23 +217,31 @@ typedef struct {
  *
  * Each system's cells are grouped into bricks of up to 8 x 8 x 4 cells
  * (smaller bricks for denser systems; narrower at the far faces of the box).
- * The solvent arrays hold one region of fixed capacity per brick: on a step
- * with index t, a solvent particle is stored in the region of the brick of
- * its cell on step t's shifted grid, in no particular order within the
- * region.  The step collides each brick's particles and sites in one block
- * and writes each new solvent particle straight into the region of its brick
- * on step t+1's grid, so the binned arrays are double-buffered (x, v, tag ->
- * x_out, v_out, tag_out, swapped by the caller after every step, as in the
- * out-of-place dense form).  Region fills are kept in the binned workspace
- * per step parity (the parity of *d_step), which is why the caller's swap
- * must follow every step.  A region whose capacity (mean occupancy + 6
- * standard deviations + 16) is exceeded spills into a shared list of 8192
- * entries; beyond that MPCD_FLAG_BINERR is set and the state is invalid.
- * The surface sites are listed per brick by the thermalization of the same
- * step (sites beyond a brick's list spill into a second shared list).
- * Results are identical to the dense form's in identity order (the same
- * per-cell sums, draws and rounding).  FP32 only: other precisions return
- * MPCD_ENOTSUP from the step; no reverse nonequilibrium exchange.
+ * A solvent particle is one record of eight values of the precision
+ * (position x, y, z; its identity as the int32 bits of the fourth value;
+ * velocity x, y, z; one unused value: 32 bytes in FP32).  The record array
+ * holds one region per brick: on a step with index t, a particle is stored in
+ * the region of the brick of its cell on step t's shifted grid.  A region is
+ * split into 27 sub-regions, one per brick that can write into it (the brick
+ * itself and its neighbours along each axis), each of fixed capacity (mean
+ * occupancy + 6 standard deviations + 16; none for a neighbour that does not
+ * exist), in no particular order within a sub-region.  The step collides each
+ * brick's particles and sites in one block and writes each new solvent
+ * particle straight into its writer's sub-region of the region of its brick
+ * on step t+1's grid, so every sub-region has one writer, which also stores
+ * its fill: no device atomics.  The record arrays are double-buffered (x ->
+ * x_out, swapped by the caller after every step, as in the out-of-place
+ * dense form).  Sub-region fills are kept in the binned workspace per step
+ * parity (the parity of *d_step), which is why the caller's swap must follow
+ * every step.  A particle beyond its sub-region's capacity, or beyond the
+ * neighbouring bricks, goes to a shared overflow list of 8192 entries per
+ * parity (the brick is flagged for its reader); beyond that list
+ * MPCD_FLAG_BINERR is set and the state is invalid.  The surface sites are
+ * listed per brick by the thermalization of the same step (sites beyond a
+ * brick's list go to a second shared list).  Results are identical to the
+ * dense form's in identity order (the same per-cell sums, draws and
+ * rounding).  FP32 only: other precisions return MPCD_ENOTSUP from the step;
+ * no reverse nonequilibrium exchange.
  *
  * Host fields are filled by mpcd_binned_layout; ws and ws_bytes are the
  * caller's device buffer for the brick tables, fills, site lists and
@@ -242,7 +250,7 @@ typedef struct mpcd_binned_s {
     void *ws;            /* device: binned workspace                          */
     size_t ws_bytes;     /* bytes of ws (>= the ws_bytes the layout reports)  */
     int64_t nbricks;     /* host: bricks over all systems                     */
-    int64_t capacity;    /* host: slots of one set of binned solvent arrays   */
+    int64_t capacity;    /* host: records of one solvent record array         */
     int64_t site_slots;  /* host: site list entries over all bricks           */
     int32_t items;       /* host: members per thread of a brick block         */
 } mpcd_binned;
@@ -263,18 +271,17 @@ int mpcd_binned_init(void *stream, const mpcd_sys *sys, const int32_t *ncell, co
                      const int64_t *site_off_sys, const mpcd_binned *b);
 
 /* Dense solvent (x, v: [3N] prec, tag: [N] identities or NULL = index) into
- * the binned arrays xb, vb, tagb for the step *d_step (its grid shift, Sec.
- * II.A).  Clears that step parity's fills first. */
-int mpcd_binned_pack(void *stream, const mpcd_sys *sys, const void *x, const void *v, const int32_t *tag, void *xb,
-                     void *vb, int32_t *tagb, uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes,
-                     const mpcd_binned *b);
+ * the record array rec (b->capacity records, 16-byte aligned) for the step
+ * *d_step (its grid shift, Sec. II.A).  Clears both parities' fills and
+ * overflow lists first, and stores that step's shift table. */
+int mpcd_binned_pack(void *stream, const mpcd_sys *sys, const void *x, const void *v, const int32_t *tag, void *rec,
+                     uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes, const mpcd_binned *b);
 
-/* Binned solvent of the step *d_step back to dense arrays in identity order:
- * x[:, id], v[:, id] of the particle with identity id, tag[id] = id.  The
- * binned arrays and fills are left unchanged. */
-int mpcd_binned_unpack(void *stream, const mpcd_sys *sys, const void *xb, const void *vb, const int32_t *tagb, void *x,
-                       void *v, int32_t *tag, const uint64_t *d_step, void *ws, size_t ws_bytes,
-                       const mpcd_binned *b);
+/* The solvent records of the step *d_step back to dense arrays in identity
+ * order: x[:, id], v[:, id] of the particle with identity id, tag[id] = id.
+ * The records and fills are left unchanged. */
+int mpcd_binned_unpack(void *stream, const mpcd_sys *sys, const void *rec, void *x, void *v, int32_t *tag,
+                       const uint64_t *d_step, void *ws, size_t ws_bytes, const mpcd_binned *b);
 
 /* The first kernel of a step of the binned layout on its own: the sites of
  * step *d_step placed and thermalized (Eqs. (5) and (7), as sites_thermalize)
@@ -287,8 +294,8 @@ int mpcd_binned_sites(void *stream, const mpcd_step_args *args);
 
 /* The collision of one step of the binned layout alone (Sec. II.A, with the
  * sites as heavy solvent, Sec. II.B.2): collide, stream and bin the solvent
- * of step *d_step from x, v, tag into x_out, v_out, tag_out (the next step's
- * regions, whose fills it clears first), and write the sites' new velocities
+ * records of step *d_step from x into x_out (the next step's regions, whose
+ * fills it stores), and write the sites' new velocities
  * in place.  It needs that step's sites thermalized and listed (as mpcd_step
  * does first) and leaves the input fills, the site lists and the step counter
  * unchanged, so it can be launched again on the same input (the sites then

@@ -2025,6 +2025,8 @@ enum { BC_OVF0 = 1, BC_OVF1 = 2, BC_SOVF = 3, BC_WORDS = 16 };
 struct BinnedDev {
     const BrickInfo *brick;  // [nbricks]
     const int32_t *subpre;   // [nbricks][NCLS + 1] first slot of each sub-region within the region
+    const int4 *wtab;        // [nbricks][NCLS] the sub-region a brick writes with each class: first
+                             // slot, capacity, destination brick (-1: none), unused
     const int32_t *sys_bb;   // [nsys + 1] first brick of each system
     const int32_t *sys_bg;   // [6 nsys] log2 of the brick extent (3), bricks per axis (3)
     int32_t *cnt;            // [2][nbricks][NCLS] sub-region fills, by step parity
@@ -2035,6 +2037,8 @@ struct BinnedDev {
     int32_t *ovf_tag;        // [2 BIN_OVF_CAP] identity,
     void *ovf_xv;            // [2][6][BIN_OVF_CAP] position and velocity (prec)
     int32_t *sovf;           // [2 sovf_cap]: (brick, site) pairs
+    int32_t *oflag;          // [2][nbricks] nonzero: the overflow list may hold entries for the brick
+    double *shtab;           // [2][1 + 6 nsys] step index, then each system's shifts for it and the next step
     int64_t nbricks, cap;    // bricks; slots of one set of solvent arrays
     int32_t sovf_cap;
 };
@@ -2597,7 +2601,7 @@ __global__ void k_body_first(SysDev s, BodyDev bd, const double *J, const double
 // Momentum transfer fused with the first half of the body update (one block
 // per body); J and K are also written out.
 // After the brick collision of step t (the step index is still t): clear the
-// site counts and the overflow counters that step read, ready for step t+1's
+// site counts and the overflow flags and counters that step read, ready for step t+1's
 // site binning and for step t+1's writers (which count into this parity's
 // overflow list).  The sub-region fills need no clearing: every valid
 // sub-region is stored by its writer every step.  The brick kernel only reads
@@ -2606,7 +2610,11 @@ __device__ __forceinline__ void binned_finish(const BinnedDev &bn, uint64_t step
 {
     const int par = (int)(step & 1);
     const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn.nbricks; q += nt) bn.scnt[q] = 0;
+    int32_t *flags = bn.oflag + (int64_t)par * bn.nbricks;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < bn.nbricks; q += nt) {
+        bn.scnt[q] = 0;
+        flags[q] = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         bn.ctrl[BC_OVF0 + par] = 0;
         bn.ctrl[BC_SOVF] = 0;
@@ -3633,13 +3641,49 @@ constexpr int BRICK_MAXC = 256;  // cells per brick at most (one lane per cell)
 constexpr int BRICK_OVL = 512;   // overflow entries per brick and kind a block takes
 constexpr int BRICK_ITEMS_F32 = 4;
 
+// A binned solvent slot is one record of eight values of the precision:
+// position, identity (the int32 bits in the fourth value), velocity, and one
+// unused value; 32 bytes in FP32, written and read as two 16-byte vectors so
+// that a run of slots fills whole cache lines.
+__device__ __forceinline__ void rec_load(const float *rec, int64_t q, float p[3], float w[3], int32_t &id)
+{
+    const float4 *r = (const float4 *)rec + 2 * q;
+    const float4 a = r[0], c = r[1];
+    p[0] = a.x; p[1] = a.y; p[2] = a.z;
+    id = __float_as_int(a.w);
+    w[0] = c.x; w[1] = c.y; w[2] = c.z;
+}
+
+__device__ __forceinline__ void rec_store(float *rec, int64_t q, const float p[3], const float w[3], int32_t id)
+{
+    float4 *r = (float4 *)rec + 2 * q;
+    r[0] = make_float4(p[0], p[1], p[2], __int_as_float(id));
+    r[1] = make_float4(w[0], w[1], w[2], 0.0f);
+}
+
+__device__ __forceinline__ void rec_load(const double *rec, int64_t q, double p[3], double w[3], int32_t &id)
+{
+    const double2 *r = (const double2 *)rec + 4 * q;
+    const double2 a = r[0], c = r[1], e = r[2], f = r[3];
+    p[0] = a.x; p[1] = a.y; p[2] = c.x;
+    id = (int32_t)__double_as_longlong(c.y);
+    w[0] = e.x; w[1] = e.y; w[2] = f.x;
+}
+
+__device__ __forceinline__ void rec_store(double *rec, int64_t q, const double p[3], const double w[3], int32_t id)
+{
+    double2 *r = (double2 *)rec + 4 * q;
+    r[0] = make_double2(p[0], p[1]);
+    r[1] = make_double2(p[2], __longlong_as_double((long long)id));
+    r[2] = make_double2(w[0], w[1]);
+    r[3] = make_double2(w[2], 0.0);
+}
+
 template <typename Real> struct BrickArgs {
     SysDev s;
     BinnedDev bn;
-    const Real *x, *v;  // binned solvent of this step: [3][cap] each
-    const int32_t *tag; // [cap]
-    Real *xo, *vo;      // binned solvent of the next step
-    int32_t *tago;
+    const Real *rec;  // binned solvent records of this step: [cap][8]
+    Real *reco;       // and of the next step
     Real *xs, *vs;      // sites [3][S]
     const double *site_m;
     double cos_a, sin_a, kT_cell, dt;
@@ -3658,15 +3702,28 @@ struct BrickLds32 {
     int cnt[BRICK_MAXC];
     float par[12 * BRICK_MAXC];
     CellDrawPre pre[BRICK_MAXC];
-    int cin[NCLS], cpre[NCLS + 1];  // input sub-region fills and their prefix
+    int cpre[NCLS + 1];             // exclusive prefix of the input sub-region fills
     int32_t csub[NCLS + 1];         // this brick's sub-region offsets
     int wcnt[NCLS];                 // members written per class of this brick
     int32_t wdst[NCLS], wcap[NCLS]; // the region written with each class, its sub-region capacity
-    int64_t woff[NCLS];             // and its first slot
+    int32_t woff[NCLS];             // and its first slot
     int32_t lovf[BRICK_OVL], lsovf[BRICK_OVL];
     double sh[3], sh1[3];
-    int hdr[8];  // region members, sites, overflow solvent, overflow sites, their list lengths
+    int hdr[8];  // region members, sites, overflow solvent, overflow sites, the two list lengths,
+                 // site overflow, solvent overflow flag
 };
+
+// The shift table of the parity of step u: u, then each system's grid shifts
+// for steps u and u + 1 (threads of one block, strided over the systems).
+__device__ __forceinline__ void binned_store_shifts(const SysDev &s, const BinnedDev &bn, uint64_t seed, uint64_t u)
+{
+    double *tab = bn.shtab + (int64_t)(u & 1) * (1 + 6 * (int64_t)s.nsys);
+    for (int r = threadIdx.x; r < s.nsys; r += blockDim.x) {
+        shift_of(s, seed, u, r, tab + 1 + 6 * r);
+        shift_of(s, seed, u + 1, r, tab + 4 + 6 * r);
+    }
+    if (threadIdx.x == 0) tab[0] = (double)u;
+}
 
 // Member i of the brick: region solvent (sub-region by sub-region), listed
 // sites, then overflow solvent and overflow sites; id is the solvent identity,
@@ -3675,7 +3732,7 @@ template <typename Real>
 __device__ __forceinline__ bool brick_member(const BrickArgs<Real> &A, const BrickInfo &bi, int par_in, int i,
                                              const BrickLds32 &L, Real p[3], Real w[3], int32_t &id, uint32_t &st)
 {
-    const int64_t cap = A.bn.cap, S = A.s.S;
+    const int64_t S = A.s.S;
     const int nreg = L.hdr[0], nsite = L.hdr[1], novf = L.hdr[2];
     int64_t j = -1;
     if (i < nreg) {
@@ -3689,10 +3746,7 @@ __device__ __forceinline__ bool brick_member(const BrickArgs<Real> &A, const Bri
                 else hi = mid - 1;
             }
         }
-        const int64_t q = bi.off + L.csub[lo] + (i - L.cpre[lo]);
-        p[0] = A.x[q]; p[1] = A.x[cap + q]; p[2] = A.x[2 * cap + q];
-        w[0] = A.v[q]; w[1] = A.v[cap + q]; w[2] = A.v[2 * cap + q];
-        id = A.tag[q];
+        rec_load(A.rec, bi.off + L.csub[lo] + (i - L.cpre[lo]), p, w, id);
         return true;
     }
     if (i < nreg + nsite) {
@@ -3726,14 +3780,19 @@ template <typename Real>
 __device__ __forceinline__ int brick_local_cell(const SysDev &s, const BinnedDev &bn, const BrickInfo &bi, int64_t b,
                                                 const Real p[3], const double *sh, uint32_t &st)
 {
-    int jc[3];
-    const double shv[3] = {sh[0], sh[1], sh[2]};
-    const int32_t bb = brick_of_pos<Real>(s, bn, bi.sys, p[0], p[1], p[2], shv, jc, st);
-    if (bb != b) {
-        st |= ST_BINERR;
-        return -1;
+    const int r = bi.sys;
+    int lc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lc[d] = axis_cell(p[d], sh[d], s.a, s.inv_a, s.ncell[3 * r + d], st) - bi.org[d];
+        if ((unsigned)lc[d] >= (unsigned)bi.dim[d]) {  // the brick is cells org .. org + dim - 1
+            st |= ST_BINERR;
+            return -1;
+        }
     }
-    return ((jc[2] - bi.org[2]) * bi.dim[1] + (jc[1] - bi.org[1])) * bi.dim[0] + (jc[0] - bi.org[0]);
+    (void)bn;
+    (void)b;
+    return (lc[2] * bi.dim[1] + lc[1]) * bi.dim[0] + lc[0];
 }
 
 // The canonical index (within its system) of cell c of a brick.
@@ -3823,15 +3882,8 @@ template <typename Real>
 __device__ __forceinline__ void brick_put(const BrickArgs<Real> &A, int par_out, int32_t b, int64_t off, int32_t cap,
                                           int32_t slot, const Real p[3], const Real w[3], int32_t id, uint32_t &st)
 {
-    const int64_t C = A.bn.cap;
     if (slot < cap) {
-        const int64_t q = off + slot;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            A.xo[d * C + q] = p[d];
-            A.vo[d * C + q] = w[d];
-        }
-        A.tago[q] = id;
+        rec_store(A.reco, off + slot, p, w, id);
         return;
     }
     const int e = atomicAdd(&A.bn.ctrl[BC_OVF0 + par_out], 1);
@@ -3847,6 +3899,7 @@ __device__ __forceinline__ void brick_put(const BrickArgs<Real> &A, int par_out,
     }
     A.bn.ovf_tag[(int64_t)par_out * BIN_OVF_CAP + e] = id;
     A.bn.ovf_dest[(int64_t)par_out * BIN_OVF_CAP + e] = b;
+    A.bn.oflag[(int64_t)par_out * A.bn.nbricks + b] = 1;  // any writer may store it: no atomic needed
 }
 
 // A streamed solvent member into its class's sub-region of the next step's
@@ -3863,32 +3916,6 @@ __device__ __forceinline__ void brick_emit(const BrickArgs<Real> &A, BrickLds32 
     brick_put<Real>(A, par_out, dst, L.woff[cls], L.wcap[cls], rank, p, w, id, st);
 }
 
-// Lanes 0..NCLS-1: the region written with each class of this brick (the
-// class of a writer one brick below along an axis is 1 there, one above 2),
-// its first slot and its capacity; classes without a distinct region get none.
-__device__ __forceinline__ void brick_writer_info(const BinnedDev &bn, const BrickInfo &bi, int64_t b,
-                                                  const int32_t *g, BrickLds32 &L)
-{
-    const int t = threadIdx.x;
-    if (t >= NCLS) return;
-    const int c3[3] = {t % 3, (t / 3) % 3, t / 9};
-    const bool valid = code_valid(c3[0], g[3]) && code_valid(c3[1], g[4]) && code_valid(c3[2], g[5]);
-    int32_t db = -1;
-    L.woff[t] = 0;
-    L.wcap[t] = 0;
-    if (valid) {
-        int bc[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) bc[d] = code_dst(bi.org[d] >> g[d], c3[d], g[3 + d]);
-        db = bn.sys_bb[bi.sys] + (bc[2] * g[4] + bc[1]) * g[3] + bc[0];
-        const int32_t *dp = bn.subpre + (int64_t)db * (NCLS + 1);
-        L.woff[t] = bn.brick[db].off + dp[t];
-        L.wcap[t] = dp[t + 1] - dp[t];
-    }
-    L.wdst[t] = db;
-    (void)b;
-}
-
 template <int ITEMS>
 __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) void k_brick_collide_f32(BrickArgs<float> A)
 {
@@ -3899,44 +3926,55 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
     const uint64_t step = *A.d_step;
     const int par_in = (int)(step & 1), par_out = par_in ^ 1;
     uint32_t st = 0;
-    if (blockIdx.x == 0) {
-        if (t == 0 && A.step_next) *A.step_next = step + 1;
-        if (A.shift_out) draw_shifts(s, A.seed, step, A.shift_out);
-    }
-    for (int64_t q = (int64_t)blockIdx.x * BRICK_T + t; A.grid_clear && q < A.grid_n; q += (int64_t)gridDim.x * BRICK_T)
-        A.grid_clear[q] = 0;
     const int64_t b = tile_of_block((int)bn.nbricks);
     if (b < bn.nbricks) {
         const BrickInfo bi = bn.brick[b];
         const int r = bi.sys;
         const int ncb = bi.dim[0] * bi.dim[1] * bi.dim[2];
-        const int32_t *g = bn.sys_bg + 6 * r;
-        if (t < NCLS) {
-            // input fills (a sub-region without a writer has capacity 0)
-            const int32_t *sp = bn.subpre + b * (NCLS + 1);
-            const int s0 = sp[t], s1 = sp[t + 1];
-            L.csub[t] = s0;
-            if (t == NCLS - 1) L.csub[NCLS] = s1;
-            L.cin[t] = min(bn.cnt[((int64_t)par_in * bn.nbricks + b) * NCLS + t], s1 - s0);
-            L.wcnt[t] = 0;
-        }
-        if (t == 64) {
-            L.hdr[1] = min(bn.scnt[b], (int)bi.scap);
-            L.hdr[2] = 0;
-            L.hdr[3] = 0;
-            L.hdr[4] = min(bn.ctrl[BC_OVF0 + par_in], BIN_OVF_CAP);
-            L.hdr[5] = min(bn.ctrl[BC_SOVF], bn.sovf_cap);
-        }
-        if (t == 128) shift_of(s, A.seed, step, r, L.sh);
-        if (t == 192) shift_of(s, A.seed, step + 1, r, L.sh1);
-        for (int c = t; c < ncb; c += BRICK_T) {
-            L.cnt[c] = 0;
-#pragma unroll
-            for (int z = 0; z < 5; ++z) L.acc[5 * c + z] = 0ull;
-        }
-        __syncthreads();
-        if (t < 64) {  // exclusive prefix of the input fills (wave 0)
-            const int v = t < NCLS ? L.cin[t] : 0;
+        if (t < 64) {
+            // wave 0 reads the brick's header in one round: the input fills (a
+            // sub-region without a writer has capacity 0) and their exclusive
+            // prefix, the sub-regions this brick writes, the site count, the overflow flag and list lengths, and
+            // the grid shifts of this step and the next from the table the
+            // previous launch (or the packing) stored, drawn here if it is stale
+            int v = 0;
+            if (t < NCLS) {
+                const int32_t *sp = bn.subpre + b * (NCLS + 1);
+                const int s0 = sp[t], s1 = sp[t + 1];
+                L.csub[t] = s0;
+                if (t == NCLS - 1) L.csub[NCLS] = s1;
+                v = min(bn.cnt[((int64_t)par_in * bn.nbricks + b) * NCLS + t], s1 - s0);
+                L.wcnt[t] = 0;
+                const int4 wt = bn.wtab[b * NCLS + t];  // the sub-region this brick writes with class t
+                L.woff[t] = wt.x;
+                L.wcap[t] = wt.y;
+                L.wdst[t] = wt.z;
+            }
+            if (t == 32) {
+                const int n = bn.scnt[b];
+                L.hdr[1] = min(n, (int)bi.scap);
+                L.hdr[6] = n > (int)bi.scap;  // sites of this brick in the site overflow list
+            }
+            if (t == 33) L.hdr[7] = bn.oflag[(int64_t)par_in * bn.nbricks + b];
+            if (t == 34) L.hdr[4] = min(bn.ctrl[BC_OVF0 + par_in], BIN_OVF_CAP);
+            if (t == 35) L.hdr[5] = min(bn.ctrl[BC_SOVF], bn.sovf_cap);
+            if (t == 36) {
+                L.hdr[2] = 0;
+                L.hdr[3] = 0;
+            }
+            if (t >= 40 && t < 46) {
+                const double *tab = bn.shtab + (int64_t)par_in * (1 + 6 * (int64_t)s.nsys);
+                const int k = t - 40;
+                if (tab[0] == (double)step) {
+                    const double w = tab[1 + 6 * r + k];
+                    if (k < 3) L.sh[k] = w;
+                    else L.sh1[k - 3] = w;
+                } else if (k == 0) {
+                    shift_of(s, A.seed, step, r, L.sh);
+                } else if (k == 1) {
+                    shift_of(s, A.seed, step + 1, r, L.sh1);
+                }
+            }
             int a = v;
 #pragma unroll
             for (int o = 1; o < 32; o <<= 1) {
@@ -3946,26 +3984,35 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
             if (t <= NCLS) L.cpre[t] = a - v;
             if (t == NCLS - 1) L.hdr[0] = a;
         }
-        // overflow entries addressed to this brick (the lists are nearly always empty)
-        for (int e = t; e < L.hdr[4]; e += BRICK_T)
-            if (bn.ovf_dest[(int64_t)par_in * BIN_OVF_CAP + e] == (int32_t)b) {
-                const int k = atomicAdd(&L.hdr[2], 1);
-                if (k < BRICK_OVL) L.lovf[k] = e;
-            }
-        for (int e = t; e < L.hdr[5]; e += BRICK_T)
-            if (bn.sovf[2 * e] == (int32_t)b) {
-                const int k = atomicAdd(&L.hdr[3], 1);
-                if (k < BRICK_OVL) L.lsovf[k] = e;
-            }
+        for (int c = t; c < ncb; c += BRICK_T) {
+            L.cnt[c] = 0;
+#pragma unroll
+            for (int z = 0; z < 5; ++z) L.acc[5 * c + z] = 0ull;
+        }
         __syncthreads();
-        if (L.hdr[2] > BRICK_OVL || L.hdr[3] > BRICK_OVL) {
-            st |= ST_BINERR;
+        if (L.hdr[6] || L.hdr[7]) {  // (uniform) overflow entries may be addressed to this brick
+            if (L.hdr[7])
+                for (int e = t; e < L.hdr[4]; e += BRICK_T)
+                    if (bn.ovf_dest[(int64_t)par_in * BIN_OVF_CAP + e] == (int32_t)b) {
+                        const int k = atomicAdd(&L.hdr[2], 1);
+                        if (k < BRICK_OVL) L.lovf[k] = e;
+                    }
+            if (L.hdr[6])
+                for (int e = t; e < L.hdr[5]; e += BRICK_T)
+                    if (bn.sovf[2 * e] == (int32_t)b) {
+                        const int k = atomicAdd(&L.hdr[3], 1);
+                        if (k < BRICK_OVL) L.lsovf[k] = e;
+                    }
             __syncthreads();
-            if (t == 0) {
-                L.hdr[2] = min(L.hdr[2], BRICK_OVL);
-                L.hdr[3] = min(L.hdr[3], BRICK_OVL);
+            if (L.hdr[2] > BRICK_OVL || L.hdr[3] > BRICK_OVL) {
+                st |= ST_BINERR;
+                __syncthreads();
+                if (t == 0) {
+                    L.hdr[2] = min(L.hdr[2], BRICK_OVL);
+                    L.hdr[3] = min(L.hdr[3], BRICK_OVL);
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
         const int nmem = L.hdr[0] + L.hdr[1] + L.hdr[2] + L.hdr[3];
         const float Lb[3] = {(float)((double)s.ncell[3 * r] * s.a), (float)((double)s.ncell[3 * r + 1] * s.a),
@@ -3985,7 +4032,6 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
             // while the member loads are in flight
             for (int c = t; c < ncb; c += BRICK_T)
                 cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.pre[c]);
-            brick_writer_info(bn, bi, b, g, L);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
@@ -4005,25 +4051,41 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                     brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, L.pre[c], A.cos_a, A.sin_a, A.kT_cell, A.seed,
                                           step, L.par + 12 * c, st);
             __syncthreads();
+            // rotate and stream every member and take its rank in its class
+            // from the LDS counters; the stores wait until the counts are final
+            // (a barrier after global stores would wait for their completion)
+            int rank[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
                 if (L.cnt[lc[k]] >= 2) brick_rotate_f32(L.par + 12 * lc[k], w[k], st);
+                if (id[k] < 0) continue;  // a site: written back below
+                int32_t dst;
+                const int cls = brick_stream<float>(A, bi, Lb, p[k], w[k], L.sh1, &dst, st);
+                lc[k] = cls >= 0 ? cls : NCLS;  // NCLS: beyond the neighbouring bricks
+                rank[k] = cls >= 0 ? atomicAdd(&L.wcnt[cls], 1) : dst;
+            }
+            __syncthreads();
+            if (t < NCLS && L.wdst[t] >= 0)  // the fill of every sub-region this brick writes (zero included)
+                bn.cnt[((int64_t)par_out * bn.nbricks + L.wdst[t]) * NCLS + t] = L.wcnt[t];
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                if (lc[k] < 0) continue;
                 if (id[k] < 0) {  // a site: its new velocity back to the site arrays
                     const int64_t j = -(int64_t)id[k] - 1, S = s.S;
                     A.vs[j] = w[k][0]; A.vs[S + j] = w[k][1]; A.vs[2 * S + j] = w[k][2];
-                    continue;
+                } else if (lc[k] == NCLS) {
+                    brick_put<float>(A, par_out, rank[k], 0, 0, 0, p[k], w[k], id[k], st);
+                } else {
+                    const int c = lc[k];
+                    brick_put<float>(A, par_out, L.wdst[c], L.woff[c], L.wcap[c], rank[k], p[k], w[k], id[k], st);
                 }
-                int32_t dst;
-                const int cls = brick_stream<float>(A, bi, Lb, p[k], w[k], L.sh1, &dst, st);
-                brick_emit<float>(A, L, par_out, cls, dst, p[k], w[k], id[k], st);
             }
         } else {
             // more members than the block holds: sums over chunks of the
             // member list, then a second load of each member to rotate it
             for (int c = t; c < ncb; c += BRICK_T)
                 cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.pre[c]);
-            brick_writer_info(bn, bi, b, g, L);
             for (int i = t; i < nmem; i += BRICK_T) {
                 float p[3], w[3];
                 int32_t id;
@@ -4061,16 +4123,33 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 const int cls = brick_stream<float>(A, bi, Lb, p, w, L.sh1, &dst, st);
                 brick_emit<float>(A, L, par_out, cls, dst, p, w, id, st);
             }
+            __syncthreads();
+            if (t < NCLS && L.wdst[t] >= 0)
+                bn.cnt[((int64_t)par_out * bn.nbricks + L.wdst[t]) * NCLS + t] = L.wcnt[t];
         }
-        __syncthreads();
-        // the fill of every sub-region this brick writes (zero included)
-        if (t < NCLS && L.wdst[t] >= 0)
-            bn.cnt[((int64_t)par_out * bn.nbricks + L.wdst[t]) * NCLS + t] = L.wcnt[t];
     }
+    // after the brick's barriers, so that their waits do not include these
+    // stores: block 0 stores the step bookkeeping and the next step's shift
+    // table (the other parity), and every block clears its share of the
+    // body-centre grid for this step's insertions
+    if (blockIdx.x == 0) {
+        if (t == 0 && A.step_next) *A.step_next = step + 1;
+        if (A.shift_out) draw_shifts(s, A.seed, step, A.shift_out);
+        binned_store_shifts(s, bn, A.seed, step + 1);
+    }
+    for (int64_t q = (int64_t)blockIdx.x * BRICK_T + t; A.grid_clear && q < A.grid_n; q += (int64_t)gridDim.x * BRICK_T)
+        A.grid_clear[q] = 0;
     flag(A.status, st);
 }
 
 __global__ void k_binned_finish(BinnedDev bn, const uint64_t *d_step) { binned_finish(bn, *d_step); }
+
+// The shift table of the step *d_step (one block), for the first brick
+// collision after a packing.
+__global__ void k_binned_shtab(SysDev s, BinnedDev bn, uint64_t seed, const uint64_t *d_step)
+{
+    binned_store_shifts(s, bn, seed, *d_step);
+}
 
 // The site lists cleared, for a site listing launched on its own.
 __global__ void k_binned_clear_sites(BinnedDev bn)
@@ -4138,16 +4217,14 @@ __global__ __launch_bounds__(BODY_T) void k_forces_therm_bin(SysDev s, BodyDev b
 // of its cells on the grid of the step *d_step.
 template <typename Real>
 __global__ void k_binned_pack(SysDev s, BinnedDev bn, uint64_t seed, const uint64_t *d_step, const Real *x,
-                              const Real *v, const int32_t *tag, Real *xb, Real *vb, int32_t *tagb, uint32_t *status)
+                              const Real *v, const int32_t *tag, Real *rec, uint32_t *status)
 {
     uint32_t st = 0;
     const uint64_t step = *d_step;
     const int par = (int)(step & 1);
     BrickArgs<Real> A;
     A.bn = bn;
-    A.xo = xb;
-    A.vo = vb;
-    A.tago = tagb;
+    A.reco = rec;
     const int64_t N = s.N;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         const int r = find_sys(s.solv_off, s.nsys, i);
@@ -4167,12 +4244,12 @@ __global__ void k_binned_pack(SysDev s, BinnedDev bn, uint64_t seed, const uint6
 // Binned solvent of the step *d_step back to dense arrays in identity order
 // (x[:, id] = the member's position, tag[id] = id).
 template <typename Real>
-__global__ void k_binned_unpack(SysDev s, BinnedDev bn, const uint64_t *d_step, const Real *xb, const Real *vb,
-                                const int32_t *tagb, Real *x, Real *v, int32_t *tag, uint32_t *status)
+__global__ void k_binned_unpack(SysDev s, BinnedDev bn, const uint64_t *d_step, const Real *rec, Real *x, Real *v,
+                                int32_t *tag, uint32_t *status)
 {
     uint32_t st = 0;
     const int par = (int)(*d_step & 1);
-    const int64_t N = s.N, C = bn.cap;
+    const int64_t N = s.N;
     auto put = [&](int32_t id, const Real p[3], const Real w[3]) {
         if (id < 0 || id >= N) {
             st |= ST_BINERR;
@@ -4191,9 +4268,10 @@ __global__ void k_binned_unpack(SysDev s, BinnedDev bn, const uint64_t *d_step, 
         for (int c = 0; c < NCLS; ++c) {  // fills of sub-regions without a writer stay zero
             const int n = min(bn.cnt[((int64_t)par * bn.nbricks + b) * NCLS + c], sp[c + 1] - sp[c]);
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const int64_t q = bi.off + sp[c] + i;
-                const Real p[3] = {xb[q], xb[C + q], xb[2 * C + q]}, w[3] = {vb[q], vb[C + q], vb[2 * C + q]};
-                put(tagb[q], p, w);
+                Real p[3], w[3];
+                int32_t id;
+                rec_load(rec, bi.off + sp[c] + i, p, w, id);
+                put(id, p, w);
             }
         }
     }
@@ -4265,6 +4343,7 @@ struct BinnedPlan {
     int32_t sovf_cap = 0;
     std::vector<BrickInfo> brick;
     std::vector<int32_t> subpre, sys_bb, sys_bg;
+    std::vector<int4> wtab;
 };
 
 // tables == false: sizes only.
@@ -4356,11 +4435,28 @@ int binned_plan(const mpcd_sys *sys, const int32_t *ncell, const int64_t *solv_o
     if (P.cap >= ((int64_t)1 << 31) || P.sslots >= ((int64_t)1 << 31) || P.nbricks >= ((int64_t)1 << 30))
         return MPCD_EINVAL;
     P.sovf_cap = sovf_cap_of(sys);
+    if (tables) {  // the sub-region each brick writes with each class (the inverse of the class code)
+        P.wtab.assign((size_t)P.nbricks * NCLS, make_int4(0, 0, -1, 0));
+        for (int64_t b = 0; b < P.nbricks; ++b) {
+            const BrickInfo &bi = P.brick[b];
+            const int32_t *g = &P.sys_bg[6 * bi.sys];
+            for (int c = 0; c < NCLS; ++c) {
+                const int c3[3] = {c % 3, (c / 3) % 3, c / 9};
+                if (!(code_valid(c3[0], g[3]) && code_valid(c3[1], g[4]) && code_valid(c3[2], g[5]))) continue;
+                int bc[3];
+                for (int d = 0; d < 3; ++d) bc[d] = code_dst(bi.org[d] >> g[d], c3[d], g[3 + d]);
+                const int32_t db = P.sys_bb[bi.sys] + (bc[2] * g[4] + bc[1]) * g[3] + bc[0];
+                const int32_t *dp = &P.subpre[(size_t)db * (NCLS + 1)];
+                P.wtab[(size_t)b * NCLS + c] = make_int4((int)(P.brick[db].off + dp[c]), dp[c + 1] - dp[c], db, 0);
+            }
+        }
+    }
     return MPCD_OK;
 }
 
 struct BinnedLayout {
-    size_t ctrl, brick, subpre, sys_bb, sys_bg, cnt, scnt, sslot, ovf_dest, ovf_tag, ovf_xv, sovf, total;
+    size_t ctrl, brick, subpre, sys_bb, sys_bg, cnt, scnt, sslot, ovf_dest, ovf_tag, ovf_xv, sovf, oflag, shtab, wtab,
+        total;
 };
 
 BinnedLayout binned_layout(const mpcd_sys *sys, int64_t nbricks, int64_t sslots, int32_t sovf_cap)
@@ -4384,6 +4480,9 @@ BinnedLayout binned_layout(const mpcd_sys *sys, int64_t nbricks, int64_t sslots,
     L.ovf_tag = take(sizeof(int32_t) * 2 * BIN_OVF_CAP);
     L.ovf_xv = take(esize(sys) * 12 * BIN_OVF_CAP);
     L.sovf = take(sizeof(int32_t) * 2 * (size_t)sovf_cap);
+    L.oflag = take(sizeof(int32_t) * 2 * (size_t)nbricks);
+    L.shtab = take(sizeof(double) * 2 * (1 + 6 * (size_t)sys->nsys));
+    L.wtab = take(sizeof(int4) * NCLS * (size_t)nbricks);
     L.total = off;
     return L;
 }
@@ -4404,6 +4503,7 @@ BinnedDev binned_dev(const mpcd_sys *sys, const mpcd_binned *b)
     d.ctrl = (int32_t *)(w + L.ctrl);
     d.brick = (const BrickInfo *)(w + L.brick);
     d.subpre = (const int32_t *)(w + L.subpre);
+    d.wtab = (const int4 *)(w + L.wtab);
     d.sys_bb = (const int32_t *)(w + L.sys_bb);
     d.sys_bg = (const int32_t *)(w + L.sys_bg);
     d.cnt = (int32_t *)(w + L.cnt);
@@ -4413,6 +4513,8 @@ BinnedDev binned_dev(const mpcd_sys *sys, const mpcd_binned *b)
     d.ovf_tag = (int32_t *)(w + L.ovf_tag);
     d.ovf_xv = (void *)(w + L.ovf_xv);
     d.sovf = (int32_t *)(w + L.sovf);
+    d.oflag = (int32_t *)(w + L.oflag);
+    d.shtab = (double *)(w + L.shtab);
     d.nbricks = b->nbricks;
     d.cap = b->capacity;
     d.sovf_cap = sovf_cap_of(sys);
@@ -4931,12 +5033,8 @@ static void launch_brick_collide(const Ctx &c, hipStream_t st, const mpcd_step_a
     BrickArgs<float> A;
     A.s = c.sd;
     A.bn = binned_dev(c.sys, a->binned);
-    A.x = (const float *)a->x;
-    A.v = (const float *)a->v;
-    A.tag = a->tag;
-    A.xo = (float *)a->x_out;
-    A.vo = (float *)a->v_out;
-    A.tago = a->tag_out;
+    A.rec = (const float *)a->x;
+    A.reco = (float *)a->x_out;
     A.xs = (float *)a->xs;
     A.vs = (float *)a->vs;
     A.site_m = a->bodies.site_m;
@@ -5293,20 +5391,23 @@ static int step_checks(const mpcd_step_args *a)
     const mpcd_sys *s = a->sys;
     const mpcd_params &p = a->par;
     TRY(thermalize_checks(s, &a->bodies, p.kT, p.thermalize, a->d_step, a->xs, a->vs, a->ws, a->ws_bytes));
-    TRY(bin_checks(s, a->x, a->xs, &a->bodies, a->d_step, a->ws, a->ws_bytes));
-    TRY(collide_checks(s, a->v, a->tag, a->vs, &a->bodies, a->d_step, a->ws, a->ws_bytes, a->x, p.dt));
     TRY(wca_check(&p.wca));
     if (!tune_ok(p.tune, s->prec == MPCD_F64)) return MPCD_EINVAL;
     if (!(p.dt > 0.0)) return MPCD_EINVAL;
     if (!ok_arr(a->J, s->n_bodies, 8) || !ok_arr(a->K, s->n_bodies, 8)) return MPCD_EINVAL;
+    if (a->binned) {  // x and x_out: the solvent records of this step and the next
+        TRY(check_binned(s, a->binned));
+        if (s->prec != MPCD_F32 || a->rnemd || !p.fuse_stream) return MPCD_ENOTSUP;
+        if (!a->x || !a->x_out || !aligned(a->x, 16) || !aligned(a->x_out, 16) || a->x == a->x_out) return MPCD_EINVAL;
+        if (a->v || a->tag || a->v_out || a->tag_out || a->reorder_every != 0) return MPCD_EINVAL;
+        if (s->n_sites > 0 && !a->bodies.site_m) return MPCD_EINVAL;
+        return MPCD_OK;
+    }
+    TRY(bin_checks(s, a->x, a->xs, &a->bodies, a->d_step, a->ws, a->ws_bytes));
+    TRY(collide_checks(s, a->v, a->tag, a->vs, &a->bodies, a->d_step, a->ws, a->ws_bytes, a->x, p.dt));
     if (a->reorder_every < 0 || (a->reorder_every > 0 && !ok_arr(a->tag, s->n_solvent, 4))) return MPCD_EINVAL;
     TRY(out_checks(s, a->v, a->tag, a->x, a->x_out, a->v_out, a->tag_out));
     if (a->v_out && !p.fuse_stream) return MPCD_ENOTSUP;
-    if (a->binned) {
-        TRY(check_binned(s, a->binned));
-        if (s->prec != MPCD_F32 || a->rnemd) return MPCD_ENOTSUP;
-        if (!a->x_out || !a->v_out || !a->tag_out || !a->tag || a->reorder_every != 0) return MPCD_EINVAL;
-    }
     if (a->rnemd)
         TRY(rnemd_checks(s, a->v_out ? a->x_out : a->x, a->v_out ? a->v_out : a->v, a->tag, a->rnemd, a->rnemd_dp,
                          a->ws, a->ws_bytes));
@@ -5476,7 +5577,9 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
 {
     if (!stream || !args || nsteps < 1 || !graph_exec) return MPCD_EINVAL;
     TRY(step_checks(args));
-    if (args->v_out && ((nsteps & 1) || !args->tag)) return MPCD_EINVAL;
+    // out of place (the dense form's three output arrays, or the binned records)
+    const bool oop = args->x_out != nullptr;
+    if (oop && ((nsteps & 1) || (!args->binned && !args->tag))) return MPCD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     // the binned layout fuses each next step's thermalization and site
     // binning into the force kernel (bodies with sites, no site-site WCA)
@@ -5509,7 +5612,7 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
         return rc;
     }
     mpcd_step_args swapped = *args;  // odd steps of the out-of-place form: outputs become inputs
-    if (args->v_out) {
+    if (oop) {
         swapped.x = args->x_out;
         swapped.v = args->v_out;
         swapped.tag = args->tag_out;
@@ -5520,8 +5623,8 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
     for (int i = 0; i < nsteps && rc == MPCD_OK; ++i) {
         ov.pre_binned = overlap && i > 0;
         ov.bin_next = overlap && i + 1 < nsteps;
-        rc = step_impl(stream, (args->v_out && (i & 1)) ? &swapped : args, overlap ? &ov : nullptr);
-        if (rc == MPCD_OK && !args->v_out && args->reorder_every > 0 && (i + 1) % args->reorder_every == 0)
+        rc = step_impl(stream, (oop && (i & 1)) ? &swapped : args, overlap ? &ov : nullptr);
+        if (rc == MPCD_OK && !oop && args->reorder_every > 0 && (i + 1) % args->reorder_every == 0)
             rc = mpcd_reorder(stream, args->sys, args->x, args->v, (int32_t *)args->tag, args->ws, args->ws_bytes);
     }
     hipGraph_t graph = nullptr;
@@ -5737,25 +5840,29 @@ int mpcd_binned_init(void *stream, const mpcd_sys *sys, const int32_t *ncell, co
     TRY(hip_check(hipMemcpy(w + L.subpre, P.subpre.data(), sizeof(int32_t) * P.subpre.size(), hipMemcpyHostToDevice)));
     TRY(hip_check(hipMemcpy(w + L.sys_bb, P.sys_bb.data(), sizeof(int32_t) * P.sys_bb.size(), hipMemcpyHostToDevice)));
     TRY(hip_check(hipMemcpy(w + L.sys_bg, P.sys_bg.data(), sizeof(int32_t) * P.sys_bg.size(), hipMemcpyHostToDevice)));
+    TRY(hip_check(hipMemcpy(w + L.wtab, P.wtab.data(), sizeof(int4) * P.wtab.size(), hipMemcpyHostToDevice)));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (int32_t *)(w + L.ctrl), (int64_t)BC_WORDS, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * NCLS * P.nbricks, 256)), dim3(256), 0, st,
                        (int32_t *)(w + L.cnt), 2 * NCLS * P.nbricks, 0);  // both parities' fills
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(P.nbricks, 256)), dim3(256), 0, st, (int32_t *)(w + L.scnt),
                        P.nbricks, 0);  // the site counts
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * P.nbricks, 256)), dim3(256), 0, st, (int32_t *)(w + L.oflag),
+                       2 * P.nbricks, 0);  // the overflow flags
+    const int64_t tab_words = 4 * (1 + 6 * (int64_t)sys->nsys);  // both shift tables: NaN, matching no step
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(tab_words, 256)), dim3(256), 0, st, (int32_t *)(w + L.shtab),
+                       tab_words, -1);
     return launch_check();
 }
 
-int mpcd_binned_pack(void *stream, const mpcd_sys *sys, const void *x, const void *v, const int32_t *tag, void *xb,
-                     void *vb, int32_t *tagb, uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes,
-                     const mpcd_binned *b)
+int mpcd_binned_pack(void *stream, const mpcd_sys *sys, const void *x, const void *v, const int32_t *tag, void *rec,
+                     uint64_t seed, const uint64_t *d_step, void *ws, size_t ws_bytes, const mpcd_binned *b)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
     TRY(check_binned(sys, b));
     const size_t es = esize(sys);
     const int64_t N = sys->n_solvent;
-    if (!ok_arr(x, N, es) || !ok_arr(v, N, es) || !ok_arr(tag, 0, 4) || !ok_arr(xb, b->capacity, es) ||
-        !ok_arr(vb, b->capacity, es) || !ok_arr(tagb, b->capacity, 4) || !d_step)
+    if (!ok_arr(x, N, es) || !ok_arr(v, N, es) || !ok_arr(tag, 0, 4) || !rec || !aligned(rec, 16) || !d_step)
         return MPCD_EINVAL;
     const BinnedDev bn = binned_dev(sys, b);
     const SysDev sd = make_sysdev(sys);
@@ -5765,28 +5872,29 @@ int mpcd_binned_pack(void *stream, const mpcd_sys *sys, const void *x, const voi
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * NCLS * bn.nbricks, 256)), dim3(256), 0, st, bn.cnt,
                        2 * NCLS * bn.nbricks, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, bn.ctrl + BC_OVF0, (int64_t)2, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * bn.nbricks, 256)), dim3(256), 0, st, bn.oflag, 2 * bn.nbricks, 0);
+    hipLaunchKernelGGL(k_binned_shtab, dim3(1), dim3(256), 0, st, sd, bn, seed, d_step);
     if (N > 0) {
         const unsigned g = grid_for(N, 256, 1 << 16);
         if (sys->prec == MPCD_F64)
             hipLaunchKernelGGL(k_binned_pack<double>, dim3(g), dim3(256), 0, st, sd, bn, seed, d_step,
-                               (const double *)x, (const double *)v, tag, (double *)xb, (double *)vb, tagb, status);
+                               (const double *)x, (const double *)v, tag, (double *)rec, status);
         else
             hipLaunchKernelGGL(k_binned_pack<float>, dim3(g), dim3(256), 0, st, sd, bn, seed, d_step,
-                               (const float *)x, (const float *)v, tag, (float *)xb, (float *)vb, tagb, status);
+                               (const float *)x, (const float *)v, tag, (float *)rec, status);
     }
     return launch_check();
 }
 
-int mpcd_binned_unpack(void *stream, const mpcd_sys *sys, const void *xb, const void *vb, const int32_t *tagb, void *x,
-                       void *v, int32_t *tag, const uint64_t *d_step, void *ws, size_t ws_bytes, const mpcd_binned *b)
+int mpcd_binned_unpack(void *stream, const mpcd_sys *sys, const void *rec, void *x, void *v, int32_t *tag,
+                       const uint64_t *d_step, void *ws, size_t ws_bytes, const mpcd_binned *b)
 {
     TRY(check_sys(sys));
     TRY(check_ws(sys, ws, ws_bytes));
     TRY(check_binned(sys, b));
     const size_t es = esize(sys);
     const int64_t N = sys->n_solvent;
-    if (!ok_arr(x, N, es) || !ok_arr(v, N, es) || !ok_arr(tag, N, 4) || !ok_arr(xb, b->capacity, es) ||
-        !ok_arr(vb, b->capacity, es) || !ok_arr(tagb, b->capacity, 4) || !d_step)
+    if (!ok_arr(x, N, es) || !ok_arr(v, N, es) || !ok_arr(tag, N, 4) || !rec || !aligned(rec, 16) || !d_step)
         return MPCD_EINVAL;
     if (N == 0) return MPCD_OK;
     const BinnedDev bn = binned_dev(sys, b);
@@ -5795,11 +5903,11 @@ int mpcd_binned_unpack(void *stream, const mpcd_sys *sys, const void *xb, const 
     uint32_t *status = at<uint32_t>(ws, layout_of(sys).status);
     const unsigned g = (unsigned)std::min<int64_t>(bn.nbricks, 1 << 16);
     if (sys->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_binned_unpack<double>, dim3(g), dim3(256), 0, st, sd, bn, d_step, (const double *)xb,
-                           (const double *)vb, tagb, (double *)x, (double *)v, tag, status);
+        hipLaunchKernelGGL(k_binned_unpack<double>, dim3(g), dim3(256), 0, st, sd, bn, d_step, (const double *)rec,
+                           (double *)x, (double *)v, tag, status);
     else
-        hipLaunchKernelGGL(k_binned_unpack<float>, dim3(g), dim3(256), 0, st, sd, bn, d_step, (const float *)xb,
-                           (const float *)vb, tagb, (float *)x, (float *)v, tag, status);
+        hipLaunchKernelGGL(k_binned_unpack<float>, dim3(g), dim3(256), 0, st, sd, bn, d_step, (const float *)rec,
+                           (float *)x, (float *)v, tag, status);
     return launch_check();
 }
 

@@ -136,8 +136,8 @@ def load(path: str = LIB_PATH):
                                          C.POINTER(MpcdBinned)]),
         "mpcd_binned_init": (C.c_int, [vp, sp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                        C.POINTER(MpcdBinned)]),
-        "mpcd_binned_pack": (C.c_int, [vp, sp, vp, vp, vp, vp, vp, vp, u64, vp, vp, sz, C.POINTER(MpcdBinned)]),
-        "mpcd_binned_unpack": (C.c_int, [vp, sp, vp, vp, vp, vp, vp, vp, vp, vp, sz, C.POINTER(MpcdBinned)]),
+        "mpcd_binned_pack": (C.c_int, [vp, sp, vp, vp, vp, vp, u64, vp, vp, sz, C.POINTER(MpcdBinned)]),
+        "mpcd_binned_unpack": (C.c_int, [vp, sp, vp, vp, vp, vp, vp, vp, sz, C.POINTER(MpcdBinned)]),
         "mpcd_binned_collide": (C.c_int, [vp, C.POINTER(MpcdStepArgs)]),
         "mpcd_binned_sites": (C.c_int, [vp, C.POINTER(MpcdStepArgs)]),
     }

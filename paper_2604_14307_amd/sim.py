@@ -167,17 +167,18 @@ class GPUSystem:
         L.check(self.lib.mpcd_binned_init(self.stream, C.byref(self.csys), *hp, C.byref(b)), "mpcd_binned_init")
         cap = int(b.capacity)
         xd, vd, td = self.x, self.v, self.tag
-        self.x = torch.zeros((3, cap), dtype=self.real, device=self.device)
-        self.v = torch.zeros((3, cap), dtype=self.real, device=self.device)
-        self.tag = torch.full((cap,), -1, dtype=torch.int32, device=self.device)
-        self.x2, self.v2, self.tag2 = torch.zeros_like(self.x), torch.zeros_like(self.v), torch.full_like(self.tag, -1)
+        # x, x2: the solvent records of the current and the next step (8
+        # values each: position, identity bits, velocity, unused); no v, tag
+        self.x = torch.zeros((cap, 8), dtype=self.real, device=self.device)
+        self.x2 = torch.zeros_like(self.x)
+        self.v = self.v2 = self.tag = self.tag2 = None
         self._pack(xd, vd, td)
-        self._state = self._STATE + ("bws",)
+        self._state = tuple(k for k in self._STATE if k not in ("v", "tag")) + ("bws",)
 
     def _pack(self, xd, vd, td):
         L.check(self.lib.mpcd_binned_pack(self.stream, C.byref(self.csys), _ptr(xd), _ptr(vd), _ptr(td), _ptr(self.x),
-                                          _ptr(self.v), _ptr(self.tag), self.params["seed"], _ptr(self.d_step),
-                                          _ptr(self.ws), self.ws_bytes, C.byref(self.binned)), "mpcd_binned_pack")
+                                          self.params["seed"], _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
+                                          C.byref(self.binned)), "mpcd_binned_pack")
 
     def dense_solvent(self):
         """(x [3,N], v [3,N], tag [N]) of the current solvent as device tensors:
@@ -189,9 +190,9 @@ class GPUSystem:
         xd = torch.full((3, self.N), float("nan"), dtype=self.real, device=self.device)
         vd = torch.full((3, self.N), float("nan"), dtype=self.real, device=self.device)
         td = torch.full((self.N,), -1, dtype=torch.int32, device=self.device)
-        L.check(self.lib.mpcd_binned_unpack(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(self.v),
-                                            _ptr(self.tag), _ptr(xd), _ptr(vd), _ptr(td), _ptr(self.d_step),
-                                            _ptr(self.ws), self.ws_bytes, C.byref(self.binned)), "mpcd_binned_unpack")
+        L.check(self.lib.mpcd_binned_unpack(self.stream, C.byref(self.csys), _ptr(self.x), _ptr(xd), _ptr(vd),
+                                            _ptr(td), _ptr(self.d_step), _ptr(self.ws), self.ws_bytes,
+                                            C.byref(self.binned)), "mpcd_binned_unpack")
         return xd, vd, td
 
     # ------------------------------------------------------------------
