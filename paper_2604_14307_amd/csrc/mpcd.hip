@@ -327,8 +327,10 @@ constexpr int SCAN_T = 1024, SCAN_V = 4, SCAN_TILE = SCAN_T * SCAN_V;
 constexpr int64_t SCAN_BIG_C = 1 << 19;
 constexpr int scan_v(int64_t C) { return C > SCAN_BIG_C ? 16 : 4; }
 
-// Slots per bucket of the body-centre grid.
-constexpr int GRID_K = 8;
+// Slots per bucket of the body-centre grid: at one or two bodies per cell on
+// average a bucket of 32 practically never overflows (a body whose 27
+// neighbouring buckets include a full one takes the all-pairs loop).
+constexpr int GRID_K = 32;
 
 // Reverse nonequilibrium exchange: key histogram bins over [0, RN_KMAX) (the
 // last bin also takes larger keys), candidate capacity per slab, pair limit.
@@ -2948,7 +2950,15 @@ __global__ __launch_bounds__(BODY_T) void k_forces_prep(SysDev s, BodyDev bd, mp
 // contribute and is skipped).  Lanes 0..5 then add f_j and d_j x f_j in site
 // order.  With kick != 0 the second half kick follows; with advance_step set,
 // block 0 advances the step counter.
-__device__ __forceinline__ double min_image(double t, double L) { return t - L * rint(t / L); }
+// Minimum image t - L rint(t / L).  Within half a box the quotient rounds to
+// a zero (ties to even at exactly one half) and the result is t itself (a
+// negative zero becomes +0, as t - L rint(t / L) gives), so that case skips
+// the division.
+__device__ __forceinline__ double min_image(double t, double L)
+{
+    if (fabs(t) < 0.5 * L) return t + 0.0;
+    return t - L * rint(t / L);
+}
 
 __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid,
                                                         SiteFrames fr, ExtForce E, double dt, int kick,
@@ -2960,6 +2970,7 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
     __shared__ int s_ovf, s_nnb;
     __shared__ int nb[NCAND];
     __shared__ double sh[6 * SH_PAD];
+    __shared__ double sp[3][BODY_T];  // a chunk of one candidate body's site positions
     __shared__ double fT[6];
     const int64_t i = blockIdx.x;
     if (advance_step && i == 0 && threadIdx.x == 0) *advance_step = *advance_step + 1;
@@ -3054,42 +3065,67 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
     const int64_t j0 = bd.site_off[i], j1 = bd.site_off[i + 1];
     double acc = 0.0;
     for (int64_t c0 = j0; c0 < j1; c0 += BODY_T) {
+        // one site of body i per thread; the candidate bodies in ascending
+        // order, each one's sites staged through LDS in chunks and taken in
+        // ascending order (the same pairs and sums as one site at a time)
         const int64_t j = c0 + t;
-        if (j < j1) {
-            const double pj[3] = {fr.pos[j], fr.pos[S + j], fr.pos[2 * S + j]};
-            double f[3] = {0.0, 0.0, 0.0};
-            for (int q = 0; q < ncand; ++q) {
-                const int64_t b2 = use_grid ? (int64_t)nb[q] : jb + q;
-                if (b2 == i) continue;
+        const bool active = j < j1;
+        double pj[3] = {0.0, 0.0, 0.0};
+        if (active) {
+            pj[0] = fr.pos[j];
+            pj[1] = fr.pos[S + j];
+            pj[2] = fr.pos[2 * S + j];
+        }
+        double f[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < ncand; ++q) {
+            const int64_t b2 = use_grid ? (int64_t)nb[q] : jb + q;
+            if (b2 == i) continue;  // (uniform)
+            bool near = false;
+            if (active) {
                 double d2 = 0.0;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const double d = min_image(pj[k] - bd.pos[k * B + b2], Lb[k]);
                     d2 = d2 + d * d;
                 }
-                if (!(d2 <= cut_s)) continue;
-                for (int64_t k2 = bd.site_off[b2]; k2 < bd.site_off[b2 + 1]; ++k2) {
-                    double dr[3];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) dr[k] = min_image(pj[k] - fr.pos[k * S + k2], Lb[k]);
-                    const double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
-                    if (!(r2 <= rc2)) continue;
-                    const double rr = sqrt(r2);
-                    const double shf = rr - wca.delta;
-                    if (!(shf > 0.0)) {
-                        st |= ST_NONFINITE;
-                        continue;
-                    }
-                    const double is = wca.sigma / shf;
-                    const double is2 = is * is;
-                    const double is6 = (is2 * is2) * is2;
-                    const double is12 = is6 * is6;
-                    const double frr = ((24.0 * wca.eps) * (2.0 * is12 - is6)) / shf;
-                    const double fo = frr / rr;
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) f[k] = f[k] + fo * dr[k];
-                }
+                near = d2 <= cut_s;
             }
+            if (!__syncthreads_or(near)) continue;  // no site of this chunk within reach of b2
+            const int64_t k0 = bd.site_off[b2], k1 = bd.site_off[b2 + 1];
+            for (int64_t kc = k0; kc < k1; kc += BODY_T) {
+                const int nk = (int)((k1 - kc) < BODY_T ? (k1 - kc) : BODY_T);
+                if (t < nk) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) sp[k][t] = fr.pos[k * S + kc + t];
+                }
+                __syncthreads();
+                if (near) {
+                    for (int u = 0; u < nk; ++u) {
+                        double dr[3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) dr[k] = min_image(pj[k] - sp[k][u], Lb[k]);
+                        const double r2 = (dr[0] * dr[0] + dr[1] * dr[1]) + dr[2] * dr[2];
+                        if (!(r2 <= rc2)) continue;
+                        const double rr = sqrt(r2);
+                        const double shf = rr - wca.delta;
+                        if (!(shf > 0.0)) {
+                            st |= ST_NONFINITE;
+                            continue;
+                        }
+                        const double is = wca.sigma / shf;
+                        const double is2 = is * is;
+                        const double is6 = (is2 * is2) * is2;
+                        const double is12 = is6 * is6;
+                        const double frr = ((24.0 * wca.eps) * (2.0 * is12 - is6)) / shf;
+                        const double fo = frr / rr;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) f[k] = f[k] + fo * dr[k];
+                    }
+                }
+                __syncthreads();  // the chunk is consumed
+            }
+        }
+        if (active) {
             const double d[3] = {fr.off[j], fr.off[S + j], fr.off[2 * S + j]};
             double c[3];
             cross3(d, f, c);

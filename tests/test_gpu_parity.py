@@ -410,20 +410,36 @@ def point_bodies(ncell, centres, seed):
     return W.make_system(ncell, 0, [tpl] * len(centres), centres, q, rng)
 
 
+# slots per bucket of the kernels' body-centre grid
+GRID_SLOTS = 32
+
+
+def fullest_grid_cell(centres, ncell, rc):
+    """Bodies in the fullest cell of the body-centre grid (cells of edge
+    L / floor(0.999 L / rc) per axis, as the kernels build it)."""
+    L = np.asarray(ncell, dtype=np.float64)
+    ng = np.maximum(np.floor(0.999 * L / rc), 1.0)
+    cell = np.floor(np.asarray(centres) / (L / ng)).astype(np.int64)
+    _, counts = np.unique(cell, axis=0, return_counts=True)
+    return int(counts.max())
+
+
 @pytest.mark.parametrize("case", ["many", "crowded"])
 def test_wca_forces_neighbour_grid_bit_exact(case):
     """Body-centre WCA forces through the hashed neighbour grid equal the
     oracle's all-pairs loop: 2000 random point bodies (many partners per
-    body), and 30 bodies crowded into one grid cell (a bucket overflows and
-    the kernel falls back to all pairs)."""
+    body), and 45 bodies crowded into one grid cell (a bucket of 32 slots
+    overflows and the kernel falls back to all pairs)."""
     rng = np.random.default_rng(12)
     if case == "many":
         ncell, centres = (20, 20, 20), rng.random((2000, 3)) * 20.0
     else:
         ncell = (3, 3, 3)
-        centres = np.concatenate([0.2 + 1.1 * rng.random((30, 3)), 1.6 + 1.3 * rng.random((10, 3))])
+        centres = np.concatenate([0.2 + 1.1 * rng.random((45, 3)), 1.6 + 1.3 * rng.random((10, 3))])
     wl = point_bodies(ncell, centres, 13)
     par = W.srd_params(13, wca=W.wca_spheres(sigma=1.0))
+    if case == "crowded":
+        assert fullest_grid_cell(centres, ncell, 2.0 ** (1.0 / 6.0)) > GRID_SLOTS
     o = oracle.OracleSystem(wl, par)
     g = gpu_system(wl, par, prec="f64")
     o.body_forces()
@@ -470,9 +486,11 @@ def test_site_wca_crowded_bodies_fall_back_to_all_pairs():
     rng = np.random.default_rng(52)
     cube = np.array([[x, y, z] for x in (-0.5, 0.5) for y in (-0.5, 0.5) for z in (-0.5, 0.5)])
     tpl = W.rigid_template(cube, 1.0)
-    centres = np.concatenate([0.5 + 2.5 * rng.random((30, 3)), 6.0 + 3.0 * rng.random((10, 3))])
-    wl = W.make_system((10, 10, 10), 0, [tpl] * 40, centres, W.random_quaternions(rng, 40), rng)
+    centres = np.concatenate([0.5 + 2.5 * rng.random((45, 3)), 6.0 + 3.0 * rng.random((10, 3))])
+    wl = W.make_system((10, 10, 10), 0, [tpl] * 55, centres, W.random_quaternions(rng, 55), rng)
     par = W.srd_params(52, wca=W.wca_sites(sigma=0.7))
+    # the grid's cutoff for site-site WCA: twice the sites' reach plus the pair cutoff
+    assert fullest_grid_cell(centres, (10, 10, 10), 2.0 * np.sqrt(0.75) + 0.7 * 2.0 ** (1.0 / 6.0)) > GRID_SLOTS
     o = oracle.OracleSystem(wl, par)
     g = gpu_system(wl, par, prec="f64")
     o.body_forces()
