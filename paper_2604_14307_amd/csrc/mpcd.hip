@@ -1450,22 +1450,32 @@ constexpr double FIX_SCALE = 0x1p32, FIX_UNIT = 0x1p-32, FIX_LIM = 0x1p62;
 
 __device__ __forceinline__ long long fix_round(double a) { return __double2ll_rn(a); }
 
-__device__ __forceinline__ void fixed_terms(double mk, float fv0, float fv1, float fv2, long long q[5],
-                                            uint32_t &st)
+// The terms from mS = m 2^32 and q0 = its rounding, which a caller can form
+// once per species: (m 2^32) v equals (m v) 2^32 exactly (scaling by a power
+// of two commutes with rounding; neither product can underflow or overflow).
+__device__ __forceinline__ void fixed_terms_scaled(double mS, long long q0, float fv0, float fv1, float fv2,
+                                                   long long q[5], uint32_t &st)
 {
     const double v0 = (double)fv0, v1 = (double)fv1, v2 = (double)fv2;
-    const double a0 = (mk * v0) * FIX_SCALE, a1 = (mk * v1) * FIX_SCALE, a2 = (mk * v2) * FIX_SCALE;
-    const double ak = (mk * ((v0 * v0 + v1 * v1) + v2 * v2)) * FIX_SCALE;
+    const double a0 = mS * v0, a1 = mS * v1, a2 = mS * v2;
+    const double ak = mS * ((v0 * v0 + v1 * v1) + v2 * v2);
     if (!(fabs(a0) < FIX_LIM && fabs(a1) < FIX_LIM && fabs(a2) < FIX_LIM && ak < FIX_LIM)) {
         st |= ST_FIXOVF;
         q[0] = q[1] = q[2] = q[3] = q[4] = 0;
         return;
     }
-    q[0] = fix_round(mk * FIX_SCALE);
+    q[0] = q0;
     q[1] = fix_round(a0);
     q[2] = fix_round(a1);
     q[3] = fix_round(a2);
     q[4] = fix_round(ak);
+}
+
+__device__ __forceinline__ void fixed_terms(double mk, float fv0, float fv1, float fv2, long long q[5],
+                                            uint32_t &st)
+{
+    const double mS = mk * FIX_SCALE;
+    fixed_terms_scaled(mS, fix_round(mS), fv0, fv1, fv2, q, st);
 }
 
 // Relative kinetic energy of a cell, 1/2 (sum m |v|^2 - |sum m v|^2 / sum m),
@@ -4051,6 +4061,8 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
             }
         }
         const int nmem = L.hdr[0] + L.hdr[1] + L.hdr[2] + L.hdr[3];
+        const double mS_solvent = s.m * FIX_SCALE;  // the solvent's fixed-point mass, once
+        const long long q0_solvent = fix_round(mS_solvent);
         const float Lb[3] = {(float)((double)s.ncell[3 * r] * s.a), (float)((double)s.ncell[3 * r + 1] * s.a),
                              (float)((double)s.ncell[3 * r + 2] * s.a)};
         if (nmem <= ITEMS * BRICK_T) {
@@ -4073,9 +4085,12 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 if (lc[k] < 0) continue;
                 lc[k] = brick_local_cell<float>(s, bn, bi, b, p[k], L.sh, st);
                 if (lc[k] < 0) continue;
-                const double mk = id[k] >= 0 ? s.m : A.site_m[-(int64_t)id[k] - 1];
                 long long q[5];
-                fixed_terms(mk, w[k][0], w[k][1], w[k][2], q, st);
+                if (id[k] >= 0) {
+                    fixed_terms_scaled(mS_solvent, q0_solvent, w[k][0], w[k][1], w[k][2], q, st);
+                } else {
+                    fixed_terms(A.site_m[-(int64_t)id[k] - 1], w[k][0], w[k][1], w[k][2], q, st);
+                }
                 unsigned long long *acc = L.acc + 5 * lc[k];
 #pragma unroll
                 for (int z = 0; z < 5; ++z) atomicAdd(acc + z, (unsigned long long)q[z]);
@@ -4128,9 +4143,12 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 if (!brick_member<float>(A, bi, par_in, i, L, p, w, id, st)) continue;
                 const int c = brick_local_cell<float>(s, bn, bi, b, p, L.sh, st);
                 if (c < 0) continue;
-                const double mk = id >= 0 ? s.m : A.site_m[-(int64_t)id - 1];
                 long long q[5];
-                fixed_terms(mk, w[0], w[1], w[2], q, st);
+                if (id >= 0) {
+                    fixed_terms_scaled(mS_solvent, q0_solvent, w[0], w[1], w[2], q, st);
+                } else {
+                    fixed_terms(A.site_m[-(int64_t)id - 1], w[0], w[1], w[2], q, st);
+                }
 #pragma unroll
                 for (int z = 0; z < 5; ++z) atomicAdd(L.acc + 5 * c + z, (unsigned long long)q[z]);
                 atomicAdd(&L.cnt[c], 1);
