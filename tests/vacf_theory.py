@@ -31,13 +31,14 @@ def gamma_t(w, R, eta=ETA0, nu=NU0, rho=RHO0, c0=C0, eta_b=ETA_B):
     return (4.0 * math.pi / 3.0) * eta * R * x ** 2 * num / den
 
 
-def ct_theory(t, R, kT=1.0, dw=1e-3, wmax=1e3, **fluid):
+def ct_theory(t, R, kT=1.0, dw=1e-3, wmax=1e3, M=None, **fluid):
     """C_T(t) = (3 kT / 2 pi) int e^{-i w t} / (gamma_T - i w M_S) dw by the
     trapezoid rule on [-wmax, wmax] with step dw (the paper's quadrature);
-    gamma_T(0) = 6 pi eta R (its limit) at w = 0."""
+    gamma_T(0) = 6 pi eta R (its limit) at w = 0.  M: a particle mass in place
+    of the neutrally buoyant M_S (the same friction, another inertia)."""
     rho = fluid.get("rho", RHO0)
     eta = fluid.get("eta", ETA0)
-    MS = 4.0 * math.pi * R ** 3 * rho / 3.0
+    MS = 4.0 * math.pi * R ** 3 * rho / 3.0 if M is None else float(M)
     n = int(round(wmax / dw))
     w = dw * np.arange(1, n + 1)
     f = 1.0 / (gamma_t(w, R, **fluid) - 1j * w * MS)
@@ -51,13 +52,14 @@ def ct_theory(t, R, kT=1.0, dw=1e-3, wmax=1e3, **fluid):
     return np.array(out)
 
 
-def cr_theory(t, R, kT=1.0, eta=ETA0, nu=NU0, rho=RHO0):
+def cr_theory(t, R, kT=1.0, eta=ETA0, nu=NU0, rho=RHO0, I=None):
     """C_R(t): inverse Laplace transform of (3 kT / I_S) / (s + gamma_R(s) / I_S)
     with gamma_R = 8 pi eta R^3 [1 + (R^2 s/nu) / (3 (1 + sqrt(R^2 s / nu)))],
-    I_S = 2 M_S R^2 / 5 (mpmath's numerical inversion, as in the paper)."""
+    I_S = 2 M_S R^2 / 5 (mpmath's numerical inversion, as in the paper).  I: a
+    moment of inertia in place of I_S."""
     import mpmath as mp
     MS = 4.0 * math.pi * R ** 3 * rho / 3.0
-    IS = 2.0 * MS * R * R / 5.0
+    IS = 2.0 * MS * R * R / 5.0 if I is None else float(I)
 
     def F(s):
         a = R * R * s / nu
