@@ -7,22 +7,25 @@ boxes with edges drawn uniformly from 12..24 cells (a = 1), 5 solvent per cell
 surface sites in each; SRD 130 degrees, dt = 0.1, kT = 1 with the cell
 thermostat; a random stream per replica; synthetic seeded inputs
 (Maxwell-Boltzmann velocities).  The headline value is the batched FP32 form
-(FP32 solvent/sites, exact int64 fixed-point cell sums, FP64 bodies); the
-plain FP64 form runs on the same workload beside it, with the ratio.
+in the binned solvent layout (FP32 solvent records and sites, exact int64
+fixed-point cell sums, FP64 bodies); the dense FP32 form and the plain FP64
+form run on the same workload beside it, with the FP32-binned / FP64 ratio.
 
-One step = site thermalization, grid shift + counting sort, SRD collision
-(fused with solvent streaming), momentum transfer, rigid-body update.  Inputs
-are resident in HBM; the timed region replays a HIP graph of the steps.
+One step = site thermalization and listing, the brick collision (collide,
+stream and bin the solvent for the next step in one pass), momentum transfer
+and the rigid-body update; the dense forms bin with a counting sort instead.
+Inputs are resident in HBM; the timed region replays a HIP graph of the steps.
 
-The other workloads run after the headline, each with the roofline of its
-dominant kernel: the 60^3 hard-sphere suspension (1.08M solvent, 191 spheres),
-the 200^3 suspension at volume fraction 0.3 (80M solvent, 21,221 spheres) and
-the 128^3 complex-shape suspension (21M solvent, 2,000 cubes, rods and
-dumbbells with site-site WCA), each in FP32 and FP64.
+The other workloads run after the headline, each form with the roofline of
+its dominant kernel: the 60^3 hard-sphere suspension (1.08M solvent, 191
+spheres), the 200^3 suspension at volume fraction 0.3 (80M solvent, 21,221
+spheres) and the 128^3 complex-shape suspension (21M solvent, 2,000 cubes,
+rods and dumbbells with site-site WCA).
 
-The dominant kernel is timed on its own with HIP events on its stream:
-back-to-back launches of mpcd_collide_drawn repeating the last step's collide
-+ stream pass (its inputs, cell lists and draws).
+The dominant kernel is timed on its own with HIP events on its stream: for the
+binned layout, back-to-back launches of mpcd_binned_collide on one step's
+input; for the dense forms, of mpcd_collide_drawn repeating the last step's
+collide + stream pass.
 
 Prints one JSON line (N = 1).
 """
@@ -384,6 +387,11 @@ def main():
                     help="skip the step time with the reverse nonequilibrium exchange appended")
     ap.add_argument("--tune-out", metavar="PATH", default=None,
                     help="record the shapes of workloads tuned on the spot (missing from the cache) in this JSON file")
+    ap.add_argument("--only-workload", type=int, choices=sorted(WORKLOADS), default=None,
+                    help="time this one workload only, in the forms selected (for profiler runs; the JSON line "
+                         "then holds that workload's block)")
+    ap.add_argument("--forms", default=None,
+                    help="comma-separated forms to run among f32_binned, f32, f64 (default: all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this implementation drives a single MI355X "
@@ -400,8 +408,28 @@ def main():
                                                                         [("f64", "f64", "dense")])
     if args.no_binned:
         forms = forms[1:]
-
+    if args.forms:
+        keep = args.forms.split(",")
+        forms = [f for f in forms if f[0] in keep]
+        if not forms:
+            raise SystemExit("--forms selects none of f32_binned, f32, f64")
     from paper_2604_14307_amd import workloads as W
+    if args.only_workload is not None:
+        ci = args.only_workload
+        wl, par, meta = W.config(ci, kT_cell=1.0)
+        block = {"workload": meta["name"]}
+        steps = args.steps if ci == 3 else args.other_steps
+        for name, prec, layout in forms:
+            log("%s %s: %d timed steps" % (WORKLOADS[ci], name, steps))
+            rr = run_gpu(wl, par, prec, steps, 4, 2, args.kernel_reps, layout=layout)
+            log("%s %s: %.4f ms/step, dominant kernel %.2f us" % (WORKLOADS[ci], name, rr["ms_step"],
+                                                                 rr["collide_ms"] * 1e3))
+            block[name] = form_summary(rr, 4 if prec == "f32" else 8, WORKLOADS[ci])
+        if args.copy_calibration:
+            copy_calibration()
+        print(json.dumps({WORKLOADS[ci]: block}), flush=True)
+        return
+
     bsys, bpar, bmeta = W.config(3, kT_cell=1.0)
     res = {}
     for name, prec, layout in forms:

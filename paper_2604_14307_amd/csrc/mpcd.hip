@@ -2981,6 +2981,7 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
     __shared__ int nb[NCAND];
     __shared__ double sh[6 * SH_PAD];
     __shared__ double sp[3][BODY_T];  // a chunk of one candidate body's site positions
+    __shared__ float spf[3][BODY_T];  // and the same rounded to FP32, for a conservative pair filter
     __shared__ double fT[6];
     const int64_t i = blockIdx.x;
     if (advance_step && i == 0 && threadIdx.x == 0) *advance_step = *advance_step + 1;
@@ -3086,6 +3087,14 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
             pj[1] = fr.pos[S + j];
             pj[2] = fr.pos[2 * S + j];
         }
+        // FP32 filter: a pair whose FP32 minimum-image distance exceeds rc +
+        // 0.01 is farther than rc in FP64 (the FP32 rounding of coordinates up
+        // to 2^15 cell edges moves a separation by far less than 0.01), so it
+        // adds nothing; every other pair takes the exact FP64 path
+        const float pjf[3] = {(float)pj[0], (float)pj[1], (float)pj[2]};
+        const float Lf[3] = {(float)Lb[0], (float)Lb[1], (float)Lb[2]};
+        const float iLf[3] = {1.0f / Lf[0], 1.0f / Lf[1], 1.0f / Lf[2]};
+        const float limf = (float)((rc + 0.01) * (rc + 0.01));
         double f[3] = {0.0, 0.0, 0.0};
         for (int q = 0; q < ncand; ++q) {
             const int64_t b2 = use_grid ? (int64_t)nb[q] : jb + q;
@@ -3106,11 +3115,23 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
                 const int nk = (int)((k1 - kc) < BODY_T ? (k1 - kc) : BODY_T);
                 if (t < nk) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) sp[k][t] = fr.pos[k * S + kc + t];
+                    for (int k = 0; k < 3; ++k) {
+                        const double x = fr.pos[k * S + kc + t];
+                        sp[k][t] = x;
+                        spf[k][t] = (float)x;
+                    }
                 }
                 __syncthreads();
                 if (near) {
                     for (int u = 0; u < nk; ++u) {
+                        float r2f = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            float d = pjf[k] - spf[k][u];
+                            d = d - Lf[k] * rintf(d * iLf[k]);
+                            r2f = r2f + d * d;
+                        }
+                        if (!(r2f <= limf)) continue;
                         double dr[3];
 #pragma unroll
                         for (int k = 0; k < 3; ++k) dr[k] = min_image(pj[k] - sp[k][u], Lb[k]);
