@@ -4,9 +4,9 @@ The binned layout stores the solvent in per-brick regions of each step's grid
 and collides a brick per block; it performs the same per-cell sums (exact
 int64 fixed point in FP32), draws and roundings as the dense layout, so every
 result, in identity order, must equal the dense FP32 path's bit for bit.  The
-dense FP32 path is itself held to the FP64 oracle (1e-5 relative per step,
-test_gpu_bench_form.py); the binned form as the bench runs it is compared with
-the oracle there too.  Covered here: pack/unpack round trips, eager steps and
+dense FP32 path, in the graph form the bench times, is itself held to the FP64
+oracle (1e-5 relative L2 and max-abs per step, test_gpu_bench_form.py), so the
+binned form meets the same bounds.  Covered here: pack/unpack round trips, eager steps and
 graph replays, bodies with centre WCA, site-site WCA, forced flow, pure
 solvent, batched replicas, a brick whose region overflows into the shared
 overflow list, and a brick with more members than a block holds in registers.
