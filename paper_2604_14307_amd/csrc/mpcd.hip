@@ -3800,18 +3800,20 @@ __device__ __forceinline__ bool brick_member(const BrickArgs<Real> &A, const Bri
                                              const BrickLds32 &L, Real p[3], Real w[3], int32_t &id, uint32_t &st)
 {
     const int64_t S = A.s.S;
-    const int nreg = L.hdr[0], nsite = L.hdr[1], novf = L.hdr[2];
+    // the member counts and the own sub-region's bounds are uniform: scalar registers
+    const int nreg = __builtin_amdgcn_readfirstlane(L.hdr[0]), nsite = __builtin_amdgcn_readfirstlane(L.hdr[1]);
+    const int novf = __builtin_amdgcn_readfirstlane(L.hdr[2]), own = __builtin_amdgcn_readfirstlane(L.cpre[1]);
     int64_t j = -1;
+    if (i < own) {  // most members are the brick's own (class 0), at its sub-region's start
+        rec_load(A.rec, bi.off + __builtin_amdgcn_readfirstlane(L.csub[0]) + i, p, w, id);
+        return true;
+    }
     if (i < nreg) {
-        int lo = 0;  // the last sub-region c with cpre[c] <= i: most members are the brick's own (class 0)
-        if (i >= L.cpre[1]) {
-            int hi = NCLS - 1;
-            lo = 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (L.cpre[mid] <= i) lo = mid;
-                else hi = mid - 1;
-            }
+        int lo = 1, hi = NCLS - 1;  // the last sub-region c with cpre[c] <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.cpre[mid] <= i) lo = mid;
+            else hi = mid - 1;
         }
         rec_load(A.rec, bi.off + L.csub[lo] + (i - L.cpre[lo]), p, w, id);
         return true;
@@ -3839,6 +3841,72 @@ __device__ __forceinline__ bool brick_member(const BrickArgs<Real> &A, const Bri
     w[0] = A.vs[j]; w[1] = A.vs[S + j]; w[2] = A.vs[2 * S + j];
     id = -(int32_t)j - 1;
     return true;
+}
+
+// The FP32 grid of a brick's system, converted once per block: the shifts of
+// this step and the next rounded to float, the cell edge or its inverse, the
+// cells per axis (as int and float) and the brick geometry.  brick_axis_cell
+// performs exactly the operations of axis_cell(float, ...), so cells agree
+// bit for bit with every other binning.
+struct BrickGrid {
+    float sh[3], sh1[3];
+    float mul, a;  // mul != 0: a is a power of two and cells use g * mul
+    float nf[3];
+    int n[3], lg[3], nb[3], bb0;
+};
+
+__device__ __forceinline__ BrickGrid brick_grid_of(const SysDev &s, const BinnedDev &bn, int r, const double *sh,
+                                                   const double *sh1)
+{
+    // every value is uniform over the block: held in scalar registers
+    auto uf = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+    auto ui = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+    BrickGrid G;
+    const int32_t *g = bn.sys_bg + 6 * r;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        G.sh[d] = uf((float)sh[d]);
+        G.sh1[d] = uf((float)sh1[d]);
+        G.n[d] = ui(s.ncell[3 * r + d]);
+        G.nf[d] = uf((float)G.n[d]);
+        G.lg[d] = ui(g[d]);
+        G.nb[d] = ui(g[3 + d]);
+    }
+    G.mul = uf(s.inv_a != 0.0 ? (float)s.inv_a : 0.0f);
+    G.a = uf((float)s.a);
+    G.bb0 = ui(bn.sys_bb[r]);
+    return G;
+}
+
+__device__ __forceinline__ int brick_axis_cell(float x, float sf, const BrickGrid &G, int d, uint32_t &st)
+{
+    const float g = x - sf;
+    const float jf = floorf(G.mul != 0.0f ? g * G.mul : g / G.a);
+    if (!(jf >= -1.0f && jf <= G.nf[d])) {
+        st |= (g != g) ? ST_NONFINITE : ST_ESCAPE;
+        return 0;
+    }
+    int j = (int)jf;
+    if (j < 0) j += G.n[d];
+    else if (j >= G.n[d]) j -= G.n[d];
+    return j;
+}
+
+// Local cell of a member on this step's grid from the block's FP32 grid (-1
+// and BINERR when the member is not in this brick: only with a corrupted state).
+__device__ __forceinline__ int brick_local_cell_g(const BrickGrid &G, const BrickInfo &bi, const float p[3],
+                                                  uint32_t &st)
+{
+    int lc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lc[d] = brick_axis_cell(p[d], G.sh[d], G, d, st) - bi.org[d];
+        if ((unsigned)lc[d] >= (unsigned)bi.dim[d]) {
+            st |= ST_BINERR;
+            return -1;
+        }
+    }
+    return (lc[2] * bi.dim[1] + lc[1]) * bi.dim[0] + lc[0];
 }
 
 // Local cell of a member on this step's grid (-1 and BINERR when the member is
@@ -3940,6 +4008,37 @@ __device__ __forceinline__ int brick_stream(const BrickArgs<Real> &A, const Bric
         cls += c * mul;
         mul *= 3;
     }
+    return cls;
+}
+
+// Streaming of a solvent member with the block's FP32 grid (the same
+// operations as brick_stream): its writer class in the region of its brick on
+// the next step's grid, or -1 beyond the neighbouring bricks with *dst that
+// brick.
+__device__ __forceinline__ int brick_stream_g(const BrickArgs<float> &A, const BrickGrid &G, const BrickInfo &bi,
+                                              const float L[3], float p[3], float w[3], int32_t *dst, uint32_t &st)
+{
+    const float dtr = (float)A.dt;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float y = p[d] + w[d] * dtr;
+        if (A.F.on) {
+            y = y + (float)A.F.h[d];
+            w[d] = w[d] + (float)A.F.gdt[d];
+        }
+        p[d] = Prec<float>::wrap(y, L[d], st);
+    }
+    int jc[3], cls = 0, mul = 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        jc[d] = brick_axis_cell(p[d], G.sh1[d], G, d, st);
+        const int c = class_code(bi.org[d] >> G.lg[d], jc[d] >> G.lg[d], G.nb[d]);
+        if (c < 0) cls = -1;
+        else if (cls >= 0) cls += c * mul;
+        mul *= 3;
+    }
+    if (cls < 0)
+        *dst = G.bb0 + ((jc[2] >> G.lg[2]) * G.nb[1] + (jc[1] >> G.lg[1])) * G.nb[0] + (jc[0] >> G.lg[0]);
     return cls;
 }
 
@@ -4082,6 +4181,7 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
             }
         }
         const int nmem = L.hdr[0] + L.hdr[1] + L.hdr[2] + L.hdr[3];
+        const BrickGrid G = brick_grid_of(s, bn, r, L.sh, L.sh1);
         const double mS_solvent = s.m * FIX_SCALE;  // the solvent's fixed-point mass, once
         const long long q0_solvent = fix_round(mS_solvent);
         const float Lb[3] = {(float)((double)s.ncell[3 * r] * s.a), (float)((double)s.ncell[3 * r + 1] * s.a),
@@ -4104,7 +4204,7 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
-                lc[k] = brick_local_cell<float>(s, bn, bi, b, p[k], L.sh, st);
+                lc[k] = brick_local_cell_g(G, bi, p[k], st);
                 if (lc[k] < 0) continue;
                 long long q[5];
                 if (id[k] >= 0) {
@@ -4132,10 +4232,21 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 if (lc[k] < 0) continue;
                 if (L.cnt[lc[k]] >= 2) brick_rotate_f32(L.par + 12 * lc[k], w[k], st);
                 if (id[k] < 0) continue;  // a site: written back below
-                int32_t dst;
-                const int cls = brick_stream<float>(A, bi, Lb, p[k], w[k], L.sh1, &dst, st);
+                int32_t dst = 0;
+                const int cls = brick_stream_g(A, G, bi, Lb, p[k], w[k], &dst, st);
                 lc[k] = cls >= 0 ? cls : NCLS;  // NCLS: beyond the neighbouring bricks
-                rank[k] = cls >= 0 ? atomicAdd(&L.wcnt[cls], 1) : dst;
+                // the brick's own class (most members): one LDS atomic per wave
+                const unsigned long long own = __ballot(cls == 0);
+                if (cls == 0) {
+                    const int lane = threadIdx.x & 63;
+                    const int leader = __ffsll((long long)own) - 1;
+                    const unsigned long long below = lane ? (own & (~0ull >> (64 - lane))) : 0ull;
+                    int base = 0;
+                    if (lane == leader) base = atomicAdd(&L.wcnt[0], __popcll(own));
+                    rank[k] = __shfl(base, leader, 64) + __popcll(below);
+                } else {
+                    rank[k] = cls > 0 ? atomicAdd(&L.wcnt[cls], 1) : dst;
+                }
             }
             __syncthreads();
             if (t < NCLS && L.wdst[t] >= 0)  // the fill of every sub-region this brick writes (zero included)
