@@ -335,10 +335,12 @@ def roofline(r, prec_bytes, wtag):
     if r.get("layout") == "binned":
         kern, ms, nbytes = "k_brick_collide_f32", r["collide_ms"], brick_bytes(N, S)
         ach = nbytes / (ms * 1e-3) / 1e9
+        traffic = measured_traffic(kern, wtag)
         return {"bound": "hbm", "kernel": kern + " (binned layout: collide + stream + bin for the next step)",
                 "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                "traffic": measured_traffic(kern, wtag), "avg_launch_us": ms * 1e3,
-                "algorithmic_bytes_per_launch": nbytes}
+                "traffic": traffic, "avg_launch_us": ms * 1e3, "algorithmic_bytes_per_launch": nbytes,
+                # measured HBM bytes (committed counters) over the live launch time
+                "traffic_frac": None if traffic is None else traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
     kname = collide_kernel_name(r["tuning"]["tile_items_cells_cap_tiles"][0],
                                 r["tuning"]["tune_items_fill_drawcells_inline_overlap"][3], prec_bytes == 8)
     kern, ms, nbytes = kname, r["collide_ms"], collide_bytes(N, S, prec_bytes)
