@@ -9,7 +9,8 @@ oracle (1e-5 relative L2 and max-abs per step, test_gpu_bench_form.py), so the
 binned form meets the same bounds.  Covered here: pack/unpack round trips, eager steps and
 graph replays, bodies with centre WCA, site-site WCA, forced flow, pure
 solvent, batched replicas, a brick whose region overflows into the shared
-overflow list, and a brick with more members than a block holds in registers.
+overflow list, a brick with more members than a block holds in registers, and a
+brick with more sites than its site list holds.
 """
 import sys
 
@@ -135,6 +136,19 @@ def test_crowded_brick_overflow_and_two_pass_path():
     wl["v"] = np.concatenate([base["v"], ve], axis=1)
     gd, gb = dense_and_binned(wl, par, 6)
     assert gb.status() == 0
+
+
+def test_site_list_overflow():
+    """Six spheres of 100 sites packed into one brick of 8 x 8 x 4 cells: the
+    brick's site list (its 256 cells + 64 slots) overflows into the shared
+    site list, which the brick then scans.  No WCA, so the spheres may
+    overlap; the thermostat is on."""
+    rng = np.random.default_rng(41)
+    tpl = W.sphere_template(1.5, 100, 5.0)
+    centres = np.array([[2.0 + 1.3 * (b % 3), 2.5 + 2.5 * (b // 3), 2.0] for b in range(6)])
+    wl = W.make_system((16, 16, 16), 5, [tpl] * 6, centres, W.random_quaternions(rng, 6), rng)
+    par = W.srd_params(41, kT_cell=1.0)
+    dense_and_binned(wl, par, 8, check_every=2)
 
 
 def test_full_size_suspension_binned_equals_dense():
