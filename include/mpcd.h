@@ -217,9 +217,9 @@ typedef struct {
  *
  * Each system's cells are grouped into bricks of up to 8 x 8 x 4 cells
  * (smaller bricks for denser systems; narrower at the far faces of the box).
- * A solvent particle is one record of eight values of the precision
- * (position x, y, z; its identity as the int32 bits of the fourth value;
- * velocity x, y, z; one unused value: 32 bytes in FP32).  The record array
+ * A solvent particle is one record: in FP32 seven floats, 28 bytes (position
+ * x, y, z; its identity as the int32 bits of the fourth value; velocity x, y,
+ * z), in FP64 eight doubles (the same with one unused value).  The record array
  * holds one region per brick: on a step with index t, a particle is stored in
  * the region of the brick of its cell on step t's shifted grid.  A region is
  * split into 27 sub-regions, one per brick that can write into it (the brick

@@ -3708,24 +3708,31 @@ constexpr int BRICK_MAXC = 256;  // cells per brick at most (one lane per cell)
 constexpr int BRICK_OVL = 512;   // overflow entries per brick and kind a block takes
 constexpr int BRICK_ITEMS_F32 = 4;
 
-// A binned solvent slot is one record of eight values of the precision:
-// position, identity (the int32 bits in the fourth value), velocity, and one
-// unused value; 32 bytes in FP32, written and read as two 16-byte vectors so
-// that a run of slots fills whole cache lines.
+// A binned solvent slot is one record: in FP32 seven values, 28 bytes
+// (position, identity as the int32 bits of the fourth value, velocity), read
+// and written as a 16-byte and a 12-byte access (4-byte aligned), so that a
+// run of slots fills whole cache lines; in FP64 eight values, 64 bytes
+// (position, identity as the bits of the fourth, velocity, one unused).
+constexpr int REC_F32 = 7, REC_F64 = 8;
+
 __device__ __forceinline__ void rec_load(const float *rec, int64_t q, float p[3], float w[3], int32_t &id)
 {
-    const float4 *r = (const float4 *)rec + 2 * q;
-    const float4 a = r[0], c = r[1];
+    const float *r = rec + REC_F32 * q;
+    float4 a;
+    float c[3];
+    __builtin_memcpy(&a, r, 16);
+    __builtin_memcpy(c, r + 4, 12);
     p[0] = a.x; p[1] = a.y; p[2] = a.z;
     id = __float_as_int(a.w);
-    w[0] = c.x; w[1] = c.y; w[2] = c.z;
+    w[0] = c[0]; w[1] = c[1]; w[2] = c[2];
 }
 
 __device__ __forceinline__ void rec_store(float *rec, int64_t q, const float p[3], const float w[3], int32_t id)
 {
-    float4 *r = (float4 *)rec + 2 * q;
-    r[0] = make_float4(p[0], p[1], p[2], __int_as_float(id));
-    r[1] = make_float4(w[0], w[1], w[2], 0.0f);
+    float *r = rec + REC_F32 * q;
+    const float4 a = make_float4(p[0], p[1], p[2], __int_as_float(id));
+    __builtin_memcpy(r, &a, 16);
+    __builtin_memcpy(r + 4, w, 12);
 }
 
 __device__ __forceinline__ void rec_load(const double *rec, int64_t q, double p[3], double w[3], int32_t &id)
@@ -3749,7 +3756,7 @@ __device__ __forceinline__ void rec_store(double *rec, int64_t q, const double p
 template <typename Real> struct BrickArgs {
     SysDev s;
     BinnedDev bn;
-    const Real *rec;  // binned solvent records of this step: [cap][8]
+    const Real *rec;  // binned solvent records of this step: [cap] records
     Real *reco;       // and of the next step
     Real *xs, *vs;      // sites [3][S]
     const double *site_m;

@@ -167,9 +167,11 @@ class GPUSystem:
         L.check(self.lib.mpcd_binned_init(self.stream, C.byref(self.csys), *hp, C.byref(b)), "mpcd_binned_init")
         cap = int(b.capacity)
         xd, vd, td = self.x, self.v, self.tag
-        # x, x2: the solvent records of the current and the next step (8
-        # values each: position, identity bits, velocity, unused); no v, tag
-        self.x = torch.zeros((cap, 8), dtype=self.real, device=self.device)
+        # x, x2: the solvent records of the current and the next step (FP32: 7
+        # values each, position, identity bits, velocity; FP64: 8, with one
+        # unused); no v, tag
+        rec = 8 if self.prec == L.MPCD_F64 else 7
+        self.x = torch.zeros((cap, rec), dtype=self.real, device=self.device)
         self.x2 = torch.zeros_like(self.x)
         self.v = self.v2 = self.tag = self.tag2 = None
         self._pack(xd, vd, td)
