@@ -3703,36 +3703,50 @@ int check_ws(const mpcd_sys *s, const void *ws, size_t ws_bytes)
 // once), with no cell lists, scan, scatter, permutation or device atomics.
 // A brick with more members than the block holds in registers takes a
 // two-pass path (sums, then a second load to rotate and write).
-constexpr int BRICK_T = 512;     // threads of a brick block
-constexpr int BRICK_MAXC = 256;  // cells per brick at most (one lane per cell)
-constexpr int BRICK_OVL = 512;   // overflow entries per brick and kind a block takes
-constexpr int BRICK_ITEMS_F32 = 4;
+// A brick block holds BRICK_MEMBERS members in registers, in one of two
+// shapes.  Four waves of eight members per lane (about 150 VGPRs, three waves
+// per SIMD) with 43 KB of LDS leave three blocks resident per CU, against two
+// for eight waves of four members, so more of the solvent is in flight; the
+// eight-wave shape is faster when there are too few bricks to fill three
+// blocks per CU over several rounds.
+constexpr int BRICK_MEMBERS = 2048;  // members a block holds in registers (FP32)
+constexpr int BRICK_MAXC = 256;      // cells per brick at most (one lane per cell)
+constexpr int BRICK_OVL = 512;       // overflow entries per brick and kind a block takes
+constexpr int BRICK_T_WIDE = 256;    // threads of a block of the many-brick shape (eight members per lane)
+constexpr int BRICK_T_NARROW = 512;  // and of the few-brick shape (four per lane)
+constexpr int64_t BRICK_WIDE_MIN = 4096;  // bricks from which the four-wave shape is used
 
 // A binned solvent slot is one record: in FP32 seven values, 28 bytes
 // (position, identity as the int32 bits of the fourth value, velocity), read
 // and written as a 16-byte and a 12-byte access (4-byte aligned), so that a
 // run of slots fills whole cache lines; in FP64 eight values, 64 bytes
 // (position, identity as the bits of the fourth, velocity, one unused).
+// The FP32 record accesses are nontemporal: each record is read once and
+// written once per step, and the next step reads it only after the whole
+// array has streamed through the caches.
 constexpr int REC_F32 = 7, REC_F64 = 8;
+typedef float f4u_t __attribute__((ext_vector_type(4), aligned(4)));  // a record's first 16 bytes
+typedef float f3u_t __attribute__((ext_vector_type(3), aligned(4)));  // and its last 12
 
 __device__ __forceinline__ void rec_load(const float *rec, int64_t q, float p[3], float w[3], int32_t &id)
 {
     const float *r = rec + REC_F32 * q;
-    float4 a;
-    float c[3];
-    __builtin_memcpy(&a, r, 16);
-    __builtin_memcpy(c, r + 4, 12);
+    const f4u_t a = __builtin_nontemporal_load((const f4u_t *)r);
+    const f3u_t c = __builtin_nontemporal_load((const f3u_t *)(r + 4));
     p[0] = a.x; p[1] = a.y; p[2] = a.z;
     id = __float_as_int(a.w);
-    w[0] = c[0]; w[1] = c[1]; w[2] = c[2];
+    w[0] = c.x; w[1] = c.y; w[2] = c.z;
 }
 
 __device__ __forceinline__ void rec_store(float *rec, int64_t q, const float p[3], const float w[3], int32_t id)
 {
     float *r = rec + REC_F32 * q;
-    const float4 a = make_float4(p[0], p[1], p[2], __int_as_float(id));
-    __builtin_memcpy(r, &a, 16);
-    __builtin_memcpy(r + 4, w, 12);
+    f4u_t a;
+    a.x = p[0]; a.y = p[1]; a.z = p[2]; a.w = __int_as_float(id);
+    f3u_t c;
+    c.x = w[0]; c.y = w[1]; c.z = w[2];
+    __builtin_nontemporal_store(a, (f4u_t *)r);
+    __builtin_nontemporal_store(c, (f3u_t *)(r + 4));
 }
 
 __device__ __forceinline__ void rec_load(const double *rec, int64_t q, double p[3], double w[3], int32_t &id)
@@ -3887,16 +3901,15 @@ __device__ __forceinline__ BrickGrid brick_grid_of(const SysDev &s, const Binned
 
 __device__ __forceinline__ int brick_axis_cell(float x, float sf, const BrickGrid &G, int d, uint32_t &st)
 {
+    // selects rather than branches: the per-member code stays one basic block
     const float g = x - sf;
     const float jf = floorf(G.mul != 0.0f ? g * G.mul : g / G.a);
-    if (!(jf >= -1.0f && jf <= G.nf[d])) {
-        st |= (g != g) ? ST_NONFINITE : ST_ESCAPE;
-        return 0;
-    }
+    const bool ok = jf >= -1.0f && jf <= G.nf[d];
     int j = (int)jf;
-    if (j < 0) j += G.n[d];
-    else if (j >= G.n[d]) j -= G.n[d];
-    return j;
+    j = j < 0 ? j + G.n[d] : j;
+    j = j >= G.n[d] ? j - G.n[d] : j;
+    st |= ok ? 0u : ((g != g) ? ST_NONFINITE : ST_ESCAPE);
+    return ok ? j : 0;
 }
 
 // Local cell of a member on this step's grid from the block's FP32 grid (-1
@@ -3905,15 +3918,14 @@ __device__ __forceinline__ int brick_local_cell_g(const BrickGrid &G, const Bric
                                                   uint32_t &st)
 {
     int lc[3];
+    bool in = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         lc[d] = brick_axis_cell(p[d], G.sh[d], G, d, st) - bi.org[d];
-        if ((unsigned)lc[d] >= (unsigned)bi.dim[d]) {
-            st |= ST_BINERR;
-            return -1;
-        }
+        in = in && (unsigned)lc[d] < (unsigned)bi.dim[d];
     }
-    return (lc[2] * bi.dim[1] + lc[1]) * bi.dim[0] + lc[0];
+    st |= in ? 0u : ST_BINERR;
+    return in ? (lc[2] * bi.dim[1] + lc[1]) * bi.dim[0] + lc[0] : -1;
 }
 
 // Local cell of a member on this step's grid (-1 and BINERR when the member is
@@ -3946,19 +3958,39 @@ __device__ __forceinline__ uint64_t brick_cell_canonical(const SysDev &s, const 
     return (uint64_t)(((int64_t)(bi.org[2] + cz) * ny + (bi.org[1] + cy)) * nx + (bi.org[0] + cx));
 }
 
+// A cell's count word: members in the low 16 bits, members whose mass term
+// is in the mass sum (sites, and solvent whose terms overflowed and add
+// nothing) in the high 16 bits.  The other solvent members' mass terms all
+// equal the solvent's, so they are added per cell from the count rather
+// than one LDS atomic each.
+__device__ __forceinline__ int brick_cnt_members(int cw) { return cw & 0xffff; }
+
+__device__ __forceinline__ void brick_sum_member(unsigned long long *acc, int *cnt, bool solvent, const long long q[5])
+{
+    const bool counted = solvent && q[0] != 0;  // q[0] is 0 when the terms overflowed
+#pragma unroll
+    for (int z = 0; z < 5; ++z)
+        if (z > 0 || !solvent) atomicAdd(acc + z, (unsigned long long)q[z]);
+    atomicAdd(cnt, counted ? 1 : 1 + (1 << 16));
+}
+
 // Per-cell FP32 parameters from the exact fixed-point sums (u and lambda R
 // rounded to float), the draws finished from the cell's first call.
-__device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const BrickInfo &bi, int c, int n,
-                                                      const unsigned long long *acc, const CellDrawPre &P, double ca,
-                                                      double sa, double kT_cell, uint64_t seed, uint64_t step,
-                                                      float *par, uint32_t &st)
+__device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const BrickInfo &bi, int c, int cw,
+                                                      long long q0_solvent, const unsigned long long *acc,
+                                                      const CellDrawPre &P, double ca, double sa, double kT_cell,
+                                                      uint64_t seed, uint64_t step, float *par, uint32_t &st)
 {
+    const int n = brick_cnt_members(cw);
     CellDraw D;
     st |= cell_draw_post(seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)bi.sys, P, kT_cell > 0.0,
                          0.5 * (double)(3 * (n - 1)), D);
     long long q[5];
 #pragma unroll
     for (int z = 0; z < 5; ++z) q[z] = (long long)acc[5 * c + z];
+    // the solvent's mass terms, all equal, from their count (exact: the same
+    // int64 sum as adding each one)
+    q[0] += (long long)(n - (cw >> 16)) * q0_solvent;
     const Rot R = rotation(D.n, ca, sa);
     const double Md = (double)q[0];
     const double u0 = (double)q[1] / Md, u1 = (double)q[2] / Md, u2 = (double)q[3] / Md;
@@ -3979,11 +4011,13 @@ __device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const Bri
 __device__ __forceinline__ void brick_rotate_f32(const float *par, float w[3], uint32_t &st)
 {
     const float dl[3] = {w[0] - par[0], w[1] - par[1], w[2] - par[2]};
+    bool fin = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         w[d] = par[d] + ((par[3 + 3 * d] * dl[0] + par[4 + 3 * d] * dl[1]) + par[5 + 3 * d] * dl[2]);
-        if (!(w[d] - w[d] == 0.0f)) st |= ST_NONFINITE;
+        fin = fin && (w[d] - w[d] == 0.0f);
     }
+    st |= fin ? 0u : ST_NONFINITE;
 }
 
 // Streaming of a solvent member (position and velocity in place) and the
@@ -4033,15 +4067,20 @@ __device__ __forceinline__ int brick_stream_g(const BrickArgs<float> &A, const B
             y = y + (float)A.F.h[d];
             w[d] = w[d] + (float)A.F.gdt[d];
         }
-        p[d] = Prec<float>::wrap(y, L[d], st);
+        // the periodic wrap of wrap_f, as selects
+        y = y >= L[d] ? y - L[d] : (y < 0.0f ? y + L[d] : y);
+        st |= (y >= 0.0f && y <= L[d]) ? 0u : ((y != y) ? ST_NONFINITE : ST_ESCAPE);
+        p[d] = y;
     }
     int jc[3], cls = 0, mul = 1;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         jc[d] = brick_axis_cell(p[d], G.sh1[d], G, d, st);
-        const int c = class_code(bi.org[d] >> G.lg[d], jc[d] >> G.lg[d], G.nb[d]);
-        if (c < 0) cls = -1;
-        else if (cls >= 0) cls += c * mul;
+        // class_code as selects
+        int e = (bi.org[d] >> G.lg[d]) - (jc[d] >> G.lg[d]);
+        e = e < 0 ? e + G.nb[d] : e;
+        const int c = e == 0 ? 0 : e == 1 ? 1 : e == G.nb[d] - 1 ? 2 : -1;
+        cls = (c < 0 || cls < 0) ? -1 : cls + c * mul;
         mul *= 3;
     }
     if (cls < 0)
@@ -4089,9 +4128,11 @@ __device__ __forceinline__ void brick_emit(const BrickArgs<Real> &A, BrickLds32 
     brick_put<Real>(A, par_out, dst, L.woff[cls], L.wcap[cls], rank, p, w, id, st);
 }
 
-template <int ITEMS>
-__global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) void k_brick_collide_f32(BrickArgs<float> A)
+template <int BRICK_T>
+__global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(BRICK_T == BRICK_T_WIDE ? 3 : 4))) void
+k_brick_collide_f32(BrickArgs<float> A)
 {
+    constexpr int ITEMS = BRICK_MEMBERS / BRICK_T;
     __shared__ BrickLds32 L;
     const int t = threadIdx.x;
     const SysDev &s = A.s;
@@ -4219,16 +4260,13 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 } else {
                     fixed_terms(A.site_m[-(int64_t)id[k] - 1], w[k][0], w[k][1], w[k][2], q, st);
                 }
-                unsigned long long *acc = L.acc + 5 * lc[k];
-#pragma unroll
-                for (int z = 0; z < 5; ++z) atomicAdd(acc + z, (unsigned long long)q[z]);
-                atomicAdd(&L.cnt[lc[k]], 1);
+                brick_sum_member(L.acc + 5 * lc[k], &L.cnt[lc[k]], id[k] >= 0, q);
             }
             __syncthreads();
             for (int c = t; c < ncb; c += BRICK_T)
-                if (L.cnt[c] >= 2)
-                    brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, L.pre[c], A.cos_a, A.sin_a, A.kT_cell, A.seed,
-                                          step, L.par + 12 * c, st);
+                if (brick_cnt_members(L.cnt[c]) >= 2)
+                    brick_cell_params_f32(s, bi, c, L.cnt[c], q0_solvent, L.acc, L.pre[c], A.cos_a, A.sin_a,
+                                          A.kT_cell, A.seed, step, L.par + 12 * c, st);
             __syncthreads();
             // rotate and stream every member and take its rank in its class
             // from the LDS counters; the stores wait until the counts are final
@@ -4237,7 +4275,7 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
-                if (L.cnt[lc[k]] >= 2) brick_rotate_f32(L.par + 12 * lc[k], w[k], st);
+                if (brick_cnt_members(L.cnt[lc[k]]) >= 2) brick_rotate_f32(L.par + 12 * lc[k], w[k], st);
                 if (id[k] < 0) continue;  // a site: written back below
                 int32_t dst = 0;
                 const int cls = brick_stream_g(A, G, bi, Lb, p[k], w[k], &dst, st);
@@ -4288,15 +4326,13 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 } else {
                     fixed_terms(A.site_m[-(int64_t)id - 1], w[0], w[1], w[2], q, st);
                 }
-#pragma unroll
-                for (int z = 0; z < 5; ++z) atomicAdd(L.acc + 5 * c + z, (unsigned long long)q[z]);
-                atomicAdd(&L.cnt[c], 1);
+                brick_sum_member(L.acc + 5 * c, &L.cnt[c], id >= 0, q);
             }
             __syncthreads();
             for (int c = t; c < ncb; c += BRICK_T)
-                if (L.cnt[c] >= 2)
-                    brick_cell_params_f32(s, bi, c, L.cnt[c], L.acc, L.pre[c], A.cos_a, A.sin_a, A.kT_cell, A.seed,
-                                          step, L.par + 12 * c, st);
+                if (brick_cnt_members(L.cnt[c]) >= 2)
+                    brick_cell_params_f32(s, bi, c, L.cnt[c], q0_solvent, L.acc, L.pre[c], A.cos_a, A.sin_a,
+                                          A.kT_cell, A.seed, step, L.par + 12 * c, st);
             __syncthreads();
             // second load: each member is read again before its own write (a
             // site appears once in a brick's list)
@@ -4306,7 +4342,7 @@ __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) vo
                 if (!brick_member<float>(A, bi, par_in, i, L, p, w, id, st)) continue;
                 const int c = brick_local_cell<float>(s, bn, bi, b, p, L.sh, st);
                 if (c < 0) continue;
-                if (L.cnt[c] >= 2) brick_rotate_f32(L.par + 12 * c, w, st);
+                if (brick_cnt_members(L.cnt[c]) >= 2) brick_rotate_f32(L.par + 12 * c, w, st);
                 if (id < 0) {
                     const int64_t j = -(int64_t)id - 1, S = s.S;
                     A.vs[j] = w[0]; A.vs[S + j] = w[1]; A.vs[2 * S + j] = w[2];
@@ -4523,7 +4559,7 @@ int64_t region_cap(double mu) { return (int64_t)ceil(mu + 6.0 * sqrt(mu)) + 16; 
 int64_t site_cap(int64_t ncb, int64_t S_r) { return ncb + 64 < S_r ? ncb + 64 : S_r; }
 
 // Members a brick block holds in registers (FP32) or LDS (FP64).
-int brick_block_members(int prec) { return prec == MPCD_F64 ? 1024 : BRICK_T * BRICK_ITEMS_F32; }
+int brick_block_members(int prec) { return prec == MPCD_F64 ? 1024 : BRICK_MEMBERS; }
 
 int32_t sovf_cap_of(const mpcd_sys *sys)
 {
@@ -5244,8 +5280,12 @@ static void launch_brick_collide(const Ctx &c, hipStream_t st, const mpcd_step_a
     A.grid_n = grid.count ? (int64_t)c.L.grid_mask + 1 : 0;
     A.F = make_forcing(p.g, p.dt);
     A.status = c.status;
-    hipLaunchKernelGGL(k_brick_collide_f32<BRICK_ITEMS_F32>, dim3(xcd_grid(a->binned->nbricks)), dim3(BRICK_T), 0, st,
-                       A);
+    if (a->binned->nbricks >= BRICK_WIDE_MIN)
+        hipLaunchKernelGGL(k_brick_collide_f32<BRICK_T_WIDE>, dim3(xcd_grid(a->binned->nbricks)), dim3(BRICK_T_WIDE),
+                           0, st, A);
+    else
+        hipLaunchKernelGGL(k_brick_collide_f32<BRICK_T_NARROW>, dim3(xcd_grid(a->binned->nbricks)),
+                           dim3(BRICK_T_NARROW), 0, st, A);
 }
 
 static int bin_checks(const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
@@ -6012,7 +6052,7 @@ int mpcd_binned_layout(const mpcd_sys *sys, const int32_t *ncell, const int64_t 
     out->nbricks = P.nbricks;
     out->capacity = P.cap;
     out->site_slots = P.sslots;
-    out->items = sys->prec == MPCD_F64 ? 0 : BRICK_ITEMS_F32;
+    out->items = sys->prec == MPCD_F64 ? 0 : (int)(BRICK_MEMBERS / (P.nbricks >= BRICK_WIDE_MIN ? BRICK_T_WIDE : BRICK_T_NARROW));
     out->ws_bytes = binned_layout(sys, P.nbricks, P.sslots, P.sovf_cap).total;
     return MPCD_OK;
 }

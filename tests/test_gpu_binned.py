@@ -10,7 +10,7 @@ binned form meets the same bounds.  Covered here: pack/unpack round trips, eager
 graph replays, bodies with centre WCA, site-site WCA, forced flow, pure
 solvent, batched replicas, a brick whose region overflows into the shared
 overflow list, a brick with more members than a block holds in registers, and a
-brick with more sites than its site list holds.
+brick with more sites than its site list holds, in both block shapes.
 """
 import sys
 
@@ -149,6 +149,28 @@ def test_site_list_overflow():
     wl = W.make_system((16, 16, 16), 5, [tpl] * 6, centres, W.random_quaternions(rng, 6), rng)
     par = W.srd_params(41, kT_cell=1.0)
     dense_and_binned(wl, par, 8, check_every=2)
+
+
+def test_four_wave_blocks_crowded_brick_with_site_overflow():
+    """A box of 4096 bricks, which takes the four-wave brick block (eight
+    members per lane; the smaller systems above take the eight-wave block).
+    In its first brick six overlapping spheres of 100 sites overflow the
+    brick's site list, and 600 extra solvent crowded among them overflow its
+    region into the shared overflow list, so the brick has more members than
+    a block holds in registers (the two-pass path)."""
+    rng = np.random.default_rng(43)
+    tpl = W.sphere_template(1.5, 100, 5.0)
+    centres = np.array([[2.0 + 1.3 * (b % 3), 2.5 + 2.5 * (b // 3), 2.0] for b in range(6)])
+    wl = W.make_system((128, 128, 64), 5, [tpl] * 6, centres, W.random_quaternions(rng, 6), rng)
+    extra = 600
+    xe = np.array([[3.5], [4.0], [2.0]]) + 0.4 * (rng.random((3, extra)) - 0.5)
+    ve = rng.normal(0.0, 1.0, (3, extra))
+    wl["x"] = np.concatenate([wl["x"], xe], axis=1)
+    wl["v"] = np.concatenate([wl["v"], ve], axis=1)
+    par = W.srd_params(43, kT_cell=1.0)
+    say("binned four-wave blocks, crowded brick")
+    gd, gb = dense_and_binned(wl, par, 4, check_every=2)
+    assert gb.binned.nbricks >= 4096 and gb.binned.items == 8
 
 
 def test_full_size_suspension_binned_equals_dense():
