@@ -1444,11 +1444,23 @@ __device__ void collide_cell_f64_global(const CollideArgs &A, int64_t gc, double
 // into int64, so that the per-cell sums are exact and independent of order.
 // The fine unit matters for the thermostat: a cell's relative kinetic energy
 // is the difference of two sums, and in a cell of nearly equal velocities it
-// is small.  A member whose term reaches 2^62 units adds nothing and sets
-// FIXOVF.
-constexpr double FIX_SCALE = 0x1p32, FIX_UNIT = 0x1p-32, FIX_LIM = 0x1p62;
+// is small.  A member whose term reaches 2^51 units (|m v| or m |v|^2 of
+// 2^19) adds nothing and sets FIXOVF.
+constexpr double FIX_SCALE = 0x1p32, FIX_UNIT = 0x1p-32, FIX_LIM = 0x1p51;
 
-__device__ __forceinline__ long long fix_round(double a) { return __double2ll_rn(a); }
+// Nearest integer (ties to even) of |a| < 2^51: adding 1.5 2^52 rounds a to
+// an integer within the sum's mantissa (the sum's unit in the last place is
+// 1, and 1.5 2^52 is even, so ties go the same way), and the difference of
+// the two bit patterns is that integer.  One add and one subtraction, the
+// same value as a general double-to-int64 rounding.
+__device__ __forceinline__ long long fix_round(double a)
+{
+    const double m = 0x1.8p52;
+    return __double_as_longlong(a + m) - __double_as_longlong(m);
+}
+
+// The same for any a in the int64 range (a species' mass term, once).
+__device__ __forceinline__ long long fix_round_any(double a) { return __double2ll_rn(a); }
 
 // The terms from mS = m 2^32 and q0 = its rounding, which a caller can form
 // once per species: (m 2^32) v equals (m v) 2^32 exactly (scaling by a power
@@ -1475,7 +1487,7 @@ __device__ __forceinline__ void fixed_terms(double mk, float fv0, float fv1, flo
                                             uint32_t &st)
 {
     const double mS = mk * FIX_SCALE;
-    fixed_terms_scaled(mS, fix_round(mS), fv0, fv1, fv2, q, st);
+    fixed_terms_scaled(mS, fix_round_any(mS), fv0, fv1, fv2, q, st);
 }
 
 // Relative kinetic energy of a cell, 1/2 (sum m |v|^2 - |sum m v|^2 / sum m),
@@ -3899,11 +3911,14 @@ __device__ __forceinline__ BrickGrid brick_grid_of(const SysDev &s, const Binned
     return G;
 }
 
+// UNIT: the cell edge is 1, where g * mul is g itself (the same value, without
+// the multiplier or the division path in the block's registers).
+template <bool UNIT>
 __device__ __forceinline__ int brick_axis_cell(float x, float sf, const BrickGrid &G, int d, uint32_t &st)
 {
     // selects rather than branches: the per-member code stays one basic block
     const float g = x - sf;
-    const float jf = floorf(G.mul != 0.0f ? g * G.mul : g / G.a);
+    const float jf = floorf(UNIT ? g : (G.mul != 0.0f ? g * G.mul : g / G.a));
     const bool ok = jf >= -1.0f && jf <= G.nf[d];
     int j = (int)jf;
     j = j < 0 ? j + G.n[d] : j;
@@ -3914,6 +3929,7 @@ __device__ __forceinline__ int brick_axis_cell(float x, float sf, const BrickGri
 
 // Local cell of a member on this step's grid from the block's FP32 grid (-1
 // and BINERR when the member is not in this brick: only with a corrupted state).
+template <bool UNIT>
 __device__ __forceinline__ int brick_local_cell_g(const BrickGrid &G, const BrickInfo &bi, const float p[3],
                                                   uint32_t &st)
 {
@@ -3921,7 +3937,7 @@ __device__ __forceinline__ int brick_local_cell_g(const BrickGrid &G, const Bric
     bool in = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        lc[d] = brick_axis_cell(p[d], G.sh[d], G, d, st) - bi.org[d];
+        lc[d] = brick_axis_cell<UNIT>(p[d], G.sh[d], G, d, st) - bi.org[d];
         in = in && (unsigned)lc[d] < (unsigned)bi.dim[d];
     }
     st |= in ? 0u : ST_BINERR;
@@ -4056,6 +4072,7 @@ __device__ __forceinline__ int brick_stream(const BrickArgs<Real> &A, const Bric
 // operations as brick_stream): its writer class in the region of its brick on
 // the next step's grid, or -1 beyond the neighbouring bricks with *dst that
 // brick.
+template <bool UNIT>
 __device__ __forceinline__ int brick_stream_g(const BrickArgs<float> &A, const BrickGrid &G, const BrickInfo &bi,
                                               const float L[3], float p[3], float w[3], int32_t *dst, uint32_t &st)
 {
@@ -4075,7 +4092,7 @@ __device__ __forceinline__ int brick_stream_g(const BrickArgs<float> &A, const B
     int jc[3], cls = 0, mul = 1;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        jc[d] = brick_axis_cell(p[d], G.sh1[d], G, d, st);
+        jc[d] = brick_axis_cell<UNIT>(p[d], G.sh1[d], G, d, st);
         // class_code as selects
         int e = (bi.org[d] >> G.lg[d]) - (jc[d] >> G.lg[d]);
         e = e < 0 ? e + G.nb[d] : e;
@@ -4128,7 +4145,7 @@ __device__ __forceinline__ void brick_emit(const BrickArgs<Real> &A, BrickLds32 
     brick_put<Real>(A, par_out, dst, L.woff[cls], L.wcap[cls], rank, p, w, id, st);
 }
 
-template <int BRICK_T>
+template <int BRICK_T, bool UNIT>
 __global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(BRICK_T == BRICK_T_WIDE ? 3 : 4))) void
 k_brick_collide_f32(BrickArgs<float> A)
 {
@@ -4231,7 +4248,7 @@ k_brick_collide_f32(BrickArgs<float> A)
         const int nmem = L.hdr[0] + L.hdr[1] + L.hdr[2] + L.hdr[3];
         const BrickGrid G = brick_grid_of(s, bn, r, L.sh, L.sh1);
         const double mS_solvent = s.m * FIX_SCALE;  // the solvent's fixed-point mass, once
-        const long long q0_solvent = fix_round(mS_solvent);
+        const long long q0_solvent = fix_round_any(mS_solvent);
         const float Lb[3] = {(float)((double)s.ncell[3 * r] * s.a), (float)((double)s.ncell[3 * r + 1] * s.a),
                              (float)((double)s.ncell[3 * r + 2] * s.a)};
         if (nmem <= ITEMS * BRICK_T) {
@@ -4252,7 +4269,7 @@ k_brick_collide_f32(BrickArgs<float> A)
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
-                lc[k] = brick_local_cell_g(G, bi, p[k], st);
+                lc[k] = brick_local_cell_g<UNIT>(G, bi, p[k], st);
                 if (lc[k] < 0) continue;
                 long long q[5];
                 if (id[k] >= 0) {
@@ -4278,7 +4295,7 @@ k_brick_collide_f32(BrickArgs<float> A)
                 if (brick_cnt_members(L.cnt[lc[k]]) >= 2) brick_rotate_f32(L.par + 12 * lc[k], w[k], st);
                 if (id[k] < 0) continue;  // a site: written back below
                 int32_t dst = 0;
-                const int cls = brick_stream_g(A, G, bi, Lb, p[k], w[k], &dst, st);
+                const int cls = brick_stream_g<UNIT>(A, G, bi, Lb, p[k], w[k], &dst, st);
                 lc[k] = cls >= 0 ? cls : NCLS;  // NCLS: beyond the neighbouring bricks
                 // the brick's own class (most members): one LDS atomic per wave
                 const unsigned long long own = __ballot(cls == 0);
@@ -5280,12 +5297,16 @@ static void launch_brick_collide(const Ctx &c, hipStream_t st, const mpcd_step_a
     A.grid_n = grid.count ? (int64_t)c.L.grid_mask + 1 : 0;
     A.F = make_forcing(p.g, p.dt);
     A.status = c.status;
-    if (a->binned->nbricks >= BRICK_WIDE_MIN)
-        hipLaunchKernelGGL(k_brick_collide_f32<BRICK_T_WIDE>, dim3(xcd_grid(a->binned->nbricks)), dim3(BRICK_T_WIDE),
-                           0, st, A);
+    const dim3 nblk(xcd_grid(a->binned->nbricks));
+    const bool wide = a->binned->nbricks >= BRICK_WIDE_MIN, unit = a->sys->a == 1.0;
+    if (wide && unit)
+        hipLaunchKernelGGL((k_brick_collide_f32<BRICK_T_WIDE, true>), nblk, dim3(BRICK_T_WIDE), 0, st, A);
+    else if (wide)
+        hipLaunchKernelGGL((k_brick_collide_f32<BRICK_T_WIDE, false>), nblk, dim3(BRICK_T_WIDE), 0, st, A);
+    else if (unit)
+        hipLaunchKernelGGL((k_brick_collide_f32<BRICK_T_NARROW, true>), nblk, dim3(BRICK_T_NARROW), 0, st, A);
     else
-        hipLaunchKernelGGL(k_brick_collide_f32<BRICK_T_NARROW>, dim3(xcd_grid(a->binned->nbricks)),
-                           dim3(BRICK_T_NARROW), 0, st, A);
+        hipLaunchKernelGGL((k_brick_collide_f32<BRICK_T_NARROW, false>), nblk, dim3(BRICK_T_NARROW), 0, st, A);
 }
 
 static int bin_checks(const mpcd_sys *sys, const void *x, const void *xs, const mpcd_bodies *bodies,
