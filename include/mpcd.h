@@ -252,7 +252,9 @@ typedef struct mpcd_binned_s {
     int64_t nbricks;     /* host: bricks over all systems                     */
     int64_t capacity;    /* host: records of one solvent record array         */
     int64_t site_slots;  /* host: site list entries over all bricks           */
-    int32_t items;       /* host: members per thread of a brick block         */
+    int32_t items;       /* host: members per thread of a brick block: 7 in   */
+                         /* four-wave blocks (layouts of 4096 bricks or more), */
+                         /* else 4 in eight-wave blocks                        */
 } mpcd_binned;
 
 /* Plan of the binned layout (host only; no device work).  ncell: host

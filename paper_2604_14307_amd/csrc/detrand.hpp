@@ -301,8 +301,10 @@ __device__ inline void cell_draw_pre(uint64_t seed, uint64_t step, uint64_t cell
     P.u2 = unit32(half32(w, 5));
 }
 
-__device__ inline uint32_t cell_draw_post(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
-                                          const CellDrawPre &P, bool want_gamma, double k, CellDraw &D)
+// cell_draw_post's first part alone: the axis and call 0's two
+// Marsaglia-Tsang tests; false when both reject (cell_draw_post then
+// continues from the same state).
+__device__ inline bool cell_draw_first(const CellDrawPre &P, bool want_gamma, double k, CellDraw &D)
 {
     cell_draw_begin(D, want_gamma, k);
     D.n[0] = P.n[0];
@@ -310,6 +312,13 @@ __device__ inline uint32_t cell_draw_post(uint64_t seed, uint64_t step, uint64_t
     D.n[2] = P.n[2];
     D.have_axis = true;
     if (!D.have_gamma) D.have_gamma = mt_try(P.z1, P.u1, D.d, D.c, &D.g) || mt_try(P.z2, P.u2, D.d, D.c, &D.g);
+    return D.have_gamma;
+}
+
+__device__ inline uint32_t cell_draw_post(uint64_t seed, uint64_t step, uint64_t cell, uint64_t replica,
+                                          const CellDrawPre &P, bool want_gamma, double k, CellDraw &D)
+{
+    if (cell_draw_first(P, want_gamma, k, D)) return 0u;
     for (int call = 1; !D.have_gamma && call < RNG_MAX_CALLS; ++call)
         cell_draw_call(D, rng_draw(seed, RNG_CELL, step, cell, replica, (uint64_t)call));
     return D.have_gamma ? 0u : cell_draw_end(D);

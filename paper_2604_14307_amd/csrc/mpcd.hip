@@ -3715,13 +3715,17 @@ int check_ws(const mpcd_sys *s, const void *ws, size_t ws_bytes)
 // once), with no cell lists, scan, scatter, permutation or device atomics.
 // A brick with more members than the block holds in registers takes a
 // two-pass path (sums, then a second load to rotate and write).
-// A brick block holds BRICK_MEMBERS members in registers, in one of two
-// shapes.  Four waves of eight members per lane (about 150 VGPRs, three waves
-// per SIMD) with 43 KB of LDS leave three blocks resident per CU, against two
-// for eight waves of four members, so more of the solvent is in flight; the
-// eight-wave shape is faster when there are too few bricks to fill three
-// blocks per CU over several rounds.
-constexpr int BRICK_MEMBERS = 2048;  // members a block holds in registers (FP32)
+// A brick block holds its members in registers, in one of two shapes.  Four
+// waves of seven members per lane (1792; under 128 VGPRs, four waves per
+// SIMD) with 33 KB of LDS leave four blocks resident per CU, against two for
+// eight waves of four members per lane (2048), so more of the solvent is in
+// flight; the eight-wave shape is faster when there are too few bricks to
+// fill the CUs over several rounds.  Bricks are planned for 2048 members
+// either way (their expected members and sites, with margins); the rare
+// brick of a four-wave layout with more than 1792 takes the two-pass path.
+constexpr int BRICK_PLAN_MEMBERS = 2048;    // members a planned brick may expect, margins included
+constexpr int BRICK_MEMBERS_WIDE = 1792;    // members a four-wave block holds in registers
+constexpr int BRICK_MEMBERS_NARROW = 2048;  // and an eight-wave block
 constexpr int BRICK_MAXC = 256;      // cells per brick at most (one lane per cell)
 constexpr int BRICK_OVL = 512;       // overflow entries per brick and kind a block takes
 constexpr int BRICK_T_WIDE = 256;    // threads of a block of the many-brick shape (eight members per lane)
@@ -3800,8 +3804,14 @@ template <typename Real> struct BrickArgs {
 struct BrickLds32 {
     unsigned long long acc[5 * BRICK_MAXC];
     int cnt[BRICK_MAXC];
-    float par[12 * BRICK_MAXC];
-    CellDrawPre pre[BRICK_MAXC];
+    // per cell: the values of its first random call until its FP32 collision
+    // parameters (u, lambda R) replace them; one lane forms both
+    union {
+        CellDrawPre pre;
+        float par[12];
+        double pad[9];  // a stride of 18 banks: the cells' parameters spread over the LDS banks
+    } cell[BRICK_MAXC];
+    unsigned char more[BRICK_MAXC];  // the cell's Gamma variate needs further calls
     int cpre[NCLS + 1];             // exclusive prefix of the input sub-region fills
     int32_t csub[NCLS + 1];         // this brick's sub-region offsets
     int wcnt[NCLS];                 // members written per class of this brick
@@ -3992,15 +4002,26 @@ __device__ __forceinline__ void brick_sum_member(unsigned long long *acc, int *c
 
 // Per-cell FP32 parameters from the exact fixed-point sums (u and lambda R
 // rounded to float), the draws finished from the cell's first call.
-__device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const BrickInfo &bi, int c, int cw,
+//
+// FIRST: only call 0's two Gamma tests; false (and par untouched) when both
+// reject, and the cell is then finished by the full form, which repeats
+// those tests and continues the stream exactly as cell_draw_post does.  The
+// brick block holding its members in registers takes this form, so that
+// the further generator calls, which are rare, do not add to its registers.
+template <bool FIRST>
+__device__ __forceinline__ bool brick_cell_params_f32(const SysDev &s, const BrickInfo &bi, int c, int cw,
                                                       long long q0_solvent, const unsigned long long *acc,
                                                       const CellDrawPre &P, double ca, double sa, double kT_cell,
                                                       uint64_t seed, uint64_t step, float *par, uint32_t &st)
 {
     const int n = brick_cnt_members(cw);
     CellDraw D;
-    st |= cell_draw_post(seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)bi.sys, P, kT_cell > 0.0,
-                         0.5 * (double)(3 * (n - 1)), D);
+    if (FIRST) {
+        if (!cell_draw_first(P, kT_cell > 0.0, 0.5 * (double)(3 * (n - 1)), D)) return false;
+    } else {
+        st |= cell_draw_post(seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)bi.sys, P,
+                             kT_cell > 0.0, 0.5 * (double)(3 * (n - 1)), D);
+    }
     long long q[5];
 #pragma unroll
     for (int z = 0; z < 5; ++z) q[z] = (long long)acc[5 * c + z];
@@ -4020,6 +4041,7 @@ __device__ __forceinline__ void brick_cell_params_f32(const SysDev &s, const Bri
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) par[3 + 3 * i + j] = (float)(lam * R.R[i][j]);
+    return true;
 }
 
 // Rotation of one FP32 member about its cell's mean velocity (cells of fewer
@@ -4146,10 +4168,10 @@ __device__ __forceinline__ void brick_emit(const BrickArgs<Real> &A, BrickLds32 
 }
 
 template <int BRICK_T, bool UNIT>
-__global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(BRICK_T == BRICK_T_WIDE ? 3 : 4))) void
+__global__ __launch_bounds__(BRICK_T) __attribute__((amdgpu_waves_per_eu(4))) void
 k_brick_collide_f32(BrickArgs<float> A)
 {
-    constexpr int ITEMS = BRICK_MEMBERS / BRICK_T;
+    constexpr int ITEMS = (BRICK_T == BRICK_T_WIDE ? BRICK_MEMBERS_WIDE : BRICK_MEMBERS_NARROW) / BRICK_T;
     __shared__ BrickLds32 L;
     const int t = threadIdx.x;
     const SysDev &s = A.s;
@@ -4251,6 +4273,7 @@ k_brick_collide_f32(BrickArgs<float> A)
         const long long q0_solvent = fix_round_any(mS_solvent);
         const float Lb[3] = {(float)((double)s.ncell[3 * r] * s.a), (float)((double)s.ncell[3 * r + 1] * s.a),
                              (float)((double)s.ncell[3 * r + 2] * s.a)};
+        bool more = false;  // a cell of the register path needs further Gamma calls
         if (nmem <= ITEMS * BRICK_T) {
             float p[ITEMS][3], w[ITEMS][3];
             int32_t id[ITEMS];
@@ -4265,7 +4288,7 @@ k_brick_collide_f32(BrickArgs<float> A)
             // the cells' first random calls and the regions this brick writes,
             // while the member loads are in flight
             for (int c = t; c < ncb; c += BRICK_T)
-                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.pre[c]);
+                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
@@ -4280,11 +4303,23 @@ k_brick_collide_f32(BrickArgs<float> A)
                 brick_sum_member(L.acc + 5 * lc[k], &L.cnt[lc[k]], id[k] >= 0, q);
             }
             __syncthreads();
+            // the four-wave block takes only call 0's Gamma tests here; a cell
+            // whose variate needs further calls (about one in ten thousand)
+            // makes the block finish from a second load of its members.  The
+            // eight-wave block, whose occupancy the registers of the further
+            // calls do not lower, draws in full.
+            constexpr bool SPLIT = BRICK_T == BRICK_T_WIDE;
+            bool pend = false;
             for (int c = t; c < ncb; c += BRICK_T)
-                if (brick_cnt_members(L.cnt[c]) >= 2)
-                    brick_cell_params_f32(s, bi, c, L.cnt[c], q0_solvent, L.acc, L.pre[c], A.cos_a, A.sin_a,
-                                          A.kT_cell, A.seed, step, L.par + 12 * c, st);
-            __syncthreads();
+                if (brick_cnt_members(L.cnt[c]) >= 2) {
+                    const bool done =
+                        brick_cell_params_f32<SPLIT>(s, bi, c, L.cnt[c], q0_solvent, L.acc, L.cell[c].pre, A.cos_a,
+                                                     A.sin_a, A.kT_cell, A.seed, step, L.cell[c].par, st);
+                    L.more[c] = !done;
+                    pend = pend || !done;
+                }
+            more = SPLIT ? __syncthreads_or(pend) : (__syncthreads(), false);
+          if (!more) {
             // rotate and stream every member and take its rank in its class
             // from the LDS counters; the stores wait until the counts are final
             // (a barrier after global stores would wait for their completion)
@@ -4292,7 +4327,7 @@ k_brick_collide_f32(BrickArgs<float> A)
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
-                if (brick_cnt_members(L.cnt[lc[k]]) >= 2) brick_rotate_f32(L.par + 12 * lc[k], w[k], st);
+                if (brick_cnt_members(L.cnt[lc[k]]) >= 2) brick_rotate_f32(L.cell[lc[k]].par, w[k], st);
                 if (id[k] < 0) continue;  // a site: written back below
                 int32_t dst = 0;
                 const int cls = brick_stream_g<UNIT>(A, G, bi, Lb, p[k], w[k], &dst, st);
@@ -4326,11 +4361,12 @@ k_brick_collide_f32(BrickArgs<float> A)
                     brick_put<float>(A, par_out, L.wdst[c], L.woff[c], L.wcap[c], rank[k], p[k], w[k], id[k], st);
                 }
             }
+          }
         } else {
             // more members than the block holds: sums over chunks of the
             // member list, then a second load of each member to rotate it
             for (int c = t; c < ncb; c += BRICK_T)
-                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.pre[c]);
+                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
             for (int i = t; i < nmem; i += BRICK_T) {
                 float p[3], w[3];
                 int32_t id;
@@ -4348,18 +4384,28 @@ k_brick_collide_f32(BrickArgs<float> A)
             __syncthreads();
             for (int c = t; c < ncb; c += BRICK_T)
                 if (brick_cnt_members(L.cnt[c]) >= 2)
-                    brick_cell_params_f32(s, bi, c, L.cnt[c], q0_solvent, L.acc, L.pre[c], A.cos_a, A.sin_a,
-                                          A.kT_cell, A.seed, step, L.par + 12 * c, st);
+                    brick_cell_params_f32<false>(s, bi, c, L.cnt[c], q0_solvent, L.acc, L.cell[c].pre, A.cos_a,
+                                                 A.sin_a, A.kT_cell, A.seed, step, L.cell[c].par, st);
             __syncthreads();
+        }
+        if (nmem > ITEMS * BRICK_T || more) {
+            if (more) {  // the cells whose Gamma variate needs further calls
+                for (int c = t; c < ncb; c += BRICK_T)
+                    if (brick_cnt_members(L.cnt[c]) >= 2 && L.more[c])
+                        brick_cell_params_f32<false>(s, bi, c, L.cnt[c], q0_solvent, L.acc, L.cell[c].pre, A.cos_a,
+                                                     A.sin_a, A.kT_cell, A.seed, step, L.cell[c].par, st);
+                __syncthreads();
+            }
             // second load: each member is read again before its own write (a
-            // site appears once in a brick's list)
+            // site appears once in a brick's list, and nothing has been
+            // written yet)
             for (int i = t; i < nmem; i += BRICK_T) {
                 float p[3], w[3];
                 int32_t id;
                 if (!brick_member<float>(A, bi, par_in, i, L, p, w, id, st)) continue;
                 const int c = brick_local_cell<float>(s, bn, bi, b, p, L.sh, st);
                 if (c < 0) continue;
-                if (brick_cnt_members(L.cnt[c]) >= 2) brick_rotate_f32(L.par + 12 * c, w, st);
+                if (brick_cnt_members(L.cnt[c]) >= 2) brick_rotate_f32(L.cell[c].par, w, st);
                 if (id < 0) {
                     const int64_t j = -(int64_t)id - 1, S = s.S;
                     A.vs[j] = w[0]; A.vs[S + j] = w[1]; A.vs[2 * S + j] = w[2];
@@ -4576,7 +4622,7 @@ int64_t region_cap(double mu) { return (int64_t)ceil(mu + 6.0 * sqrt(mu)) + 16; 
 int64_t site_cap(int64_t ncb, int64_t S_r) { return ncb + 64 < S_r ? ncb + 64 : S_r; }
 
 // Members a brick block holds in registers (FP32) or LDS (FP64).
-int brick_block_members(int prec) { return prec == MPCD_F64 ? 1024 : BRICK_MEMBERS; }
+int brick_block_members(int prec) { return prec == MPCD_F64 ? 1024 : BRICK_PLAN_MEMBERS; }
 
 int32_t sovf_cap_of(const mpcd_sys *sys)
 {
@@ -6073,7 +6119,8 @@ int mpcd_binned_layout(const mpcd_sys *sys, const int32_t *ncell, const int64_t 
     out->nbricks = P.nbricks;
     out->capacity = P.cap;
     out->site_slots = P.sslots;
-    out->items = sys->prec == MPCD_F64 ? 0 : (int)(BRICK_MEMBERS / (P.nbricks >= BRICK_WIDE_MIN ? BRICK_T_WIDE : BRICK_T_NARROW));
+    out->items = sys->prec == MPCD_F64 ? 0
+                 : P.nbricks >= BRICK_WIDE_MIN ? BRICK_MEMBERS_WIDE / BRICK_T_WIDE : BRICK_MEMBERS_NARROW / BRICK_T_NARROW;
     out->ws_bytes = binned_layout(sys, P.nbricks, P.sslots, P.sovf_cap).total;
     return MPCD_OK;
 }

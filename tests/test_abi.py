@@ -160,7 +160,7 @@ def test_binned_layout_plan():
     ncells = [int(np.prod(s["ncell"])) for s in systems]
     assert b.nbricks >= sum(c // 256 for c in ncells)
     assert 3.0 * N < b.capacity < 6.0 * N
-    assert b.items == (8 if b.nbricks >= 4096 else 4) and b.ws_bytes > 0 and b.site_slots > 0
+    assert b.items == (7 if b.nbricks >= 4096 else 4) and b.ws_bytes > 0 and b.site_slots > 0
     # a denser system gets smaller bricks, not more members per block
     wl = W.make_system((16, 16, 16), 10, [], np.zeros((0, 3)), np.zeros((0, 4)), np.random.default_rng(1))
     rc, b10, N10 = binned_layout([wl])

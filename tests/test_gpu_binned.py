@@ -152,7 +152,7 @@ def test_site_list_overflow():
 
 
 def test_four_wave_blocks_crowded_brick_with_site_overflow():
-    """A box of 4096 bricks, which takes the four-wave brick block (eight
+    """A box of 4096 bricks, which takes the four-wave brick block (seven
     members per lane; the smaller systems above take the eight-wave block).
     In its first brick six overlapping spheres of 100 sites overflow the
     brick's site list, and 600 extra solvent crowded among them overflow its
@@ -170,7 +170,7 @@ def test_four_wave_blocks_crowded_brick_with_site_overflow():
     par = W.srd_params(43, kT_cell=1.0)
     say("binned four-wave blocks, crowded brick")
     gd, gb = dense_and_binned(wl, par, 4, check_every=2)
-    assert gb.binned.nbricks >= 4096 and gb.binned.items == 8
+    assert gb.binned.nbricks >= 4096 and gb.binned.items == 7
 
 
 def test_full_size_suspension_binned_equals_dense():
