@@ -480,6 +480,25 @@ def test_site_wca_mixed_shapes_bit_exact():
     assert sum(c > 0 for c in contact[:-1]) >= 1, contact  # bodies touch again before the last comparison
 
 
+def test_site_wca_small_box_bit_exact():
+    """Two cubes in contact in a small box (6 cells): site-site forces and
+    torques, then full steps, against the oracle."""
+    rng = np.random.default_rng(75)
+    cube = np.array([[x, y, z] for x in (-0.7, 0.7) for y in (-0.7, 0.7) for z in (-0.7, 0.7)])
+    tpl = W.rigid_template(cube, 1.0)
+    # two unrotated cubes whose facing sites are 0.85 apart, inside the cutoff
+    # 0.8 * 2^(1/6) but clear of the repulsive core
+    centres = np.array([[1.5, 3.0, 3.0], [3.75, 3.0, 3.0]])
+    quats = np.array([[1.0, 0.0, 0.0, 0.0]] * 2)
+    wl = W.make_system((6, 6, 6), 3, [tpl] * 2, centres, quats, rng)
+    par = W.srd_params(75, kT_cell=1.0, wca=W.wca_sites(sigma=0.8))
+    o0 = oracle.OracleSystem(wl, par)
+    o0.body_forces()
+    assert np.count_nonzero(o0.F) >= 2  # the cubes interact from the start
+    say("site WCA cubes 6^3")
+    run_parity(wl, par, 8, check_every=4)
+
+
 def test_site_wca_crowded_bodies_fall_back_to_all_pairs():
     """Small shapes packed so a grid bucket overflows: every body of the
     system becomes a candidate, with the same sums."""
