@@ -4184,44 +4184,60 @@ k_brick_collide_f32(BrickArgs<float> A)
         const BrickInfo bi = bn.brick[b];
         const int r = bi.sys;
         const int ncb = bi.dim[0] * bi.dim[1] * bi.dim[2];
+        // wave 0 reads the brick's header in one round: the input fills (a
+        // sub-region without a writer has capacity 0) and their exclusive
+        // prefix, the sub-regions this brick writes, the site count, the
+        // overflow flag and list lengths, and the grid shifts of this step and
+        // the next from the table the previous launch (or the packing) stored,
+        // drawn here if it is stale.  The loads are issued first; every lane
+        // takes its cell's first random call while they are in flight.
+        int v = 0, s0 = 0, s1 = 0, nsc = 0, ofl = 0, ovl = 0, sovl = 0;
+        int4 wt = make_int4(0, 0, 0, 0);
+        double tab0 = 0.0, tabw = 0.0;
+        if (t < NCLS) {
+            const int32_t *sp = bn.subpre + b * (NCLS + 1);
+            s0 = sp[t];
+            s1 = sp[t + 1];
+            v = bn.cnt[((int64_t)par_in * bn.nbricks + b) * NCLS + t];
+            wt = bn.wtab[b * NCLS + t];  // the sub-region this brick writes with class t
+        }
+        if (t == 32) nsc = bn.scnt[b];
+        if (t == 33) ofl = bn.oflag[(int64_t)par_in * bn.nbricks + b];
+        if (t == 34) ovl = bn.ctrl[BC_OVF0 + par_in];
+        if (t == 35) sovl = bn.ctrl[BC_SOVF];
+        if (t >= 40 && t < 46) {
+            const double *tab = bn.shtab + (int64_t)par_in * (1 + 6 * (int64_t)s.nsys);
+            tab0 = tab[0];
+            tabw = tab[1 + 6 * r + (t - 40)];
+        }
+        for (int c = t; c < ncb; c += BRICK_T)
+            cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
         if (t < 64) {
-            // wave 0 reads the brick's header in one round: the input fills (a
-            // sub-region without a writer has capacity 0) and their exclusive
-            // prefix, the sub-regions this brick writes, the site count, the overflow flag and list lengths, and
-            // the grid shifts of this step and the next from the table the
-            // previous launch (or the packing) stored, drawn here if it is stale
-            int v = 0;
             if (t < NCLS) {
-                const int32_t *sp = bn.subpre + b * (NCLS + 1);
-                const int s0 = sp[t], s1 = sp[t + 1];
                 L.csub[t] = s0;
                 if (t == NCLS - 1) L.csub[NCLS] = s1;
-                v = min(bn.cnt[((int64_t)par_in * bn.nbricks + b) * NCLS + t], s1 - s0);
+                v = min(v, s1 - s0);
                 L.wcnt[t] = 0;
-                const int4 wt = bn.wtab[b * NCLS + t];  // the sub-region this brick writes with class t
                 L.woff[t] = wt.x;
                 L.wcap[t] = wt.y;
                 L.wdst[t] = wt.z;
             }
             if (t == 32) {
-                const int n = bn.scnt[b];
-                L.hdr[1] = min(n, (int)bi.scap);
-                L.hdr[6] = n > (int)bi.scap;  // sites of this brick in the site overflow list
+                L.hdr[1] = min(nsc, (int)bi.scap);
+                L.hdr[6] = nsc > (int)bi.scap;  // sites of this brick in the site overflow list
             }
-            if (t == 33) L.hdr[7] = bn.oflag[(int64_t)par_in * bn.nbricks + b];
-            if (t == 34) L.hdr[4] = min(bn.ctrl[BC_OVF0 + par_in], BIN_OVF_CAP);
-            if (t == 35) L.hdr[5] = min(bn.ctrl[BC_SOVF], bn.sovf_cap);
+            if (t == 33) L.hdr[7] = ofl;
+            if (t == 34) L.hdr[4] = min(ovl, BIN_OVF_CAP);
+            if (t == 35) L.hdr[5] = min(sovl, bn.sovf_cap);
             if (t == 36) {
                 L.hdr[2] = 0;
                 L.hdr[3] = 0;
             }
             if (t >= 40 && t < 46) {
-                const double *tab = bn.shtab + (int64_t)par_in * (1 + 6 * (int64_t)s.nsys);
                 const int k = t - 40;
-                if (tab[0] == (double)step) {
-                    const double w = tab[1 + 6 * r + k];
-                    if (k < 3) L.sh[k] = w;
-                    else L.sh1[k - 3] = w;
+                if (tab0 == (double)step) {
+                    if (k < 3) L.sh[k] = tabw;
+                    else L.sh1[k - 3] = tabw;
                 } else if (k == 0) {
                     shift_of(s, A.seed, step, r, L.sh);
                 } else if (k == 1) {
@@ -4285,10 +4301,6 @@ k_brick_collide_f32(BrickArgs<float> A)
                 id[k] = 0;
                 if (i < nmem && brick_member<float>(A, bi, par_in, i, L, p[k], w[k], id[k], st)) lc[k] = 0;
             }
-            // the cells' first random calls and the regions this brick writes,
-            // while the member loads are in flight
-            for (int c = t; c < ncb; c += BRICK_T)
-                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
@@ -4365,8 +4377,6 @@ k_brick_collide_f32(BrickArgs<float> A)
         } else {
             // more members than the block holds: sums over chunks of the
             // member list, then a second load of each member to rotate it
-            for (int c = t; c < ncb; c += BRICK_T)
-                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
             for (int i = t; i < nmem; i += BRICK_T) {
                 float p[3], w[3];
                 int32_t id;
