@@ -4344,17 +4344,26 @@ k_brick_collide_f32(BrickArgs<float> A)
                 int32_t dst = 0;
                 const int cls = brick_stream_g<UNIT>(A, G, bi, Lb, p[k], w[k], &dst, st);
                 lc[k] = cls >= 0 ? cls : NCLS;  // NCLS: beyond the neighbouring bricks
+                rank[k] = cls > 0 ? atomicAdd(&L.wcnt[cls], 1) : dst;  // the own class: below
+            }
+            {
                 // the brick's own class (most members): one LDS atomic per wave
-                const unsigned long long own = __ballot(cls == 0);
-                if (cls == 0) {
-                    const int lane = threadIdx.x & 63;
-                    const int leader = __ffsll((long long)own) - 1;
-                    const unsigned long long below = lane ? (own & (~0ull >> (64 - lane))) : 0ull;
-                    int base = 0;
-                    if (lane == leader) base = atomicAdd(&L.wcnt[0], __popcll(own));
-                    rank[k] = __shfl(base, leader, 64) + __popcll(below);
-                } else {
-                    rank[k] = cls > 0 ? atomicAdd(&L.wcnt[cls], 1) : dst;
+                // for all of its lanes' items, then each member's rank from the
+                // ballots, item by item
+                const int lane = threadIdx.x & 63;
+                const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+                int tot = 0;
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) tot += __popcll(__ballot(lc[k] == 0 && id[k] >= 0));
+                int base = 0;
+                if (lane == 0 && tot > 0) base = atomicAdd(&L.wcnt[0], tot);
+                base = __shfl(base, 0, 64);
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) {
+                    const bool own = lc[k] == 0 && id[k] >= 0;
+                    const unsigned long long m = __ballot(own);
+                    if (own) rank[k] = base + __popcll(m & below);
+                    base += __popcll(m);
                 }
             }
             __syncthreads();
