@@ -4184,6 +4184,21 @@ k_brick_collide_f32(BrickArgs<float> A)
         const BrickInfo bi = bn.brick[b];
         const int r = bi.sys;
         const int ncb = bi.dim[0] * bi.dim[1] * bi.dim[2];
+        // The brick's own sub-region starts its region, and at 2 or more
+        // solvent per cell its first 2 ncb slots are as good as always filled:
+        // each lane loads its first members (512 per block at most) from there
+        // before the header arrives.  One beyond the fill is discarded and
+        // loaded again from its place; the slots read stay within the region.
+        constexpr int KSPEC = 512 / BRICK_T;
+        const int spec = min(min(512, 2 * ncb), bi.cap);
+        float p[ITEMS][3], w[ITEMS][3];
+        int32_t id[ITEMS];
+#pragma unroll
+        for (int k = 0; k < KSPEC; ++k) {
+            const int i = t + k * BRICK_T;
+            id[k] = 0;
+            if (i < spec) rec_load(A.rec, bi.off + i, p[k], w[k], id[k]);
+        }
         // wave 0 reads the brick's header in one round: the input fills (a
         // sub-region without a writer has capacity 0) and their exclusive
         // prefix, the sub-regions this brick writes, the site count, the
@@ -4210,8 +4225,6 @@ k_brick_collide_f32(BrickArgs<float> A)
             tab0 = tab[0];
             tabw = tab[1 + 6 * r + (t - 40)];
         }
-        for (int c = t; c < ncb; c += BRICK_T)
-            cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
         if (t < 64) {
             if (t < NCLS) {
                 L.csub[t] = s0;
@@ -4291,16 +4304,21 @@ k_brick_collide_f32(BrickArgs<float> A)
                              (float)((double)s.ncell[3 * r + 2] * s.a)};
         bool more = false;  // a cell of the register path needs further Gamma calls
         if (nmem <= ITEMS * BRICK_T) {
-            float p[ITEMS][3], w[ITEMS][3];
-            int32_t id[ITEMS];
             int lc[ITEMS];
+            const int own = __builtin_amdgcn_readfirstlane(L.cpre[1]);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int i = t + k * BRICK_T;
                 lc[k] = -1;
-                id[k] = 0;
-                if (i < nmem && brick_member<float>(A, bi, par_in, i, L, p[k], w[k], id[k], st)) lc[k] = 0;
+                if (k < KSPEC && i < spec && i < own) {
+                    lc[k] = 0;  // loaded before the header
+                } else {
+                    id[k] = 0;
+                    if (i < nmem && brick_member<float>(A, bi, par_in, i, L, p[k], w[k], id[k], st)) lc[k] = 0;
+                }
             }
+            for (int c = t; c < ncb; c += BRICK_T)
+                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
@@ -4386,6 +4404,8 @@ k_brick_collide_f32(BrickArgs<float> A)
         } else {
             // more members than the block holds: sums over chunks of the
             // member list, then a second load of each member to rotate it
+            for (int c = t; c < ncb; c += BRICK_T)
+                cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
             for (int i = t; i < nmem; i += BRICK_T) {
                 float p[3], w[3];
                 int32_t id;

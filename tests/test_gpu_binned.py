@@ -173,6 +173,19 @@ def test_four_wave_blocks_crowded_brick_with_site_overflow():
     assert gb.binned.nbricks >= 4096 and gb.binned.items == 7
 
 
+@pytest.mark.parametrize("ncell,density", [((16, 16, 16), 1), ((128, 128, 64), 1.5)])
+def test_low_density_binned(ncell, density):
+    """Few solvent per cell (the eight-wave block at 16^3, the four-wave block
+    on 4096 bricks): a brick's own sub-region then holds fewer members than
+    its lanes load before the header, and those lanes load again."""
+    rng = np.random.default_rng(47)
+    tpl = W.sphere_template(2.0, 100, 5.0)
+    wl = W.make_system(ncell, density, [tpl], np.array([[5.0, 5.0, 5.0]]), W.random_quaternions(rng, 1), rng)
+    par = W.srd_params(47, kT_cell=1.0)
+    say("binned low density %r" % (ncell,))
+    dense_and_binned(wl, par, 4, check_every=2)
+
+
 def test_full_size_suspension_binned_equals_dense():
     wl, par, _ = W.config(1)
     say("binned 60^3")
