@@ -3714,10 +3714,13 @@ int check_ws(const mpcd_sys *s, const void *ws, size_t ws_bytes)
 // writes.  The solvent therefore crosses HBM once per step (read and written
 // once), with no cell lists, scan, scatter, permutation or device atomics.
 // A brick with more members than the block holds in registers takes a
-// two-pass path (sums, then a second load to rotate and write).
+// two-pass path (sums, then a second load to rotate and write); so does a
+// four-wave block with a cell whose thermostat variate needs more than the
+// first random call (about one cell in ten thousand), whose further calls
+// then run with no members held in registers.
 // A brick block holds its members in registers, in one of two shapes.  Four
 // waves of seven members per lane (1792; under 128 VGPRs, four waves per
-// SIMD) with 33 KB of LDS leave four blocks resident per CU, against two for
+// SIMD) with 35 KB of LDS leave four blocks resident per CU, against two for
 // eight waves of four members per lane (2048), so more of the solvent is in
 // flight; the eight-wave shape is faster when there are too few bricks to
 // fill the CUs over several rounds.  Bricks are planned for 2048 members
@@ -4204,8 +4207,7 @@ k_brick_collide_f32(BrickArgs<float> A)
         // prefix, the sub-regions this brick writes, the site count, the
         // overflow flag and list lengths, and the grid shifts of this step and
         // the next from the table the previous launch (or the packing) stored,
-        // drawn here if it is stale.  The loads are issued first; every lane
-        // takes its cell's first random call while they are in flight.
+        // drawn here if it is stale.
         int v = 0, s0 = 0, s1 = 0, nsc = 0, ofl = 0, ovl = 0, sovl = 0;
         int4 wt = make_int4(0, 0, 0, 0);
         double tab0 = 0.0, tabw = 0.0;
@@ -4317,6 +4319,7 @@ k_brick_collide_f32(BrickArgs<float> A)
                     if (i < nmem && brick_member<float>(A, bi, par_in, i, L, p[k], w[k], id[k], st)) lc[k] = 0;
                 }
             }
+            // the cells' first random calls while the member loads are in flight
             for (int c = t; c < ncb; c += BRICK_T)
                 cell_draw_pre(A.seed, step, brick_cell_canonical(s, bi, c), s.replica0 + (uint64_t)r, L.cell[c].pre);
 #pragma unroll
