@@ -3731,7 +3731,7 @@ constexpr int BRICK_MEMBERS_WIDE = 1792;    // members a four-wave block holds i
 constexpr int BRICK_MEMBERS_NARROW = 2048;  // and an eight-wave block
 constexpr int BRICK_MAXC = 256;      // cells per brick at most (one lane per cell)
 constexpr int BRICK_OVL = 512;       // overflow entries per brick and kind a block takes
-constexpr int BRICK_T_WIDE = 256;    // threads of a block of the many-brick shape (eight members per lane)
+constexpr int BRICK_T_WIDE = 256;    // threads of a block of the many-brick shape (seven members per lane)
 constexpr int BRICK_T_NARROW = 512;  // and of the few-brick shape (four per lane)
 constexpr int64_t BRICK_WIDE_MIN = 4096;  // bricks from which the four-wave shape is used
 
