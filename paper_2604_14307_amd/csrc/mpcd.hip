@@ -2994,6 +2994,7 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
     __shared__ double sh[6 * SH_PAD];
     __shared__ double sp[3][BODY_T];  // a chunk of one candidate body's site positions
     __shared__ float spf[3][BODY_T];  // and the same rounded to FP32, for a conservative pair filter
+    __shared__ float sof[3][BODY_T];  // their offsets from that body's centre (minimum image), in FP32
     __shared__ double fT[6];
     const int64_t i = blockIdx.x;
     if (advance_step && i == 0 && threadIdx.x == 0) *advance_step = *advance_step + 1;
@@ -3014,6 +3015,18 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
     // centre-distance bounds with a margin far above rounding
     const double reach_b = 2.0 * wca.reach + rc, cut_b = (reach_b * reach_b) * (1.0 + 1e-9) + 1e-12;
     const double reach_s = wca.reach + rc, cut_s = (reach_s * reach_s) * (1.0 + 1e-9) + 1e-12;
+    // Wave cull of a candidate's sites.  Take a site j of this body within
+    // reach_s of candidate centre C (offset e_j), and a site u of the
+    // candidate (offset o_u, |o_u| <= reach), both as minimum images.  On an
+    // axis longer than 2 reach + 2 rc, e_j - o_u is the pair's own minimum
+    // image whenever the pair lies within rc (another image would put them at
+    // least L - rc apart on that axis), so then |e_j - o_u| <= rc on every
+    // axis.  A site u outside the box of the wave's e_j, grown by rc + 0.01
+    // (far above the FP32 rounding of offsets this small), adds nothing to any
+    // lane of the wave and is skipped.  On shorter boxes every site is kept.
+    const bool cull = Lb[0] > 2.0 * (wca.reach + rc) + 0.1 && Lb[1] > 2.0 * (wca.reach + rc) + 0.1 &&
+                      Lb[2] > 2.0 * (wca.reach + rc) + 0.1;
+    const float grow = (float)(rc + 0.01);
     bool use_grid = grid.count != nullptr;
     if (use_grid) {
         int ng[3];
@@ -3112,16 +3125,39 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
             const int64_t b2 = use_grid ? (int64_t)nb[q] : jb + q;
             if (b2 == i) continue;  // (uniform)
             bool near = false;
+            float ef[3] = {0.0f, 0.0f, 0.0f};
             if (active) {
                 double d2 = 0.0;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const double d = min_image(pj[k] - bd.pos[k * B + b2], Lb[k]);
+                    ef[k] = (float)d;
                     d2 = d2 + d * d;
                 }
                 near = d2 <= cut_s;
             }
             if (!__syncthreads_or(near)) continue;  // no site of this chunk within reach of b2
+            // the box of this wave's near sites (offsets from b2's centre)
+            float lo[3], hi[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = near ? ef[k] : INFINITY;
+                hi[k] = near ? ef[k] : -INFINITY;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = fminf(lo[k], __shfl_xor(lo[k], o, 64));
+                    hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o, 64));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                lo[k] -= grow;
+                hi[k] += grow;
+            }
+            const bool wnear = __ballot(near) != 0;
             const int64_t k0 = bd.site_off[b2], k1 = bd.site_off[b2 + 1];
             for (int64_t kc = k0; kc < k1; kc += BODY_T) {
                 const int nk = (int)((k1 - kc) < BODY_T ? (k1 - kc) : BODY_T);
@@ -3131,11 +3167,22 @@ __global__ __launch_bounds__(BODY_T) void k_site_forces(SysDev s, BodyDev bd, mp
                         const double x = fr.pos[k * S + kc + t];
                         sp[k][t] = x;
                         spf[k][t] = (float)x;
+                        sof[k][t] = (float)min_image(x - bd.pos[k * B + b2], Lb[k]);
                     }
                 }
                 __syncthreads();
-                if (near) {
-                    for (int u = 0; u < nk; ++u) {
+                // 64 candidate sites at a time: the wave keeps those inside
+                // its box and takes them in ascending order
+                for (int u0 = 0; wnear && u0 < nk; u0 += 64) {
+                    const int uq = u0 + (t & 63);
+                    bool keep = uq < nk;
+                    if (keep && cull) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) keep = keep && sof[k][uq] >= lo[k] && sof[k][uq] <= hi[k];
+                    }
+                    for (unsigned long long m = __ballot(keep); m != 0; m &= m - 1) {
+                        const int u = u0 + __builtin_ctzll(m);
+                        if (!near) continue;
                         float r2f = 0.0f;
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {

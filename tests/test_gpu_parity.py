@@ -480,9 +480,12 @@ def test_site_wca_mixed_shapes_bit_exact():
     assert sum(c > 0 for c in contact[:-1]) >= 1, contact  # bodies touch again before the last comparison
 
 
-def test_site_wca_small_box_bit_exact():
-    """Two cubes in contact in a small box (6 cells): site-site forces and
-    torques, then full steps, against the oracle."""
+@pytest.mark.parametrize("ncell", [(6, 6, 6), (6, 6, 4)])
+def test_site_wca_small_box_bit_exact(ncell):
+    """Two cubes in contact in a small box: site-site forces and torques, then
+    full steps, against the oracle.  With 6 cells on every axis the kernel
+    culls candidate sites by each wave's box; with 4 cells on one axis (no
+    longer than twice the cubes' reach plus the cutoff) it keeps them all."""
     rng = np.random.default_rng(75)
     cube = np.array([[x, y, z] for x in (-0.7, 0.7) for y in (-0.7, 0.7) for z in (-0.7, 0.7)])
     tpl = W.rigid_template(cube, 1.0)
@@ -490,12 +493,14 @@ def test_site_wca_small_box_bit_exact():
     # 0.8 * 2^(1/6) but clear of the repulsive core
     centres = np.array([[1.5, 3.0, 3.0], [3.75, 3.0, 3.0]])
     quats = np.array([[1.0, 0.0, 0.0, 0.0]] * 2)
-    wl = W.make_system((6, 6, 6), 3, [tpl] * 2, centres, quats, rng)
+    if ncell[2] == 4:
+        centres[:, 2] = 2.0
+    wl = W.make_system(ncell, 3, [tpl] * 2, centres, quats, rng)
     par = W.srd_params(75, kT_cell=1.0, wca=W.wca_sites(sigma=0.8))
     o0 = oracle.OracleSystem(wl, par)
     o0.body_forces()
     assert np.count_nonzero(o0.F) >= 2  # the cubes interact from the start
-    say("site WCA cubes 6^3")
+    say("site WCA cubes %s" % (ncell,))
     run_parity(wl, par, 8, check_every=4)
 
 
