@@ -2691,14 +2691,16 @@ constexpr int FRC_T = 64;
 // LDS of the body forces for a block of NT threads.
 constexpr int FRC_NCAND = 27 * GRID_K;
 template <int NT> struct ForceLds {
-    double sf[3][NT + 1];
+    union {
+        double sf[3][NT + 1];      // all-pairs path: each lane's contribution
+        double hc[3][FRC_NCAND];  // grid path: the contributions of the hits
+    };
     int shit[NT];
     double fsh[3];
     uint32_t s_h[27];
     int s_n[27], s_pre[28];
     int s_ovf, s_nhit;
     int hj[FRC_NCAND];
-    double hc[3][FRC_NCAND];
 };
 
 // The forces (and kick) of body i = blockIdx.x < B by a block of NT threads.
@@ -2834,10 +2836,10 @@ __device__ void body_forces_block(const SysDev &s, const BodyDev &bd, const mpcd
                     f1 = f1 + hc[1][a];
                     f2 = f2 + hc[2][a];
                 }
-                sf[0][0] = f0; sf[1][0] = f1; sf[2][0] = f2;
+                fsh[0] = f0; fsh[1] = f1; fsh[2] = f2;
             }
             __syncthreads();
-            if (t < 3) f = sf[t][0];
+            if (t < 3) f = fsh[t];
         }
         for (int64_t j0 = jb; !use_grid && j0 < je; j0 += NT) {
             const int64_t j = j0 + t;
@@ -3843,7 +3845,6 @@ template <typename Real> struct BrickArgs {
     double cos_a, sin_a, kT_cell, dt;
     uint64_t seed;
     const uint64_t *d_step;
-    uint64_t *step_next;  // when set, block 0 stores the step index + 1 there
     double *shift_out;    // when set, block 0 stores the step's grid shifts there
     int32_t *grid_clear;  // body-centre grid cleared for this step's insertions
     int64_t grid_n;
@@ -4510,11 +4511,10 @@ k_brick_collide_f32(BrickArgs<float> A)
         }
     }
     // after the brick's barriers, so that their waits do not include these
-    // stores: block 0 stores the step bookkeeping and the next step's shift
+    // stores: block 0 stores the step's grid shifts and the next step's shift
     // table (the other parity), and every block clears its share of the
     // body-centre grid for this step's insertions
     if (blockIdx.x == 0) {
-        if (t == 0 && A.step_next) *A.step_next = step + 1;
         if (A.shift_out) draw_shifts(s, A.seed, step, A.shift_out);
         binned_store_shifts(s, bn, A.seed, step + 1);
     }
@@ -4564,33 +4564,6 @@ __global__ __launch_bounds__(BODY_T) void k_therm_bin(SysDev s, BodyDev bd, Bric
     if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0)) shift_of(s, seed, step, r, bsh);
     thermalize_body<Real>(s, bd, b, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, nullptr, nullptr, nullptr,
                           &bb, lds, st);
-    flag(status, st);
-}
-
-// Step t's body forces, second half kick and step-counter advance, then the
-// same block thermalizes its body's sites for step t + 1 and bins them into
-// the bricks' site lists (binned layout, graph schedule).
-template <typename Real>
-__global__ __launch_bounds__(BODY_T) void k_forces_therm_bin(SysDev s, BodyDev bd, mpcd_wca wca, BodyGrid grid,
-                                                             ExtForce E, double dt, uint64_t *advance_step,
-                                                             BrickSiteBin bb, double kT, int thermalize, uint64_t seed,
-                                                             const uint64_t *step_next, Real *xs, Real *vs,
-                                                             double *site_d, double *vpre, uint32_t *status)
-{
-    __shared__ double bsh[3];
-    __shared__ union {
-        ForceLds<BODY_T> f;
-        ThermLds th;
-    } lds;
-    if ((int64_t)blockIdx.x >= s.B) return;
-    body_forces_block<BODY_T>(s, bd, wca, grid, E, dt, 1, advance_step, status, lds.f);
-    __syncthreads();  // the kick is stored; the LDS is free
-    const uint64_t step = *step_next;
-    uint32_t st = 0;
-    const int r = find_sys_wave(s.body_off, s.nsys, blockIdx.x);
-    if (threadIdx.x == 64 || (BODY_T <= 64 && threadIdx.x == 0)) shift_of(s, seed, step, r, bsh);
-    thermalize_body<Real>(s, bd, blockIdx.x, kT, thermalize, seed, step, xs, vs, site_d, vpre, bsh, nullptr, nullptr,
-                          nullptr, &bb, lds.th, st);
     flag(status, st);
 }
 
@@ -5386,29 +5359,8 @@ static void launch_therm_bin(const Ctx &c, hipStream_t st, const mpcd_bodies *bo
                            seed, d_step, (float *)xs, (float *)vs, site_d, vpre, c.status);
 }
 
-static void launch_forces_therm_bin(const Ctx &c, hipStream_t st, const mpcd_bodies *bodies, const mpcd_wca &wca,
-                                    const double *f_ext, double dt, uint64_t *advance, double kT, int thermalize,
-                                    uint64_t seed, const uint64_t *step_next, void *xs, void *vs,
-                                    const mpcd_binned *b)
-{
-    const BodyDev bd = make_bodydev(bodies);
-    const BodyGrid grid = body_grid(c, wca);
-    const ExtForce E = make_ext(f_ext);
-    double *site_d = at<double>(c.ws, c.L.site_d), *vpre = at<double>(c.ws, c.L.vpre);
-    const dim3 g((unsigned)c.sys->n_bodies);
-    if (c.sys->prec == MPCD_F64)
-        hipLaunchKernelGGL(k_forces_therm_bin<double>, g, dim3(BODY_T), 0, st, c.sd, bd, wca, grid, E, dt, advance,
-                           brick_site_bin(c, b), kT, thermalize, seed, step_next, (double *)xs, (double *)vs, site_d,
-                           vpre, c.status);
-    else
-        hipLaunchKernelGGL(k_forces_therm_bin<float>, g, dim3(BODY_T), 0, st, c.sd, bd, wca, grid, E, dt, advance,
-                           brick_site_bin(c, b), kT, thermalize, seed, step_next, (float *)xs, (float *)vs, site_d,
-                           vpre, c.status);
-}
-
-// The brick collision of the binned layout (FP32).  step_next: when set,
-// block 0 stores the step index + 1 there.
-static void launch_brick_collide(const Ctx &c, hipStream_t st, const mpcd_step_args *a, uint64_t *step_next)
+// The brick collision of the binned layout (FP32).
+static void launch_brick_collide(const Ctx &c, hipStream_t st, const mpcd_step_args *a)
 {
     const mpcd_params &p = a->par;
     BrickArgs<float> A;
@@ -5425,7 +5377,6 @@ static void launch_brick_collide(const Ctx &c, hipStream_t st, const mpcd_step_a
     A.dt = p.dt;
     A.seed = p.seed;
     A.d_step = a->d_step;
-    A.step_next = step_next;
     A.shift_out = at<double>(c.ws, c.L.shift);
     const BodyGrid grid = body_grid(c, p.wca);
     A.grid_clear = grid.count;
@@ -5852,22 +5803,20 @@ static int overlap_mode(const mpcd_step_args *a)
 // with the first body half-step, forces fused with the second half kick and
 // the step-counter advance.  The same operations in the same order, per
 // particle, cell and body, as calling the entry points in sequence.
-// One step of the binned layout: [thermalize + site binning], the brick
+// One step of the binned layout: thermalize + site binning, the brick
 // collision (collide, stream, bin the new solvent for the next step),
 // transfer fused with the first body half-step, forces fused with the second
-// half kick and the step-counter advance (in graphs also with the next step's
-// thermalization and site binning).
-static int step_binned(void *stream, const mpcd_step_args *a, const Overlap *ov)
+// half kick and the step-counter advance.  (Fusing the forces with the next
+// step's thermalization into one launch was slower: the one-wave force
+// blocks and the thermalization's smaller blocks each fill the CUs better.)
+static int step_binned(void *stream, const mpcd_step_args *a)
 {
     const mpcd_sys *s = a->sys;
     const mpcd_params &p = a->par;
     const Ctx c = make_ctx(s, a->ws, &p.tune);
     hipStream_t st = (hipStream_t)stream;
-    if (!(ov && ov->pre_binned))
-        launch_therm_bin(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->xs, a->vs, a->binned);
-    uint64_t *step_next = at<uint64_t>(c.ws, c.L.step_next);
-    const bool next = ov && ov->bin_next;
-    launch_brick_collide(c, st, a, next ? step_next : nullptr);
+    launch_therm_bin(c, st, &a->bodies, p.kT, p.thermalize, p.seed, a->d_step, a->xs, a->vs, a->binned);
+    launch_brick_collide(c, st, a);
     if (s->n_bodies == 0) {
         const BinnedDev bn = binned_dev(s, a->binned);
         hipLaunchKernelGGL(k_binned_finish, dim3(grid_for(bn.nbricks, 256)), dim3(256), 0, st, bn, a->d_step);
@@ -5875,18 +5824,14 @@ static int step_binned(void *stream, const mpcd_step_args *a, const Overlap *ov)
         return launch_check();
     }
     launch_transfer_first(c, st, &a->bodies, a->vs, a->J, a->K, p.dt, p.wca, a->binned, a->d_step);
-    if (next)
-        launch_forces_therm_bin(c, st, &a->bodies, p.wca, p.f_ext, p.dt, a->d_step, p.kT, p.thermalize, p.seed,
-                                step_next, a->xs, a->vs, a->binned);
-    else
-        launch_forces(c, st, &a->bodies, p.wca, p.f_ext, p.dt, 1, a->d_step);
+    launch_forces(c, st, &a->bodies, p.wca, p.f_ext, p.dt, 1, a->d_step);
     return launch_check();
 }
 
 static int step_impl(void *stream, const mpcd_step_args *a, const Overlap *ov)
 {
     TRY(step_checks(a));
-    if (a->binned) return step_binned(stream, a, ov);
+    if (a->binned) return step_binned(stream, a);
     const mpcd_sys *s = a->sys;
     const mpcd_params &p = a->par;
     const Ctx c = make_ctx(s, a->ws, &p.tune);
@@ -5970,12 +5915,8 @@ int mpcd_graph_create(void *stream, const mpcd_step_args *args, int32_t nsteps, 
     const bool oop = args->x_out != nullptr;
     if (oop && ((nsteps & 1) || (!args->binned && !args->tag))) return MPCD_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    // the binned layout fuses each next step's thermalization and site
-    // binning into the force kernel (bodies with sites, no site-site WCA)
-    const mpcd_sys *gs = args->sys;
-    const int omode = nsteps < 2 ? 0
-                      : args->binned ? ((gs->n_bodies > 0 && gs->n_sites > 0 && args->par.wca.mode != 2) ? 2 : 0)
-                                     : overlap_mode(args);
+    // (the binned layout's steps are captured as they run eagerly)
+    const int omode = (nsteps < 2 || args->binned) ? 0 : overlap_mode(args);
     Overlap ov{omode, nullptr, nullptr, nullptr, false, false};
     const bool overlap = omode != 0;
     if (omode == 1) {  // default-priority side stream and the two events, for the capture only
@@ -6195,7 +6136,7 @@ int mpcd_binned_collide(void *stream, const mpcd_step_args *a)
     hipStream_t st = (hipStream_t)stream;
     const BinnedDev bn = binned_dev(a->sys, a->binned);
     hipLaunchKernelGGL(k_binned_clear_out, dim3(grid_for(bn.nbricks, 256)), dim3(256), 0, st, bn, a->d_step);
-    launch_brick_collide(c, st, a, nullptr);
+    launch_brick_collide(c, st, a);
     return launch_check();
 }
 
