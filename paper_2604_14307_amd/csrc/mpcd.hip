@@ -2119,6 +2119,12 @@ __device__ __forceinline__ void brick_bin_site(const SysDev &s, const BrickSiteB
     int jc[3];
     const double sh[3] = {bsh[0], bsh[1], bsh[2]};
     const int32_t b = valid ? brick_of_pos<Real>(s, bn, r, xr[0], xr[1], xr[2], sh, jc, st) : -1;
+    // the brick's site list, loaded before the counter's round trip
+    int32_t soff = 0, scap = 0;
+    if (b >= 0) {
+        soff = bn.brick[b].soff;
+        scap = bn.brick[b].scap;
+    }
     const int lane = threadIdx.x & 63;
     const unsigned long long le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
     const int32_t prev = __shfl_up(b, 1, 64);
@@ -2132,9 +2138,8 @@ __device__ __forceinline__ void brick_bin_site(const SysDev &s, const BrickSiteB
     base = __shfl(base, hl, 64);
     if (b < 0) return;
     const int rank = base + (lane - hl);
-    const BrickInfo bi = bn.brick[b];
-    if (rank < bi.scap) {
-        bn.sslot[bi.soff + rank] = (int32_t)j;
+    if (rank < scap) {
+        bn.sslot[soff + rank] = (int32_t)j;
     } else {
         const int e = atomicAdd(&bn.ctrl[BC_SOVF], 1);
         if (e < bn.sovf_cap) {
@@ -2178,6 +2183,7 @@ struct ThermLds {
     double sh[6 * SH_PAD];
     double sacc[6];
     double dvw[6];
+    double bv[11];  // the body's angular momentum (4), mass, inertia (3) and momentum (3)
 };
 
 template <typename Real>
@@ -2202,6 +2208,20 @@ __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, d
     const int64_t j0 = bd.site_off[b], j1 = bd.site_off[b + 1];
     const int64_t sbase = bd.site_off[s.body_off[r]];
     const uint64_t rep = s.replica0 + (uint64_t)r;
+    // the body quantities of the closing update, loaded by 11 lanes now and
+    // put in LDS after the sites (their latency hides behind the draws)
+    double bvt = 0.0;
+    if (t < 11) {
+        const double *src = t < 4 ? bd.angmom + t * B
+                            : t == 4 ? bd.mass
+                            : t < 8  ? bd.inertia + (t - 5) * B
+                                     : bd.mom + (t - 8) * B;
+        bvt = src[b];
+    }
+    // a body of at most BODY_T sites is one chunk: each lane keeps its site's
+    // thermal velocity for the closing pass instead of storing and reloading it
+    const bool one = j1 - j0 <= BODY_T;
+    double vkeep[3] = {0.0, 0.0, 0.0};
     double acc = 0.0;
     for (int64_t c0 = j0; c0 < j1; c0 += BODY_T) {
         const int64_t j = c0 + t;
@@ -2223,7 +2243,8 @@ __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, d
                 site_d[k * S + j] = d[k];
                 xr[k] = (Real)wrap_d(R[k] + d[k], Lbox[k], st);
                 xs[k * S + j] = xr[k];
-                vpre[k * S + j] = vt[k];
+                if (one) vkeep[k] = vt[k];
+                else vpre[k * S + j] = vt[k];
                 pv[k] = mj * vt[k];
             }
             cross3(d, pv, c);
@@ -2248,16 +2269,17 @@ __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, d
         __syncthreads();
     }
     if (t < 6) sacc[t] = acc;
+    if (t < 11) lds.bv[t] = bvt;
     __syncthreads();
     if (t == 0) {
         double p[4], I[3], V[3], w[3];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) p[i] = bd.angmom[i * B + b];
-        const double Mb = bd.mass[b];
+        for (int i = 0; i < 4; ++i) p[i] = lds.bv[i];
+        const double Mb = lds.bv[4];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            I[k] = bd.inertia[k * B + b];
-            V[k] = bd.mom[k * B + b] / Mb;
+            I[k] = lds.bv[5 + k];
+            V[k] = lds.bv[8 + k] / Mb;
         }
         body_omega(q, p, A, I, w);
         double Vt[3], Lt[3], Lth[3], wth[3], wt[3];
@@ -2278,7 +2300,7 @@ __device__ void thermalize_body(const SysDev &s, const BodyDev &bd, int64_t b, d
         cross3(dw, d, c);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double vj = (dV[k] + c[k]) + vpre[k * S + j];
+            const double vj = (dV[k] + c[k]) + (one ? vkeep[k] : vpre[k * S + j]);
             const Real vr = (Real)vj;
             if (!(vj - vj == 0.0)) st |= ST_NONFINITE;
             vs[k * S + j] = vr;
