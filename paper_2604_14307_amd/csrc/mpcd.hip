@@ -2710,19 +2710,23 @@ __global__ __launch_bounds__(BODY_T) void k_transfer_first(SysDev s, BodyDev bd,
 // then advances the step counter (last kernel of a step).
 constexpr int FRC_T = 64;
 
-// LDS of the body forces for a block of NT threads.
+// LDS of the body forces for a block of NT threads.  The grid path keeps at
+// most FRC_HCAP partners within the cutoff (a body with more takes the
+// all-pairs path, with the same sums), so that the LDS stays small and many
+// one-wave blocks share a CU.
 constexpr int FRC_NCAND = 27 * GRID_K;
+constexpr int FRC_HCAP = 96;
 template <int NT> struct ForceLds {
     union {
-        double sf[3][NT + 1];      // all-pairs path: each lane's contribution
-        double hc[3][FRC_NCAND];  // grid path: the contributions of the hits
+        double sf[3][NT + 1];     // all-pairs path: each lane's contribution
+        double hc[3][FRC_HCAP];  // grid path: the contributions of the hits
     };
     int shit[NT];
     double fsh[3];
     uint32_t s_h[27];
     int s_n[27], s_pre[28];
     int s_ovf, s_nhit;
-    int hj[FRC_NCAND];
+    int hj[FRC_HCAP];
 };
 
 // The forces (and kick) of body i = blockIdx.x < B by a block of NT threads.
@@ -2832,11 +2836,16 @@ __device__ void body_forces_block(const SysDev &s, const BodyDev &bd, const mpcd
                 const double fr = ((24.0 * wca.eps) * (2.0 * is12 - is6)) / sh;
                 const double fo = fr / rr;
                 const int pos = atomicAdd(&s_nhit, 1);
-                hj[pos] = (int)j;
+                if (pos < FRC_HCAP) {
+                    hj[pos] = (int)j;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) hc[k][pos] = fo * dr[k];
+                    for (int k = 0; k < 3; ++k) hc[k][pos] = fo * dr[k];
+                }
             }
             __syncthreads();
+            use_grid = s_nhit <= FRC_HCAP;  // more partners than the list holds: all pairs
+        }
+        if (use_grid) {
             if (t == 0) {
                 // partners in ascending index, then the sequential sums
                 const int nh = s_nhit;

@@ -424,15 +424,35 @@ def fullest_grid_cell(centres, ncell, rc):
     return int(counts.max())
 
 
-@pytest.mark.parametrize("case", ["many", "crowded"])
+def ball_cluster(rng, n, centre, radius):
+    """n points uniform in a ball."""
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    return np.asarray(centre) + d * (radius * rng.random(n) ** (1.0 / 3.0))[:, None]
+
+
+@pytest.mark.parametrize("case", ["many", "crowded", "hits"])
 def test_wca_forces_neighbour_grid_bit_exact(case):
     """Body-centre WCA forces through the hashed neighbour grid equal the
     oracle's all-pairs loop: 2000 random point bodies (many partners per
-    body), and 45 bodies crowded into one grid cell (a bucket of 32 slots
-    overflows and the kernel falls back to all pairs)."""
+    body); 45 bodies crowded into one grid cell (a bucket of 32 slots
+    overflows and the kernel falls back to all pairs); and a ball of 120
+    bodies around one body at a grid corner, spread over eight cells, so
+    that bodies have more partners within the cutoff than the kernel's hit
+    list holds (96) while no bucket overflows (again all pairs)."""
     rng = np.random.default_rng(12)
     if case == "many":
         ncell, centres = (20, 20, 20), rng.random((2000, 3)) * 20.0
+    elif case == "hits":
+        ncell = (20, 20, 20)
+        corner = np.full(3, 8 * 20.0 / 17.0)  # a corner of the grid's cells (17 per axis)
+        centres = np.concatenate([corner[None, :], ball_cluster(rng, 120, corner, 1.0), rng.random((400, 3)) * 20.0])
+        rc = 2.0 ** (1.0 / 6.0)
+        assert fullest_grid_cell(centres, ncell, rc) <= GRID_SLOTS
+        d = centres[:, None, :] - centres[None, :, :]
+        d -= 20.0 * np.rint(d / 20.0)
+        partners = ((d ** 2).sum(-1) <= rc * rc).sum(1) - 1
+        assert partners.max() > 96
     else:
         ncell = (3, 3, 3)
         centres = np.concatenate([0.2 + 1.1 * rng.random((45, 3)), 1.6 + 1.3 * rng.random((10, 3))])
