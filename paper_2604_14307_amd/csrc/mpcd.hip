@@ -4003,36 +4003,52 @@ __device__ __forceinline__ BrickGrid brick_grid_of(const SysDev &s, const Binned
     return G;
 }
 
+// Status conditions of a lane's members, gathered as lane masks and turned
+// into status bits once (per member they would cost a few vector operations
+// per test).
+struct LaneFlags {
+    bool nonfinite = false, escape = false, binerr = false;
+    __device__ __forceinline__ uint32_t bits() const
+    {
+        return (nonfinite ? ST_NONFINITE : 0u) | (escape ? ST_ESCAPE : 0u) | (binerr ? ST_BINERR : 0u);
+    }
+};
+
 // UNIT: the cell edge is 1, where g * mul is g itself (the same value, without
 // the multiplier or the division path in the block's registers).
 template <bool UNIT>
-__device__ __forceinline__ int brick_axis_cell(float x, float sf, const BrickGrid &G, int d, uint32_t &st)
+__device__ __forceinline__ int brick_axis_cell(float x, float sf, const BrickGrid &G, int d, LaneFlags &lf)
 {
     // selects rather than branches: the per-member code stays one basic block
     const float g = x - sf;
     const float jf = floorf(UNIT ? g : (G.mul != 0.0f ? g * G.mul : g / G.a));
-    const bool ok = jf >= -1.0f && jf <= G.nf[d];
-    int j = (int)jf;
-    j = j < 0 ? j + G.n[d] : j;
-    j = j >= G.n[d] ? j - G.n[d] : j;
-    st |= ok ? 0u : ((g != g) ? ST_NONFINITE : ST_ESCAPE);
-    return ok ? j : 0;
+    const bool ok = jf >= -1.0f && jf <= G.nf[d];  // cells -1 .. n: at most one box edge off
+    const bool nan = g != g;
+    lf.nonfinite = lf.nonfinite || nan;
+    lf.escape = lf.escape || (!ok && !nan);
+    // exact in range; out of range the value is never selected
+    const unsigned j = (unsigned)(int)jf;
+    const unsigned n = (unsigned)G.n[d];
+    // the periodic wrap: -1 -> n - 1, n -> 0, else unchanged (the least of
+    // j, j + n and j - n as unsigned)
+    const unsigned r = min(min(j, j + n), j - n);
+    return ok ? (int)r : 0;
 }
 
 // Local cell of a member on this step's grid from the block's FP32 grid (-1
 // and BINERR when the member is not in this brick: only with a corrupted state).
 template <bool UNIT>
 __device__ __forceinline__ int brick_local_cell_g(const BrickGrid &G, const BrickInfo &bi, const float p[3],
-                                                  uint32_t &st)
+                                                  LaneFlags &lf)
 {
     int lc[3];
     bool in = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        lc[d] = brick_axis_cell<UNIT>(p[d], G.sh[d], G, d, st) - bi.org[d];
+        lc[d] = brick_axis_cell<UNIT>(p[d], G.sh[d], G, d, lf) - bi.org[d];
         in = in && (unsigned)lc[d] < (unsigned)bi.dim[d];
     }
-    st |= in ? 0u : ST_BINERR;
+    lf.binerr = lf.binerr || !in;
     return in ? (lc[2] * bi.dim[1] + lc[1]) * bi.dim[0] + lc[0] : -1;
 }
 
@@ -4178,7 +4194,7 @@ __device__ __forceinline__ int brick_stream(const BrickArgs<Real> &A, const Bric
 // brick.
 template <bool UNIT>
 __device__ __forceinline__ int brick_stream_g(const BrickArgs<float> &A, const BrickGrid &G, const BrickInfo &bi,
-                                              const float L[3], float p[3], float w[3], int32_t *dst, uint32_t &st)
+                                              const float L[3], float p[3], float w[3], int32_t *dst, LaneFlags &lf)
 {
     const float dtr = (float)A.dt;
 #pragma unroll
@@ -4190,13 +4206,15 @@ __device__ __forceinline__ int brick_stream_g(const BrickArgs<float> &A, const B
         }
         // the periodic wrap of wrap_f, as selects
         y = y >= L[d] ? y - L[d] : (y < 0.0f ? y + L[d] : y);
-        st |= (y >= 0.0f && y <= L[d]) ? 0u : ((y != y) ? ST_NONFINITE : ST_ESCAPE);
+        const bool nan = y != y;
+        lf.nonfinite = lf.nonfinite || nan;
+        lf.escape = lf.escape || (!(y >= 0.0f && y <= L[d]) && !nan);
         p[d] = y;
     }
     int jc[3], cls = 0, mul = 1;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        jc[d] = brick_axis_cell<UNIT>(p[d], G.sh1[d], G, d, st);
+        jc[d] = brick_axis_cell<UNIT>(p[d], G.sh1[d], G, d, lf);
         // class_code as selects
         int e = (bi.org[d] >> G.lg[d]) - (jc[d] >> G.lg[d]);
         e = e < 0 ? e + G.nb[d] : e;
@@ -4261,6 +4279,7 @@ k_brick_collide_f32(BrickArgs<float> A)
     const uint64_t step = *A.d_step;
     const int par_in = (int)(step & 1), par_out = par_in ^ 1;
     uint32_t st = 0;
+    LaneFlags lf;  // status conditions of the fast path's members
     const int64_t b = tile_of_block((int)bn.nbricks);
     if (b < bn.nbricks) {
         const BrickInfo bi = bn.brick[b];
@@ -4404,7 +4423,7 @@ k_brick_collide_f32(BrickArgs<float> A)
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 if (lc[k] < 0) continue;
-                lc[k] = brick_local_cell_g<UNIT>(G, bi, p[k], st);
+                lc[k] = brick_local_cell_g<UNIT>(G, bi, p[k], lf);
                 if (lc[k] < 0) continue;
                 long long q[5];
                 if (id[k] >= 0) {
@@ -4442,7 +4461,7 @@ k_brick_collide_f32(BrickArgs<float> A)
                 if (brick_cnt_members(L.cnt[lc[k]]) >= 2) brick_rotate_f32(L.cell[lc[k]].par, w[k], st);
                 if (id[k] < 0) continue;  // a site: written back below
                 int32_t dst = 0;
-                const int cls = brick_stream_g<UNIT>(A, G, bi, Lb, p[k], w[k], &dst, st);
+                const int cls = brick_stream_g<UNIT>(A, G, bi, Lb, p[k], w[k], &dst, lf);
                 lc[k] = cls >= 0 ? cls : NCLS;  // NCLS: beyond the neighbouring bricks
                 rank[k] = cls > 0 ? atomicAdd(&L.wcnt[cls], 1) : dst;  // the own class: below
             }
@@ -4551,7 +4570,7 @@ k_brick_collide_f32(BrickArgs<float> A)
     }
     for (int64_t q = (int64_t)blockIdx.x * BRICK_T + t; A.grid_clear && q < A.grid_n; q += (int64_t)gridDim.x * BRICK_T)
         A.grid_clear[q] = 0;
-    flag(A.status, st);
+    flag(A.status, st | lf.bits());
 }
 
 __global__ void k_binned_finish(BinnedDev bn, const uint64_t *d_step) { binned_finish(bn, *d_step); }

@@ -96,6 +96,36 @@ def test_escaping_particle_sets_escape():
     assert g.status() & L.FLAG_ESCAPE
 
 
+@pytest.mark.parametrize("case", ["nonfinite", "escape"])
+def test_binned_step_sets_nonfinite_and_escape(case):
+    """The binned FP32 step (the brick collision's cells and streaming) flags a
+    NaN velocity as NONFINITE, and cells carried beyond the box in one step as
+    ESCAPE, and the steps return normally.  For the escape every solvent
+    particle with x >= 8 (clear of the sphere, which reaches x = 7) moves at
+    300 along x: a cell made only of them keeps that mean and moves 30 cells
+    in a 10-cell box, while m v^2 2^32 stays below the fixed-point limit 2^51
+    (a single fast particle would need more than that to carry its cell out)."""
+    wl, par, _ = W.config(0)
+    if case == "nonfinite":
+        wl = with_velocity(wl, far_particle(wl), (np.nan, 0.0, 0.0))
+    else:
+        wl = dict(wl)
+        wl["v"] = wl["v"].copy()
+        wl["v"][:, wl["x"][0] >= 8.0] = np.array([300.0, 0.0, 0.0])[:, None]
+    g = gpu_system(wl, par, prec="f32", layout="binned")
+    g.body_forces()
+    g.step(1)
+    flags = g.status()
+    if case == "nonfinite":
+        assert flags & L.FLAG_NONFINITE
+        assert not flags & L.FLAG_ESCAPE
+    else:
+        assert flags & L.FLAG_ESCAPE
+        assert not flags & (L.FLAG_NONFINITE | L.FLAG_FIXOVF)
+    g.step(1)  # the flagged members are binned again (into cell 0 on a bad axis)
+    assert g.status() & (L.FLAG_NONFINITE if case == "nonfinite" else L.FLAG_ESCAPE)
+
+
 def test_fixed_point_overflow_sets_fixovf():
     """FP32: a velocity with m v 2^32 beyond the int64 fixed-point range adds
     nothing to its cell's sums and sets FIXOVF; the step completes."""
