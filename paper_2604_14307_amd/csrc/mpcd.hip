@@ -5857,8 +5857,9 @@ static int overlap_mode(const mpcd_step_args *a)
 // collision (collide, stream, bin the new solvent for the next step),
 // transfer fused with the first body half-step, forces fused with the second
 // half kick and the step-counter advance.  (Fusing the forces with the next
-// step's thermalization into one launch was slower: the one-wave force
-// blocks and the thermalization's smaller blocks each fill the CUs better.)
+// step's thermalization into one launch was slower: one-wave force blocks,
+// and thermalization blocks without the force code's LDS and registers, each
+// fill the CUs better.)
 static int step_binned(void *stream, const mpcd_step_args *a)
 {
     const mpcd_sys *s = a->sys;
