@@ -138,6 +138,15 @@ def test_crowded_brick_overflow_and_two_pass_path():
     assert gb.status() == 0
 
 
+def test_bodies_of_more_sites_than_a_block():
+    """Two spheres of 600 sites (three chunks of the thermalization's block,
+    more sites than a brick's list holds): the binned step against the dense
+    FP32 form."""
+    wl = W.suspension((12, 12, 12), 5, 2, 2.0, 600, 5.0, seed=36)
+    par = W.srd_params(36, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
+    dense_and_binned(wl, par, 6, check_every=3)
+
+
 def test_site_list_overflow():
     """Six spheres of 100 sites packed into one brick of 8 x 8 x 4 cells: the
     brick's site list (its 256 cells + 64 slots) overflows into the shared

@@ -524,6 +524,34 @@ def test_site_wca_small_box_bit_exact(ncell):
     run_parity(wl, par, 8, check_every=4)
 
 
+def test_bodies_of_more_sites_than_a_block_bit_exact():
+    """Two spheres of 600 sites, three chunks of a 256-thread body block: the
+    site thermalization stores and reloads the thermal velocities between
+    its passes, and the transfer's ordered sums run over chunks.  Full steps
+    against the oracle."""
+    wl = W.suspension((12, 12, 12), 5, 2, 2.0, 600, 5.0, seed=36)
+    par = W.srd_params(36, kT_cell=1.0, wca=W.wca_spheres(sigma=4.0))
+    say("600-site spheres")
+    run_parity(wl, par, 6, check_every=3)
+
+
+def test_site_wca_bodies_of_more_sites_than_a_block_bit_exact():
+    """Two spheres of 300 sites in contact through site-site WCA: each body's
+    sites take two chunks of the block, and so do each candidate's staged
+    sites, which the waves cull by their boxes.  Forces, torques and full
+    steps against the oracle."""
+    rng = np.random.default_rng(76)
+    tpl = W.sphere_template(1.5, 300, 5.0)
+    centres = np.array([[4.0, 5.0, 5.0], [7.25, 5.0, 5.0]])
+    wl = W.make_system((10, 10, 10), 3, [tpl] * 2, centres, W.random_quaternions(rng, 2), rng)
+    par = W.srd_params(76, kT_cell=1.0, wca=W.wca_sites(sigma=0.3))
+    o0 = oracle.OracleSystem(wl, par)
+    o0.body_forces()
+    assert np.count_nonzero(o0.T) > 0  # the spheres interact from the start
+    say("site WCA 300-site spheres")
+    run_parity(wl, par, 6, check_every=3)
+
+
 def test_site_wca_crowded_bodies_fall_back_to_all_pairs():
     """Small shapes packed so a grid bucket overflows: every body of the
     system becomes a candidate, with the same sums."""
