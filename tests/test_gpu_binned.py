@@ -138,6 +138,22 @@ def test_crowded_brick_overflow_and_two_pass_path():
     assert gb.status() == 0
 
 
+@pytest.mark.parametrize("a,ncell,density", [(0.5, (10, 10, 10), 5), (1.5, (10, 10, 10), 5),
+                                             (0.5, (128, 128, 64), 1)])
+def test_non_unit_cell_edge(a, ncell, density):
+    """A cell edge other than 1 (the brick collision's general cell form, by
+    the exact reciprocal for 0.5 and by division for 1.5), in the eight-wave
+    block and, in a box of 4096 bricks, the four-wave block: the binned step
+    against the dense FP32 form."""
+    rng = np.random.default_rng(78)
+    tpl = W.sphere_template(2.0 * a, 100, 5.0)
+    centre = 0.5 * a * np.asarray(ncell, dtype=np.float64)[None, :]
+    wl = W.make_system(ncell, density, [tpl], centre, W.random_quaternions(rng, 1), rng, a=a)
+    par = W.srd_params(78, kT_cell=1.0)
+    gd, gb = dense_and_binned(wl, par, 4, check_every=2)
+    assert gb.binned.items == (7 if ncell[0] == 128 else 4)
+
+
 def test_bodies_of_more_sites_than_a_block():
     """Two spheres of 600 sites (three chunks of the thermalization's block,
     more sites than a brick's list holds): the binned step against the dense

@@ -524,6 +524,24 @@ def test_site_wca_small_box_bit_exact(ncell):
     run_parity(wl, par, 8, check_every=4)
 
 
+def edge_system(a, ncell=(10, 10, 10), density=5, seed=77):
+    """One sphere of 100 sites (radius 2a) at the centre of a box of cell edge a."""
+    rng = np.random.default_rng(seed)
+    tpl = W.sphere_template(2.0 * a, 100, 5.0)
+    centre = 0.5 * a * np.asarray(ncell, dtype=np.float64)[None, :]
+    return W.make_system(ncell, density, [tpl], centre, W.random_quaternions(rng, 1), rng, a=a)
+
+
+@pytest.mark.parametrize("a", [0.5, 1.5])
+def test_non_unit_cell_edge_bit_exact(a):
+    """A cell edge other than 1: a power of two (the kernels multiply by its
+    exact reciprocal) and 1.5 (they divide), full steps against the oracle."""
+    wl = edge_system(a)
+    par = W.srd_params(77, kT_cell=1.0)
+    say("cell edge %g" % a)
+    run_parity(wl, par, 6, check_every=3)
+
+
 def test_bodies_of_more_sites_than_a_block_bit_exact():
     """Two spheres of 600 sites, three chunks of a 256-thread body block: the
     site thermalization stores and reloads the thermal velocities between
